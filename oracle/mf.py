@@ -1,0 +1,122 @@
+"""ORACLE (test infrastructure): Python side of the plain App-A matvec in ``mf_ref.c``.
+
+The term list of a model is first collapsed into the pseudocode's inputs (App. A): per-site one-site
+couplings (h_z, h_+, h_-, plus the (S_z)^2 coupling of App. B) and a pair list with a 3x3 table
+J^{alpha beta}, alpha, beta in (z, +, -), each coupling being theta[p] * w summed over the terms that
+land on it.  The C code then runs the pseudocode's row loop over all rows or over sampled rows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from workloads.model import OP_LOWER, OP_RAISE, OP_Z, OP_Z2, Model
+
+from . import build as _build
+
+_ALPHA = {OP_Z: 0, OP_RAISE: 1, OP_LOWER: 2}
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.mf_ref_matvec.restype = ctypes.c_int
+        L.mf_ref_matvec.argtypes = [ctypes.c_int32, i32p, i32p, f64p, ctypes.c_int32, i32p, i32p,
+                                    f64p, ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
+        L.mf_ref_sources.restype = ctypes.c_int
+        L.mf_ref_sources.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int64,
+                                     ctypes.c_int64, i64p]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def app_a_inputs(model: Model, theta=None):
+    """Collapse the term list into (kind, 2s, onsite[N,4], pair_i, pair_j, J[P,3,3])."""
+    theta = model.theta if theta is None else np.asarray(theta, dtype=np.float64)
+    N = len(model.sites)
+    kind, twok = model.site_arrays()
+    onsite = np.zeros((N, 4), dtype=np.complex128)  # h_z, h_zz, h_+, h_-
+    pairs: dict = {}
+    Jlist = []
+    for t in model.terms:
+        c = theta[t.param] * complex(t.w)
+        if t.site_b < 0:
+            col = {OP_Z: 0, OP_Z2: 1, OP_RAISE: 2, OP_LOWER: 3}[t.op_a]
+            onsite[t.site_a, col] += c
+            continue
+        if t.site_a == t.site_b or t.op_a not in _ALPHA or t.op_b not in _ALPHA:
+            raise ValueError("pair terms take two different sites and operators in (z, +, -)")
+        key = (t.site_a, t.site_b)
+        if key not in pairs:
+            pairs[key] = len(Jlist)
+            Jlist.append(np.zeros((3, 3), dtype=np.complex128))
+        Jlist[pairs[key]][_ALPHA[t.op_a], _ALPHA[t.op_b]] += c
+    keys = sorted(pairs, key=lambda k: pairs[k])
+    pi = np.array([k[0] for k in keys], dtype=np.int32)
+    pj = np.array([k[1] for k in keys], dtype=np.int32)
+    J = np.array(Jlist, dtype=np.complex128).reshape(-1, 3, 3) if Jlist else np.zeros((0, 3, 3), np.complex128)
+    return kind, twok, onsite, pi, pj, J
+
+
+def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
+    """y = H(theta) x in FP64 (x is upcast exactly).  rows: optional int64 target indices; then the
+    result holds y at those rows only."""
+    kind, twok, onsite, pi, pj, J = app_a_inputs(model, theta)
+    D = model.dim
+    xx = np.ascontiguousarray(np.asarray(x).reshape(-1), dtype=np.complex128)
+    if xx.shape[0] != D:
+        raise ValueError(f"x has {xx.shape[0]} entries, the basis has {D}")
+    onsite = np.ascontiguousarray(onsite)
+    J = np.ascontiguousarray(J)
+    if rows is None:
+        nrows, rp = D, None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        if rows.size and (rows.min() < 0 or rows.max() >= D):
+            raise ValueError("row index out of range")
+        nrows, rp = rows.shape[0], _p(rows, ctypes.c_int64)
+    y = np.empty(nrows, dtype=np.complex128)
+    rc = lib().mf_ref_matvec(len(model.sites), _p(kind, ctypes.c_int32), _p(twok, ctypes.c_int32),
+                             _p(onsite.view(np.float64), ctypes.c_double), len(pi),
+                             _p(pi, ctypes.c_int32), _p(pj, ctypes.c_int32),
+                             _p(J.view(np.float64), ctypes.c_double), D,
+                             _p(xx.view(np.float64), ctypes.c_double),
+                             _p(y.view(np.float64), ctypes.c_double), nrows, rp)
+    if rc != 0:
+        raise RuntimeError("mf_ref_matvec rejected its input")
+    return y
+
+
+def sources(model: Model, F0: int, count: int) -> np.ndarray:
+    """Source index (or -1) of every term for target rows F0..F0+count-1: int64 [count, n_terms]."""
+    _, twok = model.site_arrays()
+    al = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: 2}
+    tt = np.array([(t.site_a, al[t.op_a], t.site_b, al[t.op_b] if t.site_b >= 0 else 0)
+                   for t in model.terms], dtype=np.int32).reshape(-1, 4)
+    out = np.empty((count, len(model.terms)), dtype=np.int64)
+    rc = lib().mf_ref_sources(len(model.sites), _p(twok, ctypes.c_int32), len(model.terms),
+                              _p(tt, ctypes.c_int32), int(F0), int(count), _p(out, ctypes.c_int64))
+    if rc != 0:
+        raise RuntimeError("mf_ref_sources rejected its input")
+    return out
+
+
+def adjoint_model(model: Model) -> Model:
+    """Term list of H^dagger: every operator replaced by its adjoint, every weight conjugated."""
+    from workloads.model import Term
+    adj = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE}
+    terms = [Term(t.site_a, adj[t.op_a], t.site_b, adj[t.op_b] if t.site_b >= 0 else t.op_b, t.param,
+                  complex(t.w).conjugate()) for t in model.terms]
+    return Model(model.sites, terms, model.theta.copy(), name=model.name + "^dag")
