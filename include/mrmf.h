@@ -1,0 +1,204 @@
+/*
+ * mrmf — mixed-radix matrix-free spin/boson Hamiltonians on MI355X (gfx950).
+ *
+ * C ABI of the HIP library libmrmf.so.  The library applies y = H x for a lattice Hamiltonian given
+ * as a list of local dimensions and a list of one- and two-site operator terms, without storing H
+ * ("Spin Hamiltonian as Matrix-Free Linear Map", Sec. II target-driven form, Sec. III mixed-radix
+ * indexing, Sec. IV one- and two-site rules, App. A pseudocode, App. B (S_z)^2 channel, App. C
+ * truncated boson digits), drives it with a device-resident Lanczos eigensolver, applies its adjoint
+ * for gradients, and runs many lattices in one persistent launch.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Site 0 is the most significant digit: M_k = prod_{l>k} d_l, index = sum_k n_k M_k (Sec. III,
+ *    Eq. encode), i.e. C-order flattening of a tensor of shape (d_0, .., d_{N-1}).
+ *  - Local digit n = m + s for a spin (n = 0 is m = -s), n = occupation for a boson (App. C).
+ *  - Complex vectors are interleaved (re, im): c128 = 2 x double, c64 = 2 x float.
+ *  - Every pointer named d_* is DEVICE memory owned by the caller; the library never allocates device
+ *    memory.  Host arrays are read during the call only.
+ *  - Every call that takes a stream enqueues its work on that stream (a hipStream_t, passed as
+ *    void*; NULL is the null stream) and returns without synchronising.  Argument errors are
+ *    reported synchronously, before anything is enqueued; launch failures map to MRMF_E_HIP.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef MRMF_H
+#define MRMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mrmf_status;
+#define MRMF_OK 0
+#define MRMF_E_INVALID_ARG (-1)   /* bad pointer, size, site index, operator, aliasing          */
+#define MRMF_E_OVERFLOW (-2)      /* D = prod d_i >= 2^62 (single-word index bound, Sec. VI)      */
+#define MRMF_E_NOT_HERMITIAN (-3) /* some parameter group h_p differs from its adjoint (IV.A, IV.B) */
+#define MRMF_E_HIP (-4)           /* a HIP runtime call or kernel launch failed                  */
+#define MRMF_E_UNSUPPORTED (-5)   /* valid request outside what this build implements            */
+#define MRMF_E_WORKSPACE (-6)     /* workspace / scratch smaller than the size query returned     */
+
+typedef void* mrmf_stream; /* hipStream_t */
+typedef struct mrmf_plan_t* mrmf_plan;
+typedef struct mrmf_batch_t* mrmf_batch;
+
+/* Site kinds.  SPIN: k = 2s, local dimension d = k + 1 (Sec. I, Eq. 1).
+ * BOSON: k = n_max, digits 0..n_max, d = k + 1 (App. C). */
+#define MRMF_SPIN 0
+#define MRMF_BOSON 1
+typedef struct {
+    int32_t kind;
+    int32_t k;
+} mrmf_site;
+
+/* Local operators.  Z: S_z (spin) or a^dag a (boson); Z2: its square (App. B diagonal channel, one-site
+ * only); RAISE: S_+ or a^dag (digit shift +1); LOWER: S_- or a (digit shift -1) (Sec. IV.A, App. C). */
+#define MRMF_OP_Z 0
+#define MRMF_OP_Z2 1
+#define MRMF_OP_RAISE 2
+#define MRMF_OP_LOWER 3
+
+/* One term of  H(theta) = sum_t theta[param_t] * (w_re + i w_im) * O_{op_a}^{(site_a)} O_{op_b}^{(site_b)}.
+ * site_b = -1 makes it a one-site term (op_b ignored).  A two-site term needs site_a != site_b and
+ * op_a, op_b in {Z, RAISE, LOWER}: the pair channels J^{alpha beta} of Eq. (pairham).  theta is real and
+ * supplied per call in device memory, so couplings can change between calls without a new plan. */
+typedef struct {
+    int32_t site_a, op_a, site_b, op_b;
+    int32_t param, reserved;
+    double w_re, w_im;
+} mrmf_term;
+
+/* plan flags */
+#define MRMF_REQUIRE_HERMITIAN 1u /* reject unless every group h_p = sum_{param_t = p} w_t O_t is Hermitian */
+
+/* precision forms for mrmf_lanczos */
+#define MRMF_PREC_Z 0       /* c128 matvec, FP64 everything                                   */
+#define MRMF_PREC_C_IN_Z 1  /* c64 matvec on a c64 copy of v_j; FP64 dots, reorth, T solve     */
+
+/* reorthogonalisation policies for mrmf_lanczos */
+#define MRMF_REORTH_CGS2 0  /* full: classical Gram-Schmidt against all of V, applied twice       */
+#define MRMF_REORTH_NONE 1  /* plain three-term recurrence                                       */
+
+/* ---------------------------------------------------------------------------------------------- */
+/* Status text ("ok", "invalid argument", ...).  Static storage; never NULL. */
+const char* mrmf_status_string(mrmf_status s);
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t mrmf_version(void);
+
+/* Build a plan (host only, no HIP call): validates sites and terms, computes d_i, the multipliers M_i
+ * and D (Sec. III) with an overflow check (Sec. VI, index-range remark), folds the diagonal terms, and
+ * lists the off-diagonal terms with their integer source offsets (Eq. sourceoffset) and closed-form
+ * ladder tables (App. A Lambda).  n_sites in [1, 64]; every d_i in [2, 256]; params in [0, n_params).
+ * flags: MRMF_REQUIRE_HERMITIAN.  On success *out owns host memory until mrmf_plan_destroy. */
+mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_terms,
+                             const mrmf_term* terms, int32_t n_params, uint32_t flags, mrmf_plan* out);
+void mrmf_plan_destroy(mrmf_plan plan);
+
+/* D = prod d_i. */
+mrmf_status mrmf_plan_dim(mrmf_plan plan, int64_t* D);
+/* Number of off-diagonal terms (those with a RAISE or LOWER operator): the "channels". */
+mrmf_status mrmf_plan_n_offdiag(mrmf_plan plan, int32_t* n);
+/* For channel c (c = 0..n_offdiag-1, in input order): host out[c] = index of its input term. */
+mrmf_status mrmf_plan_offdiag_terms(mrmf_plan plan, int32_t* out);
+/* For channel c: host out[c] = Delta_c with source index I = F - Delta_c (Eq. sourceoffset:
+ * Delta = delta(alpha) M_i + delta(beta) M_j). */
+mrmf_status mrmf_plan_offsets(mrmf_plan plan, int64_t* out);
+
+/* Device workspace the plan's tables need (bytes, 256-aligned).  The caller allocates it and fills it
+ * once with mrmf_plan_upload (an async host-to-device copy on the stream); it is read-only afterwards
+ * and may be shared by concurrent calls. */
+mrmf_status mrmf_plan_workspace_bytes(mrmf_plan plan, size_t* bytes);
+mrmf_status mrmf_plan_upload(mrmf_plan plan, void* d_ws, size_t ws_bytes, mrmf_stream stream);
+
+/* y = H(theta) x, plain FP64 form.  d_theta: double[n_params]; d_x, d_y: c128[D], 16-byte aligned,
+ * must not overlap (the gather form reads x while writing y, Sec. II).  y is overwritten (App. A). */
+mrmf_status mrmf_matvec_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                          void* d_y, mrmf_stream stream);
+/* Same map in FP32: d_theta float[n_params]; d_x, d_y c64[D], 8-byte aligned; tables and accumulation
+ * in FP32. */
+mrmf_status mrmf_matvec_c(mrmf_plan plan, const void* d_ws, const float* d_theta, const void* d_x,
+                          void* d_y, mrmf_stream stream);
+
+/* Integer part of the map, for bit-exact checks: for rows F0..F0+count-1 and every channel c,
+ * d_out[(F - F0) * n_offdiag + c] = source index I of Eq. (sourceoffset) if both source digits are
+ * admissible, else -1.  d_out: int64, device. */
+mrmf_status mrmf_debug_sources(mrmf_plan plan, const void* d_ws, int64_t F0, int64_t count,
+                               int64_t* d_out, mrmf_stream stream);
+
+/* Adjoint of y = H(theta) x for an upstream gradient g = dL/dRe y + i dL/dIm y:
+ *   d_grad_x     = H^dagger g = H g  (c128[D]; needs a Hermitian plan, Sec. IV.A/IV.B conditions)
+ *   d_grad_theta = Re <g | h_p x>, p = 0..n_params-1  (double[n_params], h_p = dH/dtheta_p)
+ * computed in one gather pass over g plus a deterministic second-stage reduction.
+ * d_scratch: device memory of at least mrmf_adjoint_scratch_bytes.  d_grad_x must not overlap d_g. */
+mrmf_status mrmf_adjoint_scratch_bytes(mrmf_plan plan, size_t* bytes);
+mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                           const void* d_g, void* d_grad_x, double* d_grad_theta, void* d_scratch,
+                           size_t scratch_bytes, mrmf_stream stream);
+
+/* FP64 helpers on c128 vectors of length n (deterministic two-stage reductions; scratch from
+ * mrmf_reduce_scratch_bytes):  d_out[0..1] = <a|b> (re, im);  d_out[0] = ||a||_2. */
+mrmf_status mrmf_reduce_scratch_bytes(int64_t n, size_t* bytes);
+mrmf_status mrmf_dot_z(int64_t n, const void* d_a, const void* d_b, double* d_out, void* d_scratch,
+                       size_t scratch_bytes, mrmf_stream stream);
+mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scratch,
+                        size_t scratch_bytes, mrmf_stream stream);
+
+/* Device-resident Lanczos driving the matvec (the Krylov use of x -> H x, Sec. I).
+ * Step j: w = H v_j; alpha_j = Re<v_j|w>; w -= alpha_j v_j + beta_{j-1} v_{j-1};
+ * (MRMF_REORTH_CGS2 only) twice c = V^H w, w -= V c; beta_j = ||w||;
+ * stop when beta_j <= 1e-14 * ||T|| (Gershgorin estimate);
+ * v_{j+1} = w / beta_j.  Then the lowest eigenpair (theta, s) of the k x k tridiagonal T (bisection
+ * and inverse iteration on the GPU), the Ritz vector u = V s, and the explicit residual
+ * ||H u - theta u|| with the FP64 matvec.
+ *   reorth   : MRMF_REORTH_CGS2 or MRMF_REORTH_NONE
+ *   precision: MRMF_PREC_Z, or MRMF_PREC_C_IN_Z (then d_theta_c float[n_params] is required and the
+ *              matvec runs in c64 on a c64 copy of v_j; everything else stays FP64)
+ *   d_v0     : c128[D] start vector (normalised internally; zero norm -> steps = 0, theta = NaN)
+ *   d_V      : c128[(m + 1) * D] Lanczos basis, caller-owned; row j is v_j
+ *   d_alpha, d_beta : double[m]
+ *   d_result : double[4] = theta, residual estimate beta_{k-1}|s_{k-1}|, explicit residual, steps k
+ *   d_u      : c128[D] Ritz vector (written)
+ *   d_scratch: at least mrmf_lanczos_scratch_bytes(plan, m, precision)
+ * All work is enqueued on the stream; the host never waits inside the call. */
+mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes);
+mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z,
+                         const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
+                         const void* d_v0,
+                         void* d_V, double* d_alpha, double* d_beta, double* d_result, void* d_u,
+                         void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+
+/* Batched form: n independent lattices (plans), each applied to a block of nvec c64 vectors stored
+ * row-major as [D_b][nvec] (row F of lattice b holds its nvec amplitudes contiguously), all in one
+ * persistent launch.  Lattice b's block starts at element offset off_b (host query; offsets are
+ * multiples of 32 elements).  d_theta_all: float, the n_params of lattice 0, then lattice 1, ...
+ * (host query mrmf_batch_theta_offsets).  nvec in {1, 2, 4, 8}.  The batch keeps pointers to its plans'
+ * host data: destroy the batch before its plans. */
+mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, mrmf_batch* out);
+void mrmf_batch_destroy(mrmf_batch batch);
+mrmf_status mrmf_batch_total_elems(mrmf_batch batch, int64_t* elems); /* sum over b of D_b * nvec, padded */
+mrmf_status mrmf_batch_offsets(mrmf_batch batch, int64_t* out);       /* host int64[n] */
+mrmf_status mrmf_batch_theta_offsets(mrmf_batch batch, int32_t* out); /* host int32[n + 1] */
+mrmf_status mrmf_batch_workspace_bytes(mrmf_batch batch, size_t* bytes);
+mrmf_status mrmf_batch_upload(mrmf_batch batch, void* d_ws, size_t ws_bytes, mrmf_stream stream);
+/* Y_b = H_b X_b for every lattice b, one launch. */
+mrmf_status mrmf_batch_matvec_c(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
+                                const void* d_X, void* d_Y, mrmf_stream stream);
+/* Capture the batched launch (and its work-list reset) into a hipGraph owned by the batch, for the
+ * given pointers; mrmf_batch_graph_launch replays it on a stream.  Re-capturing replaces the graph. */
+mrmf_status mrmf_batch_graph_capture(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
+                                     const void* d_X, void* d_Y, mrmf_stream stream);
+mrmf_status mrmf_batch_graph_launch(mrmf_batch batch, mrmf_stream stream);
+/* Autotuner: times each candidate launch shape (rows per work item, threads per block) on the given
+ * buffers with HIP events, keeps the fastest for this batch, and writes host out[0..2] = (rows per
+ * item, block threads, candidate index).  Synchronises the stream. */
+mrmf_status mrmf_batch_autotune(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
+                                const void* d_X, void* d_Y, mrmf_stream stream, int32_t* out);
+/* Set a launch shape directly (e.g. from a tuning cache): rows per item, block threads. */
+mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t rows_per_item, int32_t block_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRMF_H */

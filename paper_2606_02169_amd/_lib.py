@@ -1,0 +1,131 @@
+"""ctypes binding of libmrmf.so: the C ABI declared in include/mrmf.h, one Python function per entry
+point with the same name.  Argument marshalling only; all work happens in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrmf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mrmf.h")
+
+MRMF_OK = 0
+MRMF_E_INVALID_ARG = -1
+MRMF_E_OVERFLOW = -2
+MRMF_E_NOT_HERMITIAN = -3
+MRMF_E_HIP = -4
+MRMF_E_UNSUPPORTED = -5
+MRMF_E_WORKSPACE = -6
+MRMF_SPIN, MRMF_BOSON = 0, 1
+MRMF_OP_Z, MRMF_OP_Z2, MRMF_OP_RAISE, MRMF_OP_LOWER = 0, 1, 2, 3
+MRMF_REQUIRE_HERMITIAN = 1
+MRMF_PREC_Z, MRMF_PREC_C_IN_Z = 0, 1
+MRMF_REORTH_CGS2, MRMF_REORTH_NONE = 0, 1
+
+
+class mrmf_site(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32)]
+
+
+class mrmf_term(ctypes.Structure):
+    _fields_ = [("site_a", ctypes.c_int32), ("op_a", ctypes.c_int32), ("site_b", ctypes.c_int32),
+                ("op_b", ctypes.c_int32), ("param", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("w_re", ctypes.c_double), ("w_im", ctypes.c_double)]
+
+
+class MrmfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+_P = ctypes.POINTER
+
+SIGNATURES = {
+    "mrmf_status_string": (ctypes.c_char_p, [_i32]),
+    "mrmf_version": (_i32, []),
+    "mrmf_plan_create": (_i32, [_i32, _P(mrmf_site), _i32, _P(mrmf_term), _i32, _u32, _P(_vp)]),
+    "mrmf_plan_destroy": (None, [_vp]),
+    "mrmf_plan_dim": (_i32, [_vp, _P(_i64)]),
+    "mrmf_plan_n_offdiag": (_i32, [_vp, _P(_i32)]),
+    "mrmf_plan_offdiag_terms": (_i32, [_vp, _P(_i32)]),
+    "mrmf_plan_offsets": (_i32, [_vp, _P(_i64)]),
+    "mrmf_plan_workspace_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_plan_upload": (_i32, [_vp, _vp, _sz, _vp]),
+    "mrmf_matvec_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_matvec_c": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_debug_sources": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp]),
+    "mrmf_adjoint_scratch_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_adjoint_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mrmf_reduce_scratch_bytes": (_i32, [_i64, _P(_sz)]),
+    "mrmf_dot_z": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mrmf_norm_z": (_i32, [_i64, _vp, _vp, _vp, _sz, _vp]),
+    "mrmf_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),
+    "mrmf_lanczos": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _sz, _vp]),
+    "mrmf_batch_create": (_i32, [_i32, _P(_vp), _i32, _P(_vp)]),
+    "mrmf_batch_destroy": (None, [_vp]),
+    "mrmf_batch_total_elems": (_i32, [_vp, _P(_i64)]),
+    "mrmf_batch_offsets": (_i32, [_vp, _P(_i64)]),
+    "mrmf_batch_theta_offsets": (_i32, [_vp, _P(_i32)]),
+    "mrmf_batch_workspace_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_batch_upload": (_i32, [_vp, _vp, _sz, _vp]),
+    "mrmf_batch_matvec_c": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_batch_graph_capture": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_batch_graph_launch": (_i32, [_vp, _vp]),
+    "mrmf_batch_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _P(_i32)]),
+    "mrmf_batch_set_shape": (_i32, [_vp, _i32, _i32]),
+}
+
+_lib = None
+
+
+def header_symbols():
+    """Names of every function declared in include/mrmf.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrmf_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """The loaded library.  Raises if libmrmf.so has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_02169_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().mrmf_status_string(int(s)).decode()
+
+
+def check(status: int, where: str):
+    if status != MRMF_OK:
+        raise MrmfError(status, where)
+
+
+def call(name: str, *args):
+    """Call an entry point and raise MrmfError on a non-OK status."""
+    st = getattr(lib(), name)(*args)
+    check(st, name)
+    return st
+
+
+def __getattr__(name):
+    # mrmf_* names resolve to the raw library functions (same names as the C ABI)
+    if name.startswith("mrmf_") and name in SIGNATURES:
+        return getattr(lib(), name)
+    raise AttributeError(name)

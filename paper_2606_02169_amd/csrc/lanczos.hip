@@ -1,0 +1,543 @@
+// Device-resident Lanczos eigensolver driving the matrix-free map (the Krylov use of x -> H x, Sec. I)
+// and the FP64 vector reductions it needs.  Every scalar of the recurrence (alpha_j, beta_j, the Gram-
+// Schmidt coefficients, the Ritz value) stays in device memory; the host only enqueues kernels.  After a
+// breakdown every later kernel of the call sees the `stopped` flag and returns at once.
+#include <cmath>
+
+#include "mrmf_internal.h"
+#include "reduce.h"
+
+namespace mrmf {
+namespace {
+
+constexpr int kRB = 256;            // threads per reduction block
+constexpr int kMaxRedBlocks = 512;  // first-stage partials per reduction
+constexpr int kGroup = 8;           // basis vectors per Gram-Schmidt block
+
+struct LzState {
+    int32_t stopped;  // recurrence ended (breakdown, zero start vector, or last step done)
+    int32_t steps;    // k: number of alpha_j computed
+    int32_t breakdown;
+    int32_t pad;
+    double tnorm;  // Gershgorin estimate of ||T|| so far
+    double nrm0;   // ||v0||
+    double theta;  // lowest Ritz value
+    double pad2;
+};
+
+int red_blocks(int64_t n) {
+    const int64_t b = (n + kRB - 1) / kRB;
+    return static_cast<int>(b < kMaxRedBlocks ? (b < 1 ? 1 : b) : kMaxRedBlocks);
+}
+
+__device__ __forceinline__ bool halted(const int32_t* stopped) { return stopped != nullptr && *stopped != 0; }
+
+// ---------------------------------------------------------------- first-stage reductions
+__global__ __launch_bounds__(kRB) void k_norm2_partial(int64_t n, const double2* __restrict__ a,
+                                                        double* __restrict__ partial,
+                                                        const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    __shared__ double lds[kRB / 64];
+    double v[1] = {0.0};
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const double2 x = a[i];
+        v[0] += x.x * x.x + x.y * x.y;
+    }
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// partial[b] = sum over the block's rows of conj(a) b
+__global__ __launch_bounds__(kRB) void k_dot_partial(int64_t n, const double2* __restrict__ a,
+                                                      const double2* __restrict__ b,
+                                                      double2* __restrict__ partial,
+                                                      const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    __shared__ double lds[2 * kRB / 64];
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const double2 x = a[i], y = b[i];
+        v[0] += x.x * y.x + x.y * y.y;
+        v[1] += x.x * y.y - x.y * y.x;
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(v[0], v[1]);
+}
+
+// ||hu - theta u||^2 partials
+__global__ __launch_bounds__(kRB) void k_resid_partial(int64_t n, const double2* __restrict__ hu,
+                                                        const double2* __restrict__ u,
+                                                        const LzState* __restrict__ st,
+                                                        double* __restrict__ partial) {
+    __shared__ double lds[kRB / 64];
+    double v[1] = {0.0};
+    const double th = st->theta;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const double2 a = hu[i], b = u[i];
+        const double rx = a.x - th * b.x, ry = a.y - th * b.y;
+        v[0] += rx * rx + ry * ry;
+    }
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// Gram-Schmidt coefficients c_i = <V_i|w>, i = 0..k-1: partial[i * nb + block]
+__global__ __launch_bounds__(kRB) void k_gemvt_partial(int64_t n, const double2* __restrict__ V, int k,
+                                                        const double2* __restrict__ w,
+                                                        double2* __restrict__ partial, int nb,
+                                                        const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    __shared__ double lds[2 * kGroup * kRB / 64];
+    const int base = blockIdx.y * kGroup;
+    double v[2 * kGroup];
+#pragma unroll
+    for (int g = 0; g < 2 * kGroup; ++g) v[g] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(nb) * kRB) {
+        const double2 y = w[i];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            if (base + g < k) {
+                const double2 x = V[int64_t(base + g) * n + i];
+                v[2 * g] += x.x * y.x + x.y * y.y;
+                v[2 * g + 1] += x.x * y.y - x.y * y.x;
+            }
+        }
+    }
+    block_sum<2 * kGroup>(v, lds);
+    if (threadIdx.x == 0) {
+        for (int g = 0; g < kGroup; ++g)
+            if (base + g < k) partial[int64_t(base + g) * nb + blockIdx.x] = make_double2(v[2 * g], v[2 * g + 1]);
+    }
+}
+
+__global__ void k_gemvt_finalize(int k, int nb, const double2* __restrict__ partial, double2* __restrict__ c,
+                                 const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sr += partial[int64_t(i) * nb + b].x;
+        si += partial[int64_t(i) * nb + b].y;
+    }
+    c[i] = make_double2(sr, si);
+}
+
+// w = (zero ? 0 : w) + sgn * sum_{i<k} c_i V_i  (k read from kdev when given)
+__global__ __launch_bounds__(kRB) void k_gemv_acc(int64_t n, const double2* __restrict__ V, int k,
+                                                   const int32_t* __restrict__ kdev,
+                                                   const double2* __restrict__ c, double2* __restrict__ w,
+                                                   int zero, double sgn, const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    const int kk = kdev ? *kdev : k;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < kk; ++g) {
+            const double2 cg = c[g], x = V[int64_t(g) * n + i];
+            ar += cg.x * x.x - cg.y * x.y;
+            ai += cg.x * x.y + cg.y * x.x;
+        }
+        if (zero) {
+            w[i] = make_double2(sgn * ar, sgn * ai);
+        } else {
+            const double2 y = w[i];
+            w[i] = make_double2(y.x + sgn * ar, y.y + sgn * ai);
+        }
+    }
+}
+
+// w -= alpha v_j; w -= beta v_{j-1}
+__global__ __launch_bounds__(kRB) void k_three_term(int64_t n, double2* __restrict__ w,
+                                                     const double2* __restrict__ vj,
+                                                     const double2* __restrict__ vjm1,
+                                                     const double* __restrict__ alpha,
+                                                     const double* __restrict__ beta,
+                                                     const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    const double a = *alpha;
+    const double b = vjm1 ? *beta : 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        double2 y = w[i];
+        const double2 x = vj[i];
+        y.x -= a * x.x;
+        y.y -= a * x.y;
+        if (vjm1) {
+            const double2 z = vjm1[i];
+            y.x -= b * z.x;
+            y.y -= b * z.y;
+        }
+        w[i] = y;
+    }
+}
+
+// dst = src / denom (and a c64 copy when dst32 is given)
+__global__ __launch_bounds__(kRB) void k_scale(int64_t n, const double2* src, double2* dst,
+                                                const double* __restrict__ denom, float2* __restrict__ dst32,
+                                                const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    const double s = *denom;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const double2 x = src[i];
+        const double2 y = make_double2(x.x / s, x.y / s);
+        dst[i] = y;
+        if (dst32) dst32[i] = make_float2(static_cast<float>(y.x), static_cast<float>(y.y));
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_upcast(int64_t n, const float2* __restrict__ src, double2* __restrict__ dst,
+                                                 const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const float2 x = src[i];
+        dst[i] = make_double2(x.x, x.y);
+    }
+}
+
+// ---------------------------------------------------------------- second stages
+__global__ void k_init_finalize(const double* __restrict__ partial, int nb, LzState* __restrict__ st) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    const double nrm = sqrt(s);
+    st->steps = 0;
+    st->breakdown = 0;
+    st->tnorm = 0.0;
+    st->nrm0 = nrm;
+    st->theta = __builtin_nan("");
+    st->stopped = (nrm > 0.0 && isfinite(nrm)) ? 0 : 1;
+}
+
+__global__ void k_alpha_finalize(const double2* __restrict__ partial, int nb, double* __restrict__ alpha,
+                                 const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b].x;
+    *alpha = s;
+}
+
+__global__ void k_beta_finalize(const double* __restrict__ partial, int nb, int j, int last,
+                                const double* __restrict__ alpha, double* __restrict__ beta,
+                                LzState* __restrict__ st) {
+    if (st->stopped) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    const double bj = sqrt(s);
+    beta[j] = bj;
+    const double t = fabs(alpha[j]) + bj + (j > 0 ? beta[j - 1] : 0.0);
+    st->tnorm = fmax(st->tnorm, t);
+    st->steps = j + 1;
+    if (last) {
+        st->stopped = 1;
+    } else if (bj <= 1e-14 * st->tnorm) {
+        st->stopped = 1;
+        st->breakdown = 1;
+    }
+}
+
+__global__ void k_scalar_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out, int sq) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    *out = sq ? sqrt(s) : s;
+}
+
+__global__ void k_dot_finalize(const double2* __restrict__ partial, int nb, double* __restrict__ out) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sr += partial[b].x;
+        si += partial[b].y;
+    }
+    out[0] = sr;
+    out[1] = si;
+}
+
+// number of eigenvalues of the k x k tridiagonal (a, b) below x (Sturm sequence)
+__device__ int sturm_count(const double* a, const double* b, int k, double x, double pivmin) {
+    int cnt = 0;
+    double q = a[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+        q = a[i] - x - b[i - 1] * b[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Lowest eigenpair of T by bisection and inverse iteration (one thread; k is small).
+// work: 5 * m doubles.  s_out: complex coefficients (s_i, 0) for the Ritz vector, zero past k.
+__global__ void k_tridiag_lowest(const double* __restrict__ alpha, const double* __restrict__ beta, int m,
+                                 LzState* __restrict__ st, double* __restrict__ work,
+                                 double2* __restrict__ s_out, double* __restrict__ result) {
+    const int k = st->steps;
+    const double qnan = __builtin_nan("");
+    for (int i = 0; i < m; ++i) s_out[i] = make_double2(0.0, 0.0);
+    if (k == 0) {
+        result[0] = result[1] = result[2] = qnan;
+        result[3] = 0.0;
+        st->theta = qnan;
+        return;
+    }
+    const double* a = alpha;
+    const double* b = beta;
+    double lo = INFINITY, hi = -INFINITY, bmax2 = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < k - 1 ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+        if (i < k - 1) bmax2 = fmax(bmax2, b[i] * b[i]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, bmax2);
+    const double tn = fmax(fabs(lo), fabs(hi));
+    lo -= 4.0 * 2.220446049250313e-16 * tn + pivmin;
+    hi += 4.0 * 2.220446049250313e-16 * tn + pivmin;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, k, mid, pivmin) >= 1)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    const double theta = 0.5 * (lo + hi);
+    // inverse iteration: LU with partial pivoting of T - theta I (rows swapped as needed)
+    double* dl = work;
+    double* d = work + m;
+    double* du = work + 2 * m;
+    double* du2 = work + 3 * m;
+    double* x = work + 4 * m;
+    double sn = 0.0;
+    for (int i = 0; i < k; ++i) x[i] = 1.0;
+    const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
+    for (int iter = 0; iter < 3; ++iter) {
+        for (int i = 0; i < k; ++i) {
+            d[i] = a[i] - theta;
+            if (i < k - 1) dl[i] = du[i] = b[i];
+            du2[i] = 0.0;
+        }
+        // factor with row interchanges, applying the same eliminations to the right-hand side
+        for (int i = 0; i < k - 1; ++i) {
+            if (fabs(d[i]) >= fabs(dl[i])) {
+                if (d[i] == 0.0) d[i] = tiny;
+                const double f = dl[i] / d[i];
+                dl[i] = f;
+                d[i + 1] -= f * du[i];
+                du2[i] = 0.0;
+                // right-hand side forward step (no swap)
+                x[i + 1] -= f * x[i];
+            } else {
+                const double f = d[i] / dl[i];
+                d[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t - f * d[i + 1];
+                if (i < k - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                const double xt = x[i];
+                x[i] = x[i + 1];
+                x[i + 1] = xt - f * x[i + 1];
+            }
+        }
+        if (d[k - 1] == 0.0) d[k - 1] = tiny;
+        // back substitution with the upper band (d, du, du2)
+        x[k - 1] /= d[k - 1];
+        if (k > 1) x[k - 2] = (x[k - 2] - du[k - 2] * x[k - 1]) / d[k - 2];
+        for (int i = k - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / d[i];
+        sn = 0.0;
+        for (int i = 0; i < k; ++i) sn += x[i] * x[i];
+        sn = sqrt(sn);
+        for (int i = 0; i < k; ++i) x[i] /= sn;
+    }
+    for (int i = 0; i < k; ++i) s_out[i] = make_double2(x[i], 0.0);
+    st->theta = theta;
+    result[0] = theta;
+    result[1] = beta[k - 1] * fabs(x[k - 1]);
+    result[3] = static_cast<double>(k);
+}
+
+// result[2] = sqrt(sum partials)
+__global__ void k_resid_finalize(const double* __restrict__ partial, int nb, const LzState* __restrict__ st,
+                                 double* __restrict__ result) {
+    if (st->steps == 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    result[2] = sqrt(s);
+}
+
+struct LzLayout {
+    size_t state, partial, coef, svec, work, tmp, x32, y32, total;
+};
+
+LzLayout lz_layout(int64_t D, int32_t m, int32_t precision) {
+    LzLayout L{};
+    size_t off = 0;
+    L.state = off;
+    off = align_up(off + sizeof(LzState), 256);
+    L.partial = off;
+    off = align_up(off + sizeof(double2) * size_t(m + 1) * kMaxRedBlocks, 256);
+    L.coef = off;
+    off = align_up(off + sizeof(double2) * size_t(m + 1), 256);
+    L.svec = off;
+    off = align_up(off + sizeof(double2) * size_t(m + 1), 256);
+    L.work = off;
+    off = align_up(off + sizeof(double) * 5 * size_t(m + 1), 256);
+    L.tmp = off;
+    off = align_up(off + sizeof(double2) * size_t(D), 256);
+    L.x32 = L.y32 = off;
+    if (precision == MRMF_PREC_C_IN_Z) {
+        off = align_up(off + sizeof(float2) * size_t(D), 256);
+        L.y32 = off;
+        off = align_up(off + sizeof(float2) * size_t(D), 256);
+    }
+    L.total = off;
+    return L;
+}
+
+int grid_for(int64_t n) {
+    const int64_t b = (n + kRB - 1) / kRB;
+    return static_cast<int>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
+}
+
+}  // namespace
+}  // namespace mrmf
+
+using namespace mrmf;
+
+extern "C" {
+
+mrmf_status mrmf_reduce_scratch_bytes(int64_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = align_up(sizeof(double2) * kMaxRedBlocks, 256);
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_dot_z(int64_t n, const void* d_a, const void* d_b, double* d_out, void* d_scratch,
+                       size_t scratch_bytes, mrmf_stream stream) {
+    if (n < 0 || !d_a || !d_b || !d_out || !d_scratch) return MRMF_E_INVALID_ARG;
+    if (scratch_bytes < sizeof(double2) * kMaxRedBlocks) return MRMF_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = red_blocks(n);
+    auto* part = static_cast<double2*>(d_scratch);
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kRB), 0, s, n, static_cast<const double2*>(d_a),
+                       static_cast<const double2*>(d_b), part, nullptr);
+    hipLaunchKernelGGL(k_dot_finalize, dim3(1), dim3(1), 0, s, part, nb, d_out);
+    return launch_status();
+}
+
+mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scratch, size_t scratch_bytes,
+                        mrmf_stream stream) {
+    if (n < 0 || !d_a || !d_out || !d_scratch) return MRMF_E_INVALID_ARG;
+    if (scratch_bytes < sizeof(double) * kMaxRedBlocks) return MRMF_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = red_blocks(n);
+    auto* part = static_cast<double*>(d_scratch);
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, n, static_cast<const double2*>(d_a), part,
+                       nullptr);
+    hipLaunchKernelGGL(k_scalar_finalize, dim3(1), dim3(1), 0, s, part, nb, d_out, 1);
+    return launch_status();
+}
+
+mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes) {
+    if (!plan || !bytes || m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
+    if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
+    *bytes = lz_layout(plan->D, m, precision).total;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z, const float* d_theta_c,
+                         int32_t precision, int32_t m, int32_t reorth, const void* d_v0, void* d_V,
+                         double* d_alpha, double* d_beta, double* d_result, void* d_u, void* d_scratch,
+                         size_t scratch_bytes, mrmf_stream stream) {
+    if (!plan || !d_ws || !d_theta_z || !d_v0 || !d_V || !d_alpha || !d_beta || !d_result || !d_u ||
+        !d_scratch)
+        return MRMF_E_INVALID_ARG;
+    if (m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
+    if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
+    if (precision == MRMF_PREC_C_IN_Z && !d_theta_c) return MRMF_E_INVALID_ARG;
+    if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE) return MRMF_E_INVALID_ARG;
+    if (!aligned(d_scratch, 256) || !aligned(d_V, 16) || !aligned(d_u, 16) || !aligned(d_v0, 16))
+        return MRMF_E_INVALID_ARG;
+    const int64_t D = plan->D;
+    const LzLayout Lo = lz_layout(D, m, precision);
+    if (scratch_bytes < Lo.total) return MRMF_E_WORKSPACE;
+    const size_t vb = sizeof(double2) * size_t(D);
+    if (ranges_overlap(d_V, vb * size_t(m + 1), d_u, vb) || ranges_overlap(d_V, vb * size_t(m + 1), d_v0, vb))
+        return MRMF_E_INVALID_ARG;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* sc = static_cast<unsigned char*>(d_scratch);
+    auto* st = reinterpret_cast<LzState*>(sc + Lo.state);
+    const int32_t* stopped = &st->stopped;
+    auto* part_d = reinterpret_cast<double*>(sc + Lo.partial);
+    auto* part_z = reinterpret_cast<double2*>(sc + Lo.partial);
+    auto* coef = reinterpret_cast<double2*>(sc + Lo.coef);
+    auto* svec = reinterpret_cast<double2*>(sc + Lo.svec);
+    auto* work = reinterpret_cast<double*>(sc + Lo.work);
+    auto* tmp = reinterpret_cast<double2*>(sc + Lo.tmp);
+    auto* x32 = reinterpret_cast<float2*>(sc + Lo.x32);
+    auto* y32 = reinterpret_cast<float2*>(sc + Lo.y32);
+    auto* V = static_cast<double2*>(d_V);
+    auto* u = static_cast<double2*>(d_u);
+    const bool c32 = precision == MRMF_PREC_C_IN_Z;
+    const int nb = red_blocks(D);
+    const int g = grid_for(D);
+    auto row = [&](int j) { return V + int64_t(j) * D; };
+
+    // v_0 = v0 / ||v0||
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, static_cast<const double2*>(d_v0), part_d,
+                       nullptr);
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(1), 0, s, part_d, nb, st);
+    hipLaunchKernelGGL(k_scale, dim3(g), dim3(kRB), 0, s, D, static_cast<const double2*>(d_v0), row(0), &st->nrm0,
+                       c32 ? x32 : nullptr, stopped);
+    mrmf_status rc = launch_status();
+    if (rc != MRMF_OK) return rc;
+
+    for (int j = 0; j < m; ++j) {
+        double2* w = row(j + 1);
+        if (c32) {
+            rc = matvec_c_impl(plan, d_ws, d_theta_c, x32, y32, s, stopped);
+            if (rc != MRMF_OK) return rc;
+            hipLaunchKernelGGL(k_upcast, dim3(g), dim3(kRB), 0, s, D, y32, w, stopped);
+        } else {
+            rc = matvec_z_impl(plan, d_ws, d_theta_z, row(j), w, s, stopped);
+            if (rc != MRMF_OK) return rc;
+        }
+        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kRB), 0, s, D, row(j), w, part_z, stopped);
+        hipLaunchKernelGGL(k_alpha_finalize, dim3(1), dim3(1), 0, s, part_z, nb, d_alpha + j, stopped);
+        hipLaunchKernelGGL(k_three_term, dim3(g), dim3(kRB), 0, s, D, w, row(j), j > 0 ? row(j - 1) : nullptr,
+                           d_alpha + j, j > 0 ? d_beta + (j - 1) : nullptr, stopped);
+        if (reorth == MRMF_REORTH_CGS2) {
+            const int k = j + 1;
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_gemvt_partial, dim3(nb, (k + kGroup - 1) / kGroup), dim3(kRB), 0, s, D, V, k,
+                                   w, part_z, nb, stopped);
+                hipLaunchKernelGGL(k_gemvt_finalize, dim3((k + 63) / 64), dim3(64), 0, s, k, nb, part_z, coef,
+                                   stopped);
+                hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, k, nullptr, coef, w, 0, -1.0,
+                                   stopped);
+            }
+        }
+        hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
+        hipLaunchKernelGGL(k_beta_finalize, dim3(1), dim3(1), 0, s, part_d, nb, j, j == m - 1 ? 1 : 0, d_alpha,
+                           d_beta, st);
+        if (j < m - 1)
+            hipLaunchKernelGGL(k_scale, dim3(g), dim3(kRB), 0, s, D, w, w, d_beta + j, c32 ? x32 : nullptr,
+                               stopped);
+        rc = launch_status();
+        if (rc != MRMF_OK) return rc;
+    }
+    // lowest Ritz pair of T, Ritz vector u = sum_i s_i v_i, explicit residual with the FP64 map
+    hipLaunchKernelGGL(k_tridiag_lowest, dim3(1), dim3(1), 0, s, d_alpha, d_beta, m, st, work, svec, d_result);
+    hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, m, &st->steps, svec, u, 1, 1.0, nullptr);
+    rc = launch_status();
+    if (rc != MRMF_OK) return rc;
+    rc = matvec_z_impl(plan, d_ws, d_theta_z, u, tmp, s, nullptr);
+    if (rc != MRMF_OK) return rc;
+    hipLaunchKernelGGL(k_resid_partial, dim3(nb), dim3(kRB), 0, s, D, tmp, u, st, part_d);
+    hipLaunchKernelGGL(k_resid_finalize, dim3(1), dim3(1), 0, s, part_d, nb, st, d_result);
+    return launch_status();
+}
+
+}  // extern "C"

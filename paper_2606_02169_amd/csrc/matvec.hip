@@ -1,0 +1,196 @@
+// Generic gather matvec y = H x (Sec. II target-driven form): one thread per output row F, no write
+// conflicts.  For each row the digits are decoded by the mixed-radix rule (Sec. III, Eq. decode), the
+// diagonal terms give one weight on x_F, and every off-diagonal channel either is rejected by the
+// admissibility test on its source digits or reads x at the fixed offset F - Delta (Eqs.
+// src_digit_two_site, sourceoffset) with the coefficient taken from the closed-form ladder tables
+// (App. A Lambda, App. B, App. C).
+//
+// This kernel reads everything from the uploaded plan at run time, so it serves any Hamiltonian; the
+// digits of the thread's row are kept in LDS (one byte per site per thread).
+#include "mrmf_internal.h"
+
+namespace mrmf {
+
+template <typename R>
+struct Cx;
+template <>
+struct Cx<double> {
+    using T = double2;
+};
+template <>
+struct Cx<float> {
+    using T = float2;
+};
+
+// floor(n / d) for n < 2^32 with magic = ceil(2^64 / d)
+__device__ __forceinline__ uint32_t div_magic(uint32_t n, uint64_t magic) {
+    return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));
+}
+
+// Matrix element <n|O|n - q> of a local operator at target digit n (admissible n assumed).
+template <typename R>
+__device__ __forceinline__ R local_factor(const PlanArgs& p, int op, int tab, int n) {
+    switch (op) {
+        case MRMF_OP_Z: return static_cast<R>(p.val[tab + n]);
+        case MRMF_OP_Z2: {
+            const R v = static_cast<R>(p.val[tab + n]);
+            return v * v;
+        }
+        case MRMF_OP_RAISE: return static_cast<R>(p.up[tab + n]);
+        default: return static_cast<R>(p.up[tab + n + 1]);
+    }
+}
+
+constexpr int kGenericBlock = 256;
+
+template <typename R, bool WIDE>
+__global__ __launch_bounds__(kGenericBlock) void k_matvec_generic(
+    PlanArgs p, const R* __restrict__ theta, const typename Cx<R>::T* __restrict__ x,
+    typename Cx<R>::T* __restrict__ y, const int32_t* __restrict__ skip) {
+    using C = typename Cx<R>::T;
+    if (skip != nullptr && *skip != 0) return;
+    __shared__ uint8_t dig[kMaxSites][kGenericBlock];
+    const int tid = threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * kGenericBlock;
+    for (int64_t F = int64_t(blockIdx.x) * kGenericBlock + tid; F < p.D; F += stride) {
+        if (WIDE) {
+            int64_t f = F;
+            for (int i = p.N - 1; i >= 0; --i) {
+                const int64_t d = p.site[i].d;
+                const int64_t q = f / d;
+                dig[i][tid] = static_cast<uint8_t>(f - q * d);
+                f = q;
+            }
+        } else {
+            uint32_t f = static_cast<uint32_t>(F);
+            for (int i = p.N - 1; i >= 0; --i) {
+                const uint32_t q = div_magic(f, p.site[i].magic);
+                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
+                f = q;
+            }
+        }
+        // diagonal weight (S_z, (S_z)^2, n, S_z S_z ...): source index is F itself
+        R dr = 0, di = 0;
+        for (int k = 0; k < p.n_diag; ++k) {
+            const DevDiag g = p.diag[k];
+            R f = local_factor<R>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+            if (g.b >= 0) f *= local_factor<R>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+            const R th = theta[g.param];
+            dr += th * static_cast<R>(g.wr) * f;
+            di += th * static_cast<R>(g.wi) * f;
+        }
+        const C xf = x[F];
+        R ar = dr * xf.x - di * xf.y;
+        R ai = dr * xf.y + di * xf.x;
+        // off-diagonal channels: admissibility on the source digits, then x at F - Delta
+        for (int c = 0; c < p.n_chan; ++c) {
+            const DevChan ch = p.chan[c];
+            const DevSite sa = p.site[ch.a];
+            const int na = dig[ch.a][tid];
+            const int sna = na - ch.qa;
+            if (sna < 0 || sna >= sa.d) continue;
+            R f = local_factor<R>(p, ch.opa, sa.tab, na);
+            if (ch.b >= 0) {
+                const DevSite sb = p.site[ch.b];
+                const int nb = dig[ch.b][tid];
+                const int snb = nb - ch.qb;
+                if (snb < 0 || snb >= sb.d) continue;
+                f *= local_factor<R>(p, ch.opb, sb.tab, nb);
+            }
+            const R th = theta[ch.param] * f;
+            const R cr = th * static_cast<R>(ch.wr), ci = th * static_cast<R>(ch.wi);
+            const C xs = x[F - ch.delta];
+            ar += cr * xs.x - ci * xs.y;
+            ai += cr * xs.y + ci * xs.x;
+        }
+        C out;
+        out.x = ar;
+        out.y = ai;
+        y[F] = out;
+    }
+}
+
+__global__ __launch_bounds__(kGenericBlock) void k_debug_sources(PlanArgs p, int64_t F0, int64_t count,
+                                                                 int64_t* __restrict__ out) {
+    const int64_t r = int64_t(blockIdx.x) * kGenericBlock + threadIdx.x;
+    if (r >= count) return;
+    const int64_t F = F0 + r;
+    for (int c = 0; c < p.n_chan; ++c) {
+        const DevChan ch = p.chan[c];
+        const int64_t da = p.site[ch.a].d;
+        const int na = static_cast<int>((F / p.site[ch.a].M) % da);
+        bool ok = na - ch.qa >= 0 && na - ch.qa < da;
+        if (ch.b >= 0) {
+            const int64_t db = p.site[ch.b].d;
+            const int nb = static_cast<int>((F / p.site[ch.b].M) % db);
+            ok = ok && nb - ch.qb >= 0 && nb - ch.qb < db;
+        }
+        out[r * p.n_chan + c] = ok ? F - ch.delta : -1;
+    }
+}
+
+namespace {
+
+int generic_grid(int64_t D) {
+    const int64_t blocks = (D + kGenericBlock - 1) / kGenericBlock;
+    return static_cast<int>(blocks < 262144 ? blocks : 262144);
+}
+
+template <typename R>
+mrmf_status matvec_generic(const mrmf_plan_t* p, const void* d_ws, const R* theta, const void* x,
+                           void* y, hipStream_t s, const int32_t* d_skip) {
+    using C = typename Cx<R>::T;
+    if (!p || !d_ws || !theta || !x || !y) return MRMF_E_INVALID_ARG;
+    if (!aligned(d_ws, 256) || !aligned(x, sizeof(C)) || !aligned(y, sizeof(C))) return MRMF_E_INVALID_ARG;
+    const size_t bytes = size_t(p->D) * sizeof(C);
+    if (ranges_overlap(x, bytes, y, bytes)) return MRMF_E_INVALID_ARG;
+    const PlanArgs a = plan_args(p, d_ws);
+    const int grid = generic_grid(p->D);
+    if (p->D <= int64_t(0xffffffffu))
+        hipLaunchKernelGGL((k_matvec_generic<R, false>), dim3(grid), dim3(kGenericBlock), 0, s, a, theta,
+                           static_cast<const C*>(x), static_cast<C*>(y), d_skip);
+    else
+        hipLaunchKernelGGL((k_matvec_generic<R, true>), dim3(grid), dim3(kGenericBlock), 0, s, a, theta,
+                           static_cast<const C*>(x), static_cast<C*>(y), d_skip);
+    return launch_status();
+}
+
+}  // namespace
+
+mrmf_status matvec_z_impl(const mrmf_plan_t* p, const void* d_ws, const double* theta, const void* x,
+                          void* y, hipStream_t s, const int32_t* d_skip) {
+    return matvec_generic<double>(p, d_ws, theta, x, y, s, d_skip);
+}
+
+mrmf_status matvec_c_impl(const mrmf_plan_t* p, const void* d_ws, const float* theta, const void* x,
+                          void* y, hipStream_t s, const int32_t* d_skip) {
+    return matvec_generic<float>(p, d_ws, theta, x, y, s, d_skip);
+}
+
+}  // namespace mrmf
+
+extern "C" {
+
+mrmf_status mrmf_matvec_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                          void* d_y, mrmf_stream stream) {
+    return mrmf::matvec_z_impl(plan, d_ws, d_theta, d_x, d_y, static_cast<hipStream_t>(stream), nullptr);
+}
+
+mrmf_status mrmf_matvec_c(mrmf_plan plan, const void* d_ws, const float* d_theta, const void* d_x,
+                          void* d_y, mrmf_stream stream) {
+    return mrmf::matvec_c_impl(plan, d_ws, d_theta, d_x, d_y, static_cast<hipStream_t>(stream), nullptr);
+}
+
+mrmf_status mrmf_debug_sources(mrmf_plan plan, const void* d_ws, int64_t F0, int64_t count,
+                               int64_t* d_out, mrmf_stream stream) {
+    if (!plan || !d_ws || !d_out || F0 < 0 || count < 0 || F0 > plan->D - count) return MRMF_E_INVALID_ARG;
+    if (count == 0 || plan->chans.empty()) return MRMF_OK;
+    const mrmf::PlanArgs a = mrmf::plan_args(plan, d_ws);
+    const int64_t blocks = (count + mrmf::kGenericBlock - 1) / mrmf::kGenericBlock;
+    if (blocks > 0x7fffffff) return MRMF_E_INVALID_ARG;
+    hipLaunchKernelGGL(mrmf::k_debug_sources, dim3(static_cast<unsigned>(blocks)), dim3(mrmf::kGenericBlock), 0,
+                       static_cast<hipStream_t>(stream), a, F0, count, d_out);
+    return mrmf::launch_status();
+}
+
+}  // extern "C"

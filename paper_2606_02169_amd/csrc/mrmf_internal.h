@@ -1,0 +1,125 @@
+// Internal declarations shared by the library's translation units (host plan, kernels, drivers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mrmf.h"
+
+namespace mrmf {
+
+constexpr int kMaxSites = 64;
+constexpr int kMaxDim = 256;  // largest local dimension d_i
+
+// Off-diagonal channel (a term with at least one ladder operator).  The source digit of site a is
+// n_a - qa (Eq. src_digit_two_site); the source index is F - delta (Eq. sourceoffset).
+struct alignas(16) DevChan {
+    int32_t a, b;      // sites, b = -1 for a one-site channel
+    int32_t opa, opb;  // MRMF_OP_*
+    int32_t qa, qb;    // digit shifts (+1 raise, -1 lower, 0 diagonal factor)
+    int32_t param, term;
+    int64_t delta, pad;
+    double wr, wi;
+};
+static_assert(sizeof(DevChan) == 64, "DevChan layout");
+
+// Diagonal term (only Z / Z2 operators).
+struct alignas(16) DevDiag {
+    int32_t a, b, opa, opb;
+    int32_t param, term, pad0, pad1;
+    double wr, wi;
+};
+static_assert(sizeof(DevDiag) == 48, "DevDiag layout");
+
+// Per-site data: local dimension, offset of the site's local tables, multiplier M_i and the
+// reciprocal used for division by d_i of numerators below 2^32 (q = hi64(magic * n)).
+struct alignas(16) DevSite {
+    int32_t d, tab;
+    int32_t kind, pad;
+    int64_t M;
+    uint64_t magic;
+};
+static_assert(sizeof(DevSite) == 32, "DevSite layout");
+
+// Kernel-side view of an uploaded plan (pointers into the caller's workspace).
+struct PlanArgs {
+    const DevSite* site;
+    const DevChan* chan;
+    const DevDiag* diag;
+    const double* val;  // val[tab + n]: S_z eigenvalue m = n - s (spin) or occupation n (boson)
+    const double* up;   // up[tab + n] = <n|R|n-1> for n >= 1 (R = S_+ or a^dagger), up[tab] = 0
+    int64_t D;
+    int32_t N, n_chan, n_diag, n_params;
+};
+
+// Tiling of the index space used by the tiled kernels: sites [k_in, N) form the inner block of
+// T_in = prod d_i consecutive rows; the outer sites index tiles.
+struct Tiling {
+    int32_t k_in = 0;
+    int32_t T_in = 1;
+};
+
+}  // namespace mrmf
+
+struct mrmf_plan_t {
+    int32_t N = 0;
+    std::vector<int32_t> kind, k, d;
+    std::vector<int64_t> M;
+    int64_t D = 1;
+    int32_t n_params = 0;
+    uint32_t flags = 0;
+    std::vector<mrmf::DevChan> chans;
+    std::vector<mrmf::DevDiag> diags;
+    std::vector<int32_t> tab;
+    std::vector<double> val, up;
+    std::vector<mrmf_term> terms;  // input copy
+    // device image
+    std::vector<unsigned char> image;
+    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0;
+    size_t ws_bytes = 0;
+    mrmf::Tiling tiling;
+};
+
+namespace mrmf {
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Plan view over an uploaded workspace.
+inline PlanArgs plan_args(const mrmf_plan_t* p, const void* d_ws) {
+    const unsigned char* b = static_cast<const unsigned char*>(d_ws);
+    PlanArgs a;
+    a.site = reinterpret_cast<const DevSite*>(b + p->off_site);
+    a.chan = reinterpret_cast<const DevChan*>(b + p->off_chan);
+    a.diag = reinterpret_cast<const DevDiag*>(b + p->off_diag);
+    a.val = reinterpret_cast<const double*>(b + p->off_val);
+    a.up = reinterpret_cast<const double*>(b + p->off_up);
+    a.D = p->D;
+    a.N = p->N;
+    a.n_chan = static_cast<int32_t>(p->chans.size());
+    a.n_diag = static_cast<int32_t>(p->diags.size());
+    a.n_params = p->n_params;
+    return a;
+}
+
+inline bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
+
+inline bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+inline mrmf_status hip_status(hipError_t e) { return e == hipSuccess ? MRMF_OK : MRMF_E_HIP; }
+
+// Launch-time error check (after hipLaunchKernelGGL).
+inline mrmf_status launch_status() { return hip_status(hipGetLastError()); }
+
+// Entry points shared between translation units.
+mrmf_status matvec_z_impl(const mrmf_plan_t* p, const void* d_ws, const double* theta,
+                          const void* x, void* y, hipStream_t s, const int32_t* d_skip);
+mrmf_status matvec_c_impl(const mrmf_plan_t* p, const void* d_ws, const float* theta,
+                          const void* x, void* y, hipStream_t s, const int32_t* d_skip);
+
+}  // namespace mrmf

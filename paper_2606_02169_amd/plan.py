@@ -1,0 +1,167 @@
+"""Python side of the HIP library: a plan object holding the C plan handle and its device workspace,
+with thin wrappers that pass torch tensors' device pointers and the current HIP stream.
+
+torch is used for device memory and streams only; every arithmetic step runs in libmrmf.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_gpu(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def _site_array(sites):
+    arr = (L.mrmf_site * len(sites))()
+    for i, s in enumerate(sites):
+        kind, k = (s.kind, s.k) if hasattr(s, "kind") else s
+        arr[i].kind, arr[i].k = int(kind), int(k)
+    return arr
+
+
+def _term_array(terms):
+    arr = (L.mrmf_term * max(1, len(terms)))()
+    for i, t in enumerate(terms):
+        if hasattr(t, "site_a"):
+            sa, oa, sb, ob, p, w = t.site_a, t.op_a, t.site_b, t.op_b, t.param, t.w
+        else:
+            sa, oa, sb, ob, p, w = t
+        w = complex(w)
+        arr[i].site_a, arr[i].op_a, arr[i].site_b, arr[i].op_b = int(sa), int(oa), int(sb), int(ob)
+        arr[i].param, arr[i].w_re, arr[i].w_im = int(p), w.real, w.imag
+    return arr
+
+
+class Plan:
+    """A Hamiltonian structure (sites + terms) compiled by mrmf_plan_create, with its tables uploaded
+    to a device workspace.  Couplings theta are passed per call."""
+
+    def __init__(self, sites: Sequence, terms: Sequence, n_params: int, require_hermitian: bool = True,
+                 device: str | torch.device = "cuda"):
+        self._handle = ctypes.c_void_p()
+        sa, ta = _site_array(sites), _term_array(terms)
+        flags = L.MRMF_REQUIRE_HERMITIAN if require_hermitian else 0
+        L.call("mrmf_plan_create", len(sites), sa, len(terms), ta, int(n_params), flags,
+               ctypes.byref(self._handle))
+        self.n_params = int(n_params)
+        self.device = torch.device(device)
+        D = ctypes.c_int64()
+        L.call("mrmf_plan_dim", self._handle, ctypes.byref(D))
+        self.D = int(D.value)
+        n = ctypes.c_int32()
+        L.call("mrmf_plan_n_offdiag", self._handle, ctypes.byref(n))
+        self.n_offdiag = int(n.value)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_plan_workspace_bytes", self._handle, ctypes.byref(nb))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        L.call("mrmf_plan_upload", self._handle, _ptr(self.ws), nb.value, _stream(self.device))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    @classmethod
+    def from_model(cls, model, **kw) -> "Plan":
+        return cls(model.sites, model.terms, model.n_params, **kw)
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib().mrmf_plan_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    # ------------------------------------------------------------------ host queries
+    def offsets(self):
+        out = (ctypes.c_int64 * max(1, self.n_offdiag))()
+        L.call("mrmf_plan_offsets", self._handle, out)
+        return [int(out[i]) for i in range(self.n_offdiag)]
+
+    def offdiag_terms(self):
+        out = (ctypes.c_int32 * max(1, self.n_offdiag))()
+        L.call("mrmf_plan_offdiag_terms", self._handle, out)
+        return [int(out[i]) for i in range(self.n_offdiag)]
+
+    # ------------------------------------------------------------------ device calls
+    def theta(self, values, dtype=torch.float64) -> torch.Tensor:
+        return torch.as_tensor(values, dtype=dtype).to(self.device)
+
+    def matvec(self, theta: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = H(theta) x; complex128 -> mrmf_matvec_z, complex64 -> mrmf_matvec_c."""
+        _need_gpu(x, "x")
+        if x.numel() != self.D:
+            raise ValueError(f"x has {x.numel()} entries, the basis has {self.D}")
+        y = torch.empty_like(x) if out is None else out
+        _need_gpu(y, "out", x.dtype)
+        if x.dtype == torch.complex128:
+            _need_gpu(theta, "theta", torch.float64)
+            L.call("mrmf_matvec_z", self._handle, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
+                   _stream(self.device))
+        elif x.dtype == torch.complex64:
+            _need_gpu(theta, "theta", torch.float32)
+            L.call("mrmf_matvec_c", self._handle, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
+                   _stream(self.device))
+        else:
+            raise ValueError("x must be complex128 or complex64")
+        return y
+
+    def debug_sources(self, F0: int, count: int) -> torch.Tensor:
+        out = torch.empty((count, self.n_offdiag), dtype=torch.int64, device=self.device)
+        L.call("mrmf_debug_sources", self._handle, _ptr(self.ws), int(F0), int(count), _ptr(out),
+               _stream(self.device))
+        return out
+
+    # ------------------------------------------------------------------ Lanczos
+    def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",
+                reorth: str = "cgs2", theta_c: torch.Tensor | None = None, keep_basis: bool = False) -> dict:
+        """Lowest eigenpair by device-resident Lanczos (mrmf_lanczos).  precision "z" (c128 matvec) or
+        "c_in_z" (c64 matvec inside the FP64 recurrence).  Returns device tensors alpha, beta, the Ritz
+        vector u and result = [theta, residual estimate, explicit residual, steps]."""
+        _need_gpu(theta, "theta", torch.float64)
+        _need_gpu(v0, "v0", torch.complex128)
+        if v0.numel() != self.D:
+            raise ValueError("v0 has the wrong length")
+        prec = {"z": L.MRMF_PREC_Z, "c_in_z": L.MRMF_PREC_C_IN_Z}[precision]
+        ro = {"cgs2": L.MRMF_REORTH_CGS2, "none": L.MRMF_REORTH_NONE}[reorth]
+        if prec == L.MRMF_PREC_C_IN_Z:
+            if theta_c is None:
+                theta_c = theta.to(torch.float32)
+            _need_gpu(theta_c, "theta_c", torch.float32)
+        dev = self.device
+        V = torch.empty((m + 1, self.D), dtype=torch.complex128, device=dev)
+        alpha = torch.zeros(m, dtype=torch.float64, device=dev)
+        beta = torch.zeros(m, dtype=torch.float64, device=dev)
+        result = torch.full((4,), float("nan"), dtype=torch.float64, device=dev)
+        u = torch.empty(self.D, dtype=torch.complex128, device=dev)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_lanczos_scratch_bytes", self._handle, int(m), prec, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        L.call("mrmf_lanczos", self._handle, _ptr(self.ws), _ptr(theta),
+               _ptr(theta_c) if theta_c is not None else None, prec, int(m), ro, _ptr(v0), _ptr(V),
+               _ptr(alpha), _ptr(beta), _ptr(result), _ptr(u), _ptr(scratch), nb.value, _stream(dev))
+        out = dict(alpha=alpha, beta=beta, result=result, u=u, scratch=scratch)
+        if keep_basis:
+            out["V"] = V
+        return out

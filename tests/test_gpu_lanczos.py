@@ -1,0 +1,101 @@
+"""GPU Lanczos (mrmf_lanczos) against the oracle's Lanczos (same algorithm, same start vector) and
+against closed forms.  Energies and residuals are compared, never eigenvectors."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lanczos as olz
+from oracle import mf
+
+pytestmark = pytest.mark.gpu
+
+
+def Plan(model):
+    from paper_2606_02169_amd.plan import Plan as P
+    return P.from_model(model)
+
+
+def run(model, x, m, **kw):
+    p = Plan(model)
+    th = torch.as_tensor(model.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda(), m, **kw)
+    torch.cuda.synchronize()
+    res = out["result"].cpu().numpy()
+    k = int(res[3]) if np.isfinite(res[3]) else 0
+    return dict(theta=res[0], resid_est=res[1], resid=res[2], steps=k,
+                alpha=out["alpha"].cpu().numpy()[:k], beta=out["beta"].cpu().numpy()[:k], u=out["u"])
+
+
+def test_config1_against_oracle_lanczos():
+    m, x = W.config(1)
+    g = run(m, x, 50)
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, 50)
+    print(f"theta gpu={g['theta']!r} oracle={o['theta']!r} resid {g['resid']:.3e} / {o['resid']:.3e}")
+    assert g["steps"] == o["steps"] == 50
+    assert abs(g["theta"] - o["theta"]) <= 1e-12 * abs(o["theta"])
+    assert np.max(np.abs(g["alpha"][:20] - o["alpha"][:20])) < 1e-11
+    assert np.max(np.abs(g["beta"][:20] - o["beta"][:20])) < 1e-11
+    assert g["resid"] < 1e-8 and abs(g["resid_est"] - g["resid"]) < 1e-8
+    ev = np.linalg.eigvalsh(__import__("oracle.kron", fromlist=["x"]).sparse_H(m).toarray())[0]
+    assert abs(g["theta"] - ev) <= g["resid"] + 1e-12          # Weyl bound
+
+
+def test_ferrimagnetic_ring_reduced_against_oracle():
+    m, x = W.config(2, reduced=12)                          # D = 2^6 3^6 = 46656
+    g = run(m, x, 60)
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, 60)
+    print(f"theta gpu={g['theta']!r} oracle={o['theta']!r}")
+    assert abs(g["theta"] - o["theta"]) <= 1e-12 * abs(o["theta"])
+    assert abs(g["resid"] - o["resid"]) <= 1e-3 * o["resid"] + 1e-12
+
+
+def test_no_reorth_recurrence():
+    m, x = W.config(2, reduced=10)
+    g = run(m, x, 40, reorth="none")
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, 40, reorth=False)
+    assert np.max(np.abs(g["alpha"][:15] - o["alpha"][:15])) < 1e-10
+    assert abs(g["theta"] - o["theta"]) <= 1e-10 * abs(o["theta"])
+
+
+def test_fp32_form_energy_error():
+    """c64 matvec inside the FP64 recurrence: ground energy against the FP64 oracle within 1e-5."""
+    m, x = W.config(3, reduced=3)                           # spin-1 3x3 torus, D = 19683
+    p = Plan(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device="cuda")
+    x128 = x.astype(np.complex128)
+    out = p.lanczos(th, torch.from_numpy(x128).cuda(), 80, precision="c_in_z")
+    torch.cuda.synchronize()
+    theta32 = float(out["result"][0])
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x128, 80)
+    err = abs(theta32 - o["theta"]) / abs(o["theta"])
+    print(f"fp32-form theta {theta32!r} fp64 oracle {o['theta']!r} rel err {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_breakdown_on_eigenvector():
+    m = W.ferrimagnetic_ring(8)
+    x = np.zeros(m.dim, dtype=np.complex128)
+    x[-1] = 1.0                                             # fully polarised: an eigenvector
+    g = run(m, x, 10)
+    assert g["steps"] == 1
+    assert abs(g["theta"] - mf.matvec(m, x)[-1].real) < 1e-14
+
+
+def test_zero_start_vector():
+    m = W.ferrimagnetic_ring(6)
+    g = run(m, np.zeros(m.dim, dtype=np.complex128), 5)
+    assert g["steps"] == 0 and np.isnan(g["theta"])
+
+
+def test_free_fermion_closed_form_large():
+    """XX chain N=20 in a field (D = 2^20): E0 = sum_{eps_k<0} eps_k - N h/2, no oracle involved."""
+    N, J, h = 20, 1.0, 0.25
+    m = W.xx_chain_in_field(N, J, h)
+    eps = J * np.cos(np.arange(1, N + 1) * np.pi / (N + 1)) + h
+    e0 = eps[eps < 0].sum() - N * h / 2
+    x = W.random_state(m.dim, np.random.default_rng(9))
+    g = run(m, x, 160)
+    print(f"E0 closed form {e0!r} gpu {g['theta']!r} resid {g['resid']:.2e}")
+    assert abs(g["theta"] - e0) <= max(g["resid"], 1e-11)
+    assert abs(g["theta"] - e0) < 1e-9

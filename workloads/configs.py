@@ -181,13 +181,13 @@ def random_model(rng, n_sites: int = 4, max_dim: int = 4096, n_params: int = 3, 
         re = float(rng.uniform(-1, 1))
         return complex(re, 0.0) if (self_adjoint and hermitian) else complex(re, float(rng.uniform(-1, 1)))
 
-    channels = [(a, b) for a in ops2 for b in ops2] if all_channels else []
+    channels = [(a, b) for a in ops2 for b in ops2] if (all_channels and n_sites > 1) else []
     for (oa, ob) in channels:
         i, j = rng.choice(n_sites, size=2, replace=False)
         sa = (oa == OP_Z and ob == OP_Z)
         add(Term(int(i), oa, int(j), ob, int(rng.integers(n_params)), weight(sa)))
     for _ in range(n_terms):
-        if rng.random() < 0.4:
+        if n_sites == 1 or rng.random() < 0.4:
             i = int(rng.integers(n_sites))
             op = int(rng.choice([OP_Z, OP_Z2, OP_RAISE, OP_LOWER]))
             add(Term(i, op, -1, OP_Z, int(rng.integers(n_params)), weight(op in (OP_Z, OP_Z2))))
