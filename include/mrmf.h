@@ -112,6 +112,33 @@ mrmf_status mrmf_plan_offsets(mrmf_plan plan, int64_t* out);
 mrmf_status mrmf_plan_workspace_bytes(mrmf_plan plan, size_t* bytes);
 mrmf_status mrmf_plan_upload(mrmf_plan plan, void* d_ws, size_t ws_bytes, mrmf_stream stream);
 
+/* Kernel selection for mrmf_matvec_z / mrmf_matvec_c (and everything that calls them).
+ *   MRMF_KERNEL_GENERIC     : one data-driven kernel for every plan (tables read at run time).
+ *   MRMF_KERNEL_SPECIALIZED : a kernel generated for this plan's structure (sites, channels, offsets and
+ *                             ladder tables as compile-time constants; couplings theta still read per
+ *                             call), compiled with hiprtc for the current device on first use; the
+ *                             index space is tiled by the low sites [N - inner_sites, N).
+ *   MRMF_KERNEL_AUTO        : specialized when the plan qualifies (D * element size < 2^32), else generic.
+ * inner_sites = 0 lets the library choose the tile.  Not thread-safe against concurrent calls on the
+ * same plan. */
+#define MRMF_KERNEL_AUTO 0
+#define MRMF_KERNEL_GENERIC 1
+#define MRMF_KERNEL_SPECIALIZED 2
+/* element types of the plain matvec */
+#define MRMF_DTYPE_Z 0 /* c128 */
+#define MRMF_DTYPE_C 1 /* c64  */
+mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites);
+/* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
+ * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only. */
+mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype);
+/* Host out[0..5] = (kernel kind used, inner sites, rows per tile T_in, block threads, grid blocks,
+ * tiles) for the given dtype, after mrmf_plan_prepare. */
+mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out);
+/* Source text of the specialized kernel for this plan and dtype, for inspection.  Host only.  Copies at
+ * most cap - 1 bytes plus a NUL into buf (cap = 0: nothing is copied) and stores the full length in
+ * *len.  MRMF_E_UNSUPPORTED when the plan does not qualify for the specialized kernel. */
+mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len);
+
 /* y = H(theta) x, plain FP64 form.  d_theta: double[n_params]; d_x, d_y: c128[D], 16-byte aligned,
  * must not overlap (the gather form reads x while writing y, Sec. II).  y is overwritten (App. A). */
 mrmf_status mrmf_matvec_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,

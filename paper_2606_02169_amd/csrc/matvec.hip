@@ -137,13 +137,18 @@ int generic_grid(int64_t D) {
 }
 
 template <typename R>
-mrmf_status matvec_generic(const mrmf_plan_t* p, const void* d_ws, const R* theta, const void* x,
-                           void* y, hipStream_t s, const int32_t* d_skip) {
+mrmf_status matvec_dispatch(mrmf_plan_t* p, const void* d_ws, const R* theta, const void* x, void* y,
+                            hipStream_t s, const int32_t* d_skip) {
     using C = typename Cx<R>::T;
     if (!p || !d_ws || !theta || !x || !y) return MRMF_E_INVALID_ARG;
     if (!aligned(d_ws, 256) || !aligned(x, sizeof(C)) || !aligned(y, sizeof(C))) return MRMF_E_INVALID_ARG;
     const size_t bytes = size_t(p->D) * sizeof(C);
     if (ranges_overlap(x, bytes, y, bytes)) return MRMF_E_INVALID_ARG;
+    if (p->kernel_mode != MRMF_KERNEL_GENERIC) {
+        const int dtype = sizeof(R) == 4 ? MRMF_DTYPE_C : MRMF_DTYPE_Z;
+        const mrmf_status st = spec_launch(p, dtype, theta, x, y, s, d_skip);
+        if (st == MRMF_OK || !(st == MRMF_E_UNSUPPORTED && p->kernel_mode == MRMF_KERNEL_AUTO)) return st;
+    }
     const PlanArgs a = plan_args(p, d_ws);
     const int grid = generic_grid(p->D);
     if (p->D <= int64_t(0xffffffffu))
@@ -157,14 +162,14 @@ mrmf_status matvec_generic(const mrmf_plan_t* p, const void* d_ws, const R* thet
 
 }  // namespace
 
-mrmf_status matvec_z_impl(const mrmf_plan_t* p, const void* d_ws, const double* theta, const void* x,
-                          void* y, hipStream_t s, const int32_t* d_skip) {
-    return matvec_generic<double>(p, d_ws, theta, x, y, s, d_skip);
+mrmf_status matvec_z_impl(mrmf_plan_t* p, const void* d_ws, const double* theta, const void* x, void* y,
+                          hipStream_t s, const int32_t* d_skip) {
+    return matvec_dispatch<double>(p, d_ws, theta, x, y, s, d_skip);
 }
 
-mrmf_status matvec_c_impl(const mrmf_plan_t* p, const void* d_ws, const float* theta, const void* x,
-                          void* y, hipStream_t s, const int32_t* d_skip) {
-    return matvec_generic<float>(p, d_ws, theta, x, y, s, d_skip);
+mrmf_status matvec_c_impl(mrmf_plan_t* p, const void* d_ws, const float* theta, const void* x, void* y,
+                          hipStream_t s, const int32_t* d_skip) {
+    return matvec_dispatch<float>(p, d_ws, theta, x, y, s, d_skip);
 }
 
 }  // namespace mrmf

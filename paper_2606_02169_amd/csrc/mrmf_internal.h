@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,18 @@ struct Tiling {
     int32_t T_in = 1;
 };
 
+// A kernel generated and compiled for one plan and element type (see jit.cpp).
+struct SpecKernel {
+    bool tried = false;
+    bool ok = false;
+    int device = -1;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int32_t k_in = 0, T_in = 0, block = 0, grid = 0;
+    int64_t n_tiles = 0;
+    std::string log;
+};
+
 }  // namespace mrmf
 
 struct mrmf_plan_t {
@@ -81,6 +94,12 @@ struct mrmf_plan_t {
     size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0;
     size_t ws_bytes = 0;
     mrmf::Tiling tiling;
+    // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type
+    int32_t kernel_mode = 0;
+    int32_t inner_pref = 0;
+    mrmf::SpecKernel spec[2];
+    std::mutex mtx;
+    ~mrmf_plan_t();
 };
 
 namespace mrmf {
@@ -116,10 +135,18 @@ inline mrmf_status hip_status(hipError_t e) { return e == hipSuccess ? MRMF_OK :
 // Launch-time error check (after hipLaunchKernelGGL).
 inline mrmf_status launch_status() { return hip_status(hipGetLastError()); }
 
+// Specialized kernels (jit.cpp).  spec_launch returns MRMF_E_UNSUPPORTED when the plan does not
+// qualify or compilation failed (the caller then uses the generic kernel under MRMF_KERNEL_AUTO).
+mrmf_status spec_prepare(mrmf_plan_t* p, int dtype);
+mrmf_status spec_launch(mrmf_plan_t* p, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
+                        const int32_t* d_skip);
+
 // Entry points shared between translation units.
-mrmf_status matvec_z_impl(const mrmf_plan_t* p, const void* d_ws, const double* theta,
+mrmf_status matvec_z_impl(mrmf_plan_t* p, const void* d_ws, const double* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
-mrmf_status matvec_c_impl(const mrmf_plan_t* p, const void* d_ws, const float* theta,
+mrmf_status matvec_c_impl(mrmf_plan_t* p, const void* d_ws, const float* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
+// Generated source of the specialized kernel (no device needed; arch only matters for compilation).
+std::string spec_source(const mrmf_plan_t* p, int dtype, int* k_in, int* T_in);
 
 }  // namespace mrmf

@@ -165,3 +165,31 @@ class Plan:
         if keep_basis:
             out["V"] = V
         return out
+
+    # ------------------------------------------------------------------ kernel selection
+    KERNELS = {"auto": 0, "generic": 1, "specialized": 2}
+
+    def set_kernel(self, kind: str = "auto", inner_sites: int = 0):
+        """Choose the matvec kernel: "generic", "specialized" (plan-specific, compiled on first use) or
+        "auto"; inner_sites = 0 lets the library pick the tile."""
+        L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites))
+
+    def prepare(self, dtype=torch.complex128):
+        """Compile and load the kernel matvec will use for this element type (synchronous)."""
+        dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
+        L.call("mrmf_plan_prepare", self._handle, dt)
+
+    def kernel_info(self, dtype=torch.complex128) -> dict:
+        dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
+        out = (ctypes.c_int32 * 6)()
+        L.call("mrmf_plan_kernel_info", self._handle, dt, out)
+        kind = {0: "auto", 1: "generic", 2: "specialized"}[out[0]]
+        return dict(kind=kind, inner_sites=out[1], rows_per_tile=out[2], block=out[3], grid=out[4], tiles=out[5])
+
+    def kernel_source(self, dtype=torch.complex128) -> str:
+        dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
+        n = ctypes.c_size_t()
+        L.call("mrmf_plan_kernel_source", self._handle, dt, None, 0, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        L.call("mrmf_plan_kernel_source", self._handle, dt, buf, n.value + 1, ctypes.byref(n))
+        return buf.value.decode()
