@@ -116,23 +116,25 @@ mrmf_status mrmf_plan_upload(mrmf_plan plan, void* d_ws, size_t ws_bytes, mrmf_s
  *   MRMF_KERNEL_GENERIC     : one data-driven kernel for every plan (tables read at run time).
  *   MRMF_KERNEL_SPECIALIZED : a kernel generated for this plan's structure (sites, channels, offsets and
  *                             ladder tables as compile-time constants; couplings theta still read per
- *                             call), compiled with hiprtc for the current device on first use; the
- *                             index space is tiled by the low sites [N - inner_sites, N).
- *   MRMF_KERNEL_AUTO        : specialized when the plan qualifies (D * element size < 2^32), else generic.
- * inner_sites = 0 lets the library choose the tile.  Not thread-safe against concurrent calls on the
- * same plan. */
+ *                             call), compiled with hiprtc for the current device on first use.  Each
+ *                             thread owns one row of the block of the low `inner_sites` sites and
+ *                             handles every digit combination of the next `unrolled_sites` sites.
+ *   MRMF_KERNEL_AUTO        : specialized when the plan qualifies (all buffer offsets, about
+ *                             2 * D * element size, below 2^31 bytes), else generic.
+ * inner_sites = 0 and unrolled_sites = -1 let the library choose.  Not thread-safe against concurrent
+ * calls on the same plan. */
 #define MRMF_KERNEL_AUTO 0
 #define MRMF_KERNEL_GENERIC 1
 #define MRMF_KERNEL_SPECIALIZED 2
 /* element types of the plain matvec */
 #define MRMF_DTYPE_Z 0 /* c128 */
 #define MRMF_DTYPE_C 1 /* c64  */
-mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites);
+mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites, int32_t unrolled_sites);
 /* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
  * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only. */
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype);
-/* Host out[0..5] = (kernel kind used, inner sites, rows per tile T_in, block threads, grid blocks,
- * tiles) for the given dtype, after mrmf_plan_prepare. */
+/* Host out[0..7] = (kernel kind used, inner sites, rows per block T_in, block threads, grid blocks,
+ * super-tiles, unrolled sites, unrolled copies) for the given dtype, after mrmf_plan_prepare. */
 mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out);
 /* Source text of the specialized kernel for this plan and dtype, for inspection.  Host only.  Copies at
  * most cap - 1 bytes plus a NUL into buf (cap = 0: nothing is copied) and stores the full length in

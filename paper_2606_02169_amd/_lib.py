@@ -63,7 +63,7 @@ SIGNATURES = {
     "mrmf_matvec_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mrmf_matvec_c": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mrmf_debug_sources": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp]),
-    "mrmf_plan_set_kernel": (_i32, [_vp, _i32, _i32]),
+    "mrmf_plan_set_kernel": (_i32, [_vp, _i32, _i32, _i32]),
     "mrmf_plan_prepare": (_i32, [_vp, _i32]),
     "mrmf_plan_kernel_info": (_i32, [_vp, _i32, _P(_i32)]),
     "mrmf_plan_kernel_source": (_i32, [_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)]),

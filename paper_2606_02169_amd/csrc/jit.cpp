@@ -1,22 +1,27 @@
 // Plan-specialized matvec kernels, generated as HIP source and compiled with hiprtc for the current
 // device.  The generated kernel applies the same map as the generic one (target-driven gather, Sec. II;
 // digits by Eq. decode; channels by Eqs. src_digit_two_site / sourceoffset; ladder factors of App. A,
-// App. B, App. C) but with the plan's structure baked in:
+// App. B, App. C) with the plan's structure baked in.
 //
-//  * the index space is tiled: the low sites [k_in, N) form an inner block of T_in consecutive rows,
-//    one thread per inner row; the outer sites' digits are the same for the whole tile, so they are
-//    computed once per tile on the scalar unit from the tile number (compile-time divisors);
-//  * a channel touching only outer sites is admissible for the whole tile or for none of it: one
-//    uniform branch, one uniform coefficient;
-//  * a channel touching inner sites gets its per-row factor (0 where inadmissible) once per thread,
-//    kept in a register across all the tiles the persistent block visits;
-//  * x is read through a buffer descriptor: the per-row part of every address (r * element size) is one
-//    register fixed for the whole kernel and the per-channel part (F0 - Delta) is a scalar, so the
-//    gather issues no vector address arithmetic; y is written with non-temporal stores so it does not
-//    evict x from the caches;
-//  * tiles are dealt to blocks so that the 8 XCDs each sweep a contiguous stretch of tiles at a time.
+// Index space.  The sites split into three groups, most significant first:
+//   uniform  [0, k_u)     digits fixed for a whole super-tile (scalar registers)
+//   unrolled [k_u, k_in)  P_U digit combinations handled by every thread, one unrolled copy each, so
+//                         these digits are compile-time constants inside a copy
+//   inner    [k_in, N)    T_in rows, one per thread
+// A super-tile is the P_U * T_in consecutive rows sharing the uniform digits.  Persistent blocks sweep
+// the super-tiles; tiles are dealt so that the 8 XCDs each work on a contiguous stretch at a time.
+//
+// Terms.  A term touching only unrolled/inner sites is "static": its coefficient per thread and copy is
+// fixed for the whole kernel (registers) and its source row lies inside the super-tile, whose x is staged
+// in LDS (zeroed halo rows absorb inadmissible lanes, whose coefficient is 0).  A term touching only
+// uniform sites is "uniform"; one touching both is "mixed".  Their uniform parts (theta-weighted ladder
+// factors) are computed once per super-tile by a few lanes into an LDS table; their admissibility is
+// decided on the scalar unit, and an inadmissible load gets an out-of-range buffer offset (no memory
+// access, value 0), so every load is issued unconditionally and the loads pipeline.  y is written with
+// non-temporal buffer stores.
 #include <hip/hiprtc.h>
 
+#include <array>
 #include <cinttypes>
 #include <cmath>
 #include <cstdio>
@@ -24,11 +29,14 @@
 #include <map>
 #include <set>
 #include <sstream>
+#include <tuple>
 
 #include "mrmf_internal.h"
 
 namespace mrmf {
 namespace {
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 std::string lit(double v, bool f32) {
     char buf[64];
@@ -36,6 +44,12 @@ std::string lit(double v, bool f32) {
         std::snprintf(buf, sizeof buf, "%af", static_cast<double>(static_cast<float>(v)));
     else
         std::snprintf(buf, sizeof buf, "%a", v);
+    return buf;
+}
+
+std::string ulit(uint64_t v) {
+    char buf[32];
+    std::snprintf(buf, sizeof buf, "%" PRIu64 "ull", v);
     return buf;
 }
 
@@ -54,351 +68,548 @@ std::vector<double> factor_table(const mrmf_plan_t* p, int site, int op) {
     return t;
 }
 
-// integer admissibility test of a uniform digit for a ladder operator ("" when always admissible)
-std::string adm_expr(const mrmf_plan_t* p, int site, int op) {
-    if (op == MRMF_OP_RAISE) return "n" + std::to_string(site) + " >= 1u";
-    if (op == MRMF_OP_LOWER) return "n" + std::to_string(site) + " <= " + std::to_string(p->d[site] - 2) + "u";
-    return "";
-}
+// ceil(2^64 / d): floor(n / d) = hi64(magic * n) for every n < 2^32
+uint64_t magic_of(uint64_t d) { return d <= 1 ? 0 : ~uint64_t(0) / d + 1; }
 
 struct Gen {
     const mrmf_plan_t* p;
     bool f32;
-    int k_in, T_in, block;
-    int64_t n_tiles;
-    std::set<std::pair<int, int>> arrays;  // (site, op) tables emitted as constant arrays
-    std::set<std::string> arrays_named;
-    std::ostringstream pre;                // constant arrays
+    Tile tl;
+    int block;
+    int64_t n_st;
 
-    bool inner(int site) const { return site >= k_in; }
-    // 0: every site of the term inner, 1: every site outer, 2: one inner and one outer site
-    int cls(int a, int b) const {
-        if (b < 0) return inner(a) ? 0 : 1;
-        if (inner(a) && inner(b)) return 0;
-        if (!inner(a) && !inner(b)) return 1;
+    int SZ() const { return f32 ? 8 : 16; }
+    bool is_inner(int s) const { return s >= tl.k_in; }
+    bool is_unrolled(int s) const { return s >= tl.k_u && s < tl.k_in; }
+    bool is_static(int s) const { return s >= tl.k_u; }
+    int64_t ST() const { return tl.T_in * tl.P_U; }
+    int udigit(int s, int64_t j) const { return static_cast<int>((j / (p->M[s] / tl.T_in)) % p->d[s]); }
+    int kind(int a, int b) const {  // 0 static, 1 uniform, 2 mixed
+        const bool sa = is_static(a);
+        if (b < 0) return sa ? 0 : 1;
+        const bool sb = is_static(b);
+        if (sa && sb) return 0;
+        if (!sa && !sb) return 1;
         return 2;
     }
+    bool has_inner(int a, int b) const { return is_inner(a) || (b >= 0 && is_inner(b)); }
+    bool has_unrolled(int a, int b) const { return is_unrolled(a) || (b >= 0 && is_unrolled(b)); }
 
-    // constant array holding a table (emitted once)
-    // all constant tables live in one array K[] (one base address for every scalar load);
-    // carray returns the offset of a table, appending it on first use
-    std::map<std::string, size_t> pool_index;
+    // constant pool (factor tables), shared by every lookup
     std::vector<double> pool;
-    size_t carray(const std::string& name, const std::vector<double>& t) {
-        auto it = pool_index.find(name);
+    std::map<std::string, size_t> pool_index;
+    size_t pool_add(const std::string& key, const std::vector<double>& t) {
+        auto it = pool_index.find(key);
         if (it != pool_index.end()) return it->second;
         const size_t off = pool.size();
         pool.insert(pool.end(), t.begin(), t.end());
-        pool_index[name] = off;
+        pool_index[key] = off;
         return off;
     }
-    // factor of (site, op) at a tile-uniform digit: a scalar load from the constant pool
-    std::string fac_uni(int site, int op) {
-        const size_t off = carray("U" + std::to_string(site) + "_" + std::to_string(op), factor_table(p, site, op));
-        return "K[" + std::to_string(off) + "u + n" + std::to_string(site) + "]";
-    }
-    // product of the two factors of an outer two-site term, one table indexed by both digits
-    std::string fac_uni2(int a, int opa, int b, int opb) {
-        const std::vector<double> ta = factor_table(p, a, opa), tb = factor_table(p, b, opb);
-        std::vector<double> t(ta.size() * tb.size());
-        for (size_t i = 0; i < ta.size(); ++i)
-            for (size_t j = 0; j < tb.size(); ++j) t[i * tb.size() + j] = ta[i] * tb[j];
-        const std::string name = "P" + std::to_string(a) + "_" + std::to_string(opa) + "_" + std::to_string(b) + "_" +
-                                 std::to_string(opb);
-        const size_t off = carray(name, t);
-        return "K[" + std::to_string(off) + "u + n" + std::to_string(a) + " * " + std::to_string(tb.size()) + "u + n" +
-               std::to_string(b) + "]";
-    }
-    // expression for the factor of (site, op) at the digit variable n<site>
-    std::string fac(int site, int op) {
-        const std::vector<double> t = factor_table(p, site, op);
-        const std::string n = "n" + std::to_string(site);
+    size_t ftab(int s, int op) { return pool_add("F" + std::to_string(s) + "_" + std::to_string(op), factor_table(p, s, op)); }
+
+    // per-lane factor of an inner site (select chain for small d, pool lookup otherwise)
+    std::string lane_fac(int s, int op) {
+        const std::vector<double> t = factor_table(p, s, op);
+        const std::string n = "n" + std::to_string(s);
         const int d = static_cast<int>(t.size());
         if (d <= 4) {
             std::string e = lit(t[d - 1], f32);
-            for (int i = d - 2; i >= 0; --i) e = "(" + n + " == " + std::to_string(i) + "u ? " + lit(t[i], f32) + " : " + e + ")";
+            for (int i = d - 2; i >= 0; --i)
+                e = "(" + n + " == " + std::to_string(i) + "u ? " + lit(t[i], f32) + " : " + e + ")";
             return e;
         }
-        const std::string name = "T" + std::to_string(site) + "_" + std::to_string(op);
-        if (!arrays.count({site, op})) {
-            arrays.insert({site, op});
-            pre << "__constant__ R " << name << "[" << d << "] = {";
-            for (int i = 0; i < d; ++i) pre << (i ? ", " : "") << lit(t[i], f32);
-            pre << "};\n";
-        }
-        return name + "[" + n + "]";
+        return "K[" + std::to_string(ftab(s, op)) + "u + " + n + "]";
+    }
+    // static part of a term in copy j: compile-time factor of unrolled sites and lane expression
+    std::pair<double, std::string> static_part(int a, int opa, int b, int opb, int64_t j) {
+        double c = 1.0;
+        std::string e;
+        auto add = [&](int s, int op) {
+            if (s < 0 || !is_static(s)) return;
+            if (is_unrolled(s)) {
+                c *= factor_table(p, s, op)[udigit(s, j)];
+            } else {
+                const std::string f = lane_fac(s, op);
+                e = e.empty() ? f : e + " * " + f;
+            }
+        };
+        add(a, opa);
+        add(b, opb);
+        return {c, e};
+    }
+    std::string admit_uniform(int a, int opa, int b, int opb) const {
+        std::string c;
+        auto add = [&](int s, int op) {
+            if (s < 0 || is_static(s)) return;
+            std::string e;
+            if (op == MRMF_OP_RAISE) e = "n" + std::to_string(s) + " >= 1u";
+            if (op == MRMF_OP_LOWER) e = "n" + std::to_string(s) + " <= " + std::to_string(p->d[s] - 2) + "u";
+            if (!e.empty()) c = c.empty() ? e : c + " && " + e;
+        };
+        add(a, opa);
+        add(b, opb);
+        return c.empty() ? "true" : c;
     }
 
     std::string source() {
         const mrmf_plan_t& P = *p;
-        const int SZ = f32 ? 8 : 16;
-        const int64_t shift = int64_t(T_in) * SZ;
-        const int nch = static_cast<int>(P.chans.size());
-        const int ndg = static_cast<int>(P.diags.size());
-        std::ostringstream o;
-        std::set<int> used_sites, used_params;
-        for (const auto& c : P.chans) {
-            used_sites.insert(c.a);
-            if (c.b >= 0) used_sites.insert(c.b);
-            used_params.insert(c.param);
-        }
-        for (const auto& g : P.diags) {
-            used_sites.insert(g.a);
-            if (g.b >= 0) used_sites.insert(g.b);
-            used_params.insert(g.param);
-        }
-        bool complex_w = false;
-        for (const auto& c : P.chans) complex_w |= c.wi != 0.0;
-        for (const auto& g : P.diags) complex_w |= g.wi != 0.0;
-        // LDS halo: inner channels read the tile's own x at r - Delta, Delta < T_in
-        int64_t pad = 0;
-        for (const auto& c : P.chans)
-            if (cls(c.a, c.b) == 0) pad = std::max<int64_t>(pad, c.delta < 0 ? -c.delta : c.delta);
-        const bool use_lds = pad > 0;
-        const int64_t rows_lds = T_in + 2 * pad + 1;  // halo, tile, halo, one slot idle lanes write to
-        std::vector<int> cI, cO, cM;  // channels by class: inner, outer, mixed
+        const int sz = SZ();
+        const int nch = static_cast<int>(P.chans.size()), ndg = static_cast<int>(P.diags.size());
+        const int64_t T = tl.T_in, PU = tl.P_U, st = ST();
+        bool cplx = false;
+        for (const auto& c : P.chans) cplx |= c.wi != 0.0;
+        for (const auto& g : P.diags) cplx |= g.wi != 0.0;
+
+        std::vector<int> cS, cU, cM, gS, gU, gM;
         for (int c = 0; c < nch; ++c) {
-            const int k = cls(P.chans[c].a, P.chans[c].b);
-            (k == 0 ? cI : k == 1 ? cO : cM).push_back(c);
+            const int k = kind(P.chans[c].a, P.chans[c].b);
+            (k == 0 ? cS : k == 1 ? cU : cM).push_back(c);
+        }
+        for (int g = 0; g < ndg; ++g) {
+            const int k = kind(P.diags[g].a, P.diags[g].b);
+            (k == 0 ? gS : k == 1 ? gU : gM).push_back(g);
+        }
+        int64_t dmax = 0, halo = 0;
+        for (const auto& c : P.chans) dmax = std::max<int64_t>(dmax, c.delta);
+        for (int c : cS) {  // inner part of Delta; the unrolled part moves between copies in the super-tile
+            const auto& ch = P.chans[c];
+            int64_t di = 0;
+            if (is_inner(ch.a)) di += int64_t(ch.qa) * P.M[ch.a];
+            if (ch.b >= 0 && is_inner(ch.b)) di += int64_t(ch.qb) * P.M[ch.b];
+            halo = std::max<int64_t>(halo, di < 0 ? -di : di);
+        }
+        // buffer base shifted down by `shift` bytes so every scalar offset is non-negative
+        const int64_t shift = (dmax + T) * sz;
+        const int64_t nrec = (P.D + dmax + T) * sz;
+        const bool use_lds = !cS.empty();
+        const int64_t xrows = st + 2 * halo + 1;  // halo, super-tile, halo, one slot idle lanes write to
+        const bool dbuf = use_lds && 2 * xrows * sz <= 49152;
+        // uniform-part table items: uniform channels, mixed channels, mixed diagonal terms
+        std::vector<std::pair<int, int>> items;
+        for (int c : cU) items.push_back({0, c});
+        for (int c : cM) items.push_back({0, c});
+        for (int g : gM) items.push_back({1, g});
+        const int nit = static_cast<int>(items.size()), nsum = static_cast<int>(gU.size());
+        const int nw = block / 64;
+        const int twaves = std::min(nw, std::max((nit + 63) / 64, (nsum + 63) / 64));
+        std::map<int, int> item_of_chan, item_of_diag;
+        for (int i = 0; i < nit; ++i) (items[i].first == 0 ? item_of_chan : item_of_diag)[items[i].second] = i;
+
+        std::ostringstream pre, o;
+        // per-item constants (global tables): for up to two uniform sites, the division magic of the
+        // site multiplier counted in super-tiles, the dimension and its magic, the factor-table offset
+        // (an absent site has quotient magic 1, so its digit is 0, dimension 1 and a 1.0 entry), the parameter
+        // and the weight
+        const size_t one = pool_add("ONE", {1.0});
+        auto emit_items = [&](const std::string& pfx, const std::vector<std::tuple<int, int, int, int, int, double, double>>& its) {
+            const int n = std::max<int>(1, its.size());
+            std::ostringstream mam, da, dam, ta, mbm, db, dbm, tb, pr, wr, wi;
+            for (size_t i = 0; i < its.size(); ++i) {
+                std::vector<std::array<uint64_t, 3>> ss;  // (multiplier in super-tiles, d, table)
+                for (auto so : {std::make_pair(std::get<0>(its[i]), std::get<1>(its[i])),
+                                std::make_pair(std::get<2>(its[i]), std::get<3>(its[i]))}) {
+                    if (so.first < 0 || is_static(so.first)) continue;
+                    ss.push_back({static_cast<uint64_t>(P.M[so.first] / st), static_cast<uint64_t>(P.d[so.first]),
+                                  static_cast<uint64_t>(ftab(so.first, so.second))});
+                }
+                // an absent site has multiplier 0: magic 1 makes its quotient, hence its digit, 0
+                while (ss.size() < 2) ss.push_back({0, 1, static_cast<uint64_t>(one)});
+                const char* sep = i ? ", " : "";
+                mam << sep << ulit(ss[0][0] == 0 ? 1 : ss[0][0] == 1 ? 0 : magic_of(ss[0][0]));
+                da << sep << ss[0][1] << "u";
+                dam << sep << ulit(magic_of(ss[0][1]));
+                ta << sep << ss[0][2] << "u";
+                mbm << sep << ulit(ss[1][0] == 0 ? 1 : ss[1][0] == 1 ? 0 : magic_of(ss[1][0]));
+                db << sep << ss[1][1] << "u";
+                dbm << sep << ulit(magic_of(ss[1][1]));
+                tb << sep << ss[1][2] << "u";
+                pr << sep << std::get<4>(its[i]);
+                wr << sep << lit(std::get<5>(its[i]), f32);
+                wi << sep << lit(std::get<6>(its[i]), f32);
+            }
+            auto arr = [&](const char* ty, const char* nm, std::ostringstream& v) {
+                const std::string s = v.str();
+                pre << "__constant__ " << ty << " " << pfx << nm << "[" << n << "] = {" << (s.empty() ? "0" : s) << "};\n";
+            };
+            arr("unsigned long long", "mam", mam);
+            arr("unsigned", "da", da);
+            arr("unsigned long long", "dam", dam);
+            arr("unsigned", "ta", ta);
+            arr("unsigned long long", "mbm", mbm);
+            arr("unsigned", "db", db);
+            arr("unsigned long long", "dbm", dbm);
+            arr("unsigned", "tb", tb);
+            arr("int", "pr", pr);
+            arr("R", "wr", wr);
+            arr("R", "wi", wi);
+        };
+        if (twaves > 0) {
+            std::vector<std::tuple<int, int, int, int, int, double, double>> its, sums;
+            for (const auto& it : items) {
+                if (it.first == 0) {
+                    const auto& ch = P.chans[it.second];
+                    its.emplace_back(ch.a, ch.opa, ch.b, ch.opb, ch.param, ch.wr, ch.wi);
+                } else {
+                    const auto& dg = P.diags[it.second];
+                    its.emplace_back(dg.a, dg.opa, dg.b, dg.opb, dg.param, dg.wr, dg.wi);
+                }
+            }
+            for (int g : gU) {
+                const auto& dg = P.diags[g];
+                sums.emplace_back(dg.a, dg.opa, dg.b, dg.opb, dg.param, dg.wr, dg.wi);
+            }
+            emit_items("I", its);
+            emit_items("Q", sums);
         }
 
+        o << "__device__ __forceinline__ unsigned dig(unsigned t, unsigned long long mm, unsigned d, unsigned long long dm) {\n"
+          << "  const unsigned q = mm ? (unsigned)__umul64hi(mm, (unsigned long long)t) : t;\n"
+          << "  return q - (unsigned)__umul64hi(dm, (unsigned long long)q) * d;\n}\n";
         o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void mrmf_spec(const R* __restrict__ theta,\n"
           << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
           << "  if (skip != nullptr && *skip != 0) return;\n";
-        if (use_lds)
-            o << "  __shared__ C lds[2 * " << rows_lds << "];\n"
-              << "  for (unsigned i = threadIdx.x; i < " << pad << "u; i += " << block << "u) {\n"
-              << "    const C z = {(R)0, (R)0};\n"
-              << "    lds[i] = z; lds[" << pad + T_in << "u + i] = z; lds[" << rows_lds << "u + i] = z; lds["
-              << rows_lds + pad + T_in << "u + i] = z;\n  }\n";
-        // lanes past the tile (r >= T_in) run the same code: their loads and stores use an out-of-range
-        // buffer offset (no memory access, loads return 0) and their coefficients are 0
-        o << "  const unsigned r0 = threadIdx.x;\n"
-          << "  const bool act = r0 < " << T_in << "u;\n"
-          << "  const unsigned r = act ? r0 : 0u;\n"
+        if (use_lds) o << "  __shared__ C xl[" << (dbuf ? 2 : 1) * xrows << "];\n";
+        if (nit > 0) {
+            o << "  __shared__ R tr[2][" << nit << "];\n";
+            if (cplx) o << "  __shared__ R ti[2][" << nit << "];\n";
+        }
+        if (nsum > 0) {
+            o << "  __shared__ R dsr[2][" << twaves << "];\n";
+            if (cplx) o << "  __shared__ R dsi[2][" << twaves << "];\n";
+        }
+        if (twaves > 0) o << "  __shared__ R Kl[KN_ALLOC];\n";  // the pool is complete only after codegen
+        o << "  const unsigned tid = threadIdx.x;\n"
+          << "  const bool act = tid < " << T << "u;\n"
+          << "  const unsigned r = act ? tid : 0u;\n"
           << "  const unsigned OOB = 0x80000000u;\n"
-          << "  const unsigned voff = act ? r * " << SZ << "u : OOB;\n";
-        for (int i : used_sites)
-            if (inner(i))
-                o << "  const unsigned n" << i << " = (r / " << P.M[i] << "u) % " << P.d[i] << "u;\n";
+          << "  const unsigned voff = act ? r * " << sz << "u : OOB;\n";
+        if (use_lds) {
+            o << "  for (unsigned i = tid; i < " << halo << "u; i += " << block << "u) {\n"
+              << "    const C z = {(R)0, (R)0};\n";
+            for (int b = 0; b < (dbuf ? 2 : 1); ++b)
+                o << "    xl[" << b * xrows << "u + i] = z; xl[" << b * xrows + halo + st << "u + i] = z;\n";
+            o << "  }\n";
+            for (int64_t j = 0; j < PU; ++j)
+                o << "  const unsigned w" << j << " = act ? " << halo + j * T << "u + r : " << xrows - 1 << "u;\n";
+        }
+        if (twaves > 0)
+            o << "  for (unsigned i = tid; i < KN; i += " << block << "u) Kl[i] = K[i];\n";
+        std::set<int> lane_sites, used_params;
+        for (const auto& c : P.chans) {
+            if (is_inner(c.a)) lane_sites.insert(c.a);
+            if (c.b >= 0 && is_inner(c.b)) lane_sites.insert(c.b);
+            used_params.insert(c.param);
+        }
+        for (const auto& g : P.diags) {
+            if (is_inner(g.a)) lane_sites.insert(g.a);
+            if (g.b >= 0 && is_inner(g.b)) lane_sites.insert(g.b);
+            used_params.insert(g.param);
+        }
+        for (int s : lane_sites) o << "  const unsigned n" << s << " = (r / " << P.M[s] << "u) % " << P.d[s] << "u;\n";
         for (int q : used_params) o << "  const R th" << q << " = theta[" << q << "];\n";
-        for (int c = 0; c < nch; ++c) {
+        auto wexpr = [&](int param, double w) { return "th" + std::to_string(param) + " * " + lit(w, f32); };
+
+        // static channel coefficients per copy (registers)
+        std::map<std::pair<int, int64_t>, std::string> kS;
+        for (int c : cS) {
             const auto& ch = P.chans[c];
-            o << "  const R cw" << c << "r = th" << ch.param << " * " << lit(ch.wr, f32) << ";\n";
-            if (complex_w) o << "  const R cw" << c << "i = th" << ch.param << " * " << lit(ch.wi, f32) << ";\n";
-        }
-        for (int g = 0; g < ndg; ++g) {
-            const auto& dg = P.diags[g];
-            o << "  const R dw" << g << "r = th" << dg.param << " * " << lit(dg.wr, f32) << ";\n";
-            if (complex_w) o << "  const R dw" << g << "i = th" << dg.param << " * " << lit(dg.wi, f32) << ";\n";
-        }
-        // per-thread parts, fixed for every tile: the inner diagonal, the inner factor of mixed terms,
-        // and the whole coefficient of inner channels (0 where the source digit is out of range)
-        o << "  R dIr = 0, dIi = 0;\n";
-        for (int g = 0; g < ndg; ++g) {
-            const auto& dg = P.diags[g];
-            const int k = cls(dg.a, dg.b);
-            if (k == 0) {
-                std::string f = fac(dg.a, dg.opa);
-                if (dg.b >= 0) f += " * " + fac(dg.b, dg.opb);
-                o << "  { const R f = " << f << "; dIr += dw" << g << "r * f;";
-                if (complex_w) o << " dIi += dw" << g << "i * f;";
-                o << " }\n";
-            } else if (k == 2) {
-                const bool ia = inner(dg.a);
-                o << "  const R fz" << g << " = " << fac(ia ? dg.a : dg.b, ia ? dg.opa : dg.opb) << ";\n";
+            const bool unr = has_unrolled(ch.a, ch.b);
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(ch.a, ch.opa, ch.b, ch.opb, j);
+                if (sp.first == 0.0) continue;
+                if (!unr && j > 0 && kS.count({c, 0})) {
+                    kS[{c, j}] = kS[{c, 0}];
+                    continue;
+                }
+                const std::string nm = "k" + std::to_string(c) + "_" + std::to_string(j);
+                const std::string le = sp.second.empty() ? std::string("(R)1") : sp.second;
+                o << "  const R " << nm << "r = act ? " << wexpr(ch.param, ch.wr) << " * " << lit(sp.first, f32) << " * "
+                  << le << " : (R)0;\n";
+                if (cplx)
+                    o << "  const R " << nm << "i = act ? " << wexpr(ch.param, ch.wi) << " * " << lit(sp.first, f32)
+                      << " * " << le << " : (R)0;\n";
+                kS[{c, j}] = nm;
             }
         }
-        for (int c : cI) {
-            const auto& ch = P.chans[c];
-            std::string f = fac(ch.a, ch.opa);
-            if (ch.b >= 0) f += " * " + fac(ch.b, ch.opb);
-            o << "  const R k" << c << "r = act ? cw" << c << "r * " << f << " : (R)0;\n";
-            if (complex_w) o << "  const R k" << c << "i = act ? cw" << c << "i * " << f << " : (R)0;\n";
-        }
+        // mixed channels: static factor per copy; lane admissibility folded into the buffer offset
+        std::map<std::pair<int, int64_t>, std::string> fM;
         for (int c : cM) {
             const auto& ch = P.chans[c];
-            const bool ia = inner(ch.a);
-            o << "  const R f" << c << " = " << fac(ia ? ch.a : ch.b, ia ? ch.opa : ch.opb) << ";\n"
-              << "  const unsigned vo" << c << " = (f" << c << " != (R)0) ? voff : OOB;\n";
+            std::string lane_e;
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(ch.a, ch.opa, ch.b, ch.opb, j);
+                if (sp.first == 0.0) continue;
+                if (!sp.second.empty()) lane_e = sp.second;
+                const std::string nm = "f" + std::to_string(c) + "_" + std::to_string(j);
+                o << "  const R " << nm << " = " << lit(sp.first, f32) << " * " << (sp.second.empty() ? "(R)1" : sp.second)
+                  << ";\n";
+                fM[{c, j}] = nm;
+            }
+            if (has_inner(ch.a, ch.b) && !lane_e.empty())
+                o << "  const unsigned vo" << c << " = (" << lane_e << " != (R)0) ? voff : OOB;\n";
         }
-        o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - "
-          << shift << "ll), (short)0, " << (P.D * SZ + shift) << ", 0x00020000);\n"
-          << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - "
-          << shift << "ll), (short)0, " << (P.D * SZ + shift) << ", 0x00020000);\n";
-        if (use_lds) o << "  const unsigned widx = act ? " << pad << "u + r : " << rows_lds - 1 << "u;\n";
-        if (use_lds) o << "  __syncthreads();\n";
-        o << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
+        // diagonal: static part per copy; static factor of mixed terms per copy
+        for (int64_t j = 0; j < PU; ++j) {
+            o << "  R dS" << j << "r = 0, dS" << j << "i = 0;\n";
+            for (int g : gS) {
+                const auto& dg = P.diags[g];
+                const auto sp = static_part(dg.a, dg.opa, dg.b, dg.opb, j);
+                if (sp.first == 0.0) continue;
+                const std::string le = sp.second.empty() ? std::string("(R)1") : sp.second;
+                o << "  { const R f = " << lit(sp.first, f32) << " * " << le << "; dS" << j << "r += "
+                  << wexpr(dg.param, dg.wr) << " * f;";
+                if (cplx) o << " dS" << j << "i += " << wexpr(dg.param, dg.wi) << " * f;";
+                o << " }\n";
+            }
+        }
+        std::map<std::pair<int, int64_t>, std::string> fD;
+        for (int g : gM) {
+            const auto& dg = P.diags[g];
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(dg.a, dg.opa, dg.b, dg.opb, j);
+                if (sp.first == 0.0) continue;
+                const std::string nm = "z" + std::to_string(g) + "_" + std::to_string(j);
+                o << "  const R " << nm << " = " << lit(sp.first, f32) << " * " << (sp.second.empty() ? "(R)1" : sp.second)
+                  << ";\n";
+                fD[{g, j}] = nm;
+            }
+        }
+        // table lanes: lane l of wave w owns item 64 w + l and uniform diagonal term 64 w + l
+        if (twaves > 0) {
+            o << "  const unsigned wv = tid >> 6, ln = tid & 63u, it = tid;\n"
+              << "  const bool has_it = it < " << nit << "u, has_q = it < " << nsum << "u;\n"
+              << "  const unsigned ii = has_it ? it : 0u, qq = has_q ? it : 0u;\n"
+              << "  const unsigned long long i_mam = Imam[ii], i_dam = Idam[ii], i_mbm = Imbm[ii], i_dbm = Idbm[ii];\n"
+              << "  const unsigned i_da = Ida[ii], i_db = Idb[ii], i_ta = Ita[ii], i_tb = Itb[ii];\n"
+              << "  const R i_wr = theta[Ipr[ii]] * Iwr[ii], i_wi = theta[Ipr[ii]] * Iwi[ii];\n"
+              << "  const unsigned long long q_mam = Qmam[qq], q_dam = Qdam[qq], q_mbm = Qmbm[qq], q_dbm = Qdbm[qq];\n"
+              << "  const unsigned q_da = Qda[qq], q_db = Qdb[qq], q_ta = Qta[qq], q_tb = Qtb[qq];\n"
+              << "  const R q_wr = has_q ? theta[Qpr[qq]] * Qwr[qq] : (R)0, q_wi = has_q ? theta[Qpr[qq]] * Qwi[qq] : (R)0;\n";
+        }
+        o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
+          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+          << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
+          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+          << "  __syncthreads();\n"
+          << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
           << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
           << "  unsigned par = 0u;\n"
-          << "  for (unsigned t = v; t < " << n_tiles << "u; t += G) {\n";
-        for (int i : used_sites)
-            if (!inner(i))
-                o << "    const unsigned n" << i << " = (t / " << (P.M[i] / T_in) << "u) % " << P.d[i] << "u;\n";
-        o << "    const unsigned F0 = t * " << T_in << "u;\n"
-          << "    const C xf = LD(xs, voff, F0 * " << SZ << "u + " << shift << "u);\n";
-
-        auto soff = [&](int64_t delta) {
+          << "  for (unsigned t = v; t < " << n_st << "u; t += G) {\n";
+        std::set<int> uni_sites;
+        for (const auto& c : P.chans) {
+            if (!is_static(c.a)) uni_sites.insert(c.a);
+            if (c.b >= 0 && !is_static(c.b)) uni_sites.insert(c.b);
+        }
+        for (int s : uni_sites) o << "    const unsigned n" << s << " = (t / " << P.M[s] / st << "u) % " << P.d[s] << "u;\n";
+        o << "    const unsigned F0 = t * " << st * sz << "u + " << shift << "u;\n";
+        auto soff = [&](int64_t j, int64_t delta) {
             std::ostringstream s;
-            s << "(F0 - " << static_cast<uint32_t>(static_cast<uint64_t>(delta)) << "u) * " << SZ << "u + " << shift
-              << "u";
+            s << "F0 + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
             return s.str();
         };
-        auto ucond = [&](int c) -> std::string {  // uniform admissibility of the outer sites of channel c
-            const auto& ch = P.chans[c];
-            std::string cnd;
-            auto add = [&](int site, int op) {
-                if (inner(site)) return;
-                const std::string e = adm_expr(p, site, op);
-                if (!e.empty()) cnd = cnd.empty() ? e : cnd + " && " + e;
-            };
-            add(ch.a, ch.opa);
-            if (ch.b >= 0) add(ch.b, ch.opb);
-            return cnd.empty() ? "true" : cnd;
-        };
-        // outer and mixed channels read x through the buffer; every load is issued (out-of-range
-        // offsets return 0 without a memory access), so the loads pipeline; groups of GS loads are
-        // issued one group ahead of their use
-        std::vector<int> cG = cO;
+        for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = LD(xs, voff, " << soff(j, 0) << ");\n";
+        std::vector<int> cG = cU;
         cG.insert(cG.end(), cM.begin(), cM.end());
-        const int GS = f32 ? 12 : 8;
-        const int ng = static_cast<int>((cG.size() + GS - 1) / GS);
+        for (int c : cG) {
+            const auto& ch = P.chans[c];
+            bool lane = false;
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(ch.a, ch.opa, ch.b, ch.opb, j);
+                if (sp.first != 0.0 && !sp.second.empty()) lane = true;
+            }
+            const std::string base = (kind(ch.a, ch.b) == 2 && lane) ? "vo" + std::to_string(c) : "voff";
+            const std::string ad = admit_uniform(ch.a, ch.opa, ch.b, ch.opb);
+            o << "    const unsigned u" << c << " = " << (ad == "true" ? base : "(" + ad + ") ? " + base + " : OOB") << ";\n";
+        }
+        const int GS = f32 ? 10 : 6;  // channels per load group
+        const int ngr = static_cast<int>((cG.size() + GS - 1) / GS);
         auto emit_loads = [&](int g) {
             for (int i = g * GS; i < std::min<int>(cG.size(), (g + 1) * GS); ++i) {
                 const int c = cG[i];
-                const bool mixed = cls(P.chans[c].a, P.chans[c].b) == 2;
-                const std::string base = mixed ? "vo" + std::to_string(c) : "voff";
-                const std::string uc = ucond(c);
-                o << "    const C s" << c << " = LD(xs, " << (uc == "true" ? base : "(" + uc + ") ? " + base + " : OOB")
-                  << ", " << soff(P.chans[c].delta) << ");\n";
+                const auto& ch = P.chans[c];
+                for (int64_t j = 0; j < PU; ++j) {
+                    if (kind(ch.a, ch.b) == 2 && !fM.count({c, j})) continue;
+                    o << "    const C s" << c << "_" << j << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
+                }
             }
         };
+        if (ngr > 0) emit_loads(0);
+        if (twaves > 0) {
+            o << "    if (wv < " << twaves << "u) {\n"
+              << "      if (has_it) {\n"
+              << "        const unsigned na = dig(t, i_mam, i_da, i_dam), nb = dig(t, i_mbm, i_db, i_dbm);\n"
+              << "        const R f = Kl[i_ta + na] * Kl[i_tb + nb];\n"
+              << "        tr[par][ii] = i_wr * f;\n"
+              << (cplx ? "        ti[par][ii] = i_wi * f;\n" : "")
+              << "      }\n";
+            if (nsum > 0) {
+                o << "      const unsigned ma = dig(t, q_mam, q_da, q_dam), mb = dig(t, q_mbm, q_db, q_dbm);\n"
+                  << "      const R g = Kl[q_ta + ma] * Kl[q_tb + mb];\n"
+                  << "      R vr = q_wr * g, vi = q_wi * g;\n"
+                  << "      for (int k = 32; k > 0; k >>= 1) { vr += __shfl_down(vr, k, 64);"
+                  << (cplx ? " vi += __shfl_down(vi, k, 64);" : "") << " }\n"
+                  << "      if (ln == 0u) { dsr[par][wv] = vr;" << (cplx ? " dsi[par][wv] = vi;" : "") << " }\n";
+            }
+            o << "    }\n";
+        }
+        if (use_lds) {
+            o << "    C* lb = xl" << (dbuf ? " + par * " + std::to_string(xrows) + "u" : std::string("")) << ";\n";
+            for (int64_t j = 0; j < PU; ++j) o << "    lb[w" << j << "] = x" << j << ";\n";
+        }
+        o << "    __syncthreads();\n"
+          << "    R dUr = (R)0, dUi = (R)0;\n";
+        for (int w = 0; w < (nsum > 0 ? twaves : 0); ++w)
+            o << "    dUr += dsr[par][" << w << "];" << (cplx ? " dUi += dsi[par][" + std::to_string(w) + "];" : "") << "\n";
+        for (int64_t j = 0; j < PU; ++j) {
+            o << "    R a" << j << "r, a" << j << "i;\n    {\n      R dr = dS" << j << "r + dUr, di = dS" << j << "i + dUi;\n";
+            for (int g : gM) {
+                auto it = fD.find({g, j});
+                if (it == fD.end()) continue;
+                const int idx = item_of_diag[g];
+                o << "      dr += tr[par][" << idx << "] * " << it->second << ";";
+                if (cplx) o << " di += ti[par][" << idx << "] * " << it->second << ";";
+                o << "\n";
+            }
+            o << "      a" << j << "r = dr * x" << j << ".x - di * x" << j << ".y; a" << j << "i = dr * x" << j
+              << ".y + di * x" << j << ".x;\n    }\n";
+        }
+        auto acc = [&](int64_t j, const std::string& kr, const std::string& ki, const std::string& s) {
+            o << "a" << j << "r += " << kr << " * " << s << ".x; a" << j << "i += " << kr << " * " << s << ".y;";
+            if (!ki.empty())
+                o << " a" << j << "r -= " << ki << " * " << s << ".y; a" << j << "i += " << ki << " * " << s << ".x;";
+        };
+        if (use_lds) {
+            for (int c : cS) {
+                for (int64_t j = 0; j < PU; ++j) {
+                    auto it = kS.find({c, j});
+                    if (it == kS.end()) continue;
+                    const int64_t off = halo + j * T - P.chans[c].delta;
+                    o << "    { const C s = lb[r + " << off << "u]; ";
+                    acc(j, it->second + "r", cplx ? it->second + "i" : "", "s");
+                    o << " }\n";
+                }
+            }
+            if (!dbuf) o << "    __syncthreads();\n";
+        }
         auto emit_accum = [&](int g) {
             for (int i = g * GS; i < std::min<int>(cG.size(), (g + 1) * GS); ++i) {
                 const int c = cG[i];
                 const auto& ch = P.chans[c];
-                const std::string cs = std::to_string(c), sc = "s" + cs;
-                std::string f;
-                if (cls(ch.a, ch.b) == 1)
-                    f = ch.b >= 0 ? fac_uni2(ch.a, ch.opa, ch.b, ch.opb) : fac_uni(ch.a, ch.opa);
-                else {
-                    const bool ia = inner(ch.a);
-                    f = fac_uni(ia ? ch.b : ch.a, ia ? ch.opb : ch.opa) + " * f" + cs;
+                const int idx = item_of_chan[c];
+                o << "    { const R kr = tr[par][" << idx << "];" << (cplx ? " const R ki = ti[par][" + std::to_string(idx) + "];" : "")
+                  << "\n";
+                for (int64_t j = 0; j < PU; ++j) {
+                    const std::string s = "s" + std::to_string(c) + "_" + std::to_string(j);
+                    if (kind(ch.a, ch.b) == 1) {
+                        o << "      ";
+                        acc(j, "kr", cplx ? "ki" : "", s);
+                        o << "\n";
+                    } else {
+                        auto it = fM.find({c, j});
+                        if (it == fM.end()) continue;
+                        o << "      { const R mr = kr * " << it->second << ";"
+                          << (cplx ? " const R mi = ki * " + it->second + ";" : "") << " ";
+                        acc(j, "mr", cplx ? "mi" : "", s);
+                        o << " }\n";
+                    }
                 }
-                o << "    { const R f = " << f << "; const R kr = cw" << cs << "r * f; ar += kr * " << sc
-                  << ".x; ai += kr * " << sc << ".y;";
-                if (complex_w)
-                    o << " const R ki = cw" << cs << "i * f; ar -= ki * " << sc << ".y; ai += ki * " << sc << ".x;";
-                o << " }\n";
+                o << "    }\n";
             }
         };
-        if (ng > 0) emit_loads(0);
-        // diagonal weight for this tile
-        o << "    R dr = dIr, di = dIi;\n";
-        for (int g = 0; g < ndg; ++g) {
-            const auto& dg = P.diags[g];
-            const int k = cls(dg.a, dg.b);
-            if (k == 0) continue;
-            std::string f;
-            if (k == 1) {
-                f = dg.b >= 0 ? fac_uni2(dg.a, dg.opa, dg.b, dg.opb) : fac_uni(dg.a, dg.opa);
-            } else {
-                const bool ia = inner(dg.a);
-                f = fac_uni(ia ? dg.b : dg.a, ia ? dg.opb : dg.opa) + " * fz" + std::to_string(g);
-            }
-            o << "    { const R f = " << f << "; dr += dw" << g << "r * f;";
-            if (complex_w) o << " di += dw" << g << "i * f;";
-            o << " }\n";
-        }
-        o << "    R ar = dr * xf.x - di * xf.y, ai = dr * xf.y + di * xf.x;\n";
-        if (use_lds) {
-            o << "    C* lb = lds + par * " << rows_lds << "u;\n"
-              << "    lb[widx] = xf;\n"
-              << "    __syncthreads();\n";
-            for (int c : cI) {
-                const std::string cs = std::to_string(c);
-                const int64_t off = pad - P.chans[c].delta;
-                o << "    { const C s = lb[r + " << off << "u]; ar += k" << cs << "r * s.x; ai += k" << cs << "r * s.y;";
-                if (complex_w) o << " ar -= k" << cs << "i * s.y; ai += k" << cs << "i * s.x;";
-                o << " }\n";
-            }
-            o << "    par ^= 1u;\n";
-        }
-        for (int g = 0; g < ng; ++g) {
-            if (g + 1 < ng) emit_loads(g + 1);
+        for (int g = 0; g < ngr; ++g) {
+            if (g + 1 < ngr) emit_loads(g + 1);
             emit_accum(g);
         }
-        o << "    { C out; out.x = ar; out.y = ai; ST(out, ys, voff, F0 * " << SZ << "u + " << shift << "u); }\n"
-          << "  }\n}\n";
+        for (int64_t j = 0; j < PU; ++j)
+            o << "    { C out; out.x = a" << j << "r; out.y = a" << j << "i; ST(out, ys, voff, " << soff(j, 0) << "); }\n";
+        o << "    par ^= 1u;\n  }\n}\n";
 
         std::ostringstream full;
-        full << "// generated: " << P.N << " sites, " << nch << " channels (" << cI.size() << " inner, " << cM.size()
-             << " mixed, " << cO.size() << " outer), " << ndg << " diagonal terms, inner block of " << T_in
-             << " rows (sites " << k_in << ".." << P.N - 1 << ")\n";
+        full << "// generated: " << P.N << " sites, " << nch << " channels (" << cS.size() << " static, " << cM.size()
+             << " mixed, " << cU.size() << " uniform), " << ndg << " diagonal terms; " << T
+             << " rows per block (sites " << tl.k_in << ".." << P.N - 1 << "), " << PU << " unrolled copies (sites "
+             << tl.k_u << ".." << tl.k_in - 1 << "), " << n_st << " super-tiles\n";
         if (f32)
             full << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
                  << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
+                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
                  << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
         else
             full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
                  << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
+                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
                  << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
-        const std::string body = o.str();
-        if (!pool.empty()) {
-            full << "__constant__ R K[" << pool.size() << "] = {";
-            for (size_t i = 0; i < pool.size(); ++i) full << (i ? ", " : "") << lit(pool[i], f32);
-            full << "};\n";
-        }
-        full << pre.str() << body;
+        full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
+        full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
+        if (pool.empty()) full << "0";
+        for (size_t i = 0; i < pool.size(); ++i) full << (i ? ", " : "") << lit(pool[i], f32);
+        full << "};\n" << pre.str() << o.str();
         return full.str();
     }
 };
 
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-// Inner block: the low sites whose product T_in <= 1024 rows, preferring blocks of at least 256
-// rows that fill whole wavefronts.
-bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int* k_in, int* T_in) {
+// Tile choice.  Inner block: the low sites with T_in <= 1024 rows, preferring blocks of at least 256
+// rows that fill whole wavefronts.  Unrolled copies: the next sites up while P_U <= 4 and at least 2048
+// super-tiles remain to fill the GPU.
+bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, Tile* tl) {
     const int N = p->N;
+    int k_in = N;
+    int64_t T = 1;
     if (inner_pref > 0) {
         if (inner_pref > N) return false;
-        int64_t T = 1;
         for (int i = N - inner_pref; i < N; ++i) T *= p->d[i];
         if (T > 1024) return false;
-        *k_in = N - inner_pref;
-        *T_in = static_cast<int>(T);
-        return true;
-    }
-    double best = -1.0;
-    int64_t T = 1;
-    for (int k = N - 1; k >= 0; --k) {
-        T *= p->d[k];
-        if (T > 1024) break;
-        const double eff = double(T) / double(round_up(T, 64));
-        const double score = eff * std::min(1.0, double(T) / 256.0);
-        if (score > best + 1e-12) {
-            best = score;
-            *k_in = k;
-            *T_in = static_cast<int>(T);
+        k_in = N - inner_pref;
+    } else {
+        double best = -1.0;
+        int64_t t = 1;
+        for (int k = N - 1; k >= 0; --k) {
+            t *= p->d[k];
+            if (t > 1024) break;
+            const double eff = double(t) / double(round_up(t, 64));
+            const double score = eff * std::min(1.0, double(t) / 256.0);
+            if (score > best + 1e-12) {
+                best = score;
+                k_in = k;
+                T = t;
+            }
         }
+        if (best < 0) return false;
     }
-    return best > 0.0;
+    int k_u = k_in;
+    int64_t PU = 1;
+    if (unroll_pref >= 0) {
+        for (int i = 0; i < unroll_pref && k_u > 0; ++i) PU *= p->d[--k_u];
+        if (PU > 16) return false;
+    } else {
+        while (k_u > 0 && PU * p->d[k_u - 1] <= 4 && p->D / (T * PU * p->d[k_u - 1]) >= 2048) PU *= p->d[--k_u];
+    }
+    tl->k_in = k_in;
+    tl->k_u = k_u;
+    tl->T_in = T;
+    tl->P_U = PU;
+    return true;
 }
 
 }  // namespace
 
-std::string spec_source(const mrmf_plan_t* p, int dtype, int* k_in_out, int* T_in_out) {
+std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int64_t SZ = f32 ? 8 : 16;
-    int k_in = 0, T_in = 0;
-    if (!choose_tiling(p, p->inner_pref, &k_in, &T_in)) return "";
-    const int64_t n_tiles = p->D / T_in;
-    if (p->D * SZ + int64_t(T_in) * SZ >= (int64_t(1) << 31) || n_tiles >= (int64_t(1) << 31)) return "";
-    Gen gen{p, f32, k_in, T_in, static_cast<int>(round_up(T_in, 64)), n_tiles};
-    *k_in_out = k_in;
-    *T_in_out = T_in;
+    Tile tl;
+    if (!choose_tiling(p, p->inner_pref, p->unroll_pref, &tl)) return "";
+    const int64_t st = tl.T_in * tl.P_U;
+    const int64_t n_st = p->D / st;
+    int64_t dmax = 0, dmin = 0;
+    for (const auto& c : p->chans) {
+        dmax = std::max<int64_t>(dmax, c.delta);
+        dmin = std::min<int64_t>(dmin, c.delta);
+    }
+    // every buffer offset below 2^31 bytes: rows plus both shifts
+    if ((p->D + dmax - dmin + 2 * tl.T_in) * SZ >= (int64_t(1) << 31) || n_st >= (int64_t(1) << 31)) return "";
+    Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
+    *tl_out = tl;
     return gen.source();
 }
 
@@ -407,14 +618,14 @@ namespace {
 mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
     K.tried = true;
     K.ok = false;
-    int k_in = 0, T_in = 0;
-    const std::string src = spec_source(p, dtype, &k_in, &T_in);
+    Tile tl;
+    const std::string src = spec_source(p, dtype, &tl);
     if (src.empty()) {
         K.log = "plan does not qualify for the specialized kernel";
         return MRMF_E_UNSUPPORTED;
     }
-    const int64_t n_tiles = p->D / T_in;
-    const int block = static_cast<int>(round_up(T_in, 64));
+    const int64_t n_st = p->D / (tl.T_in * tl.P_U);
+    const int block = static_cast<int>(round_up(tl.T_in, 64));
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
     hipDeviceProp_t prop;
@@ -452,15 +663,17 @@ mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int64_t grid = int64_t(per_cu) * prop.multiProcessorCount;
-    if (grid > n_tiles) grid = n_tiles;
+    if (grid > n_st) grid = n_st;
     if (grid >= 8) grid -= grid % 8;
     K.mod = mod;
     K.fn = fn;
-    K.k_in = k_in;
-    K.T_in = T_in;
+    K.k_in = tl.k_in;
+    K.k_u = tl.k_u;
+    K.T_in = static_cast<int32_t>(tl.T_in);
+    K.P_U = static_cast<int32_t>(tl.P_U);
     K.block = block;
     K.grid = static_cast<int32_t>(grid);
-    K.n_tiles = n_tiles;
+    K.n_tiles = n_st;
     K.device = dev;
     K.log = src;
     K.ok = true;
@@ -507,14 +720,15 @@ mrmf_plan_t::~mrmf_plan_t() {
 
 extern "C" {
 
-mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites) {
+mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites, int32_t unrolled_sites) {
     if (!plan || kind < MRMF_KERNEL_AUTO || kind > MRMF_KERNEL_SPECIALIZED || inner_sites < 0 ||
-        inner_sites > plan->N)
+        inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N)
         return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
     plan->kernel_mode = kind;
-    if (plan->inner_pref != inner_sites) {
+    if (plan->inner_pref != inner_sites || plan->unroll_pref != unrolled_sites) {
         plan->inner_pref = inner_sites;
+        plan->unroll_pref = unrolled_sites;
         for (auto& k : plan->spec) {
             if (k.mod) hipModuleUnload(k.mod);
             k = mrmf::SpecKernel{};
@@ -534,8 +748,8 @@ mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype) {
 mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len) {
     if (!plan || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) || (cap > 0 && !buf))
         return MRMF_E_INVALID_ARG;
-    int k_in = 0, T_in = 0;
-    const std::string src = mrmf::spec_source(plan, dtype, &k_in, &T_in);
+    mrmf::Tile tl;
+    const std::string src = mrmf::spec_source(plan, dtype, &tl);
     if (src.empty()) return MRMF_E_UNSUPPORTED;
     *len = src.size();
     if (cap > 0) {
@@ -557,6 +771,8 @@ mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out) {
     out[3] = spec ? K.block : 256;
     out[4] = spec ? K.grid : 0;
     out[5] = spec ? static_cast<int32_t>(K.n_tiles) : 0;
+    out[6] = spec ? K.k_in - K.k_u : 0;
+    out[7] = spec ? K.P_U : 0;
     return MRMF_OK;
 }
 

@@ -63,6 +63,13 @@ struct Tiling {
     int32_t T_in = 1;
 };
 
+// Site split of the specialized kernel: uniform [0, k_u), unrolled [k_u, k_in) with P_U digit
+// combinations, inner [k_in, N) with T_in rows.
+struct Tile {
+    int k_u = 0, k_in = 0;
+    int64_t T_in = 1, P_U = 1;
+};
+
 // A kernel generated and compiled for one plan and element type (see jit.cpp).
 struct SpecKernel {
     bool tried = false;
@@ -70,7 +77,7 @@ struct SpecKernel {
     int device = -1;
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
-    int32_t k_in = 0, T_in = 0, block = 0, grid = 0;
+    int32_t k_in = 0, k_u = 0, T_in = 0, P_U = 1, block = 0, grid = 0;
     int64_t n_tiles = 0;
     std::string log;
 };
@@ -97,6 +104,7 @@ struct mrmf_plan_t {
     // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type
     int32_t kernel_mode = 0;
     int32_t inner_pref = 0;
+    int32_t unroll_pref = -1;
     mrmf::SpecKernel spec[2];
     std::mutex mtx;
     ~mrmf_plan_t();
@@ -146,7 +154,7 @@ mrmf_status matvec_z_impl(mrmf_plan_t* p, const void* d_ws, const double* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
 mrmf_status matvec_c_impl(mrmf_plan_t* p, const void* d_ws, const float* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
-// Generated source of the specialized kernel (no device needed; arch only matters for compilation).
-std::string spec_source(const mrmf_plan_t* p, int dtype, int* k_in, int* T_in);
+// Generated source of the specialized kernel (no device needed); "" when the plan does not qualify.
+std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl);
 
 }  // namespace mrmf

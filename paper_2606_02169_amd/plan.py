@@ -169,10 +169,10 @@ class Plan:
     # ------------------------------------------------------------------ kernel selection
     KERNELS = {"auto": 0, "generic": 1, "specialized": 2}
 
-    def set_kernel(self, kind: str = "auto", inner_sites: int = 0):
+    def set_kernel(self, kind: str = "auto", inner_sites: int = 0, unrolled_sites: int = -1):
         """Choose the matvec kernel: "generic", "specialized" (plan-specific, compiled on first use) or
-        "auto"; inner_sites = 0 lets the library pick the tile."""
-        L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites))
+        "auto"; inner_sites = 0 / unrolled_sites = -1 let the library pick the tiling."""
+        L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
     def prepare(self, dtype=torch.complex128):
         """Compile and load the kernel matvec will use for this element type (synchronous)."""
@@ -181,10 +181,11 @@ class Plan:
 
     def kernel_info(self, dtype=torch.complex128) -> dict:
         dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
-        out = (ctypes.c_int32 * 6)()
+        out = (ctypes.c_int32 * 8)()
         L.call("mrmf_plan_kernel_info", self._handle, dt, out)
         kind = {0: "auto", 1: "generic", 2: "specialized"}[out[0]]
-        return dict(kind=kind, inner_sites=out[1], rows_per_tile=out[2], block=out[3], grid=out[4], tiles=out[5])
+        return dict(kind=kind, inner_sites=out[1], rows_per_block=out[2], block=out[3], grid=out[4],
+                    super_tiles=out[5], unrolled_sites=out[6], copies=out[7])
 
     def kernel_source(self, dtype=torch.complex128) -> str:
         dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C

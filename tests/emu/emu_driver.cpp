@@ -1,0 +1,85 @@
+// Runs an emulated kernel `mrmf_spec(theta, x, y, skip)` (compiled from generated HIP source together
+// with hip_emu.h) over a grid of blocks on host threads.  Test infrastructure only.
+#include <pthread.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "hip_emu.h"
+
+thread_local emu_dim3 threadIdx;
+emu_dim3 blockIdx, gridDim, blockDim;
+double emu_shfl_slot[16][64];
+
+namespace {
+pthread_barrier_t g_block_bar;
+pthread_barrier_t g_wave_bar[16];
+struct Buf {
+    const char* p;
+    size_t n;
+    const char* name;
+};
+std::vector<Buf> g_bufs;
+int g_fault = 0;
+}  // namespace
+
+void emu_syncthreads() { pthread_barrier_wait(&g_block_bar); }
+void emu_wave_barrier() { pthread_barrier_wait(&g_wave_bar[threadIdx.x >> 6]); }
+
+void emu_check(const void* p, size_t n, const char* what) {
+    const char* c = static_cast<const char*>(p);
+    for (const Buf& b : g_bufs)
+        if (c >= b.p && c + n <= b.p + b.n) return;
+    std::fprintf(stderr, "emu: %s of %zu bytes at %p outside every buffer (block %u thread %u)\n", what, n, p,
+                 blockIdx.x, threadIdx.x);
+    for (const Buf& b : g_bufs) std::fprintf(stderr, "  %s: [%p, %p)\n", b.name, (const void*)b.p, (const void*)(b.p + b.n));
+    std::fflush(stderr);
+    std::abort();
+}
+
+extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip);
+
+namespace {
+struct Arg {
+    unsigned tid;
+    const void *theta, *x;
+    void* y;
+};
+void* thread_main(void* a) {
+    Arg* g = static_cast<Arg*>(a);
+    threadIdx = emu_dim3{g->tid, 0, 0};
+    mrmf_spec(g->theta, g->x, g->y, nullptr);
+    return nullptr;
+}
+}  // namespace
+
+extern "C" int emu_run(unsigned grid, unsigned block, const void* theta, size_t theta_bytes, const void* x,
+                       size_t x_bytes, void* y, size_t y_bytes) {
+    if (block == 0 || block % 64 != 0 || block > 1024) return -1;
+    g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
+              {static_cast<const char*>(theta), theta_bytes, "theta"}};
+    gridDim = emu_dim3{grid, 1, 1};
+    blockDim = emu_dim3{block, 1, 1};
+    const unsigned nw = block / 64;
+    pthread_barrier_init(&g_block_bar, nullptr, block);
+    for (unsigned w = 0; w < nw; ++w) pthread_barrier_init(&g_wave_bar[w], nullptr, 64);
+    std::vector<pthread_t> th(block);
+    std::vector<Arg> args(block);
+    pthread_attr_t attr;
+    pthread_attr_init(&attr);
+    pthread_attr_setstacksize(&attr, 1 << 20);
+    for (unsigned b = 0; b < grid; ++b) {
+        blockIdx = emu_dim3{b, 0, 0};
+        for (unsigned t = 0; t < block; ++t) {
+            args[t] = Arg{t, theta, x, y};
+            if (pthread_create(&th[t], &attr, thread_main, &args[t]) != 0) return -2;
+        }
+        for (unsigned t = 0; t < block; ++t) pthread_join(th[t], nullptr);
+    }
+    pthread_attr_destroy(&attr);
+    pthread_barrier_destroy(&g_block_bar);
+    for (unsigned w = 0; w < nw; ++w) pthread_barrier_destroy(&g_wave_bar[w]);
+    return g_fault;
+}

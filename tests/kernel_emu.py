@@ -1,0 +1,93 @@
+"""CPU emulation of the plan-specialized kernels (test infrastructure).
+
+The library generates a HIP kernel per plan (mrmf_plan_kernel_source, host only).  Here that source is
+compiled for x86 with clang against tests/emu/hip_emu.h and run on host threads, so its indexing,
+LDS use and buffer offsets can be checked on the CPU: every buffer access that is not masked off is
+verified to lie inside x or y, and the result is compared with the oracle by the tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+
+from paper_2606_02169_amd import _lib as L
+from tests.helpers import host_plan
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(HERE, "emu")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+CACHE = os.path.join(tempfile.gettempdir(), "mrmf_emu_cache")
+
+
+def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True) -> str | None:
+    st, h = host_plan(model, require_hermitian=require_hermitian)
+    assert st == 0, st
+    try:
+        L.call("mrmf_plan_set_kernel", h, L.MRMF_KERNEL_SPECIALIZED, int(inner), int(unrolled))
+        n = ctypes.c_size_t()
+        s = L.lib().mrmf_plan_kernel_source(h, dtype, None, 0, ctypes.byref(n))
+        if s != 0:
+            return None
+        buf = ctypes.create_string_buffer(n.value + 1)
+        L.call("mrmf_plan_kernel_source", h, dtype, buf, n.value + 1, ctypes.byref(n))
+        return buf.value.decode()
+    finally:
+        L.lib().mrmf_plan_destroy(h)
+
+
+def _compile(src: str) -> ctypes.CDLL:
+    os.makedirs(CACHE, exist_ok=True)
+    key = hashlib.sha256((src + open(os.path.join(EMU, "hip_emu.h")).read()
+                          + open(os.path.join(EMU, "emu_driver.cpp")).read()).encode()).hexdigest()[:20]
+    so = os.path.join(CACHE, f"k_{key}.so")
+    if not os.path.exists(so):
+        gen = os.path.join(CACHE, f"k_{key}.cpp")
+        with open(gen, "w") as f:
+            f.write(src)
+        tmp = so + f".tmp{os.getpid()}"
+        cmd = [CLANG, "-std=c++17", "-O1", "-pthread", "-fPIC", "-shared", "-w", "-I", EMU,
+               "-include", os.path.join(EMU, "hip_emu.h"), "-x", "c++", gen,
+               os.path.join(EMU, "emu_driver.cpp"), "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"emulator build failed:\n{r.stderr[:4000]}")
+        os.replace(tmp, so)
+    lib = ctypes.CDLL(so)
+    lib.emu_run.restype = ctypes.c_int
+    lib.emu_run.argtypes = [ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                            ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
+    return lib
+
+
+def launch_shape(src: str):
+    block = int(re.search(r"__launch_bounds__\((\d+)\)", src).group(1))
+    tiles = int(re.search(r"(\d+) super-tiles", src).group(1))
+    return block, tiles
+
+
+def run(model, x: np.ndarray, theta=None, inner: int = 0, unrolled: int = -1, grid: int | None = None,
+        require_hermitian=True) -> np.ndarray:
+    """y = H x with the generated kernel, emulated on the CPU."""
+    f32 = x.dtype == np.complex64
+    src = kernel_source(model, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z, inner, unrolled,
+                        require_hermitian=require_hermitian)
+    if src is None:
+        raise ValueError("the plan does not qualify for the specialized kernel")
+    block, tiles = launch_shape(src)
+    if grid is None:
+        grid = min(tiles, 8)
+    lib = _compile(src)
+    th = np.ascontiguousarray(model.theta if theta is None else theta,
+                              dtype=np.float32 if f32 else np.float64)
+    xx = np.ascontiguousarray(x)
+    y = np.full_like(xx, np.nan)
+    rc = lib.emu_run(grid, block, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data, y.nbytes)
+    if rc != 0:
+        raise RuntimeError(f"emu_run failed: {rc}")
+    return y
