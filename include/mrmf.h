@@ -130,6 +130,22 @@ mrmf_status mrmf_plan_upload(mrmf_plan plan, void* d_ws, size_t ws_bytes, mrmf_s
 #define MRMF_DTYPE_Z 0 /* c128 */
 #define MRMF_DTYPE_C 1 /* c64  */
 mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites, int32_t unrolled_sites);
+/* Tuning knobs of the specialized kernel (each change makes the next call regenerate it):
+ *   MRMF_TUNE_SCHEDULE      : MRMF_SCHED_WINDOWS  - the grid sweeps windows of consecutive super-tiles,
+ *                                                   each XCD taking one eighth of every window;
+ *                             MRMF_SCHED_XCD_CHUNK - each XCD sweeps its own contiguous eighth of the
+ *                                                   super-tiles with its blocks side by side.
+ *   MRMF_TUNE_BRANCH_SKIP   : 1 = a channel whose tile-uniform source digits are inadmissible is skipped
+ *                             by a scalar branch; 0 = its loads are issued and masked.
+ *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default).
+ *   MRMF_TUNE_BLOCKS_PER_CU : cap on resident blocks per compute unit (0 = as many as fit). */
+#define MRMF_TUNE_SCHEDULE 0
+#define MRMF_TUNE_BRANCH_SKIP 1
+#define MRMF_TUNE_LOAD_GROUP 2
+#define MRMF_TUNE_BLOCKS_PER_CU 3
+#define MRMF_SCHED_WINDOWS 0
+#define MRMF_SCHED_XCD_CHUNK 1
+mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
 /* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
  * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only. */
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype);

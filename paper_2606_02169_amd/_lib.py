@@ -24,6 +24,8 @@ MRMF_PREC_Z, MRMF_PREC_C_IN_Z = 0, 1
 MRMF_REORTH_CGS2, MRMF_REORTH_NONE = 0, 1
 MRMF_KERNEL_AUTO, MRMF_KERNEL_GENERIC, MRMF_KERNEL_SPECIALIZED = 0, 1, 2
 MRMF_DTYPE_Z, MRMF_DTYPE_C = 0, 1
+MRMF_TUNE_SCHEDULE, MRMF_TUNE_BRANCH_SKIP, MRMF_TUNE_LOAD_GROUP, MRMF_TUNE_BLOCKS_PER_CU = 0, 1, 2, 3
+MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK = 0, 1
 
 
 class mrmf_site(ctypes.Structure):
@@ -65,6 +67,7 @@ SIGNATURES = {
     "mrmf_debug_sources": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp]),
     "mrmf_plan_set_kernel": (_i32, [_vp, _i32, _i32, _i32]),
     "mrmf_plan_prepare": (_i32, [_vp, _i32]),
+    "mrmf_plan_set_tuning": (_i32, [_vp, _i32, _i32]),
     "mrmf_plan_kernel_info": (_i32, [_vp, _i32, _P(_i32)]),
     "mrmf_plan_kernel_source": (_i32, [_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)]),
     "mrmf_adjoint_scratch_bytes": (_i32, [_vp, _P(_sz)]),

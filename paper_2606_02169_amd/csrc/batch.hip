@@ -1,0 +1,508 @@
+// Batched form: many independent lattices, each applied to a block of nvec c64 vectors, in one
+// persistent launch.  Each lattice is the same target-driven gather (Sec. II) with its own digits
+// (Sec. III, Eq. decode), channels and offsets (Sec. IV, Eq. sourceoffset) and ladder factors (App. A,
+// App. B, App. C); the lattices only share the launch.
+//
+// Layout.  Lattice b's vectors are stored row-major as [D_b][nvec] at element offset off_b of X and Y
+// (row F holds its nvec amplitudes contiguously, so one row is 8 * nvec bytes); offsets are multiples
+// of 32 elements.
+//
+// Work.  The rows of every lattice are cut into items of R consecutive rows; items are numbered
+// lattice by lattice.  Block v of the grid takes the contiguous item range [v I / G, (v+1) I / G), with
+// v chosen so that the blocks of one XCD (hardware places block b on XCD b mod 8) hold neighbouring
+// ranges.  Within an item every thread owns R / blockDim rows; for each row it decodes the digits once
+// into LDS, then for every channel forms the coefficient from the per-site factor tables (zero where
+// the source digit is inadmissible, App. A) and, where it is nonzero, gathers the nvec source
+// amplitudes of row F - Delta; a nonzero factor means both source digits are in range, so every load
+// stays inside the lattice's own block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mrmf_internal.h"
+
+namespace mrmf {
+namespace {
+
+constexpr int kBatchMaxLattices = 4096;
+constexpr int kBatchMaxSites = 32;
+constexpr int kBatchMaxBlock = 512;
+constexpr int kBatchPoolMax = 2048;  // factor-table entries of one lattice (LDS)
+
+struct alignas(16) BLat {
+    int32_t N, n_chan, n_diag, theta_off;
+    int32_t D, chan_off, diag_off, site_off;
+    int32_t pool_off, pool_n, pad0, pad1;
+    int64_t x_off, pad2;
+};
+static_assert(sizeof(BLat) == 64, "BLat layout");
+
+struct alignas(16) BSite {
+    int32_t d, pad;
+    uint64_t magic;  // ceil(2^64 / d)
+};
+static_assert(sizeof(BSite) == 16, "BSite layout");
+
+// One term: coefficient theta[param] * (wr + i wi) * pool[ta + n_a] * pool[tb + n_b]; source F - delta.
+// A one-site term has b = -1 (its second factor is the pool's 1.0 entry at tb, digit 0).
+struct alignas(16) BTerm {
+    int32_t a, b, ta, tb;
+    int32_t param, delta;
+    float wr, wi;
+};
+static_assert(sizeof(BTerm) == 32, "BTerm layout");
+
+struct BatchArgs {
+    const BLat* lat;
+    const BSite* site;
+    const BTerm* term;   // channels and diagonal terms of every lattice
+    const float* pool;   // factor tables of every lattice
+    int32_t n_lat;
+    int32_t all_real;
+};
+
+__device__ __forceinline__ uint32_t umulhi_div(uint32_t n, uint64_t magic) {
+    return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));
+}
+
+template <int NV, bool CPLX>
+__global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const float* __restrict__ theta_all,
+                                                        const float2* __restrict__ X, float2* __restrict__ Y,
+                                                        int32_t R) {
+    __shared__ int32_t ibeg[kBatchMaxLattices + 1];
+    __shared__ float pool[kBatchPoolMax];
+    __shared__ uint8_t dig[kBatchMaxSites][kBatchMaxBlock];
+    const int tid = threadIdx.x, B = blockDim.x;
+    // item numbering: ibeg[b] = sum over b' < b of ceil(D_b' / R): counts in parallel, then a serial
+    // scan over LDS by thread 0 (n <= 4096)
+    for (int b = tid; b < A.n_lat; b += B) ibeg[b + 1] = (A.lat[b].D + R - 1) / R;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t s = 0;
+        ibeg[0] = 0;
+        for (int b = 1; b <= A.n_lat; ++b) {
+            s += ibeg[b];
+            ibeg[b] = s;
+        }
+    }
+    __syncthreads();
+    const int64_t I = ibeg[A.n_lat];
+    const unsigned G = gridDim.x, bid = blockIdx.x;
+    const unsigned v = (G % 8u == 0u) ? (bid % 8u) * (G / 8u) + bid / 8u : bid;
+    const int32_t i0 = static_cast<int32_t>(int64_t(v) * I / G), i1 = static_cast<int32_t>(int64_t(v + 1) * I / G);
+    int lb = -1;
+    BLat L{};
+    int b = 0;
+    {
+        int lo = 0, hi = A.n_lat - 1;  // last lattice with ibeg[b] <= i0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ibeg[mid] <= i0) lo = mid; else hi = mid - 1;
+        }
+        b = lo;
+    }
+    for (int32_t it = i0; it < i1; ++it) {
+        while (it >= ibeg[b + 1]) ++b;
+        if (b != lb) {
+            __syncthreads();  // every thread is done with the previous lattice's tables
+            L = A.lat[b];
+            for (int k = tid; k < L.pool_n; k += B) pool[k] = A.pool[L.pool_off + k];
+            lb = b;
+            __syncthreads();
+        }
+        const float* th = theta_all + L.theta_off;
+        const float2* xb = X + L.x_off;
+        float2* yb = Y + L.x_off;
+        const int32_t r0 = (it - ibeg[b]) * R;
+        const int32_t r1 = r0 + R < L.D ? r0 + R : L.D;
+        for (int32_t F = r0 + tid; F < r1; F += B) {
+            // digits, least significant site first (Eq. decode)
+            uint32_t f = static_cast<uint32_t>(F);
+            for (int i = L.N - 1; i >= 0; --i) {
+                const BSite s = A.site[L.site_off + i];
+                const uint32_t q = umulhi_div(f, s.magic);
+                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(s.d));
+                f = q;
+            }
+            float ar[NV], ai[NV];
+            float dr = 0.f, di = 0.f;
+            for (int k = 0; k < L.n_diag; ++k) {
+                const BTerm t = A.term[L.diag_off + k];
+                const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
+                const float c = th[t.param] * fa;
+                dr += c * t.wr;
+                if (CPLX) di += c * t.wi;
+            }
+            {
+                const float2* src = xb + int64_t(F) * NV;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    const float2 s = src[q];
+                    ar[q] = dr * s.x;
+                    ai[q] = dr * s.y;
+                    if (CPLX) {
+                        ar[q] -= di * s.y;
+                        ai[q] += di * s.x;
+                    }
+                }
+            }
+            for (int k = 0; k < L.n_chan; ++k) {
+                const BTerm t = A.term[L.chan_off + k];
+                const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
+                if (fa != 0.f) {  // inadmissible source digits have factor 0 (App. A)
+                    const float c = th[t.param] * fa;
+                    const float cr = c * t.wr, ci = CPLX ? c * t.wi : 0.f;
+                    const float2* src = xb + int64_t(F - t.delta) * NV;  // Eq. sourceoffset
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        const float2 s = src[q];
+                        ar[q] += cr * s.x;
+                        ai[q] += cr * s.y;
+                        if (CPLX) {
+                            ar[q] -= ci * s.y;
+                            ai[q] += ci * s.x;
+                        }
+                    }
+                }
+            }
+            float2* dst = yb + int64_t(F) * NV;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) dst[q] = make_float2(ar[q], ai[q]);
+        }
+    }
+}
+
+template <int NV>
+void* batch_kernel_ptr(bool cplx) {
+    return cplx ? reinterpret_cast<void*>(&k_batch<NV, true>) : reinterpret_cast<void*>(&k_batch<NV, false>);
+}
+
+void* batch_kernel(int nvec, bool cplx) {
+    switch (nvec) {
+        case 1: return batch_kernel_ptr<1>(cplx);
+        case 2: return batch_kernel_ptr<2>(cplx);
+        case 4: return batch_kernel_ptr<4>(cplx);
+        default: return batch_kernel_ptr<8>(cplx);
+    }
+}
+
+// Factor table <n|O|n - q> at target digit n (0 where the source digit n - q is outside 0..d-1).
+void factor_table(const mrmf_plan_t* p, int site, int op, std::vector<float>& out) {
+    const int d = p->d[site], tab = p->tab[site];
+    for (int n = 0; n < d; ++n) {
+        double v;
+        switch (op) {
+            case MRMF_OP_Z: v = p->val[tab + n]; break;
+            case MRMF_OP_Z2: v = p->val[tab + n] * p->val[tab + n]; break;
+            case MRMF_OP_RAISE: v = n >= 1 ? p->up[tab + n] : 0.0; break;
+            default: v = n <= d - 2 ? p->up[tab + n + 1] : 0.0; break;
+        }
+        out.push_back(static_cast<float>(v));
+    }
+}
+
+struct Shape {
+    int32_t R, block;
+};
+const Shape kShapes[] = {{256, 256}, {512, 256}, {1024, 256}, {512, 512}, {1024, 512}, {2048, 512}, {256, 128}, {512, 128}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+}  // namespace
+}  // namespace mrmf
+
+struct mrmf_batch_t {
+    int32_t n = 0, nvec = 0;
+    std::vector<int64_t> off;      // element offset of each lattice's block
+    std::vector<int32_t> th_off;   // n + 1
+    int64_t total = 0;             // elements, padded
+    bool all_real = true;
+    std::vector<unsigned char> image;
+    size_t off_lat = 0, off_site = 0, off_term = 0, off_pool = 0, ws_bytes = 0;
+    int32_t R = 512, block = 256;
+    int32_t grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~mrmf_batch_t() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+mrmf::BatchArgs batch_args(const mrmf_batch_t* b, const void* d_ws) {
+    const unsigned char* w = static_cast<const unsigned char*>(d_ws);
+    mrmf::BatchArgs a;
+    a.lat = reinterpret_cast<const mrmf::BLat*>(w + b->off_lat);
+    a.site = reinterpret_cast<const mrmf::BSite*>(w + b->off_site);
+    a.term = reinterpret_cast<const mrmf::BTerm*>(w + b->off_term);
+    a.pool = reinterpret_cast<const float*>(w + b->off_pool);
+    a.n_lat = b->n;
+    a.all_real = b->all_real ? 1 : 0;
+    return a;
+}
+
+int batch_grid(const mrmf_batch_t* b) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // enough resident blocks to cover the CUs a few times over
+    const int per_cu = b->block <= 128 ? 8 : (b->block <= 256 ? 4 : 2);
+    return cus * per_cu;
+}
+
+mrmf_status launch(mrmf_batch_t* b, const void* d_ws, const float* theta, const void* X, void* Y, hipStream_t s) {
+    const mrmf::BatchArgs a = batch_args(b, d_ws);
+    void* fn = mrmf::batch_kernel(b->nvec, !b->all_real);
+    const int grid = batch_grid(b);
+    b->grid = grid;
+    int32_t R = b->R;
+    const float2* xp = static_cast<const float2*>(X);
+    float2* yp = static_cast<float2*>(Y);
+    void* args[] = {const_cast<mrmf::BatchArgs*>(&a), &theta, &xp, &yp, &R};
+    return mrmf::hip_status(hipLaunchKernel(fn, dim3(grid), dim3(b->block), args, 0, s));
+}
+
+mrmf_status check_call(const mrmf_batch_t* b, const void* d_ws, const float* th, const void* X, const void* Y) {
+    if (!b || !d_ws || !th || !X || !Y) return MRMF_E_INVALID_ARG;
+    if (!mrmf::aligned(d_ws, 256) || !mrmf::aligned(X, 8) || !mrmf::aligned(Y, 8)) return MRMF_E_INVALID_ARG;
+    const size_t bytes = size_t(b->total) * 8;
+    if (mrmf::ranges_overlap(X, bytes, Y, bytes)) return MRMF_E_INVALID_ARG;
+    return MRMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, mrmf_batch* out) {
+    using namespace mrmf;
+    if (!out) return MRMF_E_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || n > kBatchMaxLattices || !plans) return MRMF_E_INVALID_ARG;
+    if (nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8) return MRMF_E_INVALID_ARG;
+    auto* b = new (std::nothrow) mrmf_batch_t();
+    if (!b) return MRMF_E_INVALID_ARG;
+    b->n = n;
+    b->nvec = nvec;
+    std::vector<BLat> lats(n);
+    std::vector<BSite> sites;
+    std::vector<BTerm> terms;
+    std::vector<float> pool;
+    int64_t off = 0;
+    int32_t th = 0;
+    for (int i = 0; i < n; ++i) {
+        const mrmf_plan_t* p = plans[i];
+        if (!p || p->N > kBatchMaxSites || p->D >= (int64_t(1) << 31) / 2 / nvec) {
+            delete b;
+            return p ? MRMF_E_UNSUPPORTED : MRMF_E_INVALID_ARG;
+        }
+        BLat& L = lats[i];
+        L.N = p->N;
+        L.D = static_cast<int32_t>(p->D);
+        L.theta_off = th;
+        L.x_off = off;
+        L.site_off = static_cast<int32_t>(sites.size());
+        for (int s = 0; s < p->N; ++s) {
+            BSite bs{};
+            bs.d = p->d[s];
+            bs.magic = ~uint64_t(0) / uint64_t(p->d[s]) + 1;
+            sites.push_back(bs);
+        }
+        // factor pool of this lattice: entry 0 is 1.0 (second factor of a one-site term)
+        std::vector<float> lp{1.0f};
+        auto table = [&](int s, int op) {
+            const int at = static_cast<int>(lp.size());
+            factor_table(p, s, op, lp);
+            return at;
+        };
+        auto add_term = [&](int a, int opa, int bsite, int opb, int param, double wr, double wi, int64_t delta) {
+            BTerm t{};
+            t.a = a;
+            t.ta = table(a, opa);
+            t.b = bsite;
+            t.tb = bsite >= 0 ? table(bsite, opb) : 0;
+            t.param = param;
+            t.delta = static_cast<int32_t>(delta);
+            t.wr = static_cast<float>(wr);
+            t.wi = static_cast<float>(wi);
+            if (wi != 0.0) b->all_real = false;
+            terms.push_back(t);
+        };
+        L.diag_off = static_cast<int32_t>(terms.size());
+        for (const auto& g : p->diags) add_term(g.a, g.opa, g.b, g.opb, g.param, g.wr, g.wi, 0);
+        L.n_diag = static_cast<int32_t>(p->diags.size());
+        L.chan_off = static_cast<int32_t>(terms.size());
+        for (const auto& c : p->chans) add_term(c.a, c.opa, c.b, c.opb, c.param, c.wr, c.wi, c.delta);
+        L.n_chan = static_cast<int32_t>(p->chans.size());
+        if (lp.size() > size_t(kBatchPoolMax)) {
+            delete b;
+            return MRMF_E_UNSUPPORTED;
+        }
+        L.pool_off = static_cast<int32_t>(pool.size());
+        L.pool_n = static_cast<int32_t>(lp.size());
+        pool.insert(pool.end(), lp.begin(), lp.end());
+        b->off.push_back(off);
+        b->th_off.push_back(th);
+        off += (p->D * nvec + 31) / 32 * 32;
+        th += p->n_params;
+    }
+    b->th_off.push_back(th);
+    b->total = off;
+    if (off * 8 >= (int64_t(1) << 62)) {
+        delete b;
+        return MRMF_E_OVERFLOW;
+    }
+    size_t o = 0;
+    b->off_lat = o;
+    o = align_up(o + sizeof(BLat) * lats.size(), 256);
+    b->off_site = o;
+    o = align_up(o + sizeof(BSite) * sites.size(), 256);
+    b->off_term = o;
+    o = align_up(o + sizeof(BTerm) * std::max<size_t>(1, terms.size()), 256);
+    b->off_pool = o;
+    o = align_up(o + sizeof(float) * pool.size(), 256);
+    b->ws_bytes = o;
+    b->image.assign(o, 0);
+    std::memcpy(b->image.data() + b->off_lat, lats.data(), sizeof(BLat) * lats.size());
+    std::memcpy(b->image.data() + b->off_site, sites.data(), sizeof(BSite) * sites.size());
+    if (!terms.empty()) std::memcpy(b->image.data() + b->off_term, terms.data(), sizeof(BTerm) * terms.size());
+    std::memcpy(b->image.data() + b->off_pool, pool.data(), sizeof(float) * pool.size());
+    *out = b;
+    return MRMF_OK;
+}
+
+void mrmf_batch_destroy(mrmf_batch batch) { delete batch; }
+
+mrmf_status mrmf_batch_total_elems(mrmf_batch b, int64_t* elems) {
+    if (!b || !elems) return MRMF_E_INVALID_ARG;
+    *elems = b->total;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_offsets(mrmf_batch b, int64_t* out) {
+    if (!b || !out) return MRMF_E_INVALID_ARG;
+    std::memcpy(out, b->off.data(), sizeof(int64_t) * b->n);
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_theta_offsets(mrmf_batch b, int32_t* out) {
+    if (!b || !out) return MRMF_E_INVALID_ARG;
+    std::memcpy(out, b->th_off.data(), sizeof(int32_t) * (b->n + 1));
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_workspace_bytes(mrmf_batch b, size_t* bytes) {
+    if (!b || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = b->ws_bytes;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_upload(mrmf_batch b, void* d_ws, size_t ws_bytes, mrmf_stream stream) {
+    if (!b || !d_ws || !mrmf::aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
+    if (ws_bytes < b->ws_bytes) return MRMF_E_WORKSPACE;
+    return mrmf::hip_status(hipMemcpyAsync(d_ws, b->image.data(), b->ws_bytes, hipMemcpyHostToDevice,
+                                           static_cast<hipStream_t>(stream)));
+}
+
+mrmf_status mrmf_batch_matvec_c(mrmf_batch b, const void* d_ws, const float* d_theta_all, const void* d_X,
+                                void* d_Y, mrmf_stream stream) {
+    const mrmf_status st = check_call(b, d_ws, d_theta_all, d_X, d_Y);
+    if (st != MRMF_OK) return st;
+    return launch(b, d_ws, d_theta_all, d_X, d_Y, static_cast<hipStream_t>(stream));
+}
+
+mrmf_status mrmf_batch_graph_capture(mrmf_batch b, const void* d_ws, const float* d_theta_all, const void* d_X,
+                                     void* d_Y, mrmf_stream stream) {
+    mrmf_status st = check_call(b, d_ws, d_theta_all, d_X, d_Y);
+    if (st != MRMF_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MRMF_E_HIP;
+    st = launch(b, d_ws, d_theta_all, d_X, d_Y, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != MRMF_OK || e != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return st != MRMF_OK ? st : MRMF_E_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return MRMF_E_HIP;
+    }
+    b->graph = g;
+    b->exec = ex;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_graph_launch(mrmf_batch b, mrmf_stream stream) {
+    if (!b || !b->exec) return MRMF_E_INVALID_ARG;
+    return mrmf::hip_status(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+}
+
+mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t rows_per_item, int32_t block_threads) {
+    if (!b || rows_per_item < 1 || block_threads < 64 || block_threads > mrmf::kBatchMaxBlock ||
+        block_threads % 64 != 0)
+        return MRMF_E_INVALID_ARG;
+    b->R = rows_per_item;
+    b->block = block_threads;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_theta_all, const void* d_X,
+                                void* d_Y, mrmf_stream stream, int32_t* out) {
+    mrmf_status st = check_call(b, d_ws, d_theta_all, d_X, d_Y);
+    if (st != MRMF_OK) return st;
+    if (!out) return MRMF_E_INVALID_ARG;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MRMF_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return MRMF_E_HIP;
+    }
+    float best = 0.f;
+    int best_i = -1;
+    const int32_t R0 = b->R, B0 = b->block;
+    for (int i = 0; i < mrmf::kNumShapes && st == MRMF_OK; ++i) {
+        b->R = mrmf::kShapes[i].R;
+        b->block = mrmf::kShapes[i].block;
+        st = launch(b, d_ws, d_theta_all, d_X, d_Y, s);  // warm-up
+        if (st != MRMF_OK) break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && st == MRMF_OK; ++r) st = launch(b, d_ws, d_theta_all, d_X, d_Y, s);
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) st = MRMF_E_HIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (st == MRMF_OK && (best_i < 0 || ms < best)) {
+            best = ms;
+            best_i = i;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_i < 0) {
+        b->R = R0;
+        b->block = B0;
+        return st != MRMF_OK ? st : MRMF_E_HIP;
+    }
+    b->R = mrmf::kShapes[best_i].R;
+    b->block = mrmf::kShapes[best_i].block;
+    out[0] = b->R;
+    out[1] = b->block;
+    out[2] = best_i;
+    return st;
+}
+
+}  // extern "C"

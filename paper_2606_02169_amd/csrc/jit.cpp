@@ -77,6 +77,9 @@ struct Gen {
     Tile tl;
     int block;
     int64_t n_st;
+    int sched = 0;       // MRMF_SCHED_*
+    bool bskip = false;  // skip a channel whose uniform digits are inadmissible with a scalar branch
+    int gs = 0;          // channels per load group (0: default)
 
     int SZ() const { return f32 ? 8 : 16; }
     bool is_inner(int s) const { return s >= tl.k_in; }
@@ -393,9 +396,19 @@ struct Gen {
           << "ll), (short)0, " << nrec << ", 0x00020000);\n"
           << "  __syncthreads();\n"
           << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
-          << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
-          << "  unsigned par = 0u;\n"
-          << "  for (unsigned t = v; t < " << n_st << "u; t += G) {\n";
+          << "  unsigned par = 0u;\n";
+        if (sched == MRMF_SCHED_XCD_CHUNK) {
+            // XCD x (= b mod 8) sweeps the contiguous range [x C, (x + 1) C) of super-tiles with its G / 8
+            // blocks side by side, so neighbouring super-tiles are read through the same L2
+            o << "  const unsigned nx = (G % 8u == 0u) ? 8u : 1u, GX = G / nx, xcd = b % nx;\n"
+              << "  const unsigned Cx = (" << n_st << "u + nx - 1u) / nx;\n"
+              << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
+              << "  for (unsigned t = xcd * Cx + b / nx; t < t_end; t += GX) {\n";
+        } else {
+            // the grid sweeps windows of G consecutive super-tiles; XCD x takes the x-th eighth of each
+            o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
+              << "  for (unsigned t = v; t < " << n_st << "u; t += G) {\n";
+        }
         std::set<int> uni_sites;
         for (const auto& c : P.chans) {
             if (!is_static(c.a)) uni_sites.insert(c.a);
@@ -420,9 +433,14 @@ struct Gen {
             }
             const std::string base = (kind(ch.a, ch.b) == 2 && lane) ? "vo" + std::to_string(c) : "voff";
             const std::string ad = admit_uniform(ch.a, ch.opa, ch.b, ch.opb);
-            o << "    const unsigned u" << c << " = " << (ad == "true" ? base : "(" + ad + ") ? " + base + " : OOB") << ";\n";
+            if (bskip) {
+                o << "    const bool q" << c << " = " << ad << ";\n";
+                o << "    const unsigned u" << c << " = " << base << ";\n";
+            } else {
+                o << "    const unsigned u" << c << " = " << (ad == "true" ? base : "(" + ad + ") ? " + base + " : OOB") << ";\n";
+            }
         }
-        const int GS = f32 ? 10 : 6;  // channels per load group
+        const int GS = gs > 0 ? gs : (f32 ? 10 : 6);  // channels per load group
         const int ngr = static_cast<int>((cG.size() + GS - 1) / GS);
         auto emit_loads = [&](int g) {
             for (int i = g * GS; i < std::min<int>(cG.size(), (g + 1) * GS); ++i) {
@@ -430,7 +448,11 @@ struct Gen {
                 const auto& ch = P.chans[c];
                 for (int64_t j = 0; j < PU; ++j) {
                     if (kind(ch.a, ch.b) == 2 && !fM.count({c, j})) continue;
-                    o << "    const C s" << c << "_" << j << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
+                    if (bskip)
+                        o << "    C s" << c << "_" << j << " = {(R)0, (R)0}; if (q" << c << ") s" << c << "_" << j
+                          << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
+                    else
+                        o << "    const C s" << c << "_" << j << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
                 }
             }
         };
@@ -497,8 +519,8 @@ struct Gen {
                 const int c = cG[i];
                 const auto& ch = P.chans[c];
                 const int idx = item_of_chan[c];
-                o << "    { const R kr = tr[par][" << idx << "];" << (cplx ? " const R ki = ti[par][" + std::to_string(idx) + "];" : "")
-                  << "\n";
+                o << "    " << (bskip ? "if (q" + std::to_string(c) + ") " : std::string("")) << "{ const R kr = tr[par]["
+                  << idx << "];" << (cplx ? " const R ki = ti[par][" + std::to_string(idx) + "];" : "") << "\n";
                 for (int64_t j = 0; j < PU; ++j) {
                     const std::string s = "s" + std::to_string(c) + "_" + std::to_string(j);
                     if (kind(ch.a, ch.b) == 1) {
@@ -609,6 +631,9 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     // every buffer offset below 2^31 bytes: rows plus both shifts
     if ((p->D + dmax - dmin + 2 * tl.T_in) * SZ >= (int64_t(1) << 31) || n_st >= (int64_t(1) << 31)) return "";
     Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
+    gen.sched = p->tune_sched;
+    gen.bskip = p->tune_bskip != 0;
+    gen.gs = p->tune_load_group;
     *tl_out = tl;
     return gen.source();
 }
@@ -662,6 +687,7 @@ mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    if (p->tune_blocks_per_cu > 0 && p->tune_blocks_per_cu < per_cu) per_cu = p->tune_blocks_per_cu;
     int64_t grid = int64_t(per_cu) * prop.multiProcessorCount;
     if (grid > n_st) grid = n_st;
     if (grid >= 8) grid -= grid % 8;
@@ -733,6 +759,35 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
             if (k.mod) hipModuleUnload(k.mod);
             k = mrmf::SpecKernel{};
         }
+    }
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
+    if (!plan) return MRMF_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(plan->mtx);
+    switch (knob) {
+        case MRMF_TUNE_SCHEDULE:
+            if (value != MRMF_SCHED_WINDOWS && value != MRMF_SCHED_XCD_CHUNK) return MRMF_E_INVALID_ARG;
+            plan->tune_sched = value;
+            break;
+        case MRMF_TUNE_BRANCH_SKIP:
+            if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
+            plan->tune_bskip = value;
+            break;
+        case MRMF_TUNE_LOAD_GROUP:
+            if (value < 0 || value > 64) return MRMF_E_INVALID_ARG;
+            plan->tune_load_group = value;
+            break;
+        case MRMF_TUNE_BLOCKS_PER_CU:
+            if (value < 0 || value > 32) return MRMF_E_INVALID_ARG;
+            plan->tune_blocks_per_cu = value;
+            break;
+        default: return MRMF_E_INVALID_ARG;
+    }
+    for (auto& k : plan->spec) {  // the next call regenerates the kernel
+        if (k.mod) hipModuleUnload(k.mod);
+        k = mrmf::SpecKernel{};
     }
     return MRMF_OK;
 }

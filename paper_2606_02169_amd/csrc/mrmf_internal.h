@@ -91,6 +91,7 @@ struct mrmf_plan_t {
     int64_t D = 1;
     int32_t n_params = 0;
     uint32_t flags = 0;
+    bool hermitian = false;  // every parameter group h_p equals its adjoint
     std::vector<mrmf::DevChan> chans;
     std::vector<mrmf::DevDiag> diags;
     std::vector<int32_t> tab;
@@ -105,6 +106,7 @@ struct mrmf_plan_t {
     int32_t kernel_mode = 0;
     int32_t inner_pref = 0;
     int32_t unroll_pref = -1;
+    int32_t tune_sched = MRMF_SCHED_WINDOWS, tune_bskip = 0, tune_load_group = 0, tune_blocks_per_cu = 0;
     mrmf::SpecKernel spec[2];
     std::mutex mtx;
     ~mrmf_plan_t();

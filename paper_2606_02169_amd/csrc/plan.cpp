@@ -137,7 +137,8 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
             return MRMF_E_INVALID_ARG;
         }
     }
-    if ((flags & MRMF_REQUIRE_HERMITIAN) && !groups_hermitian(p->terms, n_params)) {
+    p->hermitian = groups_hermitian(p->terms, n_params);
+    if ((flags & MRMF_REQUIRE_HERMITIAN) && !p->hermitian) {
         delete p;
         return MRMF_E_NOT_HERMITIAN;
     }

@@ -133,6 +133,24 @@ class Plan:
                _stream(self.device))
         return out
 
+    # ------------------------------------------------------------------ adjoint
+    def adjoint(self, theta: torch.Tensor, x: torch.Tensor, g: torch.Tensor):
+        """(grad_x, grad_theta) of y = H(theta) x for the upstream gradient g (mrmf_adjoint_z):
+        grad_x = H g (H Hermitian), grad_theta[p] = Re <g|h_p x>.  c128 / float64 only."""
+        _need_gpu(theta, "theta", torch.float64)
+        _need_gpu(x, "x", torch.complex128)
+        _need_gpu(g, "g", torch.complex128)
+        if x.numel() != self.D or g.numel() != self.D:
+            raise ValueError("x and g must have D entries")
+        gx = torch.empty_like(g)
+        gt = torch.empty(max(1, self.n_params), dtype=torch.float64, device=self.device)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_adjoint_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        L.call("mrmf_adjoint_z", self._handle, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(g), _ptr(gx),
+               _ptr(gt), _ptr(scratch), nb.value, _stream(self.device))
+        return gx, gt[: self.n_params]
+
     # ------------------------------------------------------------------ Lanczos
     def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",
                 reorth: str = "cgs2", theta_c: torch.Tensor | None = None, keep_basis: bool = False) -> dict:
@@ -174,6 +192,14 @@ class Plan:
         "auto"; inner_sites = 0 / unrolled_sites = -1 let the library pick the tiling."""
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
+    TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3}
+
+    def set_tuning(self, **knobs):
+        """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks), branch_skip
+        (0/1), load_group (channels issued ahead, 0 = default), blocks_per_cu (0 = as many as fit)."""
+        for k, v in knobs.items():
+            L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
+
     def prepare(self, dtype=torch.complex128):
         """Compile and load the kernel matvec will use for this element type (synchronous)."""
         dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
@@ -194,3 +220,103 @@ class Plan:
         buf = ctypes.create_string_buffer(n.value + 1)
         L.call("mrmf_plan_kernel_source", self._handle, dt, buf, n.value + 1, ctypes.byref(n))
         return buf.value.decode()
+
+
+class MatvecFn(torch.autograd.Function):
+    """y = H(theta) x with a hand-written backward: grad_x = H g (Hermitian H) and
+    grad_theta[p] = Re <g|h_p x>, both from one mrmf_adjoint_z call.  Usage:
+    ``MatvecFn.apply(plan, theta, x)`` with theta float64 and x complex128 on the GPU."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, theta: torch.Tensor, x: torch.Tensor):
+        ctx.plan = plan
+        ctx.save_for_backward(theta, x)
+        return plan.matvec(theta.detach().contiguous(), x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        theta, x = ctx.saved_tensors
+        gx, gt = ctx.plan.adjoint(theta.detach().contiguous(), x.detach().contiguous(), g.contiguous())
+        return None, (gt if ctx.needs_input_grad[1] else None), (gx if ctx.needs_input_grad[2] else None)
+
+
+class Batch:
+    """Many lattices applied to blocks of nvec c64 vectors in one persistent launch
+    (mrmf_batch_matvec_c).  X and Y are flat complex64 tensors of total_elems entries; lattice b's
+    block [D_b, nvec] starts at offsets[b].  theta_all is float32, the parameters of lattice 0, then
+    lattice 1, ... (theta_offsets)."""
+
+    def __init__(self, plans: Sequence[Plan], nvec: int = 8):
+        self.plans = list(plans)          # the batch keeps pointers into its plans' host data
+        self.nvec = int(nvec)
+        self.device = self.plans[0].device
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self._handle = ctypes.c_void_p()
+        L.call("mrmf_batch_create", len(self.plans), arr, self.nvec, ctypes.byref(self._handle))
+        n = len(self.plans)
+        te = ctypes.c_int64()
+        L.call("mrmf_batch_total_elems", self._handle, ctypes.byref(te))
+        self.total_elems = int(te.value)
+        offs = (ctypes.c_int64 * n)()
+        L.call("mrmf_batch_offsets", self._handle, offs)
+        self.offsets = [int(v) for v in offs]
+        tho = (ctypes.c_int32 * (n + 1))()
+        L.call("mrmf_batch_theta_offsets", self._handle, tho)
+        self.theta_offsets = [int(v) for v in tho]
+        nb = ctypes.c_size_t()
+        L.call("mrmf_batch_workspace_bytes", self._handle, ctypes.byref(nb))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        L.call("mrmf_batch_upload", self._handle, _ptr(self.ws), nb.value, _stream(self.device))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib().mrmf_batch_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    def block(self, T: torch.Tensor, b: int) -> torch.Tensor:
+        """View of lattice b's [D_b, nvec] block inside a flat batch tensor."""
+        D = self.plans[b].D
+        return T[self.offsets[b]: self.offsets[b] + D * self.nvec].view(D, self.nvec)
+
+    def _check(self, theta_all, X, Y):
+        _need_gpu(theta_all, "theta_all", torch.float32)
+        _need_gpu(X, "X", torch.complex64)
+        _need_gpu(Y, "Y", torch.complex64)
+        if X.numel() < self.total_elems or Y.numel() < self.total_elems:
+            raise ValueError("X and Y need total_elems entries")
+        if theta_all.numel() < self.theta_offsets[-1]:
+            raise ValueError("theta_all is too short")
+
+    def matvec(self, theta_all: torch.Tensor, X: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
+        Y = torch.empty_like(X) if Y is None else Y
+        self._check(theta_all, X, Y)
+        L.call("mrmf_batch_matvec_c", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
+               _stream(self.device))
+        return Y
+
+    def capture(self, theta_all: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, stream: torch.cuda.Stream):
+        """Capture the launch for these buffers into a hipGraph owned by the batch (on a non-default
+        stream); replay() launches it."""
+        self._check(theta_all, X, Y)
+        L.call("mrmf_batch_graph_capture", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
+               ctypes.c_void_p(stream.cuda_stream))
+
+    def replay(self, stream: torch.cuda.Stream | None = None):
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        L.call("mrmf_batch_graph_launch", self._handle, ctypes.c_void_p(s))
+
+    def autotune(self, theta_all: torch.Tensor, X: torch.Tensor, Y: torch.Tensor) -> dict:
+        """Time every candidate launch shape on these buffers and keep the fastest."""
+        self._check(theta_all, X, Y)
+        out = (ctypes.c_int32 * 3)()
+        L.call("mrmf_batch_autotune", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
+               _stream(self.device), out)
+        return dict(rows_per_item=out[0], block=out[1], candidate=out[2])
+
+    def set_shape(self, rows_per_item: int, block: int):
+        L.call("mrmf_batch_set_shape", self._handle, int(rows_per_item), int(block))

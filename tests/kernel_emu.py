@@ -25,11 +25,18 @@ CLANG = "/opt/rocm/llvm/bin/clang++"
 CACHE = os.path.join(tempfile.gettempdir(), "mrmf_emu_cache")
 
 
-def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True) -> str | None:
+TUNING = {"schedule": L.MRMF_TUNE_SCHEDULE, "branch_skip": L.MRMF_TUNE_BRANCH_SKIP,
+          "load_group": L.MRMF_TUNE_LOAD_GROUP, "blocks_per_cu": L.MRMF_TUNE_BLOCKS_PER_CU}
+
+
+def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True,
+                  tuning=None) -> str | None:
     st, h = host_plan(model, require_hermitian=require_hermitian)
     assert st == 0, st
     try:
         L.call("mrmf_plan_set_kernel", h, L.MRMF_KERNEL_SPECIALIZED, int(inner), int(unrolled))
+        for k, v in (tuning or {}).items():
+            L.call("mrmf_plan_set_tuning", h, TUNING[k], int(v))
         n = ctypes.c_size_t()
         s = L.lib().mrmf_plan_kernel_source(h, dtype, None, 0, ctypes.byref(n))
         if s != 0:
@@ -72,11 +79,11 @@ def launch_shape(src: str):
 
 
 def run(model, x: np.ndarray, theta=None, inner: int = 0, unrolled: int = -1, grid: int | None = None,
-        require_hermitian=True) -> np.ndarray:
+        require_hermitian=True, tuning=None) -> np.ndarray:
     """y = H x with the generated kernel, emulated on the CPU."""
     f32 = x.dtype == np.complex64
     src = kernel_source(model, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z, inner, unrolled,
-                        require_hermitian=require_hermitian)
+                        require_hermitian=require_hermitian, tuning=tuning)
     if src is None:
         raise ValueError("the plan does not qualify for the specialized kernel")
     block, tiles = launch_shape(src)

@@ -1,0 +1,113 @@
+"""Batched persistent form (mrmf_batch_matvec_c): every lattice block against the oracle (c64, 2e-5
+relative per lattice and vector), hipGraph replays against the eager launch, and the autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import mf
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+TOL_C = 2e-5
+
+
+def build(models, xs, nvec=8):
+    from paper_2606_02169_amd.plan import Batch, Plan
+    plans = [Plan.from_model(m) for m in models]
+    B = Batch(plans, nvec)
+    X = torch.zeros(B.total_elems, dtype=torch.complex64, device=DEV)
+    for b, x in enumerate(xs):
+        B.block(X, b).copy_(torch.from_numpy(np.ascontiguousarray(x)).to(DEV))
+    th = np.concatenate([m.theta for m in models]).astype(np.float32)
+    return B, X, torch.from_numpy(th).to(DEV)
+
+
+def check_all(B, models, xs, Y, rows=None):
+    for b, (m, x) in enumerate(zip(models, xs)):
+        yb = B.block(Y, b).cpu().numpy()
+        for v in range(x.shape[1]):
+            xv = x[:, v].astype(np.complex128)
+            if rows is None:
+                ref = mf.matvec(m, xv, theta=m.theta.astype(np.float32).astype(np.float64))
+                got = yb[:, v]
+            else:
+                r = rows(m.dim)
+                ref = mf.matvec(m, xv, theta=m.theta.astype(np.float32).astype(np.float64), rows=r)
+                got = yb[r, v]
+            assert rel_err(got, ref) <= TOL_C, (b, v)
+
+
+def test_batch_reduced_against_oracle():
+    models, xs = W.config(4, reduced=24)
+    B, X, th = build(models, xs)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    check_all(B, models, xs, Y)
+
+
+@pytest.mark.parametrize("nvec", [1, 2, 4])
+def test_batch_other_widths(nvec):
+    rng = np.random.default_rng(100 + nvec)
+    models = [W.random_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=3000) for _ in range(7)]
+    xs = [W.random_state(m.dim, rng, np.complex64, nvec=nvec) for m in models]
+    B, X, th = build(models, xs, nvec)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    check_all(B, models, xs, Y)
+
+
+def test_batch_graph_replays_match_eager():
+    models, xs = W.config(4, reduced=16)
+    B, X, th = build(models, xs)
+    Y_eager = B.matvec(th, X)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    Yg = torch.zeros_like(X)
+    B.capture(th, X, Yg, s)
+    for k in range(4):
+        Yg.zero_()
+        torch.cuda.synchronize()
+        B.replay(s)
+        s.synchronize()
+        assert torch.equal(Yg, Y_eager), k
+        X.mul_(1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batch_autotune_keeps_results():
+    models, xs = W.config(4, reduced=16)
+    B, X, th = build(models, xs)
+    Y0 = B.matvec(th, X).clone()
+    Y = torch.empty_like(X)
+    best = B.autotune(th, X, Y)
+    print(best, flush=True)
+    assert best["rows_per_item"] > 0 and best["block"] % 64 == 0
+    Y1 = B.matvec(th, X)
+    torch.cuda.synchronize()
+    assert rel_err(Y1.cpu().numpy(), Y0.cpu().numpy()) <= 1e-6
+
+
+def test_batch_full_size_sampled():
+    """256 open mixed-spin chains (N in 8..16, 2s in {1,2,3}, D <= 2^22), blocks of 8 vectors."""
+    models, xs = W.config(4)
+    dims = [m.dim for m in models]
+    print(f"lattices {len(models)} sum D {sum(dims)} max D {max(dims)} min D {min(dims)}", flush=True)
+    B, X, th = build(models, xs)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+
+    def rows(D):
+        k = min(D, 300)
+        return np.unique(np.concatenate([np.arange(min(D, 40)), np.arange(max(0, D - 40), D),
+                                         rng.choice(D, k, replace=False)])).astype(np.int64)
+    for b in range(0, len(models), 8):
+        m, x = models[b], xs[b]
+        yb = B.block(Y, b).cpu().numpy()
+        r = rows(m.dim)
+        for v in (0, 7):
+            ref = mf.matvec(m, x[:, v].astype(np.complex128), theta=m.theta.astype(np.float32).astype(np.float64),
+                            rows=r)
+            assert rel_err(yb[r, v], ref) <= TOL_C, (b, v)

@@ -56,3 +56,13 @@ def test_random_models(seed):
             continue
         assert rel_err(y, mf.matvec(m, x)) <= TOL_Z
     check(m, x.astype(np.complex64), require_hermitian=herm)
+
+
+@pytest.mark.parametrize("tuning,grid", [({"schedule": 1}, 8), ({"schedule": 1}, 5), ({"branch_skip": 1}, 8),
+                                         ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16)])
+def test_tuning_variants(tuning, grid):
+    m, x = W.config(2, reduced=12)
+    check(m, x, tuning=tuning, grid=grid)
+    check(m, x.astype(np.complex64), tuning=tuning, grid=grid, unrolled=1)
+    m3, x3 = W.config(3, reduced=3)
+    check(m3, x3, tuning=tuning, grid=grid, inner=4, unrolled=1)
