@@ -138,11 +138,19 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *   MRMF_TUNE_BRANCH_SKIP   : 1 = a channel whose tile-uniform source digits are inadmissible is skipped
  *                             by a scalar branch; 0 = its loads are issued and masked.
  *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default).
- *   MRMF_TUNE_BLOCKS_PER_CU : cap on resident blocks per compute unit (0 = as many as fit). */
+ *   MRMF_TUNE_BLOCKS_PER_CU : cap on resident blocks per compute unit (0 = as many as fit).
+ *   MRMF_TUNE_VARIANT       : MRMF_VARIANT_MASKED - every channel that reads outside the super-tile is
+ *                                                   issued, masked when inadmissible;
+ *                             MRMF_VARIANT_LIST   - those channels are compacted per super-tile into a
+ *                                                   list of admissible ones that every thread walks
+ *                                                   (MRMF_TUNE_LOAD_GROUP = gathers per chunk). */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
 #define MRMF_TUNE_BLOCKS_PER_CU 3
+#define MRMF_TUNE_VARIANT 4
+#define MRMF_VARIANT_MASKED 0
+#define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0
 #define MRMF_SCHED_XCD_CHUNK 1
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);

@@ -80,6 +80,7 @@ struct Gen {
     int sched = 0;       // MRMF_SCHED_*
     bool bskip = false;  // skip a channel whose uniform digits are inadmissible with a scalar branch
     int gs = 0;          // channels per load group (0: default)
+    int variant = 0;     // MRMF_VARIANT_*
 
     int SZ() const { return f32 ? 8 : 16; }
     bool is_inner(int s) const { return s >= tl.k_in; }
@@ -153,6 +154,20 @@ struct Gen {
         add(a, opa);
         add(b, opb);
         return c.empty() ? "true" : c;
+    }
+
+    // The masked form computes each tile-uniform coefficient on one lane of the first waves, so its
+    // items (uniform and mixed channels, mixed diagonal terms) and its summed uniform diagonal terms
+    // must each fit in the block.
+    bool masked_fits() const {
+        int nit = 0, nsum = 0;
+        for (const auto& c : p->chans) nit += kind(c.a, c.b) != 0;
+        for (const auto& g : p->diags) {
+            const int k = kind(g.a, g.b);
+            nit += k == 2;
+            nsum += k == 1;
+        }
+        return nit <= block && nsum <= block;
     }
 
     std::string source() {
@@ -569,6 +584,444 @@ struct Gen {
         full << "};\n" << pre.str() << o.str();
         return full.str();
     }
+    // Second form of the generated kernel.  Per super-tile, the channels that read outside it (uniform and
+    // mixed) are not issued as masked loads: a few lanes evaluate their tile-uniform admissibility and
+    // coefficient and append the admissible ones, per unrolled copy, to a compact list in LDS (ballot
+    // and prefix count, so the order is deterministic); every thread then walks the list in chunks of U
+    // entries, issuing U gathers before their U accumulations.  A mixed channel's per-row factor (its
+    // inner-site part, zero where that digit is inadmissible) comes from a per-thread LDS table indexed by
+    // the entry's group.  The self rows of the next super-tile are loaded before the current one is
+    // computed.
+    std::string source_v2() {
+        const mrmf_plan_t& P = *p;
+        const int sz = SZ();
+        const int nch = static_cast<int>(P.chans.size()), ndg = static_cast<int>(P.diags.size());
+        const int64_t T = tl.T_in, PU = tl.P_U, st = ST();
+        bool cplx = false;
+        for (const auto& c : P.chans) cplx |= c.wi != 0.0;
+        for (const auto& g : P.diags) cplx |= g.wi != 0.0;
+        std::vector<int> cS, cG, gS, gU, gM;
+        for (int c = 0; c < nch; ++c) (kind(P.chans[c].a, P.chans[c].b) == 0 ? cS : cG).push_back(c);
+        for (int g = 0; g < ndg; ++g) {
+            const int k = kind(P.diags[g].a, P.diags[g].b);
+            (k == 0 ? gS : k == 1 ? gU : gM).push_back(g);
+        }
+        int64_t dmax = 0, halo = 0;
+        for (const auto& c : P.chans) dmax = std::max<int64_t>(dmax, c.delta);
+        for (int c : cS) {
+            const auto& ch = P.chans[c];
+            int64_t di = 0;
+            if (is_inner(ch.a)) di += int64_t(ch.qa) * P.M[ch.a];
+            if (ch.b >= 0 && is_inner(ch.b)) di += int64_t(ch.qb) * P.M[ch.b];
+            halo = std::max<int64_t>(halo, di < 0 ? -di : di);
+        }
+        const int64_t shift = (dmax + T) * sz;
+        const int64_t nrec = (P.D + dmax + T) * sz;
+        const bool use_lds = !cS.empty();
+        const int64_t xrows = st + 2 * halo + 1;
+        const int nw = block / 64;
+        const int U = gs > 0 ? gs : (f32 ? 8 : 6);  // gathers issued per chunk of the list
+
+        // lane groups: (inner site, operator) of a mixed channel's per-row factor; group 0 is 1.0, the
+        // last group is the sentinel 0.0
+        std::map<std::pair<int, int>, int> group_of;
+        auto lane_group = [&](int a, int opa, int b, int opb) {
+            int s = -1, op = 0;
+            if (is_inner(a)) { s = a; op = opa; }
+            if (b >= 0 && is_inner(b)) {
+                if (s >= 0) return -2;  // both inner: only a static channel can have that
+                s = b;
+                op = opb;
+            }
+            if (s < 0) return 0;
+            auto it = group_of.find({s, op});
+            if (it != group_of.end()) return it->second;
+            const int g = static_cast<int>(group_of.size()) + 1;
+            group_of[{s, op}] = g;
+            return g;
+        };
+        // list items per copy: (channel, copy) with a nonzero unrolled factor
+        struct Item {
+            int c, j, grp;
+            double ufac;
+        };
+        std::vector<std::vector<Item>> items(PU);
+        for (int64_t j = 0; j < PU; ++j) {
+            for (int c : cG) {
+                const auto& ch = P.chans[c];
+                double u = 1.0;
+                auto mul_unrolled = [&](int s, int op) {
+                    if (s >= 0 && is_unrolled(s)) u *= factor_table(p, s, op)[udigit(s, j)];
+                };
+                mul_unrolled(ch.a, ch.opa);
+                mul_unrolled(ch.b, ch.opb);
+                if (u == 0.0) continue;
+                items[j].push_back({c, static_cast<int>(j), lane_group(ch.a, ch.opa, ch.b, ch.opb), u});
+            }
+        }
+        const int NG = static_cast<int>(group_of.size()) + 2;  // + one, + sentinel
+        const int ZG = NG - 1;
+        int cap = 1, NI = 0;
+        std::vector<int> ioff(PU + 1, 0);
+        for (int64_t j = 0; j < PU; ++j) {
+            cap = std::max<int>(cap, static_cast<int>(items[j].size()));
+            ioff[j + 1] = ioff[j] + static_cast<int>(items[j].size());
+        }
+        NI = ioff[PU];
+        const int CAP = cap + U;  // room for the sentinel tail
+        // diagonal items of the uniform kind (summed) and mixed kind (uniform part per tile)
+        const int nsum = static_cast<int>(gU.size()), nmd = static_cast<int>(gM.size());
+
+        std::ostringstream pre, o;
+        const size_t one = pool_add("ONE", {1.0});
+        // tables of a uniform part: up to two uniform sites (quotient magic by the site multiplier counted
+        // in super-tiles, dimension and its magic, factor-table offset; an absent site has quotient magic 1,
+        // hence digit 0, dimension 1 and the 1.0 entry), parameter, weight
+        auto emit_tab = [&](const std::string& pfx, const std::vector<std::tuple<int, int, int, int, int, double, double>>& its,
+                            const std::vector<int32_t>* soffs, const std::vector<int32_t>* grps) {
+            const int n = std::max<int>(1, its.size());
+            std::ostringstream mam, da, dam, ta, mbm, db, dbm, tb, pr, wr, wi, so, gr;
+            for (size_t i = 0; i < its.size(); ++i) {
+                std::vector<std::array<uint64_t, 3>> ss;
+                for (auto sop : {std::make_pair(std::get<0>(its[i]), std::get<1>(its[i])),
+                                 std::make_pair(std::get<2>(its[i]), std::get<3>(its[i]))}) {
+                    if (sop.first < 0 || is_static(sop.first)) continue;
+                    ss.push_back({static_cast<uint64_t>(P.M[sop.first] / st), static_cast<uint64_t>(P.d[sop.first]),
+                                  static_cast<uint64_t>(ftab(sop.first, sop.second))});
+                }
+                while (ss.size() < 2) ss.push_back({0, 1, static_cast<uint64_t>(one)});
+                const char* sep = i ? ", " : "";
+                mam << sep << ulit(ss[0][0] == 0 ? 1 : ss[0][0] == 1 ? 0 : magic_of(ss[0][0]));
+                da << sep << ss[0][1] << "u";
+                dam << sep << ulit(magic_of(ss[0][1]));
+                ta << sep << ss[0][2] << "u";
+                mbm << sep << ulit(ss[1][0] == 0 ? 1 : ss[1][0] == 1 ? 0 : magic_of(ss[1][0]));
+                db << sep << ss[1][1] << "u";
+                dbm << sep << ulit(magic_of(ss[1][1]));
+                tb << sep << ss[1][2] << "u";
+                pr << sep << std::get<4>(its[i]);
+                wr << sep << lit(std::get<5>(its[i]), f32);
+                wi << sep << lit(std::get<6>(its[i]), f32);
+                if (soffs) so << sep << (*soffs)[i];
+                if (grps) gr << sep << (*grps)[i];
+            }
+            auto arr = [&](const char* ty, const char* nm, std::ostringstream& v) {
+                const std::string s = v.str();
+                pre << "__constant__ " << ty << " " << pfx << nm << "[" << n << "] = {" << (s.empty() ? "0" : s) << "};\n";
+            };
+            arr("unsigned long long", "mam", mam);
+            arr("unsigned", "da", da);
+            arr("unsigned long long", "dam", dam);
+            arr("unsigned", "ta", ta);
+            arr("unsigned long long", "mbm", mbm);
+            arr("unsigned", "db", db);
+            arr("unsigned long long", "dbm", dbm);
+            arr("unsigned", "tb", tb);
+            arr("int", "pr", pr);
+            arr("R", "wr", wr);
+            arr("R", "wi", wi);
+            if (soffs) arr("int", "so", so);
+            if (grps) arr("int", "gr", gr);
+        };
+        {
+            std::vector<std::tuple<int, int, int, int, int, double, double>> its;
+            std::vector<int32_t> soffs, grps;
+            for (int64_t j = 0; j < PU; ++j)
+                for (const Item& it : items[j]) {
+                    const auto& ch = P.chans[it.c];
+                    its.emplace_back(ch.a, ch.opa, ch.b, ch.opb, ch.param, ch.wr * it.ufac, ch.wi * it.ufac);
+                    soffs.push_back(static_cast<int32_t>(j * T * sz - ch.delta * sz));
+                    grps.push_back(it.grp);
+                }
+            emit_tab("E", its, &soffs, &grps);
+            std::vector<std::tuple<int, int, int, int, int, double, double>> md, us;
+            for (int g : gM) {
+                const auto& dg = P.diags[g];
+                md.emplace_back(dg.a, dg.opa, dg.b, dg.opb, dg.param, dg.wr, dg.wi);
+            }
+            for (int g : gU) {
+                const auto& dg = P.diags[g];
+                us.emplace_back(dg.a, dg.opa, dg.b, dg.opb, dg.param, dg.wr, dg.wi);
+            }
+            emit_tab("M", md, nullptr, nullptr);
+            emit_tab("Q", us, nullptr, nullptr);
+        }
+        o << "__device__ __forceinline__ unsigned dig(unsigned t, unsigned long long mm, unsigned d, unsigned long long dm) {\n"
+          << "  const unsigned q = mm ? (unsigned)__umul64hi(mm, (unsigned long long)t) : t;\n"
+          << "  return q - (unsigned)__umul64hi(dm, (unsigned long long)q) * d;\n}\n";
+        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void mrmf_spec(const R* __restrict__ theta,\n"
+          << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
+          << "  if (skip != nullptr && *skip != 0) return;\n";
+        const bool dbuf = use_lds && 2 * xrows * sz <= 49152;
+        if (use_lds) o << "  __shared__ C xl[" << (dbuf ? 2 : 1) * xrows << "];\n";
+        o << "  __shared__ int lso[2][" << PU * CAP << "];\n"
+          << "  __shared__ int lgr[2][" << PU * CAP << "];\n"
+          << "  __shared__ R lcr[2][" << PU * CAP << "];\n";
+        if (cplx) o << "  __shared__ R lci[2][" << PU * CAP << "];\n";
+        o << "  __shared__ int lcn[2][" << PU << "];\n"
+          << "  __shared__ R lfac[" << NG * block << "];\n";
+        if (nmd > 0) {
+            o << "  __shared__ R tr[2][" << nmd << "];\n";
+            if (cplx) o << "  __shared__ R ti[2][" << nmd << "];\n";
+        }
+        const int swaves = std::min(nw, (nsum + 63) / 64);
+        if (nsum > 0) {
+            o << "  __shared__ R dsr[2][" << swaves << "];\n";
+            if (cplx) o << "  __shared__ R dsi[2][" << swaves << "];\n";
+        }
+        o << "  __shared__ R Kl[KN_ALLOC];\n";
+        o << "  const unsigned tid = threadIdx.x, wv = tid >> 6, ln = tid & 63u;\n"
+          << "  const bool act = tid < " << T << "u;\n"
+          << "  const unsigned r = act ? tid : 0u;\n"
+          << "  const unsigned OOB = 0x80000000u;\n"
+          << "  const unsigned voff = act ? r * " << sz << "u : OOB;\n";
+        if (use_lds) {
+            o << "  for (unsigned i = tid; i < " << halo << "u; i += " << block << "u) {\n"
+              << "    const C z = {(R)0, (R)0};\n";
+            for (int b = 0; b < (dbuf ? 2 : 1); ++b)
+                o << "    xl[" << b * xrows << "u + i] = z; xl[" << b * xrows + halo + st << "u + i] = z;\n";
+            o << "  }\n";
+            for (int64_t j = 0; j < PU; ++j)
+                o << "  const unsigned w" << j << " = act ? " << halo + j * T << "u + r : " << xrows - 1 << "u;\n";
+        }
+        o << "  for (unsigned i = tid; i < KN; i += " << block << "u) Kl[i] = K[i];\n";
+        std::set<int> lane_sites, used_params;
+        for (const auto& c : P.chans) {
+            if (is_inner(c.a)) lane_sites.insert(c.a);
+            if (c.b >= 0 && is_inner(c.b)) lane_sites.insert(c.b);
+            used_params.insert(c.param);
+        }
+        for (const auto& g : P.diags) {
+            if (is_inner(g.a)) lane_sites.insert(g.a);
+            if (g.b >= 0 && is_inner(g.b)) lane_sites.insert(g.b);
+            used_params.insert(g.param);
+        }
+        for (int s : lane_sites) o << "  const unsigned n" << s << " = (r / " << P.M[s] << "u) % " << P.d[s] << "u;\n";
+        for (int q : used_params) o << "  const R th" << q << " = theta[" << q << "];\n";
+        auto wexpr = [&](int param, double w) { return "th" + std::to_string(param) + " * " + lit(w, f32); };
+        // per-thread group factors
+        o << "  lfac[tid] = act ? (R)1 : (R)0;\n"
+          << "  lfac[" << ZG * block << "u + tid] = (R)0;\n";
+        for (const auto& kv : group_of)
+            o << "  lfac[" << kv.second * block << "u + tid] = act ? " << lane_fac(kv.first.first, kv.first.second)
+              << " : (R)0;\n";
+        // static channel coefficients per copy (registers)
+        std::map<std::pair<int, int64_t>, std::string> kS;
+        for (int c : cS) {
+            const auto& ch = P.chans[c];
+            const bool unr = has_unrolled(ch.a, ch.b);
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(ch.a, ch.opa, ch.b, ch.opb, j);
+                if (sp.first == 0.0) continue;
+                if (!unr && j > 0 && kS.count({c, 0})) {
+                    kS[{c, j}] = kS[{c, 0}];
+                    continue;
+                }
+                const std::string nm = "k" + std::to_string(c) + "_" + std::to_string(j);
+                const std::string le = sp.second.empty() ? std::string("(R)1") : sp.second;
+                o << "  const R " << nm << "r = act ? " << wexpr(ch.param, ch.wr) << " * " << lit(sp.first, f32) << " * " << le
+                  << " : (R)0;\n";
+                if (cplx)
+                    o << "  const R " << nm << "i = act ? " << wexpr(ch.param, ch.wi) << " * " << lit(sp.first, f32) << " * "
+                      << le << " : (R)0;\n";
+                kS[{c, j}] = nm;
+            }
+        }
+        // static diagonal weight per copy; static factor of the mixed diagonal terms per copy
+        for (int64_t j = 0; j < PU; ++j) {
+            o << "  R dS" << j << "r = 0, dS" << j << "i = 0;\n";
+            for (int g : gS) {
+                const auto& dg = P.diags[g];
+                const auto sp = static_part(dg.a, dg.opa, dg.b, dg.opb, j);
+                if (sp.first == 0.0) continue;
+                const std::string le = sp.second.empty() ? std::string("(R)1") : sp.second;
+                o << "  { const R f = " << lit(sp.first, f32) << " * " << le << "; dS" << j << "r += " << wexpr(dg.param, dg.wr)
+                  << " * f;";
+                if (cplx) o << " dS" << j << "i += " << wexpr(dg.param, dg.wi) << " * f;";
+                o << " }\n";
+            }
+        }
+        std::map<std::pair<int, int64_t>, std::string> fD;
+        for (int i = 0; i < nmd; ++i) {
+            const auto& dg = P.diags[gM[i]];
+            for (int64_t j = 0; j < PU; ++j) {
+                const auto sp = static_part(dg.a, dg.opa, dg.b, dg.opb, j);
+                if (sp.first == 0.0) continue;
+                const std::string nm = "z" + std::to_string(i) + "_" + std::to_string(j);
+                o << "  const R " << nm << " = " << lit(sp.first, f32) << " * " << (sp.second.empty() ? "(R)1" : sp.second)
+                  << ";\n";
+                fD[{i, j}] = nm;
+            }
+        }
+        o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
+          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+          << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
+          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+          << "  __syncthreads();\n"
+          << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
+          << "  unsigned par = 0u;\n";
+        if (sched == MRMF_SCHED_XCD_CHUNK) {
+            o << "  const unsigned nx = (G % 8u == 0u) ? 8u : 1u, GX = G / nx, xcd = b % nx;\n"
+              << "  const unsigned Cx = (" << n_st << "u + nx - 1u) / nx;\n"
+              << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
+              << "  const unsigned t_step = GX;\n"
+              << "  unsigned t = xcd * Cx + b / nx;\n";
+        } else {
+            o << "  const unsigned t_end = " << n_st << "u, t_step = G;\n"
+              << "  unsigned t = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n";
+        }
+        auto soff = [&](int64_t j, int64_t delta, const std::string& base) {
+            std::ostringstream s;
+            s << base << " + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
+            return s.str();
+        };
+        // self rows of the first super-tile
+        for (int64_t j = 0; j < PU; ++j)
+            o << "  C xn" << j << " = {(R)0, (R)0};\n";
+        o << "  if (t < t_end) {\n    const unsigned Fn = t * " << st * sz << "u + " << shift << "u;\n";
+        for (int64_t j = 0; j < PU; ++j) o << "    xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
+        o << "  }\n";
+        o << "  for (; t < t_end; t += t_step) {\n"
+          << "    const unsigned F0 = t * " << st * sz << "u + " << shift << "u;\n";
+        for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = xn" << j << ";\n";
+        if (use_lds) {
+            o << "    C* lb = xl" << (dbuf ? " + par * " + std::to_string(xrows) + "u" : std::string("")) << ";\n";
+            for (int64_t j = 0; j < PU; ++j) o << "    lb[w" << j << "] = x" << j << ";\n";
+        }
+        // list construction: wave w builds the lists of copies j = w, w + nw, ...
+        if (NI > 0) {
+            o << "    for (unsigned j = wv; j < " << PU << "u; j += " << nw << "u) {\n"
+              << "      unsigned base = 0u;\n"
+              << "      const unsigned i0 = Eoff[j], ni = Eoff[j + 1u] - i0;\n"
+              << "      for (unsigned h = 0u; h < ni; h += 64u) {\n"
+              << "        const unsigned i = h + ln;\n"
+              << "        const bool has = i < ni;\n"
+              << "        const unsigned e = i0 + (has ? i : 0u);\n"
+              << "        const unsigned na = dig(t, Emam[e], Eda[e], Edam[e]), nb = dig(t, Embm[e], Edb[e], Edbm[e]);\n"
+              << "        const R f = Kl[Eta[e] + na] * Kl[Etb[e] + nb];\n"
+              << "        const bool adm = has && f != (R)0;\n"
+              << "        const unsigned long long m = __ballot(adm);\n"
+              << "        if (adm) {\n"
+              << "          const unsigned pos = base + (unsigned)__popcll(m & ((1ull << ln) - 1ull));\n"
+              << "          const unsigned q = j * " << CAP << "u + pos;\n"
+              << "          const R th = theta[Epr[e]] * f;\n"
+              << "          lso[par][q] = Eso[e]; lgr[par][q] = Egr[e]; lcr[par][q] = th * Ewr[e];\n"
+              << (cplx ? "          lci[par][q] = th * Ewi[e];\n" : "")
+              << "        }\n"
+              << "        base += (unsigned)__popcll(m);\n"
+              << "      }\n"
+              << "      if (ln < " << U << "u) {\n"
+              << "        const unsigned q = j * " << CAP << "u + base + ln;\n"
+              << "        lso[par][q] = 0; lgr[par][q] = " << ZG << "; lcr[par][q] = (R)0;\n"
+              << (cplx ? "        lci[par][q] = (R)0;\n" : "")
+              << "      }\n"
+              << "      if (ln == 0u) lcn[par][j] = base;\n"
+              << "    }\n";
+            std::ostringstream eo;
+            for (int64_t j = 0; j <= PU; ++j) eo << (j ? ", " : "") << ioff[j] << "u";
+            pre << "__constant__ unsigned Eoff[" << PU + 1 << "] = {" << eo.str() << "};\n";
+        }
+        // mixed diagonal uniform parts and the uniform diagonal sum (first waves)
+        if (nmd > 0) {
+            o << "    for (unsigned i = tid; i < " << nmd << "u; i += " << block << "u) {\n"
+              << "      const unsigned na = dig(t, Mmam[i], Mda[i], Mdam[i]), nb = dig(t, Mmbm[i], Mdb[i], Mdbm[i]);\n"
+              << "      const R f = theta[Mpr[i]] * Kl[Mta[i] + na] * Kl[Mtb[i] + nb];\n"
+              << "      tr[par][i] = f * Mwr[i];\n"
+              << (cplx ? "      ti[par][i] = f * Mwi[i];\n" : "")
+              << "    }\n";
+        }
+        if (nsum > 0) {
+            o << "    if (wv < " << swaves << "u) {\n"
+              << "      R vr = (R)0, vi = (R)0;\n"
+              << "      for (unsigned i = tid; i < " << nsum << "u; i += " << swaves * 64 << "u) {\n"
+              << "        const unsigned ma = dig(t, Qmam[i], Qda[i], Qdam[i]), mb = dig(t, Qmbm[i], Qdb[i], Qdbm[i]);\n"
+              << "        const R g = theta[Qpr[i]] * Kl[Qta[i] + ma] * Kl[Qtb[i] + mb];\n"
+              << "        vr += g * Qwr[i]; vi += g * Qwi[i];\n"
+              << "      }\n"
+              << "      for (int k = 32; k > 0; k >>= 1) { vr += __shfl_down(vr, k, 64);"
+              << (cplx ? " vi += __shfl_down(vi, k, 64);" : "") << " }\n"
+              << "      if (ln == 0u) { dsr[par][wv] = vr;" << (cplx ? " dsi[par][wv] = vi;" : "") << " }\n"
+              << "    }\n";
+        }
+        o << "    __syncthreads();\n";
+        // prefetch the self rows of the next super-tile
+        o << "    if (t + t_step < t_end) {\n      const unsigned Fn = (t + t_step) * " << st * sz << "u + " << shift << "u;\n";
+        for (int64_t j = 0; j < PU; ++j) o << "      xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
+        o << "    }\n";
+        o << "    R dUr = (R)0, dUi = (R)0;\n";
+        for (int w = 0; w < (nsum > 0 ? swaves : 0); ++w)
+            o << "    dUr += dsr[par][" << w << "];" << (cplx ? " dUi += dsi[par][" + std::to_string(w) + "];" : "") << "\n";
+        auto acc = [&](int64_t j, const std::string& kr, const std::string& ki, const std::string& s) {
+            o << "a" << j << "r += " << kr << " * " << s << ".x; a" << j << "i += " << kr << " * " << s << ".y;";
+            if (!ki.empty()) o << " a" << j << "r -= " << ki << " * " << s << ".y; a" << j << "i += " << ki << " * " << s << ".x;";
+        };
+        for (int64_t j = 0; j < PU; ++j) {
+            o << "    {\n      R a" << j << "r, a" << j << "i;\n      {\n        R dr = dS" << j << "r + dUr, di = dS" << j
+              << "i + dUi;\n";
+            for (int i = 0; i < nmd; ++i) {
+                auto it = fD.find({i, j});
+                if (it == fD.end()) continue;
+                o << "        dr += tr[par][" << i << "] * " << it->second << ";";
+                if (cplx) o << " di += ti[par][" << i << "] * " << it->second << ";";
+                o << "\n";
+            }
+            o << "        a" << j << "r = dr * x" << j << ".x - di * x" << j << ".y; a" << j << "i = dr * x" << j << ".y + di * x" << j
+              << ".x;\n      }\n";
+            if (use_lds) {
+                for (int c : cS) {
+                    auto it = kS.find({c, j});
+                    if (it == kS.end()) continue;
+                    const int64_t off = halo + j * T - P.chans[c].delta;
+                    o << "      { const C s = lb[r + " << off << "u]; ";
+                    acc(j, it->second + "r", cplx ? it->second + "i" : "", "s");
+                    o << " }\n";
+                }
+            }
+            if (NI > 0) {
+                o << "      const unsigned n = (unsigned)__builtin_amdgcn_readfirstlane(lcn[par][" << j << "]);\n"
+                  << "      for (unsigned k = " << j * CAP << "u; k < " << j * CAP << "u + n; k += " << U << "u) {\n";
+                for (int u = 0; u < U; ++u)
+                    o << "        const int so" << u << " = __builtin_amdgcn_readfirstlane(lso[par][k + " << u << "u]);"
+                      << " const int g" << u << " = __builtin_amdgcn_readfirstlane(lgr[par][k + " << u << "u]);"
+                      << " const R f" << u << " = lfac[(unsigned)g" << u << " * " << block << "u + tid];"
+                      << " const C s" << u << " = LD(xs, f" << u << " != (R)0 ? voff : OOB, F0 + (unsigned)so" << u << ");\n";
+                for (int u = 0; u < U; ++u) {
+                    o << "        { const R cr = lcr[par][k + " << u << "u] * f" << u << ";";
+                    if (cplx) o << " const R ci = lci[par][k + " << u << "u] * f" << u << ";";
+                    o << " ";
+                    acc(j, "cr", cplx ? "ci" : "", "s" + std::to_string(u));
+                    o << " }\n";
+                }
+                o << "      }\n";
+            }
+            o << "      C out; out.x = a" << j << "r; out.y = a" << j << "i; ST(out, ys, voff, " << soff(j, 0, "F0") << ");\n"
+              << "    }\n";
+        }
+        if (!dbuf) o << "    __syncthreads();\n";
+        o << "    par ^= 1u;\n  }\n}\n";
+
+        std::ostringstream full;
+        full << "// generated (list form): " << P.N << " sites, " << nch << " channels (" << cS.size() << " static, " << cG.size()
+             << " listed), " << ndg << " diagonal terms; " << T << " rows per block (sites " << tl.k_in << ".." << P.N - 1
+             << "), " << PU << " unrolled copies (sites " << tl.k_u << ".." << tl.k_in - 1 << "), " << n_st
+             << " super-tiles\n";
+        if (f32)
+            full << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
+                 << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
+                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
+        else
+            full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
+                 << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
+                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
+        full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
+        full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
+        if (pool.empty()) full << "0";
+        for (size_t i = 0; i < pool.size(); ++i) full << (i ? ", " : "") << lit(pool[i], f32);
+        full << "};\n" << pre.str() << o.str();
+        return full.str();
+    }
 };
 
 // Tile choice.  Inner block: the low sites with T_in <= 1024 rows, preferring blocks of at least 256
@@ -634,8 +1087,10 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     gen.sched = p->tune_sched;
     gen.bskip = p->tune_bskip != 0;
     gen.gs = p->tune_load_group;
+    gen.variant = p->tune_variant;
     *tl_out = tl;
-    return gen.source();
+    if (gen.variant != MRMF_VARIANT_LIST && gen.masked_fits()) return gen.source();
+    return gen.source_v2();
 }
 
 namespace {
@@ -782,6 +1237,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
         case MRMF_TUNE_BLOCKS_PER_CU:
             if (value < 0 || value > 32) return MRMF_E_INVALID_ARG;
             plan->tune_blocks_per_cu = value;
+            break;
+        case MRMF_TUNE_VARIANT:
+            if (value != MRMF_VARIANT_MASKED && value != MRMF_VARIANT_LIST) return MRMF_E_INVALID_ARG;
+            plan->tune_variant = value;
             break;
         default: return MRMF_E_INVALID_ARG;
     }

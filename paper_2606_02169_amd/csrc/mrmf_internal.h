@@ -106,7 +106,8 @@ struct mrmf_plan_t {
     int32_t kernel_mode = 0;
     int32_t inner_pref = 0;
     int32_t unroll_pref = -1;
-    int32_t tune_sched = MRMF_SCHED_WINDOWS, tune_bskip = 0, tune_load_group = 0, tune_blocks_per_cu = 0;
+    int32_t tune_sched = MRMF_SCHED_WINDOWS, tune_bskip = 0, tune_load_group = 0, tune_blocks_per_cu = 0,
+            tune_variant = MRMF_VARIANT_MASKED;
     mrmf::SpecKernel spec[2];
     std::mutex mtx;
     ~mrmf_plan_t();

@@ -192,7 +192,7 @@ class Plan:
         "auto"; inner_sites = 0 / unrolled_sites = -1 let the library pick the tiling."""
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
-    TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3}
+    TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks), branch_skip

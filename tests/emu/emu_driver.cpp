@@ -12,6 +12,14 @@
 thread_local emu_dim3 threadIdx;
 emu_dim3 blockIdx, gridDim, blockDim;
 double emu_shfl_slot[16][64];
+unsigned long long emu_ballot_slot[16][64];
+
+void emu_uniform_failed(long long mine, long long first) {
+    std::fprintf(stderr, "emu: readfirstlane of a non-uniform value (lane %u has %lld, lane 0 %lld)\n", threadIdx.x,
+                 mine, first);
+    std::fflush(stderr);
+    std::abort();
+}
 
 namespace {
 pthread_barrier_t g_block_bar;

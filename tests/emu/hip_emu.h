@@ -45,6 +45,30 @@ inline T __shfl_down(T v, int k, int width) {
     return r;
 }
 
+extern unsigned long long emu_ballot_slot[16][64];
+inline unsigned long long __ballot(int pred) {
+    const unsigned t = threadIdx.x, w = t >> 6, l = t & 63u;
+    emu_ballot_slot[w][l] = pred ? 1ull : 0ull;
+    emu_wave_barrier();
+    unsigned long long m = 0;
+    for (unsigned k = 0; k < 64; ++k) m |= emu_ballot_slot[w][k] << k;
+    emu_wave_barrier();
+    return m;
+}
+inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+// every lane must hold the same value where the kernels use this: the emulation checks it
+void emu_uniform_failed(long long mine, long long first);
+inline int emu_readfirstlane(int v) {
+    const unsigned t = threadIdx.x, w = t >> 6, l = t & 63u;
+    emu_ballot_slot[w][l] = static_cast<unsigned long long>(static_cast<unsigned>(v));
+    emu_wave_barrier();
+    const int first = static_cast<int>(static_cast<unsigned>(emu_ballot_slot[w][0]));
+    emu_wave_barrier();
+    if (first != v) emu_uniform_failed(v, first);
+    return first;
+}
+#define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((int)(v))
+
 inline unsigned long long __umul64hi(unsigned long long a, unsigned long long b) {
     return static_cast<unsigned long long>((static_cast<unsigned __int128>(a) * b) >> 64);
 }

@@ -59,10 +59,30 @@ def test_random_models(seed):
 
 
 @pytest.mark.parametrize("tuning,grid", [({"schedule": 1}, 8), ({"schedule": 1}, 5), ({"branch_skip": 1}, 8),
-                                         ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16)])
+                                         ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16),
+                                         ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5)])
 def test_tuning_variants(tuning, grid):
     m, x = W.config(2, reduced=12)
     check(m, x, tuning=tuning, grid=grid)
     check(m, x.astype(np.complex64), tuning=tuning, grid=grid, unrolled=1)
     m3, x3 = W.config(3, reduced=3)
     check(m3, x3, tuning=tuning, grid=grid, inner=4, unrolled=1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_models_list_form(seed):
+    """The list form on random mixed spin/boson models, several tilings and chunk sizes (small blocks
+    with many channels exercise the multi-pass list construction)."""
+    rng = np.random.default_rng(7700 + seed)
+    herm = seed % 3 != 0
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 8)), max_dim=30000, hermitian=herm,
+                       n_params=int(rng.integers(1, 5)), n_terms=40)
+    x = W.random_state(m.dim, rng)
+    for inner, unrolled, u in ((0, -1, 0), (1, 0, 3), (2, 1, 1), (1, 2, 7)):
+        try:
+            y = E.run(m, x, inner=inner, unrolled=unrolled, require_hermitian=herm,
+                      tuning={"variant": 1, "load_group": u})
+        except ValueError:
+            continue
+        assert rel_err(y, mf.matvec(m, x)) <= TOL_Z
+    check(m, x.astype(np.complex64), require_hermitian=herm, tuning={"variant": 1})
