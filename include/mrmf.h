@@ -154,6 +154,13 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_SCHED_WINDOWS 0
 #define MRMF_SCHED_XCD_CHUNK 1
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
+/* Autotuner for the plain matvec: times every candidate shape of the specialized kernel (inner block of
+ * 32..1024 rows, 0..2 unrolled sites, masked and list forms, list chunk 4/8/12) on the given buffers with
+ * HIP events on the stream (synchronising it), keeps the fastest in the plan and writes host
+ * out[0..4] = (variant, inner sites, unrolled sites, load group, microseconds per call).  y is
+ * overwritten; x must not overlap y. */
+mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
+                               const void* d_x, void* d_y, mrmf_stream stream, int32_t* out);
 /* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
  * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only. */
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype);

@@ -576,7 +576,11 @@ struct Gen {
             full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
                  << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
                  << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
+                 // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
+                 // constant 0; with a register scalar offset the compiler inserts no wait state between
+                 // the store and a following VALU write of its data registers, and the stored value was
+                 // then observed to be overwritten
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)((unsigned)(vo) + (unsigned)(so)), 0, 2)\n";
         full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
         full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
         if (pool.empty()) full << "0";
@@ -1014,7 +1018,11 @@ struct Gen {
             full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
                  << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
                  << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
+                 // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
+                 // constant 0; with a register scalar offset the compiler inserts no wait state between
+                 // the store and a following VALU write of its data registers, and the stored value was
+                 // then observed to be overwritten
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)((unsigned)(vo) + (unsigned)(so)), 0, 2)\n";
         full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
         full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
         if (pool.empty()) full << "0";
@@ -1256,6 +1264,93 @@ mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype) {
     if (plan->kernel_mode == MRMF_KERNEL_GENERIC) return MRMF_OK;
     const mrmf_status st = mrmf::spec_prepare(plan, dtype);
     if (st == MRMF_E_UNSUPPORTED && plan->kernel_mode == MRMF_KERNEL_AUTO) return MRMF_OK;
+    return st;
+}
+
+mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
+                               const void* d_x, void* d_y, mrmf_stream stream, int32_t* out) {
+    using namespace mrmf;
+    if (!plan || !d_ws || !d_theta || !d_x || !d_y || !out || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C))
+        return MRMF_E_INVALID_ARG;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    struct Cand {
+        int variant, inner, unrolled, group;
+    };
+    // inner blocks of 32..1024 rows, 0..2 unrolled sites with at most 9 copies, both forms, three chunk
+    // sizes for the list form
+    std::vector<Cand> cands;
+    int64_t T = 1;
+    for (int k = plan->N - 1; k >= 0; --k) {
+        T *= plan->d[k];
+        if (T > 1024) break;
+        if (T < 32) continue;
+        const int inner = plan->N - k;
+        int64_t PU = 1;
+        for (int u = 0; u <= 2 && u <= k; ++u) {
+            if (u > 0) PU *= plan->d[k - u];
+            if (PU > 9) break;
+            if (plan->D / (T * PU) < 256) break;  // too few super-tiles to fill the GPU
+            cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0});
+            for (int g : {4, 8, 12}) cands.push_back({MRMF_VARIANT_LIST, inner, u, g});
+        }
+    }
+    if (cands.empty()) return MRMF_E_UNSUPPORTED;
+    const int32_t mode0 = plan->kernel_mode, in0 = plan->inner_pref, un0 = plan->unroll_pref;
+    const int32_t v0 = plan->tune_variant, g0 = plan->tune_load_group;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MRMF_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return MRMF_E_HIP;
+    }
+    auto run = [&]() -> mrmf_status {
+        return dtype == MRMF_DTYPE_Z
+                   ? matvec_z_impl(plan, d_ws, static_cast<const double*>(d_theta), d_x, d_y, s, nullptr)
+                   : matvec_c_impl(plan, d_ws, static_cast<const float*>(d_theta), d_x, d_y, s, nullptr);
+    };
+    float best = 0.f;
+    int best_i = -1;
+    mrmf_status st = MRMF_OK;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const Cand& c = cands[i];
+        mrmf_plan_set_kernel(plan, MRMF_KERNEL_SPECIALIZED, c.inner, c.unrolled);
+        mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, c.variant);
+        mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, c.group);
+        if (spec_prepare(plan, dtype) != MRMF_OK) continue;  // this shape does not qualify
+        st = run();
+        if (st != MRMF_OK) break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && st == MRMF_OK; ++r) st = run();
+        hipEventRecord(e1, s);
+        if (st != MRMF_OK || hipEventSynchronize(e1) != hipSuccess) {
+            st = st != MRMF_OK ? st : MRMF_E_HIP;
+            break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (best_i < 0 || ms < best) {
+            best = ms;
+            best_i = static_cast<int>(i);
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != MRMF_OK || best_i < 0) {
+        mrmf_plan_set_kernel(plan, mode0, in0, un0);
+        mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, v0);
+        mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, g0);
+        return st != MRMF_OK ? st : MRMF_E_UNSUPPORTED;
+    }
+    const Cand& c = cands[best_i];
+    mrmf_plan_set_kernel(plan, MRMF_KERNEL_SPECIALIZED, c.inner, c.unrolled);
+    mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, c.variant);
+    mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, c.group);
+    st = spec_prepare(plan, dtype);
+    out[0] = c.variant;
+    out[1] = c.inner;
+    out[2] = c.unrolled;
+    out[3] = c.group;
+    out[4] = static_cast<int32_t>(best / 3.f * 1000.f);  // microseconds per call
     return st;
 }
 

@@ -62,6 +62,7 @@ class Plan:
         flags = L.MRMF_REQUIRE_HERMITIAN if require_hermitian else 0
         L.call("mrmf_plan_create", len(sites), sa, len(terms), ta, int(n_params), flags,
                ctypes.byref(self._handle))
+        self._sites, self._terms = list(sites), list(terms)
         self.n_params = int(n_params)
         self.device = torch.device(device)
         D = ctypes.c_int64()
@@ -199,6 +200,32 @@ class Plan:
         (0/1), load_group (channels issued ahead, 0 = default), blocks_per_cu (0 = as many as fit)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
+
+    def autotune(self, theta: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
+                 use_cache: bool = True) -> dict:
+        """Pick the specialized kernel's shape for this plan and element type (x.dtype): from the tuning
+        cache when the structure was tuned before, else by timing every candidate on these buffers
+        (mrmf_plan_autotune) and recording the winner."""
+        from . import tuning
+        dt = L.MRMF_DTYPE_Z if x.dtype == torch.complex128 else L.MRMF_DTYPE_C
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        key = tuning.signature(self._sites, self._terms, dt, arch)
+        ent = tuning.lookup(key) if use_cache else None
+        if ent is None:
+            y = torch.empty_like(x) if y is None else y
+            _need_gpu(x, "x")
+            _need_gpu(y, "y", x.dtype)
+            out = (ctypes.c_int32 * 5)()
+            L.call("mrmf_plan_autotune", self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
+                   _stream(self.device), out)
+            ent = dict(variant=out[0], inner_sites=out[1], unrolled_sites=out[2], load_group=out[3],
+                       us_per_call=out[4], D=self.D)
+            if use_cache:
+                tuning.store(key, ent)
+        self.set_kernel("specialized", ent["inner_sites"], ent["unrolled_sites"])
+        self.set_tuning(variant=ent["variant"], load_group=ent["load_group"])
+        self.prepare(x.dtype)
+        return dict(ent, key=key)
 
     def prepare(self, dtype=torch.complex128):
         """Compile and load the kernel matvec will use for this element type (synchronous)."""

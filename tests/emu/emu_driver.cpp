@@ -63,8 +63,18 @@ void* thread_main(void* a) {
 }
 }  // namespace
 
+// Runs blocks [b0, b1) of a grid of `grid` blocks (b1 = 0: all of them).
+extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, size_t theta_bytes, const void* x,
+                             size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1);
+
 extern "C" int emu_run(unsigned grid, unsigned block, const void* theta, size_t theta_bytes, const void* x,
                        size_t x_bytes, void* y, size_t y_bytes) {
+    return emu_run_range(grid, block, theta, theta_bytes, x, x_bytes, y, y_bytes, 0, 0);
+}
+
+extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, size_t theta_bytes, const void* x,
+                             size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1) {
+    if (b1 == 0 || b1 > grid) b1 = grid;
     if (block == 0 || block % 64 != 0 || block > 1024) return -1;
     g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
               {static_cast<const char*>(theta), theta_bytes, "theta"}};
@@ -78,7 +88,7 @@ extern "C" int emu_run(unsigned grid, unsigned block, const void* theta, size_t 
     pthread_attr_t attr;
     pthread_attr_init(&attr);
     pthread_attr_setstacksize(&attr, 1 << 20);
-    for (unsigned b = 0; b < grid; ++b) {
+    for (unsigned b = b0; b < b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
         for (unsigned t = 0; t < block; ++t) {
             args[t] = Arg{t, theta, x, y};

@@ -70,6 +70,8 @@ def _compile(src: str) -> ctypes.CDLL:
     lib.emu_run.restype = ctypes.c_int
     lib.emu_run.argtypes = [ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
+    lib.emu_run_range.restype = ctypes.c_int
+    lib.emu_run_range.argtypes = lib.emu_run.argtypes + [ctypes.c_uint, ctypes.c_uint]
     return lib
 
 
@@ -80,7 +82,7 @@ def launch_shape(src: str):
 
 
 def run(model, x: np.ndarray, theta=None, inner: int = 0, unrolled: int = -1, grid: int | None = None,
-        require_hermitian=True, tuning=None) -> np.ndarray:
+        require_hermitian=True, tuning=None, blocks=None) -> np.ndarray:
     """y = H x with the generated kernel, emulated on the CPU."""
     f32 = x.dtype == np.complex64
     src = kernel_source(model, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z, inner, unrolled,
@@ -95,7 +97,9 @@ def run(model, x: np.ndarray, theta=None, inner: int = 0, unrolled: int = -1, gr
                               dtype=np.float32 if f32 else np.float64)
     xx = np.ascontiguousarray(x)
     y = np.full_like(xx, np.nan)
-    rc = lib.emu_run(grid, block, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data, y.nbytes)
+    b0, b1 = blocks if blocks is not None else (0, 0)
+    rc = lib.emu_run_range(grid, block, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data,
+                           y.nbytes, b0, b1)
     if rc != 0:
         raise RuntimeError(f"emu_run failed: {rc}")
     return y

@@ -89,3 +89,58 @@ def test_specialized_equals_generic_bitwise_structure():
     a = run(plan(m, "generic"), m.theta, x)
     b = run(plan(m, "specialized"), m.theta, x)
     assert rel_err(b, a) <= 1e-13
+
+
+@pytest.mark.parametrize("k,inner,unrolled,U,cap", [(2, 6, 1, 4, 0), (2, 6, 1, 8, 0), (2, 7, 0, 4, 0),
+                                                    (3, 5, 1, 4, 0), (3, 5, 2, 8, 0), (3, 6, 0, 8, 2)])
+def test_list_form_full_size(k, inner, unrolled, U, cap):
+    """List form at full size with several blocks per compute unit: sampled rows against the oracle,
+    the whole vector against the masked form, and two runs bit-identical.  (A 128-bit store whose data
+    registers were rewritten right after it once corrupted the real part of whole rows here.)"""
+    from paper_2606_02169_amd.plan import Plan
+    m, x = W.config(k)
+    dev = torch.device("cuda")
+    f32 = x.dtype == np.complex64
+    rd = torch.float32 if f32 else torch.float64
+    xt = torch.from_numpy(x).to(dev)
+    th = torch.as_tensor(m.theta, dtype=rd, device=dev)
+    ref = Plan.from_model(m)
+    ref.set_kernel("specialized", 0, 0)
+    y0 = ref.matvec(th, xt)
+    p = Plan.from_model(m)
+    p.set_kernel("specialized", inner, unrolled)
+    p.set_tuning(variant=1, load_group=U, blocks_per_cu=cap)
+    ya = p.matvec(th, xt).clone()
+    yb = p.matvec(th, xt)
+    torch.cuda.synchronize()
+    print(p.kernel_info(xt.dtype), flush=True)
+    assert torch.equal(ya, yb)
+    tol = TOL_C if f32 else TOL_Z
+    assert ((ya - y0).norm() / y0.norm()).item() <= (1e-6 if f32 else 1e-13)
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([np.arange(300), np.arange(m.dim - 300, m.dim),
+                                     rng.choice(m.dim, 4000, replace=False)])).astype(np.int64)
+    yr = ya[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    assert rel_err(yr, mf.matvec(m, x.astype(np.complex128), rows=rows)) <= tol
+
+
+def test_plan_autotune_and_cache(tmp_path, monkeypatch):
+    """mrmf_plan_autotune on a reduced ring: the chosen shape reproduces the result, the cache entry is
+    written and a second plan of the same structure takes it without a search."""
+    from paper_2606_02169_amd.plan import Plan
+    monkeypatch.setenv("MRMF_TUNE_CACHE", str(tmp_path / "tune.json"))
+    m, x = W.config(2, reduced=14)
+    dev = torch.device("cuda")
+    xt = torch.from_numpy(x).to(dev)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device=dev)
+    p = Plan.from_model(m)
+    ent = p.autotune(th, xt)
+    print(ent, flush=True)
+    assert (tmp_path / "tune.json").exists()
+    y = p.matvec(th, xt)
+    torch.cuda.synchronize()
+    assert rel_err(y.cpu().numpy(), mf.matvec(m, x)) <= TOL_Z
+    q = Plan.from_model(m)
+    ent2 = q.autotune(th, xt)
+    assert ent2["key"] == ent["key"] and ent2["inner_sites"] == ent["inner_sites"]
+    assert q.kernel_info()["inner_sites"] == ent["inner_sites"]
