@@ -1,16 +1,23 @@
 """Throughput of the matrix-free map y = H x on one MI355X.
 
-Workload: the periodic mixed-spin ferrimagnetic ring, 20 sites alternating s = 1/2 and s = 1
-(D = 2^10 * 3^10 = 60,466,176), XXZ bonds J_xy = 1.0, J_z = 1.2, single-ion anisotropy 0.5 (S_z)^2 on
-the s = 1 sites, field 0.1 S_z; complex128 state drawn from seed 2, already resident in HBM.  A step is
-one plain FP64 (complex128) H x.
+Default workload (the headline line): the periodic mixed-spin ferrimagnetic ring, 20 sites alternating
+s = 1/2 and s = 1 (D = 2^10 * 3^10 = 60,466,176), XXZ bonds J_xy = 1.0, J_z = 1.2, single-ion anisotropy
+0.5 (S_z)^2 on the s = 1 sites, field 0.1 S_z; complex128 state drawn from seed 2, resident in HBM.  A
+step is one plain FP64 (complex128) H x.  Prints one JSON line: matvecs/s, the roofline of the matvec
+kernel (algorithmic bytes 2 * D * 16 per launch over the mean launch time, measured with HIP events on
+the launch stream, against 8 TB/s), the HBM traffic from committed rocprofv3 counters when they were
+taken on the same kernel, and the CPU oracle timed on the host cores.
 
-Prints one JSON line: matvecs/s, the roofline of the matvec kernel (algorithmic bytes 2 * D * 16 per
-launch over the mean launch time, measured with HIP events on the launch stream, against 8 TB/s), the
-HBM traffic read from committed rocprofv3 counters when they were taken on the same kernel, and the
-CPU oracle timed on a bounded sample of rows on the host cores.
+Other workloads (one JSON line each; not part of the headline):
+  --workload lanczos4x4  4x4 periodic spin-1 Heisenberg (D = 3^16): FP32 (c64) matvec inside the FP64
+                         Lanczos against the plain FP64 form: steps and wall time to 1e-5 relative
+                         ground-energy error, end to end and matvec only
+  --workload batched     256 open mixed chains x 8 c64 vectors in one persistent hipGraph launch,
+                         against separate plain c64 and c128 calls per vector
+  --workload adjoint     Tavis-Cummings (12 spins + boson cut at 64): forward and adjoint times and
+                         gradient error against the oracle
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
 from __future__ import annotations
 
@@ -37,76 +44,81 @@ def log(msg):
 def kernel_fingerprint(plan, dtype) -> str:
     """Hash of the kernel source the plan launches (counters are valid only for the same kernel)."""
     info = plan.kernel_info(dtype)
-    if info["kind"] == "specialized":
-        src = plan.kernel_source(dtype)
-    else:
-        src = "generic"
+    src = plan.kernel_source(dtype) if info["kind"] == "specialized" else "generic"
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
+def cuda_time(fn, stream, reps: int):
+    """Mean ms per call over reps back-to-back calls, HIP events on the launch stream."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def cpu_baseline(model, x_host, target_s: float = 12.0):
-    """The oracle's FP64 matvec on a contiguous sample of rows, on the host cores; scaled to
-    matvecs/s of the full vector."""
+    """The oracle's FP64 matvec on the host cores: the full vector, repeated to about target_s seconds
+    (or a row sample if one full pass would take longer); scaled to matvecs/s of the full vector."""
     import numpy as np
     from oracle import mf
     D = model.dim
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    # calibrate on a short sample, then run about target_s seconds of rows
     rows = np.arange(D // 3, D // 3 + 200_000, dtype=np.int64)
     t0 = time.perf_counter()
     mf.matvec(model, x_host, rows=rows)
-    dt = time.perf_counter() - t0
-    n = int(min(D, max(200_000, 200_000 * target_s / max(dt, 1e-6))))
+    est_full = (time.perf_counter() - t0) * D / rows.size
+    if est_full <= target_s:
+        reps = max(1, int(target_s / max(est_full, 1e-3)))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            y = mf.matvec(model, x_host)
+        dt = time.perf_counter() - t0
+        rows_all = np.arange(D, dtype=np.int64)
+        return (dict(value=reps / dt, unit="matvecs/s", cores=threads, kind="oracle",
+                     sample=f"{reps} full FP64 matvecs (D={D}) in {dt:.1f} s: plain C App-A row loop, "
+                            f"OpenMP over rows"), rows_all, y)
+    n = int(D * target_s / est_full)
     start = (D - n) // 2
     rows = np.arange(start, start + n, dtype=np.int64)
     t0 = time.perf_counter()
     y_rows = mf.matvec(model, x_host, rows=rows)
     dt = time.perf_counter() - t0
-    rows_per_s = n / dt
-    return dict(value=rows_per_s / D, unit="matvecs/s", cores=threads, kind="oracle",
-                sample=f"rows [{start}, {start + n}) of D={D} ({n} rows, {dt:.1f} s), plain C "
-                       f"App-A row loop, FP64, OpenMP over rows"), rows, y_rows
+    return (dict(value=n / dt / D, unit="matvecs/s", cores=threads, kind="oracle",
+                 sample=f"rows [{start}, {start + n}) of D={D} in {dt:.1f} s, scaled to the full vector; "
+                        f"plain C App-A row loop, OpenMP over rows"), rows, y_rows)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the matvec is measured on one GPU's share; "
-              "a multi-GPU run is not part of this build (--gpus 1).", file=sys.stderr)
-        sys.exit(2)
-
+# ------------------------------------------------------------------------------------------ headline
+def bench_ring(args, dev):
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2606_02169_amd.plan import Plan
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU (the HIP library has no CPU path)", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
     t0 = time.perf_counter()
     model, x_host = W.config(2)
     log(f"inputs: {model.name} D={model.dim} generated in {time.perf_counter() - t0:.1f} s")
     D = model.dim
     plan = Plan.from_model(model, device=dev)
-    plan.set_kernel(args.kernel)
-    plan.prepare(torch.complex128)
-    info = plan.kernel_info(torch.complex128)
-    log(f"kernel: {info}")
     x = torch.from_numpy(x_host).to(dev)
     y = torch.empty_like(x)
     theta = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    if args.kernel == "auto":
+        tuned = plan.autotune(theta, x, y)
+        log(f"tuned shape: {tuned}")
+    else:
+        plan.set_kernel(args.kernel)
+        plan.prepare(torch.complex128)
+    info = plan.kernel_info(torch.complex128)
+    log(f"kernel: {info}")
 
     if args.profile:
         # a plain copy of known size (x -> y, 2 * D * 16 bytes of HBM traffic) in the same process, so
@@ -162,25 +174,247 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ferrimagnetic_ring_N20_c128", "sites": "20 (s=1/2, s=1 alternating), periodic",
                    "D": D, "couplings": "Jxy=1.0 Jz=1.2 D_si=0.5 hz=0.1", "seed": 2,
-                   "kernel": info["kind"]},
+                   "kernel": {k: info[k] for k in ("kind", "inner_sites", "unrolled_sites", "block", "grid")}},
         "effective_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes, "mean_launch_ms": mean_launch_ms,
                      "kernel_fingerprint": fp},
     }
-
     if not (args.no_cpu_baseline or args.profile):
-        # oracle timing and a sampled parity check of the timed output (the oracle is a baseline only)
+        # oracle timing and a parity check of the timed output (the oracle is a baseline only)
         cb, rows, y_rows = cpu_baseline(model, x_host)
-        y_gpu = y[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        if rows.size == D:
+            y_gpu = y.cpu().numpy()
+        else:
+            y_gpu = y[torch.from_numpy(rows).to(dev)].cpu().numpy()
         err = float(np.linalg.norm(y_gpu - y_rows) / np.linalg.norm(y_rows))
         out["cpu_baseline"] = cb
-        out["sampled_rel_err_vs_oracle"] = err
-        log(f"cpu baseline: {cb}; sampled rel err {err:.3e}")
+        out["rel_err_vs_oracle"] = err
+        log(f"cpu baseline: {cb}; rel err vs oracle {err:.3e}")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------------------------------ Lanczos
+def bench_lanczos(args, dev):
+    import numpy as np
+    import torch
+    from scipy.linalg import eigvalsh_tridiagonal
+
+    import workloads as W
+    from paper_2606_02169_amd.plan import Plan
+
+    model, x32 = W.config(3)
+    D = model.dim
+    v0 = torch.from_numpy(x32.astype(np.complex128)).to(dev)
+    th64 = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+    th32 = th64.float()
+    stream = torch.cuda.current_stream(dev)
+    pz = Plan.from_model(model, device=dev)
+    pc = Plan.from_model(model, device=dev)
+    xz = v0.clone()
+    yz = torch.empty_like(xz)
+    xc = torch.from_numpy(x32).to(dev)
+    yc = torch.empty_like(xc)
+    log(f"tuned c128: {pz.autotune(th64, xz, yz)}")
+    log(f"tuned c64: {pc.autotune(th32, xc, yc)}")
+    for _ in range(3):
+        pz.matvec(th64, xz, out=yz)
+        pc.matvec(th32, xc, out=yc)
+    mv_z = cuda_time(lambda: pz.matvec(th64, xz, out=yz), stream, 20)
+    mv_c = cuda_time(lambda: pc.matvec(th32, xc, out=yc), stream, 20)
+    del xz, yz, xc, yc
+
+    def ritz_curve(alpha, beta, k):
+        a = alpha[:k]
+        b = beta[: k - 1]
+        return np.array([eigvalsh_tridiagonal(a[:i], b[: i - 1], select="i", select_range=(0, 0))[0]
+                         for i in range(1, k + 1)])
+
+    def run(plan, prec, m, reorth="cgs2"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.lanczos(th64, v0, m, precision=prec, reorth=reorth, theta_c=th32)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = r["result"].cpu().numpy()
+        k = int(res[3])
+        return dict(theta=float(res[0]), resid=float(res[2]), steps=k, seconds=dt,
+                    alpha=r["alpha"].cpu().numpy()[:k], beta=r["beta"].cpu().numpy()[:k])
+
+    m_ref = args.lanczos_ref_steps
+    ref = run(pz, "z", m_ref)
+    E_ref = ref["theta"]
+    log(f"reference: {m_ref} FP64 steps, theta {E_ref!r} residual {ref['resid']:.3e} in {ref['seconds']:.1f} s")
+    out = {"metric": "Lanczos ground energy: FP32 (c64) matvec in FP64 Lanczos vs plain FP64, time to 1e-5",
+           "workload": "square4x4_spin1_periodic", "D": D, "seed": 3,
+           "reference": {"steps": ref["steps"], "theta": E_ref, "residual": ref["resid"],
+                         "seconds": ref["seconds"]},
+           "matvec_ms": {"c128": mv_z, "c64": mv_c}, "forms": {}}
+    m = args.lanczos_steps
+    for name, plan, prec in (("fp64", pz, "z"), ("fp32_in_fp64", pc, "c_in_z")):
+        full = run(plan, prec, m)
+        curve = ritz_curve(full["alpha"], full["beta"], full["steps"])
+        rel = np.abs(curve - E_ref) / abs(E_ref)
+        hit = np.nonzero(rel <= 1e-5)[0]
+        k5 = int(hit[0]) + 1 if hit.size else None
+        timed = run(plan, prec, k5) if k5 else None
+        out["forms"][name] = {
+            "steps": m, "theta": full["theta"], "rel_err": abs(full["theta"] - E_ref) / abs(E_ref),
+            "residual": full["resid"], "seconds": full["seconds"],
+            "steps_to_1e-5": k5, "seconds_to_1e-5": timed["seconds"] if timed else None,
+            "rel_err_at_1e-5_run": (abs(timed["theta"] - E_ref) / abs(E_ref)) if timed else None,
+            "matvec_ms": mv_z if prec == "z" else mv_c}
+        log(f"{name}: {out['forms'][name]}")
+    nz = run(pz, "z", m, reorth="none")
+    nc = run(pc, "c_in_z", m, reorth="none")
+    out["no_reorth"] = {"fp64": {"seconds": nz["seconds"], "rel_err": abs(nz["theta"] - E_ref) / abs(E_ref)},
+                        "fp32_in_fp64": {"seconds": nc["seconds"],
+                                         "rel_err": abs(nc["theta"] - E_ref) / abs(E_ref)}}
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------------------------------ batched
+def bench_batched(args, dev):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import mf
+    from paper_2606_02169_amd.plan import Batch, Plan
+
+    t0 = time.perf_counter()
+    models, xs = W.config(4)
+    log(f"inputs: {len(models)} lattices, sum D {sum(m.dim for m in models)} in {time.perf_counter() - t0:.1f} s")
+    plans = [Plan.from_model(m, device=dev) for m in models]
+    B = Batch(plans, 8)
+    X = torch.zeros(B.total_elems, dtype=torch.complex64, device=dev)
+    for b, x in enumerate(xs):
+        B.block(X, b).copy_(torch.from_numpy(np.ascontiguousarray(x)).to(dev))
+    Y = torch.empty_like(X)
+    th = torch.from_numpy(np.concatenate([m.theta for m in models]).astype(np.float32)).to(dev)
+    shape = B.autotune(th, X, Y)
+    s = torch.cuda.Stream(device=dev)
+    B.capture(th, X, Y, s)
+    for _ in range(3):
+        B.replay(s)
+    s.synchronize()
+    K = max(3, args.steps // 5)
+    a = torch.cuda.Event(enable_timing=True)
+    b_ = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(K):
+        B.replay(s)
+    b_.record(s)
+    s.synchronize()
+    ms_graph = a.elapsed_time(b_) / K
+    sumD = sum(m.dim for m in models)
+    vec_mv = len(models) * 8
+    # errors on sampled rows of every 8th lattice, against the oracle in FP64
+    rng = np.random.default_rng(5)
+    errs = []
+    for bi in range(0, len(models), 8):
+        m, x = models[bi], xs[bi]
+        r = np.unique(rng.choice(m.dim, min(m.dim, 500), replace=False)).astype(np.int64)
+        yb = B.block(Y, bi).cpu().numpy()
+        for v in (0, 7):
+            ref = mf.matvec(m, x[:, v].astype(np.complex128), rows=r)
+            errs.append(float(np.linalg.norm(yb[r, v] - ref) / np.linalg.norm(ref)))
+    # separate per-vector launches of the plain forms (contiguous single vectors)
+    stream = torch.cuda.current_stream(dev)
+    cols_c = [torch.from_numpy(np.ascontiguousarray(x[:, 0])).to(dev) for x in xs]
+    outs_c = [torch.empty_like(c) for c in cols_c]
+    ths = [torch.as_tensor(m.theta, dtype=torch.float64, device=dev) for m in models]
+    ths32 = [t.float() for t in ths]
+    for p, c, o, t in zip(plans, cols_c, outs_c, ths32):
+        p.matvec(t, c, out=o)
+
+    def sep_c():
+        for _ in range(8):
+            for p, c, o, t in zip(plans, cols_c, outs_c, ths32):
+                p.matvec(t, c, out=o)
+    ms_sep_c = cuda_time(sep_c, stream, 1)
+    cols_z = [c.to(torch.complex128) for c in cols_c]
+    outs_z = [torch.empty_like(c) for c in cols_z]
+    for p, c, o, t in zip(plans, cols_z, outs_z, ths):
+        p.matvec(t, c, out=o)
+
+    def sep_z():
+        for _ in range(8):
+            for p, c, o, t in zip(plans, cols_z, outs_z, ths):
+                p.matvec(t, c, out=o)
+    ms_sep_z = cuda_time(sep_z, stream, 1)
+    out = {"metric": "batched vector-matvecs/s (256 lattices x 8 c64 vectors, one persistent hipGraph launch)",
+           "workload": "mixed_chains_256x8_c64", "seed": 4, "sum_D": sumD, "vector_matvecs_per_launch": vec_mv,
+           "shape": shape, "ms_per_launch": ms_graph, "vector_matvecs_per_s": vec_mv / ms_graph * 1e3,
+           "effective_GBps": 2 * sumD * 8 * 8 / (ms_graph * 1e-3) / 1e9,
+           "max_rel_err_sampled_vs_fp64_oracle": max(errs),
+           "separate_c64_calls": {"ms_for_2048": ms_sep_c, "vector_matvecs_per_s": vec_mv / ms_sep_c * 1e3},
+           "separate_c128_calls": {"ms_for_2048": ms_sep_z, "vector_matvecs_per_s": vec_mv / ms_sep_z * 1e3}}
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------------------------------ adjoint
+def bench_adjoint(args, dev):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import grad as ograd
+    from paper_2606_02169_amd.plan import Plan
+
+    model, x = W.config(5)
+    p = Plan.from_model(model, device=dev)
+    xt = torch.from_numpy(x).to(dev)
+    th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+    p.autotune(th, xt)
+    stream = torch.cuda.current_stream(dev)
+    g = xt / torch.vdot(xt, xt).real
+    for _ in range(3):
+        p.adjoint(th, xt, g)
+    ms_fwd = cuda_time(lambda: p.matvec(th, xt), stream, 50)
+    ms_adj = cuda_time(lambda: p.adjoint(th, xt, g), stream, 50)
+    # Rayleigh quotient gradients: dL/dx = 2 (Hx - L x)/<x|x>, dL/dtheta_p = <x|h_p|x>/<x|x>
+    y = p.matvec(th, xt)
+    L = (torch.vdot(xt, y).real / torch.vdot(xt, xt).real).item()
+    gx, gt = p.adjoint(th, xt, g)
+    gx = 2 * gx - 2 * L * g                  # dL/dx of Re<x|Hx>/<x|x> through the adjoint
+    L_ref, gx_ref, gt_ref = ograd.rayleigh(model, x)
+    out = {"metric": "adjoint (grad_x = H g and all coupling gradients) time vs forward matvec",
+           "workload": "tavis_cummings_12x64_c128", "D": model.dim, "n_params": model.n_params,
+           "forward_ms": ms_fwd, "adjoint_ms": ms_adj,
+           "rel_err_grad_x": float(np.linalg.norm(gx.cpu().numpy() - gx_ref) / np.linalg.norm(gx_ref)),
+           "max_abs_err_grad_theta": float(np.max(np.abs(gt.cpu().numpy() - gt_ref))),
+           "loss": L, "loss_ref": L_ref}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
+    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint"])
+    ap.add_argument("--lanczos-steps", type=int, default=100)
+    ap.add_argument("--lanczos-ref-steps", type=int, default=150)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the matvec is measured on one GPU's share; "
+              "a multi-GPU run is not part of this build (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (the HIP library has no CPU path)", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "batched": bench_batched,
+     "adjoint": bench_adjoint}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

@@ -134,7 +134,9 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *   MRMF_TUNE_SCHEDULE      : MRMF_SCHED_WINDOWS  - the grid sweeps windows of consecutive super-tiles,
  *                                                   each XCD taking one eighth of every window;
  *                             MRMF_SCHED_XCD_CHUNK - each XCD sweeps its own contiguous eighth of the
- *                                                   super-tiles with its blocks side by side.
+ *                                                   super-tiles with its blocks side by side;
+ *                             MRMF_SCHED_BLOCK_RUN - each block sweeps its own contiguous run of
+ *                                                   super-tiles (runs of one XCD adjacent).
  *   MRMF_TUNE_BRANCH_SKIP   : 1 = a channel whose tile-uniform source digits are inadmissible is skipped
  *                             by a scalar branch; 0 = its loads are issued and masked.
  *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default).
@@ -153,6 +155,7 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0
 #define MRMF_SCHED_XCD_CHUNK 1
+#define MRMF_SCHED_BLOCK_RUN 2
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
 /* Autotuner for the plain matvec: times every candidate shape of the specialized kernel (inner block of
  * 32..1024 rows, 0..2 unrolled sites, masked and list forms, list chunk 4/8/12) on the given buffers with

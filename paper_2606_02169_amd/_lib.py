@@ -26,7 +26,7 @@ MRMF_KERNEL_AUTO, MRMF_KERNEL_GENERIC, MRMF_KERNEL_SPECIALIZED = 0, 1, 2
 MRMF_DTYPE_Z, MRMF_DTYPE_C = 0, 1
 MRMF_TUNE_SCHEDULE, MRMF_TUNE_BRANCH_SKIP, MRMF_TUNE_LOAD_GROUP, MRMF_TUNE_BLOCKS_PER_CU = 0, 1, 2, 3
 MRMF_TUNE_VARIANT, MRMF_VARIANT_MASKED, MRMF_VARIANT_LIST = 4, 0, 1
-MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK = 0, 1
+MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 
 
 class mrmf_site(ctypes.Structure):

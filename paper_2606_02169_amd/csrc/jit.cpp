@@ -419,6 +419,13 @@ struct Gen {
               << "  const unsigned Cx = (" << n_st << "u + nx - 1u) / nx;\n"
               << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
               << "  for (unsigned t = xcd * Cx + b / nx; t < t_end; t += GX) {\n";
+        } else if (sched == MRMF_SCHED_BLOCK_RUN) {
+            // every block sweeps its own contiguous run of super-tiles, so a neighbour read as a channel
+            // source is read again, as the block's own rows, a few super-tiles later through its own L1;
+            // the runs of the blocks of one XCD are adjacent
+            o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
+              << "  const unsigned t_end = (unsigned)(((unsigned long long)(v + 1u) * " << n_st << "ull) / G);\n"
+              << "  for (unsigned t = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G); t < t_end; ++t) {\n";
         } else {
             // the grid sweeps windows of G consecutive super-tiles; XCD x takes the x-th eighth of each
             o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
@@ -870,6 +877,10 @@ struct Gen {
               << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
               << "  const unsigned t_step = GX;\n"
               << "  unsigned t = xcd * Cx + b / nx;\n";
+        } else if (sched == MRMF_SCHED_BLOCK_RUN) {
+            o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
+              << "  const unsigned t_end = (unsigned)(((unsigned long long)(v + 1u) * " << n_st << "ull) / G), t_step = 1u;\n"
+              << "  unsigned t = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G);\n";
         } else {
             o << "  const unsigned t_end = " << n_st << "u, t_step = G;\n"
               << "  unsigned t = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n";
@@ -1231,7 +1242,8 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
     std::lock_guard<std::mutex> lk(plan->mtx);
     switch (knob) {
         case MRMF_TUNE_SCHEDULE:
-            if (value != MRMF_SCHED_WINDOWS && value != MRMF_SCHED_XCD_CHUNK) return MRMF_E_INVALID_ARG;
+            if (value != MRMF_SCHED_WINDOWS && value != MRMF_SCHED_XCD_CHUNK && value != MRMF_SCHED_BLOCK_RUN)
+                return MRMF_E_INVALID_ARG;
             plan->tune_sched = value;
             break;
         case MRMF_TUNE_BRANCH_SKIP:
@@ -1289,7 +1301,9 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         for (int u = 0; u <= 2 && u <= k; ++u) {
             if (u > 0) PU *= plan->d[k - u];
             if (PU > 9) break;
-            if (plan->D / (T * PU) < 256) break;  // too few super-tiles to fill the GPU
+            // fewer super-tiles than a quarter of the CUs leaves the GPU idle (unless the whole
+            // problem is that small)
+            if (plan->D / (T * PU) < 64 && u > 0) break;
             cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0});
             for (int g : {4, 8, 12}) cands.push_back({MRMF_VARIANT_LIST, inner, u, g});
         }

@@ -216,8 +216,13 @@ class Plan:
             _need_gpu(x, "x")
             _need_gpu(y, "y", x.dtype)
             out = (ctypes.c_int32 * 5)()
-            L.call("mrmf_plan_autotune", self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
-                   _stream(self.device), out)
+            st = L.lib().mrmf_plan_autotune(self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
+                                           _stream(self.device), out)
+            if st == L.MRMF_E_UNSUPPORTED:   # no specialized shape fits this plan: keep the default
+                self.set_kernel("auto")
+                self.prepare(x.dtype)
+                return dict(kind="default", key=key)
+            L.check(st, "mrmf_plan_autotune")
             ent = dict(variant=out[0], inner_sites=out[1], unrolled_sites=out[2], load_group=out[3],
                        us_per_call=out[4], D=self.D)
             if use_cache:

@@ -60,7 +60,8 @@ def test_random_models(seed):
 
 @pytest.mark.parametrize("tuning,grid", [({"schedule": 1}, 8), ({"schedule": 1}, 5), ({"branch_skip": 1}, 8),
                                          ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16),
-                                         ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5)])
+                                         ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5),
+                                         ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7)])
 def test_tuning_variants(tuning, grid):
     m, x = W.config(2, reduced=12)
     check(m, x, tuning=tuning, grid=grid)
