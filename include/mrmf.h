@@ -157,9 +157,16 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_SCHED_XCD_CHUNK 1
 #define MRMF_SCHED_BLOCK_RUN 2
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
+/* Shape of the specialized kernel for one element type only (e.g. from a tuning cache): form
+ * (MRMF_VARIANT_*), inner sites, unrolled sites, load group; selection becomes MRMF_KERNEL_AUTO for that
+ * element type (the generic kernel runs when the shape does not fit).  mrmf_plan_set_kernel and
+ * mrmf_plan_set_tuning set both element types. */
+mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, int32_t inner_sites,
+                                int32_t unrolled_sites, int32_t load_group);
 /* Autotuner for the plain matvec: times every candidate shape of the specialized kernel (inner block of
  * 32..1024 rows, 0..2 unrolled sites, masked and list forms, list chunk 4/8/12) on the given buffers with
- * HIP events on the stream (synchronising it), keeps the fastest in the plan and writes host
+ * HIP events on the stream (synchronising it), keeps the fastest in the plan for this element type only
+ * (selection MRMF_KERNEL_AUTO) and writes host
  * out[0..4] = (variant, inner sites, unrolled sites, load group, microseconds per call).  y is
  * overwritten; x must not overlap y. */
 mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
@@ -236,8 +243,9 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
  * row-major as [D_b][nvec] (row F of lattice b holds its nvec amplitudes contiguously), all in one
  * persistent launch.  Lattice b's block starts at element offset off_b (host query; offsets are
  * multiples of 32 elements).  d_theta_all: float, the n_params of lattice 0, then lattice 1, ...
- * (host query mrmf_batch_theta_offsets).  nvec in {1, 2, 4, 8}.  The batch keeps pointers to its plans'
- * host data: destroy the batch before its plans. */
+ * (host query mrmf_batch_theta_offsets; the array must hold at least the last offset's count of
+ * floats).  nvec in {1, 2, 4, 8}; at most 4096 lattices of at most 32 sites each, D_b * nvec < 2^30.
+ * The batch copies what it needs from the plans at creation; the plans may be destroyed afterwards. */
 mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, mrmf_batch* out);
 void mrmf_batch_destroy(mrmf_batch batch);
 mrmf_status mrmf_batch_total_elems(mrmf_batch batch, int64_t* elems); /* sum over b of D_b * nvec, padded */
@@ -253,13 +261,16 @@ mrmf_status mrmf_batch_matvec_c(mrmf_batch batch, const void* d_ws, const float*
 mrmf_status mrmf_batch_graph_capture(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
                                      const void* d_X, void* d_Y, mrmf_stream stream);
 mrmf_status mrmf_batch_graph_launch(mrmf_batch batch, mrmf_stream stream);
-/* Autotuner: times each candidate launch shape (rows per work item, threads per block) on the given
- * buffers with HIP events, keeps the fastest for this batch, and writes host out[0..2] = (rows per
- * item, block threads, candidate index).  Synchronises the stream. */
+/* Autotuner: times each candidate launch shape (tile-row limit, threads per block) on the given
+ * buffers with HIP events, keeps the fastest for this batch, and writes host out[0..2] = (tile-row
+ * limit, block threads, candidate index).  Synchronises the stream. */
 mrmf_status mrmf_batch_autotune(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
                                 const void* d_X, void* d_Y, mrmf_stream stream, int32_t* out);
-/* Set a launch shape directly (e.g. from a tuning cache): rows per item, block threads. */
-mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t rows_per_item, int32_t block_threads);
+/* Set a launch shape directly (e.g. from a tuning cache).  Each lattice's rows are cut into tiles spanned
+ * by its low sites, of at most tile_rows_max rows, one of (64, 128, 256, 512) * 8 / nvec; a block holds
+ * max(1, block / T) such tiles in LDS at a time.  block_threads: a multiple of 64, at most 512 and at
+ * most 4096 / nvec. */
+mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t tile_rows_max, int32_t block_threads);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,7 @@ SIGNATURES = {
     "mrmf_plan_prepare": (_i32, [_vp, _i32]),
     "mrmf_plan_set_tuning": (_i32, [_vp, _i32, _i32]),
     "mrmf_plan_autotune": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _P(_i32)]),
+    "mrmf_plan_set_shape": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "mrmf_plan_kernel_info": (_i32, [_vp, _i32, _P(_i32)]),
     "mrmf_plan_kernel_source": (_i32, [_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)]),
     "mrmf_adjoint_scratch_bytes": (_i32, [_vp, _P(_sz)]),

@@ -9,7 +9,7 @@
 //     grad_x[F]       = sum_c theta_{p_c} t_c(F)                       t_c(F) = w_c f_c(F) g[F - Delta_c]
 //     grad_theta[p]  += Re conj(t_c(F)) x[F]       for every channel c of group p
 // (diagonal terms are channels with Delta = 0).  Per-parameter sums are kept per thread in LDS, summed
-// per block in thread order, and the block partials are summed in block order by a second kernel, so
+// per block in a fixed order, and the block partials are summed by a second kernel in a fixed order, so
 // the result does not depend on scheduling.
 #include "mrmf_internal.h"
 
@@ -29,7 +29,13 @@ __device__ __forceinline__ double local_factor64(const PlanArgs& p, int op, int 
     }
 }
 
+// floor(n / d) for n < 2^32 with magic = ceil(2^64 / d)
+__device__ __forceinline__ uint32_t div_magic32(uint32_t n, uint64_t magic) {
+    return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));
+}
+
 // One pass for parameters [p0, p0 + kAdjParamChunk); the pass with p0 == 0 also writes grad_x.
+template <bool WIDE>
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const double* __restrict__ theta,
                                                        const double2* __restrict__ x,
                                                        const double2* __restrict__ g,
@@ -42,12 +48,21 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const double*
     const bool write_gx = p0 == 0;
     const int64_t stride = int64_t(gridDim.x) * kAdjBlock;
     for (int64_t F = int64_t(blockIdx.x) * kAdjBlock + tid; F < p.D; F += stride) {
-        int64_t f = F;
-        for (int i = p.N - 1; i >= 0; --i) {  // Eq. decode, least significant site first
-            const int64_t d = p.site[i].d;
-            const int64_t q = f / d;
-            dig[i][tid] = static_cast<uint8_t>(f - q * d);
-            f = q;
+        if (WIDE) {
+            int64_t f = F;
+            for (int i = p.N - 1; i >= 0; --i) {  // Eq. decode, least significant site first
+                const int64_t d = p.site[i].d;
+                const int64_t q = f / d;
+                dig[i][tid] = static_cast<uint8_t>(f - q * d);
+                f = q;
+            }
+        } else {
+            uint32_t f = static_cast<uint32_t>(F);
+            for (int i = p.N - 1; i >= 0; --i) {
+                const uint32_t q = div_magic32(f, p.site[i].magic);
+                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
+                f = q;
+            }
         }
         const double2 xf = x[F];
         const double2 gf = g[F];
@@ -90,20 +105,31 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const double*
     __syncthreads();
     const int np = p.n_params - p0 < kAdjParamChunk ? p.n_params - p0 : kAdjParamChunk;
     if (tid < np) {
+        // thread q sums its parameter's column starting at column q (a rotation that keeps the threads
+        // on different LDS banks); the order is fixed, so the result is deterministic
         double s = 0.0;
-        for (int t = 0; t < kAdjBlock; ++t) s += acc[tid][t];
+        for (int k = 0; k < kAdjBlock; ++k) s += acc[tid][(k + tid) & (kAdjBlock - 1)];
         partial[int64_t(blockIdx.x) * p.n_params + p0 + tid] = s;
     }
 }
 
-// grad_theta[p] = sum over blocks of partial[b][p], in block order.
-__global__ void k_adjoint_finalize(int nb, int n_params, const double* __restrict__ partial,
-                                   double* __restrict__ out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_params) return;
+constexpr int kFinBlock = 256;
+
+// grad_theta[q] = sum over blocks b of partial[b][q]: one block per parameter, each thread a fixed strided
+// subset of the blocks, then a fixed-order tree over the threads.
+__global__ __launch_bounds__(kFinBlock) void k_adjoint_finalize(int nb, int n_params, const double* __restrict__ partial,
+                                                              double* __restrict__ out) {
+    __shared__ double red[kFinBlock];
+    const int q = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[int64_t(b) * n_params + q];
-    out[q] = s;
+    for (int b = t; b < nb; b += kFinBlock) s += partial[int64_t(b) * n_params + q];
+    red[t] = s;
+    __syncthreads();
+    for (int h = kFinBlock / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) out[q] = red[0];
 }
 
 int adjoint_grid(int64_t D) {
@@ -143,16 +169,22 @@ mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_the
     double* partial = static_cast<double*>(d_scratch);
     const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
     const int passes = plan->n_params > 0 ? (plan->n_params + kAdjParamChunk - 1) / kAdjParamChunk : 1;
+    const bool wide = plan->D > int64_t(0xffffffffu);
     for (int k = 0; k < passes; ++k) {
-        hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kAdjBlock), 0, s, a, theta,
-                           static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
-                           static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
+        if (wide)
+            hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(kAdjBlock), 0, s, a, theta,
+                               static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
+                               static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
+        else
+            hipLaunchKernelGGL(k_adjoint<false>, dim3(grid), dim3(kAdjBlock), 0, s, a, theta,
+                               static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
+                               static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
         const mrmf_status st = launch_status();
         if (st != MRMF_OK) return st;
     }
     if (plan->n_params > 0) {
-        hipLaunchKernelGGL(k_adjoint_finalize, dim3((plan->n_params + 63) / 64), dim3(64), 0, s, grid,
-                           plan->n_params, partial, d_grad_theta);
+        hipLaunchKernelGGL(k_adjoint_finalize, dim3(plan->n_params), dim3(kFinBlock), 0, s, grid, plan->n_params,
+                           partial, d_grad_theta);
         return launch_status();
     }
     return MRMF_OK;

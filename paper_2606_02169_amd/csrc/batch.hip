@@ -7,14 +7,17 @@
 // (row F holds its nvec amplitudes contiguously, so one row is 8 * nvec bytes); offsets are multiples
 // of 32 elements.
 //
-// Work.  The rows of every lattice are cut into items of R consecutive rows; items are numbered
-// lattice by lattice.  Block v of the grid takes the contiguous item range [v I / G, (v+1) I / G), with
-// v chosen so that the blocks of one XCD (hardware places block b on XCD b mod 8) hold neighbouring
-// ranges.  Within an item every thread owns R / blockDim rows; for each row it decodes the digits once
-// into LDS, then for every channel forms the coefficient from the per-site factor tables (zero where
-// the source digit is inadmissible, App. A) and, where it is nonzero, gathers the nvec source
-// amplitudes of row F - Delta; a nonzero factor means both source digits are in range, so every load
-// stays inside the lattice's own block.
+// Work.  For a launch shape (R_max, block B), lattice b's rows are cut into tiles spanned by its low
+// sites (T_b = prod of the low d_i, the largest such product <= R_max), and an item is the P = max(1,
+// B / T_b) consecutive tiles that one block holds in LDS at a time (rows stored vector-major, so that
+// consecutive threads read consecutive 8-byte words).  Items are numbered lattice by lattice; block v of
+// the grid takes the contiguous item range [v I / G, (v+1) I / G), v chosen so that the blocks of one XCD
+// (block b runs on XCD b mod 8) hold neighbouring ranges.  Every thread owns rows of the item; for each
+// row it decodes the digits once into LDS, then for every channel forms the coefficient from the
+// per-site factor tables (zero where a source digit is inadmissible, App. A) and, where it is nonzero,
+// reads the nvec source amplitudes of row F - Delta: from LDS when both sites of the channel lie in the
+// tile (the source is then in the same tile), else from global memory.  A nonzero factor means both
+// source digits are in range, so no read leaves the lattice.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,15 +33,19 @@ namespace {
 constexpr int kBatchMaxLattices = 4096;
 constexpr int kBatchMaxSites = 32;
 constexpr int kBatchMaxBlock = 512;
-constexpr int kBatchPoolMax = 2048;  // factor-table entries of one lattice (LDS)
+constexpr int kBatchPoolMax = 2048;    // factor-table entries of one lattice (LDS)
+constexpr int kBatchTileWords = 4096;  // 8-byte words of the LDS tile (32 KB): at most 4096 / nvec rows
+constexpr int kBatchRmaxCands = 4;     // tile-row limits R_max = (64, 128, 256, 512) * 8 / nvec
 
 struct alignas(16) BLat {
     int32_t N, n_chan, n_diag, theta_off;
     int32_t D, chan_off, diag_off, site_off;
     int32_t pool_off, pool_n, pad0, pad1;
     int64_t x_off, pad2;
+    int32_t tile_rows[kBatchRmaxCands];   // T_b for each R_max candidate
+    int32_t tile_sites[kBatchRmaxCands];  // number of low sites spanning T_b
 };
-static_assert(sizeof(BLat) == 64, "BLat layout");
+static_assert(sizeof(BLat) == 96, "BLat layout");
 
 struct alignas(16) BSite {
     int32_t d, pad;
@@ -47,13 +54,14 @@ struct alignas(16) BSite {
 static_assert(sizeof(BSite) == 16, "BSite layout");
 
 // One term: coefficient theta[param] * (wr + i wi) * pool[ta + n_a] * pool[tb + n_b]; source F - delta.
-// A one-site term has b = -1 (its second factor is the pool's 1.0 entry at tb, digit 0).
+// A one-site term has b = -1 (its second factor is the pool's 1.0 entry at tb, digit 0).  low = number of
+// low sites a tile must span for the term's sites to lie in it.
 struct alignas(16) BTerm {
     int32_t a, b, ta, tb;
-    int32_t param, delta;
-    float wr, wi;
+    int32_t param, delta, low, pad;
+    float wr, wi, pad1, pad2;
 };
-static_assert(sizeof(BTerm) == 32, "BTerm layout");
+static_assert(sizeof(BTerm) == 48, "BTerm layout");
 
 struct BatchArgs {
     const BLat* lat;
@@ -71,14 +79,20 @@ __device__ __forceinline__ uint32_t umulhi_div(uint32_t n, uint64_t magic) {
 template <int NV, bool CPLX>
 __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const float* __restrict__ theta_all,
                                                         const float2* __restrict__ X, float2* __restrict__ Y,
-                                                        int32_t R) {
+                                                        int32_t rc) {
+    constexpr int kRows = kBatchTileWords / NV;
     __shared__ int32_t ibeg[kBatchMaxLattices + 1];
     __shared__ float pool[kBatchPoolMax];
     __shared__ uint8_t dig[kBatchMaxSites][kBatchMaxBlock];
+    __shared__ float2 xt[NV][kRows];
     const int tid = threadIdx.x, B = blockDim.x;
-    // item numbering: ibeg[b] = sum over b' < b of ceil(D_b' / R): counts in parallel, then a serial
-    // scan over LDS by thread 0 (n <= 4096)
-    for (int b = tid; b < A.n_lat; b += B) ibeg[b + 1] = (A.lat[b].D + R - 1) / R;
+    // items: ibeg[b] = sum over b' < b of ceil(D_b' / (P_b' T_b')); counts in parallel, then a serial scan
+    // over LDS by thread 0 (n <= 4096)
+    for (int b = tid; b < A.n_lat; b += B) {
+        const int32_t T = A.lat[b].tile_rows[rc];
+        const int32_t rows = T >= B ? T : (B / T) * T;
+        ibeg[b + 1] = (A.lat[b].D + rows - 1) / rows;
+    }
     __syncthreads();
     if (tid == 0) {
         int32_t s = 0;
@@ -95,6 +109,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const int32_t i0 = static_cast<int32_t>(int64_t(v) * I / G), i1 = static_cast<int32_t>(int64_t(v + 1) * I / G);
     int lb = -1;
     BLat L{};
+    int32_t rows = 1, ks = 0;
     int b = 0;
     {
         int lo = 0, hi = A.n_lat - 1;  // last lattice with ibeg[b] <= i0
@@ -106,19 +121,28 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     }
     for (int32_t it = i0; it < i1; ++it) {
         while (it >= ibeg[b + 1]) ++b;
+        __syncthreads();  // every thread is done with the previous item's tile (and tables)
         if (b != lb) {
-            __syncthreads();  // every thread is done with the previous lattice's tables
             L = A.lat[b];
             for (int k = tid; k < L.pool_n; k += B) pool[k] = A.pool[L.pool_off + k];
+            const int32_t T = L.tile_rows[rc];
+            rows = T >= B ? T : (B / T) * T;
+            ks = L.tile_sites[rc];
             lb = b;
-            __syncthreads();
         }
         const float* th = theta_all + L.theta_off;
         const float2* xb = X + L.x_off;
         float2* yb = Y + L.x_off;
-        const int32_t r0 = (it - ibeg[b]) * R;
-        const int32_t r1 = r0 + R < L.D ? r0 + R : L.D;
-        for (int32_t F = r0 + tid; F < r1; F += B) {
+        const int32_t r0 = (it - ibeg[b]) * rows;
+        const int32_t nr = r0 + rows < L.D ? rows : L.D - r0;
+        for (int32_t r = tid; r < nr; r += B) {
+            const float2* src = xb + int64_t(r0 + r) * NV;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) xt[q][r] = src[q];
+        }
+        __syncthreads();
+        for (int32_t r = tid; r < nr; r += B) {
+            const int32_t F = r0 + r;
             // digits, least significant site first (Eq. decode)
             uint32_t f = static_cast<uint32_t>(F);
             for (int i = L.N - 1; i >= 0; --i) {
@@ -136,26 +160,36 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
                 dr += c * t.wr;
                 if (CPLX) di += c * t.wi;
             }
-            {
-                const float2* src = xb + int64_t(F) * NV;
 #pragma unroll
-                for (int q = 0; q < NV; ++q) {
-                    const float2 s = src[q];
-                    ar[q] = dr * s.x;
-                    ai[q] = dr * s.y;
-                    if (CPLX) {
-                        ar[q] -= di * s.y;
-                        ai[q] += di * s.x;
-                    }
+            for (int q = 0; q < NV; ++q) {
+                const float2 s = xt[q][r];
+                ar[q] = dr * s.x;
+                ai[q] = dr * s.y;
+                if (CPLX) {
+                    ar[q] -= di * s.y;
+                    ai[q] += di * s.x;
                 }
             }
             for (int k = 0; k < L.n_chan; ++k) {
                 const BTerm t = A.term[L.chan_off + k];
                 const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
-                if (fa != 0.f) {  // inadmissible source digits have factor 0 (App. A)
-                    const float c = th[t.param] * fa;
-                    const float cr = c * t.wr, ci = CPLX ? c * t.wi : 0.f;
-                    const float2* src = xb + int64_t(F - t.delta) * NV;  // Eq. sourceoffset
+                if (fa == 0.f) continue;  // an inadmissible source digit has factor 0 (App. A)
+                const float c = th[t.param] * fa;
+                const float cr = c * t.wr, ci = CPLX ? c * t.wi : 0.f;
+                if (t.low <= ks) {  // both sites in the tile: the source row is in LDS (Eq. sourceoffset)
+                    const int32_t rs = r - t.delta;
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        const float2 s = xt[q][rs];
+                        ar[q] += cr * s.x;
+                        ai[q] += cr * s.y;
+                        if (CPLX) {
+                            ar[q] -= ci * s.y;
+                            ai[q] += ci * s.x;
+                        }
+                    }
+                } else {
+                    const float2* src = xb + int64_t(F - t.delta) * NV;
 #pragma unroll
                     for (int q = 0; q < NV; ++q) {
                         const float2 s = src[q];
@@ -204,11 +238,14 @@ void factor_table(const mrmf_plan_t* p, int site, int op, std::vector<float>& ou
     }
 }
 
+// Launch shapes tried by the autotuner: (R_max candidate index, block threads).
 struct Shape {
-    int32_t R, block;
+    int32_t rc, block;
 };
-const Shape kShapes[] = {{256, 256}, {512, 256}, {1024, 256}, {512, 512}, {1024, 512}, {2048, 512}, {256, 128}, {512, 128}};
+const Shape kShapes[] = {{1, 128}, {2, 128}, {2, 256}, {3, 256}, {3, 512}, {0, 64}, {1, 256}, {0, 128}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+int32_t rmax_of(int rc, int nvec) { return (64 << rc) * 8 / nvec; }
 
 }  // namespace
 }  // namespace mrmf
@@ -221,7 +258,7 @@ struct mrmf_batch_t {
     bool all_real = true;
     std::vector<unsigned char> image;
     size_t off_lat = 0, off_site = 0, off_term = 0, off_pool = 0, ws_bytes = 0;
-    int32_t R = 512, block = 256;
+    int32_t rc = 2, block = 256;  // R_max candidate index and block threads
     int32_t grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -248,8 +285,8 @@ mrmf::BatchArgs batch_args(const mrmf_batch_t* b, const void* d_ws) {
 int batch_grid(const mrmf_batch_t* b) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // enough resident blocks to cover the CUs a few times over
-    const int per_cu = b->block <= 128 ? 8 : (b->block <= 256 ? 4 : 2);
+    // two resident blocks per CU (LDS: tile 32 KB, item table 16 KB, digits, factor pool)
+    const int per_cu = 2;
     return cus * per_cu;
 }
 
@@ -258,10 +295,10 @@ mrmf_status launch(mrmf_batch_t* b, const void* d_ws, const float* theta, const 
     void* fn = mrmf::batch_kernel(b->nvec, !b->all_real);
     const int grid = batch_grid(b);
     b->grid = grid;
-    int32_t R = b->R;
+    int32_t rc = b->rc;
     const float2* xp = static_cast<const float2*>(X);
     float2* yp = static_cast<float2*>(Y);
-    void* args[] = {const_cast<mrmf::BatchArgs*>(&a), &theta, &xp, &yp, &R};
+    void* args[] = {const_cast<mrmf::BatchArgs*>(&a), &theta, &xp, &yp, &rc};
     return mrmf::hip_status(hipLaunchKernel(fn, dim3(grid), dim3(b->block), args, 0, s));
 }
 
@@ -300,6 +337,14 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
             return p ? MRMF_E_UNSUPPORTED : MRMF_E_INVALID_ARG;
         }
         BLat& L = lats[i];
+        for (int rc = 0; rc < kBatchRmaxCands; ++rc) {  // tiles spanned by the low sites, <= R_max rows
+            const int64_t rmax = rmax_of(rc, nvec);
+            int64_t T = 1;
+            int k = 0;
+            while (k < p->N && T * p->d[p->N - 1 - k] <= rmax) T *= p->d[p->N - 1 - k++];
+            L.tile_rows[rc] = static_cast<int32_t>(T);
+            L.tile_sites[rc] = k;
+        }
         L.N = p->N;
         L.D = static_cast<int32_t>(p->D);
         L.theta_off = th;
@@ -326,6 +371,7 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
             t.tb = bsite >= 0 ? table(bsite, opb) : 0;
             t.param = param;
             t.delta = static_cast<int32_t>(delta);
+            t.low = p->N - (bsite >= 0 && bsite < a ? bsite : a);
             t.wr = static_cast<float>(wr);
             t.wi = static_cast<float>(wi);
             if (wi != 0.0) b->all_real = false;
@@ -450,11 +496,15 @@ mrmf_status mrmf_batch_graph_launch(mrmf_batch b, mrmf_stream stream) {
     return mrmf::hip_status(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
 }
 
-mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t rows_per_item, int32_t block_threads) {
-    if (!b || rows_per_item < 1 || block_threads < 64 || block_threads > mrmf::kBatchMaxBlock ||
-        block_threads % 64 != 0)
+mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t tile_rows_max, int32_t block_threads) {
+    if (!b || block_threads < 64 || block_threads > mrmf::kBatchMaxBlock || block_threads % 64 != 0 ||
+        block_threads > mrmf::kBatchTileWords / b->nvec)
         return MRMF_E_INVALID_ARG;
-    b->R = rows_per_item;
+    int rc = -1;
+    for (int k = 0; k < mrmf::kBatchRmaxCands; ++k)
+        if (mrmf::rmax_of(k, b->nvec) == tile_rows_max) rc = k;
+    if (rc < 0) return MRMF_E_INVALID_ARG;
+    b->rc = rc;
     b->block = block_threads;
     return MRMF_OK;
 }
@@ -473,10 +523,11 @@ mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_t
     }
     float best = 0.f;
     int best_i = -1;
-    const int32_t R0 = b->R, B0 = b->block;
+    const int32_t R0 = b->rc, B0 = b->block;
     for (int i = 0; i < mrmf::kNumShapes && st == MRMF_OK; ++i) {
-        b->R = mrmf::kShapes[i].R;
+        b->rc = mrmf::kShapes[i].rc;
         b->block = mrmf::kShapes[i].block;
+        if (b->block > mrmf::kBatchTileWords / b->nvec) continue;
         st = launch(b, d_ws, d_theta_all, d_X, d_Y, s);  // warm-up
         if (st != MRMF_OK) break;
         hipEventRecord(e0, s);
@@ -493,13 +544,13 @@ mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_t
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (best_i < 0) {
-        b->R = R0;
+        b->rc = R0;
         b->block = B0;
         return st != MRMF_OK ? st : MRMF_E_HIP;
     }
-    b->R = mrmf::kShapes[best_i].R;
+    b->rc = mrmf::kShapes[best_i].rc;
     b->block = mrmf::kShapes[best_i].block;
-    out[0] = b->R;
+    out[0] = mrmf::rmax_of(b->rc, b->nvec);
     out[1] = b->block;
     out[2] = best_i;
     return st;

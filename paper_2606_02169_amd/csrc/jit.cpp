@@ -1092,7 +1092,8 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int64_t SZ = f32 ? 8 : 16;
     Tile tl;
-    if (!choose_tiling(p, p->inner_pref, p->unroll_pref, &tl)) return "";
+    const KernelCfg& cfg = p->cfg[f32 ? MRMF_DTYPE_C : MRMF_DTYPE_Z];
+    if (!choose_tiling(p, cfg.inner, cfg.unroll, &tl)) return "";
     const int64_t st = tl.T_in * tl.P_U;
     const int64_t n_st = p->D / st;
     int64_t dmax = 0, dmin = 0;
@@ -1103,10 +1104,10 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     // every buffer offset below 2^31 bytes: rows plus both shifts
     if ((p->D + dmax - dmin + 2 * tl.T_in) * SZ >= (int64_t(1) << 31) || n_st >= (int64_t(1) << 31)) return "";
     Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
-    gen.sched = p->tune_sched;
-    gen.bskip = p->tune_bskip != 0;
-    gen.gs = p->tune_load_group;
-    gen.variant = p->tune_variant;
+    gen.sched = cfg.sched;
+    gen.bskip = cfg.bskip != 0;
+    gen.gs = cfg.group;
+    gen.variant = cfg.variant;
     *tl_out = tl;
     if (gen.variant != MRMF_VARIANT_LIST && gen.masked_fits()) return gen.source();
     return gen.source_v2();
@@ -1161,7 +1162,8 @@ mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    if (p->tune_blocks_per_cu > 0 && p->tune_blocks_per_cu < per_cu) per_cu = p->tune_blocks_per_cu;
+    const int bpc = p->cfg[dtype].blocks_per_cu;
+    if (bpc > 0 && bpc < per_cu) per_cu = bpc;
     int64_t grid = int64_t(per_cu) * prop.multiProcessorCount;
     if (grid > n_st) grid = n_st;
     if (grid >= 8) grid -= grid % 8;
@@ -1220,19 +1222,39 @@ mrmf_plan_t::~mrmf_plan_t() {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// Replace the kernel configuration of one element type; a changed configuration drops its kernel so the
+// next call regenerates it.  Caller holds the plan mutex.
+void set_cfg(mrmf_plan_t* plan, int dtype, const mrmf::KernelCfg& c) {
+    mrmf::KernelCfg& cur = plan->cfg[dtype];
+    const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
+                      cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant;
+    cur = c;
+    if (!same) {
+        mrmf::SpecKernel& k = plan->spec[dtype];
+        if (k.mod) hipModuleUnload(k.mod);
+        k = mrmf::SpecKernel{};
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sites, int32_t unrolled_sites) {
     if (!plan || kind < MRMF_KERNEL_AUTO || kind > MRMF_KERNEL_SPECIALIZED || inner_sites < 0 ||
         inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N)
         return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
-    plan->kernel_mode = kind;
-    if (plan->inner_pref != inner_sites || plan->unroll_pref != unrolled_sites) {
-        plan->inner_pref = inner_sites;
-        plan->unroll_pref = unrolled_sites;
-        for (auto& k : plan->spec) {
-            if (k.mod) hipModuleUnload(k.mod);
-            k = mrmf::SpecKernel{};
-        }
+    for (int dt = 0; dt < 2; ++dt) {
+        mrmf::KernelCfg c = plan->cfg[dt];
+        c.mode = kind;
+        c.inner = inner_sites;
+        c.unroll = unrolled_sites;
+        set_cfg(plan, dt, c);
     }
     return MRMF_OK;
 }
@@ -1240,42 +1262,60 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
     if (!plan) return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
-    switch (knob) {
-        case MRMF_TUNE_SCHEDULE:
-            if (value != MRMF_SCHED_WINDOWS && value != MRMF_SCHED_XCD_CHUNK && value != MRMF_SCHED_BLOCK_RUN)
-                return MRMF_E_INVALID_ARG;
-            plan->tune_sched = value;
-            break;
-        case MRMF_TUNE_BRANCH_SKIP:
-            if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
-            plan->tune_bskip = value;
-            break;
-        case MRMF_TUNE_LOAD_GROUP:
-            if (value < 0 || value > 64) return MRMF_E_INVALID_ARG;
-            plan->tune_load_group = value;
-            break;
-        case MRMF_TUNE_BLOCKS_PER_CU:
-            if (value < 0 || value > 32) return MRMF_E_INVALID_ARG;
-            plan->tune_blocks_per_cu = value;
-            break;
-        case MRMF_TUNE_VARIANT:
-            if (value != MRMF_VARIANT_MASKED && value != MRMF_VARIANT_LIST) return MRMF_E_INVALID_ARG;
-            plan->tune_variant = value;
-            break;
-        default: return MRMF_E_INVALID_ARG;
+    for (int dt = 0; dt < 2; ++dt) {
+        mrmf::KernelCfg c = plan->cfg[dt];
+        switch (knob) {
+            case MRMF_TUNE_SCHEDULE:
+                if (value != MRMF_SCHED_WINDOWS && value != MRMF_SCHED_XCD_CHUNK && value != MRMF_SCHED_BLOCK_RUN)
+                    return MRMF_E_INVALID_ARG;
+                c.sched = value;
+                break;
+            case MRMF_TUNE_BRANCH_SKIP:
+                if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
+                c.bskip = value;
+                break;
+            case MRMF_TUNE_LOAD_GROUP:
+                if (value < 0 || value > 64) return MRMF_E_INVALID_ARG;
+                c.group = value;
+                break;
+            case MRMF_TUNE_BLOCKS_PER_CU:
+                if (value < 0 || value > 32) return MRMF_E_INVALID_ARG;
+                c.blocks_per_cu = value;
+                break;
+            case MRMF_TUNE_VARIANT:
+                if (value != MRMF_VARIANT_MASKED && value != MRMF_VARIANT_LIST) return MRMF_E_INVALID_ARG;
+                c.variant = value;
+                break;
+            default: return MRMF_E_INVALID_ARG;
+        }
+        set_cfg(plan, dt, c);
     }
-    for (auto& k : plan->spec) {  // the next call regenerates the kernel
-        if (k.mod) hipModuleUnload(k.mod);
-        k = mrmf::SpecKernel{};
-    }
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, int32_t inner_sites,
+                                int32_t unrolled_sites, int32_t load_group) {
+    if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) ||
+        (variant != MRMF_VARIANT_MASKED && variant != MRMF_VARIANT_LIST) || inner_sites < 0 ||
+        inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N || load_group < 0 || load_group > 64)
+        return MRMF_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(plan->mtx);
+    mrmf::KernelCfg c;  // schedule and block cap at their defaults
+    c.mode = MRMF_KERNEL_AUTO;
+    c.inner = inner_sites;
+    c.unroll = unrolled_sites;
+    c.variant = variant;
+    c.group = load_group;
+    set_cfg(plan, dtype, c);
     return MRMF_OK;
 }
 
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype) {
     if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C)) return MRMF_E_INVALID_ARG;
-    if (plan->kernel_mode == MRMF_KERNEL_GENERIC) return MRMF_OK;
+    const int32_t mode = plan->cfg[dtype].mode;
+    if (mode == MRMF_KERNEL_GENERIC) return MRMF_OK;
     const mrmf_status st = mrmf::spec_prepare(plan, dtype);
-    if (st == MRMF_E_UNSUPPORTED && plan->kernel_mode == MRMF_KERNEL_AUTO) return MRMF_OK;
+    if (st == MRMF_E_UNSUPPORTED && mode == MRMF_KERNEL_AUTO) return MRMF_OK;
     return st;
 }
 
@@ -1309,8 +1349,21 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         }
     }
     if (cands.empty()) return MRMF_E_UNSUPPORTED;
-    const int32_t mode0 = plan->kernel_mode, in0 = plan->inner_pref, un0 = plan->unroll_pref;
-    const int32_t v0 = plan->tune_variant, g0 = plan->tune_load_group;
+    mrmf::KernelCfg cfg0;
+    {
+        std::lock_guard<std::mutex> lk(plan->mtx);
+        cfg0 = plan->cfg[dtype];
+    }
+    auto apply = [&](const Cand& c, int32_t mode) {
+        std::lock_guard<std::mutex> lk(plan->mtx);
+        mrmf::KernelCfg k;
+        k.mode = mode;
+        k.inner = c.inner;
+        k.unroll = c.unrolled;
+        k.variant = c.variant;
+        k.group = c.group;
+        set_cfg(plan, dtype, k);
+    };
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return MRMF_E_HIP;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1327,9 +1380,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     mrmf_status st = MRMF_OK;
     for (size_t i = 0; i < cands.size(); ++i) {
         const Cand& c = cands[i];
-        mrmf_plan_set_kernel(plan, MRMF_KERNEL_SPECIALIZED, c.inner, c.unrolled);
-        mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, c.variant);
-        mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, c.group);
+        apply(c, MRMF_KERNEL_SPECIALIZED);
         if (spec_prepare(plan, dtype) != MRMF_OK) continue;  // this shape does not qualify
         st = run();
         if (st != MRMF_OK) break;
@@ -1350,15 +1401,12 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st != MRMF_OK || best_i < 0) {
-        mrmf_plan_set_kernel(plan, mode0, in0, un0);
-        mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, v0);
-        mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, g0);
+        std::lock_guard<std::mutex> lk(plan->mtx);
+        set_cfg(plan, dtype, cfg0);
         return st != MRMF_OK ? st : MRMF_E_UNSUPPORTED;
     }
     const Cand& c = cands[best_i];
-    mrmf_plan_set_kernel(plan, MRMF_KERNEL_SPECIALIZED, c.inner, c.unrolled);
-    mrmf_plan_set_tuning(plan, MRMF_TUNE_VARIANT, c.variant);
-    mrmf_plan_set_tuning(plan, MRMF_TUNE_LOAD_GROUP, c.group);
+    apply(c, MRMF_KERNEL_AUTO);
     st = spec_prepare(plan, dtype);
     out[0] = c.variant;
     out[1] = c.inner;
@@ -1387,7 +1435,7 @@ mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out) {
     if (!plan || !out || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C)) return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
     const mrmf::SpecKernel& K = plan->spec[dtype];
-    const bool spec = plan->kernel_mode != MRMF_KERNEL_GENERIC && K.ok;
+    const bool spec = plan->cfg[dtype].mode != MRMF_KERNEL_GENERIC && K.ok;
     out[0] = spec ? MRMF_KERNEL_SPECIALIZED : MRMF_KERNEL_GENERIC;
     out[1] = spec ? plan->N - K.k_in : 0;
     out[2] = spec ? K.T_in : 0;

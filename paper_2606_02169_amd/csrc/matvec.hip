@@ -144,10 +144,11 @@ mrmf_status matvec_dispatch(mrmf_plan_t* p, const void* d_ws, const R* theta, co
     if (!aligned(d_ws, 256) || !aligned(x, sizeof(C)) || !aligned(y, sizeof(C))) return MRMF_E_INVALID_ARG;
     const size_t bytes = size_t(p->D) * sizeof(C);
     if (ranges_overlap(x, bytes, y, bytes)) return MRMF_E_INVALID_ARG;
-    if (p->kernel_mode != MRMF_KERNEL_GENERIC) {
-        const int dtype = sizeof(R) == 4 ? MRMF_DTYPE_C : MRMF_DTYPE_Z;
+    const int dtype = sizeof(R) == 4 ? MRMF_DTYPE_C : MRMF_DTYPE_Z;
+    const int32_t mode = p->cfg[dtype].mode;
+    if (mode != MRMF_KERNEL_GENERIC) {
         const mrmf_status st = spec_launch(p, dtype, theta, x, y, s, d_skip);
-        if (st == MRMF_OK || !(st == MRMF_E_UNSUPPORTED && p->kernel_mode == MRMF_KERNEL_AUTO)) return st;
+        if (st == MRMF_OK || !(st == MRMF_E_UNSUPPORTED && mode == MRMF_KERNEL_AUTO)) return st;
     }
     const PlanArgs a = plan_args(p, d_ws);
     const int grid = generic_grid(p->D);

@@ -70,6 +70,14 @@ struct Tile {
     int64_t T_in = 1, P_U = 1;
 };
 
+// Kernel selection and shape knobs of one element type (MRMF_KERNEL_*, MRMF_TUNE_*).
+struct KernelCfg {
+    int32_t mode = MRMF_KERNEL_AUTO;
+    int32_t inner = 0;    // inner sites, 0 = library's choice
+    int32_t unroll = -1;  // unrolled sites, -1 = library's choice
+    int32_t sched = MRMF_SCHED_WINDOWS, bskip = 0, group = 0, blocks_per_cu = 0, variant = MRMF_VARIANT_MASKED;
+};
+
 // A kernel generated and compiled for one plan and element type (see jit.cpp).
 struct SpecKernel {
     bool tried = false;
@@ -103,11 +111,8 @@ struct mrmf_plan_t {
     size_t ws_bytes = 0;
     mrmf::Tiling tiling;
     // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type
-    int32_t kernel_mode = 0;
-    int32_t inner_pref = 0;
-    int32_t unroll_pref = -1;
-    int32_t tune_sched = MRMF_SCHED_WINDOWS, tune_bskip = 0, tune_load_group = 0, tune_blocks_per_cu = 0,
-            tune_variant = MRMF_VARIANT_MASKED;
+    // kernel selection and shape, per element type (MRMF_DTYPE_Z, MRMF_DTYPE_C)
+    mrmf::KernelCfg cfg[2];
     mrmf::SpecKernel spec[2];
     std::mutex mtx;
     ~mrmf_plan_t();

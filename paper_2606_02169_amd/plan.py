@@ -219,7 +219,6 @@ class Plan:
             st = L.lib().mrmf_plan_autotune(self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
                                            _stream(self.device), out)
             if st == L.MRMF_E_UNSUPPORTED:   # no specialized shape fits this plan: keep the default
-                self.set_kernel("auto")
                 self.prepare(x.dtype)
                 return dict(kind="default", key=key)
             L.check(st, "mrmf_plan_autotune")
@@ -227,8 +226,8 @@ class Plan:
                        us_per_call=out[4], D=self.D)
             if use_cache:
                 tuning.store(key, ent)
-        self.set_kernel("specialized", ent["inner_sites"], ent["unrolled_sites"])
-        self.set_tuning(variant=ent["variant"], load_group=ent["load_group"])
+        L.call("mrmf_plan_set_shape", self._handle, dt, int(ent["variant"]), int(ent["inner_sites"]),
+               int(ent["unrolled_sites"]), int(ent["load_group"]))
         self.prepare(x.dtype)
         return dict(ent, key=key)
 
@@ -348,7 +347,9 @@ class Batch:
         out = (ctypes.c_int32 * 3)()
         L.call("mrmf_batch_autotune", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
                _stream(self.device), out)
-        return dict(rows_per_item=out[0], block=out[1], candidate=out[2])
+        return dict(tile_rows_max=out[0], block=out[1], candidate=out[2])
 
-    def set_shape(self, rows_per_item: int, block: int):
-        L.call("mrmf_batch_set_shape", self._handle, int(rows_per_item), int(block))
+    def set_shape(self, tile_rows_max: int, block: int):
+        """Launch shape: tiles of at most tile_rows_max rows ((64, 128, 256, 512) * 8 / nvec) and block
+        threads (a multiple of 64, at most 512 and 4096 / nvec)."""
+        L.call("mrmf_batch_set_shape", self._handle, int(tile_rows_max), int(block))

@@ -83,7 +83,7 @@ def test_batch_autotune_keeps_results():
     Y = torch.empty_like(X)
     best = B.autotune(th, X, Y)
     print(best, flush=True)
-    assert best["rows_per_item"] > 0 and best["block"] % 64 == 0
+    assert best["tile_rows_max"] > 0 and best["block"] % 64 == 0
     Y1 = B.matvec(th, X)
     torch.cuda.synchronize()
     assert rel_err(Y1.cpu().numpy(), Y0.cpu().numpy()) <= 1e-6
@@ -111,3 +111,15 @@ def test_batch_full_size_sampled():
             ref = mf.matvec(m, x[:, v].astype(np.complex128), theta=m.theta.astype(np.float32).astype(np.float64),
                             rows=r)
             assert rel_err(yb[r, v], ref) <= TOL_C, (b, v)
+
+
+@pytest.mark.parametrize("rmax,block", [(64, 64), (128, 128), (512, 256), (512, 512), (256, 512)])
+def test_batch_every_shape(rmax, block):
+    """Each launch shape (tiles of at most rmax rows held in LDS, block threads) gives the oracle's
+    result, including tiles smaller than the block (several tiles per item) and larger ones."""
+    models, xs = W.config(4, reduced=12)
+    B, X, th = build(models, xs)
+    B.set_shape(rmax, block)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    check_all(B, models, xs, Y)
