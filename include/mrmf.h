@@ -244,7 +244,8 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
  * persistent launch.  Lattice b's block starts at element offset off_b (host query; offsets are
  * multiples of 32 elements).  d_theta_all: float, the n_params of lattice 0, then lattice 1, ...
  * (host query mrmf_batch_theta_offsets; the array must hold at least the last offset's count of
- * floats).  nvec in {1, 2, 4, 8}; at most 4096 lattices of at most 32 sites each, D_b * nvec < 2^30.
+ * floats).  nvec in {1, 2, 4, 8}; at most 2048 lattices, each of at most 32 sites, 128 terms and 128
+ * couplings, with D_b * nvec < 2^30.
  * The batch copies what it needs from the plans at creation; the plans may be destroyed afterwards. */
 mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, mrmf_batch* out);
 void mrmf_batch_destroy(mrmf_batch batch);

@@ -30,17 +30,19 @@
 namespace mrmf {
 namespace {
 
-constexpr int kBatchMaxLattices = 4096;
+constexpr int kBatchMaxLattices = 2048;
 constexpr int kBatchMaxSites = 32;
 constexpr int kBatchMaxBlock = 512;
 constexpr int kBatchPoolMax = 2048;    // factor-table entries of one lattice (LDS)
 constexpr int kBatchTileWords = 4096;  // 8-byte words of the LDS tile (32 KB): at most 4096 / nvec rows
 constexpr int kBatchRmaxCands = 4;     // tile-row limits R_max = (64, 128, 256, 512) * 8 / nvec
+constexpr int kBatchMaxTerms = 128;    // terms (channels + diagonal) of one lattice, held in LDS
+constexpr int kBatchMaxParams = 128;   // couplings of one lattice, held in LDS
 
 struct alignas(16) BLat {
     int32_t N, n_chan, n_diag, theta_off;
     int32_t D, chan_off, diag_off, site_off;
-    int32_t pool_off, pool_n, pad0, pad1;
+    int32_t pool_off, pool_n, n_params, pad1;
     int64_t x_off, pad2;
     int32_t tile_rows[kBatchRmaxCands];   // T_b for each R_max candidate
     int32_t tile_sites[kBatchRmaxCands];  // number of low sites spanning T_b
@@ -85,9 +87,12 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     __shared__ float pool[kBatchPoolMax];
     __shared__ uint8_t dig[kBatchMaxSites][kBatchMaxBlock];
     __shared__ float2 xt[NV][kRows];
+    __shared__ BTerm tl[kBatchMaxTerms];  // the current lattice's diagonal terms, then its channels
+    __shared__ BSite sl[kBatchMaxSites];
+    __shared__ float thl[kBatchMaxParams];
     const int tid = threadIdx.x, B = blockDim.x;
     // items: ibeg[b] = sum over b' < b of ceil(D_b' / (P_b' T_b')); counts in parallel, then a serial scan
-    // over LDS by thread 0 (n <= 4096)
+    // over LDS by thread 0 (n <= 2048)
     for (int b = tid; b < A.n_lat; b += B) {
         const int32_t T = A.lat[b].tile_rows[rc];
         const int32_t rows = T >= B ? T : (B / T) * T;
@@ -107,9 +112,11 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const unsigned G = gridDim.x, bid = blockIdx.x;
     const unsigned v = (G % 8u == 0u) ? (bid % 8u) * (G / 8u) + bid / 8u : bid;
     const int32_t i0 = static_cast<int32_t>(int64_t(v) * I / G), i1 = static_cast<int32_t>(int64_t(v + 1) * I / G);
+    // the current lattice's descriptor, kept in scalar registers (every field is block-uniform)
     int lb = -1;
-    BLat L{};
-    int32_t rows = 1, ks = 0;
+    int32_t N = 0, n_chan = 0, n_diag = 0, D = 0, rows = 1, ks = 0;
+    const float2* xb = X;
+    float2* yb = Y;
     int b = 0;
     {
         int lo = 0, hi = A.n_lat - 1;  // last lattice with ibeg[b] <= i0
@@ -121,20 +128,32 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     }
     for (int32_t it = i0; it < i1; ++it) {
         while (it >= ibeg[b + 1]) ++b;
+        b = __builtin_amdgcn_readfirstlane(b);
         __syncthreads();  // every thread is done with the previous item's tile (and tables)
         if (b != lb) {
-            L = A.lat[b];
-            for (int k = tid; k < L.pool_n; k += B) pool[k] = A.pool[L.pool_off + k];
-            const int32_t T = L.tile_rows[rc];
+            const BLat* L = A.lat + b;
+            N = __builtin_amdgcn_readfirstlane(L->N);
+            n_chan = __builtin_amdgcn_readfirstlane(L->n_chan);
+            n_diag = __builtin_amdgcn_readfirstlane(L->n_diag);
+            D = __builtin_amdgcn_readfirstlane(L->D);
+            const int32_t T = __builtin_amdgcn_readfirstlane(L->tile_rows[rc]);
+            ks = __builtin_amdgcn_readfirstlane(L->tile_sites[rc]);
             rows = T >= B ? T : (B / T) * T;
-            ks = L.tile_sites[rc];
+            const int64_t xo = L->x_off;
+            xb = X + xo;
+            yb = Y + xo;
+            const int32_t po = __builtin_amdgcn_readfirstlane(L->pool_off), pn = __builtin_amdgcn_readfirstlane(L->pool_n);
+            for (int k = tid; k < pn; k += B) pool[k] = A.pool[po + k];
+            // descriptors into LDS: diagonal terms then channels (stored contiguously), sites, couplings
+            const int32_t t0 = L->diag_off, nt = n_diag + n_chan, s0 = L->site_off, th0 = L->theta_off;
+            for (int k = tid; k < nt; k += B) tl[k] = A.term[t0 + k];
+            for (int k = tid; k < N; k += B) sl[k] = A.site[s0 + k];
+            for (int k = tid; k < A.lat[b].n_params; k += B) thl[k] = theta_all[th0 + k];
             lb = b;
+            __syncthreads();
         }
-        const float* th = theta_all + L.theta_off;
-        const float2* xb = X + L.x_off;
-        float2* yb = Y + L.x_off;
         const int32_t r0 = (it - ibeg[b]) * rows;
-        const int32_t nr = r0 + rows < L.D ? rows : L.D - r0;
+        const int32_t nr = r0 + rows < D ? rows : D - r0;
         for (int32_t r = tid; r < nr; r += B) {
             const float2* src = xb + int64_t(r0 + r) * NV;
 #pragma unroll
@@ -145,18 +164,18 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
             const int32_t F = r0 + r;
             // digits, least significant site first (Eq. decode)
             uint32_t f = static_cast<uint32_t>(F);
-            for (int i = L.N - 1; i >= 0; --i) {
-                const BSite s = A.site[L.site_off + i];
+            for (int i = N - 1; i >= 0; --i) {
+                const BSite s = sl[i];
                 const uint32_t q = umulhi_div(f, s.magic);
                 dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(s.d));
                 f = q;
             }
             float ar[NV], ai[NV];
             float dr = 0.f, di = 0.f;
-            for (int k = 0; k < L.n_diag; ++k) {
-                const BTerm t = A.term[L.diag_off + k];
+            for (int k = 0; k < n_diag; ++k) {
+                const BTerm t = tl[k];
                 const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
-                const float c = th[t.param] * fa;
+                const float c = thl[t.param] * fa;
                 dr += c * t.wr;
                 if (CPLX) di += c * t.wi;
             }
@@ -170,11 +189,11 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
                     ai[q] += di * s.x;
                 }
             }
-            for (int k = 0; k < L.n_chan; ++k) {
-                const BTerm t = A.term[L.chan_off + k];
+            for (int k = 0; k < n_chan; ++k) {
+                const BTerm t = tl[n_diag + k];
                 const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
                 if (fa == 0.f) continue;  // an inadmissible source digit has factor 0 (App. A)
-                const float c = th[t.param] * fa;
+                const float c = thl[t.param] * fa;
                 const float cr = c * t.wr, ci = CPLX ? c * t.wi : 0.f;
                 if (t.low <= ks) {  // both sites in the tile: the source row is in LDS (Eq. sourceoffset)
                     const int32_t rs = r - t.delta;
@@ -285,7 +304,7 @@ mrmf::BatchArgs batch_args(const mrmf_batch_t* b, const void* d_ws) {
 int batch_grid(const mrmf_batch_t* b) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // two resident blocks per CU (LDS: tile 32 KB, item table 16 KB, digits, factor pool)
+    // two resident blocks per CU (LDS: tile 32 KB, item table 8 KB, digits, factor pool, descriptors)
     const int per_cu = 2;
     return cus * per_cu;
 }
@@ -332,7 +351,8 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
     int32_t th = 0;
     for (int i = 0; i < n; ++i) {
         const mrmf_plan_t* p = plans[i];
-        if (!p || p->N > kBatchMaxSites || p->D >= (int64_t(1) << 31) / 2 / nvec) {
+        if (!p || p->N > kBatchMaxSites || p->D >= (int64_t(1) << 31) / 2 / nvec || p->n_params > kBatchMaxParams ||
+            p->chans.size() + p->diags.size() > size_t(kBatchMaxTerms)) {
             delete b;
             return p ? MRMF_E_UNSUPPORTED : MRMF_E_INVALID_ARG;
         }
@@ -346,6 +366,7 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
             L.tile_sites[rc] = k;
         }
         L.N = p->N;
+        L.n_params = p->n_params;
         L.D = static_cast<int32_t>(p->D);
         L.theta_off = th;
         L.x_off = off;

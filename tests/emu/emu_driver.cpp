@@ -9,8 +9,8 @@
 
 #include "hip_emu.h"
 
-thread_local emu_dim3 threadIdx;
-emu_dim3 blockIdx, gridDim, blockDim;
+thread_local emu_dim3 threadIdx, blockIdx;
+emu_dim3 gridDim, blockDim;
 double emu_shfl_slot[16][64];
 unsigned long long emu_ballot_slot[16][64];
 
@@ -51,14 +51,20 @@ extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* 
 
 namespace {
 struct Arg {
-    unsigned tid;
+    unsigned tid, b0, b1;
     const void *theta, *x;
     void* y;
 };
+// One host thread per GPU thread of the block, kept for every block of the range; a block barrier
+// separates consecutive blocks (their __shared__ storage is the same static storage).
 void* thread_main(void* a) {
     Arg* g = static_cast<Arg*>(a);
     threadIdx = emu_dim3{g->tid, 0, 0};
-    mrmf_spec(g->theta, g->x, g->y, nullptr);
+    for (unsigned b = g->b0; b < g->b1; ++b) {
+        blockIdx = emu_dim3{b, 0, 0};
+        mrmf_spec(g->theta, g->x, g->y, nullptr);
+        pthread_barrier_wait(&g_block_bar);
+    }
     return nullptr;
 }
 }  // namespace
@@ -88,14 +94,21 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
     pthread_attr_t attr;
     pthread_attr_init(&attr);
     pthread_attr_setstacksize(&attr, 1 << 20);
-    for (unsigned b = b0; b < b1; ++b) {
-        blockIdx = emu_dim3{b, 0, 0};
-        for (unsigned t = 0; t < block; ++t) {
-            args[t] = Arg{t, theta, x, y};
-            if (pthread_create(&th[t], &attr, thread_main, &args[t]) != 0) return -2;
+    int rc = 0;
+    unsigned started = 0;
+    for (unsigned t = 0; t < block; ++t) {
+        args[t] = Arg{t, b0, b1, theta, x, y};
+        if (pthread_create(&th[t], &attr, thread_main, &args[t]) != 0) {
+            rc = -2;
+            break;
         }
-        for (unsigned t = 0; t < block; ++t) pthread_join(th[t], nullptr);
+        ++started;
     }
+    if (rc != 0) {  // cannot run a partial block: report and stop (the started threads wait at a barrier)
+        std::fprintf(stderr, "emu: could not start %u threads\n", block);
+        std::abort();
+    }
+    for (unsigned t = 0; t < started; ++t) pthread_join(th[t], nullptr);
     pthread_attr_destroy(&attr);
     pthread_barrier_destroy(&g_block_bar);
     for (unsigned w = 0; w < nw; ++w) pthread_barrier_destroy(&g_wave_bar[w]);

@@ -26,8 +26,8 @@
 struct emu_dim3 {
     unsigned x, y, z;
 };
-extern thread_local emu_dim3 threadIdx;
-extern emu_dim3 blockIdx, gridDim, blockDim;
+extern thread_local emu_dim3 threadIdx, blockIdx;
+extern emu_dim3 gridDim, blockDim;
 
 void emu_syncthreads();
 void emu_wave_barrier();

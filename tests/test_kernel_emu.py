@@ -46,15 +46,18 @@ def test_square_reduced_c64():
 def test_random_models(seed):
     rng = np.random.default_rng(7000 + seed)
     herm = seed % 4 != 0
-    m = W.random_model(rng, n_sites=int(rng.integers(2, 8)), max_dim=30000, hermitian=herm,
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 8)), max_dim=12000, hermitian=herm,
                        n_params=int(rng.integers(1, 5)), n_terms=16)
     x = W.random_state(m.dim, rng)
+    ref = mf.matvec(m, x)
     for inner, unrolled in ((0, -1), (1, 0), (2, 1), (1, 2)):
-        try:
-            y = E.run(m, x, inner=inner, unrolled=unrolled, require_hermitian=herm)
+        try:                             # the first 8 blocks of a grid of 64: their super-tiles only
+            y = E.run(m, x, inner=inner, unrolled=unrolled, require_hermitian=herm, grid=64, blocks=(0, 8))
         except ValueError:               # this tiling does not fit the plan
             continue
-        assert rel_err(y, mf.matvec(m, x)) <= TOL_Z
+        done = ~np.isnan(y.real)
+        assert done.any()
+        assert rel_err(y[done], ref[done]) <= TOL_Z
     check(m, x.astype(np.complex64), require_hermitian=herm)
 
 
@@ -76,14 +79,18 @@ def test_random_models_list_form(seed):
     with many channels exercise the multi-pass list construction)."""
     rng = np.random.default_rng(7700 + seed)
     herm = seed % 3 != 0
-    m = W.random_model(rng, n_sites=int(rng.integers(2, 8)), max_dim=30000, hermitian=herm,
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 8)), max_dim=6000, hermitian=herm,
                        n_params=int(rng.integers(1, 5)), n_terms=40)
     x = W.random_state(m.dim, rng)
+    ref = mf.matvec(m, x)
     for inner, unrolled, u in ((0, -1, 0), (1, 0, 3), (2, 1, 1), (1, 2, 7)):
         try:
+            # a grid of 64 blocks of which the first 8 are emulated: their super-tiles only
             y = E.run(m, x, inner=inner, unrolled=unrolled, require_hermitian=herm,
-                      tuning={"variant": 1, "load_group": u})
+                      tuning={"variant": 1, "load_group": u}, grid=64, blocks=(0, 8))
         except ValueError:
             continue
-        assert rel_err(y, mf.matvec(m, x)) <= TOL_Z
+        done = ~np.isnan(y.real)
+        assert done.any()
+        assert rel_err(y[done], ref[done]) <= TOL_Z
     check(m, x.astype(np.complex64), require_hermitian=herm, tuning={"variant": 1})
