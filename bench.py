@@ -16,6 +16,8 @@ Other workloads (one JSON line each; not part of the headline):
                          against separate plain c64 and c128 calls per vector
   --workload adjoint     Tavis-Cummings (12 spins + boson cut at 64): forward and adjoint times and
                          gradient error against the oracle
+  --workload paper       the paper's chain testbeds (spin-1 ring N=15, mixed ring (1/2)^6(1)^6(3/2)^6):
+                         matvecs/s and a Lanczos ground state, beside the paper's CPU figures
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
@@ -391,6 +393,60 @@ def bench_adjoint(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------------------------------ paper testbeds
+PAPER_TABLE1 = {  # Table I, matrix-free rows (CPU, model not stated, 60 threads): context only
+    "spin1_ring_N15": {"matvecs_per_s": 6.137, "eigensolve_s": 29.28, "residual": 2.961e-10},
+    "mixed_ring_N18": {"matvecs_per_s": 0.04387, "eigensolve_s": 2748.0, "residual": 7.296e-10},
+}
+
+
+def bench_paper(args, dev):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import mf
+    from paper_2606_02169_amd.plan import Plan
+
+    out = {"metric": "H·x matvecs/s and Lanczos on the paper's chain testbeds C1 and C2 (synthetic, same lattices)",
+           "cases": {}}
+    stream = torch.cuda.current_stream(dev)
+    for model, seed, m_steps in ((W.paper_c1(), 11, 100), (W.paper_c2(), 12, 60)):
+        rng = np.random.default_rng(seed)
+        x_host = W.random_state(model.dim, rng)
+        D = model.dim
+        plan = Plan.from_model(model, device=dev)
+        x = torch.from_numpy(x_host).to(dev)
+        y = torch.empty_like(x)
+        th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+        tuned = plan.autotune(th, x, y)
+        for _ in range(3):
+            plan.matvec(th, x, out=y)
+        ms = cuda_time(lambda: plan.matvec(th, x, out=y), stream, 20)
+        rows = np.unique(rng.choice(D, 3000, replace=False)).astype(np.int64)
+        ref = mf.matvec(model, x_host, rows=rows)
+        err = float(np.linalg.norm(y[torch.from_numpy(rows).to(dev)].cpu().numpy() - ref) / np.linalg.norm(ref))
+        del y
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.lanczos(th, x, m_steps)
+        torch.cuda.synchronize()
+        lz_s = time.perf_counter() - t0
+        res = r["result"].cpu().numpy()
+        del r
+        torch.cuda.empty_cache()
+        paper = PAPER_TABLE1[model.name]
+        out["cases"][model.name] = {
+            "D": D, "seed": seed, "kernel": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites")},
+            "matvec_ms_c128": ms, "matvecs_per_s": 1000.0 / ms, "effective_GBps": 2 * D * 16 / ms / 1e6,
+            "sampled_rel_err_vs_oracle": err,
+            "lanczos": {"steps": int(res[3]), "reorth": "CGS2", "seconds": lz_s, "E0": float(res[0]),
+                        "residual": float(res[2])},
+            "paper_cpu_mf": paper, "matvec_speedup_vs_paper_cpu": (1000.0 / ms) / paper["matvecs_per_s"]}
+        log(f"{model.name}: {out['cases'][model.name]}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +455,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
-    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint"])
+    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint", "paper"])
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
     args = ap.parse_args()
@@ -414,7 +470,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "batched": bench_batched,
-     "adjoint": bench_adjoint}[args.workload](args, dev)
+     "adjoint": bench_adjoint, "paper": bench_paper}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

@@ -8,11 +8,12 @@ its output without sharing any of the computation they are compared on.
 from .model import (SPIN, BOSON, OP_Z, OP_Z2, OP_RAISE, OP_LOWER, Site, Term, Model,
                     spin_site, boson_site, dim_of, xxz_bond_terms)
 from .configs import (heisenberg_chain, ferrimagnetic_ring, square_lattice_spin1, batched_chains,
-                      tavis_cummings, random_model, xx_chain_in_field, random_state, config)
+                      tavis_cummings, random_model, xx_chain_in_field, random_state, config,
+                      staggered_xxz_ring, paper_c1, paper_c2)
 
 __all__ = [
     "SPIN", "BOSON", "OP_Z", "OP_Z2", "OP_RAISE", "OP_LOWER", "Site", "Term", "Model",
     "spin_site", "boson_site", "dim_of", "xxz_bond_terms", "heisenberg_chain", "ferrimagnetic_ring",
     "square_lattice_spin1", "batched_chains", "tavis_cummings", "random_model", "xx_chain_in_field",
-    "random_state", "config",
+    "random_state", "config", "staggered_xxz_ring", "paper_c1", "paper_c2",
 ]

@@ -142,6 +142,30 @@ def tavis_cummings(n_spins: int = 12, n_max: int = 64, omega: float = 1.0, omega
     return Model(sites, terms, theta, name=f"tavis_cummings_{n_spins}x{n_max}")
 
 
+def staggered_xxz_ring(two_s: List[int], jxy: float = 1.0, jz: float = 1.0, h: float = 0.2,
+                       name: str = "staggered_xxz_ring") -> Model:
+    """Periodic XXZ chain with sites 2s = two_s[i] and a staggered field +h on even sites, -h on odd sites.
+    Parameters: theta = [J_xy, J_z, h] (the sign of the field is carried by the term weight)."""
+    N = len(two_s)
+    terms: List[Term] = []
+    for i in range(N):
+        terms.append(Term(i, OP_Z, -1, OP_Z, 2, 1.0 if i % 2 == 0 else -1.0))
+    for i in range(N):
+        terms += xxz_bond_terms(i, (i + 1) % N, 0, 1)
+    return Model([spin_site(k) for k in two_s], terms, np.array([jxy, jz, h], dtype=np.float64), name=name)
+
+
+def paper_c1() -> Model:
+    """The paper's first testbed: spin-1 periodic chain, N = 15, J_xy = J_z = 1, staggered field 0.2."""
+    return staggered_xxz_ring([2] * 15, name="spin1_ring_N15")
+
+
+def paper_c2() -> Model:
+    """The paper's second testbed: periodic chain of 6 spin-1/2, then 6 spin-1, then 6 spin-3/2 sites,
+    J_xy = J_z = 1, staggered field 0.2 (D = 24^6)."""
+    return staggered_xxz_ring([1] * 6 + [2] * 6 + [3] * 6, name="mixed_ring_N18")
+
+
 def xx_chain_in_field(N: int, J: float, h: float) -> Model:
     """Open spin-1/2 XX chain J(S^x S^x + S^y S^y) in a uniform field h S_z: free fermions."""
     terms: List[Term] = [Term(i, OP_Z, -1, OP_Z, 1, 1.0) for i in range(N)]
