@@ -54,15 +54,20 @@ typedef struct {
 } mrmf_site;
 
 /* Local operators.  Z: S_z (spin) or a^dag a (boson); Z2: its square (App. B diagonal channel, one-site
- * only); RAISE: S_+ or a^dag (digit shift +1); LOWER: S_- or a (digit shift -1) (Sec. IV.A, App. C). */
+ * only); RAISE: S_+ or a^dag (digit shift +1); LOWER: S_- or a (digit shift -1) (Sec. IV.A, App. C);
+ * RAISE2 / LOWER2: (S_+)^2 / (S_-)^2, or a^dag^2 / a^2 (digit shift +2 / -2, one-site only: the q = +-2
+ * local monomials of App. B, e.g. the E (S_x^2 - S_y^2) = (E/2)(S_+^2 + S_-^2) zero-field-splitting term),
+ * coefficient the product of the two one-step ladder elements. */
 #define MRMF_OP_Z 0
 #define MRMF_OP_Z2 1
 #define MRMF_OP_RAISE 2
 #define MRMF_OP_LOWER 3
+#define MRMF_OP_RAISE2 4
+#define MRMF_OP_LOWER2 5
 
 /* One term of  H(theta) = sum_t theta[param_t] * (w_re + i w_im) * O_{op_a}^{(site_a)} O_{op_b}^{(site_b)}.
- * site_b = -1 makes it a one-site term (op_b ignored).  A two-site term needs site_a != site_b and
- * op_a, op_b in {Z, RAISE, LOWER}: the pair channels J^{alpha beta} of Eq. (pairham).  theta is real and
+ * site_b = -1 makes it a one-site term (op_b ignored; op_a any MRMF_OP_*).  A two-site term needs
+ * site_a != site_b and op_a, op_b in {Z, RAISE, LOWER}: the pair channels J^{alpha beta} of Eq. (pairham).  theta is real and
  * supplied per call in device memory, so couplings can change between calls without a new plan. */
 typedef struct {
     int32_t site_a, op_a, site_b, op_b;
@@ -145,12 +150,17 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                                                   issued, masked when inadmissible;
  *                             MRMF_VARIANT_LIST   - those channels are compacted per super-tile into a
  *                                                   list of admissible ones that every thread walks
- *                                                   (MRMF_TUNE_LOAD_GROUP = gathers per chunk). */
+ *                                                   (MRMF_TUNE_LOAD_GROUP = gathers per chunk).
+ *   MRMF_TUNE_ADDRESSING    : 0 = 32-bit buffer offsets while a vector (plus its gather reach) fits in
+ *                             2 GiB, 64-bit global addresses beyond that (default); 1 = 64-bit addresses
+ *                             always.  Either way every channel offset |Delta| plus a super-tile must stay
+ *                             below 2^31 bytes, else the plan keeps the generic kernel. */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
 #define MRMF_TUNE_BLOCKS_PER_CU 3
 #define MRMF_TUNE_VARIANT 4
+#define MRMF_TUNE_ADDRESSING 5
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0

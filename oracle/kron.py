@@ -7,7 +7,8 @@ with site 0 the leftmost factor, so that the flattened index is the mixed-radix 
 (notation guide), n = 0 is m = -s; for a boson site n is the occupation (App. C).
 
 Local matrices (Sec. IV.A for spins; standard truncated boson ladder for App. C):
-  spin : S_z = diag(m), <m+1|S_+|m> = sqrt(s(s+1) - m(m+1)), S_- = S_+^T, (S_z)^2
+  spin : S_z = diag(m), <m+1|S_+|m> = sqrt(s(s+1) - m(m+1)), S_- = S_+^T, (S_z)^2, (S_+)^2, (S_-)^2
+         (the (S_+-)^2 matrices as matrix products of the one-step ones)
   boson: n = diag(n), <n+1|a^dagger|n> = sqrt(n+1), a = (a^dagger)^T, n^2
 Only for small systems (dense: D <= a few thousand; sparse: D up to ~1e6).
 """
@@ -16,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from workloads.model import BOSON, OP_LOWER, OP_RAISE, OP_Z, OP_Z2, SPIN, Model, Site
+from workloads.model import BOSON, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN, Model, Site
 
 
 def local_ops(site: Site) -> dict:
@@ -36,7 +37,8 @@ def local_ops(site: Site) -> dict:
             up[i + 1, i] = np.sqrt(n[i] + 1)
     else:
         raise ValueError(site.kind)
-    return {OP_Z: z, OP_Z2: z @ z, OP_RAISE: up, OP_LOWER: up.T.copy()}
+    return {OP_Z: z, OP_Z2: z @ z, OP_RAISE: up, OP_LOWER: up.T.copy(), OP_RAISE2: up @ up,
+            OP_LOWER2: up.T @ up.T}
 
 
 def _factors(model: Model, t):

@@ -1,7 +1,7 @@
 """ORACLE (test infrastructure): Python side of the plain App-A matvec in ``mf_ref.c``.
 
 The term list of a model is first collapsed into the pseudocode's inputs (App. A): per-site one-site
-couplings (h_z, h_+, h_-, plus the (S_z)^2 coupling of App. B) and a pair list with a 3x3 table
+couplings (h_z, h_+, h_-, plus the (S_z)^2 and (S_+-)^2 couplings of App. B) and a pair list with a 3x3 table
 J^{alpha beta}, alpha, beta in (z, +, -), each coupling being theta[p] * w summed over the terms that
 land on it.  The C code then runs the pseudocode's row loop over all rows or over sampled rows.
 """
@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from workloads.model import OP_LOWER, OP_RAISE, OP_Z, OP_Z2, Model
+from workloads.model import OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, Model
 
 from . import build as _build
 
@@ -43,17 +43,17 @@ def _p(a, t):
 
 
 def app_a_inputs(model: Model, theta=None):
-    """Collapse the term list into (kind, 2s, onsite[N,4], pair_i, pair_j, J[P,3,3])."""
+    """Collapse the term list into (kind, 2s, onsite[N,6], pair_i, pair_j, J[P,3,3])."""
     theta = model.theta if theta is None else np.asarray(theta, dtype=np.float64)
     N = len(model.sites)
     kind, twok = model.site_arrays()
-    onsite = np.zeros((N, 4), dtype=np.complex128)  # h_z, h_zz, h_+, h_-
+    onsite = np.zeros((N, 6), dtype=np.complex128)  # h_z, h_zz, h_+, h_-, h_++, h_--
     pairs: dict = {}
     Jlist = []
     for t in model.terms:
         c = theta[t.param] * complex(t.w)
         if t.site_b < 0:
-            col = {OP_Z: 0, OP_Z2: 1, OP_RAISE: 2, OP_LOWER: 3}[t.op_a]
+            col = {OP_Z: 0, OP_Z2: 1, OP_RAISE: 2, OP_LOWER: 3, OP_RAISE2: 4, OP_LOWER2: 5}[t.op_a]
             onsite[t.site_a, col] += c
             continue
         if t.site_a == t.site_b or t.op_a not in _ALPHA or t.op_b not in _ALPHA:
@@ -102,7 +102,7 @@ def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
 def sources(model: Model, F0: int, count: int) -> np.ndarray:
     """Source index (or -1) of every term for target rows F0..F0+count-1: int64 [count, n_terms]."""
     _, twok = model.site_arrays()
-    al = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: 2}
+    al = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: 2, OP_RAISE2: 3, OP_LOWER2: 4}
     tt = np.array([(t.site_a, al[t.op_a], t.site_b, al[t.op_b] if t.site_b >= 0 else 0)
                    for t in model.terms], dtype=np.int32).reshape(-1, 4)
     out = np.empty((count, len(model.terms)), dtype=np.int64)
@@ -116,7 +116,8 @@ def sources(model: Model, F0: int, count: int) -> np.ndarray:
 def adjoint_model(model: Model) -> Model:
     """Term list of H^dagger: every operator replaced by its adjoint, every weight conjugated."""
     from workloads.model import Term
-    adj = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE}
+    adj = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE, OP_RAISE2: OP_LOWER2,
+           OP_LOWER2: OP_RAISE2}
     terms = [Term(t.site_a, adj[t.op_a], t.site_b, adj[t.op_b] if t.site_b >= 0 else t.op_b, t.param,
                   complex(t.w).conjugate()) for t in model.terms]
     return Model(model.sites, terms, model.theta.copy(), name=model.name + "^dag")

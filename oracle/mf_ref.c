@@ -14,7 +14,11 @@
  *     splitting, App. B), applied right after the h_z term of the same site;
  *   - truncated boson digits (App. C): the local digit is the occupation n,
  *     "z" is the number operator, "+" is a^dagger and "-" is a, with the
- *     square-root factors evaluated on the source occupation.
+ *     square-root factors evaluated on the source occupation;
+ *   - one-site (S_+)^2 and (S_-)^2 couplings (the q = +-2 channels of App. B,
+ *     Eq. generic_local_shift, as in the zero-field-splitting E term): source
+ *     digit n -+ 2, coefficient the product of the two one-step ladder elements
+ *     taken on the reconstructed source projection.
  *
  * Couplings are complex; x and y are interleaved (re, im) FP64 arrays.
  * The code is deliberately plain: one division and one modulo per digit,
@@ -26,12 +30,20 @@
 #include <stdlib.h>
 
 enum { KIND_SPIN = 0, KIND_BOSON = 1 };
-enum { AL_Z = 0, AL_P = 1, AL_M = 2 }; /* alpha in {z, +, -} */
+enum { AL_Z = 0, AL_P = 1, AL_M = 2, AL_PP = 3, AL_MM = 4 }; /* alpha in {z, +, -}; ++, -- one-site only */
 
 #define MAXSITES 64
 
-/* delta(z) = 0, delta(+) = +1, delta(-) = -1   (App. A) */
-static int delta_of(int alpha) { return alpha == AL_Z ? 0 : (alpha == AL_P ? 1 : -1); }
+/* delta(z) = 0, delta(+) = +1, delta(-) = -1 (App. A); q = +-2 for (S_+-)^2 (App. B) */
+static int delta_of(int alpha) {
+    switch (alpha) {
+        case AL_Z: return 0;
+        case AL_P: return 1;
+        case AL_M: return -1;
+        case AL_PP: return 2;
+        default: return -2;
+    }
+}
 
 /* projection of a local digit: m = n - s for a spin (notation guide), n for a boson */
 static double proj(int kind, int twok, int n) {
@@ -64,7 +76,8 @@ static int multipliers(int32_t N, const int32_t* twok, int64_t* M, int64_t* D) {
 }
 
 /*
- * onsite : [N][4] complex couplings (h_z, h_zz, h_+, h_-) as interleaved doubles, i.e. [N][4][2]
+ * onsite : [N][6] complex couplings (h_z, h_zz, h_+, h_-, h_++, h_--) as interleaved doubles, i.e.
+ *          [N][6][2]; h_++ multiplies (S_+)^2 (or a^dagger^2), h_-- multiplies (S_-)^2 (or a^2)
  * pair_i, pair_j : the P active pairs
  * J      : [P][3][3] complex couplings J^{alpha beta}, alpha, beta in (z, +, -), i.e. [P][3][3][2]
  * x      : [D] complex input;  y : [nrows] complex output
@@ -91,17 +104,29 @@ int mf_ref_matvec(int32_t N, const int32_t* kind, const int32_t* twok, const dou
         for (int i = 0; i < N; ++i) {
             int d = twok[i] + 1;
             double m = proj(kind[i], twok[i], n[i]);
-            acc += h[4 * i + 0] * m * xc[F];
-            acc += h[4 * i + 1] * (m * m) * xc[F];
+            acc += h[6 * i + 0] * m * xc[F];
+            acc += h[6 * i + 1] * (m * m) * xc[F];
             if (n[i] > 0) {
                 int64_t src = F - M[i];
                 double ms = proj(kind[i], twok[i], n[i] - 1);
-                acc += h[4 * i + 2] * lambda_local(kind[i], twok[i], AL_P, ms) * xc[src];
+                acc += h[6 * i + 2] * lambda_local(kind[i], twok[i], AL_P, ms) * xc[src];
             }
             if (n[i] < d - 1) {
                 int64_t src = F + M[i];
                 double ms = proj(kind[i], twok[i], n[i] + 1);
-                acc += h[4 * i + 3] * lambda_local(kind[i], twok[i], AL_M, ms) * xc[src];
+                acc += h[6 * i + 3] * lambda_local(kind[i], twok[i], AL_M, ms) * xc[src];
+            }
+            if (n[i] >= 2) { /* (S_+)^2: source digit n - 2, coefficient C_+^(2) on the source m */
+                int64_t src = F - 2 * M[i];
+                double ms = proj(kind[i], twok[i], n[i] - 2);
+                double c2 = lambda_local(kind[i], twok[i], AL_P, ms + 1.0) * lambda_local(kind[i], twok[i], AL_P, ms);
+                acc += h[6 * i + 4] * c2 * xc[src];
+            }
+            if (n[i] <= d - 3) { /* (S_-)^2: source digit n + 2, coefficient C_-^(2) on the source m */
+                int64_t src = F + 2 * M[i];
+                double ms = proj(kind[i], twok[i], n[i] + 2);
+                double c2 = lambda_local(kind[i], twok[i], AL_M, ms - 1.0) * lambda_local(kind[i], twok[i], AL_M, ms);
+                acc += h[6 * i + 5] * c2 * xc[src];
             }
         }
 
@@ -128,7 +153,7 @@ int mf_ref_matvec(int32_t N, const int32_t* kind, const int32_t* twok, const dou
 /*
  * Source index of every term for the target rows F0 .. F0+count-1 (Eq. sourceoffset, with the
  * admissibility test on the source digits): out[r][t] = I, or -1 when the term cannot reach F.
- * terms : [n_terms][4] = (site_a, alpha_a, site_b, alpha_b), alpha in (z, +, -) = (0, 1, 2);
+ * terms : [n_terms][4] = (site_a, alpha_a, site_b, alpha_b), alpha in (z, +, -, ++, --) = (0..4);
  *         site_b = -1 for one-site terms.
  */
 int mf_ref_sources(int32_t N, const int32_t* twok, int32_t n_terms, const int32_t* terms,

@@ -25,7 +25,9 @@ __device__ __forceinline__ double local_factor64(const PlanArgs& p, int op, int 
         case MRMF_OP_Z: return p.val[tab + n];
         case MRMF_OP_Z2: return p.val[tab + n] * p.val[tab + n];
         case MRMF_OP_RAISE: return p.up[tab + n];
-        default: return p.up[tab + n + 1];
+        case MRMF_OP_LOWER: return p.up[tab + n + 1];
+        case MRMF_OP_RAISE2: return p.up[tab + n] * p.up[tab + n - 1];
+        default: return p.up[tab + n + 1] * p.up[tab + n + 2];
     }
 }
 

@@ -244,17 +244,7 @@ void* batch_kernel(int nvec, bool cplx) {
 
 // Factor table <n|O|n - q> at target digit n (0 where the source digit n - q is outside 0..d-1).
 void factor_table(const mrmf_plan_t* p, int site, int op, std::vector<float>& out) {
-    const int d = p->d[site], tab = p->tab[site];
-    for (int n = 0; n < d; ++n) {
-        double v;
-        switch (op) {
-            case MRMF_OP_Z: v = p->val[tab + n]; break;
-            case MRMF_OP_Z2: v = p->val[tab + n] * p->val[tab + n]; break;
-            case MRMF_OP_RAISE: v = n >= 1 ? p->up[tab + n] : 0.0; break;
-            default: v = n <= d - 2 ? p->up[tab + n + 1] : 0.0; break;
-        }
-        out.push_back(static_cast<float>(v));
-    }
+    for (int n = 0; n < p->d[site]; ++n) out.push_back(static_cast<float>(local_factor_host(p, site, op, n)));
 }
 
 // Launch shapes tried by the autotuner: (R_max candidate index, block threads).

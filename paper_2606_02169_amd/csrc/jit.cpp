@@ -57,14 +57,7 @@ std::string ulit(uint64_t v) {
 std::vector<double> factor_table(const mrmf_plan_t* p, int site, int op) {
     const int d = p->d[site], tab = p->tab[site];
     std::vector<double> t(d, 0.0);
-    for (int n = 0; n < d; ++n) {
-        switch (op) {
-            case MRMF_OP_Z: t[n] = p->val[tab + n]; break;
-            case MRMF_OP_Z2: t[n] = p->val[tab + n] * p->val[tab + n]; break;
-            case MRMF_OP_RAISE: t[n] = n >= 1 ? p->up[tab + n] : 0.0; break;
-            default: t[n] = n <= d - 2 ? p->up[tab + n + 1] : 0.0; break;
-        }
-    }
+    for (int n = 0; n < d; ++n) t[n] = local_factor_host(p, site, op, n);
     return t;
 }
 
@@ -81,6 +74,73 @@ struct Gen {
     bool bskip = false;  // skip a channel whose uniform digits are inadmissible with a scalar branch
     int gs = 0;          // channels per load group (0: default)
     int variant = 0;     // MRMF_VARIANT_*
+    // 64-bit addressing: the super-tile base is a 64-bit byte offset and every access builds its buffer
+    // resource at base + scalar offset (a single resource with 32-bit offsets covers 2 GiB only)
+    bool wide = false;
+
+    // scalar byte offset of copy j's rows shifted by -delta, relative to a super-tile base `b`
+    std::string soff_expr(const std::string& b, int64_t j, int64_t delta) const {
+        const int64_t T = tl.T_in, sz = SZ();
+        std::ostringstream s;
+        if (wide)
+            s << b << " + (unsigned long long)(" << (j * T * sz - delta * sz) << "ll)";
+        else
+            s << b << " + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
+        return s.str();
+    }
+    // declaration of the super-tile base `b` for super-tile `t` (shift: the 32-bit form's base offset)
+    std::string base_decl(const std::string& b, const std::string& t, int64_t shift) const {
+        std::ostringstream s;
+        if (wide)
+            s << "const unsigned long long " << b << " = (unsigned long long)(" << t << ") * " << ST() * SZ() << "ull;";
+        else
+            s << "const unsigned " << b << " = " << (t.find(' ') != std::string::npos ? "(" + t + ")" : t) << " * "
+              << ST() * SZ() << "u + " << shift << "u;";
+        return s.str();
+    }
+    std::string rsrc_decls(int64_t shift, int64_t nrec) const {
+        std::ostringstream o;
+        if (wide)
+            o << "  const char* const xs = (const char*)x;\n  char* const ys = (char*)y;\n";
+        else
+            o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
+              << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+              << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
+              << "ll), (short)0, " << nrec << ", 0x00020000);\n";
+        return o.str();
+    }
+    // element types and the load / store macros LD(resource, lane offset, scalar offset), ST(value, ...)
+    std::string prelude() const {
+        std::ostringstream full;
+        if (f32)
+            full << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
+                 << "typedef unsigned U __attribute__((ext_vector_type(2)));\n";
+        else
+            full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
+                 << "typedef unsigned U __attribute__((ext_vector_type(4)));\n";
+        if (wide) {
+            // a buffer resource per access, based at the super-tile's byte offset (scalar arithmetic only);
+            // the lane offset stays a 32-bit register and a masked lane's 0x80000000 reads zero / drops
+            // its store as in the 32-bit form
+            const char* bits = f32 ? "64" : "128";
+            full << "#define RS(p) __builtin_amdgcn_make_buffer_rsrc((void*)(p), (short)0, 0x7fffffff, 0x00020000)\n"
+                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b" << bits
+                 << "(RS((rs) + (so)), (int)(vo), 0, 0))\n"
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b" << bits
+                 << "(__builtin_bit_cast(U, (v)), RS((rs) + (so)), (int)(vo), 0, 2)\n";
+        } else if (f32) {
+            full << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
+        } else {
+            full << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
+                 // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
+                 // constant 0; with a register scalar offset the compiler inserts no wait state between
+                 // the store and a following VALU write of its data registers, and the stored value was
+                 // then observed to be overwritten
+                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)((unsigned)(vo) + (unsigned)(so)), 0, 2)\n";
+        }
+        return full.str();
+    }
 
     int SZ() const { return f32 ? 8 : 16; }
     bool is_inner(int s) const { return s >= tl.k_in; }
@@ -149,6 +209,9 @@ struct Gen {
             std::string e;
             if (op == MRMF_OP_RAISE) e = "n" + std::to_string(s) + " >= 1u";
             if (op == MRMF_OP_LOWER) e = "n" + std::to_string(s) + " <= " + std::to_string(p->d[s] - 2) + "u";
+            if (op == MRMF_OP_RAISE2) e = "n" + std::to_string(s) + " >= 2u";
+            if (op == MRMF_OP_LOWER2)  // d <= 2: never admissible (the unsigned digit is never below 0)
+                e = p->d[s] >= 3 ? "n" + std::to_string(s) + " <= " + std::to_string(p->d[s] - 3) + "u" : "false";
             if (!e.empty()) c = c.empty() ? e : c + " && " + e;
         };
         add(a, opa);
@@ -405,10 +468,7 @@ struct Gen {
               << "  const unsigned q_da = Qda[qq], q_db = Qdb[qq], q_ta = Qta[qq], q_tb = Qtb[qq];\n"
               << "  const R q_wr = has_q ? theta[Qpr[qq]] * Qwr[qq] : (R)0, q_wi = has_q ? theta[Qpr[qq]] * Qwi[qq] : (R)0;\n";
         }
-        o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
-          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
-          << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
-          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+        o << rsrc_decls(shift, nrec)
           << "  __syncthreads();\n"
           << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
           << "  unsigned par = 0u;\n";
@@ -437,12 +497,8 @@ struct Gen {
             if (c.b >= 0 && !is_static(c.b)) uni_sites.insert(c.b);
         }
         for (int s : uni_sites) o << "    const unsigned n" << s << " = (t / " << P.M[s] / st << "u) % " << P.d[s] << "u;\n";
-        o << "    const unsigned F0 = t * " << st * sz << "u + " << shift << "u;\n";
-        auto soff = [&](int64_t j, int64_t delta) {
-            std::ostringstream s;
-            s << "F0 + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
-            return s.str();
-        };
+        o << "    " << base_decl("F0", "t", shift) << "\n";
+        auto soff = [&](int64_t j, int64_t delta) { return soff_expr("F0", j, delta); };
         for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = LD(xs, voff, " << soff(j, 0) << ");\n";
         std::vector<int> cG = cU;
         cG.insert(cG.end(), cM.begin(), cM.end());
@@ -574,20 +630,7 @@ struct Gen {
              << " mixed, " << cU.size() << " uniform), " << ndg << " diagonal terms; " << T
              << " rows per block (sites " << tl.k_in << ".." << P.N - 1 << "), " << PU << " unrolled copies (sites "
              << tl.k_u << ".." << tl.k_in - 1 << "), " << n_st << " super-tiles\n";
-        if (f32)
-            full << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
-                 << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
-        else
-            full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
-                 << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
-                 // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
-                 // constant 0; with a register scalar offset the compiler inserts no wait state between
-                 // the store and a following VALU write of its data registers, and the stored value was
-                 // then observed to be overwritten
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)((unsigned)(vo) + (unsigned)(so)), 0, 2)\n";
+        full << prelude();
         full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
         full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
         if (pool.empty()) full << "0";
@@ -864,10 +907,7 @@ struct Gen {
                 fD[{i, j}] = nm;
             }
         }
-        o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
-          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
-          << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
-          << "ll), (short)0, " << nrec << ", 0x00020000);\n"
+        o << rsrc_decls(shift, nrec)
           << "  __syncthreads();\n"
           << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
           << "  unsigned par = 0u;\n";
@@ -885,19 +925,15 @@ struct Gen {
             o << "  const unsigned t_end = " << n_st << "u, t_step = G;\n"
               << "  unsigned t = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n";
         }
-        auto soff = [&](int64_t j, int64_t delta, const std::string& base) {
-            std::ostringstream s;
-            s << base << " + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
-            return s.str();
-        };
+        auto soff = [&](int64_t j, int64_t delta, const std::string& base) { return soff_expr(base, j, delta); };
         // self rows of the first super-tile
         for (int64_t j = 0; j < PU; ++j)
             o << "  C xn" << j << " = {(R)0, (R)0};\n";
-        o << "  if (t < t_end) {\n    const unsigned Fn = t * " << st * sz << "u + " << shift << "u;\n";
+        o << "  if (t < t_end) {\n    " << base_decl("Fn", "t", shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "    xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
         o << "  }\n";
         o << "  for (; t < t_end; t += t_step) {\n"
-          << "    const unsigned F0 = t * " << st * sz << "u + " << shift << "u;\n";
+          << "    " << base_decl("F0", "t", shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = xn" << j << ";\n";
         if (use_lds) {
             o << "    C* lb = xl" << (dbuf ? " + par * " + std::to_string(xrows) + "u" : std::string("")) << ";\n";
@@ -960,7 +996,7 @@ struct Gen {
         }
         o << "    __syncthreads();\n";
         // prefetch the self rows of the next super-tile
-        o << "    if (t + t_step < t_end) {\n      const unsigned Fn = (t + t_step) * " << st * sz << "u + " << shift << "u;\n";
+        o << "    if (t + t_step < t_end) {\n      " << base_decl("Fn", "t + t_step", shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "      xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
         o << "    }\n";
         o << "    R dUr = (R)0, dUi = (R)0;\n";
@@ -999,7 +1035,8 @@ struct Gen {
                     o << "        const int so" << u << " = __builtin_amdgcn_readfirstlane(lso[par][k + " << u << "u]);"
                       << " const int g" << u << " = __builtin_amdgcn_readfirstlane(lgr[par][k + " << u << "u]);"
                       << " const R f" << u << " = lfac[(unsigned)g" << u << " * " << block << "u + tid];"
-                      << " const C s" << u << " = LD(xs, f" << u << " != (R)0 ? voff : OOB, F0 + (unsigned)so" << u << ");\n";
+                      << " const C s" << u << " = LD(xs, f" << u << " != (R)0 ? voff : OOB, F0 + "
+                      << (wide ? "(unsigned long long)(long long)so" : "(unsigned)so") << u << ");\n";
                 for (int u = 0; u < U; ++u) {
                     o << "        { const R cr = lcr[par][k + " << u << "u] * f" << u << ";";
                     if (cplx) o << " const R ci = lci[par][k + " << u << "u] * f" << u << ";";
@@ -1020,20 +1057,7 @@ struct Gen {
              << " listed), " << ndg << " diagonal terms; " << T << " rows per block (sites " << tl.k_in << ".." << P.N - 1
              << "), " << PU << " unrolled copies (sites " << tl.k_u << ".." << tl.k_in - 1 << "), " << n_st
              << " super-tiles\n";
-        if (f32)
-            full << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
-                 << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
-        else
-            full << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
-                 << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
-                 << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
-                 // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
-                 // constant 0; with a register scalar offset the compiler inserts no wait state between
-                 // the store and a following VALU write of its data registers, and the stored value was
-                 // then observed to be overwritten
-                 << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)((unsigned)(vo) + (unsigned)(so)), 0, 2)\n";
+        full << prelude();
         full << "#define KN " << pool.size() << "u\n#define KN_ALLOC " << std::max<size_t>(pool.size(), 1) << "\n";
         full << "__constant__ R K[" << std::max<size_t>(pool.size(), 1) << "] = {";
         if (pool.empty()) full << "0";
@@ -1101,9 +1125,14 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
         dmax = std::max<int64_t>(dmax, c.delta);
         dmin = std::min<int64_t>(dmin, c.delta);
     }
-    // every buffer offset below 2^31 bytes: rows plus both shifts
-    if ((p->D + dmax - dmin + 2 * tl.T_in) * SZ >= (int64_t(1) << 31) || n_st >= (int64_t(1) << 31)) return "";
+    // 32-bit buffer offsets when every offset (rows plus both shifts) stays below 2^31 bytes, else 64-bit
+    // super-tile bases; in both forms a channel's offset from its super-tile, |Delta| + st rows, is a
+    // 32-bit signed scalar
+    const int64_t lim = int64_t(1) << 31;
+    if (n_st >= lim || (std::max<int64_t>(dmax, -dmin) + st) * SZ >= lim) return "";
+    const bool wide = cfg.wide != 0 || (p->D + dmax - dmin + 2 * tl.T_in) * SZ >= lim;
     Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
+    gen.wide = wide;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
     gen.gs = cfg.group;
@@ -1231,7 +1260,8 @@ namespace {
 void set_cfg(mrmf_plan_t* plan, int dtype, const mrmf::KernelCfg& c) {
     mrmf::KernelCfg& cur = plan->cfg[dtype];
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
-                      cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant;
+                      cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
+                      cur.wide == c.wide;
     cur = c;
     if (!same) {
         mrmf::SpecKernel& k = plan->spec[dtype];
@@ -1285,6 +1315,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
             case MRMF_TUNE_VARIANT:
                 if (value != MRMF_VARIANT_MASKED && value != MRMF_VARIANT_LIST) return MRMF_E_INVALID_ARG;
                 c.variant = value;
+                break;
+            case MRMF_TUNE_ADDRESSING:
+                if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
+                c.wide = value;
                 break;
             default: return MRMF_E_INVALID_ARG;
         }

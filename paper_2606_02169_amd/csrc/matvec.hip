@@ -37,7 +37,9 @@ __device__ __forceinline__ R local_factor(const PlanArgs& p, int op, int tab, in
             return v * v;
         }
         case MRMF_OP_RAISE: return static_cast<R>(p.up[tab + n]);
-        default: return static_cast<R>(p.up[tab + n + 1]);
+        case MRMF_OP_LOWER: return static_cast<R>(p.up[tab + n + 1]);
+        case MRMF_OP_RAISE2: return static_cast<R>(p.up[tab + n] * p.up[tab + n - 1]);
+        default: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
     }
 }
 

@@ -76,6 +76,7 @@ struct KernelCfg {
     int32_t inner = 0;    // inner sites, 0 = library's choice
     int32_t unroll = -1;  // unrolled sites, -1 = library's choice
     int32_t sched = MRMF_SCHED_WINDOWS, bskip = 0, group = 0, blocks_per_cu = 0, variant = MRMF_VARIANT_MASKED;
+    int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
 };
 
 // A kernel generated and compiled for one plan and element type (see jit.cpp).
@@ -164,5 +165,7 @@ mrmf_status matvec_c_impl(mrmf_plan_t* p, const void* d_ws, const float* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
 // Generated source of the specialized kernel (no device needed); "" when the plan does not qualify.
 std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl);
+// <n|O|n - q> of site's operator op at target digit n; 0 where the source digit is out of range
+double local_factor_host(const mrmf_plan_t* p, int site, int op, int n);
 
 }  // namespace mrmf

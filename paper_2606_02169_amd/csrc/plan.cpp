@@ -18,9 +18,23 @@ using mrmf::DevSite;
 
 namespace {
 
-int shift_of(int op) { return op == MRMF_OP_RAISE ? 1 : (op == MRMF_OP_LOWER ? -1 : 0); }
+int shift_of(int op) {
+    switch (op) {
+        case MRMF_OP_RAISE: return 1;
+        case MRMF_OP_LOWER: return -1;
+        case MRMF_OP_RAISE2: return 2;
+        case MRMF_OP_LOWER2: return -2;
+        default: return 0;
+    }
+}
 int adjoint_op(int op) {
-    return op == MRMF_OP_RAISE ? MRMF_OP_LOWER : (op == MRMF_OP_LOWER ? MRMF_OP_RAISE : op);
+    switch (op) {
+        case MRMF_OP_RAISE: return MRMF_OP_LOWER;
+        case MRMF_OP_LOWER: return MRMF_OP_RAISE;
+        case MRMF_OP_RAISE2: return MRMF_OP_LOWER2;
+        case MRMF_OP_LOWER2: return MRMF_OP_RAISE2;
+        default: return op;
+    }
 }
 
 // Hermiticity of every parameter group h_p (Sec. IV.A: h_- = conj(h_+); Eq. pairham:
@@ -57,6 +71,26 @@ bool groups_hermitian(const std::vector<mrmf_term>& terms, int32_t n_params) {
 }
 
 }  // namespace
+
+namespace mrmf {
+
+// <n|O|n - q> of a local operator at target digit n, 0 where the source digit n - q is outside 0..d-1.
+// up[n] = <n|R|n-1>, so R^2 at target n is up[n] up[n-1] and L^2 is up[n+1] up[n+2] (App. B).
+double local_factor_host(const mrmf_plan_t* p, int site, int op, int n) {
+    const int d = p->d[site], tab = p->tab[site];
+    const double* val = p->val.data() + tab;
+    const double* up = p->up.data() + tab;
+    switch (op) {
+        case MRMF_OP_Z: return val[n];
+        case MRMF_OP_Z2: return val[n] * val[n];
+        case MRMF_OP_RAISE: return n >= 1 ? up[n] : 0.0;
+        case MRMF_OP_LOWER: return n <= d - 2 ? up[n + 1] : 0.0;
+        case MRMF_OP_RAISE2: return n >= 2 ? up[n] * up[n - 1] : 0.0;
+        default: return n <= d - 3 ? up[n + 1] * up[n + 2] : 0.0;
+    }
+}
+
+}  // namespace mrmf
 
 extern "C" {
 
@@ -124,10 +158,10 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
     p->terms.assign(terms, terms + n_terms);
     for (int t = 0; t < n_terms; ++t) {
         const mrmf_term& x = terms[t];
-        bool ok = x.site_a >= 0 && x.site_a < n_sites && x.op_a >= MRMF_OP_Z && x.op_a <= MRMF_OP_LOWER &&
+        bool ok = x.site_a >= 0 && x.site_a < n_sites && x.op_a >= MRMF_OP_Z && x.op_a <= MRMF_OP_LOWER2 &&
                   x.param >= 0 && x.param < n_params && std::isfinite(x.w_re) && std::isfinite(x.w_im);
         if (ok && x.site_b >= 0) {
-            ok = x.site_b < n_sites && x.site_b != x.site_a && x.op_a != MRMF_OP_Z2 &&
+            ok = x.site_b < n_sites && x.site_b != x.site_a && x.op_a != MRMF_OP_Z2 && x.op_a <= MRMF_OP_LOWER &&
                  x.op_b >= MRMF_OP_Z && x.op_b <= MRMF_OP_LOWER && x.op_b != MRMF_OP_Z2;
         } else if (ok) {
             ok = x.site_b == -1;

@@ -27,7 +27,7 @@ CACHE = os.path.join(tempfile.gettempdir(), "mrmf_emu_cache")
 
 TUNING = {"schedule": L.MRMF_TUNE_SCHEDULE, "branch_skip": L.MRMF_TUNE_BRANCH_SKIP,
           "load_group": L.MRMF_TUNE_LOAD_GROUP, "blocks_per_cu": L.MRMF_TUNE_BLOCKS_PER_CU,
-          "variant": L.MRMF_TUNE_VARIANT}
+          "variant": L.MRMF_TUNE_VARIANT, "addressing": L.MRMF_TUNE_ADDRESSING}
 
 
 def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True,

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from workloads.model import OP_LOWER, OP_RAISE, OP_Z, OP_Z2, Model, Term, boson_site, spin_site
+from workloads.model import (OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, Model, Term, boson_site,
+                             spin_site)
 from paper_2606_02169_amd import _lib as L
 from tests.helpers import host_plan
 
@@ -43,7 +44,7 @@ def test_offsets_match_ravel_multi_index(seed):
     terms = (ctypes.c_int32 * max(1, n.value))()
     L.call("mrmf_plan_offdiag_terms", h, terms)
     dims = [s.d for s in m.sites]
-    shift = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1}
+    shift = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}
     offs = _offsets(h, n.value)
     expected_terms = [i for i, t in enumerate(m.terms)
                       if shift[t.op_a] != 0 or (t.site_b >= 0 and shift[t.op_b] != 0)]
@@ -82,6 +83,11 @@ def test_plan_errors():
     assert host_plan(Model([spin_site(1)], [Term(0, OP_Z, -1, OP_Z, 1)], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
     # (S_z)^2 inside a pair term
     assert host_plan(Model([spin_site(2)] * 2, [Term(0, OP_Z2, 1, OP_Z)], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
+    # (S_+-)^2 is one-site only
+    for op in (OP_RAISE2, OP_LOWER2):
+        assert host_plan(Model([spin_site(2)] * 2, [Term(0, op, 1, OP_Z)], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
+        assert host_plan(Model([spin_site(2)] * 2, [Term(0, OP_Z, 1, op)], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
+    assert host_plan(Model([spin_site(2)], [Term(0, 6)], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
     # trivial site (d = 1) and d > 256
     assert host_plan(Model([spin_site(0)], [], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
     assert host_plan(Model([boson_site(300)], [], np.ones(1)))[0] == L.MRMF_E_INVALID_ARG
@@ -95,6 +101,9 @@ def test_plan_errors():
     nh2 = Model([spin_site(1)] * 2, [Term(0, OP_RAISE, 1, OP_LOWER, 0, 0.5 + 0.1j),
                                      Term(0, OP_LOWER, 1, OP_RAISE, 0, 0.5 + 0.1j)], np.ones(1))
     assert host_plan(nh2)[0] == L.MRMF_E_NOT_HERMITIAN
+    r2 = [Term(0, OP_RAISE2, -1, OP_Z, 0, 0.3 + 0.2j)]
+    assert host_plan(Model([spin_site(3)], r2, np.ones(1)))[0] == L.MRMF_E_NOT_HERMITIAN
+    assert host_plan(Model([spin_site(3)], r2 + [Term(0, OP_LOWER2, -1, OP_Z, 0, 0.3 - 0.2j)], np.ones(1)))[0] == 0
     h2 = Model([spin_site(1)] * 2, [Term(0, OP_RAISE, 1, OP_LOWER, 0, 0.5 + 0.1j),
                                     Term(1, OP_RAISE, 0, OP_LOWER, 0, 0.5 - 0.1j)], np.ones(1))
     assert host_plan(h2)[0] == 0           # partner written with the sites swapped

@@ -1,0 +1,122 @@
+"""One-site (S_+)^2 / (S_-)^2 (a^dag^2 / a^2) channels, the q = +-2 local monomials of App. B, on the GPU:
+generic and specialized matvec, both element types and kernel forms, the adjoint, the batched form and
+Lanczos, each against the oracle or a closed form."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import grad as ograd
+from oracle import mf
+from tests.helpers import rel_err
+from workloads.model import (OP_LOWER2, OP_RAISE2, OP_Z, OP_Z2, Model, Term, boson_site, spin_site,
+                             xxz_bond_terms)
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+TOL_Z, TOL_C = 1e-12, 2e-5
+
+
+def zfs_lattice():
+    """Spin-1 / spin-3/2 / boson chain with zero-field splitting on every spin (D S_z^2 + (E/2)(S_+^2 +
+    S_-^2)), squeezing on the bosons, XXZ bonds; theta = [J, Delta-scale, D, E, squeeze]."""
+    sites = [spin_site(2), spin_site(3), boson_site(5), spin_site(2), spin_site(3), spin_site(2), boson_site(4),
+             spin_site(3)]
+    terms = []
+    for i in range(len(sites) - 1):
+        terms += xxz_bond_terms(i, i + 1, 0, 1)
+    for i, s in enumerate(sites):
+        if s.kind == 0:
+            terms += [Term(i, OP_Z2, -1, OP_Z, 2, 1.0), Term(i, OP_RAISE2, -1, OP_Z, 3, 0.5),
+                      Term(i, OP_LOWER2, -1, OP_Z, 3, 0.5)]
+        else:
+            terms += [Term(i, OP_Z, -1, OP_Z, 2, 1.0), Term(i, OP_RAISE2, -1, OP_Z, 4, 0.5 + 0.2j),
+                      Term(i, OP_LOWER2, -1, OP_Z, 4, 0.5 - 0.2j)]
+    return Model(sites, terms, np.array([1.0, 0.8, 0.45, 0.12, 0.2]), name="zfs_chain")
+
+
+def run(p, theta, x):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    rd = torch.float64 if x.dtype == np.complex128 else torch.float32
+    y = p.matvec(torch.as_tensor(theta, dtype=rd, device=DEV), xt)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,variant", [("generic", 0), ("specialized", 0), ("specialized", 1)])
+def test_zfs_lattice_matvec(kind, variant):
+    from paper_2606_02169_amd.plan import Plan
+    m = zfs_lattice()
+    rng = np.random.default_rng(41)
+    x = W.random_state(m.dim, rng)
+    p = Plan.from_model(m)
+    p.set_kernel(kind)
+    if kind == "specialized":
+        p.set_tuning(variant=variant)
+    print(m.dim, kind, variant, flush=True)
+    ref = mf.matvec(m, x)
+    assert rel_err(run(p, m.theta, x), ref) <= TOL_Z
+    x32 = x.astype(np.complex64)
+    assert rel_err(run(p, m.theta, x32), mf.matvec(m, x32.astype(np.complex128))) <= TOL_C
+    assert p.kernel_info()["kind"] == kind
+
+
+@pytest.mark.parametrize("inner,unrolled", [(1, 1), (2, 1), (3, 0), (2, 2)])
+def test_zfs_lattice_tilings(inner, unrolled):
+    """q = +-2 channels on inner (static), unrolled and uniform sites of the specialized kernel."""
+    from paper_2606_02169_amd.plan import Plan
+    m = zfs_lattice()
+    x = W.random_state(m.dim, np.random.default_rng(42))
+    p = Plan.from_model(m)
+    p.set_kernel("specialized", inner, unrolled)
+    ref = mf.matvec(m, x)
+    for v in (0, 1):
+        p.set_tuning(variant=v)
+        print(inner, unrolled, v, p.kernel_info(), flush=True)
+        assert rel_err(run(p, m.theta, x), ref) <= TOL_Z
+
+
+def test_zfs_lattice_adjoint():
+    from paper_2606_02169_amd.plan import Plan
+    m = zfs_lattice()
+    rng = np.random.default_rng(43)
+    x, g = W.random_state(m.dim, rng), W.random_state(m.dim, rng)
+    p = Plan.from_model(m)
+    gx, gt = p.adjoint(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), torch.from_numpy(g).to(DEV))
+    rgx, rgt = ograd.adjoint(m, x, g)
+    assert rel_err(gx.cpu().numpy(), rgx) <= 1e-12
+    assert np.max(np.abs(gt.cpu().numpy() - rgt)) <= 1e-12 * max(1.0, np.max(np.abs(rgt)))
+
+
+def test_zfs_batch():
+    from paper_2606_02169_amd.plan import Batch, Plan
+    rng = np.random.default_rng(44)
+    models = [W.zero_field_splitting(k, float(rng.uniform(0.2, 1)), float(rng.uniform(0, 0.3))) for k in (2, 3, 4)]
+    models.append(zfs_lattice())
+    plans = [Plan.from_model(mm) for mm in models]
+    B = Batch(plans, 4)
+    X = torch.zeros(B.total_elems, dtype=torch.complex64, device=DEV)
+    xs = [W.random_state(mm.dim, rng, np.complex64, nvec=4) for mm in models]
+    for b, xv in enumerate(xs):
+        B.block(X, b).copy_(torch.from_numpy(xv).to(DEV))
+    th = torch.from_numpy(np.concatenate([mm.theta for mm in models]).astype(np.float32)).to(DEV)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    for b, (mm, xv) in enumerate(zip(models, xs)):
+        yb = B.block(Y, b).cpu().numpy()
+        for v in range(4):
+            ref = mf.matvec(mm, xv[:, v].astype(np.complex128), theta=mm.theta.astype(np.float32).astype(np.float64))
+            assert rel_err(yb[:, v], ref) <= TOL_C, (b, v)
+
+
+def test_squeezed_oscillator_lanczos():
+    """Lanczos ground energy of omega n + (g/2)(a^dag^2 + a^2) (truncated far above the ground state)
+    against sqrt(omega^2 - g^2)/2 - omega/2."""
+    from paper_2606_02169_amd.plan import Plan
+    w, g = 1.0, 0.35
+    m = Model([boson_site(120)], [Term(0, OP_Z, -1, OP_Z, 0, 1.0), Term(0, OP_RAISE2, -1, OP_Z, 1, 0.5),
+                                  Term(0, OP_LOWER2, -1, OP_Z, 1, 0.5)], np.array([w, g]))
+    x = W.random_state(m.dim, np.random.default_rng(45))
+    p = Plan.from_model(m)
+    r = p.lanczos(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), 80)["result"].cpu().numpy()
+    assert abs(r[0] - (np.sqrt(w * w - g * g) / 2 - w / 2)) <= 1e-10

@@ -144,3 +144,55 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     ent2 = q.autotune(th, xt)
     assert ent2["key"] == ent["key"] and ent2["inner_sites"] == ent["inner_sites"]
     assert q.kernel_info()["inner_sites"] == ent["inner_sites"]
+
+
+@pytest.mark.parametrize("seed,variant", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 1), (5, 0)])
+def test_wide_addressing_random_models(seed, variant):
+    """64-bit addressing (a buffer resource per access at the super-tile's 64-bit base), forced on small
+    random models: both forms, both element types, against the oracle."""
+    rng = np.random.default_rng(5100 + seed)
+    herm = seed % 3 != 0
+    m = W.random_model(rng, n_sites=int(rng.integers(3, 8)), max_dim=40000, hermitian=herm,
+                       n_params=int(rng.integers(1, 4)), n_terms=14)
+    print(f"seed={seed} variant={variant} D={m.dim} sites={[s.d for s in m.sites]}", flush=True)
+    p = plan(m, inner=0, require_hermitian=herm)
+    p.set_tuning(variant=variant, addressing=1)
+    x = W.random_state(m.dim, rng)
+    assert rel_err(run(p, m.theta, x), mf.matvec(m, x)) <= TOL_Z
+    assert p.kernel_info()["kind"] == "specialized"
+    assert "RS(" in p.kernel_source()
+    x32 = x.astype(np.complex64)
+    assert rel_err(run(p, m.theta, x32), mf.matvec(m, x32.astype(np.complex128))) <= TOL_C
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_wide_addressing_beyond_2gib(variant):
+    """The mixed (1/2)^6 (1)^6 (3/2)^6 ring (D = 24^6, 3.06 GB per complex128 vector, so 32-bit buffer
+    offsets cannot reach it): the specialized kernel against the generic one on the whole vector and
+    against the oracle on sampled rows, including both ends."""
+    from paper_2606_02169_amd.plan import Plan
+    m = W.paper_c2()
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(77)
+    x = W.random_state(m.dim, rng)
+    xt = torch.from_numpy(x).to(dev)
+    del x
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device=dev)
+    g = Plan.from_model(m)
+    g.set_kernel("generic")
+    y0 = g.matvec(th, xt)
+    p = Plan.from_model(m)
+    p.set_kernel("specialized", 5, 0)
+    p.set_tuning(variant=variant)
+    y = p.matvec(th, xt)
+    torch.cuda.synchronize()
+    print(p.kernel_info(), flush=True)
+    assert "RS(" in p.kernel_source()
+    assert ((y - y0).norm() / y0.norm()).item() <= 1e-14
+    del y0
+    rows = np.unique(np.concatenate([np.arange(300), np.arange(m.dim - 300, m.dim),
+                                     rng.choice(m.dim, 3000, replace=False)])).astype(np.int64)
+    idx = torch.from_numpy(rows).to(dev)
+    yr = y[idx].cpu().numpy()
+    xr = xt.cpu().numpy()
+    assert rel_err(yr, mf.matvec(m, xr, rows=rows)) <= TOL_Z

@@ -64,7 +64,8 @@ def test_random_models(seed):
 @pytest.mark.parametrize("tuning,grid", [({"schedule": 1}, 8), ({"schedule": 1}, 5), ({"branch_skip": 1}, 8),
                                          ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16),
                                          ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5),
-                                         ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7)])
+                                         ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7),
+                                         ({"addressing": 1}, 8), ({"addressing": 1, "variant": 1}, 6)])
 def test_tuning_variants(tuning, grid):
     m, x = W.config(2, reduced=12)
     check(m, x, tuning=tuning, grid=grid)
@@ -94,3 +95,25 @@ def test_random_models_list_form(seed):
         assert done.any()
         assert rel_err(y[done], ref[done]) <= TOL_Z
     check(m, x.astype(np.complex64), require_hermitian=herm, tuning={"variant": 1})
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_double_ladder_channels(variant):
+    """q = +-2 one-site channels (zero-field splitting, squeezing) on inner, unrolled and uniform sites,
+    both forms (a subset of the blocks is emulated)."""
+    from workloads.model import OP_LOWER2, OP_RAISE2, OP_Z, OP_Z2, Model, Term, boson_site, spin_site
+    sites = [spin_site(3), boson_site(4), spin_site(2), spin_site(3), spin_site(2), boson_site(5)]
+    terms = []
+    for i in range(len(sites) - 1):
+        terms += W.xxz_bond_terms(i, i + 1, 0, 0)
+    for i, s in enumerate(sites):
+        terms += [Term(i, OP_Z2 if s.kind == 0 else OP_Z, -1, OP_Z, 1, 1.0),
+                  Term(i, OP_RAISE2, -1, OP_Z, 2, 0.5 + 0.1j * i), Term(i, OP_LOWER2, -1, OP_Z, 2, 0.5 - 0.1j * i)]
+    m = Model(sites, terms, np.array([1.0, 0.4, 0.3]))
+    x = W.random_state(m.dim, np.random.default_rng(17))
+    ref = mf.matvec(m, x)
+    for inner, unrolled in ((1, 1), (2, 1), (3, 0), (2, 2)):
+        y = E.run(m, x, inner=inner, unrolled=unrolled, tuning={"variant": variant}, grid=32, blocks=(0, 6))
+        done = ~np.isnan(y.real)
+        assert done.any()
+        assert rel_err(y[done], ref[done]) <= TOL_Z, (inner, unrolled)

@@ -5,7 +5,8 @@ import pytest
 import scipy.sparse.linalg as spla
 
 import workloads as W
-from workloads.model import OP_LOWER, OP_RAISE, OP_Z, OP_Z2, Model, Term, boson_site, spin_site
+from workloads.model import (OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, Model, Term, boson_site,
+                             spin_site)
 from oracle import grad, kron, lanczos, mf
 
 
@@ -49,7 +50,7 @@ def test_sources_match_ravel_multi_index():
         D = m.dim
         src = mf.sources(m, 0, D)
         digits = np.array(np.unravel_index(np.arange(D), dims)).T       # C order: site 0 slowest
-        shift = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1}
+        shift = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}
         for t_i, t in enumerate(m.terms):
             nd = digits.copy()
             nd[:, t.site_a] -= shift[t.op_a]
@@ -155,6 +156,63 @@ def test_single_spin_in_field(two_s):
 def test_single_ion_anisotropy():
     m = Model([spin_site(2)], [Term(0, OP_Z2, -1, OP_Z, 0, 0.5)], np.ones(1))
     assert np.allclose(np.sort(np.linalg.eigvalsh(dense_from_mf(m))), [0, 0.5, 0.5], atol=1e-15)
+
+
+# ------------------------------------------------------------------ q = +-2 local monomials (App. B)
+@pytest.mark.parametrize("kind,k", [("spin", 2), ("spin", 3), ("spin", 4), ("spin", 5), ("boson", 6)])
+def test_double_ladder_matrix_elements(kind, k):
+    """(S_+)^2 and (S_-)^2 (a^dag^2, a^2) from the oracle's row loop against the closed-form elements
+    <m+2|S_+^2|m> = sqrt((s-m)(s+m+1)(s-m-1)(s+m+2)) and <n+2|a^dag^2|n> = sqrt((n+1)(n+2))."""
+    site = spin_site(k) if kind == "spin" else boson_site(k)
+    d = k + 1
+    expect = np.zeros((d, d))
+    for n in range(d - 2):
+        if kind == "spin":
+            s, m = k / 2, n - k / 2
+            expect[n + 2, n] = np.sqrt((s - m) * (s + m + 1) * (s - m - 1) * (s + m + 2))
+        else:
+            expect[n + 2, n] = np.sqrt((n + 1) * (n + 2))
+    up2 = dense_from_mf(Model([site], [Term(0, OP_RAISE2, -1, OP_Z, 0, 1.0)], np.ones(1)))
+    dn2 = dense_from_mf(Model([site], [Term(0, OP_LOWER2, -1, OP_Z, 0, 1.0)], np.ones(1)))
+    assert np.allclose(up2, expect, atol=1e-14, rtol=0)
+    assert np.allclose(dn2, expect.T, atol=1e-14, rtol=0)
+
+
+def test_zero_field_splitting_spin1():
+    """D (S_z^2 - s(s+1)/3) + E (S_x^2 - S_y^2) for s = 1 has eigenvalues -2D/3 and D/3 -+ E."""
+    Dz, E = 0.83, 0.21
+    ev = np.linalg.eigvalsh(dense_from_mf(W.zero_field_splitting(2, Dz, E))) - 2.0 * Dz / 3.0
+    assert np.allclose(ev, np.sort([-2 * Dz / 3, Dz / 3 - E, Dz / 3 + E]), atol=1e-14)
+
+
+def test_zero_field_splitting_spin32():
+    """For s = 3/2 the same Hamiltonian has two Kramers doublets at -+sqrt(D^2 + 3 E^2)."""
+    Dz, E = 0.57, 0.13
+    ev = np.linalg.eigvalsh(dense_from_mf(W.zero_field_splitting(3, Dz, E))) - 5.0 * Dz / 4.0
+    r = np.sqrt(Dz * Dz + 3 * E * E)
+    assert np.allclose(ev, [-r, -r, r, r], atol=1e-14)
+
+
+def test_squeezing_oscillator_spectrum():
+    """omega n + (g/2)(a^dag^2 + a^2) is a squeezed oscillator: E_n = sqrt(omega^2 - g^2)(n + 1/2) -
+    omega/2 for |g| < omega; with a truncation far above the low states they agree to rounding."""
+    w, g, nmax = 1.0, 0.35, 90
+    m = Model([boson_site(nmax)], [Term(0, OP_Z, -1, OP_Z, 0, 1.0), Term(0, OP_RAISE2, -1, OP_Z, 1, 0.5),
+                                   Term(0, OP_LOWER2, -1, OP_Z, 1, 0.5)], np.array([w, g]))
+    ev = np.linalg.eigvalsh(dense_from_mf(m))[:6]
+    eps = np.sqrt(w * w - g * g)
+    assert np.allclose(ev, eps * (np.arange(6) + 0.5) - w / 2, atol=1e-10, rtol=0)
+
+
+def test_double_ladder_in_products():
+    """The oracle's (S_+)^2 on a site of a several-site lattice equals the Kronecker embedding of the
+    square of its S_+ (an operator product, not the row loop's two-coefficient product)."""
+    sites = [spin_site(3), boson_site(4), spin_site(2)]
+    for site in range(3):
+        for op, base in ((OP_RAISE2, OP_RAISE), (OP_LOWER2, OP_LOWER)):
+            Hm = dense_from_mf(Model(sites, [Term(site, op, -1, OP_Z, 0, 1.0)], np.ones(1)))
+            H1 = kron.dense_H(Model(sites, [Term(site, base, -1, OP_Z, 0, 1.0)], np.ones(1)))
+            assert np.allclose(Hm, H1 @ H1, atol=1e-13, rtol=0)
 
 
 @pytest.mark.parametrize("boson_first", [False, True])

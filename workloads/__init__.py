@@ -5,15 +5,15 @@ parameter vectors and random state vectors.  It contains none of the matrix-free
 (no index decoding, no ladder coefficients, no matvec), so the oracle and the GPU path can both consume
 its output without sharing any of the computation they are compared on.
 """
-from .model import (SPIN, BOSON, OP_Z, OP_Z2, OP_RAISE, OP_LOWER, Site, Term, Model,
+from .model import (SPIN, BOSON, OP_Z, OP_Z2, OP_RAISE, OP_LOWER, OP_RAISE2, OP_LOWER2, Site, Term, Model,
                     spin_site, boson_site, dim_of, xxz_bond_terms)
 from .configs import (heisenberg_chain, ferrimagnetic_ring, square_lattice_spin1, batched_chains,
                       tavis_cummings, random_model, xx_chain_in_field, random_state, config,
-                      staggered_xxz_ring, paper_c1, paper_c2)
+                      staggered_xxz_ring, paper_c1, paper_c2, zero_field_splitting)
 
 __all__ = [
-    "SPIN", "BOSON", "OP_Z", "OP_Z2", "OP_RAISE", "OP_LOWER", "Site", "Term", "Model",
+    "SPIN", "BOSON", "OP_Z", "OP_Z2", "OP_RAISE", "OP_LOWER", "OP_RAISE2", "OP_LOWER2", "Site", "Term", "Model",
     "spin_site", "boson_site", "dim_of", "xxz_bond_terms", "heisenberg_chain", "ferrimagnetic_ring",
     "square_lattice_spin1", "batched_chains", "tavis_cummings", "random_model", "xx_chain_in_field",
-    "random_state", "config", "staggered_xxz_ring", "paper_c1", "paper_c2",
+    "random_state", "config", "staggered_xxz_ring", "paper_c1", "paper_c2", "zero_field_splitting",
 ]

@@ -11,8 +11,8 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .model import (BOSON, OP_LOWER, OP_RAISE, OP_Z, OP_Z2, SPIN, Model, Site, Term, boson_site,
-                    dim_of, spin_site, xxz_bond_terms)
+from .model import (BOSON, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN, Model, Site, Term,
+                    boson_site, dim_of, spin_site, xxz_bond_terms)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -166,6 +166,14 @@ def paper_c2() -> Model:
     return staggered_xxz_ring([1] * 6 + [2] * 6 + [3] * 6, name="mixed_ring_N18")
 
 
+def zero_field_splitting(two_s: int, Dz: float, E: float) -> Model:
+    """One spin with the zero-field splitting of App. B without its constant:
+    Dz (S_z)^2 + (E/2) ((S_+)^2 + (S_-)^2)  =  Dz (S_z)^2 + E ((S_x)^2 - (S_y)^2).  theta = [Dz, E]."""
+    terms = [Term(0, OP_Z2, -1, OP_Z, 0, 1.0), Term(0, OP_RAISE2, -1, OP_Z, 1, 0.5),
+             Term(0, OP_LOWER2, -1, OP_Z, 1, 0.5)]
+    return Model([spin_site(two_s)], terms, np.array([Dz, E], dtype=np.float64), name=f"zfs_2s{two_s}")
+
+
 def xx_chain_in_field(N: int, J: float, h: float) -> Model:
     """Open spin-1/2 XX chain J(S^x S^x + S^y S^y) in a uniform field h S_z: free fermions."""
     terms: List[Term] = [Term(i, OP_Z, -1, OP_Z, 1, 1.0) for i in range(N)]
@@ -174,7 +182,8 @@ def xx_chain_in_field(N: int, J: float, h: float) -> Model:
     return Model([spin_site(1)] * N, terms, np.array([J, h], dtype=np.float64), name=f"xx_chain_N{N}")
 
 
-_ADJ = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE}
+_ADJ = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE, OP_RAISE2: OP_LOWER2,
+        OP_LOWER2: OP_RAISE2}
 
 
 def random_model(rng, n_sites: int = 4, max_dim: int = 4096, n_params: int = 3, n_terms: int = 12,
@@ -213,7 +222,7 @@ def random_model(rng, n_sites: int = 4, max_dim: int = 4096, n_params: int = 3, 
     for _ in range(n_terms):
         if n_sites == 1 or rng.random() < 0.4:
             i = int(rng.integers(n_sites))
-            op = int(rng.choice([OP_Z, OP_Z2, OP_RAISE, OP_LOWER]))
+            op = int(rng.choice([OP_Z, OP_Z2, OP_RAISE, OP_LOWER, OP_RAISE2, OP_LOWER2]))
             add(Term(i, op, -1, OP_Z, int(rng.integers(n_params)), weight(op in (OP_Z, OP_Z2))))
         else:
             i, j = rng.choice(n_sites, size=2, replace=False)

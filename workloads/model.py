@@ -12,6 +12,8 @@ with site_b = -1 for a one-site term.  Operators (local matrices are defined by 
     OP_Z2     (S_z)^2, or n^2 on a boson site                       (one-site only)
     OP_RAISE  S_+ on a spin site, a^dagger on a boson site
     OP_LOWER  S_- on a spin site, a on a boson site
+    OP_RAISE2 (S_+)^2, or a^dagger^2                                (one-site only)
+    OP_LOWER2 (S_-)^2, or a^2                                       (one-site only)
 
 Sites are listed most significant first (site 0 is the leftmost Kronecker factor), following the
 multiplier definition of Sec. III.
@@ -24,7 +26,7 @@ from typing import List, Sequence
 import numpy as np
 
 SPIN, BOSON = 0, 1
-OP_Z, OP_Z2, OP_RAISE, OP_LOWER = 0, 1, 2, 3
+OP_Z, OP_Z2, OP_RAISE, OP_LOWER, OP_RAISE2, OP_LOWER2 = 0, 1, 2, 3, 4, 5
 
 
 @dataclass(frozen=True)
