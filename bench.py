@@ -393,6 +393,43 @@ def bench_adjoint(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------------------------------ propagation
+def bench_propagate(args, dev):
+    """exp(-i H dt) on the 20-site ring (c128): Chebyshev terms per step, time per step and per term,
+    against the plain matvec; invariants (norm, reversal) on the same vector."""
+    import torch
+
+    import workloads as W
+    from paper_2606_02169_amd.plan import Plan
+
+    model, x = W.config(2)
+    p = Plan.from_model(model, device=dev)
+    xt = torch.from_numpy(x).to(dev)
+    del x
+    th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+    p.autotune(th, xt)
+    stream = torch.cuda.current_stream(dev)
+    dt, steps = 0.05, 4
+    bnd = p.norm_bound(model.theta)
+    bounds = (-bnd, bnd)
+    r = p.propagate(th, xt, dt, 1, bounds=bounds)
+    nt = r["n_terms"]
+    out = torch.empty_like(xt)
+    ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, 3) / steps
+    y = torch.empty_like(xt)
+    ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 20)
+    back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
+    res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
+           "workload": "ferrimagnetic_ring_N20_c128", "D": model.dim, "dt": dt, "steps": steps,
+           "norm_bound": bnd, "terms_per_step": nt, "ms_per_step": ms, "ms_per_term": ms / max(1, nt - 1),
+           "matvec_ms": ms_mv, "overhead_per_term_ms": ms / max(1, nt - 1) - ms_mv,
+           "update_effective_GBps": 6 * model.dim * 16 / ((ms / max(1, nt - 1) - ms_mv) * 1e6),
+           "norm_drift": abs(torch.linalg.vector_norm(out).item() - torch.linalg.vector_norm(xt).item()),
+           "reversal_rel_err": ((back - xt).norm() / xt.norm()).item()}
+    log(str(res))
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------------------------------------ paper testbeds
 PAPER_TABLE1 = {  # Table I, matrix-free rows (CPU, model not stated, 60 threads): context only
     "spin1_ring_N15": {"matvecs_per_s": 6.137, "eigensolve_s": 29.28, "residual": 2.961e-10},
@@ -455,7 +492,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
-    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint", "paper"])
+    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint", "paper",
+                                                                  "propagate"])
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
     args = ap.parse_args()
@@ -470,7 +508,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "batched": bench_batched,
-     "adjoint": bench_adjoint, "paper": bench_paper}[args.workload](args, dev)
+     "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

@@ -249,6 +249,36 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
                          void* d_V, double* d_alpha, double* d_beta, double* d_result, void* d_u,
                          void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
 
+/* Time propagation x = exp(-i H dt)^n_steps x0 through the matvec (exact flat-basis propagation under
+ * rebuilt or driven couplings, Sec. VII): each step applies the Chebyshev expansion
+ *     exp(-i H dt) = exp(-i b dt) sum_k (2 - delta_k0) (-i)^k J_k(a dt) T_k((H - b) / a),
+ * a = (e_max - e_min) / 2, b = (e_max + e_min) / 2, cut where 2 sum of the remaining |J_k(a dt)| <= tol;
+ * one matvec and one fused vector update per term.  The spectrum of every step's H must lie in
+ * [e_min, e_max] (else the series diverges): mrmf_plan_norm_bound gives a safe symmetric bound.
+ *   d_theta      : double[n_params] for step 0; step s uses d_theta + s * theta_stride (0 = fixed H;
+ *                  n_params = a piecewise-constant drive stored step by step)
+ *   dt           : step length (negative runs backwards); n_steps >= 0
+ *   tol          : truncation bound relative to ||x0||, in (0, 1)
+ *   d_x0, d_x    : c128[D]; d_x may equal d_x0 (in place) but may not partly overlap it
+ *   d_scratch    : mrmf_propagate_scratch_bytes (three vectors), 256-B aligned
+ *   h_n_terms    : host int32 (may be NULL): Chebyshev terms per step, known when the call returns
+ * Requires a plan whose parameter groups are Hermitian (MRMF_E_NOT_HERMITIAN otherwise);
+ * MRMF_E_UNSUPPORTED when a step would need more than 2^20 terms. */
+mrmf_status mrmf_propagate_scratch_bytes(mrmf_plan plan, size_t* bytes);
+mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_theta, int64_t theta_stride,
+                             double dt, int32_t n_steps, double e_min, double e_max, double tol,
+                             const void* d_x0, void* d_x, void* d_scratch, size_t scratch_bytes,
+                             int32_t* h_n_terms, mrmf_stream stream);
+
+/* Host-only: upper bound on ||H(theta)||_2, sum over terms of |theta_p w_t| ||O_a|| ||O_b|| (triangle
+ * inequality; a one-site factor's norm is its largest matrix element).  h_theta: host double[n_params]. */
+mrmf_status mrmf_plan_norm_bound(mrmf_plan plan, const double* h_theta, double* bound);
+
+/* Host-only: the Bessel weights J_0(z) .. J_{K}(z) (z >= 0) used by mrmf_propagate_z, with K the smallest
+ * index whose tail 2 sum_{k > K} |J_k(z)| is <= tol; *n_terms = K + 1 and h_out (may be NULL, else at
+ * least cap doubles) receives them.  MRMF_E_UNSUPPORTED when more than cap terms would be needed. */
+mrmf_status mrmf_cheb_bessel(double z, double tol, int32_t cap, double* h_out, int32_t* n_terms);
+
 /* Batched form: n independent lattices (plans), each applied to a block of nvec c64 vectors stored
  * row-major as [D_b][nvec] (row F of lattice b holds its nvec amplitudes contiguously), all in one
  * persistent launch.  Lattice b's block starts at element offset off_b (host query; offsets are

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 from typing import Sequence
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -151,6 +152,49 @@ class Plan:
         L.call("mrmf_adjoint_z", self._handle, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(g), _ptr(gx),
                _ptr(gt), _ptr(scratch), nb.value, _stream(self.device))
         return gx, gt[: self.n_params]
+
+    # ------------------------------------------------------------------ time propagation
+    def norm_bound(self, theta) -> float:
+        """Upper bound on ||H(theta)||_2 (mrmf_plan_norm_bound; theta on the host or the device)."""
+        th = np.ascontiguousarray(theta.detach().cpu().numpy() if isinstance(theta, torch.Tensor) else theta,
+                                  dtype=np.float64)
+        if th.size < self.n_params:
+            raise ValueError("theta has fewer than n_params entries")
+        out = ctypes.c_double()
+        L.call("mrmf_plan_norm_bound", self._handle, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+               ctypes.byref(out))
+        return float(out.value)
+
+    def propagate(self, theta: torch.Tensor, x0: torch.Tensor, dt: float, n_steps: int = 1,
+                  bounds: tuple | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
+        """x = exp(-i H dt)^n_steps x0 by Chebyshev expansion (mrmf_propagate_z).  theta: float64
+        [n_params] (fixed H) or [n_steps, n_params] (a piecewise-constant drive, row s for step s).
+        bounds = (e_min, e_max) must contain the spectrum of every step's H; default: +-max over the
+        steps of mrmf_plan_norm_bound.  Returns dict(x=..., n_terms=Chebyshev terms per step)."""
+        _need_gpu(theta, "theta", torch.float64)
+        _need_gpu(x0, "x0", torch.complex128)
+        if x0.numel() != self.D:
+            raise ValueError("x0 has the wrong length")
+        stride = 0
+        if theta.dim() == 2:
+            if theta.shape[0] < n_steps or theta.shape[1] != self.n_params:
+                raise ValueError("theta must be [n_steps, n_params]")
+            stride = self.n_params
+        if bounds is None:
+            th = theta.detach().cpu().numpy().reshape(-1, max(1, self.n_params)) if self.n_params else np.zeros((1, 0))
+            b = max(self.norm_bound(r) for r in th[: max(1, n_steps)])
+            b = b if b > 0 else 1.0
+            bounds = (-b, b)
+        x = torch.empty_like(x0) if out is None else out
+        _need_gpu(x, "out", torch.complex128)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_propagate_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        nt = ctypes.c_int32()
+        L.call("mrmf_propagate_z", self._handle, _ptr(self.ws), _ptr(theta), int(stride), float(dt), int(n_steps),
+               float(bounds[0]), float(bounds[1]), float(tol), _ptr(x0), _ptr(x), _ptr(scratch), nb.value,
+               ctypes.byref(nt), _stream(self.device))
+        return dict(x=x, n_terms=int(nt.value), bounds=tuple(bounds), scratch=scratch)
 
     # ------------------------------------------------------------------ Lanczos
     def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",

@@ -134,3 +134,50 @@ def test_named_configs_build():
     assert W.config(2, with_state=False)[0].dim == 2 ** 10 * 3 ** 10
     assert W.config(3, with_state=False)[0].dim == 3 ** 16
     assert W.config(5, with_state=False)[0].dim == 4096 * 65
+
+
+# ------------------------------------------------------------------ propagation host helpers
+@pytest.mark.parametrize("z", [0.0, 1e-6, 0.3, 2.0, 17.5, 140.0, 2500.0])
+def test_cheb_bessel_weights(z):
+    """The Chebyshev weights J_k(z) of mrmf_propagate_z against scipy.special.jv, and the cut: the
+    dropped tail 2 sum_{k > K} |J_k| is at most tol while keeping J_K would exceed it."""
+    from scipy.special import jv
+    tol, cap = 1e-13, 8192
+    out = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    L.call("mrmf_cheb_bessel", z, tol, cap, out, ctypes.byref(n))
+    K = n.value - 1
+    got = np.array(out[: n.value])
+    ref = jv(np.arange(n.value), z)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.sqrt(z))
+    tail = 2 * np.abs(jv(np.arange(K + 1, K + 400), z)).sum()
+    assert tail <= tol * 1.0001
+    if K > 0:
+        assert tail + 2 * abs(ref[K]) > tol
+    assert L.lib().mrmf_cheb_bessel(z, tol, max(1, K), None, ctypes.byref(n)) == (
+        L.MRMF_E_UNSUPPORTED if K >= 1 else 0)
+    assert L.lib().mrmf_cheb_bessel(-1.0, tol, cap, None, ctypes.byref(n)) == L.MRMF_E_INVALID_ARG
+    assert L.lib().mrmf_cheb_bessel(z, 0.0, cap, None, ctypes.byref(n)) == L.MRMF_E_INVALID_ARG
+
+
+def test_norm_bound():
+    """mrmf_plan_norm_bound: >= the spectral radius on random models; equal to it for one term."""
+    from oracle import kron
+    rng = np.random.default_rng(12)
+    for _ in range(5):
+        m = W.random_model(rng, n_sites=3, max_dim=300)
+        st, h = host_plan(m)
+        assert st == 0
+        b = ctypes.c_double()
+        th = np.ascontiguousarray(m.theta, dtype=np.float64)
+        L.call("mrmf_plan_norm_bound", h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(b))
+        L.lib().mrmf_plan_destroy(h)
+        ev = np.linalg.eigvalsh(kron.dense_H(m))
+        assert b.value >= np.max(np.abs(ev)) * (1 - 1e-12)
+    one = Model([spin_site(3), boson_site(4)], [Term(1, OP_LOWER, -1, OP_Z, 0, 0.7)], np.array([1.5]))
+    st, h = host_plan(one, require_hermitian=False)
+    b = ctypes.c_double()
+    th = np.array([1.5])
+    L.call("mrmf_plan_norm_bound", h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(b))
+    L.lib().mrmf_plan_destroy(h)
+    assert abs(b.value - 1.5 * 0.7 * 2.0) <= 1e-15        # ||a|| on n_max = 4 is sqrt(4)
