@@ -408,6 +408,7 @@ def bench_propagate(args, dev):
     del x
     th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
     p.autotune(th, xt)
+    tuned_cheb = p.autotune(th, xt, kernel="cheb")
     stream = torch.cuda.current_stream(dev)
     dt, steps = 0.05, 4
     bnd = p.norm_bound(model.theta)
@@ -418,16 +419,75 @@ def bench_propagate(args, dev):
     ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, 3) / steps
     y = torch.empty_like(xt)
     ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 20)
+    p.set_tuning(cheb_fused=0)
+    ms_two = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, 3) / steps
+    p.set_tuning(cheb_fused=1)
     back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
     res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
            "workload": "ferrimagnetic_ring_N20_c128", "D": model.dim, "dt": dt, "steps": steps,
            "norm_bound": bnd, "terms_per_step": nt, "ms_per_step": ms, "ms_per_term": ms / max(1, nt - 1),
-           "matvec_ms": ms_mv, "overhead_per_term_ms": ms / max(1, nt - 1) - ms_mv,
-           "update_effective_GBps": 6 * model.dim * 16 / ((ms / max(1, nt - 1) - ms_mv) * 1e6),
+           "matvec_ms": ms_mv, "two_pass_ms_per_step": ms_two, "two_pass_ms_per_term": ms_two / max(1, nt - 1),
+           "fused_speedup": ms_two / ms, "cheb_kernel": {k: tuned_cheb.get(k) for k in
+                                                         ("key", "variant", "inner_sites", "unrolled_sites",
+                                                          "load_group", "us_per_call")},
            "norm_drift": abs(torch.linalg.vector_norm(out).item() - torch.linalg.vector_norm(xt).item()),
            "reversal_rel_err": ((back - xt).norm() / xt.norm()).item()}
     log(str(res))
     print(json.dumps(res), flush=True)
+
+
+# ------------------------------------------------------------------------------------------ restricted basis
+def bench_sector(args, dev):
+    """Fixed-S_z sectors (restricted basis, combinatorial-rank lookup): the 20-site ring's S_z = 0 sector
+    and the spin-1 ring N = 15 at S_z = 0, against the full-basis matvec of the same lattice."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import sector as osec
+    from paper_2606_02169_amd.plan import Plan, Sector
+
+    out = {"metric": "sector H·x (P H P^T) matvecs/s and sector Lanczos", "cases": {}}
+    stream = torch.cuda.current_stream(dev)
+    for name, model in (("ferrimagnetic_ring_N20_Sz0", W.config(2, with_state=False)[0]),
+                        ("spin1_ring_N15_Sz0", W.paper_c1())):
+        plan = Plan.from_model(model, device=dev)
+        Q = Sector.digit_sum_of(model.sites, 0.0)
+        S = Sector(plan, Q)
+        rng = np.random.default_rng(31)
+        x = W.random_state(S.dim, rng)
+        xt = torch.from_numpy(x).to(dev)
+        th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+        y = torch.empty_like(xt)
+        for _ in range(3):
+            S.matvec(th, xt, out=y)
+        ms = cuda_time(lambda: S.matvec(th, xt, out=y), stream, 20)
+        lab = osec.labels(model, Q)
+        rows = np.unique(rng.choice(S.dim, 2000, replace=False)).astype(np.int64)
+        err = float(np.linalg.norm(y[torch.from_numpy(rows).to(dev)].cpu().numpy()
+                                   - osec.matvec(model, Q, x, lab=lab, rows=rows))
+                    / np.linalg.norm(osec.matvec(model, Q, x, lab=lab, rows=rows)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = S.lanczos(th, xt, 100)
+        torch.cuda.synchronize()
+        lz = time.perf_counter() - t0
+        res = r["result"].cpu().numpy()
+        del r
+        xf = torch.zeros(model.dim, dtype=torch.complex128, device=dev)
+        plan.autotune(th, xf)
+        yf = torch.empty_like(xf)
+        ms_full = cuda_time(lambda: plan.matvec(th, xf, out=yf), stream, 20)
+        del xf, yf
+        torch.cuda.empty_cache()
+        out["cases"][name] = {
+            "D_full": model.dim, "D_sector": S.dim, "digit_sum": Q, "sector_matvec_ms": ms,
+            "sector_matvecs_per_s": 1000.0 / ms, "sector_rows_per_s": S.dim / ms * 1e3,
+            "sector_effective_GBps": 2 * S.dim * 16 / ms / 1e6, "full_matvec_ms": ms_full,
+            "sampled_rel_err_vs_oracle": err,
+            "lanczos": {"steps": int(res[3]), "seconds": lz, "E0": float(res[0]), "residual": float(res[2])}}
+        log(f"{name}: {out['cases'][name]}")
+    print(json.dumps(out), flush=True)
 
 
 # ------------------------------------------------------------------------------------------ paper testbeds
@@ -493,7 +553,7 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
     ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint", "paper",
-                                                                  "propagate"])
+                                                                  "propagate", "sector"])
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
     args = ap.parse_args()
@@ -508,7 +568,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "batched": bench_batched,
-     "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate}[args.workload](args, dev)
+     "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
+     "sector": bench_sector}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

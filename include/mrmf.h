@@ -154,13 +154,17 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *   MRMF_TUNE_ADDRESSING    : 0 = 32-bit buffer offsets while a vector (plus its gather reach) fits in
  *                             2 GiB, 64-bit global addresses beyond that (default); 1 = 64-bit addresses
  *                             always.  Either way every channel offset |Delta| plus a super-tile must stay
- *                             below 2^31 bytes, else the plan keeps the generic kernel. */
+ *                             below 2^31 bytes, else the plan keeps the generic kernel.
+ *   MRMF_TUNE_CHEB_FUSED    : 1 = mrmf_propagate_z runs each Chebyshev term as one launch of the
+ *                             specialized kernel with the Chebyshev-step epilogue (default); 0 = a matvec
+ *                             and a separate vector update per term. */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
 #define MRMF_TUNE_BLOCKS_PER_CU 3
 #define MRMF_TUNE_VARIANT 4
 #define MRMF_TUNE_ADDRESSING 5
+#define MRMF_TUNE_CHEB_FUSED 6
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0
@@ -170,7 +174,8 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
 /* Shape of the specialized kernel for one element type only (e.g. from a tuning cache): form
  * (MRMF_VARIANT_*), inner sites, unrolled sites, load group; selection becomes MRMF_KERNEL_AUTO for that
  * element type (the generic kernel runs when the shape does not fit).  mrmf_plan_set_kernel and
- * mrmf_plan_set_tuning set both element types. */
+ * mrmf_plan_set_tuning set both element types.  dtype = MRMF_SOURCE_CHEB sets the shape of the
+ * Chebyshev-step kernel of mrmf_propagate_z, which otherwise follows the c128 shape. */
 mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, int32_t inner_sites,
                                 int32_t unrolled_sites, int32_t load_group);
 /* Autotuner for the plain matvec: times every candidate shape of the specialized kernel (inner block of
@@ -178,7 +183,9 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
  * HIP events on the stream (synchronising it), keeps the fastest in the plan for this element type only
  * (selection MRMF_KERNEL_AUTO) and writes host
  * out[0..4] = (variant, inner sites, unrolled sites, load group, microseconds per call).  y is
- * overwritten; x must not overlap y. */
+ * overwritten; x must not overlap y.  dtype = MRMF_SOURCE_CHEB tunes the Chebyshev-step kernel of
+ * mrmf_propagate_z instead (c128, double theta); then d_y must hold 2 D c128 elements (the step's
+ * previous-term and accumulator vectors), all overwritten. */
 mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
                                const void* d_x, void* d_y, mrmf_stream stream, int32_t* out);
 /* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
@@ -190,6 +197,8 @@ mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out);
 /* Source text of the specialized kernel for this plan and dtype, for inspection.  Host only.  Copies at
  * most cap - 1 bytes plus a NUL into buf (cap = 0: nothing is copied) and stores the full length in
  * *len.  MRMF_E_UNSUPPORTED when the plan does not qualify for the specialized kernel. */
+#define MRMF_SOURCE_CHEB 2 /* dtype value of mrmf_plan_kernel_source: the c128 kernel with the fused
+                             Chebyshev-step epilogue that mrmf_propagate_z launches */
 mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len);
 
 /* y = H(theta) x, plain FP64 form.  d_theta: double[n_params]; d_x, d_y: c128[D], 16-byte aligned,
@@ -278,6 +287,42 @@ mrmf_status mrmf_plan_norm_bound(mrmf_plan plan, const double* h_theta, double* 
  * index whose tail 2 sum_{k > K} |J_k(z)| is <= tol; *n_terms = K + 1 and h_out (may be NULL, else at
  * least cap doubles) receives them.  MRMF_E_UNSUPPORTED when more than cap terms would be needed. */
 mrmf_status mrmf_cheb_bessel(double z, double tol, int32_t cap, double* h_out, int32_t* n_terms);
+
+/* Restricted basis of a globally constrained sector (Sec. VI, case 2; App. D): the product states whose
+ * local digits sum to digit_sum (a spin digit is n = m + s, so a fixed total magnetization M is
+ * digit_sum = M + sum_i s_i; with bosons the digit sum is the excitation number).  Sector vectors are
+ * packed in ascending full-basis order (site 0 most significant); the packed position of a state is its
+ * combinatorial rank (the Lehmer-code-style lookup of Sec. VI.B), so no table of labels is stored.
+ * The sector matvec is y = P H P^T x: channels whose source leaves the sector (every one-site ladder
+ * channel, and pair channels with q_a + q_b != 0) contribute nothing and are dropped at creation.
+ * mrmf_sector_create copies what it needs from the plan (the plan may be destroyed afterwards);
+ * MRMF_E_INVALID_ARG for digit_sum outside 0 .. sum_i (d_i - 1) or a maximal digit sum above 65535.
+ * Workspace: caller-owned, 256-B aligned, mrmf_sector_workspace_bytes, filled by mrmf_sector_upload. */
+typedef struct mrmf_sector_t* mrmf_sector;
+mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* out);
+void mrmf_sector_destroy(mrmf_sector sector);
+mrmf_status mrmf_sector_dim(mrmf_sector sector, int64_t* dim);
+mrmf_status mrmf_sector_workspace_bytes(mrmf_sector sector, size_t* bytes);
+mrmf_status mrmf_sector_upload(mrmf_sector sector, void* d_ws, size_t ws_bytes, mrmf_stream stream);
+/* y = P H(theta) P^T x on packed sector vectors (c128 / c64, 16-B / 8-B aligned, not overlapping). */
+mrmf_status mrmf_sector_matvec_z(mrmf_sector sector, const void* d_ws, const double* d_theta, const void* d_x,
+                                 void* d_y, mrmf_stream stream);
+mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const float* d_theta, const void* d_x,
+                                 void* d_y, mrmf_stream stream);
+/* d_out[i] = full-basis index of packed row r0 + i (int64, device); d_scratch: >= 8 N bytes of device
+ * memory the call may overwrite. */
+mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0, int64_t count, int64_t* d_out,
+                               void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+/* Membership test: d_out[i] = packed row of full-basis index d_F[i], or -1 when it is not a sector state
+ * (including indices outside 0 .. D-1). */
+mrmf_status mrmf_sector_lookup(mrmf_sector sector, const void* d_ws, const int64_t* d_F, int64_t count,
+                               int64_t* d_out, mrmf_stream stream);
+/* Lanczos in the sector: the arguments and results of mrmf_lanczos with vectors of the sector's dimension. */
+mrmf_status mrmf_sector_lanczos_scratch_bytes(mrmf_sector sector, int32_t m, int32_t precision, size_t* bytes);
+mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const double* d_theta_z,
+                                const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
+                                const void* d_v0, void* d_V, double* d_alpha, double* d_beta, double* d_result,
+                                void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
 
 /* Batched form: n independent lattices (plans), each applied to a block of nvec c64 vectors stored
  * row-major as [D_b][nvec] (row F of lattice b holds its nvec amplitudes contiguously), all in one

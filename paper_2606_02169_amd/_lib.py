@@ -27,6 +27,8 @@ MRMF_DTYPE_Z, MRMF_DTYPE_C = 0, 1
 MRMF_TUNE_SCHEDULE, MRMF_TUNE_BRANCH_SKIP, MRMF_TUNE_LOAD_GROUP, MRMF_TUNE_BLOCKS_PER_CU = 0, 1, 2, 3
 MRMF_TUNE_VARIANT, MRMF_VARIANT_MASKED, MRMF_VARIANT_LIST = 4, 0, 1
 MRMF_TUNE_ADDRESSING = 5
+MRMF_TUNE_CHEB_FUSED = 6
+MRMF_SOURCE_CHEB = 2
 MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 
 
@@ -87,6 +89,18 @@ SIGNATURES = {
                                 ctypes.c_double, _vp, _vp, _vp, _sz, _P(_i32), _vp]),
     "mrmf_plan_norm_bound": (_i32, [_vp, _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mrmf_cheb_bessel": (_i32, [ctypes.c_double, ctypes.c_double, _i32, _P(ctypes.c_double), _P(_i32)]),
+    "mrmf_sector_create": (_i32, [_vp, _i32, _P(_vp)]),
+    "mrmf_sector_destroy": (None, [_vp]),
+    "mrmf_sector_dim": (_i32, [_vp, _P(_i64)]),
+    "mrmf_sector_workspace_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_sector_upload": (_i32, [_vp, _vp, _sz, _vp]),
+    "mrmf_sector_matvec_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_sector_matvec_c": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_sector_labels": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _sz, _vp]),
+    "mrmf_sector_lookup": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "mrmf_sector_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),
+    "mrmf_sector_lanczos": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _sz, _vp]),
     "mrmf_batch_create": (_i32, [_i32, _P(_vp), _i32, _P(_vp)]),
     "mrmf_batch_destroy": (None, [_vp]),
     "mrmf_batch_total_elems": (_i32, [_vp, _P(_i64)]),

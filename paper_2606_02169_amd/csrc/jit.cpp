@@ -77,6 +77,38 @@ struct Gen {
     // 64-bit addressing: the super-tile base is a 64-bit byte offset and every access builds its buffer
     // resource at base + scalar offset (a single resource with 32-bit offsets covers 2 GiB only)
     bool wide = false;
+    // Chebyshev-step epilogue (time propagation): instead of y = H x the kernel computes
+    // p = ea (H x) + eb x + eg y, writes it to y and adds (ecr + i eci) p to acc
+    bool epi = false;
+
+    std::string kernel_head() const {
+        std::ostringstream o;
+        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void " << (epi ? "mrmf_spec_cheb" : "mrmf_spec")
+          << "(const R* __restrict__ theta,\n    const C* __restrict__ x, C* __restrict__ y, ";
+        if (epi) o << "C* __restrict__ acc, R ea, R eb, R eg, R ecr, R eci, ";
+        o << "const int* __restrict__ skip) {\n  if (skip != nullptr && *skip != 0) return;\n";
+        return o.str();
+    }
+    // store of copy j's result out (= (H x) at the row) at scalar offset so; xj is the row's own x
+    std::string store_out(const std::string& ind, int64_t j, const std::string& so, bool braces) const {
+        std::ostringstream o;
+        const std::string J = std::to_string(j);
+        if (!epi) {
+            o << ind << (braces ? "{ " : "") << "C out; out.x = a" << J << "r; out.y = a" << J << "i; ST(out, ys, voff, "
+              << so << ");" << (braces ? " }" : "") << "\n";
+            return o.str();
+        }
+        // the scheduling barrier keeps the two extra loads next to their use (hoisted over the whole
+        // super-tile they would hold two vectors of registers per unrolled copy)
+        o << ind << "{ __builtin_amdgcn_sched_barrier(0);\n"
+          << ind << "  const C pv = LD(ys, voff, " << so << "), av = LD(as, voff, " << so << ");\n"
+          << ind << "  C np; np.x = ea * a" << J << "r + eb * x" << J << ".x + eg * pv.x; np.y = ea * a" << J << "i + eb * x"
+          << J << ".y + eg * pv.y;\n"
+          << ind << "  ST(np, ys, voff, " << so << ");\n"
+          << ind << "  C na; na.x = av.x + ecr * np.x - eci * np.y; na.y = av.y + ecr * np.y + eci * np.x;\n"
+          << ind << "  ST(na, as, voff, " << so << "); }\n";
+        return o.str();
+    }
 
     // scalar byte offset of copy j's rows shifted by -delta, relative to a super-tile base `b`
     std::string soff_expr(const std::string& b, int64_t j, int64_t delta) const {
@@ -100,13 +132,18 @@ struct Gen {
     }
     std::string rsrc_decls(int64_t shift, int64_t nrec) const {
         std::ostringstream o;
-        if (wide)
+        if (wide) {
             o << "  const char* const xs = (const char*)x;\n  char* const ys = (char*)y;\n";
-        else
+            if (epi) o << "  char* const as = (char*)acc;\n";
+        } else {
             o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)x - " << shift
               << "ll), (short)0, " << nrec << ", 0x00020000);\n"
               << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)y - " << shift
               << "ll), (short)0, " << nrec << ", 0x00020000);\n";
+            if (epi)
+                o << "  const __amdgpu_buffer_rsrc_t as = __builtin_amdgcn_make_buffer_rsrc((void*)((char*)acc - " << shift
+                  << "ll), (short)0, " << nrec << ", 0x00020000);\n";
+        }
         return o.str();
     }
     // element types and the load / store macros LD(resource, lane offset, scalar offset), ST(value, ...)
@@ -347,9 +384,7 @@ struct Gen {
         o << "__device__ __forceinline__ unsigned dig(unsigned t, unsigned long long mm, unsigned d, unsigned long long dm) {\n"
           << "  const unsigned q = mm ? (unsigned)__umul64hi(mm, (unsigned long long)t) : t;\n"
           << "  return q - (unsigned)__umul64hi(dm, (unsigned long long)q) * d;\n}\n";
-        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void mrmf_spec(const R* __restrict__ theta,\n"
-          << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
-          << "  if (skip != nullptr && *skip != 0) return;\n";
+        o << kernel_head();
         if (use_lds) o << "  __shared__ C xl[" << (dbuf ? 2 : 1) * xrows << "];\n";
         if (nit > 0) {
             o << "  __shared__ R tr[2][" << nit << "];\n";
@@ -622,7 +657,7 @@ struct Gen {
             emit_accum(g);
         }
         for (int64_t j = 0; j < PU; ++j)
-            o << "    { C out; out.x = a" << j << "r; out.y = a" << j << "i; ST(out, ys, voff, " << soff(j, 0) << "); }\n";
+            o << store_out("    ", j, soff(j, 0), true);
         o << "    par ^= 1u;\n  }\n}\n";
 
         std::ostringstream full;
@@ -803,9 +838,7 @@ struct Gen {
         o << "__device__ __forceinline__ unsigned dig(unsigned t, unsigned long long mm, unsigned d, unsigned long long dm) {\n"
           << "  const unsigned q = mm ? (unsigned)__umul64hi(mm, (unsigned long long)t) : t;\n"
           << "  return q - (unsigned)__umul64hi(dm, (unsigned long long)q) * d;\n}\n";
-        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void mrmf_spec(const R* __restrict__ theta,\n"
-          << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
-          << "  if (skip != nullptr && *skip != 0) return;\n";
+        o << kernel_head();
         const bool dbuf = use_lds && 2 * xrows * sz <= 49152;
         if (use_lds) o << "  __shared__ C xl[" << (dbuf ? 2 : 1) * xrows << "];\n";
         o << "  __shared__ int lso[2][" << PU * CAP << "];\n"
@@ -1046,8 +1079,7 @@ struct Gen {
                 }
                 o << "      }\n";
             }
-            o << "      C out; out.x = a" << j << "r; out.y = a" << j << "i; ST(out, ys, voff, " << soff(j, 0, "F0") << ");\n"
-              << "    }\n";
+            o << store_out("      ", j, soff(j, 0, "F0"), false) << "    }\n";
         }
         if (!dbuf) o << "    __syncthreads();\n";
         o << "    par ^= 1u;\n  }\n}\n";
@@ -1112,11 +1144,11 @@ bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, Tile* 
 
 }  // namespace
 
-std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
+std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int64_t SZ = f32 ? 8 : 16;
     Tile tl;
-    const KernelCfg& cfg = p->cfg[f32 ? MRMF_DTYPE_C : MRMF_DTYPE_Z];
+    const KernelCfg& cfg = p->cfg[epi && p->cheb_shape_set ? kSlotCheb : f32 ? MRMF_DTYPE_C : MRMF_DTYPE_Z];
     if (!choose_tiling(p, cfg.inner, cfg.unroll, &tl)) return "";
     const int64_t st = tl.T_in * tl.P_U;
     const int64_t n_st = p->D / st;
@@ -1133,6 +1165,7 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
     const bool wide = cfg.wide != 0 || (p->D + dmax - dmin + 2 * tl.T_in) * SZ >= lim;
     Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
     gen.wide = wide;
+    gen.epi = epi;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
     gen.gs = cfg.group;
@@ -1144,11 +1177,13 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out) {
 
 namespace {
 
-mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
+// slot: MRMF_DTYPE_Z, MRMF_DTYPE_C, or kSlotCheb (c128 with the Chebyshev-step epilogue)
+mrmf_status compile_spec(mrmf_plan_t* p, int slot, SpecKernel& K) {
     K.tried = true;
     K.ok = false;
+    const int dtype = slot == kSlotCheb ? MRMF_DTYPE_Z : slot;
     Tile tl;
-    const std::string src = spec_source(p, dtype, &tl);
+    const std::string src = spec_source(p, dtype, &tl, slot == kSlotCheb);
     if (src.empty()) {
         K.log = "plan does not qualify for the specialized kernel";
         return MRMF_E_UNSUPPORTED;
@@ -1184,14 +1219,14 @@ mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
     hipModule_t mod;
     if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return MRMF_E_HIP;
     hipFunction_t fn;
-    if (hipModuleGetFunction(&fn, mod, "mrmf_spec") != hipSuccess) {
+    if (hipModuleGetFunction(&fn, mod, slot == kSlotCheb ? "mrmf_spec_cheb" : "mrmf_spec") != hipSuccess) {
         hipModuleUnload(mod);
         return MRMF_E_HIP;
     }
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int bpc = p->cfg[dtype].blocks_per_cu;
+    const int bpc = p->cfg[slot == kSlotCheb && p->cheb_shape_set ? kSlotCheb : dtype].blocks_per_cu;
     if (bpc > 0 && bpc < per_cu) per_cu = bpc;
     int64_t grid = int64_t(per_cu) * prop.multiProcessorCount;
     if (grid > n_st) grid = n_st;
@@ -1214,7 +1249,7 @@ mrmf_status compile_spec(mrmf_plan_t* p, int dtype, SpecKernel& K) {
 }  // namespace
 
 mrmf_status spec_prepare(mrmf_plan_t* p, int dtype) {
-    if (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) return MRMF_E_INVALID_ARG;
+    if (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != kSlotCheb) return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mtx);
     SpecKernel& K = p->spec[dtype];
     int dev = 0;
@@ -1242,6 +1277,24 @@ mrmf_status spec_launch(mrmf_plan_t* p, int dtype, const void* theta, const void
     return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
 }
 
+mrmf_status spec_launch_cheb(mrmf_plan_t* p, const double* theta, const void* x, void* prev, void* acc, double ea,
+                             double eb, double eg, double ecr, double eci, hipStream_t s) {
+    mrmf_status st = spec_prepare(p, kSlotCheb);
+    if (st != MRMF_OK) return st;
+    const SpecKernel& K = p->spec[kSlotCheb];
+    struct {
+        const void* theta;
+        const void* x;
+        void* y;
+        void* acc;
+        double ea, eb, eg, ecr, eci;
+        const int32_t* skip;
+    } args{theta, x, prev, acc, ea, eb, eg, ecr, eci, nullptr};
+    size_t size = sizeof(args);
+    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
+    return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
+}
+
 }  // namespace mrmf
 
 mrmf_plan_t::~mrmf_plan_t() {
@@ -1255,18 +1308,24 @@ extern "C" {
 
 namespace {
 
-// Replace the kernel configuration of one element type; a changed configuration drops its kernel so the
-// next call regenerates it.  Caller holds the plan mutex.
-void set_cfg(mrmf_plan_t* plan, int dtype, const mrmf::KernelCfg& c) {
-    mrmf::KernelCfg& cur = plan->cfg[dtype];
+// Replace the kernel configuration of one element type (or of the Chebyshev-step kernel, slot
+// kSlotCheb); a changed configuration drops the kernels built from it so the next call regenerates them.
+// Caller holds the plan mutex.
+void set_cfg(mrmf_plan_t* plan, int slot, const mrmf::KernelCfg& c) {
+    mrmf::KernelCfg& cur = plan->cfg[slot];
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
                       cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
-                      cur.wide == c.wide;
+                      cur.wide == c.wide && (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
     cur = c;
+    if (slot == mrmf::kSlotCheb) plan->cheb_shape_set = true;
     if (!same) {
-        mrmf::SpecKernel& k = plan->spec[dtype];
-        if (k.mod) hipModuleUnload(k.mod);
-        k = mrmf::SpecKernel{};
+        const bool cheb_follows = slot == MRMF_DTYPE_Z && !plan->cheb_shape_set;
+        for (int s : {slot, cheb_follows ? mrmf::kSlotCheb : -1}) {
+            if (s < 0) continue;
+            mrmf::SpecKernel& k = plan->spec[s];
+            if (k.mod) hipModuleUnload(k.mod);
+            k = mrmf::SpecKernel{};
+        }
     }
 }
 
@@ -1320,6 +1379,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
                 c.wide = value;
                 break;
+            case MRMF_TUNE_CHEB_FUSED:
+                if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
+                c.cheb_fused = value;
+                break;
             default: return MRMF_E_INVALID_ARG;
         }
         set_cfg(plan, dt, c);
@@ -1329,7 +1392,7 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
 
 mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, int32_t inner_sites,
                                 int32_t unrolled_sites, int32_t load_group) {
-    if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) ||
+    if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
         (variant != MRMF_VARIANT_MASKED && variant != MRMF_VARIANT_LIST) || inner_sites < 0 ||
         inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N || load_group < 0 || load_group > 64)
         return MRMF_E_INVALID_ARG;
@@ -1340,6 +1403,8 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     c.unroll = unrolled_sites;
     c.variant = variant;
     c.group = load_group;
+    c.cheb_fused = plan->cfg[dtype].cheb_fused;
+    c.wide = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].wide;
     set_cfg(plan, dtype, c);
     return MRMF_OK;
 }
@@ -1356,8 +1421,10 @@ mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype) {
 mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
                                const void* d_x, void* d_y, mrmf_stream stream, int32_t* out) {
     using namespace mrmf;
-    if (!plan || !d_ws || !d_theta || !d_x || !d_y || !out || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C))
+    if (!plan || !d_ws || !d_theta || !d_x || !d_y || !out ||
+        (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB))
         return MRMF_E_INVALID_ARG;
+    const bool cheb = dtype == MRMF_SOURCE_CHEB;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     struct Cand {
         int variant, inner, unrolled, group;
@@ -1384,9 +1451,11 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     }
     if (cands.empty()) return MRMF_E_UNSUPPORTED;
     mrmf::KernelCfg cfg0;
+    bool cheb_set0 = false;
     {
         std::lock_guard<std::mutex> lk(plan->mtx);
         cfg0 = plan->cfg[dtype];
+        cheb_set0 = plan->cheb_shape_set;
     }
     auto apply = [&](const Cand& c, int32_t mode) {
         std::lock_guard<std::mutex> lk(plan->mtx);
@@ -1396,6 +1465,8 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         k.unroll = c.unrolled;
         k.variant = c.variant;
         k.group = c.group;
+        k.wide = plan->cfg[cheb ? MRMF_DTYPE_Z : dtype].wide;
+        k.cheb_fused = plan->cfg[dtype].cheb_fused;
         set_cfg(plan, dtype, k);
     };
     hipEvent_t e0, e1;
@@ -1405,6 +1476,9 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         return MRMF_E_HIP;
     }
     auto run = [&]() -> mrmf_status {
+        if (cheb)  // prev = H x, acc += 0: the memory traffic of one Chebyshev step
+            return spec_launch_cheb(plan, static_cast<const double*>(d_theta), d_x, d_y,
+                                    static_cast<char*>(d_y) + size_t(plan->D) * 16, 1.0, 0.0, 0.0, 0.0, 0.0, s);
         return dtype == MRMF_DTYPE_Z
                    ? matvec_z_impl(plan, d_ws, static_cast<const double*>(d_theta), d_x, d_y, s, nullptr)
                    : matvec_c_impl(plan, d_ws, static_cast<const float*>(d_theta), d_x, d_y, s, nullptr);
@@ -1437,6 +1511,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     if (st != MRMF_OK || best_i < 0) {
         std::lock_guard<std::mutex> lk(plan->mtx);
         set_cfg(plan, dtype, cfg0);
+        if (cheb) plan->cheb_shape_set = cheb_set0;
         return st != MRMF_OK ? st : MRMF_E_UNSUPPORTED;
     }
     const Cand& c = cands[best_i];
@@ -1451,10 +1526,12 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
 }
 
 mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len) {
-    if (!plan || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) || (cap > 0 && !buf))
+    if (!plan || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
+        (cap > 0 && !buf))
         return MRMF_E_INVALID_ARG;
     mrmf::Tile tl;
-    const std::string src = mrmf::spec_source(plan, dtype, &tl);
+    const bool cheb = dtype == MRMF_SOURCE_CHEB;
+    const std::string src = mrmf::spec_source(plan, cheb ? MRMF_DTYPE_Z : dtype, &tl, cheb);
     if (src.empty()) return MRMF_E_UNSUPPORTED;
     *len = src.size();
     if (cap > 0) {

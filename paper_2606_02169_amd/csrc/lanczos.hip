@@ -440,26 +440,33 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
 }
 
 mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes) {
-    if (!plan || !bytes || m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
+    if (!plan) return MRMF_E_INVALID_ARG;
+    return lanczos_scratch_bytes(plan->D, m, precision, bytes);
+}
+
+}  // extern "C"
+
+namespace mrmf {
+
+mrmf_status lanczos_scratch_bytes(int64_t D, int32_t m, int32_t precision, size_t* bytes) {
+    if (!bytes || m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
     if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
-    *bytes = lz_layout(plan->D, m, precision).total;
+    *bytes = lz_layout(D, m, precision).total;
     return MRMF_OK;
 }
 
-mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z, const float* d_theta_c,
-                         int32_t precision, int32_t m, int32_t reorth, const void* d_v0, void* d_V,
-                         double* d_alpha, double* d_beta, double* d_result, void* d_u, void* d_scratch,
-                         size_t scratch_bytes, mrmf_stream stream) {
-    if (!plan || !d_ws || !d_theta_z || !d_v0 || !d_V || !d_alpha || !d_beta || !d_result || !d_u ||
-        !d_scratch)
-        return MRMF_E_INVALID_ARG;
+// The recurrence for any map of dimension D: mv_z applies it to a c128 vector, mv_c (C_IN_Z form) to a
+// c64 one; both enqueue on the stream and honour the `stopped` flag.
+mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, int32_t precision, int32_t m,
+                        int32_t reorth, const void* d_v0, void* d_V, double* d_alpha, double* d_beta,
+                        double* d_result, void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
+    if (!d_v0 || !d_V || !d_alpha || !d_beta || !d_result || !d_u || !d_scratch) return MRMF_E_INVALID_ARG;
     if (m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
     if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
-    if (precision == MRMF_PREC_C_IN_Z && !d_theta_c) return MRMF_E_INVALID_ARG;
+    if (precision == MRMF_PREC_C_IN_Z && !mv_c) return MRMF_E_INVALID_ARG;
     if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE) return MRMF_E_INVALID_ARG;
     if (!aligned(d_scratch, 256) || !aligned(d_V, 16) || !aligned(d_u, 16) || !aligned(d_v0, 16))
         return MRMF_E_INVALID_ARG;
-    const int64_t D = plan->D;
     const LzLayout Lo = lz_layout(D, m, precision);
     if (scratch_bytes < Lo.total) return MRMF_E_WORKSPACE;
     const size_t vb = sizeof(double2) * size_t(D);
@@ -497,11 +504,11 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
     for (int j = 0; j < m; ++j) {
         double2* w = row(j + 1);
         if (c32) {
-            rc = matvec_c_impl(plan, d_ws, d_theta_c, x32, y32, s, stopped);
+            rc = mv_c(x32, y32, s, stopped);
             if (rc != MRMF_OK) return rc;
             hipLaunchKernelGGL(k_upcast, dim3(g), dim3(kRB), 0, s, D, y32, w, stopped);
         } else {
-            rc = matvec_z_impl(plan, d_ws, d_theta_z, row(j), w, s, stopped);
+            rc = mv_z(row(j), w, s, stopped);
             if (rc != MRMF_OK) return rc;
         }
         hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kRB), 0, s, D, row(j), w, part_z, stopped);
@@ -533,11 +540,31 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
     hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, m, &st->steps, svec, u, 1, 1.0, nullptr);
     rc = launch_status();
     if (rc != MRMF_OK) return rc;
-    rc = matvec_z_impl(plan, d_ws, d_theta_z, u, tmp, s, nullptr);
+    rc = mv_z(u, tmp, s, nullptr);
     if (rc != MRMF_OK) return rc;
     hipLaunchKernelGGL(k_resid_partial, dim3(nb), dim3(kRB), 0, s, D, tmp, u, st, part_d);
     hipLaunchKernelGGL(k_resid_finalize, dim3(1), dim3(1), 0, s, part_d, nb, st, d_result);
     return launch_status();
+}
+
+}  // namespace mrmf
+
+extern "C" {
+
+mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z, const float* d_theta_c,
+                         int32_t precision, int32_t m, int32_t reorth, const void* d_v0, void* d_V,
+                         double* d_alpha, double* d_beta, double* d_result, void* d_u, void* d_scratch,
+                         size_t scratch_bytes, mrmf_stream stream) {
+    if (!plan || !d_ws || !d_theta_z) return MRMF_E_INVALID_ARG;
+    if (precision == MRMF_PREC_C_IN_Z && !d_theta_c) return MRMF_E_INVALID_ARG;
+    const MatvecOp mv_z = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
+        return matvec_z_impl(plan, d_ws, d_theta_z, x, y, s, stop);
+    };
+    const MatvecOp mv_c = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
+        return matvec_c_impl(plan, d_ws, d_theta_c, x, y, s, stop);
+    };
+    return lanczos_run(plan->D, mv_z, mv_c, precision, m, reorth, d_v0, d_V, d_alpha, d_beta, d_result, d_u,
+                       d_scratch, scratch_bytes, stream);
 }
 
 }  // extern "C"

@@ -11,17 +11,6 @@
 
 namespace mrmf {
 
-template <typename R>
-struct Cx;
-template <>
-struct Cx<double> {
-    using T = double2;
-};
-template <>
-struct Cx<float> {
-    using T = float2;
-};
-
 // floor(n / d) for n < 2^32 with magic = ceil(2^64 / d)
 __device__ __forceinline__ uint32_t div_magic(uint32_t n, uint64_t magic) {
     return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -13,6 +14,18 @@
 namespace mrmf {
 
 constexpr int kMaxSites = 64;
+
+// complex element type of a real type
+template <typename R>
+struct Cx;
+template <>
+struct Cx<double> {
+    using T = double2;
+};
+template <>
+struct Cx<float> {
+    using T = float2;
+};
 constexpr int kMaxDim = 256;  // largest local dimension d_i
 
 // Off-diagonal channel (a term with at least one ladder operator).  The source digit of site a is
@@ -77,7 +90,11 @@ struct KernelCfg {
     int32_t unroll = -1;  // unrolled sites, -1 = library's choice
     int32_t sched = MRMF_SCHED_WINDOWS, bskip = 0, group = 0, blocks_per_cu = 0, variant = MRMF_VARIANT_MASKED;
     int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
+    int32_t cheb_fused = 1;  // time propagation: fused Chebyshev-step kernel (c128 configuration only)
 };
+
+// Slot of the c128 kernel with the Chebyshev-step epilogue in mrmf_plan_t::spec (after the dtypes).
+constexpr int kSlotCheb = 2;
 
 // A kernel generated and compiled for one plan and element type (see jit.cpp).
 struct SpecKernel {
@@ -113,8 +130,9 @@ struct mrmf_plan_t {
     mrmf::Tiling tiling;
     // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type
     // kernel selection and shape, per element type (MRMF_DTYPE_Z, MRMF_DTYPE_C)
-    mrmf::KernelCfg cfg[2];
-    mrmf::SpecKernel spec[2];
+    mrmf::KernelCfg cfg[3];       // [kSlotCheb]: shape of the Chebyshev-step kernel once set explicitly
+    bool cheb_shape_set = false;  // else that kernel takes the c128 configuration
+    mrmf::SpecKernel spec[3];  // c128, c64, c128 with the Chebyshev-step epilogue
     std::mutex mtx;
     ~mrmf_plan_t();
 };
@@ -163,8 +181,20 @@ mrmf_status matvec_z_impl(mrmf_plan_t* p, const void* d_ws, const double* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
 mrmf_status matvec_c_impl(mrmf_plan_t* p, const void* d_ws, const float* theta,
                           const void* x, void* y, hipStream_t s, const int32_t* d_skip);
+// A map x -> y enqueued on a stream (device pointers; `stopped` non-null: skip when the device flag is set).
+using MatvecOp = std::function<mrmf_status(const void* x, void* y, hipStream_t s, const int32_t* stopped)>;
+// Lanczos (the recurrence of mrmf_lanczos) for any map of dimension D; mv_c may be empty for MRMF_PREC_Z.
+mrmf_status lanczos_scratch_bytes(int64_t D, int32_t m, int32_t precision, size_t* bytes);
+mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, int32_t precision, int32_t m,
+                        int32_t reorth, const void* d_v0, void* d_V, double* d_alpha, double* d_beta,
+                        double* d_result, void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
 // Generated source of the specialized kernel (no device needed); "" when the plan does not qualify.
-std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl);
+std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl, bool epi = false);
+// Fused Chebyshev step (time propagation) with the specialized c128 kernel:
+// p = ea (H x) + eb x + eg prev;  prev = p;  acc += (ecr + i eci) p.  MRMF_E_UNSUPPORTED when the plan
+// has no specialized kernel.
+mrmf_status spec_launch_cheb(mrmf_plan_t* p, const double* theta, const void* x, void* prev, void* acc, double ea,
+                             double eb, double eg, double ecr, double eci, hipStream_t s);
 // <n|O|n - q> of site's operator op at target digit n; 0 where the source digit is out of range
 double local_factor_host(const mrmf_plan_t* p, int site, int op, int n);
 

@@ -4,9 +4,11 @@
 // Each step of length dt applies the Chebyshev expansion of the exponential (Jacobi-Anger):
 //     exp(-i H dt) = exp(-i b dt) sum_k (2 - delta_k0) (-i)^k J_k(a dt) T_k(Ht),   Ht = (H - b) / a,
 // where [b - a, b + a] contains the spectrum of H (caller's bounds; mrmf_plan_norm_bound gives a safe
-// symmetric one).  T_k(Ht) v follows the three-term recurrence phi_k = 2 Ht phi_{k-1} - phi_{k-2}, one
-// matvec and one fused vector update per term; the series is cut where the remaining Bessel weights sum
-// below the tolerance (|T_k(Ht)| <= 1 on the spectrum).  A piecewise-constant drive supplies one
+// symmetric one).  T_k(Ht) v follows the three-term recurrence phi_k = 2 Ht phi_{k-1} - phi_{k-2}: one
+// launch of the plan's specialized kernel with a Chebyshev-step epilogue per term (it reads the row's
+// phi_{k-2} and accumulator and writes phi_k and the accumulator, so H phi never goes to memory), or, for
+// plans on the generic kernel, a matvec and a fused vector update; the series is cut where the remaining
+// Bessel weights sum below the tolerance (|T_k(Ht)| <= 1 on the spectrum).  A piecewise-constant drive supplies one
 // parameter vector per step (theta + s * theta_stride): the plan and its kernels are reused as they are.
 #include <cmath>
 #include <vector>
@@ -23,12 +25,14 @@ int prop_grid(int64_t n) {
     return static_cast<int>(b < 16384 ? (b < 1 ? 1 : b) : 16384);
 }
 
-// acc = c0 * state, cur = state (state may be acc itself: each element is read before it is written)
-__global__ __launch_bounds__(kPB) void k_cheb_init(int64_t n, const double2* state, double2* cur, double2* acc,
-                                                   double c0r, double c0i) {
+// acc = c0 * state, cur = state, prev = 0 (state may be acc itself: each element is read before it is
+// written; prev starts at zero because the fused first step reads it with weight 0)
+__global__ __launch_bounds__(kPB) void k_cheb_init(int64_t n, const double2* state, double2* cur, double2* prev,
+                                                   double2* acc, double c0r, double c0i) {
     for (int64_t i = int64_t(blockIdx.x) * kPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kPB) {
         const double2 v = state[i];
         cur[i] = v;
+        prev[i] = make_double2(0.0, 0.0);
         acc[i] = make_double2(c0r * v.x - c0i * v.y, c0r * v.y + c0i * v.x);
     }
 }
@@ -184,23 +188,32 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
     double2* x = static_cast<double2*>(d_x);
     const int64_t n = plan->D;
     const int grid = prop_grid(n);
+    // the specialized kernel with the Chebyshev-step epilogue does matvec and update in one pass (no
+    // H phi vector written and read back); plans without a specialized kernel take the two-pass form
+    const bool fused = n_steps > 0 && nt > 1 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC &&
+                       plan->cfg[MRMF_DTYPE_Z].cheb_fused != 0 && spec_prepare(plan, kSlotCheb) == MRMF_OK;
     for (int st = 0; st < n_steps; ++st) {
         const double* th = plan->n_params > 0 ? d_theta + int64_t(st) * theta_stride : nullptr;
         const double2* state = st == 0 ? static_cast<const double2*>(d_x0) : x;
         double2* cur = v0;
         double2* prev = v1;
-        hipLaunchKernelGGL(k_cheb_init, dim3(grid), dim3(kPB), 0, s, n, state, cur, x, cr[0], ci[0]);
+        hipLaunchKernelGGL(k_cheb_init, dim3(grid), dim3(kPB), 0, s, n, state, cur, prev, x, cr[0], ci[0]);
         mrmf_status rc = launch_status();
         if (rc != MRMF_OK) return rc;
         for (int k = 1; k < nt; ++k) {
-            rc = matvec_z_impl(plan, d_ws, th, cur, hv, s, nullptr);
-            if (rc != MRMF_OK) return rc;
             const bool first = k == 1;
-            hipLaunchKernelGGL(k_cheb_update, dim3(grid), dim3(kPB), 0, s, n, hv, cur, prev, x,
-                               (first ? 1.0 : 2.0) / a, -(first ? 1.0 : 2.0) * b / a, -1.0, first ? 0 : 1, cr[k],
-                               ci[k]);
-            rc = launch_status();
-            if (rc != MRMF_OK) return rc;
+            const double ea = (first ? 1.0 : 2.0) / a, eb = -(first ? 1.0 : 2.0) * b / a, eg = first ? 0.0 : -1.0;
+            if (fused) {
+                rc = spec_launch_cheb(plan, th, cur, prev, x, ea, eb, eg, cr[k], ci[k], s);
+                if (rc != MRMF_OK) return rc;
+            } else {
+                rc = matvec_z_impl(plan, d_ws, th, cur, hv, s, nullptr);
+                if (rc != MRMF_OK) return rc;
+                hipLaunchKernelGGL(k_cheb_update, dim3(grid), dim3(kPB), 0, s, n, hv, cur, prev, x, ea, eb, eg,
+                                   first ? 0 : 1, cr[k], ci[k]);
+                rc = launch_status();
+                if (rc != MRMF_OK) return rc;
+            }
             double2* t = cur;
             cur = prev;
             prev = t;

@@ -1,0 +1,386 @@
+// Restricted basis of a globally constrained sector (Sec. VI, case 2): every product state whose local
+// digits sum to Q (fixed total magnetization for spins, fixed excitation number with bosons), stored
+// packed in ascending full-basis order.  The lookup is a combinatorial ranking (the Lehmer-code-style
+// option of Sec. VI.B) instead of a search or a hash: with C_k(q) the number of digit tuples of sites
+// k..N-1 summing to q and R_k(q, v) = sum_{v' < v} C_{k+1}(q - v'),
+//     rank(n_0 .. n_{N-1}) = sum_k R_k(Q_k, n_k),     Q_0 = Q,  Q_{k+1} = Q_k - n_k,
+// and unranking walks the same tables site by site.  A target row is unranked once; the source of a
+// channel on sites i < j differs from the target only in n_i, n_j and in the remaining sums Q_k for
+// i < k <= j, so its rank is the target's plus the change of those j - i + 1 table terms: no search and
+// no table of labels in memory.  A channel that changes the digit sum has no source in the sector (the
+// failed membership test of Sec. VI.B) and is dropped when the sector is built; one-site ladder channels
+// are such channels.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "mrmf_internal.h"
+
+struct mrmf_sector_t {
+    int32_t N = 0, Q = 0;
+    int64_t Dr = 0;
+    int32_t n_params = 0;
+    bool hermitian = false;
+    std::vector<int32_t> d;
+    std::vector<int64_t> M;
+    std::vector<mrmf::DevChan> chans;  // digit-sum preserving channels
+    std::vector<mrmf::DevDiag> diags;
+    std::vector<unsigned char> image;  // device image: sites, channels, diagonal terms, tables, rank tables
+    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_rt = 0, off_rto = 0;
+    size_t ws_bytes = 0;
+};
+
+namespace mrmf {
+namespace {
+
+constexpr int kSB = 256;
+
+struct SectorArgs {
+    PlanArgs p;              // chan: the sector's channels
+    const int64_t* rt;       // rank tables: site k at rt + rto[k], entry (q, v) at q * (d_k + 1) + v
+    const int64_t* rto;      // per-site offsets into rt
+    int64_t Dr;
+    int32_t Q, pad;
+};
+
+SectorArgs sector_args(const mrmf_sector_t* S, const void* d_ws) {
+    const unsigned char* b = static_cast<const unsigned char*>(d_ws);
+    SectorArgs a;
+    a.p.site = reinterpret_cast<const DevSite*>(b + S->off_site);
+    a.p.chan = reinterpret_cast<const DevChan*>(b + S->off_chan);
+    a.p.diag = reinterpret_cast<const DevDiag*>(b + S->off_diag);
+    a.p.val = reinterpret_cast<const double*>(b + S->off_val);
+    a.p.up = reinterpret_cast<const double*>(b + S->off_up);
+    a.p.D = S->Dr;
+    a.p.N = S->N;
+    a.p.n_chan = static_cast<int32_t>(S->chans.size());
+    a.p.n_diag = static_cast<int32_t>(S->diags.size());
+    a.p.n_params = S->n_params;
+    a.rt = reinterpret_cast<const int64_t*>(b + S->off_rt);
+    a.rto = reinterpret_cast<const int64_t*>(b + S->off_rto);
+    a.Dr = S->Dr;
+    a.Q = S->Q;
+    a.pad = 0;
+    return a;
+}
+
+// <n|O|n - q> of a local operator at target digit n (admissible n assumed)
+template <typename R>
+__device__ __forceinline__ R sfactor(const PlanArgs& p, int op, int tab, int n) {
+    switch (op) {
+        case MRMF_OP_Z: return static_cast<R>(p.val[tab + n]);
+        case MRMF_OP_Z2: return static_cast<R>(p.val[tab + n] * p.val[tab + n]);
+        case MRMF_OP_RAISE: return static_cast<R>(p.up[tab + n]);
+        case MRMF_OP_LOWER: return static_cast<R>(p.up[tab + n + 1]);
+        case MRMF_OP_RAISE2: return static_cast<R>(p.up[tab + n] * p.up[tab + n - 1]);
+        default: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
+    }
+}
+
+__device__ __forceinline__ int64_t rtab(const SectorArgs& a, int k, int q, int v) {
+    return a.rt[a.rto[k] + int64_t(q) * (a.p.site[k].d + 1) + v];
+}
+
+// Digits and remaining sums of packed row r (rem[k] = Q_k).
+__device__ __forceinline__ void unrank(const SectorArgs& a, int64_t r, uint8_t (*dig)[kSB], uint16_t (*rem)[kSB],
+                                       int tid) {
+    int q = a.Q;
+    int64_t left = r;
+    for (int k = 0; k < a.p.N; ++k) {
+        const int d = a.p.site[k].d;
+        const int vmax = q < d - 1 ? q : d - 1;
+        const int64_t* R = a.rt + a.rto[k] + int64_t(q) * (d + 1);
+        int v = 0;
+        while (v < vmax && R[v + 1] <= left) ++v;
+        dig[k][tid] = static_cast<uint8_t>(v);
+        rem[k][tid] = static_cast<uint16_t>(q);
+        left -= R[v];
+        q -= v;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSB) void k_sector_matvec(SectorArgs a, const R* __restrict__ theta,
+                                                       const typename Cx<R>::T* __restrict__ x,
+                                                       typename Cx<R>::T* __restrict__ y,
+                                                       const int32_t* __restrict__ skip) {
+    using C = typename Cx<R>::T;
+    if (skip != nullptr && *skip != 0) return;
+    __shared__ uint8_t dig[kMaxSites][kSB];
+    __shared__ uint16_t rem[kMaxSites][kSB];
+    const int tid = threadIdx.x;
+    const PlanArgs& p = a.p;
+    for (int64_t r = int64_t(blockIdx.x) * kSB + tid; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
+        unrank(a, r, dig, rem, tid);
+        R dr = 0, di = 0;
+        for (int k = 0; k < p.n_diag; ++k) {
+            const DevDiag g = p.diag[k];
+            R f = sfactor<R>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+            if (g.b >= 0) f *= sfactor<R>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+            const R th = theta[g.param];
+            dr += th * static_cast<R>(g.wr) * f;
+            di += th * static_cast<R>(g.wi) * f;
+        }
+        const C xf = x[r];
+        R ar = dr * xf.x - di * xf.y;
+        R ai = dr * xf.y + di * xf.x;
+        for (int c = 0; c < p.n_chan; ++c) {
+            const DevChan ch = p.chan[c];
+            const int na = dig[ch.a][tid], nb = dig[ch.b][tid];
+            const int sa = na - ch.qa, sb = nb - ch.qb;
+            if (sa < 0 || sa >= p.site[ch.a].d || sb < 0 || sb >= p.site[ch.b].d) continue;
+            // source rank: the terms of sites i..j change (i < j the two sites)
+            const bool a_first = ch.a < ch.b;
+            const int i = a_first ? ch.a : ch.b, j = a_first ? ch.b : ch.a;
+            const int ni = a_first ? na : nb, nsi = a_first ? sa : sb;
+            const int nj = a_first ? nb : na, nsj = a_first ? sb : sa;
+            const int dq = nsi - ni;  // the remaining sums after site i drop by dq
+            const int qi = rem[i][tid];
+            int64_t drank = rtab(a, i, qi, nsi) - rtab(a, i, qi, ni);
+            for (int k = i + 1; k < j; ++k) {
+                const int qk = rem[k][tid], nk = dig[k][tid];
+                drank += rtab(a, k, qk - dq, nk) - rtab(a, k, qk, nk);
+            }
+            const int qj = rem[j][tid];
+            drank += rtab(a, j, qj - dq, nsj) - rtab(a, j, qj, nj);
+            const R f = sfactor<R>(p, ch.opa, p.site[ch.a].tab, na) * sfactor<R>(p, ch.opb, p.site[ch.b].tab, nb);
+            const R th = theta[ch.param] * f;
+            const R cr = th * static_cast<R>(ch.wr), ci = th * static_cast<R>(ch.wi);
+            const C xs = x[r + drank];
+            ar += cr * xs.x - ci * xs.y;
+            ai += cr * xs.y + ci * xs.x;
+        }
+        C out;
+        out.x = ar;
+        out.y = ai;
+        y[r] = out;
+    }
+}
+
+// Full-basis index F = sum_k n_k M_k of packed rows r0 .. r0 + count - 1.
+__global__ __launch_bounds__(kSB) void k_sector_labels(SectorArgs a, const int64_t* __restrict__ M, int64_t r0,
+                                                       int64_t count, int64_t* __restrict__ out) {
+    __shared__ uint8_t dig[kMaxSites][kSB];
+    __shared__ uint16_t rem[kMaxSites][kSB];
+    const int tid = threadIdx.x;
+    for (int64_t i = int64_t(blockIdx.x) * kSB + tid; i < count; i += int64_t(gridDim.x) * kSB) {
+        unrank(a, r0 + i, dig, rem, tid);
+        int64_t F = 0;
+        for (int k = 0; k < a.p.N; ++k) F += int64_t(dig[k][tid]) * M[k];
+        out[i] = F;
+    }
+}
+
+// Packed row of each full-basis index, or -1 when it is not a sector state (membership test).
+__global__ __launch_bounds__(kSB) void k_sector_lookup(SectorArgs a, int64_t D, const int64_t* __restrict__ F,
+                                                       int64_t count, int64_t* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * kSB + threadIdx.x; i < count; i += int64_t(gridDim.x) * kSB) {
+        int64_t f = F[i];
+        if (f < 0 || f >= D) {
+            out[i] = -1;
+            continue;
+        }
+        // decode (least significant site first), then rank from site 0 with the remaining sums
+        uint8_t n[kMaxSites];
+        for (int k = a.p.N - 1; k >= 0; --k) {
+            const int64_t d = a.p.site[k].d;
+            const int64_t qq = f / d;
+            n[k] = static_cast<uint8_t>(f - qq * d);
+            f = qq;
+        }
+        int q = a.Q;
+        int64_t rank = 0;
+        bool ok = true;
+        for (int k = 0; k < a.p.N; ++k) {
+            if (n[k] > q) {
+                ok = false;
+                break;
+            }
+            rank += rtab(a, k, q, n[k]);
+            q -= n[k];
+        }
+        out[i] = (ok && q == 0) ? rank : -1;
+    }
+}
+
+int sector_grid(int64_t n) {
+    const int64_t b = (n + kSB - 1) / kSB;
+    return static_cast<int>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
+}
+
+template <typename R>
+mrmf_status sector_matvec(const mrmf_sector_t* S, const void* d_ws, const R* theta, const void* x, void* y,
+                          hipStream_t s, const int32_t* skip) {
+    using C = typename Cx<R>::T;
+    hipLaunchKernelGGL(k_sector_matvec<R>, dim3(sector_grid(S->Dr)), dim3(kSB), 0, s, sector_args(S, d_ws), theta,
+                       static_cast<const C*>(x), static_cast<C*>(y), skip);
+    return launch_status();
+}
+
+mrmf_status check_matvec_args(const mrmf_sector_t* S, const void* d_ws, const void* theta, const void* x, void* y,
+                              size_t elem) {
+    if (!S || !d_ws || !x || !y || (S->n_params > 0 && !theta)) return MRMF_E_INVALID_ARG;
+    if (!aligned(d_ws, 256) || !aligned(x, elem) || !aligned(y, elem)) return MRMF_E_INVALID_ARG;
+    const size_t vb = size_t(S->Dr) * elem;
+    if (ranges_overlap(x, vb, y, vb)) return MRMF_E_INVALID_ARG;
+    return MRMF_OK;
+}
+
+}  // namespace
+}  // namespace mrmf
+
+using namespace mrmf;
+
+extern "C" {
+
+mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* out) {
+    if (!plan || !out) return MRMF_E_INVALID_ARG;
+    *out = nullptr;
+    int qmax = 0;
+    for (int k = 0; k < plan->N; ++k) qmax += plan->d[k] - 1;
+    if (digit_sum < 0 || digit_sum > qmax || qmax > 65535) return MRMF_E_INVALID_ARG;
+    auto* S = new mrmf_sector_t;
+    S->N = plan->N;
+    S->Q = digit_sum;
+    S->n_params = plan->n_params;
+    S->hermitian = plan->hermitian;
+    S->d = plan->d;
+    S->M = plan->M;
+    const int N = plan->N, Q = digit_sum;
+    // C_k(q) for q = 0..Q (C_N(0) = 1), then R_k(q, v) = sum_{v' < v} C_{k+1}(q - v'), v = 0..d_k
+    std::vector<std::vector<int64_t>> cnt(N + 1, std::vector<int64_t>(Q + 1, 0));
+    cnt[N][0] = 1;
+    for (int k = N - 1; k >= 0; --k)
+        for (int q = 0; q <= Q; ++q) {
+            int64_t c = 0;
+            for (int v = 0; v < plan->d[k] && v <= q; ++v) c += cnt[k + 1][q - v];
+            cnt[k][q] = c;
+        }
+    S->Dr = cnt[0][Q];
+    std::vector<int64_t> rt, rto(N);
+    for (int k = 0; k < N; ++k) {
+        rto[k] = static_cast<int64_t>(rt.size());
+        const int d = plan->d[k];
+        for (int q = 0; q <= Q; ++q) {
+            int64_t acc = 0;
+            for (int v = 0; v <= d; ++v) {
+                rt.push_back(acc);
+                if (v < d && v <= q) acc += cnt[k + 1][q - v];
+            }
+        }
+    }
+    for (const auto& c : plan->chans)
+        if (c.b >= 0 && c.qa + c.qb == 0) S->chans.push_back(c);
+    S->diags = plan->diags;
+    // device image
+    size_t off = 0;
+    auto section = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    S->off_site = section(sizeof(DevSite) * N);
+    S->off_chan = section(sizeof(DevChan) * std::max<size_t>(1, S->chans.size()));
+    S->off_diag = section(sizeof(DevDiag) * std::max<size_t>(1, S->diags.size()));
+    S->off_val = section(sizeof(double) * plan->val.size());
+    S->off_up = section(sizeof(double) * plan->up.size());
+    S->off_rt = section(sizeof(int64_t) * rt.size());
+    S->off_rto = section(sizeof(int64_t) * N);
+    S->ws_bytes = off;
+    S->image.assign(off, 0);
+    std::memcpy(S->image.data() + S->off_site, plan->image.data() + plan->off_site, sizeof(DevSite) * N);
+    if (!S->chans.empty()) std::memcpy(S->image.data() + S->off_chan, S->chans.data(), sizeof(DevChan) * S->chans.size());
+    if (!S->diags.empty()) std::memcpy(S->image.data() + S->off_diag, S->diags.data(), sizeof(DevDiag) * S->diags.size());
+    std::memcpy(S->image.data() + S->off_val, plan->val.data(), sizeof(double) * plan->val.size());
+    std::memcpy(S->image.data() + S->off_up, plan->up.data(), sizeof(double) * plan->up.size());
+    std::memcpy(S->image.data() + S->off_rt, rt.data(), sizeof(int64_t) * rt.size());
+    std::memcpy(S->image.data() + S->off_rto, rto.data(), sizeof(int64_t) * N);
+    *out = S;
+    return MRMF_OK;
+}
+
+void mrmf_sector_destroy(mrmf_sector sector) { delete sector; }
+
+mrmf_status mrmf_sector_dim(mrmf_sector sector, int64_t* dim) {
+    if (!sector || !dim) return MRMF_E_INVALID_ARG;
+    *dim = sector->Dr;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_sector_workspace_bytes(mrmf_sector sector, size_t* bytes) {
+    if (!sector || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = sector->ws_bytes;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_sector_upload(mrmf_sector sector, void* d_ws, size_t ws_bytes, mrmf_stream stream) {
+    if (!sector || !d_ws || !aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
+    if (ws_bytes < sector->ws_bytes) return MRMF_E_WORKSPACE;
+    return hip_status(hipMemcpyAsync(d_ws, sector->image.data(), sector->ws_bytes, hipMemcpyHostToDevice,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+mrmf_status mrmf_sector_matvec_z(mrmf_sector sector, const void* d_ws, const double* d_theta, const void* d_x,
+                                 void* d_y, mrmf_stream stream) {
+    const mrmf_status st = check_matvec_args(sector, d_ws, d_theta, d_x, d_y, 16);
+    if (st != MRMF_OK) return st;
+    return sector_matvec<double>(sector, d_ws, d_theta, d_x, d_y, static_cast<hipStream_t>(stream), nullptr);
+}
+
+mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const float* d_theta, const void* d_x,
+                                 void* d_y, mrmf_stream stream) {
+    const mrmf_status st = check_matvec_args(sector, d_ws, d_theta, d_x, d_y, 8);
+    if (st != MRMF_OK) return st;
+    return sector_matvec<float>(sector, d_ws, d_theta, d_x, d_y, static_cast<hipStream_t>(stream), nullptr);
+}
+
+mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0, int64_t count, int64_t* d_out,
+                               void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
+    if (!sector || !d_ws || !d_out || !d_scratch || r0 < 0 || count < 0 || r0 + count > sector->Dr ||
+        !aligned(d_out, 8) || !aligned(d_scratch, 8))
+        return MRMF_E_INVALID_ARG;
+    if (scratch_bytes < sizeof(int64_t) * size_t(sector->N)) return MRMF_E_WORKSPACE;
+    if (count == 0) return MRMF_OK;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const mrmf_status st = hip_status(hipMemcpyAsync(d_scratch, sector->M.data(), sizeof(int64_t) * sector->N,
+                                                     hipMemcpyHostToDevice, s));
+    if (st != MRMF_OK) return st;
+    hipLaunchKernelGGL(k_sector_labels, dim3(sector_grid(count)), dim3(kSB), 0, s, sector_args(sector, d_ws),
+                       static_cast<const int64_t*>(d_scratch), r0, count, d_out);
+    return launch_status();
+}
+
+mrmf_status mrmf_sector_lookup(mrmf_sector sector, const void* d_ws, const int64_t* d_F, int64_t count,
+                               int64_t* d_out, mrmf_stream stream) {
+    if (!sector || !d_ws || !d_F || !d_out || count < 0 || !aligned(d_F, 8) || !aligned(d_out, 8))
+        return MRMF_E_INVALID_ARG;
+    if (count == 0) return MRMF_OK;
+    int64_t D = 1;
+    for (int k = 0; k < sector->N; ++k) D *= sector->d[k];
+    hipLaunchKernelGGL(k_sector_lookup, dim3(sector_grid(count)), dim3(kSB), 0, static_cast<hipStream_t>(stream),
+                       sector_args(sector, d_ws), D, d_F, count, d_out);
+    return launch_status();
+}
+
+mrmf_status mrmf_sector_lanczos_scratch_bytes(mrmf_sector sector, int32_t m, int32_t precision, size_t* bytes) {
+    if (!sector) return MRMF_E_INVALID_ARG;
+    return lanczos_scratch_bytes(sector->Dr, m, precision, bytes);
+}
+
+mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const double* d_theta_z,
+                                const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
+                                const void* d_v0, void* d_V, double* d_alpha, double* d_beta, double* d_result,
+                                void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
+    if (!sector || !d_ws || (sector->n_params > 0 && !d_theta_z) || !aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
+    if (precision == MRMF_PREC_C_IN_Z && sector->n_params > 0 && !d_theta_c) return MRMF_E_INVALID_ARG;
+    const MatvecOp mv_z = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
+        return sector_matvec<double>(sector, d_ws, d_theta_z, x, y, s, stop);
+    };
+    const MatvecOp mv_c = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
+        return sector_matvec<float>(sector, d_ws, d_theta_c, x, y, s, stop);
+    };
+    return lanczos_run(sector->Dr, mv_z, mv_c, precision, m, reorth, d_v0, d_V, d_alpha, d_beta, d_result, d_u,
+                       d_scratch, scratch_bytes, stream);
+}
+
+}  // extern "C"

@@ -202,32 +202,8 @@ class Plan:
         """Lowest eigenpair by device-resident Lanczos (mrmf_lanczos).  precision "z" (c128 matvec) or
         "c_in_z" (c64 matvec inside the FP64 recurrence).  Returns device tensors alpha, beta, the Ritz
         vector u and result = [theta, residual estimate, explicit residual, steps]."""
-        _need_gpu(theta, "theta", torch.float64)
-        _need_gpu(v0, "v0", torch.complex128)
-        if v0.numel() != self.D:
-            raise ValueError("v0 has the wrong length")
-        prec = {"z": L.MRMF_PREC_Z, "c_in_z": L.MRMF_PREC_C_IN_Z}[precision]
-        ro = {"cgs2": L.MRMF_REORTH_CGS2, "none": L.MRMF_REORTH_NONE}[reorth]
-        if prec == L.MRMF_PREC_C_IN_Z:
-            if theta_c is None:
-                theta_c = theta.to(torch.float32)
-            _need_gpu(theta_c, "theta_c", torch.float32)
-        dev = self.device
-        V = torch.empty((m + 1, self.D), dtype=torch.complex128, device=dev)
-        alpha = torch.zeros(m, dtype=torch.float64, device=dev)
-        beta = torch.zeros(m, dtype=torch.float64, device=dev)
-        result = torch.full((4,), float("nan"), dtype=torch.float64, device=dev)
-        u = torch.empty(self.D, dtype=torch.complex128, device=dev)
-        nb = ctypes.c_size_t()
-        L.call("mrmf_lanczos_scratch_bytes", self._handle, int(m), prec, ctypes.byref(nb))
-        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
-        L.call("mrmf_lanczos", self._handle, _ptr(self.ws), _ptr(theta),
-               _ptr(theta_c) if theta_c is not None else None, prec, int(m), ro, _ptr(v0), _ptr(V),
-               _ptr(alpha), _ptr(beta), _ptr(result), _ptr(u), _ptr(scratch), nb.value, _stream(dev))
-        out = dict(alpha=alpha, beta=beta, result=result, u=u, scratch=scratch)
-        if keep_basis:
-            out["V"] = V
-        return out
+        return _lanczos("mrmf_lanczos", self._handle, self.ws, self.D, self.device, theta, v0, m, precision,
+                        reorth, theta_c, keep_basis)
 
     # ------------------------------------------------------------------ kernel selection
     KERNELS = {"auto": 0, "generic": 1, "specialized": 2}
@@ -237,23 +213,34 @@ class Plan:
         "auto"; inner_sites = 0 / unrolled_sites = -1 let the library pick the tiling."""
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
-    TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5}
+    TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
+              "cheb_fused": 6}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
         branch_skip (0/1), load_group (channels issued ahead, 0 = default), blocks_per_cu (0 = as many as
         fit), variant (0 masked, 1 list), addressing (0 = 64-bit only where 32-bit offsets cannot reach,
-        1 = always 64-bit)."""
+        1 = always 64-bit), cheb_fused (1 = propagate with the fused Chebyshev-step kernel, 0 = matvec +
+        update)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 
     def autotune(self, theta: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
-                 use_cache: bool = True) -> dict:
+                 use_cache: bool = True, kernel: str = "matvec") -> dict:
         """Pick the specialized kernel's shape for this plan and element type (x.dtype): from the tuning
         cache when the structure was tuned before, else by timing every candidate on these buffers
-        (mrmf_plan_autotune) and recording the winner."""
+        (mrmf_plan_autotune) and recording the winner.  kernel="cheb" tunes the Chebyshev-step kernel of
+        propagate (c128; y then needs 2 D elements)."""
         from . import tuning
         dt = L.MRMF_DTYPE_Z if x.dtype == torch.complex128 else L.MRMF_DTYPE_C
+        if kernel == "cheb":
+            if x.dtype != torch.complex128:
+                raise ValueError("the Chebyshev-step kernel is c128")
+            dt = L.MRMF_SOURCE_CHEB
+            if y is None:
+                y = torch.empty(2 * self.D, dtype=torch.complex128, device=x.device)
+            if y.numel() < 2 * self.D:
+                raise ValueError("y must hold 2 D elements for the Chebyshev-step kernel")
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         key = tuning.signature(self._sites, self._terms, dt, arch)
         ent = tuning.lookup(key) if use_cache else None
@@ -265,7 +252,8 @@ class Plan:
             st = L.lib().mrmf_plan_autotune(self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
                                            _stream(self.device), out)
             if st == L.MRMF_E_UNSUPPORTED:   # no specialized shape fits this plan: keep the default
-                self.prepare(x.dtype)
+                if dt != L.MRMF_SOURCE_CHEB:
+                    self.prepare(x.dtype)
                 return dict(kind="default", key=key)
             L.check(st, "mrmf_plan_autotune")
             ent = dict(variant=out[0], inner_sites=out[1], unrolled_sites=out[2], load_group=out[3],
@@ -274,7 +262,8 @@ class Plan:
                 tuning.store(key, ent)
         L.call("mrmf_plan_set_shape", self._handle, dt, int(ent["variant"]), int(ent["inner_sites"]),
                int(ent["unrolled_sites"]), int(ent["load_group"]))
-        self.prepare(x.dtype)
+        if dt != L.MRMF_SOURCE_CHEB:
+            self.prepare(x.dtype)
         return dict(ent, key=key)
 
     def prepare(self, dtype=torch.complex128):
@@ -399,3 +388,106 @@ class Batch:
         """Launch shape: tiles of at most tile_rows_max rows ((64, 128, 256, 512) * 8 / nvec) and block
         threads (a multiple of 64, at most 512 and 4096 / nvec)."""
         L.call("mrmf_batch_set_shape", self._handle, int(tile_rows_max), int(block))
+
+
+def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, theta_c, keep_basis) -> dict:
+    """Shared marshalling of mrmf_lanczos / mrmf_sector_lanczos (same arguments, vectors of length D)."""
+    _need_gpu(theta, "theta", torch.float64)
+    _need_gpu(v0, "v0", torch.complex128)
+    if v0.numel() != D:
+        raise ValueError("v0 has the wrong length")
+    prec = {"z": L.MRMF_PREC_Z, "c_in_z": L.MRMF_PREC_C_IN_Z}[precision]
+    ro = {"cgs2": L.MRMF_REORTH_CGS2, "none": L.MRMF_REORTH_NONE}[reorth]
+    if prec == L.MRMF_PREC_C_IN_Z:
+        if theta_c is None:
+            theta_c = theta.to(torch.float32)
+        _need_gpu(theta_c, "theta_c", torch.float32)
+    V = torch.empty((m + 1, D), dtype=torch.complex128, device=dev)
+    alpha = torch.zeros(m, dtype=torch.float64, device=dev)
+    beta = torch.zeros(m, dtype=torch.float64, device=dev)
+    result = torch.full((4,), float("nan"), dtype=torch.float64, device=dev)
+    u = torch.empty(D, dtype=torch.complex128, device=dev)
+    nb = ctypes.c_size_t()
+    L.call(fn + "_scratch_bytes", handle, int(m), prec, ctypes.byref(nb))
+    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    L.call(fn, handle, _ptr(ws), _ptr(theta), _ptr(theta_c) if theta_c is not None else None, prec, int(m), ro,
+           _ptr(v0), _ptr(V), _ptr(alpha), _ptr(beta), _ptr(result), _ptr(u), _ptr(scratch), nb.value,
+           _stream(dev))
+    out = dict(alpha=alpha, beta=beta, result=result, u=u, scratch=scratch)
+    if keep_basis:
+        out["V"] = V
+    return out
+
+
+class Sector:
+    """Restricted basis of the states whose local digits sum to digit_sum (mrmf_sector_*): packed vectors
+    of length dim in ascending full-basis order, the matvec P H P^T, labels, lookup and Lanczos."""
+
+    def __init__(self, plan: Plan, digit_sum: int):
+        self.device = plan.device
+        self.n_params = plan.n_params
+        self.digit_sum = int(digit_sum)
+        self._handle = ctypes.c_void_p()
+        L.call("mrmf_sector_create", plan.handle, self.digit_sum, ctypes.byref(self._handle))
+        n = ctypes.c_int64()
+        L.call("mrmf_sector_dim", self._handle, ctypes.byref(n))
+        self.dim = int(n.value)
+        self.n_sites = len(plan._sites)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_sector_workspace_bytes", self._handle, ctypes.byref(nb))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        L.call("mrmf_sector_upload", self._handle, _ptr(self.ws), nb.value, _stream(self.device))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    @staticmethod
+    def digit_sum_of(sites, magnetization: float) -> int:
+        """Digit sum of the fixed-total-S_z sector M (spin sites only: n = m + s)."""
+        q = magnetization + sum(0.5 * (s.k if hasattr(s, "k") else s[1]) for s in sites)
+        if abs(q - round(q)) > 1e-9:
+            raise ValueError("M + sum s_i must be an integer")
+        return int(round(q))
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib().mrmf_sector_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    def matvec(self, theta: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = P H(theta) P^T x (c128 with float64 theta, or c64 with float32 theta)."""
+        f32 = x.dtype == torch.complex64
+        _need_gpu(x, "x", torch.complex64 if f32 else torch.complex128)
+        _need_gpu(theta, "theta", torch.float32 if f32 else torch.float64)
+        if x.numel() != self.dim:
+            raise ValueError("x has the wrong length")
+        y = torch.empty_like(x) if out is None else out
+        _need_gpu(y, "out", x.dtype)
+        L.call("mrmf_sector_matvec_c" if f32 else "mrmf_sector_matvec_z", self._handle, _ptr(self.ws), _ptr(theta),
+               _ptr(x), _ptr(y), _stream(self.device))
+        return y
+
+    def labels(self, r0: int = 0, count: int | None = None) -> torch.Tensor:
+        """Full-basis index of packed rows r0 .. r0 + count - 1 (int64 device tensor)."""
+        count = self.dim - r0 if count is None else int(count)
+        out = torch.empty(max(1, count), dtype=torch.int64, device=self.device)
+        scratch = torch.empty(max(1, self.n_sites), dtype=torch.int64, device=self.device)
+        L.call("mrmf_sector_labels", self._handle, _ptr(self.ws), int(r0), count, _ptr(out), _ptr(scratch),
+               scratch.numel() * 8, _stream(self.device))
+        return out[:count]
+
+    def lookup(self, F: torch.Tensor) -> torch.Tensor:
+        """Packed row of each full-basis index (int64 device tensor), -1 outside the sector."""
+        _need_gpu(F, "F", torch.int64)
+        out = torch.empty_like(F)
+        L.call("mrmf_sector_lookup", self._handle, _ptr(self.ws), _ptr(F), F.numel(), _ptr(out),
+               _stream(self.device))
+        return out
+
+    def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",
+                reorth: str = "cgs2", theta_c: torch.Tensor | None = None, keep_basis: bool = False) -> dict:
+        """Lowest eigenpair in the sector (mrmf_sector_lanczos); the results of Plan.lanczos."""
+        return _lanczos("mrmf_sector_lanczos", self._handle, self.ws, self.dim, self.device, theta, v0, m,
+                        precision, reorth, theta_c, keep_basis)

@@ -47,7 +47,10 @@ void emu_check(const void* p, size_t n, const char* what) {
     std::abort();
 }
 
-extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip);
+// A generated source defines one of the two kernels: the plain matvec or the Chebyshev-step form.
+extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
+extern "C" void mrmf_spec_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
+                               double ecr, double eci, const int* skip) __attribute__((weak));
 
 namespace {
 struct Arg {
@@ -55,6 +58,12 @@ struct Arg {
     const void *theta, *x;
     void* y;
 };
+// Chebyshev-step launch: accumulator and epilogue scalars (cheb = false: the plain matvec)
+struct ChebCall {
+    bool cheb = false;
+    void* acc = nullptr;
+    double ea = 0, eb = 0, eg = 0, ecr = 0, eci = 0;
+} g_cheb;
 // One host thread per GPU thread of the block, kept for every block of the range; a block barrier
 // separates consecutive blocks (their __shared__ storage is the same static storage).
 void* thread_main(void* a) {
@@ -62,7 +71,11 @@ void* thread_main(void* a) {
     threadIdx = emu_dim3{g->tid, 0, 0};
     for (unsigned b = g->b0; b < g->b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
-        mrmf_spec(g->theta, g->x, g->y, nullptr);
+        if (g_cheb.cheb)
+            mrmf_spec_cheb(g->theta, g->x, g->y, g_cheb.acc, g_cheb.ea, g_cheb.eb, g_cheb.eg, g_cheb.ecr, g_cheb.eci,
+                           nullptr);
+        else
+            mrmf_spec(g->theta, g->x, g->y, nullptr);
         pthread_barrier_wait(&g_block_bar);
     }
     return nullptr;
@@ -82,8 +95,10 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
                              size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1) {
     if (b1 == 0 || b1 > grid) b1 = grid;
     if (block == 0 || block % 64 != 0 || block > 1024) return -1;
+    if (g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr) return -3;
     g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
               {static_cast<const char*>(theta), theta_bytes, "theta"}};
+    if (g_cheb.cheb) g_bufs.push_back({static_cast<const char*>(g_cheb.acc), x_bytes, "acc"});
     gridDim = emu_dim3{grid, 1, 1};
     blockDim = emu_dim3{block, 1, 1};
     const unsigned nw = block / 64;
@@ -113,4 +128,15 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
     pthread_barrier_destroy(&g_block_bar);
     for (unsigned w = 0; w < nw; ++w) pthread_barrier_destroy(&g_wave_bar[w]);
     return g_fault;
+}
+
+// The Chebyshev-step kernel over blocks [b0, b1): y (prev) and acc are updated in place; acc has the
+// length of x.
+extern "C" int emu_run_cheb(unsigned grid, unsigned block, const void* theta, size_t theta_bytes, const void* x,
+                            size_t x_bytes, void* prev, void* acc, double ea, double eb, double eg, double ecr,
+                            double eci, unsigned b0, unsigned b1) {
+    g_cheb = ChebCall{true, acc, ea, eb, eg, ecr, eci};
+    const int rc = emu_run_range(grid, block, theta, theta_bytes, x, x_bytes, prev, x_bytes, b0, b1);
+    g_cheb = ChebCall{};
+    return rc;
 }

@@ -68,6 +68,7 @@ inline int emu_readfirstlane(int v) {
     return first;
 }
 #define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((int)(v))
+#define __builtin_amdgcn_sched_barrier(mask) ((void)0)  /* instruction scheduling only */
 
 inline unsigned long long __umul64hi(unsigned long long a, unsigned long long b) {
     return static_cast<unsigned long long>((static_cast<unsigned __int128>(a) * b) >> 64);

@@ -72,6 +72,10 @@ def _compile(src: str) -> ctypes.CDLL:
                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_range.restype = ctypes.c_int
     lib.emu_run_range.argtypes = lib.emu_run.argtypes + [ctypes.c_uint, ctypes.c_uint]
+    lib.emu_run_cheb.restype = ctypes.c_int
+    lib.emu_run_cheb.argtypes = ([ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
+                                 + [ctypes.c_uint, ctypes.c_uint])
     return lib
 
 
@@ -103,3 +107,26 @@ def run(model, x: np.ndarray, theta=None, inner: int = 0, unrolled: int = -1, gr
     if rc != 0:
         raise RuntimeError(f"emu_run failed: {rc}")
     return y
+
+
+def run_cheb(model, x: np.ndarray, prev: np.ndarray, acc: np.ndarray, ea: float, eb: float, eg: float, c: complex,
+             inner: int = 0, unrolled: int = -1, grid: int | None = None, tuning=None, blocks=None):
+    """The Chebyshev-step kernel (c128): returns (prev', acc') with prev' = ea H x + eb x + eg prev and
+    acc' = acc + c prev', emulated on the CPU (rows outside the emulated blocks keep their inputs)."""
+    src = kernel_source(model, L.MRMF_SOURCE_CHEB, inner, unrolled, tuning=tuning)
+    if src is None:
+        raise ValueError("the plan does not qualify for the specialized kernel")
+    block, tiles = launch_shape(src)
+    if grid is None:
+        grid = min(tiles, 8)
+    lib = _compile(src)
+    th = np.ascontiguousarray(model.theta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.complex128)
+    pv = np.array(prev, dtype=np.complex128, copy=True)
+    av = np.array(acc, dtype=np.complex128, copy=True)
+    b0, b1 = blocks if blocks is not None else (0, 0)
+    rc = lib.emu_run_cheb(grid, block, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, pv.ctypes.data,
+                          av.ctypes.data, ea, eb, eg, c.real, c.imag, b0, b1)
+    if rc != 0:
+        raise RuntimeError(f"emu_run_cheb failed: {rc}")
+    return pv, av

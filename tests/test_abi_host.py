@@ -181,3 +181,27 @@ def test_norm_bound():
     L.call("mrmf_plan_norm_bound", h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(b))
     L.lib().mrmf_plan_destroy(h)
     assert abs(b.value - 1.5 * 0.7 * 2.0) <= 1e-15        # ||a|| on n_max = 4 is sqrt(4)
+
+
+# ------------------------------------------------------------------ restricted basis (host side)
+def test_sector_dimensions_and_errors():
+    """mrmf_sector_dim against the oracle's enumeration for every digit sum of random lattices; invalid
+    digit sums are rejected."""
+    from oracle import sector as osec
+    rng = np.random.default_rng(21)
+    for _ in range(4):
+        m = W.random_model(rng, n_sites=5, max_dim=3000)
+        st, h = host_plan(m)
+        assert st == 0
+        qmax = sum(s.d - 1 for s in m.sites)
+        for Q in range(qmax + 1):
+            sec = ctypes.c_void_p()
+            L.call("mrmf_sector_create", h, Q, ctypes.byref(sec))
+            n = ctypes.c_int64()
+            L.call("mrmf_sector_dim", sec, ctypes.byref(n))
+            assert n.value == osec.labels(m, Q).size
+            L.lib().mrmf_sector_destroy(sec)
+        sec = ctypes.c_void_p()
+        assert L.lib().mrmf_sector_create(h, qmax + 1, ctypes.byref(sec)) == L.MRMF_E_INVALID_ARG
+        assert L.lib().mrmf_sector_create(h, -1, ctypes.byref(sec)) == L.MRMF_E_INVALID_ARG
+        L.lib().mrmf_plan_destroy(h)

@@ -97,6 +97,27 @@ def test_full_size_ring_invariants():
     assert np.abs(x[t(rows)].cpu().numpy() - x0[rows]).max() > 1e-4      # it did move
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_fused_step_matches_two_pass(k):
+    """The specialized kernel's fused Chebyshev step against the generic kernel's matvec + update on the
+    reduced ring / torus (sampled against the oracle as well)."""
+    m, x0 = W.config(k, reduced=3 if k == 3 else 14)
+    x0 = x0.astype(np.complex128)
+    a, b = mk(m), mk(m)
+    b.set_kernel("generic")
+    th = t(m.theta)
+    tuned = a.autotune(th, t(x0), kernel="cheb", use_cache=False)
+    print("cheb shape", tuned, flush=True)
+    ra = a.propagate(th, t(x0), 0.2, 2)
+    rb = b.propagate(th, t(x0), 0.2, 2)
+    a.prepare(torch.complex128)
+    assert a.kernel_info()["kind"] == "specialized" and b.kernel_info()["kind"] == "generic"
+    xa, xb = ra["x"].cpu().numpy(), rb["x"].cpu().numpy()
+    assert rel_err(xa, xb) <= 1e-13
+    if m.dim <= 200000:
+        assert rel_err(xa, oprop.propagate(m, x0, 0.2, 2)) <= 1e-11
+
+
 def test_propagate_errors():
     from paper_2606_02169_amd import _lib as L
     m = W.xx_chain_in_field(4, 1.0, 0.2)

@@ -1,0 +1,120 @@
+"""Restricted basis of a fixed digit-sum sector (mrmf_sector_*, Sec. VI case 2) against the restricted-
+basis oracle: labels and lookups bit-exact, the sector matvec to the matvec tolerances, the worked lookup
+example of App. D, sector Lanczos against closed forms and the oracle, and the 20-site ring's S_z = 0
+sector on sampled rows."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import lanczos as olz
+from oracle import sector as osec
+from tests.helpers import rel_err
+from workloads.model import OP_LOWER, OP_RAISE, Model, Term, spin_site
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+TOL_Z, TOL_C = 1e-12, 2e-5
+
+
+def t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def sector(model, Q, **kw):
+    from paper_2606_02169_amd.plan import Plan, Sector
+    return Sector(Plan.from_model(model, **kw), Q)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sector_random_models(seed):
+    rng = np.random.default_rng(6100 + seed)
+    herm = seed % 3 != 0
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 7)), max_dim=20000, hermitian=herm,
+                       n_params=int(rng.integers(1, 4)), n_terms=20)
+    qmax = sum(s.d - 1 for s in m.sites)
+    Q = int(rng.integers(0, qmax + 1))
+    lab = osec.labels(m, Q)
+    print(f"seed={seed} D={m.dim} Q={Q} Dr={lab.size}", flush=True)
+    S = sector(m, Q, require_hermitian=herm)
+    assert S.dim == lab.size
+    assert np.array_equal(S.labels().cpu().numpy(), lab)
+    F = np.concatenate([lab[:50], rng.integers(-3, m.dim + 3, 400)])
+    assert np.array_equal(S.lookup(t(F.astype(np.int64))).cpu().numpy(), osec.lookup(lab, F))
+    x = W.random_state(lab.size, rng)
+    y = S.matvec(t(m.theta), t(x)).cpu().numpy()
+    assert rel_err(y, osec.matvec(m, Q, x, lab=lab)) <= TOL_Z
+    x32 = x.astype(np.complex64)
+    y32 = S.matvec(t(m.theta.astype(np.float32)), t(x32)).cpu().numpy()
+    ref32 = osec.matvec(m, Q, x32.astype(np.complex128), theta=m.theta.astype(np.float32).astype(np.float64), lab=lab)
+    assert rel_err(y32, ref32) <= TOL_C
+
+
+def test_app_d_lookup_example_on_gpu():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lookup_toy_N4_M0.json")))
+    N, J = g["n_sites"], 1.7
+    m = Model([spin_site(1)] * N, [Term(N - 1 - 2, OP_RAISE, N - 1 - 0, OP_LOWER, 0, 0.5)], np.array([J]))
+    S = sector(m, g["magnetization"] + N // 2, require_hermitian=False)
+    assert S.labels().cpu().tolist() == [int(s, 2) for s, _ in g["table"]]
+    ex = g["example"]
+    F = t(np.array([int(ex["source_label"], 2), int(ex["invalid_label"], 2)], dtype=np.int64))
+    assert S.lookup(F).cpu().tolist() == [ex["source_index"], -1]
+    x = np.zeros(6, dtype=np.complex128)
+    x[ex["source_index"]] = 1.0
+    y = S.matvec(t(m.theta), t(x)).cpu().numpy()
+    expect = np.zeros(6, dtype=np.complex128)
+    expect[ex["target_index"]] = ex["coefficient_over_J"] * J
+    assert np.array_equal(y, expect)
+
+
+def test_one_magnon_sector_lanczos():
+    """Sector Lanczos on the open XX chain (N = 24) in its one-magnon (24 states) and two-magnon (276
+    states) sectors against the free-fermion ground energies."""
+    N, J, h = 24, 1.0, 0.2
+    m = W.xx_chain_in_field(N, J, h)
+    eps = np.sort(J * np.cos(np.arange(1, N + 1) * np.pi / (N + 1)))
+    for Q, e0 in ((1, eps[0] + h - N * h / 2), (2, eps[0] + eps[1] + 2 * h - N * h / 2)):
+        S = sector(m, Q)
+        x = W.random_state(S.dim, np.random.default_rng(Q))
+        r = S.lanczos(t(m.theta), t(x), min(S.dim, 60))["result"].cpu().numpy()
+        assert abs(r[0] - e0) <= 1e-12
+
+
+def test_ring_sector_lanczos_reduced():
+    """The 20-site ring's structure at N = 12 in its S_z = 0 sector: sector Lanczos against the oracle's
+    Lanczos on the oracle's sector matvec."""
+    m, _ = W.config(2, reduced=12)
+    Q = Sector_digit_sum(m, 0.0)
+    lab = osec.labels(m, Q)
+    x = W.random_state(lab.size, np.random.default_rng(5))
+    S = sector(m, Q)
+    r = S.lanczos(t(m.theta), t(x), 80)["result"].cpu().numpy()
+    o = olz.lanczos(lambda v: osec.matvec(m, Q, v, lab=lab), x, 80)
+    assert abs(r[0] - o["theta"]) <= 1e-10 * abs(o["theta"])
+
+
+def Sector_digit_sum(m, M):
+    from paper_2606_02169_amd.plan import Sector
+    return Sector.digit_sum_of(m.sites, M)
+
+
+def test_ring20_sz0_sector_sampled():
+    """20-site ferrimagnetic ring, S_z = 0 sector (7,873,260 states): sampled rows against the oracle,
+    labels of the sampled rows against the oracle's enumeration."""
+    m, _ = W.config(2, with_state=False)
+    Q = Sector_digit_sum(m, 0.0)
+    S = sector(m, Q)
+    assert S.dim == 7873260
+    rng = np.random.default_rng(7)
+    x = W.random_state(S.dim, rng)
+    y = S.matvec(t(m.theta), t(x))
+    torch.cuda.synchronize()
+    lab = osec.labels(m, Q)
+    rows = np.unique(np.concatenate([np.arange(200), np.arange(S.dim - 200, S.dim),
+                                     rng.choice(S.dim, 3000, replace=False)])).astype(np.int64)
+    assert np.array_equal(S.labels().cpu().numpy()[rows], lab[rows])
+    got = y[t(rows)].cpu().numpy()
+    assert rel_err(got, osec.matvec(m, Q, x, lab=lab, rows=rows)) <= TOL_Z

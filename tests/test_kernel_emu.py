@@ -117,3 +117,18 @@ def test_double_ladder_channels(variant):
         done = ~np.isnan(y.real)
         assert done.any()
         assert rel_err(y[done], ref[done]) <= TOL_Z, (inner, unrolled)
+
+
+@pytest.mark.parametrize("variant,addressing", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_chebyshev_step_epilogue(variant, addressing):
+    """The c128 kernel with the fused Chebyshev step: prev' = ea H x + eb x + eg prev, acc' = acc + c prev',
+    against the oracle's H x on the emulated blocks."""
+    rng = np.random.default_rng(31 + variant)
+    m = W.random_model(rng, n_sites=5, max_dim=4000, n_params=2)
+    x, prev, acc = (W.random_state(m.dim, rng) for _ in range(3))
+    ea, eb, eg, c = 0.37, -0.21, -1.0, 0.3 - 0.8j
+    hx = mf.matvec(m, x)
+    p2, a2 = E.run_cheb(m, x, prev, acc, ea, eb, eg, c, tuning={"variant": variant, "addressing": addressing})
+    want_p = ea * hx + eb * x + eg * prev
+    assert rel_err(p2, want_p) <= 1e-12
+    assert rel_err(a2, acc + c * want_p) <= 1e-12
