@@ -27,6 +27,8 @@ struct mrmf_sector_t {
     std::vector<mrmf::DevDiag> diags;
     std::vector<unsigned char> image;  // device image: sites, channels, diagonal terms, tables, rank tables
     size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_rt = 0, off_rto = 0;
+    int32_t n_rt = 0;
+    int64_t rt_max = 0;  // largest rank-table entry (32-bit LDS tables when below 2^31)
     size_t ws_bytes = 0;
 };
 
@@ -40,7 +42,7 @@ struct SectorArgs {
     const int64_t* rt;       // rank tables: site k at rt + rto[k], entry (q, v) at q * (d_k + 1) + v
     const int64_t* rto;      // per-site offsets into rt
     int64_t Dr;
-    int32_t Q, pad;
+    int32_t Q, n_rt;         // digit sum, number of rank-table entries
 };
 
 SectorArgs sector_args(const mrmf_sector_t* S, const void* d_ws) {
@@ -60,7 +62,7 @@ SectorArgs sector_args(const mrmf_sector_t* S, const void* d_ws) {
     a.rto = reinterpret_cast<const int64_t*>(b + S->off_rto);
     a.Dr = S->Dr;
     a.Q = S->Q;
-    a.pad = 0;
+    a.n_rt = S->n_rt;
     return a;
 }
 
@@ -157,6 +159,98 @@ __global__ __launch_bounds__(kSB) void k_sector_matvec(SectorArgs a, const R* __
     }
 }
 
+// The same map with the rank tables, their per-site offsets and the digits / remaining sums of the
+// block's rows in LDS (dynamic shared memory sized for this lattice): unranking and the source-rank
+// updates then read LDS only.  RT is int32_t when every rank fits, else int64_t.
+template <typename R, typename RT>
+__global__ __launch_bounds__(kSB) void k_sector_matvec_lds(SectorArgs a, const R* __restrict__ theta,
+                                                           const typename Cx<R>::T* __restrict__ x,
+                                                           typename Cx<R>::T* __restrict__ y,
+                                                           const int32_t* __restrict__ skip) {
+    using C = typename Cx<R>::T;
+    if (skip != nullptr && *skip != 0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.p.N;
+    RT* lrt = reinterpret_cast<RT*>(smem);
+    int32_t* lro = reinterpret_cast<int32_t*>(smem + sizeof(RT) * size_t(a.n_rt));  // offset of site k
+    int32_t* ld1 = lro + N;                                                         // d_k + 1
+    uint16_t* rem = reinterpret_cast<uint16_t*>(ld1 + N);                            // [N][kSB]
+    uint8_t* dig = reinterpret_cast<uint8_t*>(rem + size_t(N) * kSB);                // [N][kSB]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < a.n_rt; i += kSB) lrt[i] = static_cast<RT>(a.rt[i]);
+    for (int k = tid; k < N; k += kSB) {
+        lro[k] = static_cast<int32_t>(a.rto[k]);
+        ld1[k] = a.p.site[k].d + 1;
+    }
+    __syncthreads();
+    const PlanArgs& p = a.p;
+    auto rt = [&](int k, int q, int v) -> int64_t { return lrt[lro[k] + q * ld1[k] + v]; };
+    for (int64_t r = int64_t(blockIdx.x) * kSB + tid; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
+        {   // unrank: the digit of site k is the v with R_k(q, v) <= left < R_k(q, v + 1)
+            int q = a.Q;
+            int64_t left = r;
+            for (int k = 0; k < N; ++k) {
+                const int d1 = ld1[k];
+                const int vmax = q < d1 - 2 ? q : d1 - 2;
+                const RT* Rk = lrt + lro[k] + q * d1;
+                int v = 0;
+                while (v < vmax && Rk[v + 1] <= left) ++v;
+                dig[k * kSB + tid] = static_cast<uint8_t>(v);
+                rem[k * kSB + tid] = static_cast<uint16_t>(q);
+                left -= Rk[v];
+                q -= v;
+            }
+        }
+        R dr = 0, di = 0;
+        for (int k = 0; k < p.n_diag; ++k) {
+            const DevDiag g = p.diag[k];
+            R f = sfactor<R>(p, g.opa, p.site[g.a].tab, dig[g.a * kSB + tid]);
+            if (g.b >= 0) f *= sfactor<R>(p, g.opb, p.site[g.b].tab, dig[g.b * kSB + tid]);
+            const R th = theta[g.param];
+            dr += th * static_cast<R>(g.wr) * f;
+            di += th * static_cast<R>(g.wi) * f;
+        }
+        const C xf = x[r];
+        R ar = dr * xf.x - di * xf.y;
+        R ai = dr * xf.y + di * xf.x;
+        for (int c = 0; c < p.n_chan; ++c) {
+            const DevChan ch = p.chan[c];
+            const int na = dig[ch.a * kSB + tid], nb = dig[ch.b * kSB + tid];
+            const int sa = na - ch.qa, sb = nb - ch.qb;
+            if (sa < 0 || sa >= ld1[ch.a] - 1 || sb < 0 || sb >= ld1[ch.b] - 1) continue;
+            const bool a_first = ch.a < ch.b;
+            const int i = a_first ? ch.a : ch.b, j = a_first ? ch.b : ch.a;
+            const int ni = a_first ? na : nb, nsi = a_first ? sa : sb;
+            const int nj = a_first ? nb : na, nsj = a_first ? sb : sa;
+            const int dq = nsi - ni;
+            const int qi = rem[i * kSB + tid];
+            int64_t drank = rt(i, qi, nsi) - rt(i, qi, ni);
+            for (int k = i + 1; k < j; ++k) {
+                const int qk = rem[k * kSB + tid], nk = dig[k * kSB + tid];
+                drank += rt(k, qk - dq, nk) - rt(k, qk, nk);
+            }
+            const int qj = rem[j * kSB + tid];
+            drank += rt(j, qj - dq, nsj) - rt(j, qj, nj);
+            const R f = sfactor<R>(p, ch.opa, p.site[ch.a].tab, na) * sfactor<R>(p, ch.opb, p.site[ch.b].tab, nb);
+            const R th = theta[ch.param] * f;
+            const R cr = th * static_cast<R>(ch.wr), ci = th * static_cast<R>(ch.wi);
+            const C xs = x[r + drank];
+            ar += cr * xs.x - ci * xs.y;
+            ai += cr * xs.y + ci * xs.x;
+        }
+        C out;
+        out.x = ar;
+        out.y = ai;
+        y[r] = out;
+    }
+}
+
+// Dynamic LDS of k_sector_matvec_lds for this sector (0 when it exceeds 64 KB: global-table kernel).
+size_t sector_lds_bytes(const mrmf_sector_t* S, bool rt32) {
+    const size_t b = (rt32 ? 4 : 8) * size_t(S->n_rt) + 8 * size_t(S->N) + 3 * size_t(S->N) * kSB;
+    return b <= 65536 ? b : 0;
+}
+
 // Full-basis index F = sum_k n_k M_k of packed rows r0 .. r0 + count - 1.
 __global__ __launch_bounds__(kSB) void k_sector_labels(SectorArgs a, const int64_t* __restrict__ M, int64_t r0,
                                                        int64_t count, int64_t* __restrict__ out) {
@@ -212,8 +306,18 @@ template <typename R>
 mrmf_status sector_matvec(const mrmf_sector_t* S, const void* d_ws, const R* theta, const void* x, void* y,
                           hipStream_t s, const int32_t* skip) {
     using C = typename Cx<R>::T;
-    hipLaunchKernelGGL(k_sector_matvec<R>, dim3(sector_grid(S->Dr)), dim3(kSB), 0, s, sector_args(S, d_ws), theta,
-                       static_cast<const C*>(x), static_cast<C*>(y), skip);
+    const bool rt32 = S->rt_max < (int64_t(1) << 31);
+    const size_t lds = sector_lds_bytes(S, rt32);
+    const dim3 grid(sector_grid(S->Dr)), block(kSB);
+    if (lds == 0)
+        hipLaunchKernelGGL(k_sector_matvec<R>, grid, block, 0, s, sector_args(S, d_ws), theta,
+                           static_cast<const C*>(x), static_cast<C*>(y), skip);
+    else if (rt32)
+        hipLaunchKernelGGL((k_sector_matvec_lds<R, int32_t>), grid, block, lds, s, sector_args(S, d_ws), theta,
+                           static_cast<const C*>(x), static_cast<C*>(y), skip);
+    else
+        hipLaunchKernelGGL((k_sector_matvec_lds<R, int64_t>), grid, block, lds, s, sector_args(S, d_ws), theta,
+                           static_cast<const C*>(x), static_cast<C*>(y), skip);
     return launch_status();
 }
 
@@ -285,6 +389,8 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->off_val = section(sizeof(double) * plan->val.size());
     S->off_up = section(sizeof(double) * plan->up.size());
     S->off_rt = section(sizeof(int64_t) * rt.size());
+    S->n_rt = static_cast<int32_t>(rt.size());
+    for (int64_t v : rt) S->rt_max = std::max(S->rt_max, v);
     S->off_rto = section(sizeof(int64_t) * N);
     S->ws_bytes = off;
     S->image.assign(off, 0);
