@@ -17,7 +17,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from workloads.model import BOSON, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN, Model, Site
+from workloads.model import (BOSON, OP_LOCAL_BASE, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN,
+                             Model, Site)
 
 
 def local_ops(site: Site) -> dict:
@@ -41,14 +42,33 @@ def local_ops(site: Site) -> dict:
             OP_LOWER2: up.T @ up.T}
 
 
+def general_op(model: Model, op: int, site: int) -> np.ndarray:
+    """The d x d matrix of general one-site operator op (App. B local monomials given as one band):
+    M[n, n - shift] = values[n] wherever n - shift is a digit."""
+    lo = model.local_ops[op - OP_LOCAL_BASE]
+    if lo.site != site:
+        raise ValueError("a general operator acts on its own site only")
+    d = model.sites[site].d
+    M = np.zeros((d, d))
+    for n in range(d):
+        if 0 <= n - lo.shift < d:
+            M[n, n - lo.shift] = lo.values[n]
+    return M
+
+
+def op_matrix(model: Model, op: int, site: int) -> np.ndarray:
+    if op >= OP_LOCAL_BASE:
+        return general_op(model, op, site)
+    return local_ops(model.sites[site])[op]
+
+
 def _factors(model: Model, t):
     facs = [None] * len(model.sites)
-    ops_a = local_ops(model.sites[t.site_a])
-    facs[t.site_a] = ops_a[t.op_a]
+    facs[t.site_a] = op_matrix(model, t.op_a, t.site_a)
     if t.site_b >= 0:
         if t.site_b == t.site_a:
             raise ValueError("a two-site term needs two different sites")
-        facs[t.site_b] = local_ops(model.sites[t.site_b])[t.op_b]
+        facs[t.site_b] = op_matrix(model, t.op_b, t.site_b)
     return facs
 
 

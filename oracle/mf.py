@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from workloads.model import OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, Model
+from workloads.model import OP_LOCAL_BASE, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, Model
 
 from . import build as _build
 
@@ -31,6 +31,9 @@ def lib():
         L.mf_ref_matvec.restype = ctypes.c_int
         L.mf_ref_matvec.argtypes = [ctypes.c_int32, i32p, i32p, f64p, ctypes.c_int32, i32p, i32p,
                                     f64p, ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
+        L.mf_ref_general_add.restype = ctypes.c_int
+        L.mf_ref_general_add.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, i64p, f64p, f64p,
+                                         ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
         L.mf_ref_sources.restype = ctypes.c_int
         L.mf_ref_sources.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int64,
                                      ctypes.c_int64, i64p]
@@ -51,6 +54,8 @@ def app_a_inputs(model: Model, theta=None):
     pairs: dict = {}
     Jlist = []
     for t in model.terms:
+        if _is_general(t):
+            continue                       # handled by general_inputs / mf_ref_general_add
         c = theta[t.param] * complex(t.w)
         if t.site_b < 0:
             col = {OP_Z: 0, OP_Z2: 1, OP_RAISE: 2, OP_LOWER: 3, OP_RAISE2: 4, OP_LOWER2: 5}[t.op_a]
@@ -68,6 +73,47 @@ def app_a_inputs(model: Model, theta=None):
     pj = np.array([k[1] for k in keys], dtype=np.int32)
     J = np.array(Jlist, dtype=np.complex128).reshape(-1, 3, 3) if Jlist else np.zeros((0, 3, 3), np.complex128)
     return kind, twok, onsite, pi, pj, J
+
+
+def _is_general(t) -> bool:
+    return t.op_a >= OP_LOCAL_BASE or (t.site_b >= 0 and t.op_b >= OP_LOCAL_BASE)
+
+
+def _band(model: Model, op: int, site: int):
+    """(shift, table at target digits) of one operator: a general one's given table, or the band of the
+    closed-form local matrix of a built-in one (oracle.kron.local_ops)."""
+    from . import kron
+    if op >= OP_LOCAL_BASE:
+        lo = model.local_ops[op - OP_LOCAL_BASE]
+        if lo.site != site:
+            raise ValueError("a general operator acts on its own site only")
+        return lo.shift, np.asarray(lo.values, dtype=np.float64)
+    Mx = kron.local_ops(model.sites[site])[op]
+    d = Mx.shape[0]
+    q = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}[op]
+    return q, np.array([Mx[n, n - q] if 0 <= n - q < d else 0.0 for n in range(d)])
+
+
+def general_inputs(model: Model, theta=None):
+    """Terms with a general one-site operator as (gterm [n,4], toff [n,2], tab, c [n] complex)."""
+    theta = model.theta if theta is None else np.asarray(theta, dtype=np.float64)
+    gterm, toff, tab, c = [], [], [], []
+    size = 0
+    for t in model.terms:
+        if not _is_general(t):
+            continue
+        qa, ta = _band(model, t.op_a, t.site_a)
+        if t.site_b >= 0:
+            qb, tb = _band(model, t.op_b, t.site_b)
+        else:
+            qb, tb = 0, np.zeros(0)
+        gterm.append((t.site_a, qa, t.site_b, qb))
+        toff.append((size, size + ta.size))
+        tab += [ta, tb]
+        size += ta.size + tb.size
+        c.append(theta[t.param] * complex(t.w))
+    return (np.array(gterm, dtype=np.int32).reshape(-1, 4), np.array(toff, dtype=np.int64).reshape(-1, 2),
+            np.concatenate(tab) if tab else np.zeros(1), np.array(c, dtype=np.complex128))
 
 
 def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
@@ -96,6 +142,15 @@ def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
                              _p(y.view(np.float64), ctypes.c_double), nrows, rp)
     if rc != 0:
         raise RuntimeError("mf_ref_matvec rejected its input")
+    gterm, toff, tab, c = general_inputs(model, theta)
+    if gterm.shape[0]:
+        rc = lib().mf_ref_general_add(len(model.sites), _p(twok, ctypes.c_int32), gterm.shape[0],
+                                      _p(gterm, ctypes.c_int32), _p(toff, ctypes.c_int64),
+                                      _p(tab, ctypes.c_double), _p(c.view(np.float64), ctypes.c_double), D,
+                                      _p(xx.view(np.float64), ctypes.c_double),
+                                      _p(y.view(np.float64), ctypes.c_double), nrows, rp)
+        if rc != 0:
+            raise RuntimeError("mf_ref_general_add rejected its input")
     return y
 
 

@@ -151,6 +151,44 @@ int mf_ref_matvec(int32_t N, const int32_t* kind, const int32_t* twok, const dou
 }
 
 /*
+ * General one-site bands (App. B: any local monomial (S_+)^p (S_z)^r (S_-)^l is one band of the local
+ * matrix): term t couples site a with shift qa and table ta (ta[n] = <n|O_a|n - qa> at target digit n) and,
+ * when b >= 0, site b with qb and tb.  Adds to y (rows as in mf_ref_matvec):
+ *   y_F += c_t ta[n_a] tb[n_b] x[F - qa M_a - qb M_b]   when n_a - qa and n_b - qb are digits.
+ * gterm : [n_gen][4] = (a, qa, b, qb);  toff : [n_gen][2] offsets of ta, tb in tab;  c : [n_gen][2] complex.
+ */
+int mf_ref_general_add(int32_t N, const int32_t* twok, int32_t n_gen, const int32_t* gterm,
+                       const int64_t* toff, const double* tab, const double* c, int64_t D, const double* x,
+                       double* y, int64_t nrows, const int64_t* rows) {
+    int64_t M[MAXSITES], Dm;
+    if (multipliers(N, twok, M, &Dm) != 0 || Dm != D) return -1;
+    const double complex* xc = (const double complex*)x;
+    double complex* yc = (double complex*)y;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t F = rows ? rows[r] : r;
+        double complex acc = 0.0;
+        for (int t = 0; t < n_gen; ++t) {
+            const int32_t* g = gterm + 4 * t;
+            int a = g[0], qa = g[1], b = g[2], qb = g[3];
+            int na = (int)((F / M[a]) % (int64_t)(twok[a] + 1));
+            if (na - qa < 0 || na - qa > twok[a]) continue;
+            double f = tab[toff[2 * t] + na];
+            int64_t src = F - (int64_t)qa * M[a];
+            if (b >= 0) {
+                int nb = (int)((F / M[b]) % (int64_t)(twok[b] + 1));
+                if (nb - qb < 0 || nb - qb > twok[b]) continue;
+                f *= tab[toff[2 * t + 1] + nb];
+                src -= (int64_t)qb * M[b];
+            }
+            acc += (c[2 * t] + I * c[2 * t + 1]) * f * xc[src];
+        }
+        yc[r] += acc;
+    }
+    return 0;
+}
+
+/*
  * Source index of every term for the target rows F0 .. F0+count-1 (Eq. sourceoffset, with the
  * admissibility test on the source digits): out[r][t] = I, or -1 when the term cannot reach F.
  * terms : [n_terms][4] = (site_a, alpha_a, site_b, alpha_b), alpha in (z, +, -, ++, --) = (0..4);

@@ -335,3 +335,43 @@ def test_rayleigh_gradient_fd():
             fd = (loss(x + d) - loss(x - d)) / (2 * h)
             comp = gx[k].real if unit == 1.0 else gx[k].imag
             assert abs(fd - comp) < 1e-8
+
+
+# ------------------------------------------------------------------ general one-site operators (App. B)
+def test_aklt_chain_ground_energy():
+    """S.S + (1/3)(S.S)^2 on a periodic spin-1 ring (AKLT): the valence-bond solid is the unique ground
+    state with energy exactly -2/3 per bond; on an open chain it is fourfold degenerate (edge spins)."""
+    for N in (4, 6):
+        ev = np.linalg.eigvalsh(dense_from_mf(W.bilinear_biquadratic_chain(N, 1 / 3)))
+        assert abs(ev[0] + 2 * N / 3) <= 1e-12 and ev[1] - ev[0] > 0.1
+    ev = np.linalg.eigvalsh(dense_from_mf(W.bilinear_biquadratic_chain(5, 1 / 3, periodic=False)))
+    assert np.allclose(ev[:4], -2 * 4 / 3, atol=1e-12) and ev[4] - ev[0] > 0.1
+
+
+@pytest.mark.parametrize("beta", [-0.7, 0.25, 1.0])
+def test_bilinear_biquadratic_two_sites(beta):
+    """Two spin-1: S.S = [S(S+1) - 4] / 2 on total spin S, so the levels are x + beta x^2 for
+    x = -2 (S = 0, once), -1 (S = 1, 3 times), 1 (S = 2, 5 times)."""
+    m = W.bilinear_biquadratic_chain(2, beta, periodic=False)
+    ev = np.linalg.eigvalsh(dense_from_mf(m))
+    expect = np.sort([-2 + 4 * beta] + [-1 + beta] * 3 + [1 + beta] * 5)
+    assert np.allclose(ev, expect, atol=1e-13)
+
+
+def test_general_operator_tables_against_products():
+    """The monomial tables of the bilinear-biquadratic model are bands of products of the oracle's own
+    closed-form spin matrices (oracle.kron.local_ops), and the oracle's row loop with general operators
+    equals the Kronecker definition on random general models."""
+    m = W.bilinear_biquadratic_chain(3, 0.4)
+    o = kron.local_ops(spin_site(2))
+    z, p, q = o[OP_Z], o[OP_RAISE], o[OP_LOWER]
+    want = [z @ z, z @ p, p @ z, z @ q, q @ z, p @ p, q @ q, p @ q, q @ p]
+    for k, M in enumerate(want):
+        assert np.allclose(kron.general_op(m, W.OP_LOCAL_BASE + k, 0), M, atol=1e-15, rtol=0)
+    rng = np.random.default_rng(17)
+    for _ in range(6):
+        g = W.random_general_model(rng, n_sites=4, max_dim=900)
+        x = W.random_state(g.dim, rng)
+        H = kron.dense_H(g)
+        assert np.allclose(H, H.conj().T, atol=1e-14)
+        assert np.linalg.norm(mf.matvec(g, x) - H @ x) <= 1e-13 * np.linalg.norm(H @ x)

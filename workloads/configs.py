@@ -11,8 +11,8 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .model import (BOSON, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN, Model, Site, Term,
-                    boson_site, dim_of, spin_site, xxz_bond_terms)
+from .model import (BOSON, OP_LOCAL_BASE, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAISE2, OP_Z, OP_Z2, SPIN, LocalOp,
+                    Model, Site, Term, boson_site, dim_of, spin_site, xxz_bond_terms)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -172,6 +172,109 @@ def zero_field_splitting(two_s: int, Dz: float, E: float) -> Model:
     terms = [Term(0, OP_Z2, -1, OP_Z, 0, 1.0), Term(0, OP_RAISE2, -1, OP_Z, 1, 0.5),
              Term(0, OP_LOWER2, -1, OP_Z, 1, 0.5)]
     return Model([spin_site(two_s)], terms, np.array([Dz, E], dtype=np.float64), name=f"zfs_2s{two_s}")
+
+
+def spin_matrices(two_s: int):
+    """S_z, S_+, S_- of one spin as dense matrices (basis m = -s .. s, the digit order of Sec. III)."""
+    s = two_s / 2.0
+    m = np.arange(two_s + 1) - s
+    up = np.zeros((two_s + 1, two_s + 1))
+    for i in range(two_s):
+        up[i + 1, i] = np.sqrt(s * (s + 1) - m[i] * (m[i] + 1))
+    return np.diag(m), up, up.T.copy()
+
+
+def band_op(site: int, M: np.ndarray) -> LocalOp:
+    """The single band of a one-site matrix M as a general operator (raises if M has two bands)."""
+    d = M.shape[0]
+    shifts = {i - j for i in range(d) for j in range(d) if M[i, j] != 0.0}
+    if len(shifts) > 1:
+        raise ValueError("operator has more than one band")
+    q = shifts.pop() if shifts else 0
+    return LocalOp(site, q, tuple(float(M[n, n - q]) if 0 <= n - q < d else 0.0 for n in range(d)))
+
+
+def bilinear_biquadratic_chain(N: int, beta: float, periodic: bool = True, two_s: int = 2) -> Model:
+    """sum over bonds of S_i . S_j + beta (S_i . S_j)^2 (App. B higher powers): the square expands into
+    products of one-site monomials S_z^2, S_z S_+, S_+ S_z, S_z S_-, S_- S_z, S_+^2, S_-^2, S_+ S_-, S_- S_+
+    on each site, given as general one-site operators.  beta = 1/3 on spin 1 is the AKLT chain.
+    theta = [1 (bilinear), beta]."""
+    z, p, m = spin_matrices(two_s)
+    prods = {"zz": z @ z, "zp": z @ p, "pz": p @ z, "zm": z @ m, "mz": m @ z, "pp": p @ p, "mm": m @ m,
+             "pm": p @ m, "mp": m @ p}
+    ops, idx = [], {}
+    for site in range(N):
+        for key, M in prods.items():
+            idx[(site, key)] = OP_LOCAL_BASE + len(ops)
+            ops.append(band_op(site, M))
+    # (S_i . S_j)^2 with S_i . S_j = A + (B + C)/2, A = z z, B = + -, C = - +
+    square = [("zz", "zz", 1.0), ("zp", "zm", 0.5), ("pz", "mz", 0.5), ("zm", "zp", 0.5), ("mz", "pz", 0.5),
+              ("pp", "mm", 0.25), ("pm", "mp", 0.25), ("mp", "pm", 0.25), ("mm", "pp", 0.25)]
+    terms: List[Term] = []
+    bonds = [(i, i + 1) for i in range(N - 1)] + ([(N - 1, 0)] if periodic else [])
+    for i, j in bonds:
+        terms += xxz_bond_terms(i, j, 0, 0)
+        for ka, kb, w in square:
+            terms.append(Term(i, idx[(i, ka)], j, idx[(j, kb)], 1, w))
+    return Model([spin_site(two_s)] * N, terms, np.array([1.0, beta]), name=f"blbq_N{N}",
+                 local_ops=ops)
+
+
+def adjoint_op(op: LocalOp) -> LocalOp:
+    """O^dagger of a real one-band operator: shift -q, <n|O^dag|n + q> = <n + q|O|n>."""
+    d = len(op.values)
+    q = op.shift
+    return LocalOp(op.site, -q, tuple(float(op.values[n + q]) if 0 <= n + q < d else 0.0 for n in range(d)))
+
+
+def random_general_model(rng, n_sites: int = 4, max_dim: int = 4096, n_params: int = 3, n_ops: int = 6,
+                         n_terms: int = 10, hermitian: bool = True) -> Model:
+    """Random mixed spin/boson lattice whose terms use random general one-site operators (random band,
+    random real values) alone, paired with each other, or with built-in operators; with hermitian=True
+    every term comes with its adjoint (operator adjoints and conjugate weight) in the same group."""
+    base = random_model(rng, n_sites=n_sites, max_dim=max_dim, n_params=n_params, n_terms=4,
+                        hermitian=hermitian, all_channels=False)
+    ops: List[LocalOp] = []
+    adj_of = {}
+    for _ in range(n_ops):
+        site = int(rng.integers(n_sites))
+        d = base.sites[site].d
+        q = int(rng.integers(-(d - 1), d))
+        vals = tuple(float(v) if 0 <= n - q < d else 0.0 for n, v in enumerate(rng.uniform(-1, 1, d)))
+        a = LocalOp(site, q, vals)
+        ops.append(a)
+        ops.append(adjoint_op(a))
+        ia, ib = OP_LOCAL_BASE + len(ops) - 2, OP_LOCAL_BASE + len(ops) - 1
+        adj_of[ia], adj_of[ib] = ib, ia
+    builtin_adj = {OP_Z: OP_Z, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE}
+    terms = list(base.terms)
+    for _ in range(n_terms):
+        g = OP_LOCAL_BASE + 2 * int(rng.integers(n_ops))
+        site = ops[g - OP_LOCAL_BASE].site
+        w = complex(rng.uniform(-1, 1), rng.uniform(-1, 1))
+        p = int(rng.integers(n_params))
+        kind = rng.integers(3)
+        if kind == 0 or n_sites == 1:                                   # one-site
+            t = Term(site, g, -1, OP_Z, p, w)
+            ta = Term(site, adj_of[g], -1, OP_Z, p, w.conjugate())
+        else:
+            other = [k for k in range(n_sites) if k != site]
+            j = int(rng.choice(other))
+            if kind == 1:                                               # with a built-in operator
+                ob = int(rng.choice([OP_Z, OP_RAISE, OP_LOWER]))
+                t = Term(site, g, j, ob, p, w)
+                ta = Term(site, adj_of[g], j, builtin_adj[ob], p, w.conjugate())
+            else:                                                       # two general operators
+                cand = [OP_LOCAL_BASE + 2 * k for k in range(n_ops) if ops[2 * k].site == j]
+                if not cand:
+                    continue
+                h = int(rng.choice(cand))
+                t = Term(site, g, j, h, p, w)
+                ta = Term(site, adj_of[g], j, adj_of[h], p, w.conjugate())
+        terms.append(t)
+        if hermitian:
+            terms.append(ta)
+    return Model(base.sites, terms, base.theta, name="random_general", local_ops=ops)
 
 
 def xx_chain_in_field(N: int, J: float, h: float) -> Model:

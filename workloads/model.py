@@ -27,6 +27,7 @@ import numpy as np
 
 SPIN, BOSON = 0, 1
 OP_Z, OP_Z2, OP_RAISE, OP_LOWER, OP_RAISE2, OP_LOWER2 = 0, 1, 2, 3, 4, 5
+OP_LOCAL_BASE = 16          # op OP_LOCAL_BASE + i: entry i of Model.local_ops
 
 
 @dataclass(frozen=True)
@@ -58,6 +59,15 @@ class Term:
     w: complex = 1.0
 
 
+@dataclass(frozen=True)
+class LocalOp:
+    """A general one-site operator on one band: <n|O|n - shift> = values[n] for the target digit n
+    (entries whose source n - shift is outside 0..d-1 are ignored)."""
+    site: int
+    shift: int
+    values: tuple
+
+
 @dataclass
 class Model:
     sites: List[Site]
@@ -65,6 +75,7 @@ class Model:
     theta: np.ndarray                     # float64 [n_params]
     name: str = ""
     meta: dict = field(default_factory=dict)
+    local_ops: List[LocalOp] = field(default_factory=list)
 
     @property
     def n_params(self) -> int:
