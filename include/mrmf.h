@@ -64,6 +64,19 @@ typedef struct {
 #define MRMF_OP_LOWER 3
 #define MRMF_OP_RAISE2 4
 #define MRMF_OP_LOWER2 5
+/* General one-site operators (App. B: any local monomial (S_+)^p (S_z)^r (S_-)^l, quadrupolar factors,
+ * truncated local sets): MRMF_OP_LOCAL(i) names entry i of the local-operator list given to
+ * mrmf_plan_create_ex.  Such an operator lives on one band: <n|O|n'> is nonzero only for n - n' = shift,
+ * and values[n] = <n|O|n - shift> for the target digit n (entries whose source n - shift is outside
+ * 0..d-1 are ignored).  It may appear in one-site terms and on either side of two-site terms (the general
+ * alpha-beta channels), always on its own site. */
+#define MRMF_OP_LOCAL_BASE 16
+#define MRMF_OP_LOCAL(i) (MRMF_OP_LOCAL_BASE + (i))
+typedef struct {
+    int32_t site;          /* the site it acts on (its d gives the table length) */
+    int32_t shift;         /* q in (-d, d) */
+    const double* values;  /* host, d entries, read during mrmf_plan_create_ex only */
+} mrmf_local_op;
 
 /* One term of  H(theta) = sum_t theta[param_t] * (w_re + i w_im) * O_{op_a}^{(site_a)} O_{op_b}^{(site_b)}.
  * site_b = -1 makes it a one-site term (op_b ignored; op_a any MRMF_OP_*).  A two-site term needs
@@ -99,6 +112,12 @@ int32_t mrmf_version(void);
  * flags: MRMF_REQUIRE_HERMITIAN.  On success *out owns host memory until mrmf_plan_destroy. */
 mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_terms,
                              const mrmf_term* terms, int32_t n_params, uint32_t flags, mrmf_plan* out);
+/* The same with a list of general one-site operators (MRMF_OP_LOCAL(i), i < n_local <= 4096).  A term
+ * may combine them with the built-in operators; Hermiticity (MRMF_REQUIRE_HERMITIAN) is then checked
+ * numerically, band by band, against the adjoint of every group (relative tolerance 1e-12). */
+mrmf_status mrmf_plan_create_ex(int32_t n_sites, const mrmf_site* sites, int32_t n_terms,
+                                const mrmf_term* terms, int32_t n_params, uint32_t flags, int32_t n_local,
+                                const mrmf_local_op* local, mrmf_plan* out);
 void mrmf_plan_destroy(mrmf_plan plan);
 
 /* D = prod d_i. */

@@ -169,10 +169,18 @@ def sources(model: Model, F0: int, count: int) -> np.ndarray:
 
 
 def adjoint_model(model: Model) -> Model:
-    """Term list of H^dagger: every operator replaced by its adjoint, every weight conjugated."""
-    from workloads.model import Term
+    """Term list of H^dagger: every operator replaced by its adjoint, every weight conjugated.  A general
+    one-site operator's adjoint is its transposed band (shift -q, <n|O^dag|n + q> = <n + q|O|n>)."""
+    from workloads.model import LocalOp, Term
     adj = {OP_Z: OP_Z, OP_Z2: OP_Z2, OP_RAISE: OP_LOWER, OP_LOWER: OP_RAISE, OP_RAISE2: OP_LOWER2,
            OP_LOWER2: OP_RAISE2}
-    terms = [Term(t.site_a, adj[t.op_a], t.site_b, adj[t.op_b] if t.site_b >= 0 else t.op_b, t.param,
+    ops = []
+    for lo in model.local_ops:
+        d, q = len(lo.values), lo.shift
+        ops.append(LocalOp(lo.site, -q, tuple(lo.values[n + q] if 0 <= n + q < d else 0.0 for n in range(d))))
+
+    def a(op):
+        return op if op >= OP_LOCAL_BASE else adj[op]     # general op i -> entry i of the adjoint list
+    terms = [Term(t.site_a, a(t.op_a), t.site_b, a(t.op_b) if t.site_b >= 0 else t.op_b, t.param,
                   complex(t.w).conjugate()) for t in model.terms]
-    return Model(model.sites, terms, model.theta.copy(), name=model.name + "^dag")
+    return Model(model.sites, terms, model.theta.copy(), name=model.name + "^dag", local_ops=ops)

@@ -42,6 +42,13 @@ class mrmf_term(ctypes.Structure):
                 ("w_re", ctypes.c_double), ("w_im", ctypes.c_double)]
 
 
+class mrmf_local_op(ctypes.Structure):
+    _fields_ = [("site", ctypes.c_int32), ("shift", ctypes.c_int32), ("values", ctypes.POINTER(ctypes.c_double))]
+
+
+MRMF_OP_LOCAL_BASE = 16
+
+
 class MrmfError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -59,6 +66,8 @@ SIGNATURES = {
     "mrmf_status_string": (ctypes.c_char_p, [_i32]),
     "mrmf_version": (_i32, []),
     "mrmf_plan_create": (_i32, [_i32, _P(mrmf_site), _i32, _P(mrmf_term), _i32, _u32, _P(_vp)]),
+    "mrmf_plan_create_ex": (_i32, [_i32, _P(mrmf_site), _i32, _P(mrmf_term), _i32, _u32, _i32, _P(mrmf_local_op),
+                                   _P(_vp)]),
     "mrmf_plan_destroy": (None, [_vp]),
     "mrmf_plan_dim": (_i32, [_vp, _P(_i64)]),
     "mrmf_plan_n_offdiag": (_i32, [_vp, _P(_i32)]),

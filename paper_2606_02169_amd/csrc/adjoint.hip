@@ -27,7 +27,8 @@ __device__ __forceinline__ double local_factor64(const PlanArgs& p, int op, int 
         case MRMF_OP_RAISE: return p.up[tab + n];
         case MRMF_OP_LOWER: return p.up[tab + n + 1];
         case MRMF_OP_RAISE2: return p.up[tab + n] * p.up[tab + n - 1];
-        default: return p.up[tab + n + 1] * p.up[tab + n + 2];
+        case MRMF_OP_LOWER2: return p.up[tab + n + 1] * p.up[tab + n + 2];
+        default: return p.up[p.lofs[op - MRMF_OP_LOCAL_BASE] + n];  // general one-site operator
     }
 }
 

@@ -180,6 +180,16 @@ struct Gen {
     }
 
     int SZ() const { return f32 ? 8 : 16; }
+    int op_shift(int op) const {
+        if (op >= MRMF_OP_LOCAL_BASE) return p->lshift[op - MRMF_OP_LOCAL_BASE];
+        switch (op) {
+            case MRMF_OP_RAISE: return 1;
+            case MRMF_OP_LOWER: return -1;
+            case MRMF_OP_RAISE2: return 2;
+            case MRMF_OP_LOWER2: return -2;
+            default: return 0;
+        }
+    }
     bool is_inner(int s) const { return s >= tl.k_in; }
     bool is_unrolled(int s) const { return s >= tl.k_u && s < tl.k_in; }
     bool is_static(int s) const { return s >= tl.k_u; }
@@ -243,12 +253,15 @@ struct Gen {
         std::string c;
         auto add = [&](int s, int op) {
             if (s < 0 || is_static(s)) return;
+            // the source digit n - q must lie in 0..d-1 (q: the operator's digit shift)
             std::string e;
-            if (op == MRMF_OP_RAISE) e = "n" + std::to_string(s) + " >= 1u";
-            if (op == MRMF_OP_LOWER) e = "n" + std::to_string(s) + " <= " + std::to_string(p->d[s] - 2) + "u";
-            if (op == MRMF_OP_RAISE2) e = "n" + std::to_string(s) + " >= 2u";
-            if (op == MRMF_OP_LOWER2)  // d <= 2: never admissible (the unsigned digit is never below 0)
-                e = p->d[s] >= 3 ? "n" + std::to_string(s) + " <= " + std::to_string(p->d[s] - 3) + "u" : "false";
+            const int q = op_shift(op), d = p->d[s];
+            if (q >= d || d - 1 + q < 0)  // (S_+-)^2 on a spin 1/2: never admissible
+                e = "false";
+            else if (q > 0)
+                e = "n" + std::to_string(s) + " >= " + std::to_string(q) + "u";
+            else if (q < 0)
+                e = "n" + std::to_string(s) + " <= " + std::to_string(d - 1 + q) + "u";
             if (!e.empty()) c = c.empty() ? e : c + " && " + e;
         };
         add(a, opa);

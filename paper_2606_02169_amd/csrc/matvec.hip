@@ -28,7 +28,8 @@ __device__ __forceinline__ R local_factor(const PlanArgs& p, int op, int tab, in
         case MRMF_OP_RAISE: return static_cast<R>(p.up[tab + n]);
         case MRMF_OP_LOWER: return static_cast<R>(p.up[tab + n + 1]);
         case MRMF_OP_RAISE2: return static_cast<R>(p.up[tab + n] * p.up[tab + n - 1]);
-        default: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
+        case MRMF_OP_LOWER2: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
+        default: return static_cast<R>(p.up[p.lofs[op - MRMF_OP_LOCAL_BASE] + n]);  // general one-site operator
     }
 }
 

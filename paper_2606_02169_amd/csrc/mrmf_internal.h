@@ -65,6 +65,7 @@ struct PlanArgs {
     const DevDiag* diag;
     const double* val;  // val[tab + n]: S_z eigenvalue m = n - s (spin) or occupation n (boson)
     const double* up;   // up[tab + n] = <n|R|n-1> for n >= 1 (R = S_+ or a^dagger), up[tab] = 0
+    const int32_t* lofs;  // general one-site operator i: its table <n|O|n - q> at up[lofs[i] + n]
     int64_t D;
     int32_t N, n_chan, n_diag, n_params;
 };
@@ -121,11 +122,12 @@ struct mrmf_plan_t {
     std::vector<mrmf::DevChan> chans;
     std::vector<mrmf::DevDiag> diags;
     std::vector<int32_t> tab;
+    std::vector<int32_t> lsite, lshift, lofs;  // general one-site operators: site, shift, table offset in up
     std::vector<double> val, up;
     std::vector<mrmf_term> terms;  // input copy
     // device image
     std::vector<unsigned char> image;
-    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0;
+    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0;
     size_t ws_bytes = 0;
     mrmf::Tiling tiling;
     // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type
@@ -150,6 +152,7 @@ inline PlanArgs plan_args(const mrmf_plan_t* p, const void* d_ws) {
     a.diag = reinterpret_cast<const DevDiag*>(b + p->off_diag);
     a.val = reinterpret_cast<const double*>(b + p->off_val);
     a.up = reinterpret_cast<const double*>(b + p->off_up);
+    a.lofs = reinterpret_cast<const int32_t*>(b + p->off_lofs);
     a.D = p->D;
     a.N = p->N;
     a.n_chan = static_cast<int32_t>(p->chans.size());

@@ -18,7 +18,7 @@ using mrmf::DevSite;
 
 namespace {
 
-int shift_of(int op) {
+int builtin_shift(int op) {
     switch (op) {
         case MRMF_OP_RAISE: return 1;
         case MRMF_OP_LOWER: return -1;
@@ -27,44 +27,62 @@ int shift_of(int op) {
         default: return 0;
     }
 }
-int adjoint_op(int op) {
-    switch (op) {
-        case MRMF_OP_RAISE: return MRMF_OP_LOWER;
-        case MRMF_OP_LOWER: return MRMF_OP_RAISE;
-        case MRMF_OP_RAISE2: return MRMF_OP_LOWER2;
-        case MRMF_OP_LOWER2: return MRMF_OP_RAISE2;
-        default: return op;
-    }
+
+// Digit shift q of an operator: <n|O|n'> is nonzero only for n - n' = q.
+int shift_of(const mrmf_plan_t* p, int op) {
+    return op >= MRMF_OP_LOCAL_BASE ? p->lshift[op - MRMF_OP_LOCAL_BASE] : builtin_shift(op);
 }
 
-// Hermiticity of every parameter group h_p (Sec. IV.A: h_- = conj(h_+); Eq. pairham:
-// conj(J^{ab}) = J^{bar a bar b}).  Terms are keyed by their operator with the two sites in
-// ascending order (operators on different sites commute).
-bool groups_hermitian(const std::vector<mrmf_term>& terms, int32_t n_params) {
-    using Key = std::tuple<int, int, int, int>;
-    std::vector<std::map<Key, std::complex<double>>> groups(n_params);
-    std::vector<double> scale(n_params, 0.0);
-    for (const auto& t : terms) {
-        Key k;
-        if (t.site_b < 0)
-            k = Key(t.site_a, t.op_a, -1, 0);
-        else if (t.site_a < t.site_b)
-            k = Key(t.site_a, t.op_a, t.site_b, t.op_b);
-        else
-            k = Key(t.site_b, t.op_b, t.site_a, t.op_a);
-        std::complex<double> w(t.w_re, t.w_im);
-        groups[t.param][k] += w;
-        scale[t.param] = std::max(scale[t.param], std::abs(w));
+// Hermiticity of every parameter group h_p = sum_{param_t = p} w_t O_a O_b (Sec. IV.A: h_- = conj(h_+);
+// Eq. pairham: conj(J^{ab}) = J^{bar a bar b}), checked numerically: a group's terms are summed band by
+// band, a band being (site a, shift q_a, site b, shift q_b) with the two sites in ascending order (operators
+// on different sites commute), into the coefficient matrix M[n_a][n_b] of its target digits; the adjoint
+// band (q -> -q) must carry M'[n_a - q_a][n_b - q_b] = conj(M[n_a][n_b]).
+bool groups_hermitian(const mrmf_plan_t* p) {
+    using Band = std::tuple<int, int, int, int>;
+    std::vector<std::map<Band, std::vector<std::complex<double>>>> groups(p->n_params);
+    std::vector<double> scale(p->n_params, 0.0);
+    for (const auto& t : p->terms) {
+        int sa = t.site_a, oa = t.op_a, sb = t.site_b, ob = t.site_b >= 0 ? t.op_b : MRMF_OP_Z;
+        if (sb >= 0 && sb < sa) {
+            std::swap(sa, sb);
+            std::swap(oa, ob);
+        }
+        const int da = p->d[sa], db = sb >= 0 ? p->d[sb] : 1;
+        const Band key(sa, shift_of(p, oa), sb, sb >= 0 ? shift_of(p, ob) : 0);
+        auto& M = groups[t.param][key];
+        if (M.empty()) M.assign(size_t(da) * db, 0.0);
+        const std::complex<double> w(t.w_re, t.w_im);
+        for (int na = 0; na < da; ++na) {
+            const double fa = mrmf::local_factor_host(p, sa, oa, na);
+            if (fa == 0.0) continue;
+            for (int nb = 0; nb < db; ++nb) {
+                const double fb = sb >= 0 ? mrmf::local_factor_host(p, sb, ob, nb) : 1.0;
+                M[size_t(na) * db + nb] += w * fa * fb;
+            }
+        }
     }
-    for (int p = 0; p < n_params; ++p) {
-        const double tol = 1e-13 * std::max(1.0, scale[p]);
-        for (const auto& kv : groups[p]) {
-            const Key& k = kv.first;
-            Key a(std::get<0>(k), adjoint_op(std::get<1>(k)), std::get<2>(k),
-                  std::get<2>(k) < 0 ? 0 : adjoint_op(std::get<3>(k)));
-            auto it = groups[p].find(a);
-            std::complex<double> wa = it == groups[p].end() ? 0.0 : it->second;
-            if (std::abs(kv.second - std::conj(wa)) > tol) return false;
+    for (int g = 0; g < p->n_params; ++g)
+        for (const auto& kv : groups[g])
+            for (const auto& v : kv.second) scale[g] = std::max(scale[g], std::abs(v));
+    for (int g = 0; g < p->n_params; ++g) {
+        const double tol = 1e-12 * std::max(1.0, scale[g]);
+        for (const auto& kv : groups[g]) {
+            const int sa = std::get<0>(kv.first), qa = std::get<1>(kv.first);
+            const int sb = std::get<2>(kv.first), qb = std::get<3>(kv.first);
+            const int da = p->d[sa], db = sb >= 0 ? p->d[sb] : 1;
+            auto it = groups[g].find(Band(sa, -qa, sb, -qb));
+            for (int na = 0; na < da; ++na)
+                for (int nb = 0; nb < db; ++nb) {
+                    const std::complex<double> v = kv.second[size_t(na) * db + nb];
+                    const int ma = na - qa, mb = nb - qb;
+                    std::complex<double> u = 0.0;
+                    if (ma >= 0 && ma < da && mb >= 0 && mb < db && it != groups[g].end())
+                        u = it->second[size_t(ma) * db + mb];
+                    else if (v == 0.0)
+                        continue;
+                    if (std::abs(v - std::conj(u)) > tol) return false;
+                }
         }
     }
     return true;
@@ -86,7 +104,11 @@ double local_factor_host(const mrmf_plan_t* p, int site, int op, int n) {
         case MRMF_OP_RAISE: return n >= 1 ? up[n] : 0.0;
         case MRMF_OP_LOWER: return n <= d - 2 ? up[n + 1] : 0.0;
         case MRMF_OP_RAISE2: return n >= 2 ? up[n] * up[n - 1] : 0.0;
-        default: return n <= d - 3 ? up[n + 1] * up[n + 2] : 0.0;
+        case MRMF_OP_LOWER2: return n <= d - 3 ? up[n + 1] * up[n + 2] : 0.0;
+        default: {  // general one-site operator: its table is zero where the source is out of range
+            const int i = op - MRMF_OP_LOCAL_BASE;
+            return p->up[p->lofs[i] + n];
+        }
     }
 }
 
@@ -112,10 +134,17 @@ int32_t mrmf_version(void) { return 10000; }
 mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_terms,
                              const mrmf_term* terms, int32_t n_params, uint32_t flags,
                              mrmf_plan* out) {
+    return mrmf_plan_create_ex(n_sites, sites, n_terms, terms, n_params, flags, 0, nullptr, out);
+}
+
+mrmf_status mrmf_plan_create_ex(int32_t n_sites, const mrmf_site* sites, int32_t n_terms,
+                                const mrmf_term* terms, int32_t n_params, uint32_t flags, int32_t n_local,
+                                const mrmf_local_op* local, mrmf_plan* out) {
     if (!out) return MRMF_E_INVALID_ARG;
     *out = nullptr;
     if (n_sites < 1 || n_sites > mrmf::kMaxSites || !sites) return MRMF_E_INVALID_ARG;
     if (n_terms < 0 || (n_terms > 0 && !terms) || n_params < 0) return MRMF_E_INVALID_ARG;
+    if (n_local < 0 || n_local > 4096 || (n_local > 0 && !local)) return MRMF_E_INVALID_ARG;
     if (flags & ~MRMF_REQUIRE_HERMITIAN) return MRMF_E_INVALID_ARG;
 
     auto* p = new (std::nothrow) mrmf_plan_t();
@@ -154,27 +183,40 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
     }
     p->D = acc;
 
-    // terms
-    p->terms.assign(terms, terms + n_terms);
-    for (int t = 0; t < n_terms; ++t) {
-        const mrmf_term& x = terms[t];
-        bool ok = x.site_a >= 0 && x.site_a < n_sites && x.op_a >= MRMF_OP_Z && x.op_a <= MRMF_OP_LOWER2 &&
-                  x.param >= 0 && x.param < n_params && std::isfinite(x.w_re) && std::isfinite(x.w_im);
-        if (ok && x.site_b >= 0) {
-            ok = x.site_b < n_sites && x.site_b != x.site_a && x.op_a != MRMF_OP_Z2 && x.op_a <= MRMF_OP_LOWER &&
-                 x.op_b >= MRMF_OP_Z && x.op_b <= MRMF_OP_LOWER && x.op_b != MRMF_OP_Z2;
-        } else if (ok) {
-            ok = x.site_b == -1;
-        }
+    // general one-site operators
+    for (int i = 0; i < n_local; ++i) {
+        const mrmf_local_op& o = local[i];
+        bool ok = o.site >= 0 && o.site < n_sites && o.values != nullptr;
+        if (ok) ok = o.shift > -p->d[o.site] && o.shift < p->d[o.site];
+        for (int n = 0; ok && n < p->d[o.site]; ++n) ok = std::isfinite(o.values[n]);
         if (!ok) {
             delete p;
             return MRMF_E_INVALID_ARG;
         }
+        p->lsite.push_back(o.site);
+        p->lshift.push_back(o.shift);
     }
-    p->hermitian = groups_hermitian(p->terms, n_params);
-    if ((flags & MRMF_REQUIRE_HERMITIAN) && !p->hermitian) {
-        delete p;
-        return MRMF_E_NOT_HERMITIAN;
+    // terms: a general operator on its own site anywhere; built-in two-site factors Z, RAISE, LOWER
+    auto op_ok = [&](int op, int site, bool pair) {
+        if (op >= MRMF_OP_LOCAL_BASE) return op - MRMF_OP_LOCAL_BASE < n_local && p->lsite[op - MRMF_OP_LOCAL_BASE] == site;
+        if (op < MRMF_OP_Z || op > MRMF_OP_LOWER2) return false;
+        return !pair || op == MRMF_OP_Z || op == MRMF_OP_RAISE || op == MRMF_OP_LOWER;
+    };
+    p->terms.assign(terms, terms + n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        const mrmf_term& x = terms[t];
+        const bool pair = x.site_b >= 0;
+        bool ok = x.site_a >= 0 && x.site_a < n_sites && x.param >= 0 && x.param < n_params &&
+                  std::isfinite(x.w_re) && std::isfinite(x.w_im);
+        if (ok && pair)
+            ok = x.site_b < n_sites && x.site_b != x.site_a && op_ok(x.op_a, x.site_a, true) &&
+                 op_ok(x.op_b, x.site_b, true);
+        else if (ok)
+            ok = x.site_b == -1 && op_ok(x.op_a, x.site_a, false);
+        if (!ok) {
+            delete p;
+            return MRMF_E_INVALID_ARG;
+        }
     }
 
     // local tables: val[n] = m or n; up[n] = <n|R|n-1> = sqrt(n (d - n)) for a spin
@@ -194,10 +236,22 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
         }
     }
 
+    // general operators' tables after the sites' ones, zero where the source digit is out of range
+    for (int i = 0; i < n_local; ++i) {
+        const int d = p->d[local[i].site], q = local[i].shift;
+        p->lofs.push_back(static_cast<int32_t>(p->up.size()));
+        for (int n = 0; n < d; ++n) p->up.push_back(n - q >= 0 && n - q < d ? local[i].values[n] : 0.0);
+    }
+    p->hermitian = groups_hermitian(p);
+    if ((flags & MRMF_REQUIRE_HERMITIAN) && !p->hermitian) {
+        delete p;
+        return MRMF_E_NOT_HERMITIAN;
+    }
+
     // channels and diagonal terms
     for (int t = 0; t < n_terms; ++t) {
         const mrmf_term& x = terms[t];
-        const int qa = shift_of(x.op_a), qb = x.site_b >= 0 ? shift_of(x.op_b) : 0;
+        const int qa = shift_of(p, x.op_a), qb = x.site_b >= 0 ? shift_of(p, x.op_b) : 0;
         if (qa == 0 && qb == 0) {
             DevDiag g{};
             g.a = x.site_a;
@@ -251,6 +305,8 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
     off = align_up(off + sizeof(double) * p->val.size(), 256);
     p->off_up = off;
     off = align_up(off + sizeof(double) * p->up.size(), 256);
+    p->off_lofs = off;
+    off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, p->lofs.size()), 256);
     p->ws_bytes = off;
     p->image.assign(off, 0);
     for (int i = 0; i < n_sites; ++i) {
@@ -268,6 +324,8 @@ mrmf_status mrmf_plan_create(int32_t n_sites, const mrmf_site* sites, int32_t n_
         std::memcpy(p->image.data() + p->off_diag, p->diags.data(), sizeof(DevDiag) * p->diags.size());
     std::memcpy(p->image.data() + p->off_val, p->val.data(), sizeof(double) * p->val.size());
     std::memcpy(p->image.data() + p->off_up, p->up.data(), sizeof(double) * p->up.size());
+    if (!p->lofs.empty())
+        std::memcpy(p->image.data() + p->off_lofs, p->lofs.data(), sizeof(int32_t) * p->lofs.size());
     *out = p;
     return MRMF_OK;
 }

@@ -26,7 +26,7 @@ struct mrmf_sector_t {
     std::vector<mrmf::DevChan> chans;  // digit-sum preserving channels
     std::vector<mrmf::DevDiag> diags;
     std::vector<unsigned char> image;  // device image: sites, channels, diagonal terms, tables, rank tables
-    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_rt = 0, off_rto = 0;
+    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0, off_rt = 0, off_rto = 0;
     int32_t n_rt = 0;
     int64_t rt_max = 0;  // largest rank-table entry (32-bit LDS tables when below 2^31)
     size_t ws_bytes = 0;
@@ -53,6 +53,7 @@ SectorArgs sector_args(const mrmf_sector_t* S, const void* d_ws) {
     a.p.diag = reinterpret_cast<const DevDiag*>(b + S->off_diag);
     a.p.val = reinterpret_cast<const double*>(b + S->off_val);
     a.p.up = reinterpret_cast<const double*>(b + S->off_up);
+    a.p.lofs = reinterpret_cast<const int32_t*>(b + S->off_lofs);
     a.p.D = S->Dr;
     a.p.N = S->N;
     a.p.n_chan = static_cast<int32_t>(S->chans.size());
@@ -75,7 +76,8 @@ __device__ __forceinline__ R sfactor(const PlanArgs& p, int op, int tab, int n) 
         case MRMF_OP_RAISE: return static_cast<R>(p.up[tab + n]);
         case MRMF_OP_LOWER: return static_cast<R>(p.up[tab + n + 1]);
         case MRMF_OP_RAISE2: return static_cast<R>(p.up[tab + n] * p.up[tab + n - 1]);
-        default: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
+        case MRMF_OP_LOWER2: return static_cast<R>(p.up[tab + n + 1] * p.up[tab + n + 2]);
+        default: return static_cast<R>(p.up[p.lofs[op - MRMF_OP_LOCAL_BASE] + n]);  // general one-site operator
     }
 }
 
@@ -388,6 +390,7 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->off_diag = section(sizeof(DevDiag) * std::max<size_t>(1, S->diags.size()));
     S->off_val = section(sizeof(double) * plan->val.size());
     S->off_up = section(sizeof(double) * plan->up.size());
+    S->off_lofs = section(sizeof(int32_t) * std::max<size_t>(1, plan->lofs.size()));
     S->off_rt = section(sizeof(int64_t) * rt.size());
     S->n_rt = static_cast<int32_t>(rt.size());
     for (int64_t v : rt) S->rt_max = std::max(S->rt_max, v);
@@ -399,6 +402,8 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     if (!S->diags.empty()) std::memcpy(S->image.data() + S->off_diag, S->diags.data(), sizeof(DevDiag) * S->diags.size());
     std::memcpy(S->image.data() + S->off_val, plan->val.data(), sizeof(double) * plan->val.size());
     std::memcpy(S->image.data() + S->off_up, plan->up.data(), sizeof(double) * plan->up.size());
+    if (!plan->lofs.empty())
+        std::memcpy(S->image.data() + S->off_lofs, plan->lofs.data(), sizeof(int32_t) * plan->lofs.size());
     std::memcpy(S->image.data() + S->off_rt, rt.data(), sizeof(int64_t) * rt.size());
     std::memcpy(S->image.data() + S->off_rto, rto.data(), sizeof(int64_t) * N);
     *out = S;

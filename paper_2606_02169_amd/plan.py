@@ -39,6 +39,18 @@ def _site_array(sites):
     return arr
 
 
+def _local_array(ops):
+    """ctypes array of mrmf_local_op (and the value buffers it points into, to keep alive)."""
+    arr = (L.mrmf_local_op * max(1, len(ops)))()
+    keep = []
+    for i, o in enumerate(ops):
+        v = np.ascontiguousarray(np.asarray(o.values, dtype=np.float64))
+        keep.append(v)
+        arr[i].site, arr[i].shift = int(o.site), int(o.shift)
+        arr[i].values = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return arr, keep
+
+
 def _term_array(terms):
     arr = (L.mrmf_term * max(1, len(terms)))()
     for i, t in enumerate(terms):
@@ -57,13 +69,16 @@ class Plan:
     to a device workspace.  Couplings theta are passed per call."""
 
     def __init__(self, sites: Sequence, terms: Sequence, n_params: int, require_hermitian: bool = True,
-                 device: str | torch.device = "cuda"):
+                 device: str | torch.device = "cuda", local_ops: Sequence = ()):
         self._handle = ctypes.c_void_p()
         sa, ta = _site_array(sites), _term_array(terms)
         flags = L.MRMF_REQUIRE_HERMITIAN if require_hermitian else 0
-        L.call("mrmf_plan_create", len(sites), sa, len(terms), ta, int(n_params), flags,
+        la, keep = _local_array(local_ops)
+        L.call("mrmf_plan_create_ex", len(sites), sa, len(terms), ta, int(n_params), flags, len(local_ops), la,
                ctypes.byref(self._handle))
+        del keep
         self._sites, self._terms = list(sites), list(terms)
+        self._local = [(int(o.site), int(o.shift)) for o in local_ops]
         self.n_params = int(n_params)
         self.device = torch.device(device)
         D = ctypes.c_int64()
@@ -80,7 +95,7 @@ class Plan:
 
     @classmethod
     def from_model(cls, model, **kw) -> "Plan":
-        return cls(model.sites, model.terms, model.n_params, **kw)
+        return cls(model.sites, model.terms, model.n_params, local_ops=getattr(model, "local_ops", ()), **kw)
 
     @property
     def handle(self):
@@ -242,7 +257,7 @@ class Plan:
             if y.numel() < 2 * self.D:
                 raise ValueError("y must hold 2 D elements for the Chebyshev-step kernel")
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
-        key = tuning.signature(self._sites, self._terms, dt, arch)
+        key = tuning.signature(self._sites, self._terms, dt, arch, self._local)
         ent = tuning.lookup(key) if use_cache else None
         if ent is None:
             y = torch.empty_like(x) if y is None else y

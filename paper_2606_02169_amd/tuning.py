@@ -22,10 +22,13 @@ def cache_path() -> str:
                                                               "tuning.json")
 
 
-def signature(sites, terms, dtype_code: int, arch: str) -> str:
+def signature(sites, terms, dtype_code: int, arch: str, local_ops=()) -> str:
     """Key of a plan structure: site kinds and dimensions, each term's sites and operators (couplings and
-    weights do not change the kernel's shape), the element type and the architecture."""
+    weights do not change the kernel's shape), the (site, shift) of general one-site operators, the
+    element type and the architecture."""
     parts = [arch, str(int(dtype_code))]
+    for site, shift in local_ops:
+        parts.append(f"l{int(site)}:{int(shift)}")
     for s in sites:
         kind, k = (s.kind, s.k) if hasattr(s, "kind") else s
         parts.append(f"s{int(kind)}:{int(k)}")

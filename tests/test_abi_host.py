@@ -205,3 +205,54 @@ def test_sector_dimensions_and_errors():
         assert L.lib().mrmf_sector_create(h, qmax + 1, ctypes.byref(sec)) == L.MRMF_E_INVALID_ARG
         assert L.lib().mrmf_sector_create(h, -1, ctypes.byref(sec)) == L.MRMF_E_INVALID_ARG
         L.lib().mrmf_plan_destroy(h)
+
+
+# ------------------------------------------------------------------ general one-site operators
+def test_general_operator_validation_and_hermiticity():
+    from workloads.model import LocalOp
+    s1 = spin_site(2)
+    up = LocalOp(0, 1, (0.0, 1.2, 0.7))
+    dn = W.adjoint_op(up)
+    G = W.OP_LOCAL_BASE
+    # a Hermitian pair, alone and against a built-in operator on another site
+    ok = Model([s1, s1], [Term(0, G, -1, OP_Z, 0, 0.5), Term(0, G + 1, -1, OP_Z, 0, 0.5),
+                          Term(0, G, 1, OP_LOWER, 0, 0.3j), Term(0, G + 1, 1, OP_RAISE, 0, -0.3j)], np.ones(1),
+               local_ops=[up, dn])
+    assert host_plan(ok)[0] == 0
+    # the adjoint missing, or with a different table
+    lone = Model([s1, s1], [Term(0, G, -1, OP_Z, 0, 0.5)], np.ones(1), local_ops=[up, dn])
+    assert host_plan(lone)[0] == L.MRMF_E_NOT_HERMITIAN
+    off = LocalOp(0, -1, (1.2, 0.71, 0.0))
+    bad = Model([s1], [Term(0, G, -1, OP_Z, 0, 0.5), Term(0, G + 1, -1, OP_Z, 0, 0.5)], np.ones(1),
+                local_ops=[up, off])
+    assert host_plan(bad)[0] == L.MRMF_E_NOT_HERMITIAN
+    # Z S_+ is one band; its adjoint S_- Z written from the other side's matrix product also passes
+    z, p, m = W.spin_matrices(2)
+    zp, mz = W.band_op(0, z @ p), W.band_op(0, m @ z)
+    assert host_plan(Model([s1], [Term(0, G, -1, OP_Z, 0, 1.0), Term(0, G + 1, -1, OP_Z, 0, 1.0)], np.ones(1),
+                           local_ops=[zp, mz]))[0] == 0
+    # an operator on another site than its term, an index past the list, a shift out of range
+    assert host_plan(Model([s1, s1], [Term(1, G, -1, OP_Z)], np.ones(1), local_ops=[up, dn]),
+                     require_hermitian=False)[0] == L.MRMF_E_INVALID_ARG
+    assert host_plan(Model([s1], [Term(0, G + 2, -1, OP_Z)], np.ones(1), local_ops=[up, dn]),
+                     require_hermitian=False)[0] == L.MRMF_E_INVALID_ARG
+    assert host_plan(Model([s1], [Term(0, G, -1, OP_Z)], np.ones(1), local_ops=[LocalOp(0, 3, (1.0, 1.0, 1.0))]),
+                     require_hermitian=False)[0] == L.MRMF_E_INVALID_ARG
+    # channel offsets of general operators: Delta = q_a M_a + q_b M_b
+    g = W.random_general_model(np.random.default_rng(4), n_sites=4, max_dim=2000)
+    st, h = host_plan(g)
+    assert st == 0
+    n = ctypes.c_int32()
+    L.call("mrmf_plan_n_offdiag", h, ctypes.byref(n))
+    terms = (ctypes.c_int32 * max(1, n.value))()
+    L.call("mrmf_plan_offdiag_terms", h, terms)
+    offs = (ctypes.c_int64 * max(1, n.value))()
+    L.call("mrmf_plan_offsets", h, offs)
+    M = [int(np.prod([s.d for s in g.sites[k + 1:]])) for k in range(len(g.sites))]
+    shift = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}
+    sh = lambda op: g.local_ops[op - W.OP_LOCAL_BASE].shift if op >= W.OP_LOCAL_BASE else shift[op]
+    for c in range(n.value):
+        t = g.terms[terms[c]]
+        want = sh(t.op_a) * M[t.site_a] + (sh(t.op_b) * M[t.site_b] if t.site_b >= 0 else 0)
+        assert offs[c] == want
+    L.lib().mrmf_plan_destroy(h)

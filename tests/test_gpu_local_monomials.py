@@ -120,3 +120,69 @@ def test_squeezed_oscillator_lanczos():
     p = Plan.from_model(m)
     r = p.lanczos(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), 80)["result"].cpu().numpy()
     assert abs(r[0] - (np.sqrt(w * w - g * g) / 2 - w / 2)) <= 1e-10
+
+
+# ------------------------------------------------------------------ general one-site operators
+@pytest.mark.parametrize("seed", range(6))
+def test_general_operators_random(seed):
+    """Random general one-site operators (any band; alone, with built-in operators, or paired): generic and
+    specialized kernels in both forms and element types, the adjoint, and the digit-sum sector."""
+    from paper_2606_02169_amd.plan import Plan, Sector
+    from oracle import sector as osec
+    rng = np.random.default_rng(7300 + seed)
+    m = W.random_general_model(rng, n_sites=int(rng.integers(3, 7)), max_dim=30000, n_params=3)
+    x = W.random_state(m.dim, rng)
+    ref = mf.matvec(m, x)
+    print(f"seed={seed} D={m.dim} terms={len(m.terms)} ops={len(m.local_ops)}", flush=True)
+    for kind, var in (("generic", 0), ("specialized", 0), ("specialized", 1)):
+        p = Plan.from_model(m)
+        p.set_kernel(kind)
+        if kind == "specialized":
+            p.set_tuning(variant=var)
+        assert rel_err(run(p, m.theta, x), ref) <= TOL_Z, (kind, var)
+        x32 = x.astype(np.complex64)
+        assert rel_err(run(p, m.theta, x32), mf.matvec(m, x32.astype(np.complex128))) <= TOL_C
+    p = Plan.from_model(m)
+    g = W.random_state(m.dim, rng)
+    gx, gt = p.adjoint(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), torch.from_numpy(g).to(DEV))
+    rgx, rgt = ograd.adjoint(m, x, g)
+    assert rel_err(gx.cpu().numpy(), rgx) <= 1e-12
+    assert np.max(np.abs(gt.cpu().numpy() - rgt)) <= 1e-12 * max(1.0, np.max(np.abs(rgt)))
+    Q = sum(s.d - 1 for s in m.sites) // 2
+    S = Sector(p, Q)
+    xs = W.random_state(S.dim, rng)
+    ys = S.matvec(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(xs).to(DEV)).cpu().numpy()
+    assert rel_err(ys, osec.matvec(m, Q, xs)) <= TOL_Z
+
+
+def test_general_operators_batch():
+    from paper_2606_02169_amd.plan import Batch, Plan
+    rng = np.random.default_rng(7400)
+    models = [W.random_general_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=4000, n_params=2, n_ops=3,
+                                     n_terms=6) for _ in range(5)]
+    models.append(W.bilinear_biquadratic_chain(6, 1 / 3))
+    B = Batch([Plan.from_model(mm) for mm in models], 2)
+    X = torch.zeros(B.total_elems, dtype=torch.complex64, device=DEV)
+    xs = [W.random_state(mm.dim, rng, np.complex64, nvec=2) for mm in models]
+    for b, xv in enumerate(xs):
+        B.block(X, b).copy_(torch.from_numpy(xv).to(DEV))
+    th = torch.from_numpy(np.concatenate([mm.theta for mm in models]).astype(np.float32)).to(DEV)
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    for b, (mm, xv) in enumerate(zip(models, xs)):
+        yb = B.block(Y, b).cpu().numpy()
+        for v in range(2):
+            ref = mf.matvec(mm, xv[:, v].astype(np.complex128), theta=mm.theta.astype(np.float32).astype(np.float64))
+            assert rel_err(yb[:, v], ref) <= TOL_C, (b, v)
+
+
+@pytest.mark.parametrize("N", [10, 14])
+def test_aklt_lanczos(N):
+    """Lanczos on the periodic AKLT chain (D = 3^N): ground energy -2N/3, the valence-bond solid."""
+    from paper_2606_02169_amd.plan import Plan
+    m = W.bilinear_biquadratic_chain(N, 1 / 3)
+    x = W.random_state(m.dim, np.random.default_rng(N))
+    p = Plan.from_model(m)
+    r = p.lanczos(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), 80)["result"].cpu().numpy()
+    print(N, r, flush=True)
+    assert abs(r[0] + 2 * N / 3) <= 1e-9 and r[2] <= 1e-5

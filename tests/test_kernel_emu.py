@@ -132,3 +132,28 @@ def test_chebyshev_step_epilogue(variant, addressing):
     want_p = ea * hx + eb * x + eg * prev
     assert rel_err(p2, want_p) <= 1e-12
     assert rel_err(a2, acc + c * want_p) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_general_operators(seed):
+    """Random general one-site operators (any band, alone, with built-in operators or paired), both
+    forms, several tilings, on the emulated blocks."""
+    rng = np.random.default_rng(400 + seed)
+    m = W.random_general_model(rng, n_sites=int(rng.integers(3, 7)), max_dim=6000, n_params=2)
+    x = W.random_state(m.dim, rng)
+    ref = mf.matvec(m, x)
+    for inner, unrolled, var in ((0, -1, 0), (1, 1, 0), (2, 0, 1), (1, 2, 1)):
+        try:
+            y = E.run(m, x, inner=inner, unrolled=unrolled, tuning={"variant": var}, grid=32, blocks=(0, 6))
+        except ValueError:
+            continue
+        done = ~np.isnan(y.real)
+        assert done.any()
+        assert rel_err(y[done], ref[done]) <= TOL_Z, (inner, unrolled, var)
+
+
+def test_aklt_chain_emulated():
+    m = W.bilinear_biquadratic_chain(7, 1 / 3)
+    x = W.random_state(m.dim, np.random.default_rng(5))
+    check(m, x, tuning={"variant": 1})
+    check(m, x.astype(np.complex64), unrolled=1)

@@ -375,3 +375,14 @@ def test_general_operator_tables_against_products():
         H = kron.dense_H(g)
         assert np.allclose(H, H.conj().T, atol=1e-14)
         assert np.linalg.norm(mf.matvec(g, x) - H @ x) <= 1e-13 * np.linalg.norm(H @ x)
+
+
+def test_adjoint_model_with_general_operators():
+    """The oracle's adjoint term list (transposed bands for general operators) applies H^dagger of the
+    Kronecker definition on non-Hermitian random general models."""
+    rng = np.random.default_rng(23)
+    for _ in range(4):
+        m = W.random_general_model(rng, n_sites=4, max_dim=800, hermitian=False)
+        g = W.random_state(m.dim, rng)
+        H = kron.dense_H(m)
+        assert np.linalg.norm(mf.matvec(mf.adjoint_model(m), g) - H.conj().T @ g) <= 1e-13 * np.linalg.norm(H @ g)
