@@ -410,17 +410,18 @@ def bench_propagate(args, dev):
     p.autotune(th, xt)
     tuned_cheb = p.autotune(th, xt, kernel="cheb")
     stream = torch.cuda.current_stream(dev)
-    dt, steps = 0.05, 4
+    dt, steps = 0.05, (2 if args.profile else 4)
     bnd = p.norm_bound(model.theta)
     bounds = (-bnd, bnd)
     r = p.propagate(th, xt, dt, 1, bounds=bounds)
     nt = r["n_terms"]
     out = torch.empty_like(xt)
-    ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, 3) / steps
+    reps = 1 if args.profile else 3
+    ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
     y = torch.empty_like(xt)
-    ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 20)
+    ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 3 if args.profile else 20)
     p.set_tuning(cheb_fused=0)
-    ms_two = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, 3) / steps
+    ms_two = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
     p.set_tuning(cheb_fused=1)
     back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
     res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
@@ -449,8 +450,9 @@ def bench_sector(args, dev):
 
     out = {"metric": "sector H·x (P H P^T) matvecs/s and sector Lanczos", "cases": {}}
     stream = torch.cuda.current_stream(dev)
-    for name, model in (("ferrimagnetic_ring_N20_Sz0", W.config(2, with_state=False)[0]),
-                        ("spin1_ring_N15_Sz0", W.paper_c1())):
+    cases = (("ferrimagnetic_ring_N20_Sz0", W.config(2, with_state=False)[0]),
+             ("spin1_ring_N15_Sz0", W.paper_c1()))
+    for name, model in cases[:1] if args.profile else cases:
         plan = Plan.from_model(model, device=dev)
         Q = Sector.digit_sum_of(model.sites, 0.0)
         S = Sector(plan, Q)
@@ -461,7 +463,10 @@ def bench_sector(args, dev):
         y = torch.empty_like(xt)
         for _ in range(3):
             S.matvec(th, xt, out=y)
-        ms = cuda_time(lambda: S.matvec(th, xt, out=y), stream, 20)
+        ms = cuda_time(lambda: S.matvec(th, xt, out=y), stream, 5 if args.profile else 20)
+        if args.profile:
+            out["cases"][name] = {"D_sector": S.dim, "sector_matvec_ms": ms}
+            continue
         lab = osec.labels(model, Q)
         rows = np.unique(rng.choice(S.dim, 2000, replace=False)).astype(np.int64)
         err = float(np.linalg.norm(y[torch.from_numpy(rows).to(dev)].cpu().numpy()

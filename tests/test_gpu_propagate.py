@@ -139,3 +139,14 @@ def test_propagate_errors():
                                    ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(small.data_ptr()), small.numel(),
                                    None, None)
     assert st == L.MRMF_E_WORKSPACE
+
+
+def test_propagate_zero_steps_and_zero_time():
+    m = W.xx_chain_in_field(6, 1.0, 0.3)
+    x0 = W.random_state(m.dim, np.random.default_rng(2))
+    p = mk(m)
+    r = p.propagate(t(m.theta), t(x0), 0.3, 0)
+    assert np.array_equal(r["x"].cpu().numpy(), x0)                 # zero steps: a copy
+    r = p.propagate(t(m.theta), t(x0), 0.0, 3, bounds=(-5.0, 5.0))
+    assert r["n_terms"] == 1
+    assert np.array_equal(r["x"].cpu().numpy(), x0)                 # dt = 0: the identity, exactly

@@ -118,3 +118,29 @@ def test_ring20_sz0_sector_sampled():
     assert np.array_equal(S.labels().cpu().numpy()[rows], lab[rows])
     got = y[t(rows)].cpu().numpy()
     assert rel_err(got, osec.matvec(m, Q, x, lab=lab, rows=rows)) <= TOL_Z
+
+
+def test_sector_edge_cases():
+    """The two one-state sectors (all digits 0, all digits maximal), a sector of a one-site lattice, and
+    argument errors."""
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m, _ = W.config(2, reduced=8)
+    qmax = sum(s.d - 1 for s in m.sites)
+    plan = Plan.from_model(m)
+    for Q in (0, qmax):
+        S = Sector(plan, Q)
+        assert S.dim == 1
+        lab = osec.labels(m, Q)
+        assert S.labels().cpu().tolist() == lab.tolist()
+        x = np.array([0.3 - 0.4j])
+        y = S.matvec(t(m.theta), t(x)).cpu().numpy()
+        assert rel_err(y, osec.matvec(m, Q, x, lab=lab)) <= TOL_Z
+    one = W.Model([W.spin_site(3)], [W.Term(0, W.OP_Z, -1, W.OP_Z, 0, 1.0)], np.array([0.7]))
+    S1 = Sector(Plan.from_model(one), 2)
+    assert S1.dim == 1 and S1.labels().cpu().tolist() == [2]
+    from paper_2606_02169_amd import _lib as L
+    with pytest.raises(L.MrmfError):
+        Sector(plan, qmax + 1)
+    S = Sector(plan, qmax // 2)
+    with pytest.raises(ValueError):
+        S.matvec(t(m.theta), t(np.zeros(S.dim + 1, dtype=np.complex128)))
