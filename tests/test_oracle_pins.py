@@ -386,3 +386,31 @@ def test_adjoint_model_with_general_operators():
         g = W.random_state(m.dim, rng)
         H = kron.dense_H(m)
         assert np.linalg.norm(mf.matvec(mf.adjoint_model(m), g) - H.conj().T @ g) <= 1e-13 * np.linalg.norm(H @ g)
+
+
+def test_truncated_spin_local_sets():
+    """A spin chain whose sites keep only some levels (Sec. VI case 1) through general operators on
+    d-level sites is the full Hamiltonian projected onto the kept levels (P H P^T with the product
+    projector), and keeping every level gives the full spin back."""
+    two_s, N, J, h = 3, 3, 0.9, 0.35
+
+    def model(levels, first):
+        ops, terms = [], []
+        for i in range(N):
+            base = W.OP_LOCAL_BASE + len(ops)
+            ops += W.truncated_spin_ops(i, two_s, levels, first)
+            terms.append(Term(i, base, -1, OP_Z, 1, 1.0))                       # h S_z
+        for i in range(N - 1):
+            zi, pi_, mi = (W.OP_LOCAL_BASE + 3 * i + k for k in range(3))
+            zj, pj, mj = (W.OP_LOCAL_BASE + 3 * (i + 1) + k for k in range(3))
+            terms += [Term(i, pi_, i + 1, mj, 0, 0.5), Term(i, mi, i + 1, pj, 0, 0.5), Term(i, zi, i + 1, zj, 0, 1.0)]
+        return Model([W.boson_site(levels - 1)] * N, terms, np.array([J, h]), local_ops=ops)
+
+    full = Model([spin_site(two_s)] * N, [Term(i, OP_Z, -1, OP_Z, 1, 1.0) for i in range(N)]
+                 + [t for i in range(N - 1) for t in W.xxz_bond_terms(i, i + 1, 0, 0)], np.array([J, h]))
+    Hf = kron.dense_H(full)
+    assert np.allclose(dense_from_mf(model(two_s + 1, 0)), Hf, atol=1e-14)
+    for levels, first in ((2, 0), (3, 1)):
+        keep = np.arange(first, first + levels)
+        idx = np.ravel_multi_index(np.meshgrid(*([keep] * N), indexing="ij"), [two_s + 1] * N).ravel()
+        assert np.allclose(dense_from_mf(model(levels, first)), Hf[np.ix_(idx, idx)], atol=1e-14)

@@ -12,7 +12,7 @@ from .configs import (heisenberg_chain, ferrimagnetic_ring, square_lattice_spin1
                       tavis_cummings, random_model, xx_chain_in_field, random_state, config,
                       staggered_xxz_ring, paper_c1, paper_c2, zero_field_splitting,
                       spin_matrices, band_op, bilinear_biquadratic_chain, adjoint_op,
-                      random_general_model)
+                      random_general_model, truncated_spin_ops)
 
 __all__ = [
     "SPIN", "BOSON", "OP_Z", "OP_Z2", "OP_RAISE", "OP_LOWER", "OP_RAISE2", "OP_LOWER2", "OP_LOCAL_BASE", "LocalOp", "Site", "Term",
@@ -21,4 +21,5 @@ __all__ = [
     "square_lattice_spin1", "batched_chains", "tavis_cummings", "random_model", "xx_chain_in_field",
     "random_state", "config", "staggered_xxz_ring", "paper_c1", "paper_c2", "zero_field_splitting",
     "spin_matrices", "band_op", "bilinear_biquadratic_chain", "adjoint_op", "random_general_model",
+    "truncated_spin_ops",
 ]

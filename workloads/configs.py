@@ -220,6 +220,15 @@ def bilinear_biquadratic_chain(N: int, beta: float, periodic: bool = True, two_s
                  local_ops=ops)
 
 
+def truncated_spin_ops(site: int, two_s: int, levels: int, first: int = 0) -> List[LocalOp]:
+    """S_z, S_+, S_- of a spin s restricted to `levels` consecutive levels m = -s + first .. (a reduced
+    local set, Sec. VI case 1: the site is declared with d = levels, e.g. boson_site(levels - 1), and only
+    these general operators act on it)."""
+    z, p, m = spin_matrices(two_s)
+    sl = slice(first, first + levels)
+    return [band_op(site, z[sl, sl]), band_op(site, p[sl, sl]), band_op(site, m[sl, sl])]
+
+
 def adjoint_op(op: LocalOp) -> LocalOp:
     """O^dagger of a real one-band operator: shift -q, <n|O^dag|n + q> = <n + q|O|n>."""
     d = len(op.values)
