@@ -153,6 +153,16 @@ def bench_ring(args, dev):
     log(f"timed {K} steps: {ms_per_step:.4f} ms/step, launch mean {mean_launch_ms:.4f} ms "
         f"(min {min(launch_ms):.4f}, max {max(launch_ms):.4f})")
 
+    # the stream ceiling of this GPU for the same bytes: a plain device copy of x into y (read D x 16 B,
+    # write D x 16 B), timed the same way after the matvec loop
+    if not args.profile:
+        for _ in range(2):
+            y.copy_(x)
+        copy_ms = cuda_time(lambda: y.copy_(x), stream, 10)
+        copy_GBps = alg_bytes / (copy_ms * 1e-3) / 1e9
+    else:
+        copy_GBps = None
+
     traffic = None
     fp = kernel_fingerprint(plan, torch.complex128)
     if os.path.exists(TRAFFIC_FILE):
@@ -181,7 +191,8 @@ def bench_ring(args, dev):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes, "mean_launch_ms": mean_launch_ms,
-                     "kernel_fingerprint": fp},
+                     "kernel_fingerprint": fp, "copy_GBps": copy_GBps,
+                     "frac_of_copy": achieved / copy_GBps if copy_GBps else None},
     }
     if not (args.no_cpu_baseline or args.profile):
         # oracle timing and a parity check of the timed output (the oracle is a baseline only)

@@ -8,110 +8,144 @@
 // formed while gathering H g.  One pass over the rows therefore gives both:
 //     grad_x[F]       = sum_c theta_{p_c} t_c(F)                       t_c(F) = w_c f_c(F) g[F - Delta_c]
 //     grad_theta[p]  += Re conj(t_c(F)) x[F]       for every channel c of group p
-// (diagonal terms are channels with Delta = 0).  Per-parameter sums are kept per thread in LDS, summed
-// per block in a fixed order, and the block partials are summed by a second kernel in a fixed order, so
-// the result does not depend on scheduling.
+// (diagonal terms are channels with Delta = 0).  Per-parameter sums are reduced over each wave with a
+// fixed butterfly, accumulated per wave in LDS in row order, summed per block in a fixed order, and the
+// block partials are summed by a second kernel in a fixed order, so the result does not depend on
+// scheduling.
 #include "mrmf_internal.h"
 
 namespace mrmf {
 namespace {
 
-constexpr int kAdjBlock = 128;
-constexpr int kAdjParamChunk = 32;  // parameters accumulated per pass (LDS: 32 x 128 doubles)
+constexpr int kAdjBlock = 256;
+constexpr int kAdjParamChunk = 32;  // parameters accumulated per pass (LDS: 32 x 4 doubles)
 constexpr int kAdjMaxGrid = 2048;
+constexpr int kAdjRows = 4;  // rows per thread per iteration (1 when their digits would not fit in LDS)
 
-__device__ __forceinline__ double local_factor64(const PlanArgs& p, int op, int tab, int n) {
-    switch (op) {
-        case MRMF_OP_Z: return p.val[tab + n];
-        case MRMF_OP_Z2: return p.val[tab + n] * p.val[tab + n];
-        case MRMF_OP_RAISE: return p.up[tab + n];
-        case MRMF_OP_LOWER: return p.up[tab + n + 1];
-        case MRMF_OP_RAISE2: return p.up[tab + n] * p.up[tab + n - 1];
-        case MRMF_OP_LOWER2: return p.up[tab + n + 1] * p.up[tab + n + 2];
-        default: return p.up[p.lofs[op - MRMF_OP_LOCAL_BASE] + n];  // general one-site operator
-    }
-}
+constexpr int kAdjMaxLdsTable = 4096;  // doubles of per-term factor tables staged in LDS (32 KB)
 
 // floor(n / d) for n < 2^32 with magic = ceil(2^64 / d)
 __device__ __forceinline__ uint32_t div_magic32(uint32_t n, uint64_t magic) {
     return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));
 }
 
-// One pass for parameters [p0, p0 + kAdjParamChunk); the pass with p0 == 0 also writes grad_x.
-template <bool WIDE>
-__global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const double* __restrict__ theta,
+// One pass for parameters [p0, p0 + kAdjParamChunk); the pass with p0 == 0 also writes grad_x.  Every
+// lane of a wave walks the same row slots (lanes past D carry zeros), so the contributions
+// Re conj(t) x_F of each run of consecutive terms with one parameter are summed per lane, then over the
+// wave with a fixed butterfly, and added by lane 0 to the wave's accumulator in LDS: the per-parameter
+// state is one double per wave instead of one per thread, which keeps the occupancy of the gather high.
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <bool WIDE, bool LDS_TAB, int R>
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const AdjTerm* __restrict__ terms, int n_terms,
+                                                       const double* __restrict__ ftab_g, int n_ftab,
+                                                       const double* __restrict__ theta,
                                                        const double2* __restrict__ x,
                                                        const double2* __restrict__ g,
                                                        double2* __restrict__ gx, int p0,
                                                        double* __restrict__ partial) {
-    __shared__ uint8_t dig[kMaxSites][kAdjBlock];
-    __shared__ double acc[kAdjParamChunk][kAdjBlock];
-    const int tid = threadIdx.x;
-    for (int q = 0; q < kAdjParamChunk; ++q) acc[q][tid] = 0.0;
+    constexpr int kWaves = kAdjBlock / 64;
+    __shared__ double acc[kAdjParamChunk][kWaves];
+    // dynamic LDS: [factor tables when LDS_TAB][digits: N x (R * kAdjBlock) bytes]
+    extern __shared__ double ltab[];
+    uint8_t* dig_base = reinterpret_cast<uint8_t*>(ltab + (LDS_TAB ? n_ftab : 0));
+    auto dig = [&](int site, int slot) -> uint8_t& { return dig_base[site * (R * kAdjBlock) + slot]; };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < kAdjParamChunk * kWaves; i += kAdjBlock) acc[i / kWaves][i % kWaves] = 0.0;
+    const double* ftab = ftab_g;
+    if (LDS_TAB) {
+        for (int i = tid; i < n_ftab; i += kAdjBlock) ltab[i] = ftab_g[i];
+        ftab = ltab;
+    }
+    __syncthreads();
     const bool write_gx = p0 == 0;
-    const int64_t stride = int64_t(gridDim.x) * kAdjBlock;
-    for (int64_t F = int64_t(blockIdx.x) * kAdjBlock + tid; F < p.D; F += stride) {
-        if (WIDE) {
-            int64_t f = F;
-            for (int i = p.N - 1; i >= 0; --i) {  // Eq. decode, least significant site first
-                const int64_t d = p.site[i].d;
-                const int64_t q = f / d;
-                dig[i][tid] = static_cast<uint8_t>(f - q * d);
-                f = q;
+    const int64_t stride = int64_t(gridDim.x) * kAdjBlock * R;
+    // each thread carries R rows (r * kAdjBlock apart) through every term
+    for (int64_t base = int64_t(blockIdx.x) * kAdjBlock * R; base < p.D; base += stride) {
+        int64_t F[R];
+        bool act[R];
+        double2 xf[R], gf[R];
+        double hr[R], hi[R];
+        for (int r = 0; r < R; ++r) {
+            F[r] = base + r * kAdjBlock + tid;
+            act[r] = F[r] < p.D;
+            const int slot = r * kAdjBlock + tid;
+            if (act[r]) {
+                if (WIDE) {
+                    int64_t f = F[r];
+                    for (int i = p.N - 1; i >= 0; --i) {  // Eq. decode, least significant site first
+                        const int64_t d = p.site[i].d;
+                        const int64_t q = f / d;
+                        dig(i, slot) = static_cast<uint8_t>(f - q * d);
+                        f = q;
+                    }
+                } else {
+                    uint32_t f = static_cast<uint32_t>(F[r]);
+                    for (int i = p.N - 1; i >= 0; --i) {
+                        const uint32_t q = div_magic32(f, p.site[i].magic);
+                        dig(i, slot) = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
+                        f = q;
+                    }
+                }
+            } else {
+                for (int i = 0; i < p.N; ++i) dig(i, slot) = 0;
             }
-        } else {
-            uint32_t f = static_cast<uint32_t>(F);
-            for (int i = p.N - 1; i >= 0; --i) {
-                const uint32_t q = div_magic32(f, p.site[i].magic);
-                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
-                f = q;
+            xf[r] = act[r] ? x[F[r]] : make_double2(0.0, 0.0);
+            gf[r] = act[r] ? g[F[r]] : make_double2(0.0, 0.0);
+            hr[r] = 0.0;
+            hi[r] = 0.0;
+        }
+        // consecutive terms of one parameter are summed per lane first: one wave sum per run
+        double run = 0.0;
+        int run_q = -1;
+        for (int k = 0; k < n_terms; ++k) {
+            const AdjTerm T = terms[k];
+            const int q = T.param - p0;
+            const int qq = q >= 0 && q < kAdjParamChunk ? q : -1;
+            if (qq != run_q) {
+                if (run_q >= 0) {
+                    const double v = wave_sum(run);
+                    if (lane == 0) acc[run_q][wave] += v;
+                }
+                run = 0.0;
+                run_q = qq;
+            }
+            const double th = theta[T.param];
+            double fa[R];
+            double2 gs[R];
+            for (int r = 0; r < R; ++r) {  // factors (zero where a source digit is out of range), then gathers
+                const int slot = r * kAdjBlock + tid;
+                fa[r] = ftab[T.ta + dig(T.a, slot)];
+                if (T.b >= 0) fa[r] *= ftab[T.tb + dig(T.b, slot)];
+                if (T.diag)
+                    gs[r] = gf[r];
+                else
+                    gs[r] = (act[r] && fa[r] != 0.0) ? g[F[r] - T.delta] : make_double2(0.0, 0.0);  // Eq. sourceoffset
+            }
+            for (int r = 0; r < R; ++r) {
+                const double tr = fa[r] * (T.wr * gs[r].x - T.wi * gs[r].y);
+                const double ti = fa[r] * (T.wr * gs[r].y + T.wi * gs[r].x);
+                hr[r] += th * tr;
+                hi[r] += th * ti;
+                if (qq >= 0) run += tr * xf[r].x + ti * xf[r].y;
             }
         }
-        const double2 xf = x[F];
-        const double2 gf = g[F];
-        double hr = 0.0, hi = 0.0;
-        for (int k = 0; k < p.n_diag; ++k) {
-            const DevDiag dg = p.diag[k];
-            double fa = local_factor64(p, dg.opa, p.site[dg.a].tab, dig[dg.a][tid]);
-            if (dg.b >= 0) fa *= local_factor64(p, dg.opb, p.site[dg.b].tab, dig[dg.b][tid]);
-            const double tr = fa * (dg.wr * gf.x - dg.wi * gf.y);
-            const double ti = fa * (dg.wr * gf.y + dg.wi * gf.x);
-            const double th = theta[dg.param];
-            hr += th * tr;
-            hi += th * ti;
-            const int q = dg.param - p0;
-            if (q >= 0 && q < kAdjParamChunk) acc[q][tid] += tr * xf.x + ti * xf.y;
+        if (run_q >= 0) {
+            const double v = wave_sum(run);
+            if (lane == 0) acc[run_q][wave] += v;
         }
-        for (int c = 0; c < p.n_chan; ++c) {
-            const DevChan ch = p.chan[c];
-            const DevSite sa = p.site[ch.a];
-            const int na = dig[ch.a][tid];
-            if (na - ch.qa < 0 || na - ch.qa >= sa.d) continue;  // source digit admissible (Eq. src_digit)
-            double fa = local_factor64(p, ch.opa, sa.tab, na);
-            if (ch.b >= 0) {
-                const DevSite sb = p.site[ch.b];
-                const int nb = dig[ch.b][tid];
-                if (nb - ch.qb < 0 || nb - ch.qb >= sb.d) continue;
-                fa *= local_factor64(p, ch.opb, sb.tab, nb);
-            }
-            const double2 gs = g[F - ch.delta];  // Eq. sourceoffset
-            const double tr = fa * (ch.wr * gs.x - ch.wi * gs.y);
-            const double ti = fa * (ch.wr * gs.y + ch.wi * gs.x);
-            const double th = theta[ch.param];
-            hr += th * tr;
-            hi += th * ti;
-            const int q = ch.param - p0;
-            if (q >= 0 && q < kAdjParamChunk) acc[q][tid] += tr * xf.x + ti * xf.y;
-        }
-        if (write_gx) gx[F] = make_double2(hr, hi);
+        if (write_gx)
+            for (int r = 0; r < R; ++r)
+                if (act[r]) gx[F[r]] = make_double2(hr[r], hi[r]);
     }
     __syncthreads();
     const int np = p.n_params - p0 < kAdjParamChunk ? p.n_params - p0 : kAdjParamChunk;
-    if (tid < np) {
-        // thread q sums its parameter's column starting at column q (a rotation that keeps the threads
-        // on different LDS banks); the order is fixed, so the result is deterministic
+    if (tid < np) {  // fixed order over the block's waves
         double s = 0.0;
-        for (int k = 0; k < kAdjBlock; ++k) s += acc[tid][(k + tid) & (kAdjBlock - 1)];
+        for (int w = 0; w < kWaves; ++w) s += acc[tid][w];
         partial[int64_t(blockIdx.x) * p.n_params + p0 + tid] = s;
     }
 }
@@ -173,15 +207,29 @@ mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_the
     const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
     const int passes = plan->n_params > 0 ? (plan->n_params + kAdjParamChunk - 1) / kAdjParamChunk : 1;
     const bool wide = plan->D > int64_t(0xffffffffu);
+    const int n_ftab = static_cast<int>(plan->ftab.size()), n_terms = static_cast<int>(plan->adj.size());
+    const bool lds_tab = n_ftab <= kAdjMaxLdsTable;
+    const size_t tab_bytes = lds_tab ? sizeof(double) * n_ftab : 0;
+    // several rows per thread only when the grid stays full (small lattices need every wave they can get)
+    const int rows = tab_bytes + size_t(plan->N) * kAdjRows * kAdjBlock <= 60000 &&
+                             plan->D >= int64_t(kAdjMaxGrid) * kAdjBlock * kAdjRows
+                         ? kAdjRows
+                         : 1;
+    using K = void (*)(PlanArgs, const AdjTerm*, int, const double*, int, const double*, const double2*,
+                       const double2*, double2*, int, double*);
+    const K kern = rows == kAdjRows
+                       ? (wide ? (lds_tab ? k_adjoint<true, true, kAdjRows> : k_adjoint<true, false, kAdjRows>)
+                               : (lds_tab ? k_adjoint<false, true, kAdjRows> : k_adjoint<false, false, kAdjRows>))
+                       : (wide ? (lds_tab ? k_adjoint<true, true, 1> : k_adjoint<true, false, 1>)
+                               : (lds_tab ? k_adjoint<false, true, 1> : k_adjoint<false, false, 1>));
+    const unsigned char* wsb = static_cast<const unsigned char*>(d_ws);
+    const AdjTerm* terms = reinterpret_cast<const AdjTerm*>(wsb + plan->off_adj);
+    const double* ftab = reinterpret_cast<const double*>(wsb + plan->off_ftab);
     for (int k = 0; k < passes; ++k) {
-        if (wide)
-            hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(kAdjBlock), 0, s, a, theta,
-                               static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
-                               static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
-        else
-            hipLaunchKernelGGL(k_adjoint<false>, dim3(grid), dim3(kAdjBlock), 0, s, a, theta,
-                               static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
-                               static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
+        const size_t lds = tab_bytes + size_t(plan->N) * rows * kAdjBlock;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kAdjBlock), lds, s, a, terms, n_terms, ftab, n_ftab, theta,
+                           static_cast<const double2*>(d_x), static_cast<const double2*>(d_g),
+                           static_cast<double2*>(d_grad_x), k * kAdjParamChunk, partial);
         const mrmf_status st = launch_status();
         if (st != MRMF_OK) return st;
     }

@@ -48,6 +48,17 @@ struct alignas(16) DevDiag {
 };
 static_assert(sizeof(DevDiag) == 48, "DevDiag layout");
 
+// One term for the adjoint kernel: sites, offsets of its factor tables (value at the target digit, zero
+// where the source digit is out of range) in the plan's factor-table array, parameter, offset, weight.
+struct alignas(16) AdjTerm {
+    int32_t a, b;    // b = -1: one-site term
+    int32_t ta, tb;  // table offsets
+    int32_t param, diag;
+    int64_t delta;
+    double wr, wi;
+};
+static_assert(sizeof(AdjTerm) == 48, "AdjTerm layout");
+
 // Per-site data: local dimension, offset of the site's local tables, multiplier M_i and the
 // reciprocal used for division by d_i of numerators below 2^32 (q = hi64(magic * n)).
 struct alignas(16) DevSite {
@@ -128,6 +139,10 @@ struct mrmf_plan_t {
     // device image
     std::vector<unsigned char> image;
     size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0;
+    // adjoint term list (diagonal terms first, then channels, input order within each) and factor tables
+    std::vector<mrmf::AdjTerm> adj;
+    std::vector<double> ftab;
+    size_t off_adj = 0, off_ftab = 0;
     size_t ws_bytes = 0;
     mrmf::Tiling tiling;
     // kernel selection (MRMF_KERNEL_*) and the specialized kernels per element type

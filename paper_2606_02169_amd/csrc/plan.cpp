@@ -307,6 +307,22 @@ mrmf_status mrmf_plan_create_ex(int32_t n_sites, const mrmf_site* sites, int32_t
     off = align_up(off + sizeof(double) * p->up.size(), 256);
     p->off_lofs = off;
     off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, p->lofs.size()), 256);
+    // adjoint term list with per-term factor tables
+    auto ftable = [&](int site, int op) {
+        const int32_t at = static_cast<int32_t>(p->ftab.size());
+        for (int n = 0; n < p->d[site]; ++n) p->ftab.push_back(mrmf::local_factor_host(p, site, op, n));
+        return at;
+    };
+    for (const auto& g : p->diags)
+        p->adj.push_back({g.a, g.b, ftable(g.a, g.opa), g.b >= 0 ? ftable(g.b, g.opb) : 0, g.param, 1, 0, g.wr, g.wi});
+    for (const auto& c : p->chans)
+        p->adj.push_back({c.a, c.b, ftable(c.a, c.opa), c.b >= 0 ? ftable(c.b, c.opb) : 0, c.param, 0, c.delta, c.wr,
+                          c.wi});
+    if (p->ftab.empty()) p->ftab.push_back(0.0);
+    p->off_adj = off;
+    off = align_up(off + sizeof(mrmf::AdjTerm) * std::max<size_t>(1, p->adj.size()), 256);
+    p->off_ftab = off;
+    off = align_up(off + sizeof(double) * p->ftab.size(), 256);
     p->ws_bytes = off;
     p->image.assign(off, 0);
     for (int i = 0; i < n_sites; ++i) {
@@ -326,6 +342,9 @@ mrmf_status mrmf_plan_create_ex(int32_t n_sites, const mrmf_site* sites, int32_t
     std::memcpy(p->image.data() + p->off_up, p->up.data(), sizeof(double) * p->up.size());
     if (!p->lofs.empty())
         std::memcpy(p->image.data() + p->off_lofs, p->lofs.data(), sizeof(int32_t) * p->lofs.size());
+    if (!p->adj.empty())
+        std::memcpy(p->image.data() + p->off_adj, p->adj.data(), sizeof(mrmf::AdjTerm) * p->adj.size());
+    std::memcpy(p->image.data() + p->off_ftab, p->ftab.data(), sizeof(double) * p->ftab.size());
     *out = p;
     return MRMF_OK;
 }
