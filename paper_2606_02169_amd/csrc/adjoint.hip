@@ -34,9 +34,27 @@ __device__ __forceinline__ uint32_t div_magic32(uint32_t n, uint64_t magic) {
 // Re conj(t) x_F of each run of consecutive terms with one parameter are summed per lane, then over the
 // wave with a fixed butterfly, and added by lane 0 to the wave's accumulator in LDS: the per-parameter
 // state is one double per wave instead of one per thread, which keeps the occupancy of the gather high.
+// v moved across lanes by one DPP pattern (rows outside row_mask contribute 0), one 32-bit half at a time
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u)), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u >> 32)), CTRL, ROW_MASK, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint64_t>(static_cast<uint32_t>(lo)));
+}
+
+// Sum over the 64 lanes of a wave with a fixed pattern of DPP moves (lane pairs 1 and 2 apart, the half
+// and full row mirrors, then the row broadcasts of lanes 15 and 31); the total ends in lane 63.
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_move<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xf>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xf>(v);  // row_mirror: every lane holds its row's sum
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;                      // lane 63: the wave's sum
 }
 
 template <bool WIDE, bool LDS_TAB, int R>
@@ -108,7 +126,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const AdjTerm
             if (qq != run_q) {
                 if (run_q >= 0) {
                     const double v = wave_sum(run);
-                    if (lane == 0) acc[run_q][wave] += v;
+                    if (lane == 63) acc[run_q][wave] += v;
                 }
                 run = 0.0;
                 run_q = qq;
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(PlanArgs p, const AdjTerm
         }
         if (run_q >= 0) {
             const double v = wave_sum(run);
-            if (lane == 0) acc[run_q][wave] += v;
+            if (lane == 63) acc[run_q][wave] += v;
         }
         if (write_gx)
             for (int r = 0; r < R; ++r)
