@@ -176,7 +176,9 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                             below 2^31 bytes, else the plan keeps the generic kernel.
  *   MRMF_TUNE_CHEB_FUSED    : 1 = mrmf_propagate_z runs each Chebyshev term as one launch of the
  *                             specialized kernel with the Chebyshev-step epilogue (default); 0 = a matvec
- *                             and a separate vector update per term. */
+ *                             and a separate vector update per term.
+ *   MRMF_TUNE_WAVES_PER_EU  : 0 = the compiler's register allocation (default); 1..8 = ask for at least
+ *                             that many resident waves per SIMD (a register budget; may spill). */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
@@ -184,6 +186,7 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_TUNE_VARIANT 4
 #define MRMF_TUNE_ADDRESSING 5
 #define MRMF_TUNE_CHEB_FUSED 6
+#define MRMF_TUNE_WAVES_PER_EU 7
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0

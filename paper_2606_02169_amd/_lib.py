@@ -28,6 +28,7 @@ MRMF_TUNE_SCHEDULE, MRMF_TUNE_BRANCH_SKIP, MRMF_TUNE_LOAD_GROUP, MRMF_TUNE_BLOCK
 MRMF_TUNE_VARIANT, MRMF_VARIANT_MASKED, MRMF_VARIANT_LIST = 4, 0, 1
 MRMF_TUNE_ADDRESSING = 5
 MRMF_TUNE_CHEB_FUSED = 6
+MRMF_TUNE_WAVES_PER_EU = 7
 MRMF_SOURCE_CHEB = 2
 MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 

@@ -80,10 +80,13 @@ struct Gen {
     // Chebyshev-step epilogue (time propagation): instead of y = H x the kernel computes
     // p = ea (H x) + eb x + eg y, writes it to y and adds (ecr + i eci) p to acc
     bool epi = false;
+    int waves_per_eu = 0;  // > 0: ask the compiler for at least this many waves per SIMD (register budget)
 
     std::string kernel_head() const {
         std::ostringstream o;
-        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") void " << (epi ? "mrmf_spec_cheb" : "mrmf_spec")
+        o << "extern \"C\" __global__ __launch_bounds__(" << block << ") ";
+        if (waves_per_eu > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves_per_eu << "))) ";
+        o << "void " << (epi ? "mrmf_spec_cheb" : "mrmf_spec")
           << "(const R* __restrict__ theta,\n    const C* __restrict__ x, C* __restrict__ y, ";
         if (epi) o << "C* __restrict__ acc, R ea, R eb, R eg, R ecr, R eci, ";
         o << "const int* __restrict__ skip) {\n  if (skip != nullptr && *skip != 0) return;\n";
@@ -1179,6 +1182,7 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     Gen gen{p, f32, tl, static_cast<int>(round_up(tl.T_in, 64)), n_st};
     gen.wide = wide;
     gen.epi = epi;
+    gen.waves_per_eu = cfg.waves_per_eu;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
     gen.gs = cfg.group;
@@ -1328,7 +1332,8 @@ void set_cfg(mrmf_plan_t* plan, int slot, const mrmf::KernelCfg& c) {
     mrmf::KernelCfg& cur = plan->cfg[slot];
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
                       cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
-                      cur.wide == c.wide && (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
+                      cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu &&
+                      (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
     cur = c;
     if (slot == mrmf::kSlotCheb) plan->cheb_shape_set = true;
     if (!same) {
@@ -1395,6 +1400,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
             case MRMF_TUNE_CHEB_FUSED:
                 if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
                 c.cheb_fused = value;
+                break;
+            case MRMF_TUNE_WAVES_PER_EU:
+                if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
+                c.waves_per_eu = value;
                 break;
             default: return MRMF_E_INVALID_ARG;
         }

@@ -103,6 +103,7 @@ struct KernelCfg {
     int32_t sched = MRMF_SCHED_WINDOWS, bskip = 0, group = 0, blocks_per_cu = 0, variant = MRMF_VARIANT_MASKED;
     int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
     int32_t cheb_fused = 1;  // time propagation: fused Chebyshev-step kernel (c128 configuration only)
+    int32_t waves_per_eu = 0;  // register budget hint for the generated kernel (0: the compiler's choice)
 };
 
 // Slot of the c128 kernel with the Chebyshev-step epilogue in mrmf_plan_t::spec (after the dtypes).

@@ -229,14 +229,14 @@ class Plan:
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
     TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
-              "cheb_fused": 6}
+              "cheb_fused": 6, "waves_per_eu": 7}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
         branch_skip (0/1), load_group (channels issued ahead, 0 = default), blocks_per_cu (0 = as many as
         fit), variant (0 masked, 1 list), addressing (0 = 64-bit only where 32-bit offsets cannot reach,
         1 = always 64-bit), cheb_fused (1 = propagate with the fused Chebyshev-step kernel, 0 = matvec +
-        update)."""
+        update), waves_per_eu (0 = compiler's choice, else a minimum of resident waves per SIMD)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 
