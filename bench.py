@@ -389,6 +389,17 @@ def bench_adjoint(args, dev):
         p.adjoint(th, xt, g)
     ms_fwd = cuda_time(lambda: p.matvec(th, xt), stream, 50)
     ms_adj = cuda_time(lambda: p.adjoint(th, xt, g), stream, 50)
+    # the same calls replayed from HIP graphs of 20 calls each: device time without the Python and
+    # allocation overhead of the eager calls above (kernels already built by the warm-up)
+    graph_ms = {}
+    for name, fn in (("forward", lambda: p.matvec(th, xt)), ("adjoint", lambda: p.adjoint(th, xt, g))):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            for _ in range(20):
+                fn()
+        gr.replay()
+        torch.cuda.synchronize()
+        graph_ms[name] = cuda_time(gr.replay, stream, 10) / 20
     # Rayleigh quotient gradients: dL/dx = 2 (Hx - L x)/<x|x>, dL/dtheta_p = <x|h_p|x>/<x|x>
     y = p.matvec(th, xt)
     L = (torch.vdot(xt, y).real / torch.vdot(xt, xt).real).item()
@@ -397,7 +408,8 @@ def bench_adjoint(args, dev):
     L_ref, gx_ref, gt_ref = ograd.rayleigh(model, x)
     out = {"metric": "adjoint (grad_x = H g and all coupling gradients) time vs forward matvec",
            "workload": "tavis_cummings_12x64_c128", "D": model.dim, "n_params": model.n_params,
-           "forward_ms": ms_fwd, "adjoint_ms": ms_adj,
+           "forward_ms": ms_fwd, "adjoint_ms": ms_adj, "forward_graph_ms": graph_ms["forward"],
+           "adjoint_graph_ms": graph_ms["adjoint"], "adjoint_form": "generated" if p.grad_kernel_ready() else "generic",
            "rel_err_grad_x": float(np.linalg.norm(gx.cpu().numpy() - gx_ref) / np.linalg.norm(gx_ref)),
            "max_abs_err_grad_theta": float(np.max(np.abs(gt.cpu().numpy() - gt_ref))),
            "loss": L, "loss_ref": L_ref}

@@ -178,7 +178,13 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                             specialized kernel with the Chebyshev-step epilogue (default); 0 = a matvec
  *                             and a separate vector update per term.
  *   MRMF_TUNE_WAVES_PER_EU  : 0 = the compiler's register allocation (default); 1..8 = ask for at least
- *                             that many resident waves per SIMD (a register budget; may spill). */
+ *                             that many resident waves per SIMD (a register budget; may spill).
+ *   MRMF_TUNE_FAR_LOADS     : 0 = every gather with the default cache policy (default); k in 10..40 = in
+ *                             the masked form, a channel whose offset |Delta| spans at least 2^k bytes
+ *                             is loaded non-temporal (its lines are the first the L2 evicts), so the
+ *                             windows of near channels stay resident.  Results are unchanged.
+ *   MRMF_TUNE_GRAD_BLOCKS_PER_CU : blocks of 256 threads per compute unit of the generated
+ *                             coupling-gradient kernel of mrmf_adjoint_z (0 = default 2; 1..8). */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
@@ -187,6 +193,8 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_TUNE_ADDRESSING 5
 #define MRMF_TUNE_CHEB_FUSED 6
 #define MRMF_TUNE_WAVES_PER_EU 7
+#define MRMF_TUNE_FAR_LOADS 8
+#define MRMF_TUNE_GRAD_BLOCKS_PER_CU 9
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0
@@ -211,7 +219,9 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
 mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, const void* d_theta,
                                const void* d_x, void* d_y, mrmf_stream stream, int32_t* out);
 /* Build (compile and load) the kernel mrmf_matvec_z (dtype Z) or mrmf_matvec_c (dtype C) will use, now
- * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only. */
+ * rather than on the first call (e.g. before stream capture).  Synchronous; host-side only.
+ * dtype = MRMF_SOURCE_GRAD builds the generated coupling-gradient kernel of mrmf_adjoint_z and returns
+ * MRMF_E_UNSUPPORTED when the plan does not qualify for it (the adjoint then runs its generic pass). */
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype);
 /* Host out[0..7] = (kernel kind used, inner sites, rows per block T_in, block threads, grid blocks,
  * super-tiles, unrolled sites, unrolled copies) for the given dtype, after mrmf_plan_prepare. */
@@ -221,6 +231,8 @@ mrmf_status mrmf_plan_kernel_info(mrmf_plan plan, int32_t dtype, int32_t* out);
  * *len.  MRMF_E_UNSUPPORTED when the plan does not qualify for the specialized kernel. */
 #define MRMF_SOURCE_CHEB 2 /* dtype value of mrmf_plan_kernel_source: the c128 kernel with the fused
                              Chebyshev-step epilogue that mrmf_propagate_z launches */
+#define MRMF_SOURCE_GRAD 3 /* dtype value of mrmf_plan_kernel_source only: the generated coupling-gradient
+                             kernel of mrmf_adjoint_z */
 mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len);
 
 /* y = H(theta) x, plain FP64 form.  d_theta: double[n_params]; d_x, d_y: c128[D], 16-byte aligned,
@@ -241,8 +253,12 @@ mrmf_status mrmf_debug_sources(mrmf_plan plan, const void* d_ws, int64_t F0, int
 /* Adjoint of y = H(theta) x for an upstream gradient g = dL/dRe y + i dL/dIm y:
  *   d_grad_x     = H^dagger g = H g  (c128[D]; needs a Hermitian plan, Sec. IV.A/IV.B conditions)
  *   d_grad_theta = Re <g | h_p x>, p = 0..n_params-1  (double[n_params], h_p = dH/dtheta_p)
- * computed in one gather pass over g plus a deterministic second-stage reduction.
- * d_scratch: device memory of at least mrmf_adjoint_scratch_bytes.  d_grad_x must not overlap d_g. */
+ * Two forms, both with deterministic block sums and a second-stage reduction in a fixed order: unless the
+ * kernel selection is MRMF_KERNEL_GENERIC, d_grad_x comes from the plan's matvec applied to g and the
+ * couplings from a kernel generated for the plan (parameter sums in registers; plans with 1..48
+ * parameters and vectors below 2^31 bytes); otherwise, or when the plan does not qualify, one generic
+ * gather pass over g computes both.
+ * d_scratch: device memory of at least mrmf_adjoint_scratch_bytes.  d_grad_x must not overlap d_g or d_x. */
 mrmf_status mrmf_adjoint_scratch_bytes(mrmf_plan plan, size_t* bytes);
 mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
                            const void* d_g, void* d_grad_x, double* d_grad_theta, void* d_scratch,

@@ -29,7 +29,10 @@ MRMF_TUNE_VARIANT, MRMF_VARIANT_MASKED, MRMF_VARIANT_LIST = 4, 0, 1
 MRMF_TUNE_ADDRESSING = 5
 MRMF_TUNE_CHEB_FUSED = 6
 MRMF_TUNE_WAVES_PER_EU = 7
+MRMF_TUNE_FAR_LOADS = 8
+MRMF_TUNE_GRAD_BLOCKS_PER_CU = 9
 MRMF_SOURCE_CHEB = 2
+MRMF_SOURCE_GRAD = 3
 MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 
 

@@ -219,9 +219,18 @@ mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_the
     mrmf_adjoint_scratch_bytes(plan, &need);
     if (scratch_bytes < need) return MRMF_E_WORKSPACE;
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    double* partial = static_cast<double*>(d_scratch);
+    // generated form: one pass of the kernel generated for the plan, then the fixed-order reduction
+    if (plan->n_params > 0 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC && grad_prepare(plan) == MRMF_OK) {
+        int nb = 0;
+        const mrmf_status st = grad_launch(plan, d_theta, d_x, d_g, d_grad_x, partial, adjoint_grid(plan->D), &nb, s);
+        if (st != MRMF_OK) return st;
+        hipLaunchKernelGGL(k_adjoint_finalize, dim3(plan->n_params), dim3(kFinBlock), 0, s, nb, plan->n_params,
+                           partial, d_grad_theta);
+        return launch_status();
+    }
     const PlanArgs a = plan_args(plan, d_ws);
     const int grid = adjoint_grid(plan->D);
-    double* partial = static_cast<double*>(d_scratch);
     const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
     const int passes = plan->n_params > 0 ? (plan->n_params + kAdjParamChunk - 1) / kAdjParamChunk : 1;
     const bool wide = plan->D > int64_t(0xffffffffu);

@@ -81,6 +81,7 @@ struct Gen {
     // p = ea (H x) + eb x + eg y, writes it to y and adds (ecr + i eci) p to acc
     bool epi = false;
     int waves_per_eu = 0;  // > 0: ask the compiler for at least this many waves per SIMD (register budget)
+    int far_nt = 0;        // > 0: gathers reaching |Delta| >= 2^far_nt bytes use LDN (non-temporal)
 
     std::string kernel_head() const {
         std::ostringstream o;
@@ -166,13 +167,17 @@ struct Gen {
             full << "#define RS(p) __builtin_amdgcn_make_buffer_rsrc((void*)(p), (short)0, 0x7fffffff, 0x00020000)\n"
                  << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b" << bits
                  << "(RS((rs) + (so)), (int)(vo), 0, 0))\n"
+                 << "#define LDN(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b" << bits
+                 << "(RS((rs) + (so)), (int)(vo), 0, 2))\n"
                  << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b" << bits
                  << "(__builtin_bit_cast(U, (v)), RS((rs) + (so)), (int)(vo), 0, 2)\n";
         } else if (f32) {
             full << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 0))\n"
+                 << "#define LDN(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), (int)(so), 2))\n"
                  << "#define ST(v, rs, vo, so) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), (int)(so), 2)\n";
         } else {
             full << "#define LD(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 0))\n"
+                 << "#define LDN(rs, vo, so) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), (int)(so), 2))\n"
                  // 128-bit store: the offset goes into the VGPR operand and the scalar offset is the
                  // constant 0; with a register scalar offset the compiler inserts no wait state between
                  // the store and a following VALU write of its data registers, and the stored value was
@@ -183,6 +188,10 @@ struct Gen {
     }
 
     int SZ() const { return f32 ? 8 : 16; }
+    // a channel whose offset reaches far enough for a non-temporal load (MRMF_TUNE_FAR_LOADS)
+    bool far(int64_t delta) const {
+        return far_nt > 0 && static_cast<double>(delta < 0 ? -delta : delta) * SZ() >= std::ldexp(1.0, far_nt);
+    }
     int op_shift(int op) const {
         if (op >= MRMF_OP_LOCAL_BASE) return p->lshift[op - MRMF_OP_LOCAL_BASE];
         switch (op) {
@@ -575,13 +584,15 @@ struct Gen {
             for (int i = g * GS; i < std::min<int>(cG.size(), (g + 1) * GS); ++i) {
                 const int c = cG[i];
                 const auto& ch = P.chans[c];
+                const char* ld = far(ch.delta) ? "LDN" : "LD";
                 for (int64_t j = 0; j < PU; ++j) {
                     if (kind(ch.a, ch.b) == 2 && !fM.count({c, j})) continue;
                     if (bskip)
                         o << "    C s" << c << "_" << j << " = {(R)0, (R)0}; if (q" << c << ") s" << c << "_" << j
-                          << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
+                          << " = " << ld << "(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
                     else
-                        o << "    const C s" << c << "_" << j << " = LD(xs, u" << c << ", " << soff(j, ch.delta) << ");\n";
+                        o << "    const C s" << c << "_" << j << " = " << ld << "(xs, u" << c << ", " << soff(j, ch.delta)
+                          << ");\n";
                 }
             }
         };
@@ -1160,6 +1171,190 @@ bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, Tile* 
 
 }  // namespace
 
+// Adjoint kernel generated for one plan (c128, Hermitian groups).  For an upstream gradient g the adjoint
+// needs grad_x = H g and grad_theta_p = Re <g | h_p x> = Re <h_p g | x> (h_p Hermitian), and both come from
+// the terms of the gather form (Sec. II) applied to g:
+//     t = w f(F) g[F - Delta],   grad_x[F] += theta_p t,   grad_theta_p += Re conj(t) x_F.
+// The plan is compiled in: digits from the row index by shifts or by multiplication with compile-time
+// reciprocals (Eq. decode), each one-site factor table <n|O|n - q> as a select over literals (d <= 3) or an
+// LDS table, one register accumulator per parameter.  A zero factor (inadmissible source) masks its gather
+// to the out-of-range offset, which reads zero.  The channels are taken in groups whose gathers are all
+// issued before any of them is used (a scheduling barrier keeps them together), so a row waits for memory
+// once per group.  Each thread sums its rows; at the end every parameter is summed over the wave by a fixed
+// pattern of DPP moves and over the block's four waves in a fixed order into partial[block * n_params + p],
+// so the result does not depend on scheduling.  "" when the plan has no parameters, more than
+// kGradMaxParams, or a vector of 2^31 bytes or more.
+std::string grad_source(const mrmf_plan_t* p) {
+    const int np = p->n_params, N = p->N;
+    if (np < 1 || np > kGradMaxParams || p->D * 16 >= (int64_t(1) << 31)) return "";
+    std::vector<double> lds;                       // tables of sites with d > 3
+    std::map<std::pair<int, int>, size_t> lds_at;  // (site, op) -> offset in lds
+    // one-site factor <n|O|n - q> at the row's digit of `site`, as an expression
+    auto factor = [&](int site, int op) -> std::string {
+        const int d = p->d[site];
+        const std::string n = "n" + std::to_string(site);
+        std::ostringstream e;
+        if (d == 1) {
+            e << lit(local_factor_host(p, site, op, 0), false);
+        } else if (d <= 3) {
+            e << "(" << n << " == 0u ? " << lit(local_factor_host(p, site, op, 0), false) << " : ";
+            if (d == 2) {
+                e << lit(local_factor_host(p, site, op, 1), false) << ")";
+            } else {
+                e << "(" << n << " == 1u ? " << lit(local_factor_host(p, site, op, 1), false) << " : "
+                  << lit(local_factor_host(p, site, op, 2), false) << "))";
+            }
+        } else {
+            auto it = lds_at.find({site, op});
+            if (it == lds_at.end()) {
+                it = lds_at.emplace(std::make_pair(site, op), lds.size()).first;
+                for (int v = 0; v < d; ++v) lds.push_back(local_factor_host(p, site, op, v));
+            }
+            e << "Kl[" << it->second << "u + " << n << "]";
+        }
+        return e.str();
+    };
+    struct T {
+        int a, opa, b, opb, param;
+        double wr, wi;
+        int64_t delta;
+        bool diag;
+    };
+    std::vector<T> terms;
+    for (const auto& g : p->diags) terms.push_back({g.a, g.opa, g.b, g.opb, g.param, g.wr, g.wi, 0, true});
+    for (const auto& c : p->chans) terms.push_back({c.a, c.opa, c.b, c.opb, c.param, c.wr, c.wi, c.delta, false});
+    std::set<int> used;
+    for (const T& t : terms) {
+        used.insert(t.a);
+        if (t.b >= 0) used.insert(t.b);
+    }
+    std::set<int> params_used;
+    for (const T& t : terms) params_used.insert(t.param);
+    // accumulation of term k with source value sk (complex) and factor fk
+    auto accumulate = [&](std::ostringstream& o, const T& t, const std::string& f, const std::string& s) {
+        o << "      { const double c = " << f << " * " << lit(t.wr, false) << ";";
+        if (t.wi == 0.0) {
+            o << " const double e = c * th" << t.param << ";"
+              << " hr = fma(e, " << s << ".x, hr); hi = fma(e, " << s << ".y, hi);"
+              << " a" << t.param << " = fma(c, " << s << ".x * xf.x + " << s << ".y * xf.y, a" << t.param << "); }\n";
+        } else {
+            o << " const double ci = " << f << " * " << lit(t.wi, false) << ";"
+              << " const double tr = c * " << s << ".x - ci * " << s << ".y, ti = c * " << s << ".y + ci * " << s << ".x;"
+              << " hr = fma(th" << t.param << ", tr, hr); hi = fma(th" << t.param << ", ti, hi);"
+              << " a" << t.param << " = fma(tr, xf.x, fma(ti, xf.y, a" << t.param << ")); }\n";
+        }
+    };
+    auto fexpr = [&](const T& t) {
+        std::string f = factor(t.a, t.opa);
+        if (t.b >= 0) f = "(" + f + " * " + factor(t.b, t.opb) + ")";
+        return f;
+    };
+    std::ostringstream body;
+    // diagonal terms: the source is g_F itself
+    for (const T& t : terms)
+        if (t.diag) accumulate(body, t, fexpr(t), "gf");
+    // channels in groups of at most kGroup gathers
+    std::vector<const T*> ch;
+    for (const T& t : terms)
+        if (!t.diag) ch.push_back(&t);
+    constexpr int kGroup = 12;
+    const int ngr = static_cast<int>((ch.size() + kGroup - 1) / kGroup);
+    const int gsz = ngr > 0 ? static_cast<int>((ch.size() + ngr - 1) / ngr) : 0;
+    for (size_t g0 = 0; g0 < ch.size(); g0 += gsz) {
+        const size_t g1 = std::min(ch.size(), g0 + gsz);
+        body << "    {\n";
+        for (size_t k = g0; k < g1; ++k)
+            body << "      const double f" << k - g0 << " = " << fexpr(*ch[k]) << ";\n";
+        for (size_t k = g0; k < g1; ++k)
+            body << "      const C s" << k - g0 << " = LD(gs, f" << k - g0 << " != 0.0 ? vf - " << ch[k]->delta * 16
+                 << "u : OOB);\n";
+        body << "      __builtin_amdgcn_sched_barrier(0);\n";
+        for (size_t k = g0; k < g1; ++k)
+            accumulate(body, *ch[k], "f" + std::to_string(k - g0), "s" + std::to_string(k - g0));
+        body << "    }\n";
+    }
+    std::ostringstream o;
+    o << "// generated adjoint kernel: " << N << " sites, " << p->diags.size() << " diagonal terms, " << p->chans.size()
+      << " channels, " << np << " parameters\n";
+    o << "typedef double C __attribute__((ext_vector_type(2)));\n"
+      << "typedef unsigned U2 __attribute__((ext_vector_type(2)));\n"
+      << "typedef unsigned U4 __attribute__((ext_vector_type(4)));\n"
+      << "#define LD(rs, vo) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), 0, 0))\n"
+      << "#define OOB 0x80000000u\n";
+    if (!lds.empty()) {
+        o << "__constant__ double K[" << lds.size() << "] = {";
+        for (size_t i = 0; i < lds.size(); ++i) o << (i ? ", " : "") << lit(lds[i], false);
+        o << "};\n";
+    }
+    o << "// v moved across lanes by one DPP pattern (rows outside row_mask take 0), one 32-bit half at a time\n"
+      << "template <int CTRL, int ROW_MASK>\n__device__ __forceinline__ double dpp_move(double v) {\n"
+      << "  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);\n"
+      << "  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW_MASK, 0xf, false);\n"
+      << "  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROW_MASK, 0xf, false);\n"
+      << "  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);\n}\n"
+      << "// sum over the 64 lanes (pairs, quads, half-row and row mirrors, row broadcasts 15 and 31): lane 63\n"
+      << "__device__ __forceinline__ double wave_sum(double v) {\n"
+      << "  v += dpp_move<0xB1, 0xf>(v);\n  v += dpp_move<0x4E, 0xf>(v);\n  v += dpp_move<0x141, 0xf>(v);\n"
+      << "  v += dpp_move<0x140, 0xf>(v);\n  v += dpp_move<0x142, 0xa>(v);\n  v += dpp_move<0x143, 0xc>(v);\n"
+      << "  return v;\n}\n";
+    o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_grad(const double* __restrict__ theta,\n"
+      << "    const C* __restrict__ x, const C* __restrict__ g, C* __restrict__ gx, double* __restrict__ partial) {\n"
+      << "  __shared__ double red[" << np << "][4];\n";
+    if (!lds.empty())
+        o << "  __shared__ double Kl[" << lds.size() << "];\n"
+          << "  for (unsigned i = threadIdx.x; i < " << lds.size() << "u; i += 256u) Kl[i] = K[i];\n"
+          << "  __syncthreads();\n";
+    o << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, " << p->D * 16
+      << ", 0x00020000);\n"
+      << "  const __amdgpu_buffer_rsrc_t gs = __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, " << p->D * 16
+      << ", 0x00020000);\n"
+      << "  const __amdgpu_buffer_rsrc_t os = __builtin_amdgcn_make_buffer_rsrc((void*)gx, (short)0, " << p->D * 16
+      << ", 0x00020000);\n"
+      << "  const unsigned tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;\n";
+    for (int q : params_used) o << "  const double th" << q << " = theta[" << q << "];\n";
+    for (int q = 0; q < np; ++q) o << "  double a" << q << " = 0.0;\n";
+    o << "  for (unsigned F = blockIdx.x * 256u + tid; F < " << p->D << "u; F += gridDim.x * 256u) {\n"
+      << "    const unsigned vf = F * 16u;\n"
+      << "    unsigned f = F;\n";
+    for (int i = N - 1; i >= 0; --i) {  // Eq. decode, least significant site first
+        const uint64_t d = static_cast<uint64_t>(p->d[i]);
+        const std::string I = std::to_string(i);
+        const bool use = used.count(i) != 0;
+        if (d == 1) {
+            if (use) o << "    const unsigned n" << I << " = 0u;\n";
+        } else if (i == 0) {
+            if (use) o << "    const unsigned n0 = f;\n";
+        } else if ((d & (d - 1)) == 0) {
+            if (use) o << "    const unsigned n" << I << " = f & " << d - 1 << "u;";
+            else o << "   ";
+            o << " f >>= " << __builtin_ctzll(d) << "u;\n";
+        } else if (use) {
+            o << "    const unsigned q" << I << " = (unsigned)__umul64hi(" << ulit(magic_of(d)) << ", (unsigned long long)f);\n"
+              << "    const unsigned n" << I << " = f - q" << I << " * " << d << "u; f = q" << I << ";\n";
+        } else {
+            o << "    f = (unsigned)__umul64hi(" << ulit(magic_of(d)) << ", (unsigned long long)f);\n";
+        }
+    }
+    o << "    const C gf = LD(gs, vf), xf = LD(xs, vf);\n"
+      << "    double hr = 0.0, hi = 0.0;\n"
+      << body.str()
+      << "    { C out; out.x = hr; out.y = hi;\n"
+      << "      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, out), os, (int)vf, 0, 2); }\n"
+      << "  }\n";
+    for (int q = 0; q < np; ++q)
+        o << "  { const double v = wave_sum(a" << q << "); if (lane == 63u) red[" << q << "][wave] = v; }\n";
+    o << "  __syncthreads();\n"
+      << "  const __amdgpu_buffer_rsrc_t ps = __builtin_amdgcn_make_buffer_rsrc((void*)partial, (short)0, gridDim.x * "
+      << np * 8 << "u, 0x00020000);\n"
+      << "  if (tid < " << np << "u) {\n"
+      << "    const double v = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];\n"
+      << "    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), ps, (int)((blockIdx.x * " << np
+      << "u + tid) * 8u), 0, 0);\n"
+      << "  }\n"
+      << "}\n";
+    return o.str();
+}
+
 std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int64_t SZ = f32 ? 8 : 16;
@@ -1183,6 +1378,7 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     gen.wide = wide;
     gen.epi = epi;
     gen.waves_per_eu = cfg.waves_per_eu;
+    gen.far_nt = cfg.far_nt;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
     gen.gs = cfg.group;
@@ -1193,6 +1389,44 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
 }
 
 namespace {
+
+// Compiles a generated source with hiprtc for the current device's architecture and loads kernel `name`;
+// on a compile error the log (and the source) goes to *log and the result is MRMF_E_UNSUPPORTED.
+mrmf_status rtc_build(const std::string& src, const char* name, const hipDeviceProp_t& prop, hipModule_t* mod_out,
+                      hipFunction_t* fn_out, std::string* log_out) {
+    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "mrmf_gen.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return MRMF_E_HIP;
+    const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult cr = hiprtcCompileProgram(prog, 7, opts);
+    size_t log_size = 0;
+    hiprtcGetProgramLogSize(prog, &log_size);
+    std::string log(log_size, '\0');
+    if (log_size) hiprtcGetProgramLog(prog, &log[0]);
+    if (cr != HIPRTC_SUCCESS) {
+        *log_out = "hiprtc: " + log + "\n" + src;
+        hiprtcDestroyProgram(&prog);
+        return MRMF_E_UNSUPPORTED;
+    }
+    size_t code_size = 0;
+    hiprtcGetCodeSize(prog, &code_size);
+    std::vector<char> code(code_size);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    hipModule_t mod;
+    if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return MRMF_E_HIP;
+    hipFunction_t fn;
+    if (hipModuleGetFunction(&fn, mod, name) != hipSuccess) {
+        hipModuleUnload(mod);
+        return MRMF_E_HIP;
+    }
+    *mod_out = mod;
+    *fn_out = fn;
+    return MRMF_OK;
+}
 
 // slot: MRMF_DTYPE_Z, MRMF_DTYPE_C, or kSlotCheb (c128 with the Chebyshev-step epilogue)
 mrmf_status compile_spec(mrmf_plan_t* p, int slot, SpecKernel& K) {
@@ -1211,35 +1445,10 @@ mrmf_status compile_spec(mrmf_plan_t* p, int slot, SpecKernel& K) {
     if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MRMF_E_HIP;
-    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    const size_t colon = arch.find(':');
-    if (colon != std::string::npos) arch = arch.substr(0, colon);
-    hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "mrmf_spec.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
-        return MRMF_E_HIP;
-    const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult cr = hiprtcCompileProgram(prog, 7, opts);
-    size_t log_size = 0;
-    hiprtcGetProgramLogSize(prog, &log_size);
-    std::string log(log_size, '\0');
-    if (log_size) hiprtcGetProgramLog(prog, &log[0]);
-    if (cr != HIPRTC_SUCCESS) {
-        K.log = "hiprtc: " + log + "\n" + src;
-        hiprtcDestroyProgram(&prog);
-        return MRMF_E_UNSUPPORTED;
-    }
-    size_t code_size = 0;
-    hiprtcGetCodeSize(prog, &code_size);
-    std::vector<char> code(code_size);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
     hipModule_t mod;
-    if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return MRMF_E_HIP;
     hipFunction_t fn;
-    if (hipModuleGetFunction(&fn, mod, slot == kSlotCheb ? "mrmf_spec_cheb" : "mrmf_spec") != hipSuccess) {
-        hipModuleUnload(mod);
-        return MRMF_E_HIP;
-    }
+    const mrmf_status bs = rtc_build(src, slot == kSlotCheb ? "mrmf_spec_cheb" : "mrmf_spec", prop, &mod, &fn, &K.log);
+    if (bs != MRMF_OK) return bs;
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
@@ -1312,11 +1521,64 @@ mrmf_status spec_launch_cheb(mrmf_plan_t* p, const double* theta, const void* x,
     return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
 }
 
+mrmf_status grad_prepare(mrmf_plan_t* p) {
+    std::lock_guard<std::mutex> lk(p->mtx);
+    SpecKernel& K = p->grad;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
+    if (K.tried && K.device == dev) return K.ok ? MRMF_OK : MRMF_E_UNSUPPORTED;
+    if (K.mod) hipModuleUnload(K.mod);
+    K = SpecKernel{};
+    K.device = dev;
+    K.tried = true;
+    const std::string src = grad_source(p);
+    if (src.empty()) {
+        K.log = "plan does not qualify for the generated gradient kernel";
+        return MRMF_E_UNSUPPORTED;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MRMF_E_HIP;
+    hipModule_t mod;
+    hipFunction_t fn;
+    const mrmf_status bs = rtc_build(src, "mrmf_grad", prop, &mod, &fn, &K.log);
+    if (bs != MRMF_OK) return bs;
+    // rows per thread against waves per SIMD: blocks_per_cu blocks of four waves on every CU (a tuning
+    // knob, 2 by default), never more blocks than row groups of 256
+    const int bpc = p->cfg[MRMF_DTYPE_Z].grad_blocks_per_cu > 0 ? p->cfg[MRMF_DTYPE_Z].grad_blocks_per_cu : 2;
+    const int64_t groups = (p->D + 255) / 256;
+    K.mod = mod;
+    K.fn = fn;
+    K.block = 256;
+    K.grid = static_cast<int32_t>(std::min<int64_t>(groups, int64_t(bpc) * prop.multiProcessorCount));
+    K.log = src;
+    K.ok = true;
+    return MRMF_OK;
+}
+
+mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, const void* g, void* gx, double* partial,
+                        int max_grid, int* grid, hipStream_t s) {
+    mrmf_status st = grad_prepare(p);
+    if (st != MRMF_OK) return st;
+    const SpecKernel& K = p->grad;
+    *grid = std::min(K.grid, max_grid);
+    struct {
+        const double* theta;
+        const void* x;
+        const void* g;
+        void* gx;
+        double* partial;
+    } args{theta, x, g, gx, partial};
+    size_t size = sizeof(args);
+    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
+    return hip_status(hipModuleLaunchKernel(K.fn, *grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
+}
+
 }  // namespace mrmf
 
 mrmf_plan_t::~mrmf_plan_t() {
     for (auto& k : spec)
         if (k.mod) hipModuleUnload(k.mod);
+    if (grad.mod) hipModuleUnload(grad.mod);
 }
 
 extern "C" {
@@ -1332,7 +1594,7 @@ void set_cfg(mrmf_plan_t* plan, int slot, const mrmf::KernelCfg& c) {
     mrmf::KernelCfg& cur = plan->cfg[slot];
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
                       cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
-                      cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu &&
+                      cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu && cur.far_nt == c.far_nt &&
                       (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
     cur = c;
     if (slot == mrmf::kSlotCheb) plan->cheb_shape_set = true;
@@ -1405,6 +1667,16 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
                 c.waves_per_eu = value;
                 break;
+            case MRMF_TUNE_FAR_LOADS:
+                if (value != 0 && (value < 10 || value > 40)) return MRMF_E_INVALID_ARG;
+                c.far_nt = value;
+                break;
+            case MRMF_TUNE_GRAD_BLOCKS_PER_CU:
+                if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
+                c.grad_blocks_per_cu = value;
+                if (dt == MRMF_DTYPE_Z && plan->grad.mod) hipModuleUnload(plan->grad.mod);
+                if (dt == MRMF_DTYPE_Z) plan->grad = mrmf::SpecKernel{};
+                break;
             default: return MRMF_E_INVALID_ARG;
         }
         set_cfg(plan, dt, c);
@@ -1427,12 +1699,15 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     c.group = load_group;
     c.cheb_fused = plan->cfg[dtype].cheb_fused;
     c.wide = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].wide;
+    c.far_nt = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_nt;
     set_cfg(plan, dtype, c);
     return MRMF_OK;
 }
 
 mrmf_status mrmf_plan_prepare(mrmf_plan plan, int32_t dtype) {
-    if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C)) return MRMF_E_INVALID_ARG;
+    if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_GRAD))
+        return MRMF_E_INVALID_ARG;
+    if (dtype == MRMF_SOURCE_GRAD) return mrmf::grad_prepare(plan);
     const int32_t mode = plan->cfg[dtype].mode;
     if (mode == MRMF_KERNEL_GENERIC) return MRMF_OK;
     const mrmf_status st = mrmf::spec_prepare(plan, dtype);
@@ -1548,12 +1823,14 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
 }
 
 mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, size_t cap, size_t* len) {
-    if (!plan || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
+    if (!plan || !len ||
+        (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB && dtype != MRMF_SOURCE_GRAD) ||
         (cap > 0 && !buf))
         return MRMF_E_INVALID_ARG;
     mrmf::Tile tl;
     const bool cheb = dtype == MRMF_SOURCE_CHEB;
-    const std::string src = mrmf::spec_source(plan, cheb ? MRMF_DTYPE_Z : dtype, &tl, cheb);
+    const std::string src = dtype == MRMF_SOURCE_GRAD ? mrmf::grad_source(plan)
+                                                      : mrmf::spec_source(plan, cheb ? MRMF_DTYPE_Z : dtype, &tl, cheb);
     if (src.empty()) return MRMF_E_UNSUPPORTED;
     *len = src.size();
     if (cap > 0) {

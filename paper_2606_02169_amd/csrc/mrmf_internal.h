@@ -104,10 +104,15 @@ struct KernelCfg {
     int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
     int32_t cheb_fused = 1;  // time propagation: fused Chebyshev-step kernel (c128 configuration only)
     int32_t waves_per_eu = 0;  // register budget hint for the generated kernel (0: the compiler's choice)
+    int32_t far_nt = 0;  // > 0: masked-form gathers with |Delta| >= 2^far_nt bytes are non-temporal loads
+    int32_t grad_blocks_per_cu = 0;  // blocks per CU of the generated gradient kernel (0: the default, 2)
 };
 
 // Slot of the c128 kernel with the Chebyshev-step epilogue in mrmf_plan_t::spec (after the dtypes).
 constexpr int kSlotCheb = 2;
+
+// Largest parameter count the generated coupling-gradient kernel keeps in registers (one accumulator each).
+constexpr int kGradMaxParams = 48;
 
 // A kernel generated and compiled for one plan and element type (see jit.cpp).
 struct SpecKernel {
@@ -151,6 +156,7 @@ struct mrmf_plan_t {
     mrmf::KernelCfg cfg[3];       // [kSlotCheb]: shape of the Chebyshev-step kernel once set explicitly
     bool cheb_shape_set = false;  // else that kernel takes the c128 configuration
     mrmf::SpecKernel spec[3];  // c128, c64, c128 with the Chebyshev-step epilogue
+    mrmf::SpecKernel grad;     // coupling-gradient kernel of the adjoint (c128)
     std::mutex mtx;
     ~mrmf_plan_t();
 };
@@ -216,5 +222,12 @@ mrmf_status spec_launch_cheb(mrmf_plan_t* p, const double* theta, const void* x,
                              double eb, double eg, double ecr, double eci, hipStream_t s);
 // <n|O|n - q> of site's operator op at target digit n; 0 where the source digit is out of range
 double local_factor_host(const mrmf_plan_t* p, int site, int op, int n);
+// Adjoint kernel generated for the plan (jit.cpp): source ("" when the plan does not qualify), compilation,
+// and a launch of at most max_grid blocks of 256 threads writing gx = H g and partial[block][param]
+// (*grid: the blocks launched).  MRMF_E_UNSUPPORTED when the plan does not qualify.
+std::string grad_source(const mrmf_plan_t* p);
+mrmf_status grad_prepare(mrmf_plan_t* p);
+mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, const void* g, void* gx, double* partial,
+                        int max_grid, int* grid, hipStream_t s);
 
 }  // namespace mrmf

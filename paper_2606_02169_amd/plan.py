@@ -229,14 +229,17 @@ class Plan:
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
     TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
-              "cheb_fused": 6, "waves_per_eu": 7}
+              "cheb_fused": 6, "waves_per_eu": 7, "far_loads": 8, "grad_blocks_per_cu": 9}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
         branch_skip (0/1), load_group (channels issued ahead, 0 = default), blocks_per_cu (0 = as many as
         fit), variant (0 masked, 1 list), addressing (0 = 64-bit only where 32-bit offsets cannot reach,
         1 = always 64-bit), cheb_fused (1 = propagate with the fused Chebyshev-step kernel, 0 = matvec +
-        update), waves_per_eu (0 = compiler's choice, else a minimum of resident waves per SIMD)."""
+        update), waves_per_eu (0 = compiler's choice, else a minimum of resident waves per SIMD),
+        far_loads (0 = default cache policy, k = masked-form gathers reaching 2^k bytes or more are
+        non-temporal), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
+        kernel, 0 = default)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 
@@ -285,6 +288,14 @@ class Plan:
         """Compile and load the kernel matvec will use for this element type (synchronous)."""
         dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C
         L.call("mrmf_plan_prepare", self._handle, dt)
+
+    def grad_kernel_ready(self) -> bool:
+        """Build the adjoint's generated coupling-gradient kernel now; False when the plan does not qualify
+        for it (mrmf_adjoint_z then runs its generic pass)."""
+        st = L.lib().mrmf_plan_prepare(self._handle, L.MRMF_SOURCE_GRAD)
+        if st not in (0, L.MRMF_E_UNSUPPORTED):
+            L.check(st, "mrmf_plan_prepare")
+        return st == 0
 
     def kernel_info(self, dtype=torch.complex128) -> dict:
         dt = L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C

@@ -13,6 +13,13 @@ thread_local emu_dim3 threadIdx, blockIdx;
 emu_dim3 gridDim, blockDim;
 double emu_shfl_slot[16][64];
 unsigned long long emu_ballot_slot[16][64];
+int emu_dpp_slot[16][64];
+
+void emu_dpp_unsupported(int ctrl) {
+    std::fprintf(stderr, "emu: DPP control 0x%x is not emulated\n", ctrl);
+    std::fflush(stderr);
+    std::abort();
+}
 
 void emu_uniform_failed(long long mine, long long first) {
     std::fprintf(stderr, "emu: readfirstlane of a non-uniform value (lane %u has %lld, lane 0 %lld)\n", threadIdx.x,
@@ -30,6 +37,7 @@ struct Buf {
     const char* name;
 };
 std::vector<Buf> g_bufs;
+Buf g_extra{nullptr, 0, ""};  // one more buffer of the next launch (the adjoint kernel's partial sums)
 int g_fault = 0;
 }  // namespace
 
@@ -47,8 +55,11 @@ void emu_check(const void* p, size_t n, const char* what) {
     std::abort();
 }
 
-// A generated source defines one of the two kernels: the plain matvec or the Chebyshev-step form.
+// A generated source defines one of the kernels: the plain matvec, the Chebyshev-step form, or the
+// adjoint's coupling-gradient kernel.
 extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
+extern "C" void mrmf_grad(const double* theta, const void* x, const void* g, void* gx, double* partial)
+    __attribute__((weak));
 extern "C" void mrmf_spec_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
                                double ecr, double eci, const int* skip) __attribute__((weak));
 
@@ -64,6 +75,12 @@ struct ChebCall {
     void* acc = nullptr;
     double ea = 0, eb = 0, eg = 0, ecr = 0, eci = 0;
 } g_cheb;
+// Adjoint-kernel launch: its extra pointers (the launch's `theta`, `x`, `y` slots hold theta, x, gx)
+struct GradCall {
+    bool on = false;
+    const void* g = nullptr;
+    double* partial = nullptr;
+} g_grad;
 // One host thread per GPU thread of the block, kept for every block of the range; a block barrier
 // separates consecutive blocks (their __shared__ storage is the same static storage).
 void* thread_main(void* a) {
@@ -71,7 +88,9 @@ void* thread_main(void* a) {
     threadIdx = emu_dim3{g->tid, 0, 0};
     for (unsigned b = g->b0; b < g->b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
-        if (g_cheb.cheb)
+        if (g_grad.on)
+            mrmf_grad(static_cast<const double*>(g->theta), g->x, g_grad.g, g->y, g_grad.partial);
+        else if (g_cheb.cheb)
             mrmf_spec_cheb(g->theta, g->x, g->y, g_cheb.acc, g_cheb.ea, g_cheb.eb, g_cheb.eg, g_cheb.ecr, g_cheb.eci,
                            nullptr);
         else
@@ -95,10 +114,12 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
                              size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1) {
     if (b1 == 0 || b1 > grid) b1 = grid;
     if (block == 0 || block % 64 != 0 || block > 1024) return -1;
-    if (g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr) return -3;
+    if (g_grad.on ? mrmf_grad == nullptr : g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr) return -3;
     g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
               {static_cast<const char*>(theta), theta_bytes, "theta"}};
     if (g_cheb.cheb) g_bufs.push_back({static_cast<const char*>(g_cheb.acc), x_bytes, "acc"});
+    if (g_grad.on) g_bufs.push_back({static_cast<const char*>(g_grad.g), x_bytes, "g"});
+    if (g_extra.p) g_bufs.push_back(g_extra);
     gridDim = emu_dim3{grid, 1, 1};
     blockDim = emu_dim3{block, 1, 1};
     const unsigned nw = block / 64;
@@ -138,5 +159,17 @@ extern "C" int emu_run_cheb(unsigned grid, unsigned block, const void* theta, si
     g_cheb = ChebCall{true, acc, ea, eb, eg, ecr, eci};
     const int rc = emu_run_range(grid, block, theta, theta_bytes, x, x_bytes, prev, x_bytes, b0, b1);
     g_cheb = ChebCall{};
+    return rc;
+}
+
+// The adjoint kernel over all `grid` blocks of 256 threads: gx (length of x) = H g, partial holds
+// grid x n_params doubles (a buffer of its own: registered through g_bufs below).
+extern "C" int emu_run_grad(unsigned grid, const void* theta, size_t theta_bytes, const void* x, size_t x_bytes,
+                            const void* g, void* gx, void* partial, size_t partial_bytes) {
+    g_grad = GradCall{true, g, static_cast<double*>(partial)};
+    g_extra = {static_cast<const char*>(partial), partial_bytes, "partial"};
+    const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, gx, x_bytes, 0, 0);
+    g_grad = GradCall{};
+    g_extra = {nullptr, 0, ""};
     return rc;
 }

@@ -11,6 +11,7 @@
 
 #include <pthread.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -22,6 +23,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define __constant__ static const
+using std::fma;
 
 struct emu_dim3 {
     unsigned x, y, z;
@@ -68,6 +70,33 @@ inline int emu_readfirstlane(int v) {
     return first;
 }
 #define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((int)(v))
+
+// DPP lane moves (the controls the kernels use: quad_perm, row_mirror, row_half_mirror, row_bcast:15,
+// row_bcast:31).  A lane of a row or bank outside the masks keeps `old`; a lane with no source lane
+// keeps `old` unless bound_ctrl, then 0.
+extern int emu_dpp_slot[16][64];
+void emu_dpp_unsupported(int ctrl);
+inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    const unsigned t = threadIdx.x, w = t >> 6, l = t & 63u, row = l >> 4;
+    emu_dpp_slot[w][l] = src;
+    emu_wave_barrier();
+    int s = -1;
+    if (ctrl >= 0 && ctrl <= 0xff) s = static_cast<int>((l & ~3u) + ((static_cast<unsigned>(ctrl) >> (2 * (l & 3u))) & 3u));
+    else if (ctrl == 0x140) s = static_cast<int>((row << 4) + (15u - (l & 15u)));
+    else if (ctrl == 0x141) s = static_cast<int>((l & ~7u) + (7u - (l & 7u)));
+    else if (ctrl == 0x142) s = row >= 1 ? static_cast<int>(row << 4) - 1 : -1;
+    else if (ctrl == 0x143) s = row >= 2 ? 31 : -1;
+    else emu_dpp_unsupported(ctrl);
+    int r = old;
+    if (((row_mask >> row) & 1) && ((bank_mask >> ((l >> 2) & 3u)) & 1)) {
+        if (s >= 0) r = emu_dpp_slot[w][s];
+        else if (bound_ctrl) r = 0;
+    }
+    emu_wave_barrier();
+    return r;
+}
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, row_mask, bank_mask, bound) \
+    emu_update_dpp((old), (src), (ctrl), (row_mask), (bank_mask), (bound))
 #define __builtin_amdgcn_sched_barrier(mask) ((void)0)  /* instruction scheduling only */
 
 inline unsigned long long __umul64hi(unsigned long long a, unsigned long long b) {

@@ -27,7 +27,8 @@ CACHE = os.path.join(tempfile.gettempdir(), "mrmf_emu_cache")
 
 TUNING = {"schedule": L.MRMF_TUNE_SCHEDULE, "branch_skip": L.MRMF_TUNE_BRANCH_SKIP,
           "load_group": L.MRMF_TUNE_LOAD_GROUP, "blocks_per_cu": L.MRMF_TUNE_BLOCKS_PER_CU,
-          "variant": L.MRMF_TUNE_VARIANT, "addressing": L.MRMF_TUNE_ADDRESSING}
+          "variant": L.MRMF_TUNE_VARIANT, "addressing": L.MRMF_TUNE_ADDRESSING,
+          "far_loads": L.MRMF_TUNE_FAR_LOADS}
 
 
 def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True,
@@ -72,6 +73,9 @@ def _compile(src: str) -> ctypes.CDLL:
                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_range.restype = ctypes.c_int
     lib.emu_run_range.argtypes = lib.emu_run.argtypes + [ctypes.c_uint, ctypes.c_uint]
+    lib.emu_run_grad.restype = ctypes.c_int
+    lib.emu_run_grad.argtypes = [ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_cheb.restype = ctypes.c_int
     lib.emu_run_cheb.argtypes = ([ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
@@ -130,3 +134,22 @@ def run_cheb(model, x: np.ndarray, prev: np.ndarray, acc: np.ndarray, ea: float,
     if rc != 0:
         raise RuntimeError(f"emu_run_cheb failed: {rc}")
     return pv, av
+
+
+def run_grad(model, x: np.ndarray, g: np.ndarray, grid: int):
+    """The adjoint kernel generated for the plan (c128), emulated on the CPU: (grad_x = H g, per-block
+    partial sums [grid][n_params] whose column sums are Re <g | h_p x>)."""
+    src = kernel_source(model, L.MRMF_SOURCE_GRAD)
+    if src is None:
+        raise ValueError("the plan does not qualify for the generated adjoint kernel")
+    lib = _compile(src)
+    th = np.ascontiguousarray(model.theta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.complex128)
+    gg = np.ascontiguousarray(g, dtype=np.complex128)
+    gx = np.full_like(xx, np.nan)
+    part = np.full((grid, len(model.theta)), np.nan)
+    rc = lib.emu_run_grad(grid, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, gg.ctypes.data, gx.ctypes.data,
+                          part.ctypes.data, part.nbytes)
+    if rc != 0:
+        raise RuntimeError(f"emu_run_grad failed: {rc}")
+    return gx, part

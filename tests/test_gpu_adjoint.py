@@ -1,5 +1,6 @@
 """The hand-written adjoint (mrmf_adjoint_z behind MatvecFn) against the oracle's gradient formulas,
-central finite differences of the GPU loss, and torch.autograd.gradcheck."""
+central finite differences of the GPU loss, and torch.autograd.gradcheck; both forms (the plan's matvec
+plus the generated coupling-gradient kernel, and the generic fused gather pass)."""
 import numpy as np
 import pytest
 import torch
@@ -22,15 +23,20 @@ def t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+@pytest.mark.parametrize("kind", ["auto", "generic"])
 @pytest.mark.parametrize("seed", range(8))
-def test_adjoint_random_models(seed):
+def test_adjoint_random_models(seed, kind):
     rng = np.random.default_rng(9000 + seed)
     m = W.random_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=6000, n_params=int(rng.integers(1, 40)),
                        n_terms=int(rng.integers(4, 40)))
-    print(f"seed={seed} D={m.dim} params={m.n_params} terms={len(m.terms)}", flush=True)
+    print(f"seed={seed} kind={kind} D={m.dim} params={m.n_params} terms={len(m.terms)}", flush=True)
     x = W.random_state(m.dim, rng)
     g = W.random_state(m.dim, rng)
     p = mk(m)
+    if kind == "generic":
+        p.set_kernel("generic")
+    else:
+        assert p.grad_kernel_ready()
     gx, gt = p.adjoint(t(m.theta), t(x), t(g))
     rgx, rgt = ograd.adjoint(m, x, g)
     assert rel_err(gx.cpu().numpy(), rgx) <= 1e-12
@@ -48,6 +54,7 @@ def test_tavis_cummings_rayleigh_gradients():
     the Hellmann-Feynman closed forms and central finite differences in FP64."""
     m, x = W.config(5)
     p = mk(m)
+    assert p.grad_kernel_ready()
     theta = t(m.theta).requires_grad_(True)
     xt = t(x).requires_grad_(True)
     L = loss_torch(p, theta, xt)
@@ -97,3 +104,22 @@ def test_adjoint_rejects_non_hermitian():
     with pytest.raises(L.MrmfError) as e:
         p.adjoint(t(m.theta), x, x.clone())
     assert e.value.status == L.MRMF_E_NOT_HERMITIAN
+
+
+@pytest.mark.parametrize("n_params,bpc", [(60, 0), (48, 8), (7, 1)])
+def test_adjoint_parameter_counts(n_params, bpc):
+    """Beyond 48 parameters the generic pass runs; at the limit and below, the generated kernel with eight
+    blocks per CU and with one (D = 82,944 on 256 blocks: a ragged second row per thread)."""
+    rng = np.random.default_rng(9100 + n_params)
+    m = W.random_model(rng, n_sites=10, max_dim=500000, n_params=n_params, n_terms=70)
+    x, g = W.random_state(m.dim, rng), W.random_state(m.dim, rng)
+    p = mk(m)
+    p.set_tuning(grad_blocks_per_cu=bpc)
+    assert p.grad_kernel_ready() == (n_params <= 48)
+    print(f"D={m.dim} params={m.n_params} terms={len(m.terms)} bpc={bpc}", flush=True)
+    gx, gt = p.adjoint(t(m.theta), t(x), t(g))
+    rgx, rgt = ograd.adjoint(m, x, g)
+    assert rel_err(gx.cpu().numpy(), rgx) <= 1e-12
+    assert np.max(np.abs(gt.cpu().numpy() - rgt)) <= 1e-12 * max(1.0, np.max(np.abs(rgt)))
+    gx2, gt2 = p.adjoint(t(m.theta), t(x), t(g))                       # deterministic: same bits again
+    assert torch.equal(gx, gx2) and torch.equal(gt, gt2)

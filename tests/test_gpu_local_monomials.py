@@ -186,3 +186,19 @@ def test_aklt_lanczos(N):
     r = p.lanczos(torch.from_numpy(m.theta).to(DEV), torch.from_numpy(x).to(DEV), 80)["result"].cpu().numpy()
     print(N, r, flush=True)
     assert abs(r[0] + 2 * N / 3) <= 1e-9 and r[2] <= 1e-5
+
+
+def test_autotune_general_operator_plan():
+    """Every candidate shape of the specialized kernel compiles and runs for a plan built from general
+    operators (AKLT, N = 12); the chosen one reproduces the oracle."""
+    from paper_2606_02169_amd.plan import Plan
+    m = W.bilinear_biquadratic_chain(12, 1 / 3)
+    x = W.random_state(m.dim, np.random.default_rng(12))
+    p = Plan.from_model(m)
+    th = torch.from_numpy(m.theta).to(DEV)
+    xt = torch.from_numpy(x).to(DEV)
+    tuned = p.autotune(th, xt, use_cache=False)
+    print(tuned, flush=True)
+    rows = np.unique(np.random.default_rng(1).choice(m.dim, 2000, replace=False)).astype(np.int64)
+    y = p.matvec(th, xt)
+    assert rel_err(y[torch.from_numpy(rows).to(DEV)].cpu().numpy(), mf.matvec(m, x, rows=rows)) <= TOL_Z

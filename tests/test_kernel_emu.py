@@ -65,7 +65,8 @@ def test_random_models(seed):
                                          ({"branch_skip": 1, "schedule": 1, "load_group": 3}, 16),
                                          ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5),
                                          ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7),
-                                         ({"addressing": 1}, 8), ({"addressing": 1, "variant": 1}, 6)])
+                                         ({"addressing": 1}, 8), ({"addressing": 1, "variant": 1}, 6),
+                                         ({"far_loads": 10}, 8), ({"far_loads": 12, "addressing": 1}, 8)])
 def test_tuning_variants(tuning, grid):
     m, x = W.config(2, reduced=12)
     check(m, x, tuning=tuning, grid=grid)
@@ -157,3 +158,37 @@ def test_aklt_chain_emulated():
     x = W.random_state(m.dim, np.random.default_rng(5))
     check(m, x, tuning={"variant": 1})
     check(m, x.astype(np.complex64), unrolled=1)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_adjoint_kernel(seed):
+    """The adjoint kernel generated for the plan: grad_x = H g over every row, and the column sums of its
+    per-block partials equal Re <g | h_p x> of the oracle, with grids of one row per thread and of several
+    rows per thread (ragged last pass); built-in and general one-site operators, real and complex weights."""
+    from oracle import grad as ograd
+    rng = np.random.default_rng(7600 + seed)
+    if seed % 2 == 0:
+        m = W.random_model(rng, n_sites=int(rng.integers(2, 7)), max_dim=3000, n_params=int(rng.integers(1, 6)),
+                           n_terms=14)
+    else:
+        m = W.random_general_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=3000, n_params=4)
+    x, g = W.random_state(m.dim, rng), W.random_state(m.dim, rng)
+    rgx, ref = ograd.adjoint(m, x, g)
+    for grid in ((m.dim + 255) // 256, 2):
+        gx, part = E.run_grad(m, x, g, grid)
+        assert part.shape == (grid, m.n_params) and np.all(np.isfinite(part))
+        assert rel_err(gx, rgx) <= 1e-12
+        assert np.max(np.abs(part.sum(0) - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_adjoint_kernel_tavis_cummings():
+    """Spins with a large boson (d = 17: factor tables in LDS, decode by reciprocal), 24 channels in two
+    gather groups, on the generated adjoint kernel."""
+    from oracle import grad as ograd
+    rng = np.random.default_rng(7700)
+    m = W.tavis_cummings(12, 16, 1.0, 0.9, rng)
+    x, g = W.random_state(m.dim, rng), W.random_state(m.dim, rng)
+    rgx, ref = ograd.adjoint(m, x, g)
+    gx, part = E.run_grad(m, x, g, 3)
+    assert rel_err(gx, rgx) <= 1e-12
+    assert np.max(np.abs(part.sum(0) - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
