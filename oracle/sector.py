@@ -49,5 +49,9 @@ def dense(model, Q: int, theta=None) -> np.ndarray:
     """The restricted Hamiltonian as a dense matrix (small sectors)."""
     lab = labels(model, Q)
     n = lab.size
-    cols = [matvec(model, Q, np.eye(n, dtype=np.complex128)[:, k], theta, lab) for k in range(n)]
+    cols = []
+    for k in range(n):                  # column k = the restricted map applied to unit vector k
+        e = np.zeros(n, dtype=np.complex128)
+        e[k] = 1.0
+        cols.append(matvec(model, Q, e, theta, lab))
     return np.stack(cols, axis=1) if n else np.zeros((0, 0), dtype=np.complex128)

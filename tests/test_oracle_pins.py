@@ -12,7 +12,11 @@ from oracle import grad, kron, lanczos, mf
 
 def dense_from_mf(model, theta=None):
     D = model.dim
-    cols = [mf.matvec(model, np.eye(D, dtype=np.complex128)[:, k], theta=theta) for k in range(D)]
+    cols = []
+    for k in range(D):
+        e = np.zeros(D, dtype=np.complex128)
+        e[k] = 1.0
+        cols.append(mf.matvec(model, e, theta=theta))
     return np.stack(cols, axis=1)
 
 
