@@ -377,7 +377,8 @@ mrmf_status mrmf_batch_offsets(mrmf_batch batch, int64_t* out);       /* host in
 mrmf_status mrmf_batch_theta_offsets(mrmf_batch batch, int32_t* out); /* host int32[n + 1] */
 mrmf_status mrmf_batch_workspace_bytes(mrmf_batch batch, size_t* bytes);
 mrmf_status mrmf_batch_upload(mrmf_batch batch, void* d_ws, size_t ws_bytes, mrmf_stream stream);
-/* Y_b = H_b X_b for every lattice b, one launch. */
+/* Y_b = H_b X_b for every lattice b, one launch.  d_X, d_Y: 16-byte aligned (8-byte when nvec = 1), not
+ * overlapping; d_ws 256-byte aligned. */
 mrmf_status mrmf_batch_matvec_c(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
                                 const void* d_X, void* d_Y, mrmf_stream stream);
 /* Capture the batched launch (and its work-list reset) into a hipGraph owned by the batch, for the
@@ -385,9 +386,10 @@ mrmf_status mrmf_batch_matvec_c(mrmf_batch batch, const void* d_ws, const float*
 mrmf_status mrmf_batch_graph_capture(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
                                      const void* d_X, void* d_Y, mrmf_stream stream);
 mrmf_status mrmf_batch_graph_launch(mrmf_batch batch, mrmf_stream stream);
-/* Autotuner: times each candidate launch shape (tile-row limit, threads per block) on the given
- * buffers with HIP events, keeps the fastest for this batch, and writes host out[0..2] = (tile-row
- * limit, block threads, candidate index).  Synchronises the stream. */
+/* Autotuner: times each candidate launch shape (tile-row limit, threads per block, schedule) on the
+ * given buffers with HIP events, keeps the fastest for this batch, and writes host out[0..2] = (tile-row
+ * limit, block threads, candidate index); mrmf_batch_get_shape reports the schedule chosen.
+ * Synchronises the stream. */
 mrmf_status mrmf_batch_autotune(mrmf_batch batch, const void* d_ws, const float* d_theta_all,
                                 const void* d_X, void* d_Y, mrmf_stream stream, int32_t* out);
 /* Set a launch shape directly (e.g. from a tuning cache).  Each lattice's rows are cut into tiles spanned
@@ -395,6 +397,16 @@ mrmf_status mrmf_batch_autotune(mrmf_batch batch, const void* d_ws, const float*
  * max(1, block / T) such tiles in LDS at a time.  block_threads: a multiple of 64, at most 512 and at
  * most 4096 / nvec. */
 mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t tile_rows_max, int32_t block_threads);
+/* Work schedule of the persistent grid over the work items (a block's tiles, numbered lattice by
+ * lattice): MRMF_BATCH_SCHED_RUNS (default) - each block takes a contiguous run of items, the runs of
+ * one XCD adjacent; MRMF_BATCH_SCHED_WINDOWS - the grid sweeps windows of consecutive items, each XCD
+ * taking one eighth of every window, so that the items one XCD holds at a time are neighbours (their
+ * cross-tile gathers meet in that XCD's L2).  Results are identical. */
+#define MRMF_BATCH_SCHED_RUNS 0
+#define MRMF_BATCH_SCHED_WINDOWS 1
+mrmf_status mrmf_batch_set_schedule(mrmf_batch batch, int32_t sched);
+/* Host out[0..3] = (tile-row limit, block threads, schedule, grid blocks) of the current launch shape. */
+mrmf_status mrmf_batch_get_shape(mrmf_batch batch, int32_t* out);
 
 #ifdef __cplusplus
 }

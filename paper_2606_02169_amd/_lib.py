@@ -33,6 +33,7 @@ MRMF_TUNE_FAR_LOADS = 8
 MRMF_TUNE_GRAD_BLOCKS_PER_CU = 9
 MRMF_SOURCE_CHEB = 2
 MRMF_SOURCE_GRAD = 3
+MRMF_BATCH_SCHED_RUNS, MRMF_BATCH_SCHED_WINDOWS = 0, 1
 MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 
 
@@ -126,6 +127,8 @@ SIGNATURES = {
     "mrmf_batch_graph_launch": (_i32, [_vp, _vp]),
     "mrmf_batch_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _P(_i32)]),
     "mrmf_batch_set_shape": (_i32, [_vp, _i32, _i32]),
+    "mrmf_batch_set_schedule": (_i32, [_vp, _i32]),
+    "mrmf_batch_get_shape": (_i32, [_vp, _P(_i32)]),
 }
 
 _lib = None

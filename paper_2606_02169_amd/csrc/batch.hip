@@ -10,9 +10,13 @@
 // Work.  For a launch shape (R_max, block B), lattice b's rows are cut into tiles spanned by its low
 // sites (T_b = prod of the low d_i, the largest such product <= R_max), and an item is the P = max(1,
 // B / T_b) consecutive tiles that one block holds in LDS at a time (rows stored vector-major, so that
-// consecutive threads read consecutive 8-byte words).  Items are numbered lattice by lattice; block v of
-// the grid takes the contiguous item range [v I / G, (v+1) I / G), v chosen so that the blocks of one XCD
-// (block b runs on XCD b mod 8) hold neighbouring ranges.  Every thread owns rows of the item; for each
+// consecutive threads read consecutive 8-byte words).  Items are numbered lattice by lattice.  Two
+// schedules: runs - block v of the grid takes the contiguous item range [v I / G, (v+1) I / G), v chosen
+// so that the blocks of one XCD (block b runs on XCD b mod 8) hold neighbouring ranges; windows - the
+// grid sweeps windows of G consecutive items, the blocks of one XCD taking one eighth of each window side
+// by side, so that the items an XCD works on at one time are neighbours and the gathers of one item find
+// the rows its neighbours have just read in the XCD's L2 (at the price of reloading a lattice's
+// descriptors whenever a block moves to another lattice).  Every thread owns rows of the item; for each
 // row it decodes the digits once into LDS, then for every channel forms the coefficient from the
 // per-site factor tables (zero where a source digit is inadmissible, App. A) and, where it is nonzero,
 // reads the nvec source amplitudes of row F - Delta: from LDS when both sites of the channel lie in the
@@ -78,10 +82,38 @@ __device__ __forceinline__ uint32_t umulhi_div(uint32_t n, uint64_t magic) {
     return static_cast<uint32_t>(__umul64hi(magic, static_cast<uint64_t>(n)));
 }
 
+// The NV amplitudes of one row (NV * 8 contiguous bytes; 16-byte aligned when NV >= 2) in 16-byte loads
+// and stores where the row allows it.
+template <int NV>
+__device__ __forceinline__ void load_row(const float2* __restrict__ src, float2 (&v)[NV]) {
+    if constexpr (NV == 1) {
+        v[0] = src[0];
+    } else {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+        for (int q = 0; q < NV / 2; ++q) {
+            const float4 w = s4[q];
+            v[2 * q] = make_float2(w.x, w.y);
+            v[2 * q + 1] = make_float2(w.z, w.w);
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_row(float2* __restrict__ dst, const float (&re)[NV], const float (&im)[NV]) {
+    if constexpr (NV == 1) {
+        dst[0] = make_float2(re[0], im[0]);
+    } else {
+        float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+        for (int q = 0; q < NV / 2; ++q) d4[q] = make_float4(re[2 * q], im[2 * q], re[2 * q + 1], im[2 * q + 1]);
+    }
+}
+
 template <int NV, bool CPLX>
 __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const float* __restrict__ theta_all,
                                                         const float2* __restrict__ X, float2* __restrict__ Y,
-                                                        int32_t rc) {
+                                                        int32_t rc, int32_t sched) {
     constexpr int kRows = kBatchTileWords / NV;
     __shared__ int32_t ibeg[kBatchMaxLattices + 1];
     __shared__ float pool[kBatchPoolMax];
@@ -111,7 +143,10 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const int64_t I = ibeg[A.n_lat];
     const unsigned G = gridDim.x, bid = blockIdx.x;
     const unsigned v = (G % 8u == 0u) ? (bid % 8u) * (G / 8u) + bid / 8u : bid;
-    const int32_t i0 = static_cast<int32_t>(int64_t(v) * I / G), i1 = static_cast<int32_t>(int64_t(v + 1) * I / G);
+    const bool windows = sched == 1;
+    const int32_t i0 = windows ? static_cast<int32_t>(v) : static_cast<int32_t>(int64_t(v) * I / G);
+    const int32_t i1 = windows ? static_cast<int32_t>(I) : static_cast<int32_t>(int64_t(v + 1) * I / G);
+    const int32_t step = windows ? static_cast<int32_t>(G) : 1;
     // the current lattice's descriptor, kept in scalar registers (every field is block-uniform)
     int lb = -1;
     int32_t N = 0, n_chan = 0, n_diag = 0, D = 0, rows = 1, ks = 0;
@@ -126,7 +161,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
         }
         b = lo;
     }
-    for (int32_t it = i0; it < i1; ++it) {
+    for (int32_t it = i0; it < i1; it += step) {
         while (it >= ibeg[b + 1]) ++b;
         b = __builtin_amdgcn_readfirstlane(b);
         __syncthreads();  // every thread is done with the previous item's tile (and tables)
@@ -155,9 +190,10 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
         const int32_t r0 = (it - ibeg[b]) * rows;
         const int32_t nr = r0 + rows < D ? rows : D - r0;
         for (int32_t r = tid; r < nr; r += B) {
-            const float2* src = xb + int64_t(r0 + r) * NV;
+            float2 v[NV];
+            load_row<NV>(xb + int64_t(r0 + r) * NV, v);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) xt[q][r] = src[q];
+            for (int q = 0; q < NV; ++q) xt[q][r] = v[q];
         }
         __syncthreads();
         for (int32_t r = tid; r < nr; r += B) {
@@ -208,10 +244,11 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
                         }
                     }
                 } else {
-                    const float2* src = xb + int64_t(F - t.delta) * NV;
+                    float2 v[NV];
+                    load_row<NV>(xb + int64_t(F - t.delta) * NV, v);
 #pragma unroll
                     for (int q = 0; q < NV; ++q) {
-                        const float2 s = src[q];
+                        const float2 s = v[q];
                         ar[q] += cr * s.x;
                         ai[q] += cr * s.y;
                         if (CPLX) {
@@ -221,9 +258,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
                     }
                 }
             }
-            float2* dst = yb + int64_t(F) * NV;
-#pragma unroll
-            for (int q = 0; q < NV; ++q) dst[q] = make_float2(ar[q], ai[q]);
+            store_row<NV>(yb + int64_t(F) * NV, ar, ai);
         }
     }
 }
@@ -268,6 +303,7 @@ struct mrmf_batch_t {
     std::vector<unsigned char> image;
     size_t off_lat = 0, off_site = 0, off_term = 0, off_pool = 0, ws_bytes = 0;
     int32_t rc = 2, block = 256;  // R_max candidate index and block threads
+    int32_t sched = 0;            // MRMF_BATCH_SCHED_*
     int32_t grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -304,16 +340,17 @@ mrmf_status launch(mrmf_batch_t* b, const void* d_ws, const float* theta, const 
     void* fn = mrmf::batch_kernel(b->nvec, !b->all_real);
     const int grid = batch_grid(b);
     b->grid = grid;
-    int32_t rc = b->rc;
+    int32_t rc = b->rc, sched = b->sched;
     const float2* xp = static_cast<const float2*>(X);
     float2* yp = static_cast<float2*>(Y);
-    void* args[] = {const_cast<mrmf::BatchArgs*>(&a), &theta, &xp, &yp, &rc};
+    void* args[] = {const_cast<mrmf::BatchArgs*>(&a), &theta, &xp, &yp, &rc, &sched};
     return mrmf::hip_status(hipLaunchKernel(fn, dim3(grid), dim3(b->block), args, 0, s));
 }
 
 mrmf_status check_call(const mrmf_batch_t* b, const void* d_ws, const float* th, const void* X, const void* Y) {
     if (!b || !d_ws || !th || !X || !Y) return MRMF_E_INVALID_ARG;
-    if (!mrmf::aligned(d_ws, 256) || !mrmf::aligned(X, 8) || !mrmf::aligned(Y, 8)) return MRMF_E_INVALID_ARG;
+    const size_t al = b->nvec >= 2 ? 16 : 8;  // rows are moved in 16-byte words when they hold two or more
+    if (!mrmf::aligned(d_ws, 256) || !mrmf::aligned(X, al) || !mrmf::aligned(Y, al)) return MRMF_E_INVALID_ARG;
     const size_t bytes = size_t(b->total) * 8;
     if (mrmf::ranges_overlap(X, bytes, Y, bytes)) return MRMF_E_INVALID_ARG;
     return MRMF_OK;
@@ -520,6 +557,21 @@ mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t tile_rows_max, int32_t bl
     return MRMF_OK;
 }
 
+mrmf_status mrmf_batch_set_schedule(mrmf_batch b, int32_t sched) {
+    if (!b || (sched != MRMF_BATCH_SCHED_RUNS && sched != MRMF_BATCH_SCHED_WINDOWS)) return MRMF_E_INVALID_ARG;
+    b->sched = sched;
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_batch_get_shape(mrmf_batch b, int32_t* out) {
+    if (!b || !out) return MRMF_E_INVALID_ARG;
+    out[0] = mrmf::rmax_of(b->rc, b->nvec);
+    out[1] = b->block;
+    out[2] = b->sched;
+    out[3] = batch_grid(b);
+    return MRMF_OK;
+}
+
 mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_theta_all, const void* d_X,
                                 void* d_Y, mrmf_stream stream, int32_t* out) {
     mrmf_status st = check_call(b, d_ws, d_theta_all, d_X, d_Y);
@@ -534,10 +586,12 @@ mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_t
     }
     float best = 0.f;
     int best_i = -1;
-    const int32_t R0 = b->rc, B0 = b->block;
-    for (int i = 0; i < mrmf::kNumShapes && st == MRMF_OK; ++i) {
-        b->rc = mrmf::kShapes[i].rc;
-        b->block = mrmf::kShapes[i].block;
+    const int32_t R0 = b->rc, B0 = b->block, S0 = b->sched;
+    // candidates: every shape with the runs schedule, then every shape with the windows schedule
+    for (int i = 0; i < 2 * mrmf::kNumShapes && st == MRMF_OK; ++i) {
+        b->rc = mrmf::kShapes[i % mrmf::kNumShapes].rc;
+        b->block = mrmf::kShapes[i % mrmf::kNumShapes].block;
+        b->sched = i / mrmf::kNumShapes;
         if (b->block > mrmf::kBatchTileWords / b->nvec) continue;
         st = launch(b, d_ws, d_theta_all, d_X, d_Y, s);  // warm-up
         if (st != MRMF_OK) break;
@@ -557,10 +611,12 @@ mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_t
     if (best_i < 0) {
         b->rc = R0;
         b->block = B0;
+        b->sched = S0;
         return st != MRMF_OK ? st : MRMF_E_HIP;
     }
-    b->rc = mrmf::kShapes[best_i].rc;
-    b->block = mrmf::kShapes[best_i].block;
+    b->rc = mrmf::kShapes[best_i % mrmf::kNumShapes].rc;
+    b->block = mrmf::kShapes[best_i % mrmf::kNumShapes].block;
+    b->sched = best_i / mrmf::kNumShapes;
     out[0] = mrmf::rmax_of(b->rc, b->nvec);
     out[1] = b->block;
     out[2] = best_i;

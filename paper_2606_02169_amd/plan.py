@@ -408,12 +408,21 @@ class Batch:
         out = (ctypes.c_int32 * 3)()
         L.call("mrmf_batch_autotune", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
                _stream(self.device), out)
-        return dict(tile_rows_max=out[0], block=out[1], candidate=out[2])
+        return dict(self.shape(), candidate=out[2])
 
-    def set_shape(self, tile_rows_max: int, block: int):
-        """Launch shape: tiles of at most tile_rows_max rows ((64, 128, 256, 512) * 8 / nvec) and block
-        threads (a multiple of 64, at most 512 and 4096 / nvec)."""
+    def set_shape(self, tile_rows_max: int, block: int, schedule: str | None = None):
+        """Launch shape: tiles of at most tile_rows_max rows ((64, 128, 256, 512) * 8 / nvec), block
+        threads (a multiple of 64, at most 512 and 4096 / nvec) and, when given, the work schedule
+        ("runs": a contiguous run of items per block; "windows": consecutive items side by side)."""
         L.call("mrmf_batch_set_shape", self._handle, int(tile_rows_max), int(block))
+        if schedule is not None:
+            L.call("mrmf_batch_set_schedule", self._handle,
+                   {"runs": L.MRMF_BATCH_SCHED_RUNS, "windows": L.MRMF_BATCH_SCHED_WINDOWS}[schedule])
+
+    def shape(self) -> dict:
+        out = (ctypes.c_int32 * 4)()
+        L.call("mrmf_batch_get_shape", self._handle, out)
+        return dict(tile_rows_max=out[0], block=out[1], schedule=("runs", "windows")[out[2]], grid=out[3])
 
 
 def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, theta_c, keep_basis) -> dict:

@@ -95,7 +95,10 @@ def test_batch_full_size_sampled():
     dims = [m.dim for m in models]
     print(f"lattices {len(models)} sum D {sum(dims)} max D {max(dims)} min D {min(dims)}", flush=True)
     B, X, th = build(models, xs)
-    Y = B.matvec(th, X)
+    B.set_shape(512, 512, "runs")
+    Y = B.matvec(th, X).clone()
+    B.set_shape(512, 512, "windows")
+    assert torch.equal(B.matvec(th, X), Y)       # same rows, same arithmetic: identical bits
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
 
@@ -113,13 +116,36 @@ def test_batch_full_size_sampled():
             assert rel_err(yb[r, v], ref) <= TOL_C, (b, v)
 
 
+@pytest.mark.parametrize("schedule", ["runs", "windows"])
 @pytest.mark.parametrize("rmax,block", [(64, 64), (128, 128), (512, 256), (512, 512), (256, 512)])
-def test_batch_every_shape(rmax, block):
-    """Each launch shape (tiles of at most rmax rows held in LDS, block threads) gives the oracle's
-    result, including tiles smaller than the block (several tiles per item) and larger ones."""
+def test_batch_every_shape(rmax, block, schedule):
+    """Each launch shape (tiles of at most rmax rows held in LDS, block threads, work schedule) gives the
+    oracle's result, including tiles smaller than the block (several tiles per item) and larger ones."""
     models, xs = W.config(4, reduced=12)
     B, X, th = build(models, xs)
-    B.set_shape(rmax, block)
+    B.set_shape(rmax, block, schedule)
+    assert B.shape()["schedule"] == schedule
     Y = B.matvec(th, X)
     torch.cuda.synchronize()
     check_all(B, models, xs, Y)
+
+
+@pytest.mark.parametrize("nvec", [1, 2, 4])
+def test_batch_vector_counts_and_alignment(nvec):
+    """nvec = 1, 2, 4 against the oracle (rows moved in 8-byte words for one vector, 16-byte words
+    otherwise); with two or more vectors a block that is only 8-byte aligned is refused, nothing launched."""
+    from paper_2606_02169_amd import _lib as L
+    from paper_2606_02169_amd.plan import _ptr, _stream
+    rng = np.random.default_rng(40 + nvec)
+    models = W.config(4, reduced=6, with_state=False)[0]
+    xs = [W.random_state(m.dim, rng, np.complex64, nvec=nvec) for m in models]
+    B, X, th = build(models, xs, nvec=nvec)
+    B.set_shape(64 * 8 // nvec, 64, "windows")
+    Y = B.matvec(th, X)
+    torch.cuda.synchronize()
+    check_all(B, models, xs, Y)
+    Xs = torch.zeros(B.total_elems + 1, dtype=torch.complex64, device=DEV)[1:]   # 8-byte aligned only
+    Ys = torch.empty(B.total_elems + 1, dtype=torch.complex64, device=DEV)[1:]
+    st = L.lib().mrmf_batch_matvec_c(B._handle, _ptr(B.ws), _ptr(th), _ptr(Xs), _ptr(Ys), _stream(DEV))
+    assert st == (L.MRMF_OK if nvec == 1 else L.MRMF_E_INVALID_ARG)
+    torch.cuda.synchronize()
