@@ -42,6 +42,7 @@ constexpr int kBatchTileWords = 4096;  // 8-byte words of the LDS tile (32 KB): 
 constexpr int kBatchRmaxCands = 4;     // tile-row limits R_max = (64, 128, 256, 512) * 8 / nvec
 constexpr int kBatchMaxTerms = 128;    // terms (channels + diagonal) of one lattice, held in LDS
 constexpr int kBatchMaxParams = 128;   // couplings of one lattice, held in LDS
+constexpr int kBatchGather = 4;        // global-memory channels whose gathers are issued together
 
 struct alignas(16) BLat {
     int32_t N, n_chan, n_diag, theta_off;
@@ -50,8 +51,9 @@ struct alignas(16) BLat {
     int64_t x_off, pad2;
     int32_t tile_rows[kBatchRmaxCands];   // T_b for each R_max candidate
     int32_t tile_sites[kBatchRmaxCands];  // number of low sites spanning T_b
+    int32_t n_local[kBatchRmaxCands];     // channels whose source lies in the tile (a prefix of the list)
 };
-static_assert(sizeof(BLat) == 96, "BLat layout");
+static_assert(sizeof(BLat) == 112, "BLat layout");
 
 struct alignas(16) BSite {
     int32_t d, pad;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const int32_t step = windows ? static_cast<int32_t>(G) : 1;
     // the current lattice's descriptor, kept in scalar registers (every field is block-uniform)
     int lb = -1;
-    int32_t N = 0, n_chan = 0, n_diag = 0, D = 0, rows = 1, ks = 0;
+    int32_t N = 0, n_chan = 0, n_diag = 0, D = 0, rows = 1, ks = 0, n_loc = 0;
     const float2* xb = X;
     float2* yb = Y;
     int b = 0;
@@ -173,6 +175,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
             D = __builtin_amdgcn_readfirstlane(L->D);
             const int32_t T = __builtin_amdgcn_readfirstlane(L->tile_rows[rc]);
             ks = __builtin_amdgcn_readfirstlane(L->tile_sites[rc]);
+            n_loc = __builtin_amdgcn_readfirstlane(L->n_local[rc]);
             rows = T >= B ? T : (B / T) * T;
             const int64_t xo = L->x_off;
             xb = X + xo;
@@ -225,35 +228,60 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
                     ai[q] += di * s.x;
                 }
             }
-            for (int k = 0; k < n_chan; ++k) {
+            // channels whose sites both lie in the tile (the first n_loc): the source row is in LDS
+            // (Eq. sourceoffset)
+            for (int k = 0; k < n_loc; ++k) {
                 const BTerm t = tl[n_diag + k];
                 const float fa = pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
                 if (fa == 0.f) continue;  // an inadmissible source digit has factor 0 (App. A)
                 const float c = thl[t.param] * fa;
                 const float cr = c * t.wr, ci = CPLX ? c * t.wi : 0.f;
-                if (t.low <= ks) {  // both sites in the tile: the source row is in LDS (Eq. sourceoffset)
-                    const int32_t rs = r - t.delta;
+                const int32_t rs = r - t.delta;
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) {
-                        const float2 s = xt[q][rs];
-                        ar[q] += cr * s.x;
-                        ai[q] += cr * s.y;
-                        if (CPLX) {
-                            ar[q] -= ci * s.y;
-                            ai[q] += ci * s.x;
+                for (int q = 0; q < NV; ++q) {
+                    const float2 s = xt[q][rs];
+                    ar[q] += cr * s.x;
+                    ai[q] += cr * s.y;
+                    if (CPLX) {
+                        ar[q] -= ci * s.y;
+                        ai[q] += ci * s.x;
+                    }
+                }
+            }
+            // the others read global memory, kBatchGather channels at a time: every gather of a group is
+            // issued (masked where the factor is 0) before any of them is used
+            for (int k0 = n_loc; k0 < n_chan; k0 += kBatchGather) {
+                float cr[kBatchGather], ci[kBatchGather];
+                float2 v[kBatchGather][NV];
+#pragma unroll
+                for (int u = 0; u < kBatchGather; ++u) {
+                    cr[u] = 0.f;
+                    ci[u] = 0.f;
+                    if (k0 + u < n_chan) {
+                        const BTerm t = tl[n_diag + k0 + u];
+                        const float fa =
+                            pool[t.ta + dig[t.a][tid]] * (t.b >= 0 ? pool[t.tb + dig[t.b][tid]] : 1.f);
+                        const float c = thl[t.param] * fa;
+                        cr[u] = c * t.wr;
+                        ci[u] = CPLX ? c * t.wi : 0.f;
+                        if (fa != 0.f) {  // a nonzero factor: both source digits in range (App. A)
+                            load_row<NV>(xb + int64_t(F - t.delta) * NV, v[u]);
+                            continue;
                         }
                     }
-                } else {
-                    float2 v[NV];
-                    load_row<NV>(xb + int64_t(F - t.delta) * NV, v);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) v[u][q] = make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int u = 0; u < kBatchGather; ++u) {
 #pragma unroll
                     for (int q = 0; q < NV; ++q) {
-                        const float2 s = v[q];
-                        ar[q] += cr * s.x;
-                        ai[q] += cr * s.y;
+                        const float2 s = v[u][q];
+                        ar[q] += cr[u] * s.x;
+                        ai[q] += cr[u] * s.y;
                         if (CPLX) {
-                            ar[q] -= ci * s.y;
-                            ai[q] += ci * s.x;
+                            ar[q] -= ci[u] * s.y;
+                            ai[q] += ci[u] * s.x;
                         }
                     }
                 }
@@ -431,6 +459,15 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
         L.chan_off = static_cast<int32_t>(terms.size());
         for (const auto& c : p->chans) add_term(c.a, c.opa, c.b, c.opb, c.param, c.wr, c.wi, c.delta);
         L.n_chan = static_cast<int32_t>(p->chans.size());
+        // channels by the number of low sites a tile must span (stable), so that for every tile size the
+        // channels whose source lies in the tile are a prefix of the list
+        std::stable_sort(terms.begin() + L.chan_off, terms.end(),
+                         [](const BTerm& u, const BTerm& v) { return u.low < v.low; });
+        for (int rc = 0; rc < kBatchRmaxCands; ++rc) {
+            int32_t nl = 0;
+            for (size_t k = L.chan_off; k < terms.size(); ++k) nl += terms[k].low <= L.tile_sites[rc];
+            L.n_local[rc] = nl;
+        }
         if (lp.size() > size_t(kBatchPoolMax)) {
             delete b;
             return MRMF_E_UNSUPPORTED;
