@@ -99,3 +99,24 @@ def test_free_fermion_closed_form_large():
     print(f"E0 closed form {e0!r} gpu {g['theta']!r} resid {g['resid']:.2e}")
     assert abs(g["theta"] - e0) <= max(g["resid"], 1e-11)
     assert abs(g["theta"] - e0) < 1e-9
+
+
+def test_long_run_orthonormal_basis():
+    """240 steps on config 1 (D = 4096): the whole basis stays orthonormal to rounding, the first steps agree
+    with the oracle's recurrence (later alpha_j of any two codes part once the ground state has converged),
+    and the Ritz value with the oracle's."""
+    m, x = W.config(1)
+    p = Plan(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda(), 240,
+                    keep_basis=True)
+    torch.cuda.synchronize()
+    res = out["result"].cpu().numpy()
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, 240)
+    assert int(res[3]) == o["steps"] == 240
+    assert abs(res[0] - o["theta"]) <= 1e-12 * abs(o["theta"])
+    a = out["alpha"].cpu().numpy()
+    assert np.max(np.abs(a[:30] - o["alpha"][:30])) < 1e-12
+    V = out["V"].reshape(241, -1)[:240].cpu().numpy()
+    G = V.conj() @ V.T
+    assert np.max(np.abs(G - np.eye(240))) <= 1e-12
