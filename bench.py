@@ -308,7 +308,13 @@ def bench_batched(args, dev):
         B.block(X, b).copy_(torch.from_numpy(np.ascontiguousarray(x)).to(dev))
     Y = torch.empty_like(X)
     th = torch.from_numpy(np.concatenate([m.theta for m in models]).astype(np.float32)).to(dev)
-    shape = B.autotune(th, X, Y)
+    if args.profile:
+        # a short run for profiler counters: the shape the autotuner selects for this workload on MI355X,
+        # warm-up and timed graph replays only
+        B.set_shape(512, 512, "windows")
+        shape = B.shape()
+    else:
+        shape = B.autotune(th, X, Y)
     s = torch.cuda.Stream(device=dev)
     B.capture(th, X, Y, s)
     for _ in range(3):
@@ -335,6 +341,14 @@ def bench_batched(args, dev):
         for v in (0, 7):
             ref = mf.matvec(m, x[:, v].astype(np.complex128), rows=r)
             errs.append(float(np.linalg.norm(yb[r, v] - ref) / np.linalg.norm(ref)))
+    out = {"metric": "batched vector-matvecs/s (256 lattices x 8 c64 vectors, one persistent hipGraph launch)",
+           "workload": "mixed_chains_256x8_c64", "seed": 4, "sum_D": sumD, "vector_matvecs_per_launch": vec_mv,
+           "shape": shape, "ms_per_launch": ms_graph, "vector_matvecs_per_s": vec_mv / ms_graph * 1e3,
+           "effective_GBps": 2 * sumD * 8 * 8 / (ms_graph * 1e-3) / 1e9,
+           "max_rel_err_sampled_vs_fp64_oracle": max(errs)}
+    if args.profile:
+        print(json.dumps(out), flush=True)
+        return
     # separate per-vector launches of the plain forms (contiguous single vectors)
     stream = torch.cuda.current_stream(dev)
     cols_c = [torch.from_numpy(np.ascontiguousarray(x[:, 0])).to(dev) for x in xs]
@@ -359,13 +373,8 @@ def bench_batched(args, dev):
             for p, c, o, t in zip(plans, cols_z, outs_z, ths):
                 p.matvec(t, c, out=o)
     ms_sep_z = cuda_time(sep_z, stream, 1)
-    out = {"metric": "batched vector-matvecs/s (256 lattices x 8 c64 vectors, one persistent hipGraph launch)",
-           "workload": "mixed_chains_256x8_c64", "seed": 4, "sum_D": sumD, "vector_matvecs_per_launch": vec_mv,
-           "shape": shape, "ms_per_launch": ms_graph, "vector_matvecs_per_s": vec_mv / ms_graph * 1e3,
-           "effective_GBps": 2 * sumD * 8 * 8 / (ms_graph * 1e-3) / 1e9,
-           "max_rel_err_sampled_vs_fp64_oracle": max(errs),
-           "separate_c64_calls": {"ms_for_2048": ms_sep_c, "vector_matvecs_per_s": vec_mv / ms_sep_c * 1e3},
-           "separate_c128_calls": {"ms_for_2048": ms_sep_z, "vector_matvecs_per_s": vec_mv / ms_sep_z * 1e3}}
+    out["separate_c64_calls"] = {"ms_for_2048": ms_sep_c, "vector_matvecs_per_s": vec_mv / ms_sep_c * 1e3}
+    out["separate_c128_calls"] = {"ms_for_2048": ms_sep_z, "vector_matvecs_per_s": vec_mv / ms_sep_z * 1e3}
     print(json.dumps(out), flush=True)
 
 
