@@ -342,11 +342,21 @@ void mrmf_sector_destroy(mrmf_sector sector);
 mrmf_status mrmf_sector_dim(mrmf_sector sector, int64_t* dim);
 mrmf_status mrmf_sector_workspace_bytes(mrmf_sector sector, size_t* bytes);
 mrmf_status mrmf_sector_upload(mrmf_sector sector, void* d_ws, size_t ws_bytes, mrmf_stream stream);
-/* y = P H(theta) P^T x on packed sector vectors (c128 / c64, 16-B / 8-B aligned, not overlapping). */
+/* y = P H(theta) P^T x on packed sector vectors (c128 / c64, 16-B / 8-B aligned, not overlapping).
+ * Unless the plan's kernel selection was MRMF_KERNEL_GENERIC when the sector was made, the first call
+ * per element type and device generates and compiles a kernel for this sector (sites, channels, factor
+ * and rank tables compiled in); sectors that do not qualify (more than 64 sites, rank tables over 48 KB,
+ * vectors of 2^31 bytes or more) and generic-mode sectors run the generic kernel. */
 mrmf_status mrmf_sector_matvec_z(mrmf_sector sector, const void* d_ws, const double* d_theta, const void* d_x,
                                  void* d_y, mrmf_stream stream);
 mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const float* d_theta, const void* d_x,
                                  void* d_y, mrmf_stream stream);
+/* Host *used = 1 when the matvec of this element type (MRMF_DTYPE_Z / MRMF_DTYPE_C) runs the generated
+ * sector kernel (built now if it was not yet), 0 when it runs the generic one.  Synchronous. */
+mrmf_status mrmf_sector_generated(mrmf_sector sector, int32_t dtype, int32_t* used);
+/* Source text of the generated sector kernel, for inspection; buffer contract of mrmf_plan_kernel_source.
+ * MRMF_E_UNSUPPORTED when the sector does not qualify.  Host only. */
+mrmf_status mrmf_sector_kernel_source(mrmf_sector sector, int32_t dtype, char* buf, size_t cap, size_t* len);
 /* d_out[i] = full-basis index of packed row r0 + i (int64, device); d_scratch: >= 8 N bytes of device
  * memory the call may overwrite. */
 mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0, int64_t count, int64_t* d_out,

@@ -110,6 +110,8 @@ SIGNATURES = {
     "mrmf_sector_upload": (_i32, [_vp, _vp, _sz, _vp]),
     "mrmf_sector_matvec_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mrmf_sector_matvec_c": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrmf_sector_generated": (_i32, [_vp, _i32, _P(_i32)]),
+    "mrmf_sector_kernel_source": (_i32, [_vp, _i32, _vp, _sz, _P(_sz)]),
     "mrmf_sector_labels": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _sz, _vp]),
     "mrmf_sector_lookup": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "mrmf_sector_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),

@@ -1355,6 +1355,177 @@ std::string grad_source(const mrmf_plan_t* p) {
     return o.str();
 }
 
+// Sector kernel generated for one digit-sum sector (Sec. VI, case 2; App. D) and element type.  One
+// thread per packed row r: unrank r with the combinatorial rank tables (staged in LDS), the digit of site k
+// being the largest v <= min(q_k, d_k - 1) with R_k(q_k, v) <= the rank left, then the diagonal terms and
+// every sum-preserving channel on sites i < j, whose source rank is r plus the change of the table terms
+// of sites i..j (the remaining sums q_k, i < k <= j, move by the channel's shift).  Sites, shifts, factor
+// tables (selects over literals for d <= 3, LDS otherwise) and table offsets are compiled in; a zero factor
+// (source digit out of range) masks the gather to the out-of-range offset, and the table arguments of such
+// a channel are clamped into the tables.  Gathers are issued in groups behind a scheduling barrier.
+std::string sector_source(const mrmf_sector_t* S, int dtype) {
+    const bool f32 = dtype == MRMF_DTYPE_C;
+    const int N = S->N, Q = S->Q, SZ = f32 ? 8 : 16;
+    if (N < 1 || N > 64 || S->Dr < 1 || S->Dr * SZ >= (int64_t(1) << 31)) return "";
+    const bool rt32 = S->rt_max < (int64_t(1) << 31);
+    const size_t rt_bytes = S->rt.size() * (rt32 ? 4 : 8);
+    if (rt_bytes > 48 * 1024) return "";
+    const char* RT = rt32 ? "int" : "long long";
+    std::vector<double> lds;  // factor tables of sites with d > 3
+    size_t at = 0;            // walks S->tfac in the order the tables were built
+    auto factor = [&](int site) -> std::string {
+        const int d = S->d[site];
+        const std::string n = "n" + std::to_string(site);
+        const double* t = S->tfac.data() + at;
+        at += d;
+        std::ostringstream e;
+        if (d == 1) {
+            e << lit(t[0], f32);
+        } else if (d <= 3) {
+            e << "(" << n << " == 0u ? " << lit(t[0], f32) << " : ";
+            if (d == 2) e << lit(t[1], f32) << ")";
+            else e << "(" << n << " == 1u ? " << lit(t[1], f32) << " : " << lit(t[2], f32) << "))";
+        } else {
+            e << "Kl[" << lds.size() << "u + " << n << "]";
+            for (int v = 0; v < d; ++v) lds.push_back(t[v]);
+        }
+        return e.str();
+    };
+    // rank-table entry (site k, remaining sum q, digit v) as an LDS read
+    auto rte = [&](int k, const std::string& q, const std::string& v) {
+        std::ostringstream e;
+        e << "L[" << S->rto[k] << "u + (" << q << ") * " << S->d[k] + 1 << "u + (" << v << ")]";
+        return e.str();
+    };
+    auto clampq = [&](int k, int dq) {
+        std::ostringstream e;
+        e << "(unsigned)clampi((int)q" << k << " - (" << dq << "), " << Q << ")";
+        return e.str();
+    };
+    auto clampd = [&](int k, int shift) {
+        std::ostringstream e;
+        e << "(unsigned)clampi((int)n" << k << " - (" << shift << "), " << S->d[k] - 1 << ")";
+        return e.str();
+    };
+    std::set<int> params;
+    for (const auto& g : S->diags) params.insert(g.param);
+    for (const auto& c : S->chans) params.insert(c.param);
+    std::ostringstream body;
+    body << "    R dr = (R)0, di = (R)0;\n";
+    for (const auto& g : S->diags) {
+        std::string f = factor(g.a);
+        if (g.b >= 0) f = "(" + f + " * " + factor(g.b) + ")";
+        body << "    { const R f = " << f << "; dr = fma(th" << g.param << " * " << lit(g.wr, f32) << ", f, dr);";
+        if (g.wi != 0.0) body << " di = fma(th" << g.param << " * " << lit(g.wi, f32) << ", f, di);";
+        body << " }\n";
+    }
+    body << "    const C xf = LD(xs, r * " << SZ << "u);\n"
+         << "    R ar = dr * xf.x - di * xf.y, ai = dr * xf.y + di * xf.x;\n";
+    const int nch = static_cast<int>(S->chans.size());
+    constexpr int kGroup = 6;
+    const int ngr = (nch + kGroup - 1) / kGroup;
+    const int gsz = ngr > 0 ? (nch + ngr - 1) / ngr : 0;
+    for (int g0 = 0; g0 < nch; g0 += gsz) {
+        const int g1 = std::min(nch, g0 + gsz);
+        body << "    {\n";
+        for (int c = g0; c < g1; ++c) {
+            const DevChan& ch = S->chans[c];
+            const std::string fa = factor(ch.a), fb = factor(ch.b);
+            const bool a_first = ch.a < ch.b;
+            const int i = a_first ? ch.a : ch.b, j = a_first ? ch.b : ch.a;
+            const int si = a_first ? ch.qa : ch.qb, sj = a_first ? ch.qb : ch.qa;  // target - source digit
+            const int dq = -si;  // source digit minus target digit at site i
+            const std::string u = std::to_string(c - g0);
+            body << "      const R f" << u << " = " << fa << " * " << fb << ";\n"
+                 << "      " << RT << " e" << u << " = " << rte(i, "q" + std::to_string(i), clampd(i, si)) << " - "
+                 << rte(i, "q" + std::to_string(i), "n" + std::to_string(i)) << ";\n";
+            for (int k = i + 1; k < j; ++k)
+                body << "      e" << u << " += " << rte(k, clampq(k, dq), "n" + std::to_string(k)) << " - "
+                     << rte(k, "q" + std::to_string(k), "n" + std::to_string(k)) << ";\n";
+            body << "      e" << u << " += " << rte(j, clampq(j, dq), clampd(j, sj)) << " - "
+                 << rte(j, "q" + std::to_string(j), "n" + std::to_string(j)) << ";\n"
+                 << "      const C s" << u << " = LD(xs, f" << u << " != (R)0 ? (unsigned)((" << RT << ")r + e" << u << ") * "
+                 << SZ << "u : OOB);\n";
+        }
+        body << "      __builtin_amdgcn_sched_barrier(0);\n";
+        for (int c = g0; c < g1; ++c) {
+            const DevChan& ch = S->chans[c];
+            const std::string u = std::to_string(c - g0);
+            body << "      { const R cr = th" << ch.param << " * " << lit(ch.wr, f32) << " * f" << u << ";"
+                 << " ar = fma(cr, s" << u << ".x, ar); ai = fma(cr, s" << u << ".y, ai);";
+            if (ch.wi != 0.0)
+                body << " const R ci = th" << ch.param << " * " << lit(ch.wi, f32) << " * f" << u << ";"
+                     << " ar = fma(-ci, s" << u << ".y, ar); ai = fma(ci, s" << u << ".x, ai);";
+            body << " }\n";
+        }
+        // the next group's loads stay behind this group's accumulation (the accumulators pass through an
+        // empty asm that also orders memory), so the gathers in flight per thread are one group's
+        if (g1 < nch) body << "      MRMF_GROUP_FENCE(ar, ai);\n";
+        body << "    }\n";
+    }
+    std::ostringstream o;
+    o << "// generated sector kernel: " << N << " sites, digit sum " << Q << ", " << S->Dr << " packed states, "
+      << S->diags.size() << " diagonal terms, " << nch << " channels\n";
+    if (f32)
+        o << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
+          << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
+          << "#define LD(rs, vo) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64((rs), (int)(vo), 0, 0))\n"
+          << "#define ST(v, rs, vo) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, (v)), (rs), (int)(vo), 0, 2)\n";
+    else
+        o << "typedef double R;\ntypedef double C __attribute__((ext_vector_type(2)));\n"
+          << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
+          << "#define LD(rs, vo) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), 0, 0))\n"
+          << "#define ST(v, rs, vo) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), 0, 2)\n";
+    o << "#define OOB 0x80000000u\n"
+      << "#ifndef MRMF_GROUP_FENCE\n"
+      << "#define MRMF_GROUP_FENCE(a, b) __asm__ __volatile__(\"\" : \"+v\"(a), \"+v\"(b) : : \"memory\")\n"
+      << "#endif\n"
+      << "// v clamped into 0 .. hi\n"
+      << "__device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }\n";
+    o << "__constant__ " << RT << " RTC[" << S->rt.size() << "] = {";
+    for (size_t k = 0; k < S->rt.size(); ++k) o << (k ? ", " : "") << S->rt[k];
+    o << "};\n";
+    if (!lds.empty()) {
+        o << "__constant__ R KC[" << lds.size() << "] = {";
+        for (size_t k = 0; k < lds.size(); ++k) o << (k ? ", " : "") << lit(lds[k], f32);
+        o << "};\n";
+    }
+    o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector(const R* __restrict__ theta,\n"
+      << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
+      << "  if (skip != nullptr && *skip != 0) return;\n"
+      << "  __shared__ " << RT << " L[" << S->rt.size() << "];\n"
+      << "  for (unsigned k = threadIdx.x; k < " << S->rt.size() << "u; k += 256u) L[k] = RTC[k];\n";
+    if (!lds.empty())
+        o << "  __shared__ R Kl[" << lds.size() << "];\n"
+          << "  for (unsigned k = threadIdx.x; k < " << lds.size() << "u; k += 256u) Kl[k] = KC[k];\n";
+    o << "  __syncthreads();\n"
+      << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, " << S->Dr * SZ
+      << ", 0x00020000);\n"
+      << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)y, (short)0, " << S->Dr * SZ
+      << ", 0x00020000);\n";
+    for (int q : params) o << "  const R th" << q << " = theta[" << q << "];\n";
+    o << "  for (unsigned r = blockIdx.x * 256u + threadIdx.x; r < " << S->Dr << "u; r += gridDim.x * 256u) {\n"
+      << "    unsigned q = " << Q << "u;\n"
+      << "    " << RT << " left = (" << RT << ")r;\n";
+    for (int k = 0; k < N; ++k) {  // unrank, site 0 first
+        const int d = S->d[k];
+        o << "    const unsigned q" << k << " = q;\n"
+          << "    unsigned n" << k << " = 0u;\n";
+        if (d > 1) {
+            o << "    { " << RT << " b = 0;\n";
+            for (int v = 1; v < d; ++v)
+                o << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v) + "u") << "; const bool ok = " << v
+                  << "u <= q && t <= left; n" << k << " = ok ? " << v << "u : n" << k << "; b = ok ? t : b; }\n";
+            o << "      left -= b; q -= n" << k << "; }\n";
+        }
+    }
+    o << body.str()
+      << "    { C out; out.x = ar; out.y = ai; ST(out, ys, r * " << SZ << "u); }\n"
+      << "  }\n}\n";
+    (void)at;
+    return o.str();
+}
+
 std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int64_t SZ = f32 ? 8 : 16;
@@ -1573,7 +1744,62 @@ mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, cons
     return hip_status(hipModuleLaunchKernel(K.fn, *grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
 }
 
+mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
+    if (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) return MRMF_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mtx);
+    SpecKernel& K = S->gen[dtype];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
+    if (K.tried && K.device == dev) return K.ok ? MRMF_OK : MRMF_E_UNSUPPORTED;
+    if (K.mod) hipModuleUnload(K.mod);
+    K = SpecKernel{};
+    K.device = dev;
+    K.tried = true;
+    const std::string src = sector_source(S, dtype);
+    if (src.empty()) {
+        K.log = "sector does not qualify for the generated kernel";
+        return MRMF_E_UNSUPPORTED;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MRMF_E_HIP;
+    hipModule_t mod;
+    hipFunction_t fn;
+    const mrmf_status bs = rtc_build(src, "mrmf_sector", prop, &mod, &fn, &K.log);
+    if (bs != MRMF_OK) return bs;
+    int per_cu = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t groups = (S->Dr + 255) / 256;
+    K.mod = mod;
+    K.fn = fn;
+    K.block = 256;
+    K.grid = static_cast<int32_t>(std::min<int64_t>(groups, int64_t(per_cu) * prop.multiProcessorCount));
+    K.log = src;
+    K.ok = true;
+    return MRMF_OK;
+}
+
+mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
+                              const int32_t* d_skip) {
+    mrmf_status st = sector_gen_prepare(S, dtype);
+    if (st != MRMF_OK) return st;
+    const SpecKernel& K = S->gen[dtype];
+    struct {
+        const void* theta;
+        const void* x;
+        void* y;
+        const int32_t* skip;
+    } args{theta, x, y, d_skip};
+    size_t size = sizeof(args);
+    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
+    return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
+}
+
 }  // namespace mrmf
+
+mrmf_sector_t::~mrmf_sector_t() {
+    for (auto& k : gen)
+        if (k.mod) hipModuleUnload(k.mod);
+}
 
 mrmf_plan_t::~mrmf_plan_t() {
     for (auto& k : spec)

@@ -161,6 +161,32 @@ struct mrmf_plan_t {
     ~mrmf_plan_t();
 };
 
+// A digit-sum sector of a plan's basis (sector.hip).
+struct mrmf_sector_t {
+    int32_t N = 0, Q = 0;
+    int64_t Dr = 0;
+    int32_t n_params = 0;
+    bool hermitian = false;
+    std::vector<int32_t> d;
+    std::vector<int64_t> M;
+    std::vector<mrmf::DevChan> chans;  // digit-sum preserving channels
+    std::vector<mrmf::DevDiag> diags;
+    std::vector<unsigned char> image;  // device image: sites, channels, diagonal terms, tables, rank tables
+    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0, off_rt = 0, off_rto = 0;
+    int32_t n_rt = 0;
+    int64_t rt_max = 0;  // largest rank-table entry (32-bit LDS tables when below 2^31)
+    size_t ws_bytes = 0;
+    // host copies for the generated kernel: rank tables (site k at rto[k], entry (q, v) at q (d_k + 1) + v)
+    // and the factor tables <n|O|n - q> of every term (diagonal terms, then channels; a then b, d entries
+    // each, zero where the source digit is out of range)
+    std::vector<int64_t> rt, rto;
+    std::vector<double> tfac;
+    int32_t mode = MRMF_KERNEL_AUTO;  // the plan's kernel selection when the sector was made
+    mrmf::SpecKernel gen[2];          // generated sector kernels, c128 and c64
+    std::mutex mtx;
+    ~mrmf_sector_t();
+};
+
 namespace mrmf {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -226,6 +252,12 @@ double local_factor_host(const mrmf_plan_t* p, int site, int op, int n);
 // and a launch of at most max_grid blocks of 256 threads writing gx = H g and partial[block][param]
 // (*grid: the blocks launched).  MRMF_E_UNSUPPORTED when the plan does not qualify.
 std::string grad_source(const mrmf_plan_t* p);
+// Sector kernel generated for one sector and element type (jit.cpp): "" when the sector does not qualify
+// (more than 64 sites, no terms, or a vector of 2^31 bytes or more); launch returns MRMF_E_UNSUPPORTED then.
+std::string sector_source(const mrmf_sector_t* S, int dtype);
+mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype);
+mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
+                              const int32_t* d_skip);
 mrmf_status grad_prepare(mrmf_plan_t* p);
 mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, const void* g, void* gx, double* partial,
                         int max_grid, int* grid, hipStream_t s);

@@ -16,22 +16,6 @@
 
 #include "mrmf_internal.h"
 
-struct mrmf_sector_t {
-    int32_t N = 0, Q = 0;
-    int64_t Dr = 0;
-    int32_t n_params = 0;
-    bool hermitian = false;
-    std::vector<int32_t> d;
-    std::vector<int64_t> M;
-    std::vector<mrmf::DevChan> chans;  // digit-sum preserving channels
-    std::vector<mrmf::DevDiag> diags;
-    std::vector<unsigned char> image;  // device image: sites, channels, diagonal terms, tables, rank tables
-    size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0, off_rt = 0, off_rto = 0;
-    int32_t n_rt = 0;
-    int64_t rt_max = 0;  // largest rank-table entry (32-bit LDS tables when below 2^31)
-    size_t ws_bytes = 0;
-};
-
 namespace mrmf {
 namespace {
 
@@ -305,9 +289,16 @@ int sector_grid(int64_t n) {
 }
 
 template <typename R>
-mrmf_status sector_matvec(const mrmf_sector_t* S, const void* d_ws, const R* theta, const void* x, void* y,
+mrmf_status sector_matvec(mrmf_sector_t* S, const void* d_ws, const R* theta, const void* x, void* y,
                           hipStream_t s, const int32_t* skip) {
     using C = typename Cx<R>::T;
+    // the kernel generated for this sector unless the plan asked for the generic kernel; the generic
+    // kernels below when the sector does not qualify for it
+    if (S->mode != MRMF_KERNEL_GENERIC) {
+        const int dtype = sizeof(R) == 8 ? MRMF_DTYPE_Z : MRMF_DTYPE_C;
+        const mrmf_status st = sector_gen_launch(S, dtype, theta, x, y, s, skip);
+        if (st != MRMF_E_UNSUPPORTED) return st;
+    }
     const bool rt32 = S->rt_max < (int64_t(1) << 31);
     const size_t lds = sector_lds_bytes(S, rt32);
     const dim3 grid(sector_grid(S->Dr)), block(kSB);
@@ -378,6 +369,20 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     for (const auto& c : plan->chans)
         if (c.b >= 0 && c.qa + c.qb == 0) S->chans.push_back(c);
     S->diags = plan->diags;
+    S->rt = rt;
+    S->rto = rto;
+    S->mode = plan->cfg[MRMF_DTYPE_Z].mode;
+    auto add_fac = [&](int site, int op) {
+        for (int n = 0; n < plan->d[site]; ++n) S->tfac.push_back(local_factor_host(plan, site, op, n));
+    };
+    for (const auto& g : S->diags) {
+        add_fac(g.a, g.opa);
+        if (g.b >= 0) add_fac(g.b, g.opb);
+    }
+    for (const auto& c : S->chans) {
+        add_fac(c.a, c.opa);
+        add_fac(c.b, c.opb);
+    }
     // device image
     size_t off = 0;
     auto section = [&](size_t bytes) {
@@ -443,6 +448,32 @@ mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const flo
     const mrmf_status st = check_matvec_args(sector, d_ws, d_theta, d_x, d_y, 8);
     if (st != MRMF_OK) return st;
     return sector_matvec<float>(sector, d_ws, d_theta, d_x, d_y, static_cast<hipStream_t>(stream), nullptr);
+}
+
+mrmf_status mrmf_sector_kernel_source(mrmf_sector sector, int32_t dtype, char* buf, size_t cap, size_t* len) {
+    if (!sector || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) || (cap > 0 && !buf))
+        return MRMF_E_INVALID_ARG;
+    const std::string src = sector_source(sector, dtype);
+    if (src.empty()) return MRMF_E_UNSUPPORTED;
+    *len = src.size();
+    if (cap > 0) {
+        const size_t n = src.size() < cap - 1 ? src.size() : cap - 1;
+        std::memcpy(buf, src.data(), n);
+        buf[n] = '\0';
+    }
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_sector_generated(mrmf_sector sector, int32_t dtype, int32_t* used) {
+    if (!sector || !used || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C)) return MRMF_E_INVALID_ARG;
+    if (sector->mode == MRMF_KERNEL_GENERIC) {
+        *used = 0;
+        return MRMF_OK;
+    }
+    const mrmf_status st = sector_gen_prepare(sector, dtype);
+    if (st != MRMF_OK && st != MRMF_E_UNSUPPORTED) return st;
+    *used = st == MRMF_OK ? 1 : 0;
+    return MRMF_OK;
 }
 
 mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0, int64_t count, int64_t* d_out,

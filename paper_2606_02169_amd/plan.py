@@ -491,6 +491,14 @@ class Sector:
                 pass
             self._handle = None
 
+    def generated(self, dtype=torch.complex128) -> bool:
+        """True when the matvec of this element type runs the kernel generated for the sector (built now
+        if it was not yet), False when it runs the generic one."""
+        used = ctypes.c_int32()
+        L.call("mrmf_sector_generated", self._handle,
+               L.MRMF_DTYPE_Z if dtype == torch.complex128 else L.MRMF_DTYPE_C, ctypes.byref(used))
+        return bool(used.value)
+
     def matvec(self, theta: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """y = P H(theta) P^T x (c128 with float64 theta, or c64 with float32 theta)."""
         f32 = x.dtype == torch.complex64

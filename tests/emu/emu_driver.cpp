@@ -60,6 +60,7 @@ void emu_check(const void* p, size_t n, const char* what) {
 extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
 extern "C" void mrmf_grad(const double* theta, const void* x, const void* g, void* gx, double* partial)
     __attribute__((weak));
+extern "C" void mrmf_sector(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
 extern "C" void mrmf_spec_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
                                double ecr, double eci, const int* skip) __attribute__((weak));
 
@@ -81,6 +82,7 @@ struct GradCall {
     const void* g = nullptr;
     double* partial = nullptr;
 } g_grad;
+bool g_sector = false;  // the launch runs the generated sector kernel
 // One host thread per GPU thread of the block, kept for every block of the range; a block barrier
 // separates consecutive blocks (their __shared__ storage is the same static storage).
 void* thread_main(void* a) {
@@ -88,7 +90,9 @@ void* thread_main(void* a) {
     threadIdx = emu_dim3{g->tid, 0, 0};
     for (unsigned b = g->b0; b < g->b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
-        if (g_grad.on)
+        if (g_sector)
+            mrmf_sector(g->theta, g->x, g->y, nullptr);
+        else if (g_grad.on)
             mrmf_grad(static_cast<const double*>(g->theta), g->x, g_grad.g, g->y, g_grad.partial);
         else if (g_cheb.cheb)
             mrmf_spec_cheb(g->theta, g->x, g->y, g_cheb.acc, g_cheb.ea, g_cheb.eb, g_cheb.eg, g_cheb.ecr, g_cheb.eci,
@@ -114,7 +118,9 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
                              size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1) {
     if (b1 == 0 || b1 > grid) b1 = grid;
     if (block == 0 || block % 64 != 0 || block > 1024) return -1;
-    if (g_grad.on ? mrmf_grad == nullptr : g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr) return -3;
+    if (g_sector ? mrmf_sector == nullptr
+                 : g_grad.on ? mrmf_grad == nullptr : g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr)
+        return -3;
     g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
               {static_cast<const char*>(theta), theta_bytes, "theta"}};
     if (g_cheb.cheb) g_bufs.push_back({static_cast<const char*>(g_cheb.acc), x_bytes, "acc"});
@@ -171,5 +177,14 @@ extern "C" int emu_run_grad(unsigned grid, const void* theta, size_t theta_bytes
     const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, gx, x_bytes, 0, 0);
     g_grad = GradCall{};
     g_extra = {nullptr, 0, ""};
+    return rc;
+}
+
+// The generated sector kernel over all `grid` blocks of 256 threads (packed vectors x, y).
+extern "C" int emu_run_sector(unsigned grid, const void* theta, size_t theta_bytes, const void* x, size_t x_bytes,
+                              void* y, size_t y_bytes) {
+    g_sector = true;
+    const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, y, y_bytes, 0, 0);
+    g_sector = false;
     return rc;
 }

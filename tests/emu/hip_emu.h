@@ -98,6 +98,7 @@ inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mas
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, row_mask, bank_mask, bound) \
     emu_update_dpp((old), (src), (ctrl), (row_mask), (bank_mask), (bound))
 #define __builtin_amdgcn_sched_barrier(mask) ((void)0)  /* instruction scheduling only */
+#define MRMF_GROUP_FENCE(a, b) ((void)0)                 /* orders the generated code only */
 
 inline unsigned long long __umul64hi(unsigned long long a, unsigned long long b) {
     return static_cast<unsigned long long>((static_cast<unsigned __int128>(a) * b) >> 64);

@@ -76,6 +76,9 @@ def _compile(src: str) -> ctypes.CDLL:
     lib.emu_run_grad.restype = ctypes.c_int
     lib.emu_run_grad.argtypes = [ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    lib.emu_run_sector.restype = ctypes.c_int
+    lib.emu_run_sector.argtypes = [ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_cheb.restype = ctypes.c_int
     lib.emu_run_cheb.argtypes = ([ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
@@ -153,3 +156,37 @@ def run_grad(model, x: np.ndarray, g: np.ndarray, grid: int):
     if rc != 0:
         raise RuntimeError(f"emu_run_grad failed: {rc}")
     return gx, part
+
+
+def sector_source(model, digit_sum: int, dtype: int) -> str | None:
+    st, h = host_plan(model)
+    assert st == 0, st
+    s = ctypes.c_void_p()
+    try:
+        L.call("mrmf_sector_create", h, int(digit_sum), ctypes.byref(s))
+        n = ctypes.c_size_t()
+        if L.lib().mrmf_sector_kernel_source(s, dtype, None, 0, ctypes.byref(n)) != 0:
+            return None
+        buf = ctypes.create_string_buffer(n.value + 1)
+        L.call("mrmf_sector_kernel_source", s, dtype, buf, n.value + 1, ctypes.byref(n))
+        return buf.value.decode()
+    finally:
+        if s.value:
+            L.lib().mrmf_sector_destroy(s)
+        L.lib().mrmf_plan_destroy(h)
+
+
+def run_sector(model, digit_sum: int, x: np.ndarray, grid: int) -> np.ndarray:
+    """y = P H P^T x on the packed sector vector x with the generated sector kernel, emulated on the CPU."""
+    f32 = x.dtype == np.complex64
+    src = sector_source(model, digit_sum, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z)
+    if src is None:
+        raise ValueError("the sector does not qualify for the generated kernel")
+    lib = _compile(src)
+    th = np.ascontiguousarray(model.theta, dtype=np.float32 if f32 else np.float64)
+    xx = np.ascontiguousarray(x)
+    y = np.full_like(xx, np.nan)
+    rc = lib.emu_run_sector(grid, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data, y.nbytes)
+    if rc != 0:
+        raise RuntimeError(f"emu_run_sector failed: {rc}")
+    return y

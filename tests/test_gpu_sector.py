@@ -24,13 +24,17 @@ def t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def sector(model, Q, **kw):
+def sector(model, Q, kind="auto", **kw):
     from paper_2606_02169_amd.plan import Plan, Sector
-    return Sector(Plan.from_model(model, **kw), Q)
+    p = Plan.from_model(model, **kw)
+    if kind == "generic":
+        p.set_kernel("generic")
+    return Sector(p, Q)
 
 
+@pytest.mark.parametrize("kind", ["auto", "generic"])
 @pytest.mark.parametrize("seed", range(8))
-def test_sector_random_models(seed):
+def test_sector_random_models(seed, kind):
     rng = np.random.default_rng(6100 + seed)
     herm = seed % 3 != 0
     m = W.random_model(rng, n_sites=int(rng.integers(2, 7)), max_dim=20000, hermitian=herm,
@@ -38,9 +42,10 @@ def test_sector_random_models(seed):
     qmax = sum(s.d - 1 for s in m.sites)
     Q = int(rng.integers(0, qmax + 1))
     lab = osec.labels(m, Q)
-    print(f"seed={seed} D={m.dim} Q={Q} Dr={lab.size}", flush=True)
-    S = sector(m, Q, require_hermitian=herm)
+    print(f"seed={seed} kind={kind} D={m.dim} Q={Q} Dr={lab.size}", flush=True)
+    S = sector(m, Q, kind, require_hermitian=herm)
     assert S.dim == lab.size
+    assert S.generated() == S.generated(torch.complex64) == (kind == "auto")
     assert np.array_equal(S.labels().cpu().numpy(), lab)
     F = np.concatenate([lab[:50], rng.integers(-3, m.dim + 3, 400)])
     assert np.array_equal(S.lookup(t(F.astype(np.int64))).cpu().numpy(), osec.lookup(lab, F))
@@ -107,7 +112,7 @@ def test_ring20_sz0_sector_sampled():
     m, _ = W.config(2, with_state=False)
     Q = Sector_digit_sum(m, 0.0)
     S = sector(m, Q)
-    assert S.dim == 7873260
+    assert S.dim == 7873260 and S.generated()
     rng = np.random.default_rng(7)
     x = W.random_state(S.dim, rng)
     y = S.matvec(t(m.theta), t(x))

@@ -192,3 +192,33 @@ def test_adjoint_kernel_tavis_cummings():
     gx, part = E.run_grad(m, x, g, 3)
     assert rel_err(gx, rgx) <= 1e-12
     assert np.max(np.abs(part.sum(0) - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sector_kernel(seed):
+    """The kernel generated for a digit-sum sector against the sector oracle (every packed row): rings
+    with a bond between the first and last site (rank change over every site between), random mixed
+    spin/boson models with general operators, c128 and c64, one block and several rows per thread."""
+    from oracle import sector as osec
+    rng = np.random.default_rng(7800 + seed)
+    if seed == 0:
+        m = W.config(2, reduced=8, with_state=False)[0]
+    elif seed == 1:
+        m = W.tavis_cummings(6, 9, 1.0, 0.8, rng)
+    elif seed % 2 == 0:
+        m = W.random_model(rng, n_sites=int(rng.integers(3, 7)), max_dim=5000, n_params=3, n_terms=16)
+    else:
+        m = W.random_general_model(rng, n_sites=int(rng.integers(3, 6)), max_dim=5000, n_params=3)
+    qmax = sum(s.d - 1 for s in m.sites)
+    for Q in sorted({qmax // 2, max(0, qmax // 2 - 1), qmax}):
+        lab = osec.labels(m, Q)
+        if lab.size == 0:
+            continue
+        x = W.random_state(lab.size, rng)
+        ref = osec.matvec(m, Q, x, lab=lab)
+        for grid in ((lab.size + 255) // 256, 1):
+            y = E.run_sector(m, Q, x, grid)
+            assert rel_err(y, ref) <= TOL_Z, (Q, grid)
+        x32 = x.astype(np.complex64)
+        y32 = E.run_sector(m, Q, x32, 2)
+        assert rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128), lab=lab)) <= TOL_C
