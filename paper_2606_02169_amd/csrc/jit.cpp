@@ -1436,14 +1436,13 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
             const int si = a_first ? ch.qa : ch.qb, sj = a_first ? ch.qb : ch.qa;  // target - source digit
             const int dq = -si;  // source digit minus target digit at site i
             const std::string u = std::to_string(c - g0);
+            // R_k(q_k, n_k) of the target row is b_k from the unranking
             body << "      const R f" << u << " = " << fa << " * " << fb << ";\n"
-                 << "      " << RT << " e" << u << " = " << rte(i, "q" + std::to_string(i), clampd(i, si)) << " - "
-                 << rte(i, "q" + std::to_string(i), "n" + std::to_string(i)) << ";\n";
+                 << "      " << RT << " e" << u << " = " << rte(i, "q" + std::to_string(i), clampd(i, si)) << " - b" << i
+                 << ";\n";
             for (int k = i + 1; k < j; ++k)
-                body << "      e" << u << " += " << rte(k, clampq(k, dq), "n" + std::to_string(k)) << " - "
-                     << rte(k, "q" + std::to_string(k), "n" + std::to_string(k)) << ";\n";
-            body << "      e" << u << " += " << rte(j, clampq(j, dq), clampd(j, sj)) << " - "
-                 << rte(j, "q" + std::to_string(j), "n" + std::to_string(j)) << ";\n"
+                body << "      e" << u << " += " << rte(k, clampq(k, dq), "n" + std::to_string(k)) << " - b" << k << ";\n";
+            body << "      e" << u << " += " << rte(j, clampq(j, dq), clampd(j, sj)) << " - b" << j << ";\n"
                  << "      const C s" << u << " = LD(xs, f" << u << " != (R)0 ? (unsigned)((" << RT << ")r + e" << u << ") * "
                  << SZ << "u : OOB);\n";
         }
@@ -1510,13 +1509,15 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     for (int k = 0; k < N; ++k) {  // unrank, site 0 first
         const int d = S->d[k];
         o << "    const unsigned q" << k << " = q;\n"
-          << "    unsigned n" << k << " = 0u;\n";
+          << "    unsigned n" << k << " = 0u;\n"
+          << "    " << RT << " b" << k << " = 0;\n";  // R_k(q_k, n_k)
         if (d > 1) {
-            o << "    { " << RT << " b = 0;\n";
+            o << "    {\n";
             for (int v = 1; v < d; ++v)
                 o << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v) + "u") << "; const bool ok = " << v
-                  << "u <= q && t <= left; n" << k << " = ok ? " << v << "u : n" << k << "; b = ok ? t : b; }\n";
-            o << "      left -= b; q -= n" << k << "; }\n";
+                  << "u <= q && t <= left; n" << k << " = ok ? " << v << "u : n" << k << "; b" << k << " = ok ? t : b" << k
+                  << "; }\n";
+            o << "      left -= b" << k << "; q -= n" << k << "; }\n";
         }
     }
     o << body.str()
