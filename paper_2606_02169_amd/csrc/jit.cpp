@@ -1410,58 +1410,100 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     std::set<int> params;
     for (const auto& g : S->diags) params.insert(g.param);
     for (const auto& c : S->chans) params.insert(c.param);
-    std::ostringstream body;
-    body << "    R dr = (R)0, di = (R)0;\n";
-    for (const auto& g : S->diags) {
-        std::string f = factor(g.a);
-        if (g.b >= 0) f = "(" + f + " * " + factor(g.b) + ")";
-        body << "    { const R f = " << f << "; dr = fma(th" << g.param << " * " << lit(g.wr, f32) << ", f, dr);";
-        if (g.wi != 0.0) body << " di = fma(th" << g.param << " * " << lit(g.wi, f32) << ", f, di);";
-        body << " }\n";
+    // factor expressions of every term, in the order the tables were built
+    std::vector<std::string> gf(S->diags.size()), cfa(S->chans.size()), cfb(S->chans.size());
+    for (size_t g = 0; g < S->diags.size(); ++g) {
+        gf[g] = factor(S->diags[g].a);
+        if (S->diags[g].b >= 0) gf[g] = "(" + gf[g] + " * " + factor(S->diags[g].b) + ")";
     }
-    body << "    const C xf = LD(xs, r * " << SZ << "u);\n"
-         << "    R ar = dr * xf.x - di * xf.y, ai = dr * xf.y + di * xf.x;\n";
+    for (size_t c = 0; c < S->chans.size(); ++c) {
+        cfa[c] = factor(S->chans[c].a);
+        cfb[c] = factor(S->chans[c].b);
+    }
+    // The row body in site order: after site k is unranked, the diagonal terms whose sites are all known
+    // are added, every channel spanning k adds site k's change of its rank, and the channels whose last
+    // site is k issue their gathers; every kGroup gathers are accumulated, behind a fence that keeps the
+    // next loads (and table reads) after them.  So each site's digit, remaining sum and table base die once
+    // the channels spanning it have used them, even for a bond between the first and the last site.
     const int nch = static_cast<int>(S->chans.size());
+    struct Span {
+        int i, j, si, sj;
+    };
+    std::vector<Span> sp(nch);
+    for (int c = 0; c < nch; ++c) {
+        const DevChan& ch = S->chans[c];
+        const bool a_first = ch.a < ch.b;
+        sp[c] = {a_first ? ch.a : ch.b, a_first ? ch.b : ch.a, a_first ? ch.qa : ch.qb, a_first ? ch.qb : ch.qa};
+    }
     constexpr int kGroup = 6;
-    const int ngr = (nch + kGroup - 1) / kGroup;
-    const int gsz = ngr > 0 ? (nch + ngr - 1) / ngr : 0;
-    for (int g0 = 0; g0 < nch; g0 += gsz) {
-        const int g1 = std::min(nch, g0 + gsz);
-        body << "    {\n";
-        for (int c = g0; c < g1; ++c) {
+    std::vector<int> pending;
+    std::ostringstream body;
+    auto flush = [&](bool last) {
+        if (pending.empty()) return;
+        body << "    __builtin_amdgcn_sched_barrier(0);\n";
+        for (int c : pending) {
             const DevChan& ch = S->chans[c];
-            const std::string fa = factor(ch.a), fb = factor(ch.b);
-            const bool a_first = ch.a < ch.b;
-            const int i = a_first ? ch.a : ch.b, j = a_first ? ch.b : ch.a;
-            const int si = a_first ? ch.qa : ch.qb, sj = a_first ? ch.qb : ch.qa;  // target - source digit
-            const int dq = -si;  // source digit minus target digit at site i
-            const std::string u = std::to_string(c - g0);
-            // R_k(q_k, n_k) of the target row is b_k from the unranking
-            body << "      const R f" << u << " = " << fa << " * " << fb << ";\n"
-                 << "      " << RT << " e" << u << " = " << rte(i, "q" + std::to_string(i), clampd(i, si)) << " - b" << i
-                 << ";\n";
-            for (int k = i + 1; k < j; ++k)
-                body << "      e" << u << " += " << rte(k, clampq(k, dq), "n" + std::to_string(k)) << " - b" << k << ";\n";
-            body << "      e" << u << " += " << rte(j, clampq(j, dq), clampd(j, sj)) << " - b" << j << ";\n"
-                 << "      const C s" << u << " = LD(xs, f" << u << " != (R)0 ? (unsigned)((" << RT << ")r + e" << u << ") * "
-                 << SZ << "u : OOB);\n";
-        }
-        body << "      __builtin_amdgcn_sched_barrier(0);\n";
-        for (int c = g0; c < g1; ++c) {
-            const DevChan& ch = S->chans[c];
-            const std::string u = std::to_string(c - g0);
-            body << "      { const R cr = th" << ch.param << " * " << lit(ch.wr, f32) << " * f" << u << ";"
+            const std::string u = std::to_string(c);
+            // (f w) theta: a product of loop-invariant factors would be hoisted out of the row loop and
+            // kept in registers for every channel
+            body << "    { const R cr = f" << u << " * " << lit(ch.wr, f32) << " * th" << ch.param << ";"
                  << " ar = fma(cr, s" << u << ".x, ar); ai = fma(cr, s" << u << ".y, ai);";
             if (ch.wi != 0.0)
-                body << " const R ci = th" << ch.param << " * " << lit(ch.wi, f32) << " * f" << u << ";"
+                body << " const R ci = f" << u << " * " << lit(ch.wi, f32) << " * th" << ch.param << ";"
                      << " ar = fma(-ci, s" << u << ".y, ar); ai = fma(ci, s" << u << ".x, ai);";
             body << " }\n";
         }
-        // the next group's loads stay behind this group's accumulation (the accumulators pass through an
-        // empty asm that also orders memory), so the gathers in flight per thread are one group's
-        if (g1 < nch) body << "      MRMF_GROUP_FENCE(ar, ai);\n";
-        body << "    }\n";
+        if (!last) body << "    MRMF_GROUP_FENCE(ar, ai);\n";
+        pending.clear();
+    };
+    body << "    R dr = (R)0, di = (R)0, ar = (R)0, ai = (R)0;\n"
+         << "    const C xf = LD(xs, r * " << SZ << "u);\n";
+    for (int k = 0; k < N; ++k) {
+        const int d = S->d[k];
+        const std::string K = std::to_string(k);
+        body << "    const unsigned q" << K << " = q;\n"
+             << "    unsigned n" << K << " = 0u;\n"
+             << "    " << RT << " b" << K << " = 0;\n";  // R_k(q_k, n_k)
+        if (d > 1) {
+            body << "    {\n";
+            for (int v = 1; v < d; ++v)
+                body << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v) + "u") << "; const bool ok = " << v
+                     << "u <= q && t <= left; n" << K << " = ok ? " << v << "u : n" << K << "; b" << K << " = ok ? t : b" << K
+                     << "; }\n";
+            body << "      left -= b" << K << "; q -= n" << K << "; }\n";
+        }
+        for (size_t g = 0; g < S->diags.size(); ++g) {
+            const DevDiag& t = S->diags[g];
+            if (std::max(t.a, t.b) != k) continue;
+            body << "    { const R f = " << gf[g] << "; dr = fma(f * " << lit(t.wr, f32) << ", th" << t.param << ", dr);";
+            if (t.wi != 0.0) body << " di = fma(f * " << lit(t.wi, f32) << ", th" << t.param << ", di);";
+            body << " }\n";
+        }
+        for (int c = 0; c < nch; ++c) {
+            const Span& z = sp[c];
+            if (k < z.i || k > z.j) continue;
+            const std::string u = std::to_string(c);
+            const int dq = -z.si;  // source digit minus target digit at site i
+            if (k == z.i)
+                body << "    " << RT << " e" << u << " = " << rte(k, "q" + K, clampd(k, z.si)) << " - b" << K << ";\n";
+            else if (k < z.j)
+                body << "    e" << u << " += " << rte(k, clampq(k, dq), "n" + K) << " - b" << K << ";\n";
+            else
+                body << "    e" << u << " += " << rte(k, clampq(k, dq), clampd(k, z.sj)) << " - b" << K << ";\n";
+        }
+        for (int c = 0; c < nch; ++c) {
+            if (sp[c].j != k) continue;
+            const std::string u = std::to_string(c);
+            body << "    const R f" << u << " = " << cfa[c] << " * " << cfb[c] << ";\n"
+                 << "    const C s" << u << " = LD(xs, f" << u << " != (R)0 ? (unsigned)((" << RT << ")r + e" << u << ") * "
+                 << SZ << "u : OOB);\n";
+            pending.push_back(c);
+            if (static_cast<int>(pending.size()) >= kGroup) flush(false);
+        }
     }
+    flush(true);
+    body << "    ar += dr * xf.x - di * xf.y;\n"
+         << "    ai += dr * xf.y + di * xf.x;\n";
     std::ostringstream o;
     o << "// generated sector kernel: " << N << " sites, digit sum " << Q << ", " << S->Dr << " packed states, "
       << S->diags.size() << " diagonal terms, " << nch << " channels\n";
@@ -1506,20 +1548,6 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     o << "  for (unsigned r = blockIdx.x * 256u + threadIdx.x; r < " << S->Dr << "u; r += gridDim.x * 256u) {\n"
       << "    unsigned q = " << Q << "u;\n"
       << "    " << RT << " left = (" << RT << ")r;\n";
-    for (int k = 0; k < N; ++k) {  // unrank, site 0 first
-        const int d = S->d[k];
-        o << "    const unsigned q" << k << " = q;\n"
-          << "    unsigned n" << k << " = 0u;\n"
-          << "    " << RT << " b" << k << " = 0;\n";  // R_k(q_k, n_k)
-        if (d > 1) {
-            o << "    {\n";
-            for (int v = 1; v < d; ++v)
-                o << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v) + "u") << "; const bool ok = " << v
-                  << "u <= q && t <= left; n" << k << " = ok ? " << v << "u : n" << k << "; b" << k << " = ok ? t : b" << k
-                  << "; }\n";
-            o << "      left -= b" << k << "; q -= n" << k << "; }\n";
-        }
-    }
     o << body.str()
       << "    { C out; out.x = ar; out.y = ai; ST(out, ys, r * " << SZ << "u); }\n"
       << "  }\n}\n";
