@@ -1257,7 +1257,7 @@ std::string grad_source(const mrmf_plan_t* p) {
     std::vector<const T*> ch;
     for (const T& t : terms)
         if (!t.diag) ch.push_back(&t);
-    constexpr int kGroup = 12;
+    constexpr int kGroup = 24;
     const int ngr = static_cast<int>((ch.size() + kGroup - 1) / kGroup);
     const int gsz = ngr > 0 ? static_cast<int>((ch.size() + ngr - 1) / ngr) : 0;
     for (size_t g0 = 0; g0 < ch.size(); g0 += gsz) {
