@@ -153,13 +153,16 @@ def bench_ring(args, dev):
     log(f"timed {K} steps: {ms_per_step:.4f} ms/step, launch mean {mean_launch_ms:.4f} ms "
         f"(min {min(launch_ms):.4f}, max {max(launch_ms):.4f})")
 
-    # the stream ceiling of this GPU for the same bytes: a plain device copy of x into y (read D x 16 B,
-    # write D x 16 B), timed the same way after the matvec loop
+    # the stream ceiling of this GPU for the same bytes: a plain device copy of x into a second buffer
+    # (read D x 16 B, write D x 16 B), timed the same way after the matvec loop; y keeps H x for the
+    # parity check below
     if not args.profile:
+        z = torch.empty_like(x)
         for _ in range(2):
-            y.copy_(x)
-        copy_ms = cuda_time(lambda: y.copy_(x), stream, 10)
+            z.copy_(x)
+        copy_ms = cuda_time(lambda: z.copy_(x), stream, 10)
         copy_GBps = alg_bytes / (copy_ms * 1e-3) / 1e9
+        del z
     else:
         copy_GBps = None
 
