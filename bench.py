@@ -64,7 +64,7 @@ def cuda_time(fn, stream, reps: int):
     return a.elapsed_time(b) / reps
 
 
-def cpu_baseline(model, x_host, target_s: float = 12.0):
+def cpu_baseline(model, x_host, target_s: float = 15.0):
     """The oracle's FP64 matvec on the host cores: the full vector, repeated to about target_s seconds
     (or a row sample if one full pass would take longer); scaled to matvecs/s of the full vector."""
     import numpy as np
@@ -93,7 +93,7 @@ def cpu_baseline(model, x_host, target_s: float = 12.0):
         t0 = time.perf_counter()
         y_rows = mf.matvec(model, x_host, rows=rows)
         dt = time.perf_counter() - t0
-        if dt >= 0.5 * target_s or n == D:
+        if dt >= 0.7 * target_s or n == D:
             break
         n = min(D, int(n * target_s / max(dt, 1e-3)))
     return (dict(value=n / dt / D, unit="matvecs/s", cores=threads, kind="oracle",
