@@ -12,12 +12,16 @@ Other workloads (one JSON line each; not part of the headline):
   --workload lanczos4x4  4x4 periodic spin-1 Heisenberg (D = 3^16): FP32 (c64) matvec inside the FP64
                          Lanczos against the plain FP64 form: steps and wall time to 1e-5 relative
                          ground-energy error, end to end and matvec only
+  --workload lanczos_ring20  100 CGS2 Lanczos steps on the headline ring (basis 97.7 GB), plain FP64 and
+                         FP32-in-FP64, beside the sector Lanczos energies of every digit sum
   --workload batched     256 open mixed chains x 8 c64 vectors in one persistent hipGraph launch,
                          against separate plain c64 and c128 calls per vector
   --workload adjoint     Tavis-Cummings (12 spins + boson cut at 64): forward and adjoint times and
                          gradient error against the oracle
   --workload paper       the paper's chain testbeds (spin-1 ring N=15, mixed ring (1/2)^6(1)^6(3/2)^6):
                          matvecs/s and a Lanczos ground state, beside the paper's CPU figures
+  --workload propagate   Chebyshev time propagation on the ring: terms per step, time per term
+  --workload sector      S_z = 0 sectors of the ring and of C1: sector matvec and sector Lanczos
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
@@ -294,6 +298,65 @@ def bench_lanczos(args, dev):
     out["no_reorth"] = {"fp64": {"seconds": nz["seconds"], "rel_err": abs(nz["theta"] - E_ref) / abs(E_ref)},
                         "fp32_in_fp64": {"seconds": nc["seconds"],
                                          "rel_err": abs(nc["theta"] - E_ref) / abs(E_ref)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_lanczos_ring(args, dev):
+    """100 Lanczos steps (CGS2) on the 20-site ferrimagnetic ring from the seeded start vector, plain FP64
+    and FP32 matvec inside FP64; the full-basis ground energy beside the lowest sector energy (H keeps the
+    digit sum, so its lowest eigenvalue is the lowest over all sectors; sector Lanczos in every sector)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_02169_amd.plan import Plan, Sector
+
+    model, x = W.config(2)
+    D = model.dim
+    v0 = torch.from_numpy(x).to(dev)
+    del x
+    th64 = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+    th32 = th64.float()
+    m = args.lanczos_steps
+    out = {"metric": "Lanczos on the 20-site ferrimagnetic ring (c128 basis, CGS2): time per step and ground energy",
+           "workload": "ferrimagnetic_ring_N20_c128", "D": D, "seed": 2, "steps": m,
+           "basis_GB": (m + 1) * D * 16 / 1e9, "forms": {}}
+    for name, prec in (("fp64", "z"), ("fp32_in_fp64", "c_in_z")):
+        plan = Plan.from_model(model, device=dev)
+        y = torch.empty_like(v0)
+        plan.autotune(th64, v0, y)
+        if prec == "c_in_z":
+            xc = v0.to(torch.complex64)
+            plan.autotune(th32, xc, torch.empty_like(xc))
+            del xc
+        del y
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.lanczos(th64, v0, m, precision=prec, theta_c=th32)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = r["result"].cpu().numpy()
+        del r
+        torch.cuda.empty_cache()
+        out["forms"][name] = {"seconds": dt, "ms_per_step": dt / max(1, int(res[3])) * 1e3, "E0": float(res[0]),
+                              "residual": float(res[2]), "steps": int(res[3])}
+        log(f"{name}: {out['forms'][name]}")
+    if not args.profile:
+        plan = Plan.from_model(model, device=dev)
+        sectors = {}
+        for Q in range(sum(s.d - 1 for s in model.sites) + 1):
+            S = Sector(plan, Q)
+            rng = np.random.default_rng(100 + Q)
+            xs = torch.from_numpy(W.random_state(S.dim, rng)).to(dev)
+            r = S.lanczos(th64, xs, m)
+            res = r["result"].cpu().numpy()
+            sectors[Q] = {"dim": S.dim, "E0": float(res[0]), "residual": float(res[2])}
+            del r, xs, S
+            torch.cuda.empty_cache()
+        qmin = min(sectors, key=lambda q: sectors[q]["E0"])
+        out["sectors"] = sectors
+        out["lowest_sector"] = {"digit_sum": qmin, "E0": sectors[qmin]["E0"],
+                                "full_minus_sector": out["forms"]["fp64"]["E0"] - sectors[qmin]["E0"]}
     print(json.dumps(out), flush=True)
 
 
@@ -601,7 +664,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
-    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "batched", "adjoint", "paper",
+    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "lanczos_ring20", "batched",
+                                                              "adjoint", "paper",
                                                                   "propagate", "sector"])
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
@@ -616,7 +680,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "batched": bench_batched,
+    {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
      "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
      "sector": bench_sector}[args.workload](args, dev)
 

@@ -149,3 +149,29 @@ def test_sector_edge_cases():
     S = Sector(plan, qmax // 2)
     with pytest.raises(ValueError):
         S.matvec(t(m.theta), t(np.zeros(S.dim + 1, dtype=np.complex128)))
+
+
+def test_ring20_spin_flip_and_full_lanczos():
+    """Headline ring (D = 60,466,176), sector Lanczos in the digit sums 12..18 (S_z = Q - 15).  The spin
+    flip maps sector Q onto 30 - Q and reverses the field; the rest of H is flip-invariant and S_z is
+    constant in a sector, so E_Q - E_{30-Q} = 2 h_z (Q - 15) exactly (h_z = 0.1).  The lowest of these
+    sectors is Q = 14, below its neighbours; 100 full-basis Lanczos steps from the seeded vector (all
+    sectors mixed) give a Ritz value above it (variational) by less than their residual."""
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m, x = W.config(2)
+    plan = Plan.from_model(m)
+    th = t(m.theta)
+    E = {}
+    for Q in range(12, 19):
+        S = Sector(plan, Q)
+        assert S.generated()
+        r = S.lanczos(th, t(W.random_state(S.dim, np.random.default_rng(100 + Q))), 100)["result"].cpu().numpy()
+        assert r[2] <= 1e-8, (Q, r)
+        E[Q] = r[0]
+        print(Q, S.dim, repr(E[Q]), r[2], flush=True)
+    for Q in (12, 13, 14):
+        assert abs((E[Q] - E[30 - Q]) - 0.2 * (Q - 15)) <= 1e-9, Q
+    assert E[14] < min(E[13], E[15])
+    r = plan.lanczos(th, t(x), 100)["result"].cpu().numpy()
+    print("full basis", repr(r[0]), r[2], flush=True)
+    assert r[0] >= E[14] - 1e-9 and r[0] - E[14] <= r[2]
