@@ -279,15 +279,17 @@ def bench_lanczos(args, dev):
                          "seconds": ref["seconds"]},
            "matvec_ms": {"c128": mv_z, "c64": mv_c}, "forms": {}}
     m = args.lanczos_steps
-    for name, plan, prec in (("fp64", pz, "z"), ("fp32_in_fp64", pc, "c_in_z")):
-        full = run(plan, prec, m)
+    for name, plan, prec, ro in (("fp64", pz, "z", "cgs2"), ("fp32_in_fp64", pc, "c_in_z", "cgs2"),
+                                 ("fp64_cgs2_cond", pz, "z", "cgs2_cond"),
+                                 ("fp32_in_fp64_cgs2_cond", pc, "c_in_z", "cgs2_cond")):
+        full = run(plan, prec, m, ro)
         curve = ritz_curve(full["alpha"], full["beta"], full["steps"])
         rel = np.abs(curve - E_ref) / abs(E_ref)
         hit = np.nonzero(rel <= 1e-5)[0]
         k5 = int(hit[0]) + 1 if hit.size else None
-        timed = run(plan, prec, k5) if k5 else None
+        timed = run(plan, prec, k5, ro) if k5 else None
         out["forms"][name] = {
-            "steps": m, "theta": full["theta"], "rel_err": abs(full["theta"] - E_ref) / abs(E_ref),
+            "reorth": ro, "steps": m, "theta": full["theta"], "rel_err": abs(full["theta"] - E_ref) / abs(E_ref),
             "residual": full["resid"], "seconds": full["seconds"],
             "steps_to_1e-5": k5, "seconds_to_1e-5": timed["seconds"] if timed else None,
             "rel_err_at_1e-5_run": (abs(timed["theta"] - E_ref) / abs(E_ref)) if timed else None,
@@ -321,7 +323,8 @@ def bench_lanczos_ring(args, dev):
     out = {"metric": "Lanczos on the 20-site ferrimagnetic ring (c128 basis, CGS2): time per step and ground energy",
            "workload": "ferrimagnetic_ring_N20_c128", "D": D, "seed": 2, "steps": m,
            "basis_GB": (m + 1) * D * 16 / 1e9, "forms": {}}
-    for name, prec in (("fp64", "z"), ("fp32_in_fp64", "c_in_z")):
+    for name, prec, ro in (("fp64", "z", "cgs2"), ("fp32_in_fp64", "c_in_z", "cgs2"),
+                           ("fp64_cgs2_cond", "z", "cgs2_cond"), ("fp32_in_fp64_cgs2_cond", "c_in_z", "cgs2_cond")):
         plan = Plan.from_model(model, device=dev)
         y = torch.empty_like(v0)
         plan.autotune(th64, v0, y)
@@ -332,13 +335,13 @@ def bench_lanczos_ring(args, dev):
         del y
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = plan.lanczos(th64, v0, m, precision=prec, theta_c=th32)
+        r = plan.lanczos(th64, v0, m, precision=prec, reorth=ro, theta_c=th32)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = r["result"].cpu().numpy()
         del r
         torch.cuda.empty_cache()
-        out["forms"][name] = {"seconds": dt, "ms_per_step": dt / max(1, int(res[3])) * 1e3, "E0": float(res[0]),
+        out["forms"][name] = {"reorth": ro, "seconds": dt, "ms_per_step": dt / max(1, int(res[3])) * 1e3, "E0": float(res[0]),
                               "residual": float(res[2]), "steps": int(res[3])}
         log(f"{name}: {out['forms'][name]}")
     if not args.profile:

@@ -98,6 +98,9 @@ typedef struct {
 /* reorthogonalisation policies for mrmf_lanczos */
 #define MRMF_REORTH_CGS2 0  /* full: classical Gram-Schmidt against all of V, applied twice       */
 #define MRMF_REORTH_NONE 1  /* plain three-term recurrence                                       */
+#define MRMF_REORTH_CGS2_COND 2 /* full: classical Gram-Schmidt, the second pass only when the first
+                                   one shrank ||w|| by more than 1/sqrt(2) (Daniel, Gragg, Kaufman and
+                                   Stewart's criterion; the decision is taken on the device) */
 
 /* ---------------------------------------------------------------------------------------------- */
 /* Status text ("ok", "invalid argument", ...).  Static storage; never NULL. */
@@ -274,12 +277,13 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
 
 /* Device-resident Lanczos driving the matvec (the Krylov use of x -> H x, Sec. I).
  * Step j: w = H v_j; alpha_j = Re<v_j|w>; w -= alpha_j v_j + beta_{j-1} v_{j-1};
- * (MRMF_REORTH_CGS2 only) twice c = V^H w, w -= V c; beta_j = ||w||;
+ * (MRMF_REORTH_CGS2) twice c = V^H w, w -= V c; (MRMF_REORTH_CGS2_COND) once, and a second time only
+ * if that pass left ||w||^2 below half its value before it; beta_j = ||w||;
  * stop when beta_j <= 1e-14 * ||T|| (Gershgorin estimate);
  * v_{j+1} = w / beta_j.  Then the lowest eigenpair (theta, s) of the k x k tridiagonal T (bisection
  * and inverse iteration on the GPU), the Ritz vector u = V s, and the explicit residual
  * ||H u - theta u|| with the FP64 matvec.
- *   reorth   : MRMF_REORTH_CGS2 or MRMF_REORTH_NONE
+ *   reorth   : MRMF_REORTH_CGS2, MRMF_REORTH_CGS2_COND or MRMF_REORTH_NONE
  *   precision: MRMF_PREC_Z, or MRMF_PREC_C_IN_Z (then d_theta_c float[n_params] is required and the
  *              matvec runs in c64 on a c64 copy of v_j; everything else stays FP64)
  *   d_v0     : c128[D] start vector (normalised internally; zero norm -> steps = 0, theta = NaN)

@@ -18,11 +18,13 @@ struct LzState {
     int32_t stopped;  // recurrence ended (breakdown, zero start vector, or last step done)
     int32_t steps;    // k: number of alpha_j computed
     int32_t breakdown;
-    int32_t pad;
+    int32_t skip2;    // conditional Gram-Schmidt: the second pass of this step is skipped (or stopped)
     double tnorm;  // Gershgorin estimate of ||T|| so far
     double nrm0;   // ||v0||
     double theta;  // lowest Ritz value
-    double pad2;
+    double wn2;    // conditional Gram-Schmidt: ||w||^2 before the first pass
+    int32_t n_second;  // conditional Gram-Schmidt: second passes taken so far
+    int32_t pad[3];
 };
 
 int red_blocks(int64_t n) {
@@ -200,6 +202,9 @@ __global__ void k_init_finalize(const double* __restrict__ partial, int nb, LzSt
     const double nrm = sqrt(s);
     st->steps = 0;
     st->breakdown = 0;
+    st->skip2 = 0;
+    st->wn2 = 0.0;
+    st->n_second = 0;
     st->tnorm = 0.0;
     st->nrm0 = nrm;
     st->theta = __builtin_nan("");
@@ -212,6 +217,20 @@ __global__ void k_alpha_finalize(const double2* __restrict__ partial, int nb, do
     double s = 0.0;
     for (int b = 0; b < nb; ++b) s += partial[b].x;
     *alpha = s;
+}
+
+// Conditional Gram-Schmidt: wn2 = ||w||^2 before the first pass (store = 1), or after it (store = 0):
+// skip2 = 1 unless the pass shrank ||w||^2 below half (or the recurrence has stopped).
+__global__ void k_cgs_norm(const double* __restrict__ partial, int nb, int store, LzState* __restrict__ st) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    if (store) {
+        st->wn2 = s;
+        return;
+    }
+    const int skip = st->stopped != 0 || s >= 0.5 * st->wn2;
+    st->skip2 = skip;
+    if (!skip) ++st->n_second;
 }
 
 __global__ void k_beta_finalize(const double* __restrict__ partial, int nb, int j, int last,
@@ -464,7 +483,8 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
     if (m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
     if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
     if (precision == MRMF_PREC_C_IN_Z && !mv_c) return MRMF_E_INVALID_ARG;
-    if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE) return MRMF_E_INVALID_ARG;
+    if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE && reorth != MRMF_REORTH_CGS2_COND)
+        return MRMF_E_INVALID_ARG;
     if (!aligned(d_scratch, 256) || !aligned(d_V, 16) || !aligned(d_u, 16) || !aligned(d_v0, 16))
         return MRMF_E_INVALID_ARG;
     const LzLayout Lo = lz_layout(D, m, precision);
@@ -515,15 +535,26 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
         hipLaunchKernelGGL(k_alpha_finalize, dim3(1), dim3(1), 0, s, part_z, nb, d_alpha + j, stopped);
         hipLaunchKernelGGL(k_three_term, dim3(g), dim3(kRB), 0, s, D, w, row(j), j > 0 ? row(j - 1) : nullptr,
                            d_alpha + j, j > 0 ? d_beta + (j - 1) : nullptr, stopped);
-        if (reorth == MRMF_REORTH_CGS2) {
+        if (reorth == MRMF_REORTH_CGS2 || reorth == MRMF_REORTH_CGS2_COND) {
             const int k = j + 1;
+            const bool cond = reorth == MRMF_REORTH_CGS2_COND;
+            if (cond) {
+                hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
+                hipLaunchKernelGGL(k_cgs_norm, dim3(1), dim3(1), 0, s, part_d, nb, 1, st);
+            }
             for (int pass = 0; pass < 2; ++pass) {
+                // the second pass of the conditional form runs (its kernels return at once otherwise)
+                // only when the device-side test after the first pass asked for it
+                const int32_t* stop = pass == 1 && cond ? &st->skip2 : stopped;
+                if (pass == 1 && cond) {
+                    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
+                    hipLaunchKernelGGL(k_cgs_norm, dim3(1), dim3(1), 0, s, part_d, nb, 0, st);
+                }
                 hipLaunchKernelGGL(k_gemvt_partial, dim3(nb, (k + kGroup - 1) / kGroup), dim3(kRB), 0, s, D, V, k,
-                                   w, part_z, nb, stopped);
+                                   w, part_z, nb, stop);
                 hipLaunchKernelGGL(k_gemvt_finalize, dim3((k + 63) / 64), dim3(64), 0, s, k, nb, part_z, coef,
-                                   stopped);
-                hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, k, nullptr, coef, w, 0, -1.0,
-                                   stopped);
+                                   stop);
+                hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, k, nullptr, coef, w, 0, -1.0, stop);
             }
         }
         hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);

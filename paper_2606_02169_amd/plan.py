@@ -215,8 +215,10 @@ class Plan:
     def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",
                 reorth: str = "cgs2", theta_c: torch.Tensor | None = None, keep_basis: bool = False) -> dict:
         """Lowest eigenpair by device-resident Lanczos (mrmf_lanczos).  precision "z" (c128 matvec) or
-        "c_in_z" (c64 matvec inside the FP64 recurrence).  Returns device tensors alpha, beta, the Ritz
-        vector u and result = [theta, residual estimate, explicit residual, steps]."""
+        "c_in_z" (c64 matvec inside the FP64 recurrence); reorth "cgs2" (two Gram-Schmidt passes),
+        "cgs2_cond" (the second only when the first shrank ||w|| by more than 1/sqrt(2)) or "none".
+        Returns device tensors alpha, beta, the Ritz vector u and result = [theta, residual estimate,
+        explicit residual, steps]."""
         return _lanczos("mrmf_lanczos", self._handle, self.ws, self.D, self.device, theta, v0, m, precision,
                         reorth, theta_c, keep_basis)
 
@@ -432,7 +434,7 @@ def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, 
     if v0.numel() != D:
         raise ValueError("v0 has the wrong length")
     prec = {"z": L.MRMF_PREC_Z, "c_in_z": L.MRMF_PREC_C_IN_Z}[precision]
-    ro = {"cgs2": L.MRMF_REORTH_CGS2, "none": L.MRMF_REORTH_NONE}[reorth]
+    ro = {"cgs2": L.MRMF_REORTH_CGS2, "cgs2_cond": L.MRMF_REORTH_CGS2_COND, "none": L.MRMF_REORTH_NONE}[reorth]
     if prec == L.MRMF_PREC_C_IN_Z:
         if theta_c is None:
             theta_c = theta.to(torch.float32)

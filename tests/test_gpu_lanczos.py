@@ -120,3 +120,25 @@ def test_long_run_orthonormal_basis():
     V = out["V"].reshape(241, -1)[:240].cpu().numpy()
     G = V.conj() @ V.T
     assert np.max(np.abs(G - np.eye(240))) <= 1e-12
+
+
+@pytest.mark.parametrize("m_steps", [50, 240])
+def test_conditional_second_pass(m_steps):
+    """Gram-Schmidt with the second pass only where the first one shrank ||w|| by more than 1/sqrt(2):
+    config 1 against the oracle's CGS2 recurrence (the same Krylov basis up to rounding), and the whole
+    basis orthonormal to rounding, also over 240 steps past the lowest eigenvalues' convergence."""
+    m, x = W.config(1)
+    p = Plan(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda(), m_steps,
+                    reorth="cgs2_cond", keep_basis=True)
+    torch.cuda.synchronize()
+    res = out["result"].cpu().numpy()
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, m_steps)
+    assert int(res[3]) == o["steps"] == m_steps
+    assert abs(res[0] - o["theta"]) <= 1e-12 * abs(o["theta"])
+    a = out["alpha"].cpu().numpy()
+    assert np.max(np.abs(a[:20] - o["alpha"][:20])) < 1e-11
+    V = out["V"].reshape(m_steps + 1, -1)[:m_steps].cpu().numpy()
+    assert np.max(np.abs(V.conj() @ V.T - np.eye(m_steps))) <= 1e-12
+    assert res[2] < 1e-8
