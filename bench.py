@@ -518,12 +518,20 @@ def bench_propagate(args, dev):
     stream = torch.cuda.current_stream(dev)
     dt, steps = 0.05, (2 if args.profile else 4)
     bnd = p.norm_bound(model.theta)
-    bounds = (-bnd, bnd)
+    lo, hi = p.spectral_bounds(th)
+    ms_gersh = cuda_time(lambda: p.spectral_bounds(th), stream, 1 if args.profile else 5)
+    pad = 1e-9 * max(hi - lo, abs(lo), abs(hi))
+    bounds = (lo - pad, hi + pad)
     r = p.propagate(th, xt, dt, 1, bounds=bounds)
     nt = r["n_terms"]
     out = torch.empty_like(xt)
     reps = 1 if args.profile else 3
     ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
+    nt_norm, ms_norm = None, None
+    if not args.profile:
+        nt_norm = p.propagate(th, xt, dt, 1, bounds=(-bnd, bnd))["n_terms"]
+        ms_norm = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=(-bnd, bnd), out=out), stream,
+                            reps) / steps
     y = torch.empty_like(xt)
     ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 3 if args.profile else 20)
     p.set_tuning(cheb_fused=0)
@@ -532,7 +540,9 @@ def bench_propagate(args, dev):
     back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
     res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
            "workload": "ferrimagnetic_ring_N20_c128", "D": model.dim, "dt": dt, "steps": steps,
-           "norm_bound": bnd, "terms_per_step": nt, "ms_per_step": ms, "ms_per_term": ms / max(1, nt - 1),
+           "gershgorin_bounds": [lo, hi], "gershgorin_ms": ms_gersh, "terms_per_step": nt, "ms_per_step": ms,
+           "ms_per_term": ms / max(1, nt - 1), "norm_bound": bnd, "norm_bound_terms_per_step": nt_norm,
+           "norm_bound_ms_per_step": ms_norm,
            "matvec_ms": ms_mv, "two_pass_ms_per_step": ms_two, "two_pass_ms_per_term": ms_two / max(1, nt - 1),
            "fused_speedup": ms_two / ms, "cheb_kernel": {k: tuned_cheb.get(k) for k in
                                                          ("key", "variant", "inner_sites", "unrolled_sites",

@@ -305,7 +305,8 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
  *     exp(-i H dt) = exp(-i b dt) sum_k (2 - delta_k0) (-i)^k J_k(a dt) T_k((H - b) / a),
  * a = (e_max - e_min) / 2, b = (e_max + e_min) / 2, cut where 2 sum of the remaining |J_k(a dt)| <= tol;
  * one matvec and one fused vector update per term.  The spectrum of every step's H must lie in
- * [e_min, e_max] (else the series diverges): mrmf_plan_norm_bound gives a safe symmetric bound.
+ * [e_min, e_max] (else the series diverges): mrmf_spectral_bounds (device) or mrmf_plan_norm_bound (host,
+ * symmetric, looser) give safe bounds.
  *   d_theta      : double[n_params] for step 0; step s uses d_theta + s * theta_stride (0 = fixed H;
  *                  n_params = a piecewise-constant drive stored step by step)
  *   dt           : step length (negative runs backwards); n_steps >= 0
@@ -324,6 +325,16 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
 /* Host-only: upper bound on ||H(theta)||_2, sum over terms of |theta_p w_t| ||O_a|| ||O_b|| (triangle
  * inequality; a one-site factor's norm is its largest matrix element).  h_theta: host double[n_params]. */
 mrmf_status mrmf_plan_norm_bound(mrmf_plan plan, const double* h_theta, double* bound);
+
+/* Gershgorin bounds of the spectrum of H(theta): d_out[0] <= every eigenvalue <= d_out[1] (device
+ * double[2]), the extreme ends over the rows F of H_FF -+ R_F, with R_F the sum over the row's admissible
+ * channels of |theta_p w f| (at least the row's off-diagonal sum).  One pass over the rows (no vector
+ * read); usually much tighter than mrmf_plan_norm_bound, hence fewer Chebyshev terms in
+ * mrmf_propagate_z.  Needs a plan whose parameter groups are Hermitian (MRMF_E_NOT_HERMITIAN otherwise).
+ *   d_scratch : mrmf_spectral_bounds_scratch_bytes, 8-B aligned. */
+mrmf_status mrmf_spectral_bounds_scratch_bytes(mrmf_plan plan, size_t* bytes);
+mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double* d_theta, double* d_out,
+                                 void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
 
 /* Host-only: the Bessel weights J_0(z) .. J_{K}(z) (z >= 0) used by mrmf_propagate_z, with K the smallest
  * index whose tail 2 sum_{k > K} |J_k(z)| is <= tol; *n_terms = K + 1 and h_out (may be NULL, else at

@@ -102,6 +102,90 @@ __global__ __launch_bounds__(kGenericBlock) void k_matvec_generic(
     }
 }
 
+// Gershgorin discs of H(theta): every eigenvalue lies in some [H_FF - R_F, H_FF + R_F] with R_F the sum of
+// |H_FF'| over the other entries of row F.  Per row: the diagonal (real for a Hermitian plan) from the
+// diagonal terms, and for R_F the sum over the admissible channels of |theta_p w f| (at least the row's
+// off-diagonal sum, several channels may meet in one entry).  Each block writes the minimum of
+// H_FF - R_F and the maximum of H_FF + R_F over its rows to partial[2 b], partial[2 b + 1].
+template <bool WIDE>
+__global__ __launch_bounds__(kGenericBlock) void k_gershgorin(PlanArgs p, const double* __restrict__ theta,
+                                                               double* __restrict__ partial) {
+    __shared__ uint8_t dig[kMaxSites][kGenericBlock];
+    __shared__ double slo[kGenericBlock], shi[kGenericBlock];
+    const int tid = threadIdx.x;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    const int64_t stride = int64_t(gridDim.x) * kGenericBlock;
+    for (int64_t F = int64_t(blockIdx.x) * kGenericBlock + tid; F < p.D; F += stride) {
+        if (WIDE) {
+            int64_t f = F;
+            for (int i = p.N - 1; i >= 0; --i) {
+                const int64_t d = p.site[i].d;
+                const int64_t q = f / d;
+                dig[i][tid] = static_cast<uint8_t>(f - q * d);
+                f = q;
+            }
+        } else {
+            uint32_t f = static_cast<uint32_t>(F);
+            for (int i = p.N - 1; i >= 0; --i) {
+                const uint32_t q = div_magic(f, p.site[i].magic);
+                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
+                f = q;
+            }
+        }
+        double diag = 0.0, rad = 0.0;
+        for (int k = 0; k < p.n_diag; ++k) {
+            const DevDiag g = p.diag[k];
+            double fa = local_factor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+            if (g.b >= 0) fa *= local_factor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+            diag += theta[g.param] * g.wr * fa;
+        }
+        for (int c = 0; c < p.n_chan; ++c) {
+            const DevChan ch = p.chan[c];
+            const DevSite sa = p.site[ch.a];
+            const int na = dig[ch.a][tid];
+            if (na - ch.qa < 0 || na - ch.qa >= sa.d) continue;
+            double fa = local_factor<double>(p, ch.opa, sa.tab, na);
+            if (ch.b >= 0) {
+                const DevSite sb = p.site[ch.b];
+                const int nb = dig[ch.b][tid];
+                if (nb - ch.qb < 0 || nb - ch.qb >= sb.d) continue;
+                fa *= local_factor<double>(p, ch.opb, sb.tab, nb);
+            }
+            rad += fabs(theta[ch.param] * fa) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+        }
+        lo = fmin(lo, diag - rad);
+        hi = fmax(hi, diag + rad);
+    }
+    slo[tid] = lo;
+    shi[tid] = hi;
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 1; k < kGenericBlock; ++k) {
+            lo = fmin(lo, slo[k]);
+            hi = fmax(hi, shi[k]);
+        }
+        partial[2 * blockIdx.x] = lo;
+        partial[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ void k_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    double lo = partial[0], hi = partial[1];
+    for (int b = 1; b < nb; ++b) {
+        lo = fmin(lo, partial[2 * b]);
+        hi = fmax(hi, partial[2 * b + 1]);
+    }
+    out[0] = lo;
+    out[1] = hi;
+}
+
+constexpr int kGershMaxGrid = 1024;
+
+inline int gershgorin_grid(int64_t D) {
+    const int64_t b = (D + kGenericBlock - 1) / kGenericBlock;
+    return static_cast<int>(b < kGershMaxGrid ? b : kGershMaxGrid);
+}
+
 __global__ __launch_bounds__(kGenericBlock) void k_debug_sources(PlanArgs p, int64_t F0, int64_t count,
                                                                  int64_t* __restrict__ out) {
     const int64_t r = int64_t(blockIdx.x) * kGenericBlock + threadIdx.x;
@@ -189,6 +273,35 @@ mrmf_status mrmf_debug_sources(mrmf_plan plan, const void* d_ws, int64_t F0, int
     hipLaunchKernelGGL(mrmf::k_debug_sources, dim3(static_cast<unsigned>(blocks)), dim3(mrmf::kGenericBlock), 0,
                        static_cast<hipStream_t>(stream), a, F0, count, d_out);
     return mrmf::launch_status();
+}
+
+mrmf_status mrmf_spectral_bounds_scratch_bytes(mrmf_plan plan, size_t* bytes) {
+    if (!plan || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = sizeof(double) * 2 * size_t(mrmf::gershgorin_grid(plan->D));
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double* d_theta, double* d_out,
+                                 void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
+    using namespace mrmf;
+    if (!plan || !d_ws || !d_out || !d_scratch || (plan->n_params > 0 && !d_theta)) return MRMF_E_INVALID_ARG;
+    if (!plan->hermitian) return MRMF_E_NOT_HERMITIAN;
+    if (!aligned(d_ws, 256) || !aligned(d_scratch, 8) || !aligned(d_out, 8)) return MRMF_E_INVALID_ARG;
+    size_t need = 0;
+    mrmf_spectral_bounds_scratch_bytes(plan, &need);
+    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = gershgorin_grid(plan->D);
+    double* partial = static_cast<double*>(d_scratch);
+    const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
+    if (plan->D <= int64_t(0xffffffffu))
+        hipLaunchKernelGGL(k_gershgorin<false>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws), theta,
+                           partial);
+    else
+        hipLaunchKernelGGL(k_gershgorin<true>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws), theta,
+                           partial);
+    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    return launch_status();
 }
 
 }  // extern "C"

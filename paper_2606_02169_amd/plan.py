@@ -180,12 +180,29 @@ class Plan:
                ctypes.byref(out))
         return float(out.value)
 
+    def spectral_bounds(self, theta: torch.Tensor) -> tuple:
+        """(e_min, e_max) containing the spectrum of H(theta), from the Gershgorin discs of its rows
+        (mrmf_spectral_bounds, one device pass over the rows).  theta: float64 [n_params] on the device."""
+        _need_gpu(theta, "theta", torch.float64)
+        if theta.numel() < self.n_params:
+            raise ValueError("theta has fewer than n_params entries")
+        nb = ctypes.c_size_t()
+        L.call("mrmf_spectral_bounds_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        L.call("mrmf_spectral_bounds", self._handle, _ptr(self.ws), _ptr(theta.contiguous()), _ptr(out),
+               _ptr(scratch), nb.value, _stream(self.device))
+        lo, hi = out.cpu().tolist()
+        return lo, hi
+
     def propagate(self, theta: torch.Tensor, x0: torch.Tensor, dt: float, n_steps: int = 1,
-                  bounds: tuple | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
+                  bounds: tuple | str | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
         """x = exp(-i H dt)^n_steps x0 by Chebyshev expansion (mrmf_propagate_z).  theta: float64
         [n_params] (fixed H) or [n_steps, n_params] (a piecewise-constant drive, row s for step s).
-        bounds = (e_min, e_max) must contain the spectrum of every step's H; default: +-max over the
-        steps of mrmf_plan_norm_bound.  Returns dict(x=..., n_terms=Chebyshev terms per step)."""
+        bounds = (e_min, e_max) must contain the spectrum of every step's H; default (None): the extreme
+        Gershgorin ends over the steps' distinct theta rows (spectral_bounds), widened by a relative
+        1e-9 against rounding; "norm": +-max over the steps of mrmf_plan_norm_bound (looser, host only).
+        Returns dict(x=..., n_terms=Chebyshev terms per step, bounds)."""
         _need_gpu(theta, "theta", torch.float64)
         _need_gpu(x0, "x0", torch.complex128)
         if x0.numel() != self.D:
@@ -195,11 +212,29 @@ class Plan:
             if theta.shape[0] < n_steps or theta.shape[1] != self.n_params:
                 raise ValueError("theta must be [n_steps, n_params]")
             stride = self.n_params
-        if bounds is None:
+        if bounds is None or isinstance(bounds, str):
             th = theta.detach().cpu().numpy().reshape(-1, max(1, self.n_params)) if self.n_params else np.zeros((1, 0))
-            b = max(self.norm_bound(r) for r in th[: max(1, n_steps)])
-            b = b if b > 0 else 1.0
-            bounds = (-b, b)
+            th = th[: max(1, n_steps)]
+            if bounds == "norm":
+                b = max(self.norm_bound(r) for r in th)
+                b = b if b > 0 else 1.0
+                bounds = (-b, b)
+            elif bounds is None:
+                rows = np.unique(th, axis=0) if th.shape[1] else th[:1]
+                cache = self.__dict__.setdefault("_gersh_cache", {})   # the plan's terms never change
+                ends = []
+                for r in rows:
+                    key = np.ascontiguousarray(r).tobytes()
+                    if key not in cache:
+                        if len(cache) >= 256:
+                            cache.clear()
+                        cache[key] = self.spectral_bounds(torch.from_numpy(np.ascontiguousarray(r)).to(self.device))
+                    ends.append(cache[key])
+                lo, hi = min(e[0] for e in ends), max(e[1] for e in ends)
+                pad = 1e-9 * max(hi - lo, abs(lo), abs(hi), 1e-3)
+                bounds = (lo - pad, hi + pad)
+            else:
+                raise ValueError(f"unknown bounds {bounds!r}")
         x = torch.empty_like(x0) if out is None else out
         _need_gpu(x, "out", torch.complex128)
         nb = ctypes.c_size_t()

@@ -150,3 +150,115 @@ def test_propagate_zero_steps_and_zero_time():
     r = p.propagate(t(m.theta), t(x0), 0.0, 3, bounds=(-5.0, 5.0))
     assert r["n_terms"] == 1
     assert np.array_equal(r["x"].cpu().numpy(), x0)                 # dt = 0: the identity, exactly
+
+
+# ------------------------------------------------------------------ Gershgorin spectral bounds
+def gershgorin_sparse(m, theta=None):
+    """Gershgorin ends of the oracle's sparse H: min / max over rows of H_FF -+ sum_{F' != F} |H_FF'|."""
+    from oracle import kron
+    H = kron.sparse_H(m, theta).tocsr()
+    d = H.diagonal()
+    R = np.asarray(abs(H).sum(axis=1)).ravel() - np.abs(d)
+    return float((d.real - R).min()), float((d.real + R).max())
+
+
+def gershgorin_ring_dp(N, jxy=1.0, jz=1.2, dsi=0.5, hz=0.1):
+    """Gershgorin ends of the alternating s=1/2 / s=1 XXZ ring by max-plus (min-plus) transfer matrices:
+    each row's diagonal and hop radius are sums of site and bond functions of the spins m_i, so the
+    extreme ends are closed walks around the ring, with S_+|m-1> = sqrt(s(s+1) - m(m-1)) |m>."""
+    spins = [0.5 if i % 2 == 0 else 1.0 for i in range(N)]
+    ms = [np.arange(-s, s + 1) for s in spins]
+
+    def up(s, m):      # <m|S_+|m-1>, zero when m - 1 < -s
+        return np.sqrt(s * (s + 1) - m * (m - 1)) if m - 1 >= -s else 0.0
+
+    def dn(s, m):      # <m|S_-|m+1>, zero when m + 1 > s
+        return np.sqrt(s * (s + 1) - m * (m + 1)) if m + 1 <= s else 0.0
+
+    def site(i, m):
+        return hz * m + (dsi * m * m if i % 2 == 1 else 0.0)
+
+    ends = []
+    for sign in (-1.0, 1.0):
+        mats = []
+        for i in range(N):
+            j, si, sj = (i + 1) % N, spins[i], spins[(i + 1) % N]
+            A = np.empty((len(ms[i]), len(ms[j])))
+            for a, mi in enumerate(ms[i]):
+                for b, mj in enumerate(ms[j]):
+                    rad = 0.5 * abs(jxy) * (up(si, mi) * dn(sj, mj) + dn(si, mi) * up(sj, mj))
+                    A[a, b] = site(i, mi) + jz * mi * mj + sign * rad
+            mats.append(sign * A)          # maximise sign * (diag + sign * R)
+        best = -np.inf
+        for a0 in range(len(ms[0])):       # closed walks through each state of site 0
+            v = np.full(len(ms[0]), -np.inf)
+            v[a0] = 0.0
+            for A in mats:
+                v = np.max(v[:, None] + A, axis=0)
+            best = max(best, v[a0])
+        ends.append(sign * best)
+    return ends[0], ends[1]
+
+
+def test_spectral_bounds_match_gershgorin():
+    """Reduced rings and the 20-site ring (D = 60,466,176) against the max-plus ends, a reduced ring and a
+    spin-boson model against the sparse oracle matrix (no two channels share an entry in these models)."""
+    from paper_2606_02169_amd.plan import Plan
+    for N in (8, 20):
+        m, _ = W.config(2, reduced=N if N < 20 else 0, with_state=False)
+        lo, hi = mk(m).spectral_bounds(t(m.theta))
+        rlo, rhi = gershgorin_ring_dp(N)
+        print(N, (lo, hi), (rlo, rhi), flush=True)
+        assert abs(lo - rlo) <= 1e-12 * abs(rlo) and abs(hi - rhi) <= 1e-12 * abs(rhi)
+        if N == 8:
+            slo, shi = gershgorin_sparse(m)
+            assert abs(lo - slo) <= 1e-12 * abs(slo) and abs(hi - shi) <= 1e-12 * abs(shi)
+    tc = W.tavis_cummings(4, 10, 1.0, 1.0, np.random.default_rng(5))
+    lo, hi = Plan.from_model(tc).spectral_bounds(t(tc.theta))
+    slo, shi = gershgorin_sparse(tc)
+    assert abs(lo - slo) <= 1e-12 * max(1.0, abs(slo)) and abs(hi - shi) <= 1e-12 * max(1.0, abs(shi))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_spectral_bounds_contain_spectrum(seed):
+    """Random mixed models (channels may share entries, so the channel sum can exceed the row sum): the
+    bounds contain the oracle's Gershgorin interval, hence the spectrum; propagation with them matches the
+    oracle."""
+    from oracle import kron
+    rng = np.random.default_rng(8300 + seed)
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=1200, n_params=int(rng.integers(1, 4)))
+    p = mk(m)
+    lo, hi = p.spectral_bounds(t(m.theta))
+    slo, shi = gershgorin_sparse(m)
+    ev = np.linalg.eigvalsh(kron.dense_H(m))
+    tol = 1e-12 * max(1.0, abs(slo), abs(shi))
+    print(seed, m.dim, (lo, hi), (slo, shi), (ev[0], ev[-1]), flush=True)
+    assert lo <= slo + tol and hi >= shi - tol
+    assert lo <= ev[0] + tol and hi >= ev[-1] - tol
+    x0 = W.random_state(m.dim, rng)
+    r = p.propagate(t(m.theta), t(x0), 0.4, 2)
+    assert r["bounds"][0] <= lo and r["bounds"][1] >= hi
+    assert rel_err(r["x"].cpu().numpy(), oprop.propagate(m, x0, 0.4, 2)) <= 1e-11
+
+
+def test_spectral_bounds_driven_and_fewer_terms():
+    """A piecewise drive takes the extreme ends over its steps; on the reduced ring the Gershgorin default
+    needs fewer Chebyshev terms than the norm bound for the same result."""
+    rng = np.random.default_rng(8400)
+    m = W.random_model(rng, n_sites=4, max_dim=900, n_params=3)
+    steps = 5
+    thetas = np.stack([m.theta * (1 + 0.5 * np.cos(1.3 * s)) for s in range(steps)])
+    p = mk(m)
+    each = [p.spectral_bounds(t(th)) for th in thetas]
+    x0 = W.random_state(m.dim, rng)
+    r = p.propagate(t(thetas), t(x0), 0.3, steps)
+    assert r["bounds"][0] <= min(e[0] for e in each) and r["bounds"][1] >= max(e[1] for e in each)
+    assert rel_err(r["x"].cpu().numpy(), oprop.propagate(m, x0, 0.3, steps, thetas=thetas)) <= 1e-11
+    m, x0 = W.config(2, reduced=10)
+    p = mk(m)
+    g = p.propagate(t(m.theta), t(x0), 0.5, 2)
+    n = p.propagate(t(m.theta), t(x0), 0.5, 2, bounds="norm")
+    print("terms", g["n_terms"], n["n_terms"], g["bounds"], n["bounds"], flush=True)
+    assert g["n_terms"] < n["n_terms"]
+    ref = oprop.propagate(m, x0, 0.5, 2)
+    assert rel_err(g["x"].cpu().numpy(), ref) <= 1e-11 and rel_err(n["x"].cpu().numpy(), ref) <= 1e-11
