@@ -31,6 +31,8 @@ MRMF_TUNE_CHEB_FUSED = 6
 MRMF_TUNE_WAVES_PER_EU = 7
 MRMF_TUNE_FAR_LOADS = 8
 MRMF_TUNE_GRAD_BLOCKS_PER_CU = 9
+MRMF_TUNE_OUTER_FIRST = 10
+MRMF_TUNE_UNROLL_TOP = 11
 MRMF_SOURCE_CHEB = 2
 MRMF_SOURCE_GRAD = 3
 MRMF_BATCH_SCHED_RUNS, MRMF_BATCH_SCHED_WINDOWS = 0, 1
@@ -87,7 +89,7 @@ SIGNATURES = {
     "mrmf_plan_prepare": (_i32, [_vp, _i32]),
     "mrmf_plan_set_tuning": (_i32, [_vp, _i32, _i32]),
     "mrmf_plan_autotune": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _P(_i32)]),
-    "mrmf_plan_set_shape": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
+    "mrmf_plan_set_shape": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32]),
     "mrmf_plan_kernel_info": (_i32, [_vp, _i32, _P(_i32)]),
     "mrmf_plan_kernel_source": (_i32, [_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)]),
     "mrmf_adjoint_scratch_bytes": (_i32, [_vp, _P(_sz)]),

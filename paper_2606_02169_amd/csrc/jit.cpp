@@ -8,7 +8,9 @@
 //   unrolled [k_u, k_in)  P_U digit combinations handled by every thread, one unrolled copy each, so
 //                         these digits are compile-time constants inside a copy
 //   inner    [k_in, N)    T_in rows, one per thread
-// A super-tile is the P_U * T_in consecutive rows sharing the uniform digits.  Persistent blocks sweep
+// A super-tile is the P_U * T_in consecutive rows sharing the uniform digits.  Optionally site 0 is
+// unrolled as well: a super-tile is then d_0 such runs of P_C * T_in rows, M_0 rows apart, so terms
+// between site 0 and the unrolled/inner sites (the closing bond of a ring) become static.  Persistent blocks sweep
 // the super-tiles; tiles are dealt so that the 8 XCDs each work on a contiguous stretch at a time.
 //
 // Terms.  A term touching only unrolled/inner sites is "static": its coefficient per thread and copy is
@@ -82,6 +84,7 @@ struct Gen {
     bool epi = false;
     int waves_per_eu = 0;  // > 0: ask the compiler for at least this many waves per SIMD (register budget)
     int far_nt = 0;        // > 0: gathers reaching |Delta| >= 2^far_nt bytes use LDN (non-temporal)
+    int outer_first = 0;   // the k most significant (uniform) sites vary fastest in the sweep
 
     std::string kernel_head() const {
         std::ostringstream o;
@@ -116,22 +119,49 @@ struct Gen {
 
     // scalar byte offset of copy j's rows shifted by -delta, relative to a super-tile base `b`
     std::string soff_expr(const std::string& b, int64_t j, int64_t delta) const {
-        const int64_t T = tl.T_in, sz = SZ();
+        const int64_t sz = SZ();
         std::ostringstream s;
         if (wide)
-            s << b << " + (unsigned long long)(" << (j * T * sz - delta * sz) << "ll)";
+            s << b << " + (unsigned long long)(" << (copy_off(j) * sz - delta * sz) << "ll)";
         else
-            s << b << " + " << static_cast<uint32_t>(static_cast<uint64_t>(j * T * sz - delta * sz)) << "u";
+            s << b << " + " << static_cast<uint32_t>(static_cast<uint64_t>(copy_off(j) * sz - delta * sz)) << "u";
         return s.str();
     }
+    // row offset of unrolled copy j from its super-tile base
+    int64_t copy_off(int64_t j) const {
+        if (tl.x_site < 0) return j * tl.T_in;
+        return (j % tl.P_C) * tl.T_in + (j / tl.P_C) * p->M[tl.x_site];
+    }
+    // Delta of a static channel in the LDS layout, where copy j sits at j * T_in: the unrolled site 0 moves
+    // by P_C * T_in rows there instead of M_0
+    int64_t lds_delta(int c) const {
+        const auto& ch = p->chans[c];
+        int64_t d = ch.delta;
+        if (tl.x_site >= 0) {
+            const int64_t fix = tl.P_C * tl.T_in - p->M[tl.x_site];
+            if (ch.a == tl.x_site) d += int64_t(ch.qa) * fix;
+            if (ch.b == tl.x_site) d += int64_t(ch.qb) * fix;
+        }
+        return d;
+    }
     // declaration of the super-tile base `b` for super-tile `t` (shift: the 32-bit form's base offset)
+    // Natural super-tile index of sweep position e.  With outer_first = k the sweep visits the P_k
+    // combinations of the k most significant sites back to back (their channels then read super-tiles
+    // that neighbouring blocks of the same XCD load at the same time) and the rest in natural order.
+    std::string tmap(const std::string& e) const {
+        int64_t pk = 1;
+        for (int s = tl.x_site < 0 ? 0 : tl.k_u; s < std::min(outer_first, tl.k_u); ++s) pk *= p->d[s];
+        if (pk <= 1) return e;
+        return "((" + e + ") % " + std::to_string(pk) + "u * " + std::to_string(n_st / pk) + "u + (" + e + ") / " +
+               std::to_string(pk) + "u)";
+    }
     std::string base_decl(const std::string& b, const std::string& t, int64_t shift) const {
         std::ostringstream s;
         if (wide)
-            s << "const unsigned long long " << b << " = (unsigned long long)(" << t << ") * " << ST() * SZ() << "ull;";
+            s << "const unsigned long long " << b << " = (unsigned long long)(" << t << ") * " << STC() * SZ() << "ull;";
         else
             s << "const unsigned " << b << " = " << (t.find(' ') != std::string::npos ? "(" + t + ")" : t) << " * "
-              << ST() * SZ() << "u + " << shift << "u;";
+              << STC() * SZ() << "u + " << shift << "u;";
         return s.str();
     }
     std::string rsrc_decls(int64_t shift, int64_t nrec) const {
@@ -203,10 +233,14 @@ struct Gen {
         }
     }
     bool is_inner(int s) const { return s >= tl.k_in; }
-    bool is_unrolled(int s) const { return s >= tl.k_u && s < tl.k_in; }
-    bool is_static(int s) const { return s >= tl.k_u; }
-    int64_t ST() const { return tl.T_in * tl.P_U; }
-    int udigit(int s, int64_t j) const { return static_cast<int>((j / (p->M[s] / tl.T_in)) % p->d[s]); }
+    bool is_unrolled(int s) const { return (s >= tl.k_u && s < tl.k_in) || (s >= 0 && s == tl.x_site); }
+    bool is_static(int s) const { return s >= tl.k_u || (s >= 0 && s == tl.x_site); }
+    int64_t ST() const { return tl.T_in * tl.P_U; }   // rows of a super-tile (its LDS image)
+    int64_t STC() const { return tl.T_in * tl.P_C; }  // stride of the super-tile bases in rows
+    int udigit(int s, int64_t j) const {
+        if (s == tl.x_site) return static_cast<int>((j / tl.P_C) % p->d[s]);
+        return static_cast<int>(((j % tl.P_C) / (p->M[s] / tl.T_in)) % p->d[s]);
+    }
     int kind(int a, int b) const {  // 0 static, 1 uniform, 2 mixed
         const bool sa = is_static(a);
         if (b < 0) return sa ? 0 : 1;
@@ -353,7 +387,7 @@ struct Gen {
                 for (auto so : {std::make_pair(std::get<0>(its[i]), std::get<1>(its[i])),
                                 std::make_pair(std::get<2>(its[i]), std::get<3>(its[i]))}) {
                     if (so.first < 0 || is_static(so.first)) continue;
-                    ss.push_back({static_cast<uint64_t>(P.M[so.first] / st), static_cast<uint64_t>(P.d[so.first]),
+                    ss.push_back({static_cast<uint64_t>(P.M[so.first] / STC()), static_cast<uint64_t>(P.d[so.first]),
                                   static_cast<uint64_t>(ftab(so.first, so.second))});
                 }
                 // an absent site has multiplier 0: magic 1 makes its quotient, hence its digit, 0
@@ -532,31 +566,35 @@ struct Gen {
           << "  __syncthreads();\n"
           << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
           << "  unsigned par = 0u;\n";
+        // loop over sweep positions; t is the natural super-tile index (the same unless outer_first > 0)
+        const bool remap = tmap("ts") != "ts";
+        const std::string tv = remap ? "ts" : "t";
         if (sched == MRMF_SCHED_XCD_CHUNK) {
             // XCD x (= b mod 8) sweeps the contiguous range [x C, (x + 1) C) of super-tiles with its G / 8
             // blocks side by side, so neighbouring super-tiles are read through the same L2
             o << "  const unsigned nx = (G % 8u == 0u) ? 8u : 1u, GX = G / nx, xcd = b % nx;\n"
               << "  const unsigned Cx = (" << n_st << "u + nx - 1u) / nx;\n"
               << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
-              << "  for (unsigned t = xcd * Cx + b / nx; t < t_end; t += GX) {\n";
+              << "  for (unsigned " << tv << " = xcd * Cx + b / nx; " << tv << " < t_end; " << tv << " += GX) {\n";
         } else if (sched == MRMF_SCHED_BLOCK_RUN) {
             // every block sweeps its own contiguous run of super-tiles, so a neighbour read as a channel
             // source is read again, as the block's own rows, a few super-tiles later through its own L1;
             // the runs of the blocks of one XCD are adjacent
             o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
               << "  const unsigned t_end = (unsigned)(((unsigned long long)(v + 1u) * " << n_st << "ull) / G);\n"
-              << "  for (unsigned t = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G); t < t_end; ++t) {\n";
+              << "  for (unsigned " << tv << " = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G); " << tv << " < t_end; ++" << tv << ") {\n";
         } else {
             // the grid sweeps windows of G consecutive super-tiles; XCD x takes the x-th eighth of each
             o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
-              << "  for (unsigned t = v; t < " << n_st << "u; t += G) {\n";
+              << "  for (unsigned " << tv << " = v; " << tv << " < " << n_st << "u; " << tv << " += G) {\n";
         }
+        if (remap) o << "    const unsigned t = " << tmap("ts") << ";\n";
         std::set<int> uni_sites;
         for (const auto& c : P.chans) {
             if (!is_static(c.a)) uni_sites.insert(c.a);
             if (c.b >= 0 && !is_static(c.b)) uni_sites.insert(c.b);
         }
-        for (int s : uni_sites) o << "    const unsigned n" << s << " = (t / " << P.M[s] / st << "u) % " << P.d[s] << "u;\n";
+        for (int s : uni_sites) o << "    const unsigned n" << s << " = (t / " << P.M[s] / STC() << "u) % " << P.d[s] << "u;\n";
         o << "    " << base_decl("F0", "t", shift) << "\n";
         auto soff = [&](int64_t j, int64_t delta) { return soff_expr("F0", j, delta); };
         for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = LD(xs, voff, " << soff(j, 0) << ");\n";
@@ -646,7 +684,7 @@ struct Gen {
                 for (int64_t j = 0; j < PU; ++j) {
                     auto it = kS.find({c, j});
                     if (it == kS.end()) continue;
-                    const int64_t off = halo + j * T - P.chans[c].delta;
+                    const int64_t off = halo + j * T - lds_delta(c);
                     o << "    { const C s = lb[r + " << off << "u]; ";
                     acc(j, it->second + "r", cplx ? it->second + "i" : "", "s");
                     o << " }\n";
@@ -802,7 +840,7 @@ struct Gen {
                 for (auto sop : {std::make_pair(std::get<0>(its[i]), std::get<1>(its[i])),
                                  std::make_pair(std::get<2>(its[i]), std::get<3>(its[i]))}) {
                     if (sop.first < 0 || is_static(sop.first)) continue;
-                    ss.push_back({static_cast<uint64_t>(P.M[sop.first] / st), static_cast<uint64_t>(P.d[sop.first]),
+                    ss.push_back({static_cast<uint64_t>(P.M[sop.first] / STC()), static_cast<uint64_t>(P.d[sop.first]),
                                   static_cast<uint64_t>(ftab(sop.first, sop.second))});
                 }
                 while (ss.size() < 2) ss.push_back({0, 1, static_cast<uint64_t>(one)});
@@ -846,7 +884,7 @@ struct Gen {
                 for (const Item& it : items[j]) {
                     const auto& ch = P.chans[it.c];
                     its.emplace_back(ch.a, ch.opa, ch.b, ch.opb, ch.param, ch.wr * it.ufac, ch.wi * it.ufac);
-                    soffs.push_back(static_cast<int32_t>(j * T * sz - ch.delta * sz));
+                    soffs.push_back(static_cast<int32_t>(copy_off(j) * sz - ch.delta * sz));
                     grps.push_back(it.grp);
                 }
             emit_tab("E", its, &soffs, &grps);
@@ -971,29 +1009,32 @@ struct Gen {
           << "  __syncthreads();\n"
           << "  const unsigned G = gridDim.x, b = blockIdx.x;\n"
           << "  unsigned par = 0u;\n";
+        const bool remap = tmap("ts") != "ts";
+        const std::string tv = remap ? "ts" : "t";
         if (sched == MRMF_SCHED_XCD_CHUNK) {
             o << "  const unsigned nx = (G % 8u == 0u) ? 8u : 1u, GX = G / nx, xcd = b % nx;\n"
               << "  const unsigned Cx = (" << n_st << "u + nx - 1u) / nx;\n"
               << "  const unsigned t_end = (xcd + 1u) * Cx < " << n_st << "u ? (xcd + 1u) * Cx : " << n_st << "u;\n"
               << "  const unsigned t_step = GX;\n"
-              << "  unsigned t = xcd * Cx + b / nx;\n";
+              << "  unsigned " << tv << " = xcd * Cx + b / nx;\n";
         } else if (sched == MRMF_SCHED_BLOCK_RUN) {
             o << "  const unsigned v = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n"
               << "  const unsigned t_end = (unsigned)(((unsigned long long)(v + 1u) * " << n_st << "ull) / G), t_step = 1u;\n"
-              << "  unsigned t = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G);\n";
+              << "  unsigned " << tv << " = (unsigned)(((unsigned long long)v * " << n_st << "ull) / G);\n";
         } else {
             o << "  const unsigned t_end = " << n_st << "u, t_step = G;\n"
-              << "  unsigned t = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n";
+              << "  unsigned " << tv << " = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;\n";
         }
         auto soff = [&](int64_t j, int64_t delta, const std::string& base) { return soff_expr(base, j, delta); };
         // self rows of the first super-tile
         for (int64_t j = 0; j < PU; ++j)
             o << "  C xn" << j << " = {(R)0, (R)0};\n";
-        o << "  if (t < t_end) {\n    " << base_decl("Fn", "t", shift) << "\n";
+        o << "  if (" << tv << " < t_end) {\n    " << base_decl("Fn", tmap(tv), shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "    xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
         o << "  }\n";
-        o << "  for (; t < t_end; t += t_step) {\n"
-          << "    " << base_decl("F0", "t", shift) << "\n";
+        o << "  for (; " << tv << " < t_end; " << tv << " += t_step) {\n";
+        if (remap) o << "    const unsigned t = " << tmap("ts") << ";\n";
+        o << "    " << base_decl("F0", "t", shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "    const C x" << j << " = xn" << j << ";\n";
         if (use_lds) {
             o << "    C* lb = xl" << (dbuf ? " + par * " + std::to_string(xrows) + "u" : std::string("")) << ";\n";
@@ -1056,7 +1097,7 @@ struct Gen {
         }
         o << "    __syncthreads();\n";
         // prefetch the self rows of the next super-tile
-        o << "    if (t + t_step < t_end) {\n      " << base_decl("Fn", "t + t_step", shift) << "\n";
+        o << "    if (" << tv << " + t_step < t_end) {\n      " << base_decl("Fn", tmap(tv + " + t_step"), shift) << "\n";
         for (int64_t j = 0; j < PU; ++j) o << "      xn" << j << " = LD(xs, voff, " << soff(j, 0, "Fn") << ");\n";
         o << "    }\n";
         o << "    R dUr = (R)0, dUi = (R)0;\n";
@@ -1082,7 +1123,7 @@ struct Gen {
                 for (int c : cS) {
                     auto it = kS.find({c, j});
                     if (it == kS.end()) continue;
-                    const int64_t off = halo + j * T - P.chans[c].delta;
+                    const int64_t off = halo + j * T - lds_delta(c);
                     o << "      { const C s = lb[r + " << off << "u]; ";
                     acc(j, it->second + "r", cplx ? it->second + "i" : "", "s");
                     o << " }\n";
@@ -1129,7 +1170,7 @@ struct Gen {
 // Tile choice.  Inner block: the low sites with T_in <= 1024 rows, preferring blocks of at least 256
 // rows that fill whole wavefronts.  Unrolled copies: the next sites up while P_U <= 4 and at least 2048
 // super-tiles remain to fill the GPU.
-bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, Tile* tl) {
+bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, int unroll_top, Tile* tl) {
     const int N = p->N;
     int k_in = N;
     int64_t T = 1;
@@ -1165,6 +1206,13 @@ bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, Tile* 
     tl->k_in = k_in;
     tl->k_u = k_u;
     tl->T_in = T;
+    tl->P_C = PU;
+    tl->x_site = -1;
+    if (unroll_top && k_u >= 2) {  // site 0 unrolled too; at least one uniform site remains
+        if (PU * p->d[0] > 16) return false;
+        PU *= p->d[0];
+        tl->x_site = 0;
+    }
     tl->P_U = PU;
     return true;
 }
@@ -1560,9 +1608,10 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     const int64_t SZ = f32 ? 8 : 16;
     Tile tl;
     const KernelCfg& cfg = p->cfg[epi && p->cheb_shape_set ? kSlotCheb : f32 ? MRMF_DTYPE_C : MRMF_DTYPE_Z];
-    if (!choose_tiling(p, cfg.inner, cfg.unroll, &tl)) return "";
-    const int64_t st = tl.T_in * tl.P_U;
-    const int64_t n_st = p->D / st;
+    if (!choose_tiling(p, cfg.inner, cfg.unroll, cfg.unroll_top, &tl)) return "";
+    const int64_t n_st = p->D / (tl.T_in * tl.P_U);
+    // span of one super-tile's rows from its base (its copies of site 0 lie M_0 apart)
+    const int64_t st = tl.x_site < 0 ? tl.T_in * tl.P_U : (p->d[0] - 1) * p->M[0] + tl.T_in * tl.P_C;
     int64_t dmax = 0, dmin = 0;
     for (const auto& c : p->chans) {
         dmax = std::max<int64_t>(dmax, c.delta);
@@ -1579,6 +1628,7 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     gen.epi = epi;
     gen.waves_per_eu = cfg.waves_per_eu;
     gen.far_nt = cfg.far_nt;
+    gen.outer_first = cfg.outer_first;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
     gen.gs = cfg.group;
@@ -1850,6 +1900,7 @@ void set_cfg(mrmf_plan_t* plan, int slot, const mrmf::KernelCfg& c) {
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
                       cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
                       cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu && cur.far_nt == c.far_nt &&
+                      cur.outer_first == c.outer_first && cur.unroll_top == c.unroll_top &&
                       (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
     cur = c;
     if (slot == mrmf::kSlotCheb) plan->cheb_shape_set = true;
@@ -1926,6 +1977,14 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 if (value != 0 && (value < 10 || value > 40)) return MRMF_E_INVALID_ARG;
                 c.far_nt = value;
                 break;
+            case MRMF_TUNE_OUTER_FIRST:
+                if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
+                c.outer_first = value;
+                break;
+            case MRMF_TUNE_UNROLL_TOP:
+                if (value < 0 || value > 1) return MRMF_E_INVALID_ARG;
+                c.unroll_top = value;
+                break;
             case MRMF_TUNE_GRAD_BLOCKS_PER_CU:
                 if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
                 c.grad_blocks_per_cu = value;
@@ -1940,10 +1999,11 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
 }
 
 mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, int32_t inner_sites,
-                                int32_t unrolled_sites, int32_t load_group) {
+                                int32_t unrolled_sites, int32_t load_group, int32_t unroll_top) {
     if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
         (variant != MRMF_VARIANT_MASKED && variant != MRMF_VARIANT_LIST) || inner_sites < 0 ||
-        inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N || load_group < 0 || load_group > 64)
+        inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N || load_group < 0 ||
+        load_group > 64 || unroll_top < 0 || unroll_top > 1)
         return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
     mrmf::KernelCfg c;  // schedule and block cap at their defaults
@@ -1955,6 +2015,8 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     c.cheb_fused = plan->cfg[dtype].cheb_fused;
     c.wide = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].wide;
     c.far_nt = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_nt;
+    c.outer_first = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].outer_first;
+    c.unroll_top = unroll_top;
     set_cfg(plan, dtype, c);
     return MRMF_OK;
 }
@@ -1979,7 +2041,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     const bool cheb = dtype == MRMF_SOURCE_CHEB;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     struct Cand {
-        int variant, inner, unrolled, group;
+        int variant, inner, unrolled, group, top;
     };
     // inner blocks of 32..1024 rows, 0..2 unrolled sites with at most 9 copies, both forms, three chunk
     // sizes for the list form
@@ -1997,8 +2059,17 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
             // fewer super-tiles than a quarter of the CUs leaves the GPU idle (unless the whole
             // problem is that small)
             if (plan->D / (T * PU) < 64 && u > 0) break;
-            cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0});
-            for (int g : {4, 8, 12}) cands.push_back({MRMF_VARIANT_LIST, inner, u, g});
+            cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0, 0});
+            for (int g : {4, 8, 12}) cands.push_back({MRMF_VARIANT_LIST, inner, u, g, 0});
+            // site 0 unrolled as well, when a term joins it to a site of this tile (a ring's closing bond)
+            const int k_u = k - u;
+            bool wrap = false;
+            for (const auto& c : plan->chans)
+                wrap |= (c.a == 0 && c.b >= k_u) || (c.b == 0 && c.a >= k_u);
+            if (wrap && k_u >= 2 && PU * plan->d[0] <= 16 && plan->D / (T * PU * plan->d[0]) >= 64) {
+                cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0, 1});
+                cands.push_back({MRMF_VARIANT_LIST, inner, u, 4, 1});
+            }
         }
     }
     if (cands.empty()) return MRMF_E_UNSUPPORTED;
@@ -2017,6 +2088,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         k.unroll = c.unrolled;
         k.variant = c.variant;
         k.group = c.group;
+        k.unroll_top = c.top;
         k.wide = plan->cfg[cheb ? MRMF_DTYPE_Z : dtype].wide;
         k.cheb_fused = plan->cfg[dtype].cheb_fused;
         set_cfg(plan, dtype, k);
@@ -2074,6 +2146,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
     out[2] = c.unrolled;
     out[3] = c.group;
     out[4] = static_cast<int32_t>(best / 3.f * 1000.f);  // microseconds per call
+    out[5] = c.top;
     return st;
 }
 

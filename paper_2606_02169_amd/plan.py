@@ -266,7 +266,8 @@ class Plan:
         L.call("mrmf_plan_set_kernel", self._handle, self.KERNELS[kind], int(inner_sites), int(unrolled_sites))
 
     TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
-              "cheb_fused": 6, "waves_per_eu": 7, "far_loads": 8, "grad_blocks_per_cu": 9}
+              "cheb_fused": 6, "waves_per_eu": 7, "far_loads": 8, "grad_blocks_per_cu": 9,
+              "outer_first": 10, "unroll_top": 11}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
@@ -276,7 +277,9 @@ class Plan:
         update), waves_per_eu (0 = compiler's choice, else a minimum of resident waves per SIMD),
         far_loads (0 = default cache policy, k = masked-form gathers reaching 2^k bytes or more are
         non-temporal), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
-        kernel, 0 = default)."""
+        kernel, 0 = default), outer_first (k = the k most significant sites vary fastest in the sweep
+        over super-tiles, 0 = index order), unroll_top (1 = site 0 joins the unrolled copies, so terms
+        between site 0 and the low sites read LDS)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 
@@ -303,7 +306,7 @@ class Plan:
             y = torch.empty_like(x) if y is None else y
             _need_gpu(x, "x")
             _need_gpu(y, "y", x.dtype)
-            out = (ctypes.c_int32 * 5)()
+            out = (ctypes.c_int32 * 6)()
             st = L.lib().mrmf_plan_autotune(self._handle, dt, _ptr(self.ws), _ptr(theta), _ptr(x), _ptr(y),
                                            _stream(self.device), out)
             if st == L.MRMF_E_UNSUPPORTED:   # no specialized shape fits this plan: keep the default
@@ -312,11 +315,11 @@ class Plan:
                 return dict(kind="default", key=key)
             L.check(st, "mrmf_plan_autotune")
             ent = dict(variant=out[0], inner_sites=out[1], unrolled_sites=out[2], load_group=out[3],
-                       us_per_call=out[4], D=self.D)
+                       us_per_call=out[4], D=self.D, unroll_top=out[5])
             if use_cache:
                 tuning.store(key, ent)
         L.call("mrmf_plan_set_shape", self._handle, dt, int(ent["variant"]), int(ent["inner_sites"]),
-               int(ent["unrolled_sites"]), int(ent["load_group"]))
+               int(ent["unrolled_sites"]), int(ent["load_group"]), int(ent.get("unroll_top", 0)))
         if dt != L.MRMF_SOURCE_CHEB:
             self.prepare(x.dtype)
         return dict(ent, key=key)

@@ -72,13 +72,32 @@ def test_random_models(seed):
                                          ({"variant": 1}, 8), ({"variant": 1, "schedule": 1, "load_group": 5}, 5),
                                          ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7),
                                          ({"addressing": 1}, 8), ({"addressing": 1, "variant": 1}, 6),
-                                         ({"far_loads": 10}, 8), ({"far_loads": 12, "addressing": 1}, 8)])
+                                         ({"far_loads": 10}, 8), ({"far_loads": 12, "addressing": 1}, 8),
+                                         ({"outer_first": 1}, 8), ({"outer_first": 2, "variant": 1}, 8),
+                                         ({"outer_first": 3, "schedule": 1}, 5),
+                                         ({"outer_first": 1, "variant": 1, "schedule": 2, "addressing": 1}, 7)])
 def test_tuning_variants(tuning, grid):
     m, x = W.config(2, reduced=10)           # D = 6^5: 60 super-tiles of the default shape
     check(m, x, tuning=tuning, grid=grid)
     check(m, x.astype(np.complex64), tuning=tuning, grid=grid, unrolled=1)
     m3, x3 = W.config(3, reduced=3)          # 3x3 torus: the super-tiles of the first two blocks
     check(m3, x3, tuning=tuning, grid=grid, inner=4, unrolled=1, blocks=(0, 2))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_unrolled_site0(variant):
+    """Site 0 unrolled with the low sites (copies M_0 rows apart, staged together in LDS): the reduced ring
+    (its closing bond becomes static), the 3x3 torus and random mixed models, both element types."""
+    tun = {"unroll_top": 1, "variant": variant}
+    m, x = W.config(2, reduced=10)
+    check(m, x, tuning=tun, grid=8)
+    check(m, x.astype(np.complex64), tuning=tun, grid=6, inner=3, unrolled=1)
+    m3, x3 = W.config(3, reduced=3)
+    check(m3, x3, tuning=tun, grid=8, inner=4, unrolled=1, blocks=(0, 2))
+    rng = np.random.default_rng(950 + variant)
+    for _ in range(2):
+        mr = W.random_model(rng, n_sites=5, max_dim=3000, n_params=2)
+        check(mr, W.random_state(mr.dim, rng), tuning=tun, grid=4, inner=2, unrolled=1)
 
 
 @pytest.mark.parametrize("seed", range(6))
