@@ -196,3 +196,56 @@ def test_wide_addressing_beyond_2gib(variant):
     yr = y[idx].cpu().numpy()
     xr = xt.cpu().numpy()
     assert rel_err(yr, mf.matvec(m, xr, rows=rows)) <= TOL_Z
+
+
+@pytest.mark.parametrize("k,inner,unrolled,variant,U", [(2, 7, 1, 1, 4), (2, 5, 2, 0, 0), (2, 6, 1, 0, 0),
+                                                        (3, 5, 1, 1, 4), (3, 4, 1, 0, 0)])
+def test_site0_unrolled_full_size(k, inner, unrolled, variant, U):
+    """Site 0 unrolled with the low sites (MRMF_TUNE_UNROLL_TOP; the ring's closing bond (19, 0) and the
+    torus's column wraps read LDS): full size against the default shape over the whole vector, sampled
+    rows against the oracle, two runs bit-identical."""
+    from paper_2606_02169_amd.plan import Plan
+    m, x = W.config(k)
+    dev = torch.device("cuda")
+    f32 = x.dtype == np.complex64
+    rd = torch.float32 if f32 else torch.float64
+    xt = torch.from_numpy(x).to(dev)
+    th = torch.as_tensor(m.theta, dtype=rd, device=dev)
+    ref = Plan.from_model(m)
+    ref.set_kernel("specialized", 0, 0)
+    y0 = ref.matvec(th, xt)
+    p = Plan.from_model(m)
+    p.set_kernel("specialized", inner, unrolled)
+    p.set_tuning(variant=variant, load_group=U, unroll_top=1)
+    ya = p.matvec(th, xt).clone()
+    yb = p.matvec(th, xt)
+    torch.cuda.synchronize()
+    info = p.kernel_info(xt.dtype)
+    print(info, flush=True)
+    assert info["kind"] == "specialized" and info["copies"] % m.sites[0].d == 0
+    assert torch.equal(ya, yb)
+    assert ((ya - y0).norm() / y0.norm()).item() <= (1e-6 if f32 else 1e-13)
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.concatenate([np.arange(300), np.arange(m.dim - 300, m.dim),
+                                     rng.choice(m.dim, 4000, replace=False)])).astype(np.int64)
+    yr = ya[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    assert rel_err(yr, mf.matvec(m, x.astype(np.complex128), rows=rows)) <= (TOL_C if f32 else TOL_Z)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_site0_unrolled_reduced_and_propagate(variant):
+    """Reduced ring (N = 14) with site 0 unrolled: the whole vector against the oracle, and a propagation
+    through the Chebyshev-step kernel of the same shape against the propagation oracle."""
+    from oracle import propagate as oprop
+    m, x = W.config(2, reduced=14)
+    p = plan(m, inner=4)
+    p.set_tuning(variant=variant, unroll_top=1)
+    assert rel_err(run(p, m.theta, x), mf.matvec(m, x)) <= TOL_Z
+    m8, x8 = W.config(2, reduced=8)
+    q = plan(m8, inner=3)
+    q.set_tuning(variant=variant, unroll_top=1)
+    dev = torch.device("cuda")
+    r = q.propagate(torch.from_numpy(m8.theta).to(dev), torch.from_numpy(x8).to(dev), 0.3, 2)
+    q.prepare(torch.complex128)
+    assert q.kernel_info()["kind"] == "specialized"
+    assert rel_err(r["x"].cpu().numpy(), oprop.propagate(m8, x8, 0.3, 2)) <= 1e-11
