@@ -194,11 +194,12 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                             reads a super-tile that a neighbouring block of the same XCD loads at the
  *                             same time (a periodic bond from site 0 to an inner site).  Any order
  *                             covers every row once; results are unchanged.
- *   MRMF_TUNE_UNROLL_TOP    : 1 = site 0 joins the unrolled copies: a super-tile is then d_0 runs of rows
- *                             M_0 apart, staged together in LDS, so a term between site 0 and the
- *                             unrolled/inner sites (the closing bond of a ring in site order) reads its
- *                             source from LDS instead of a gather.  Needs at least two uniform sites and
- *                             at most 16 copies in all (else the generic kernel); results are unchanged. */
+ *   MRMF_TUNE_UNROLL_TOP    : k in 1..3 = sites 0..k-1 join the unrolled copies: a super-tile is then
+ *                             d_0 ... d_(k-1) runs of rows M_s apart, staged together in LDS, so a term
+ *                             among those sites and the unrolled/inner sites (the closing bond of a ring
+ *                             in site order) reads its source from LDS instead of a gather.  Needs more
+ *                             than k uniform sites and at most 16 copies in all (else the generic
+ *                             kernel); 0 = off (default).  Results are unchanged. */
 #define MRMF_TUNE_SCHEDULE 0
 #define MRMF_TUNE_BRANCH_SKIP 1
 #define MRMF_TUNE_LOAD_GROUP 2
@@ -218,7 +219,7 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_SCHED_BLOCK_RUN 2
 mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value);
 /* Shape of the specialized kernel for one element type only (e.g. from a tuning cache): form
- * (MRMF_VARIANT_*), inner sites, unrolled sites, load group, site 0 unrolled (0/1, MRMF_TUNE_UNROLL_TOP);
+ * (MRMF_VARIANT_*), inner sites, unrolled sites, load group, top sites unrolled (0..3, MRMF_TUNE_UNROLL_TOP);
  * the other tuning knobs keep their values.  Selection becomes MRMF_KERNEL_AUTO for that
  * element type (the generic kernel runs when the shape does not fit).  mrmf_plan_set_kernel and
  * mrmf_plan_set_tuning set both element types.  dtype = MRMF_SOURCE_CHEB sets the shape of the
@@ -227,11 +228,11 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
                                 int32_t unrolled_sites, int32_t load_group, int32_t unroll_top);
 /* Autotuner for the plain matvec: times every candidate shape of the specialized kernel (inner block of
  * 32..1024 rows, 0..2 unrolled sites, masked and list forms, list chunk 4/8/12; where a term joins site 0
- * to the unrolled/inner sites, also with site 0 unrolled (MRMF_TUNE_UNROLL_TOP) in the masked form and
- * the list form with chunk 4) on the given buffers with HIP events on the stream (synchronising it),
+ * to the unrolled/inner sites, also with sites 0 and 0..1 unrolled (MRMF_TUNE_UNROLL_TOP) in the masked
+ * form and the list form with chunk 4) on the given buffers with HIP events on the stream (synchronising it),
  * keeps the fastest in the plan for this element type only (selection MRMF_KERNEL_AUTO) and writes host
- * out[0..5] = (variant, inner sites, unrolled sites, load group, microseconds per call, site 0 unrolled
- * 0/1); the other tuning knobs return to their defaults.  y is
+ * out[0..5] = (variant, inner sites, unrolled sites, load group, microseconds per call, top sites
+ * unrolled 0..2); the other tuning knobs return to their defaults.  y is
  * overwritten; x must not overlap y.  dtype = MRMF_SOURCE_CHEB tunes the Chebyshev-step kernel of
  * mrmf_propagate_z instead (c128, double theta); then d_y must hold 2 D c128 elements (the step's
  * previous-term and accumulator vectors), all overwritten. */

@@ -129,19 +129,17 @@ struct Gen {
     }
     // row offset of unrolled copy j from its super-tile base
     int64_t copy_off(int64_t j) const {
-        if (tl.x_site < 0) return j * tl.T_in;
-        return (j % tl.P_C) * tl.T_in + (j / tl.P_C) * p->M[tl.x_site];
+        int64_t off = (j % tl.P_C) * tl.T_in;
+        for (int s = 0; s < tl.n_top; ++s) off += udigit(s, j) * p->M[s];
+        return off;
     }
     // Delta of a static channel in the LDS layout, where copy j sits at j * T_in: the unrolled site 0 moves
     // by P_C * T_in rows there instead of M_0
     int64_t lds_delta(int c) const {
         const auto& ch = p->chans[c];
         int64_t d = ch.delta;
-        if (tl.x_site >= 0) {
-            const int64_t fix = tl.P_C * tl.T_in - p->M[tl.x_site];
-            if (ch.a == tl.x_site) d += int64_t(ch.qa) * fix;
-            if (ch.b == tl.x_site) d += int64_t(ch.qb) * fix;
-        }
+        if (is_top(ch.a)) d += int64_t(ch.qa) * (cstride(ch.a) * tl.T_in - p->M[ch.a]);
+        if (is_top(ch.b)) d += int64_t(ch.qb) * (cstride(ch.b) * tl.T_in - p->M[ch.b]);
         return d;
     }
     // declaration of the super-tile base `b` for super-tile `t` (shift: the 32-bit form's base offset)
@@ -150,7 +148,7 @@ struct Gen {
     // that neighbouring blocks of the same XCD load at the same time) and the rest in natural order.
     std::string tmap(const std::string& e) const {
         int64_t pk = 1;
-        for (int s = tl.x_site < 0 ? 0 : tl.k_u; s < std::min(outer_first, tl.k_u); ++s) pk *= p->d[s];
+        for (int s = tl.n_top > 0 ? tl.k_u : 0; s < std::min(outer_first, tl.k_u); ++s) pk *= p->d[s];
         if (pk <= 1) return e;
         return "((" + e + ") % " + std::to_string(pk) + "u * " + std::to_string(n_st / pk) + "u + (" + e + ") / " +
                std::to_string(pk) + "u)";
@@ -233,12 +231,20 @@ struct Gen {
         }
     }
     bool is_inner(int s) const { return s >= tl.k_in; }
-    bool is_unrolled(int s) const { return (s >= tl.k_u && s < tl.k_in) || (s >= 0 && s == tl.x_site); }
-    bool is_static(int s) const { return s >= tl.k_u || (s >= 0 && s == tl.x_site); }
+    bool is_top(int s) const { return s >= 0 && s < tl.n_top; }
+    bool is_unrolled(int s) const { return (s >= tl.k_u && s < tl.k_in) || is_top(s); }
+    bool is_static(int s) const { return s >= tl.k_u || is_top(s); }
+    // copy-index stride of unrolled top site s (< n_top): the contiguous combinations vary fastest, then
+    // sites n_top - 1 .. 0
+    int64_t cstride(int s) const {
+        int64_t c = tl.P_C;
+        for (int u = s + 1; u < tl.n_top; ++u) c *= p->d[u];
+        return c;
+    }
     int64_t ST() const { return tl.T_in * tl.P_U; }   // rows of a super-tile (its LDS image)
     int64_t STC() const { return tl.T_in * tl.P_C; }  // stride of the super-tile bases in rows
     int udigit(int s, int64_t j) const {
-        if (s == tl.x_site) return static_cast<int>((j / tl.P_C) % p->d[s]);
+        if (is_top(s)) return static_cast<int>((j / cstride(s)) % p->d[s]);
         return static_cast<int>(((j % tl.P_C) / (p->M[s] / tl.T_in)) % p->d[s]);
     }
     int kind(int a, int b) const {  // 0 static, 1 uniform, 2 mixed
@@ -1207,11 +1213,11 @@ bool choose_tiling(const mrmf_plan_t* p, int inner_pref, int unroll_pref, int un
     tl->k_u = k_u;
     tl->T_in = T;
     tl->P_C = PU;
-    tl->x_site = -1;
-    if (unroll_top && k_u >= 2) {  // site 0 unrolled too; at least one uniform site remains
-        if (PU * p->d[0] > 16) return false;
-        PU *= p->d[0];
-        tl->x_site = 0;
+    tl->n_top = 0;
+    if (unroll_top > 0 && k_u > unroll_top) {  // sites 0..unroll_top-1 unrolled too; a uniform site remains
+        for (int s = 0; s < unroll_top; ++s) PU *= p->d[s];
+        if (PU > 16) return false;
+        tl->n_top = unroll_top;
     }
     tl->P_U = PU;
     return true;
@@ -1611,7 +1617,9 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     if (!choose_tiling(p, cfg.inner, cfg.unroll, cfg.unroll_top, &tl)) return "";
     const int64_t n_st = p->D / (tl.T_in * tl.P_U);
     // span of one super-tile's rows from its base (its copies of site 0 lie M_0 apart)
-    const int64_t st = tl.x_site < 0 ? tl.T_in * tl.P_U : (p->d[0] - 1) * p->M[0] + tl.T_in * tl.P_C;
+    int64_t st = tl.T_in * tl.P_C;
+    for (int s = 0; s < tl.n_top; ++s) st += (p->d[s] - 1) * p->M[s];
+    if (tl.n_top == 0) st = tl.T_in * tl.P_U;
     int64_t dmax = 0, dmin = 0;
     for (const auto& c : p->chans) {
         dmax = std::max<int64_t>(dmax, c.delta);
@@ -1982,7 +1990,7 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 c.outer_first = value;
                 break;
             case MRMF_TUNE_UNROLL_TOP:
-                if (value < 0 || value > 1) return MRMF_E_INVALID_ARG;
+                if (value < 0 || value > 3) return MRMF_E_INVALID_ARG;
                 c.unroll_top = value;
                 break;
             case MRMF_TUNE_GRAD_BLOCKS_PER_CU:
@@ -2003,7 +2011,7 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     if (!plan || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
         (variant != MRMF_VARIANT_MASKED && variant != MRMF_VARIANT_LIST) || inner_sites < 0 ||
         inner_sites > plan->N || unrolled_sites < -1 || unrolled_sites > plan->N || load_group < 0 ||
-        load_group > 64 || unroll_top < 0 || unroll_top > 1)
+        load_group > 64 || unroll_top < 0 || unroll_top > 3)
         return MRMF_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(plan->mtx);
     mrmf::KernelCfg c;  // schedule and block cap at their defaults
@@ -2066,9 +2074,12 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
             bool wrap = false;
             for (const auto& c : plan->chans)
                 wrap |= (c.a == 0 && c.b >= k_u) || (c.b == 0 && c.a >= k_u);
-            if (wrap && k_u >= 2 && PU * plan->d[0] <= 16 && plan->D / (T * PU * plan->d[0]) >= 64) {
-                cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0, 1});
-                cands.push_back({MRMF_VARIANT_LIST, inner, u, 4, 1});
+            int64_t PT = PU;
+            for (int top = 1; wrap && top <= 2 && k_u > top; ++top) {  // sites 0..top-1 unrolled too
+                PT *= plan->d[top - 1];
+                if (PT > 16 || plan->D / (T * PT) < 64) break;
+                cands.push_back({MRMF_VARIANT_MASKED, inner, u, 0, top});
+                cands.push_back({MRMF_VARIANT_LIST, inner, u, 4, top});
             }
         }
     }

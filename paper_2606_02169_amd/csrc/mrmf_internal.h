@@ -93,8 +93,8 @@ struct Tiling {
 struct Tile {
     int k_u = 0, k_in = 0;
     int64_t T_in = 1, P_U = 1;
-    int x_site = -1;   // 0: site 0 is unrolled too (its copies lie M_0 rows apart), -1: none
-    int64_t P_C = 1;   // combinations of the contiguous unrolled sites [k_u, k_in); P_U = P_C * d_0 with x_site
+    int n_top = 0;     // sites [0, n_top) are unrolled too (their copies lie M_s rows apart)
+    int64_t P_C = 1;   // combinations of the contiguous unrolled sites [k_u, k_in); P_U = P_C * d_0 ... d_(n_top-1)
 };
 
 // Kernel selection and shape knobs of one element type (MRMF_KERNEL_*, MRMF_TUNE_*).
@@ -109,7 +109,7 @@ struct KernelCfg {
     int32_t far_nt = 0;  // > 0: masked-form gathers with |Delta| >= 2^far_nt bytes are non-temporal loads
     int32_t grad_blocks_per_cu = 0;  // blocks per CU of the generated gradient kernel (0: the default, 2)
     int32_t outer_first = 0;  // the k most significant sites vary fastest in the super-tile sweep
-    int32_t unroll_top = 0;   // 1: site 0 joins the unrolled copies of every super-tile
+    int32_t unroll_top = 0;   // k: sites 0..k-1 join the unrolled copies of every super-tile
 };
 
 // Slot of the c128 kernel with the Chebyshev-step epilogue in mrmf_plan_t::spec (after the dtypes).

@@ -278,8 +278,8 @@ class Plan:
         far_loads (0 = default cache policy, k = masked-form gathers reaching 2^k bytes or more are
         non-temporal), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
         kernel, 0 = default), outer_first (k = the k most significant sites vary fastest in the sweep
-        over super-tiles, 0 = index order), unroll_top (1 = site 0 joins the unrolled copies, so terms
-        between site 0 and the low sites read LDS)."""
+        over super-tiles, 0 = index order), unroll_top (k = sites 0..k-1 join the unrolled copies, so terms
+        between them and the low sites read LDS; 0 = off)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 

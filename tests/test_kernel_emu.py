@@ -84,20 +84,21 @@ def test_tuning_variants(tuning, grid):
     check(m3, x3, tuning=tuning, grid=grid, inner=4, unrolled=1, blocks=(0, 2))
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_unrolled_site0(variant):
-    """Site 0 unrolled with the low sites (copies M_0 rows apart, staged together in LDS): the reduced ring
-    (its closing bond becomes static), the 3x3 torus and random mixed models, both element types."""
-    tun = {"unroll_top": 1, "variant": variant}
+@pytest.mark.parametrize("variant,top", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_unrolled_site0(variant, top):
+    """Sites 0..top-1 unrolled with the low sites (copies M_s rows apart, staged together in LDS): the
+    reduced ring (its closing bond becomes static), the 3x3 torus and random mixed models, both element
+    types."""
+    tun = {"unroll_top": top, "variant": variant}
     m, x = W.config(2, reduced=10)
-    check(m, x, tuning=tun, grid=8)
+    check(m, x, tuning=tun, grid=8, inner=3, unrolled=0)
     check(m, x.astype(np.complex64), tuning=tun, grid=6, inner=3, unrolled=1)
     m3, x3 = W.config(3, reduced=3)
-    check(m3, x3, tuning=tun, grid=8, inner=4, unrolled=1, blocks=(0, 2))
-    rng = np.random.default_rng(950 + variant)
+    check(m3, x3, tuning=tun, grid=8, inner=4, unrolled=0 if top == 2 else 1, blocks=(0, 2))
+    rng = np.random.default_rng(950 + 2 * variant + top)
     for _ in range(2):
         mr = W.random_model(rng, n_sites=5, max_dim=3000, n_params=2)
-        check(mr, W.random_state(mr.dim, rng), tuning=tun, grid=4, inner=2, unrolled=1)
+        check(mr, W.random_state(mr.dim, rng), tuning=tun, grid=4, inner=2, unrolled=0)
 
 
 @pytest.mark.parametrize("seed", range(6))
