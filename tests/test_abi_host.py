@@ -256,3 +256,34 @@ def test_general_operator_validation_and_hermiticity():
         want = sh(t.op_a) * M[t.site_a] + (sh(t.op_b) * M[t.site_b] if t.site_b >= 0 else 0)
         assert offs[c] == want
     L.lib().mrmf_plan_destroy(h)
+
+
+def test_spectral_bounds_argument_checks():
+    """mrmf_spectral_bounds rejects bad arguments before any launch: null pointers, a non-Hermitian plan,
+    misaligned buffers, too small a scratch (the pointers below are never dereferenced)."""
+    import workloads as W
+    from workloads.model import OP_RAISE, OP_Z, Model, Term, spin_site
+    st, h = host_plan(W.xx_chain_in_field(4, 1.0, 0.2))
+    assert st == 0
+    try:
+        nb = ctypes.c_size_t()
+        assert L.lib().mrmf_spectral_bounds_scratch_bytes(h, ctypes.byref(nb)) == 0
+        assert nb.value >= 16 and nb.value % 16 == 0
+        fake = ctypes.c_void_p(1 << 20)
+        fn = L.lib().mrmf_spectral_bounds
+        assert fn(None, fake, fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(h, None, fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(h, fake, fake, fake, None, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(h, ctypes.c_void_p((1 << 20) + 8), fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(h, fake, fake, ctypes.c_void_p((1 << 20) + 4), fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(h, fake, fake, fake, fake, nb.value - 16, None) == L.MRMF_E_WORKSPACE
+    finally:
+        L.lib().mrmf_plan_destroy(h)
+    st, q = host_plan(Model([spin_site(1)], [Term(0, OP_RAISE, -1, OP_Z, 0, 1.0)], np.ones(1)),
+                      require_hermitian=False)
+    assert st == 0
+    try:
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.lib().mrmf_spectral_bounds(q, fake, fake, fake, fake, 1 << 20, None) == L.MRMF_E_NOT_HERMITIAN
+    finally:
+        L.lib().mrmf_plan_destroy(q)
