@@ -202,7 +202,7 @@ def bench_ring(args, dev):
         "data": "synthetic",
         "config": {"workload": "ferrimagnetic_ring_N20_c128", "sites": "20 (s=1/2, s=1 alternating), periodic",
                    "D": D, "couplings": "Jxy=1.0 Jz=1.2 D_si=0.5 hz=0.1", "seed": 2,
-                   "kernel": {k: info[k] for k in ("kind", "inner_sites", "unrolled_sites", "block", "grid")}},
+                   "kernel": {k: info[k] for k in ("kind", "inner_sites", "unrolled_sites", "copies", "block", "grid")}},
         "effective_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
@@ -652,7 +652,7 @@ def bench_paper(args, dev):
         torch.cuda.synchronize()
         if args.profile:  # short run for a profiler: the matvec launches only (C1's first, then C2's)
             out["cases"][model.name] = {"D": D, "matvec_ms_c128": ms, "sampled_rel_err_vs_oracle": err,
-                                        "kernel": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites")}}
+                                        "kernel": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites", "unroll_top")}}
             continue
         t0 = time.perf_counter()
         r = plan.lanczos(th, x, m_steps)
@@ -663,7 +663,7 @@ def bench_paper(args, dev):
         torch.cuda.empty_cache()
         paper = PAPER_TABLE1[model.name]
         out["cases"][model.name] = {
-            "D": D, "seed": seed, "kernel": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites")},
+            "D": D, "seed": seed, "kernel": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites", "unroll_top")},
             "matvec_ms_c128": ms, "matvecs_per_s": 1000.0 / ms, "effective_GBps": 2 * D * 16 / ms / 1e6,
             "sampled_rel_err_vs_oracle": err,
             "lanczos": {"steps": int(res[3]), "reorth": "CGS2", "seconds": lz_s, "E0": float(res[0]),
