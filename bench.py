@@ -9,6 +9,7 @@ the launch stream, against 8 TB/s), the HBM traffic from committed rocprofv3 cou
 taken on the same kernel, and the CPU oracle timed on the host cores.
 
 Other workloads (one JSON line each; not part of the headline):
+  --workload torus      4x4 periodic spin-1 Heisenberg (D = 3^16): the matvec alone, c64 and c128
   --workload lanczos4x4  4x4 periodic spin-1 Heisenberg (D = 3^16): FP32 (c64) matvec inside the FP64
                          Lanczos against the plain FP64 form: steps and wall time to 1e-5 relative
                          ground-energy error, end to end and matvec only
@@ -223,6 +224,63 @@ def bench_ring(args, dev):
         log(f"cpu baseline: {cb}; rel err vs oracle {err:.3e}")
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------------------------------ torus
+def bench_torus(args, dev):
+    """The 4x4 periodic spin-1 Heisenberg lattice (D = 3^16, 32 bonds with J_b ~ U[0.5, 1.5], seed 3):
+    the matvec alone in its FP32 (c64) form and in the plain FP64 (c128) form, each with its autotuned
+    shape; algorithmic bytes 2 * D * b per launch (b = 8 or 16).  --dtype picks one form (profiler runs),
+    else both are timed."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2606_02169_amd.plan import Plan
+
+    model, x32 = W.config(3)
+    D = model.dim
+    stream = torch.cuda.current_stream(dev)
+    forms = {"c64": (torch.complex64, torch.float32, 8), "c128": (torch.complex128, torch.float64, 16)}
+    names = [args.dtype] if args.dtype else ["c64", "c128"]
+    out = {"metric": "H·x on the 4x4 periodic spin-1 lattice (D = 3^16): matvecs/s and effective HBM GB/s",
+           "workload": "square4x4_spin1_periodic", "D": D, "seed": 3, "forms": {}}
+    for name in names:
+        cdt, rdt, b = forms[name]
+        plan = Plan.from_model(model, device=dev)
+        x = torch.from_numpy(x32).to(dev).to(cdt)
+        y = torch.empty_like(x)
+        th = torch.as_tensor(model.theta, dtype=rdt, device=dev)
+        tuned = plan.autotune(th, x, y)
+        info = plan.kernel_info(cdt)
+        if args.profile:   # plain copy of known size in the same process: scale for the traffic counters
+            for _ in range(3):
+                y.copy_(x)
+            torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            plan.matvec(th, x, out=y)
+        ms = cuda_time(lambda: plan.matvec(th, x, out=y), stream, args.steps)
+        alg = 2 * D * b
+        res = {"ms_per_matvec": ms, "matvecs_per_s": 1000.0 / ms, "effective_GBps": alg / ms / 1e6,
+               "frac_of_peak": alg / ms / 1e6 / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": alg,
+               "kernel_fingerprint": kernel_fingerprint(plan, cdt),
+               "shape": {k: tuned.get(k) for k in ("variant", "inner_sites", "unrolled_sites", "load_group",
+                                                    "unroll_top")},
+               "kernel": {k: info[k] for k in ("inner_sites", "unrolled_sites", "copies", "block", "grid",
+                                               "super_tiles")}}
+        if not args.profile:
+            from oracle import mf
+            rng = np.random.default_rng(33)
+            rows = np.unique(rng.choice(D, 4000, replace=False)).astype(np.int64)
+            xin = x.cpu().numpy().astype(np.complex128)
+            ref = mf.matvec(model, xin, rows=rows)
+            got = y[torch.from_numpy(rows).to(dev)].cpu().numpy()
+            res["sampled_rel_err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["forms"][name] = res
+        log(f"{name}: {res}")
+        del x, y, plan
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
@@ -681,9 +739,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
-    ap.add_argument("--workload", default="ring20", choices=["ring20", "lanczos4x4", "lanczos_ring20", "batched",
-                                                              "adjoint", "paper",
-                                                                  "propagate", "sector"])
+    ap.add_argument("--workload", default="ring20", choices=["ring20", "torus", "lanczos4x4", "lanczos_ring20",
+                                                              "batched", "adjoint", "paper", "propagate", "sector"])
+    ap.add_argument("--dtype", default=None, choices=["c64", "c128"], help="torus: one element type only")
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
     args = ap.parse_args()
@@ -697,7 +755,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    {"ring20": bench_ring, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
+    {"ring20": bench_ring, "torus": bench_torus, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
      "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
      "sector": bench_sector}[args.workload](args, dev)
 

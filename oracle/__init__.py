@@ -5,8 +5,9 @@ A plain, slow, FP64 CPU implementation of what the matrix-free path computes, wr
 
 * ``kron``     : the plain definition, H as a sum of Kronecker products (site 0 leftmost), dense or
                  scipy-sparse, for tiny systems (Sec. I; Sec. III multiplier order).
-* ``mf``       : the target-driven row loop of App. A in plain C (``mf_ref.c``), extended with the
-                 (S_z)^2 channel of App. B and boson digits of App. C; full vectors or sampled rows.
+* ``mf``       : y = H x row by row in plain C (``mf_ref.c``): each row of the Kronecker sum evaluated
+                 from dense local matrices built from their closed forms (Sec. IV.A spins, App. B powers
+                 and general one-site operators, App. C bosons); full vectors or sampled rows.
 * ``lanczos``  : Lanczos with full CGS2 reorthogonalisation and the tridiagonal eigen solve (the
                  Krylov driver the paper cites in Sec. I; the paper gives no algorithm of its own).
 * ``grad``     : the gradient of y = H(theta) x (adjoint form) and of the Rayleigh quotient.

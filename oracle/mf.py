@@ -1,14 +1,15 @@
-"""ORACLE (test infrastructure): Python side of the plain App-A matvec in ``mf_ref.c``.
+"""ORACLE (test infrastructure): Python side of the plain row-by-row evaluation in ``mf_ref.c``.
 
-The term list of a model is first collapsed into the pseudocode's inputs (App. A): per-site one-site
-couplings (h_z, h_+, h_-, plus the (S_z)^2 and (S_+-)^2 couplings of App. B) and a pair list with a 3x3 table
-J^{alpha beta}, alpha, beta in (z, +, -), each coupling being theta[p] * w summed over the terms that
-land on it.  The C code then runs the pseudocode's row loop over all rows or over sampled rows.
+y = H x is computed one target row at a time as the row of the Kronecker sum that defines H (Sec. I,
+with the mixed-radix flattening of Sec. III): every term contributes the products of its local matrix
+elements times the entries of x whose digits differ from the row's only on the term's own sites.  The
+term list is passed as it is (sites, operator codes, complex coefficients theta[p] w); the built-in local
+matrices are built inside the C code from their closed forms, and a general one-site operator is handed
+over as the dense matrix of its band.
 """
 from __future__ import annotations
 
 import ctypes
-import os
 
 import numpy as np
 
@@ -16,8 +17,8 @@ from workloads.model import OP_LOCAL_BASE, OP_LOWER, OP_LOWER2, OP_RAISE, OP_RAI
 
 from . import build as _build
 
-_ALPHA = {OP_Z: 0, OP_RAISE: 1, OP_LOWER: 2}
 _lib = None
+_GENERAL = 16          # operator code of general matrix 0 in mf_ref.c
 
 
 def lib():
@@ -28,12 +29,9 @@ def lib():
         i32p = ctypes.POINTER(ctypes.c_int32)
         f64p = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)
-        L.mf_ref_matvec.restype = ctypes.c_int
-        L.mf_ref_matvec.argtypes = [ctypes.c_int32, i32p, i32p, f64p, ctypes.c_int32, i32p, i32p,
-                                    f64p, ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
-        L.mf_ref_general_add.restype = ctypes.c_int
-        L.mf_ref_general_add.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, i64p, f64p, f64p,
-                                         ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
+        L.mf_ref_apply.restype = ctypes.c_int
+        L.mf_ref_apply.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, f64p, ctypes.c_int32, i64p,
+                                   f64p, ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
         L.mf_ref_sources.restype = ctypes.c_int
         L.mf_ref_sources.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int64,
                                      ctypes.c_int64, i64p]
@@ -45,87 +43,51 @@ def _p(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def app_a_inputs(model: Model, theta=None):
-    """Collapse the term list into (kind, 2s, onsite[N,6], pair_i, pair_j, J[P,3,3])."""
-    theta = model.theta if theta is None else np.asarray(theta, dtype=np.float64)
-    N = len(model.sites)
-    kind, twok = model.site_arrays()
-    onsite = np.zeros((N, 6), dtype=np.complex128)  # h_z, h_zz, h_+, h_-, h_++, h_--
-    pairs: dict = {}
-    Jlist = []
-    for t in model.terms:
-        if _is_general(t):
-            continue                       # handled by general_inputs / mf_ref_general_add
-        c = theta[t.param] * complex(t.w)
-        if t.site_b < 0:
-            col = {OP_Z: 0, OP_Z2: 1, OP_RAISE: 2, OP_LOWER: 3, OP_RAISE2: 4, OP_LOWER2: 5}[t.op_a]
-            onsite[t.site_a, col] += c
-            continue
-        if t.site_a == t.site_b or t.op_a not in _ALPHA or t.op_b not in _ALPHA:
-            raise ValueError("pair terms take two different sites and operators in (z, +, -)")
-        key = (t.site_a, t.site_b)
-        if key not in pairs:
-            pairs[key] = len(Jlist)
-            Jlist.append(np.zeros((3, 3), dtype=np.complex128))
-        Jlist[pairs[key]][_ALPHA[t.op_a], _ALPHA[t.op_b]] += c
-    keys = sorted(pairs, key=lambda k: pairs[k])
-    pi = np.array([k[0] for k in keys], dtype=np.int32)
-    pj = np.array([k[1] for k in keys], dtype=np.int32)
-    J = np.array(Jlist, dtype=np.complex128).reshape(-1, 3, 3) if Jlist else np.zeros((0, 3, 3), np.complex128)
-    return kind, twok, onsite, pi, pj, J
-
-
-def _is_general(t) -> bool:
-    return t.op_a >= OP_LOCAL_BASE or (t.site_b >= 0 and t.op_b >= OP_LOCAL_BASE)
-
-
-def _band(model: Model, op: int, site: int):
-    """(shift, table at target digits) of one operator: a general one's given table, or the band of the
-    closed-form local matrix of a built-in one (oracle.kron.local_ops)."""
+def term_inputs(model: Model, theta=None):
+    """The term list as mf_ref_apply takes it: (term [n, 4] = site_a, op_a, site_b, op_b; coef [n] complex;
+    gen_off [g]; gen_mat), built-in operators keeping their codes and every general one-site operator
+    replaced by the index of its dense matrix (code 16 + g)."""
     from . import kron
-    if op >= OP_LOCAL_BASE:
-        lo = model.local_ops[op - OP_LOCAL_BASE]
-        if lo.site != site:
-            raise ValueError("a general operator acts on its own site only")
-        return lo.shift, np.asarray(lo.values, dtype=np.float64)
-    Mx = kron.local_ops(model.sites[site])[op]
-    d = Mx.shape[0]
-    q = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}[op]
-    return q, np.array([Mx[n, n - q] if 0 <= n - q < d else 0.0 for n in range(d)])
-
-
-def general_inputs(model: Model, theta=None):
-    """Terms with a general one-site operator as (gterm [n,4], toff [n,2], tab, c [n] complex)."""
     theta = model.theta if theta is None else np.asarray(theta, dtype=np.float64)
-    gterm, toff, tab, c = [], [], [], []
+    gen_index: dict = {}
+    mats = []
+    off = []
     size = 0
-    for t in model.terms:
-        if not _is_general(t):
-            continue
-        qa, ta = _band(model, t.op_a, t.site_a)
-        if t.site_b >= 0:
-            qb, tb = _band(model, t.op_b, t.site_b)
-        else:
-            qb, tb = 0, np.zeros(0)
-        gterm.append((t.site_a, qa, t.site_b, qb))
-        toff.append((size, size + ta.size))
-        tab += [ta, tb]
-        size += ta.size + tb.size
-        c.append(theta[t.param] * complex(t.w))
-    return (np.array(gterm, dtype=np.int32).reshape(-1, 4), np.array(toff, dtype=np.int64).reshape(-1, 2),
-            np.concatenate(tab) if tab else np.zeros(1), np.array(c, dtype=np.complex128))
+
+    def code(op, site):
+        nonlocal size
+        if op < OP_LOCAL_BASE:
+            return op
+        key = (op, site)
+        if key not in gen_index:
+            Mx = np.ascontiguousarray(kron.general_op(model, op, site), dtype=np.float64)
+            gen_index[key] = len(mats)
+            mats.append(Mx.ravel())
+            off.append(size)
+            size += Mx.size
+        return _GENERAL + gen_index[key]
+
+    term = np.zeros((len(model.terms), 4), dtype=np.int32)
+    coef = np.zeros(len(model.terms), dtype=np.complex128)
+    for i, t in enumerate(model.terms):
+        if t.site_b >= 0 and t.site_b == t.site_a:
+            raise ValueError("a two-site term needs two different sites")
+        term[i] = (t.site_a, code(t.op_a, t.site_a), t.site_b, code(t.op_b, t.site_b) if t.site_b >= 0 else 0)
+        coef[i] = theta[t.param] * complex(t.w)
+    gen_off = np.array(off, dtype=np.int64) if off else np.zeros(1, dtype=np.int64)
+    gen_mat = np.concatenate(mats) if mats else np.zeros(1)
+    return term, coef, len(mats), gen_off, gen_mat
 
 
 def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
     """y = H(theta) x in FP64 (x is upcast exactly).  rows: optional int64 target indices; then the
     result holds y at those rows only."""
-    kind, twok, onsite, pi, pj, J = app_a_inputs(model, theta)
+    kind, twok = model.site_arrays()
     D = model.dim
     xx = np.ascontiguousarray(np.asarray(x).reshape(-1), dtype=np.complex128)
     if xx.shape[0] != D:
         raise ValueError(f"x has {xx.shape[0]} entries, the basis has {D}")
-    onsite = np.ascontiguousarray(onsite)
-    J = np.ascontiguousarray(J)
+    term, coef, n_gen, gen_off, gen_mat = term_inputs(model, theta)
     if rows is None:
         nrows, rp = D, None
     else:
@@ -134,31 +96,30 @@ def matvec(model: Model, x: np.ndarray, theta=None, rows=None) -> np.ndarray:
             raise ValueError("row index out of range")
         nrows, rp = rows.shape[0], _p(rows, ctypes.c_int64)
     y = np.empty(nrows, dtype=np.complex128)
-    rc = lib().mf_ref_matvec(len(model.sites), _p(kind, ctypes.c_int32), _p(twok, ctypes.c_int32),
-                             _p(onsite.view(np.float64), ctypes.c_double), len(pi),
-                             _p(pi, ctypes.c_int32), _p(pj, ctypes.c_int32),
-                             _p(J.view(np.float64), ctypes.c_double), D,
-                             _p(xx.view(np.float64), ctypes.c_double),
-                             _p(y.view(np.float64), ctypes.c_double), nrows, rp)
+    rc = lib().mf_ref_apply(len(model.sites), _p(kind, ctypes.c_int32), _p(twok, ctypes.c_int32), term.shape[0],
+                            _p(term, ctypes.c_int32), _p(coef.view(np.float64), ctypes.c_double), n_gen,
+                            _p(gen_off, ctypes.c_int64), _p(gen_mat, ctypes.c_double), D,
+                            _p(xx.view(np.float64), ctypes.c_double), _p(y.view(np.float64), ctypes.c_double),
+                            nrows, rp)
     if rc != 0:
-        raise RuntimeError("mf_ref_matvec rejected its input")
-    gterm, toff, tab, c = general_inputs(model, theta)
-    if gterm.shape[0]:
-        rc = lib().mf_ref_general_add(len(model.sites), _p(twok, ctypes.c_int32), gterm.shape[0],
-                                      _p(gterm, ctypes.c_int32), _p(toff, ctypes.c_int64),
-                                      _p(tab, ctypes.c_double), _p(c.view(np.float64), ctypes.c_double), D,
-                                      _p(xx.view(np.float64), ctypes.c_double),
-                                      _p(y.view(np.float64), ctypes.c_double), nrows, rp)
-        if rc != 0:
-            raise RuntimeError("mf_ref_general_add rejected its input")
+        raise RuntimeError("mf_ref_apply rejected its input")
     return y
+
+
+_SHIFT = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: -1, OP_RAISE2: 2, OP_LOWER2: -2}
+
+
+def _shift(model: Model, op: int) -> int:
+    """Digit shift q of an operator (its matrix elements sit at <n|O|n - q>)."""
+    if op >= OP_LOCAL_BASE:
+        return int(model.local_ops[op - OP_LOCAL_BASE].shift)
+    return _SHIFT[op]
 
 
 def sources(model: Model, F0: int, count: int) -> np.ndarray:
     """Source index (or -1) of every term for target rows F0..F0+count-1: int64 [count, n_terms]."""
     _, twok = model.site_arrays()
-    al = {OP_Z: 0, OP_Z2: 0, OP_RAISE: 1, OP_LOWER: 2, OP_RAISE2: 3, OP_LOWER2: 4}
-    tt = np.array([(t.site_a, al[t.op_a], t.site_b, al[t.op_b] if t.site_b >= 0 else 0)
+    tt = np.array([(t.site_a, _shift(model, t.op_a), t.site_b, _shift(model, t.op_b) if t.site_b >= 0 else 0)
                    for t in model.terms], dtype=np.int32).reshape(-1, 4)
     out = np.empty((count, len(model.terms)), dtype=np.int64)
     rc = lib().mf_ref_sources(len(model.sites), _p(twok, ctypes.c_int32), len(model.terms),
