@@ -309,6 +309,8 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
  *   d_result : double[4] = theta, residual estimate beta_{k-1}|s_{k-1}|, explicit residual, steps k
  *   d_u      : c128[D] Ritz vector (written)
  *   d_scratch: at least mrmf_lanczos_scratch_bytes(plan, m, precision)
+ * Requires a plan whose parameter groups are Hermitian (MRMF_E_NOT_HERMITIAN otherwise, checked before
+ * any launch): the recurrence keeps only Re<v_j|H v_j>, so its Ritz values mean nothing for other H.
  * All work is enqueued on the stream; the host never waits inside the call. */
 mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes);
 mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z,
@@ -397,7 +399,8 @@ mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0,
  * (including indices outside 0 .. D-1). */
 mrmf_status mrmf_sector_lookup(mrmf_sector sector, const void* d_ws, const int64_t* d_F, int64_t count,
                                int64_t* d_out, mrmf_stream stream);
-/* Lanczos in the sector: the arguments and results of mrmf_lanczos with vectors of the sector's dimension. */
+/* Lanczos in the sector: the arguments, results and the Hermiticity requirement of mrmf_lanczos, with
+ * vectors of the sector's dimension. */
 mrmf_status mrmf_sector_lanczos_scratch_bytes(mrmf_sector sector, int32_t m, int32_t precision, size_t* bytes);
 mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const double* d_theta_z,
                                 const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,

@@ -588,6 +588,8 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
                          size_t scratch_bytes, mrmf_stream stream) {
     if (!plan || !d_ws || !d_theta_z) return MRMF_E_INVALID_ARG;
     if (precision == MRMF_PREC_C_IN_Z && !d_theta_c) return MRMF_E_INVALID_ARG;
+    // the recurrence keeps Re<v|Hv> only and its Ritz values are eigenvalues of H only for Hermitian H
+    if (!plan->hermitian) return MRMF_E_NOT_HERMITIAN;
     const MatvecOp mv_z = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
         return matvec_z_impl(plan, d_ws, d_theta_z, x, y, s, stop);
     };

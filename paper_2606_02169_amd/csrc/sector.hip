@@ -515,6 +515,8 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
                                 void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
     if (!sector || !d_ws || (sector->n_params > 0 && !d_theta_z) || !aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
     if (precision == MRMF_PREC_C_IN_Z && sector->n_params > 0 && !d_theta_c) return MRMF_E_INVALID_ARG;
+    // P H P^T is Hermitian when H is; the Lanczos recurrence needs it (see mrmf_lanczos)
+    if (!sector->hermitian) return MRMF_E_NOT_HERMITIAN;
     const MatvecOp mv_z = [&](const void* x, void* y, hipStream_t s, const int32_t* stop) {
         return sector_matvec<double>(sector, d_ws, d_theta_z, x, y, s, stop);
     };

@@ -287,3 +287,26 @@ def test_spectral_bounds_argument_checks():
         assert L.lib().mrmf_spectral_bounds(q, fake, fake, fake, fake, 1 << 20, None) == L.MRMF_E_NOT_HERMITIAN
     finally:
         L.lib().mrmf_plan_destroy(q)
+
+
+def test_lanczos_refuses_non_hermitian_plans():
+    """mrmf_lanczos and mrmf_sector_lanczos return MRMF_E_NOT_HERMITIAN, before any launch, for a plan
+    built without MRMF_REQUIRE_HERMITIAN whose parameter group is not Hermitian (S_+ S_- without its
+    adjoint); the pointers below are never dereferenced."""
+    from workloads.model import OP_LOWER, OP_RAISE, Model, Term, spin_site
+    m = Model([spin_site(1)] * 3, [Term(0, OP_RAISE, 1, OP_LOWER, 0, 1.0)], np.ones(1))
+    assert host_plan(m)[0] == L.MRMF_E_NOT_HERMITIAN
+    st, h = host_plan(m, require_hermitian=False)
+    assert st == 0
+    sec = ctypes.c_void_p()
+    try:
+        fake = ctypes.c_void_p(1 << 20)
+        args = (fake, fake, None, L.MRMF_PREC_Z, 4, L.MRMF_REORTH_CGS2, fake, fake, fake, fake, fake, fake, fake,
+                1 << 20, None)
+        assert L.lib().mrmf_lanczos(h, *args) == L.MRMF_E_NOT_HERMITIAN
+        L.call("mrmf_sector_create", h, 1, ctypes.byref(sec))
+        assert L.lib().mrmf_sector_lanczos(sec, *args) == L.MRMF_E_NOT_HERMITIAN
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
