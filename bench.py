@@ -69,45 +69,83 @@ def cuda_time(fn, stream, reps: int):
     return a.elapsed_time(b) / reps
 
 
-def cpu_baseline(model, x_host, target_s: float = 15.0):
-    """The oracle's FP64 matvec on the host cores: the full vector, repeated to about target_s seconds
-    (or a row sample if one full pass would take longer); scaled to matvecs/s of the full vector."""
+def host_cpu_info() -> dict:
+    """CPU model, logical CPUs this process may run on, and the physical cores among them (/proc/cpuinfo)."""
+    avail = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(os.cpu_count()))
+    model_name, cores = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            blocks = f.read().strip().split("\n\n")
+        for b in blocks:
+            kv = {}
+            for line in b.splitlines():
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+            if int(kv.get("processor", -1)) in avail:
+                model_name = model_name or kv.get("model name")
+                cores.add((kv.get("physical id", "0"), kv.get("core id", kv.get("processor"))))
+    except OSError:
+        pass
+    return {"cpu_model": model_name, "logical_cpus": len(avail), "physical_cores": len(cores) or None}
+
+
+def cpu_baseline(model, x_host, rep_s: float = 3.0, one_core_rep_s: float = 2.0):
+    """The oracle's FP64 matvec on the host cores, on a bounded sample of the same workload: a contiguous
+    block of rows in the middle of the vector sized for about rep_s seconds, timed three times after a
+    warm-up (median), on all the threads the oracle uses and again on one thread; scaled to matvecs/s of
+    the full vector (rows per second / D).  About 6 rep_s + 6 one_core_rep_s seconds of CPU work."""
     import numpy as np
     from oracle import mf
     D = model.dim
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    mf.matvec(model, x_host, rows=np.arange(min(D, 1000), dtype=np.int64))  # thread pool and tables warm
-    rows = np.arange(D // 3, min(D, D // 3 + 1_000_000), dtype=np.int64)
-    t0 = time.perf_counter()
-    mf.matvec(model, x_host, rows=rows)
-    est_full = (time.perf_counter() - t0) * D / rows.size
-    if est_full <= target_s:
-        reps = max(1, int(target_s / max(est_full, 1e-3)))
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            y = mf.matvec(model, x_host)
-        dt = time.perf_counter() - t0
-        while dt < 0.7 * target_s:   # the probe overestimated a full matvec: more repetitions, same sample kind
-            y = mf.matvec(model, x_host)
-            reps += 1
-            dt = time.perf_counter() - t0
-        rows_all = np.arange(D, dtype=np.int64)
-        return (dict(value=reps / dt, unit="matvecs/s", cores=threads, kind="oracle",
-                     sample=f"{reps} full FP64 matvecs (D={D}) in {dt:.1f} s: plain C App-A row loop, "
-                            f"OpenMP over rows"), rows_all, y)
-    n = int(D * target_s / est_full)
-    for _ in range(2):  # once more, rescaled, if the sample ran well short of the target
+
+    def block(n):
+        n = int(max(1000, min(D, n)))
         start = (D - n) // 2
-        rows = np.arange(start, start + n, dtype=np.int64)
-        t0 = time.perf_counter()
-        y_rows = mf.matvec(model, x_host, rows=rows)
-        dt = time.perf_counter() - t0
-        if dt >= 0.7 * target_s or n == D:
-            break
-        n = min(D, int(n * target_s / max(dt, 1e-3)))
-    return (dict(value=n / dt / D, unit="matvecs/s", cores=threads, kind="oracle",
-                 sample=f"rows [{start}, {start + n}) of D={D} in {dt:.1f} s, scaled to the full vector; "
-                        f"plain C App-A row loop, OpenMP over rows"), rows, y_rows)
+        return np.arange(start, start + n, dtype=np.int64)
+
+    def median_rate(rows, reps=3):
+        mf.matvec(model, x_host, rows=rows)                 # warm-up (thread pool, tables, caches)
+        ts = []
+        y = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            y = mf.matvec(model, x_host, rows=rows)
+            ts.append(time.perf_counter() - t0)
+        return rows.size / float(np.median(ts)), ts, y
+
+    threads = mf.threads()
+    probe = block(200_000)
+    r0, _, _ = median_rate(probe, reps=1)
+    rows = block(r0 * rep_s)
+    rate, ts, y_rows = median_rate(rows)
+    mf.threads(1)
+    try:
+        r1, _, _ = median_rate(block(20_000), reps=1)
+        rows1 = block(r1 * one_core_rep_s)
+        rate1, ts1, _ = median_rate(rows1)
+    finally:
+        mf.threads(threads)
+    info = host_cpu_info()
+    cb = dict(value=rate / D, unit="matvecs/s", cores=threads, kind="oracle",
+              sample=f"rows [{rows[0]}, {rows[-1] + 1}) of D={D} ({rows.size} rows), median of 3 timings "
+                     f"{', '.join(f'{t:.2f}' for t in ts)} s after a warm-up, scaled to the full vector; "
+                     f"oracle row-by-row Kronecker evaluation in C, OpenMP over rows",
+              threads=threads, one_core={"value": rate1 / D, "unit": "matvecs/s",
+                                         "sample": f"{rows1.size} rows, median of 3 timings "
+                                                   f"{', '.join(f'{t:.2f}' for t in ts1)} s"},
+              timing="median of 3 after a warm-up", **info)
+    return cb, rows, y_rows
+
+
+def oracle_residual(model, u, theta):
+    """Oracle leg beside the CPU baseline: ||H u - theta u|| of a GPU Ritz vector u (host copy) with the
+    oracle's H, and ||u||.  For Hermitian H an eigenvalue lies within ||H u - theta u|| / ||u|| of theta,
+    so this certifies a GPU energy independently of the GPU's own residual."""
+    import numpy as np
+    from oracle import mf
+    hu = mf.matvec(model, u)
+    return float(np.linalg.norm(hu - theta * u)), float(np.linalg.norm(u))
 
 
 # ------------------------------------------------------------------------------------------ headline
@@ -180,13 +218,17 @@ def bench_ring(args, dev):
     else:
         copy_GBps = None
 
-    traffic = None
+    # HBM traffic is not measured in this run: it is the committed rocprofv3 counter figure (FETCH_SIZE +
+    # WRITE_SIZE, scaled by a plain copy) for this exact kernel source, else null
+    traffic, traffic_source = None, None
     fp = kernel_fingerprint(plan, torch.complex128)
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
         if rec.get("kernel_fingerprint") == fp:
             traffic = rec.get("hbm_bytes_per_launch")
+            traffic_source = (f"committed rocprofv3 counters, profiles/{os.path.basename(TRAFFIC_FILE)}, "
+                              f"kernel fingerprint {fp}")
 
     out = {
         "metric": METRIC,
@@ -206,7 +248,7 @@ def bench_ring(args, dev):
                    "kernel": {k: info[k] for k in ("kind", "inner_sites", "unrolled_sites", "copies", "block", "grid")}},
         "effective_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_source": traffic_source,
                      "algorithmic_bytes_per_launch": alg_bytes, "mean_launch_ms": mean_launch_ms,
                      "kernel_fingerprint": fp, "copy_GBps": copy_GBps,
                      "frac_of_copy": achieved / copy_GBps if copy_GBps else None},
@@ -214,13 +256,11 @@ def bench_ring(args, dev):
     if not (args.no_cpu_baseline or args.profile):
         # oracle timing and a parity check of the timed output (the oracle is a baseline only)
         cb, rows, y_rows = cpu_baseline(model, x_host)
-        if rows.size == D:
-            y_gpu = y.cpu().numpy()
-        else:
-            y_gpu = y[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        y_gpu = y[torch.from_numpy(rows).to(dev)].cpu().numpy()
         err = float(np.linalg.norm(y_gpu - y_rows) / np.linalg.norm(y_rows))
         out["cpu_baseline"] = cb
         out["rel_err_vs_oracle"] = err
+        out["rel_err_vs_oracle_rows"] = int(rows.size)
         log(f"cpu baseline: {cb}; rel err vs oracle {err:.3e}")
     else:
         out["cpu_baseline"] = None
@@ -320,7 +360,7 @@ def bench_lanczos(args, dev):
         return np.array([eigvalsh_tridiagonal(a[:i], b[: i - 1], select="i", select_range=(0, 0))[0]
                          for i in range(1, k + 1)])
 
-    def run(plan, prec, m, reorth="cgs2"):
+    def run(plan, prec, m, reorth="cgs2", certify=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = plan.lanczos(th64, v0, m, precision=prec, reorth=reorth, theta_c=th32)
@@ -328,23 +368,31 @@ def bench_lanczos(args, dev):
         dt = time.perf_counter() - t0
         res = r["result"].cpu().numpy()
         k = int(res[3])
-        return dict(theta=float(res[0]), resid=float(res[2]), steps=k, seconds=dt,
-                    alpha=r["alpha"].cpu().numpy()[:k], beta=r["beta"].cpu().numpy()[:k])
+        out = dict(theta=float(res[0]), resid=float(res[2]), steps=k, seconds=dt,
+                   alpha=r["alpha"].cpu().numpy()[:k], beta=r["beta"].cpu().numpy()[:k])
+        if certify and not args.profile:
+            u = r["u"].cpu().numpy()
+            del r
+            out["oracle_residual"], out["u_norm"] = oracle_residual(model, u, out["theta"])
+        return out
 
     m_ref = args.lanczos_ref_steps
-    ref = run(pz, "z", m_ref)
+    ref = run(pz, "z", m_ref, certify=True)
     E_ref = ref["theta"]
-    log(f"reference: {m_ref} FP64 steps, theta {E_ref!r} residual {ref['resid']:.3e} in {ref['seconds']:.1f} s")
+    log(f"reference: {m_ref} FP64 steps, theta {E_ref!r} residual {ref['resid']:.3e} "
+        f"(oracle {ref.get('oracle_residual', float('nan')):.3e}) in {ref['seconds']:.1f} s")
     out = {"metric": "Lanczos ground energy: FP32 (c64) matvec in FP64 Lanczos vs plain FP64, time to 1e-5",
            "workload": "square4x4_spin1_periodic", "D": D, "seed": 3,
            "reference": {"steps": ref["steps"], "theta": E_ref, "residual": ref["resid"],
+                         "oracle_residual": ref.get("oracle_residual"),
+                         "certified_within": (ref["oracle_residual"] / ref["u_norm"]) if "u_norm" in ref else None,
                          "seconds": ref["seconds"]},
            "matvec_ms": {"c128": mv_z, "c64": mv_c}, "forms": {}}
     m = args.lanczos_steps
     for name, plan, prec, ro in (("fp64", pz, "z", "cgs2"), ("fp32_in_fp64", pc, "c_in_z", "cgs2"),
                                  ("fp64_cgs2_cond", pz, "z", "cgs2_cond"),
                                  ("fp32_in_fp64_cgs2_cond", pc, "c_in_z", "cgs2_cond")):
-        full = run(plan, prec, m, ro)
+        full = run(plan, prec, m, ro, certify=True)
         curve = ritz_curve(full["alpha"], full["beta"], full["steps"])
         rel = np.abs(curve - E_ref) / abs(E_ref)
         hit = np.nonzero(rel <= 1e-5)[0]
@@ -352,7 +400,7 @@ def bench_lanczos(args, dev):
         timed = run(plan, prec, k5, ro) if k5 else None
         out["forms"][name] = {
             "reorth": ro, "steps": m, "theta": full["theta"], "rel_err": abs(full["theta"] - E_ref) / abs(E_ref),
-            "residual": full["resid"], "seconds": full["seconds"],
+            "residual": full["resid"], "oracle_residual": full.get("oracle_residual"), "seconds": full["seconds"],
             "steps_to_1e-5": k5, "seconds_to_1e-5": timed["seconds"] if timed else None,
             "rel_err_at_1e-5_run": (abs(timed["theta"] - E_ref) / abs(E_ref)) if timed else None,
             "matvec_ms": mv_z if prec == "z" else mv_c}
@@ -401,10 +449,16 @@ def bench_lanczos_ring(args, dev):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = r["result"].cpu().numpy()
+        u = r["u"].cpu().numpy() if (ro == "cgs2" and not args.profile) else None
         del r
         torch.cuda.empty_cache()
         out["forms"][name] = {"reorth": ro, "seconds": dt, "ms_per_step": dt / max(1, int(res[3])) * 1e3, "E0": float(res[0]),
                               "residual": float(res[2]), "steps": int(res[3])}
+        if u is not None:
+            ro_res, nu = oracle_residual(model, u, float(res[0]))
+            del u
+            out["forms"][name]["oracle_residual"] = ro_res
+            out["forms"][name]["certified_within"] = ro_res / nu
         log(f"{name}: {out['forms'][name]}")
     if not args.profile:
         plan = Plan.from_model(model, device=dev)

@@ -32,11 +32,18 @@ def lib():
         L.mf_ref_apply.restype = ctypes.c_int
         L.mf_ref_apply.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, f64p, ctypes.c_int32, i64p,
                                    f64p, ctypes.c_int64, f64p, f64p, ctypes.c_int64, i64p]
+        L.mf_ref_threads.restype = ctypes.c_int
+        L.mf_ref_threads.argtypes = [ctypes.c_int32]
         L.mf_ref_sources.restype = ctypes.c_int
         L.mf_ref_sources.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, i32p, ctypes.c_int64,
                                      ctypes.c_int64, i64p]
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the row loops (OpenMP): n > 0 sets them; returns the count in use."""
+    return int(lib().mf_ref_threads(int(n)))
 
 
 def _p(a, t):

@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -235,4 +236,10 @@ int mf_ref_sources(int32_t N, const int32_t* twok, int32_t n_terms, const int32_
         }
     }
     return 0;
+}
+
+/* Threads the row loops use: n > 0 sets them (omp_set_num_threads); returns the current count. */
+int mf_ref_threads(int32_t n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

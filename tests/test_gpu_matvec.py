@@ -86,8 +86,9 @@ def sample_rows(D, rng, n=3000):
 
 
 def test_config2_full_size_sampled():
-    """Ferrimagnetic ring, D = 60,466,176, c128: sampled rows against the oracle, and the sum rule
-    <1|H x> of the whole output against the oracle's Hermitian-transposed evaluation."""
+    """Ferrimagnetic ring, D = 60,466,176, c128, default kernel choice: sampled rows (both ends and a
+    random sample) against the oracle.  The whole vector and the sum rule sum_F (H x)_F = <H 1|x> are
+    checked with the benchmark's kernel shape in test_gpu_fullsize.py."""
     m, x = W.config(2)
     p = Plan(m)
     y = gpu_matvec(p, m.theta, x)
