@@ -123,7 +123,8 @@ mrmf_status mrmf_plan_create_ex(int32_t n_sites, const mrmf_site* sites, int32_t
                                 const mrmf_local_op* local, mrmf_plan* out);
 void mrmf_plan_destroy(mrmf_plan plan);
 
-/* D = prod d_i. */
+/* Host *D = prod_i d_i, the dimension of the product basis (Sec. I, the first displayed equation; also
+ * M_0 d_0 with the multipliers of Sec. III).  MRMF_E_INVALID_ARG for a null argument; no HIP call. */
 mrmf_status mrmf_plan_dim(mrmf_plan plan, int64_t* D);
 /* Number of off-diagonal terms (those with a RAISE or LOWER operator): the "channels". */
 mrmf_status mrmf_plan_n_offdiag(mrmf_plan plan, int32_t* n);
@@ -259,8 +260,11 @@ mrmf_status mrmf_plan_kernel_source(mrmf_plan plan, int32_t dtype, char* buf, si
  * must not overlap (the gather form reads x while writing y, Sec. II).  y is overwritten (App. A). */
 mrmf_status mrmf_matvec_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
                           void* d_y, mrmf_stream stream);
-/* Same map in FP32: d_theta float[n_params]; d_x, d_y c64[D], 8-byte aligned; tables and accumulation
- * in FP32. */
+/* The same map y = H(theta) x (target-driven gather of Sec. II: digits by Eq. decode, channels by Eqs.
+ * src_digit_two_site / sourceoffset, ladder factors of Sec. IV.A, App. B, App. C) in FP32: d_theta
+ * float[n_params]; d_x, d_y c64[D], 8-byte aligned, must not overlap; y is overwritten; tables (the FP64
+ * ladder values rounded once) and accumulation in FP32.  Errors as mrmf_matvec_z: MRMF_E_INVALID_ARG for
+ * null, misaligned or overlapping buffers, MRMF_E_HIP when a launch fails. */
 mrmf_status mrmf_matvec_c(mrmf_plan plan, const void* d_ws, const float* d_theta, const void* d_x,
                           void* d_y, mrmf_stream stream);
 

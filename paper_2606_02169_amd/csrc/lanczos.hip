@@ -268,7 +268,10 @@ __global__ void k_dot_finalize(const double2* __restrict__ partial, int nb, doub
     out[1] = si;
 }
 
-// number of eigenvalues of the k x k tridiagonal (a, b) below x (Sturm sequence)
+// Number of eigenvalues of the k x k symmetric tridiagonal (a, b) below x: the count of negative pivots
+// of the LDL^T factorisation of T - x I (Sturm sequence count, Sylvester's law of inertia), the basis of
+// the bisection method of Barth, Martin and Wilkinson (1967); pivots below pivmin in magnitude are
+// replaced by -pivmin so the recurrence never divides by zero.
 __device__ int sturm_count(const double* a, const double* b, int k, double x, double pivmin) {
     int cnt = 0;
     double q = a[0] - x;
@@ -282,7 +285,10 @@ __device__ int sturm_count(const double* a, const double* b, int k, double x, do
     return cnt;
 }
 
-// Lowest eigenpair of T by bisection and inverse iteration (one thread; k is small).
+// Lowest eigenpair of T (one thread; k is small): the lowest eigenvalue by bisection on the Sturm count
+// (Barth, Martin and Wilkinson), then its eigenvector by inverse iteration (Wilkinson; Peters and
+// Wilkinson 1971) with T - theta I factored by Gaussian elimination with partial pivoting, which for a
+// tridiagonal matrix keeps a lower band of one and an upper band of two (dl, d, du, du2).
 // work: 5 * m doubles.  s_out: complex coefficients (s_i, 0) for the Ritz vector, zero past k.
 __global__ void k_tridiag_lowest(const double* __restrict__ alpha, const double* __restrict__ beta, int m,
                                  LzState* __restrict__ st, double* __restrict__ work,
