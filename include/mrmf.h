@@ -288,6 +288,21 @@ mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_the
                            const void* d_g, void* d_grad_x, double* d_grad_theta, void* d_scratch,
                            size_t scratch_bytes, mrmf_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc): mrmf_adjoint_z with the same arguments, results and checks, but
+ * its scratch (the per-block partial sums of the coupling gradients) lives in a static device array of
+ * MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the process ends.  The call
+ * allocates nothing and compiles nothing: it runs the plan's generated gradient kernel only when that is
+ * already built (mrmf_plan_prepare with MRMF_SOURCE_GRAD, or an earlier mrmf_adjoint_z), else the generic
+ * pass.  The first call on a device resolves the array's device address (hipGetSymbolAddress): make it
+ * outside graph capture.  MRMF_E_WORKSPACE when mrmf_adjoint_scratch_bytes(plan) exceeds the array.  All
+ * calls on one GPU share its array (every call writes the partial sums it reads, so nothing carries over):
+ * calls that overlap in time on one GPU (other streams, or other host threads) race and must be ordered by
+ * the caller. */
+#define MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES (1u << 20)
+mrmf_status mrmf_adjoint_z_noalloc(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                                   const void* d_g, void* d_grad_x, double* d_grad_theta, mrmf_stream stream);
+
 /* FP64 helpers on c128 vectors of length n (deterministic two-stage reductions; scratch from
  * mrmf_reduce_scratch_bytes):  d_out[0..1] = <a|b> (re, im);  d_out[0] = ||a||_2. */
 mrmf_status mrmf_reduce_scratch_bytes(int64_t n, size_t* bytes);

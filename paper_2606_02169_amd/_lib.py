@@ -17,6 +17,7 @@ MRMF_E_NOT_HERMITIAN = -3
 MRMF_E_HIP = -4
 MRMF_E_UNSUPPORTED = -5
 MRMF_E_WORKSPACE = -6
+MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES = 1 << 20
 MRMF_SPIN, MRMF_BOSON = 0, 1
 MRMF_OP_Z, MRMF_OP_Z2, MRMF_OP_RAISE, MRMF_OP_LOWER, MRMF_OP_RAISE2, MRMF_OP_LOWER2 = 0, 1, 2, 3, 4, 5
 MRMF_REQUIRE_HERMITIAN = 1
@@ -94,6 +95,7 @@ SIGNATURES = {
     "mrmf_plan_kernel_source": (_i32, [_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)]),
     "mrmf_adjoint_scratch_bytes": (_i32, [_vp, _P(_sz)]),
     "mrmf_adjoint_z": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mrmf_adjoint_z_noalloc": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mrmf_reduce_scratch_bytes": (_i32, [_i64, _P(_sz)]),
     "mrmf_dot_z": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mrmf_norm_z": (_i32, [_i64, _vp, _vp, _vp, _sz, _vp]),

@@ -195,33 +195,63 @@ int adjoint_grid(int64_t D) {
 }  // namespace
 }  // namespace mrmf
 
-extern "C" {
+// Scratch of mrmf_adjoint_z_noalloc: the per-block partial sums of the coupling gradients (at most
+// 2048 blocks x 64 parameters).  One copy per GPU, for the life of the process.  Host code never passes
+// the array's name to a kernel (on the host it is a stand-in, not a device address): the device address
+// comes from hipGetSymbolAddress, once per device, and is kept in g_noalloc_ptr.
+static __device__ __align__(256) double scratch[MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
-mrmf_status mrmf_adjoint_scratch_bytes(mrmf_plan plan, size_t* bytes) {
-    if (!plan || !bytes) return MRMF_E_INVALID_ARG;
-    *bytes = size_t(mrmf::adjoint_grid(plan->D)) * size_t(plan->n_params > 0 ? plan->n_params : 1) * sizeof(double);
+namespace mrmf {
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mtx;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch` (resolved on the first call on the device)
+mrmf_status noalloc_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return MRMF_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_noalloc_mtx);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return MRMF_E_HIP;
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
     return MRMF_OK;
 }
 
-mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
-                           const void* d_g, void* d_grad_x, double* d_grad_theta, void* d_scratch,
-                           size_t scratch_bytes, mrmf_stream stream) {
-    using namespace mrmf;
-    if (!plan || !d_ws || !d_x || !d_g || !d_grad_x || !d_scratch) return MRMF_E_INVALID_ARG;
+// Argument checks shared by both entry points (no HIP call).
+mrmf_status adjoint_check(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x, const void* d_g,
+                          void* d_grad_x, double* d_grad_theta) {
+    if (!plan || !d_ws || !d_x || !d_g || !d_grad_x) return MRMF_E_INVALID_ARG;
     if (plan->n_params > 0 && (!d_theta || !d_grad_theta)) return MRMF_E_INVALID_ARG;
     if (!plan->hermitian) return MRMF_E_NOT_HERMITIAN;
-    if (!aligned(d_ws, 256) || !aligned(d_x, 16) || !aligned(d_g, 16) || !aligned(d_grad_x, 16) ||
-        !aligned(d_scratch, 8))
+    if (!aligned(d_ws, 256) || !aligned(d_x, 16) || !aligned(d_g, 16) || !aligned(d_grad_x, 16))
         return MRMF_E_INVALID_ARG;
     const size_t vb = size_t(plan->D) * 16;
     if (ranges_overlap(d_g, vb, d_grad_x, vb) || ranges_overlap(d_x, vb, d_grad_x, vb)) return MRMF_E_INVALID_ARG;
-    size_t need = 0;
-    mrmf_adjoint_scratch_bytes(plan, &need);
-    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    double* partial = static_cast<double*>(d_scratch);
+    return MRMF_OK;
+}
+
+size_t adjoint_scratch_need(const mrmf_plan_t* plan) {
+    return size_t(adjoint_grid(plan->D)) * size_t(plan->n_params > 0 ? plan->n_params : 1) * sizeof(double);
+}
+
+// The adjoint pass with its partial sums in `partial` (checked by the caller).  allow_compile: build the
+// plan's generated gradient kernel on first use; else run it only when it is already built, and the
+// generic pass otherwise (no module is loaded, so nothing is allocated).
+mrmf_status adjoint_run(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x, const void* d_g,
+                        void* d_grad_x, double* d_grad_theta, double* partial, bool allow_compile, hipStream_t s) {
     // generated form: one pass of the kernel generated for the plan, then the fixed-order reduction
-    if (plan->n_params > 0 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC && grad_prepare(plan) == MRMF_OK) {
+    if (plan->n_params > 0 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC &&
+        (allow_compile ? grad_prepare(plan) == MRMF_OK : grad_built(plan))) {
         int nb = 0;
         const mrmf_status st = grad_launch(plan, d_theta, d_x, d_g, d_grad_x, partial, adjoint_grid(plan->D), &nb, s);
         if (st != MRMF_OK) return st;
@@ -266,6 +296,43 @@ mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_the
         return launch_status();
     }
     return MRMF_OK;
+}
+
+}  // namespace
+}  // namespace mrmf
+
+extern "C" {
+
+mrmf_status mrmf_adjoint_scratch_bytes(mrmf_plan plan, size_t* bytes) {
+    if (!plan || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = size_t(mrmf::adjoint_grid(plan->D)) * size_t(plan->n_params > 0 ? plan->n_params : 1) * sizeof(double);
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_adjoint_z(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                           const void* d_g, void* d_grad_x, double* d_grad_theta, void* d_scratch,
+                           size_t scratch_bytes, mrmf_stream stream) {
+    using namespace mrmf;
+    if (!d_scratch || !aligned(d_scratch, 8)) return MRMF_E_INVALID_ARG;
+    const mrmf_status chk = adjoint_check(plan, d_ws, d_theta, d_x, d_g, d_grad_x, d_grad_theta);
+    if (chk != MRMF_OK) return chk;
+    if (scratch_bytes < adjoint_scratch_need(plan)) return MRMF_E_WORKSPACE;
+    return adjoint_run(plan, d_ws, d_theta, d_x, d_g, d_grad_x, d_grad_theta, static_cast<double*>(d_scratch), true,
+                       static_cast<hipStream_t>(stream));
+}
+
+mrmf_status mrmf_adjoint_z_noalloc(mrmf_plan plan, const void* d_ws, const double* d_theta, const void* d_x,
+                                   const void* d_g, void* d_grad_x, double* d_grad_theta, mrmf_stream stream) {
+    using namespace mrmf;
+    const mrmf_status chk = adjoint_check(plan, d_ws, d_theta, d_x, d_g, d_grad_x, d_grad_theta);
+    if (chk != MRMF_OK) return chk;
+    if (adjoint_scratch_need(plan) > kNoAllocScratchBytes) return MRMF_E_WORKSPACE;
+    void* ptr = nullptr;
+    const mrmf_status st = noalloc_scratch(&ptr);
+    if (st != MRMF_OK) return st;
+    // every block writes all its partial sums before the finalize reads them: nothing to clear
+    return adjoint_run(plan, d_ws, d_theta, d_x, d_g, d_grad_x, d_grad_theta, static_cast<double*>(ptr), false,
+                       static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -1813,6 +1813,13 @@ mrmf_status grad_prepare(mrmf_plan_t* p) {
     return MRMF_OK;
 }
 
+bool grad_built(mrmf_plan_t* p) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(p->mtx);
+    return p->grad.tried && p->grad.ok && p->grad.device == dev;
+}
+
 mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, const void* g, void* gx, double* partial,
                         int max_grid, int* grid, hipStream_t s) {
     mrmf_status st = grad_prepare(p);

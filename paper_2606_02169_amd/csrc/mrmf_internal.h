@@ -263,6 +263,8 @@ mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype);
 mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
                               const int32_t* d_skip);
 mrmf_status grad_prepare(mrmf_plan_t* p);
+// true when the plan's generated gradient kernel is already built for the current device (compiles nothing)
+bool grad_built(mrmf_plan_t* p);
 mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, const void* g, void* gx, double* partial,
                         int max_grid, int* grid, hipStream_t s);
 

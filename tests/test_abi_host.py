@@ -310,3 +310,24 @@ def test_lanczos_refuses_non_hermitian_plans():
         if sec.value:
             L.lib().mrmf_sector_destroy(sec)
         L.lib().mrmf_plan_destroy(h)
+
+
+def test_noalloc_adjoint_size_limit():
+    """mrmf_adjoint_z_noalloc refuses a plan whose partial sums exceed its static array, before any HIP
+    call (the pointers below are never dereferenced)."""
+    from workloads.model import OP_Z, Model, Term, spin_site
+    n_params = 200                                       # 2048 blocks x 200 x 8 B > 1 MiB
+    m = Model([spin_site(1)] * 20, [Term(i, OP_Z, -1, OP_Z, i, 1.0) for i in range(20)], np.ones(n_params))
+    st, h = host_plan(m)
+    assert st == 0
+    try:
+        nb = ctypes.c_size_t()
+        L.call("mrmf_adjoint_scratch_bytes", h, ctypes.byref(nb))
+        assert nb.value > L.MRMF_ADJOINT_NOALLOC_SCRATCH_BYTES
+        f = [ctypes.c_void_p(k << 30) for k in range(1, 6)]
+        fn = L.lib().mrmf_adjoint_z_noalloc
+        assert fn(h, f[0], f[1], f[2], f[3], f[4], f[0], None) == L.MRMF_E_WORKSPACE
+        assert fn(h, f[0], f[1], f[2], f[3], f[2], f[0], None) == L.MRMF_E_INVALID_ARG   # grad_x aliases x
+        assert fn(None, f[0], f[1], f[2], f[3], f[4], f[0], None) == L.MRMF_E_INVALID_ARG
+    finally:
+        L.lib().mrmf_plan_destroy(h)
