@@ -183,10 +183,12 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                             and a separate vector update per term.
  *   MRMF_TUNE_WAVES_PER_EU  : 0 = the compiler's register allocation (default); 1..8 = ask for at least
  *                             that many resident waves per SIMD (a register budget; may spill).
- *   MRMF_TUNE_FAR_LOADS     : 0 = every gather with the default cache policy (default); k in 10..40 = in
- *                             the masked form, a channel whose offset |Delta| spans at least 2^k bytes
- *                             is loaded non-temporal (its lines are the first the L2 evicts), so the
- *                             windows of near channels stay resident.  Results are unchanged.
+ *   MRMF_TUNE_FAR_LOADS     : 0 = every gather with the default cache policy (default); k in 10..40 = a
+ *                             channel whose offset |Delta| spans at least 2^k bytes is loaded
+ *                             non-temporal (the list form walks such channels first, from a list of their
+ *                             own).  Results are unchanged.
+ *   MRMF_TUNE_FAR_DIR       : which channels MRMF_TUNE_FAR_LOADS takes: 0 = both directions (default),
+ *                             1 = sources behind the row (Delta > 0), 2 = sources ahead (Delta < 0).
  *   MRMF_TUNE_GRAD_BLOCKS_PER_CU : blocks of 256 threads per compute unit of the generated
  *                             coupling-gradient kernel of mrmf_adjoint_z (0 = default 2; 1..8).
  *   MRMF_TUNE_OUTER_FIRST   : 0 = super-tiles swept in index order (default); k in 1..8 = the digit
@@ -213,6 +215,7 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_TUNE_GRAD_BLOCKS_PER_CU 9
 #define MRMF_TUNE_OUTER_FIRST 10
 #define MRMF_TUNE_UNROLL_TOP 11
+#define MRMF_TUNE_FAR_DIR 12
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0

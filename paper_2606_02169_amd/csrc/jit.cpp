@@ -84,6 +84,7 @@ struct Gen {
     bool epi = false;
     int waves_per_eu = 0;  // > 0: ask the compiler for at least this many waves per SIMD (register budget)
     int far_nt = 0;        // > 0: gathers reaching |Delta| >= 2^far_nt bytes use LDN (non-temporal)
+    int far_dir = 0;       // which of them: 0 both directions, 1 sources behind (Delta > 0), 2 ahead
     int outer_first = 0;   // the k most significant (uniform) sites vary fastest in the sweep
 
     std::string kernel_head() const {
@@ -218,7 +219,8 @@ struct Gen {
     int SZ() const { return f32 ? 8 : 16; }
     // a channel whose offset reaches far enough for a non-temporal load (MRMF_TUNE_FAR_LOADS)
     bool far(int64_t delta) const {
-        return far_nt > 0 && static_cast<double>(delta < 0 ? -delta : delta) * SZ() >= std::ldexp(1.0, far_nt);
+        if (far_nt <= 0 || (far_dir == 1 && delta <= 0) || (far_dir == 2 && delta >= 0)) return false;
+        return static_cast<double>(delta < 0 ? -delta : delta) * SZ() >= std::ldexp(1.0, far_nt);
     }
     int op_shift(int op) const {
         if (op >= MRMF_OP_LOCAL_BASE) return p->lshift[op - MRMF_OP_LOCAL_BASE];
@@ -805,30 +807,40 @@ struct Gen {
             int c, j, grp;
             double ufac;
         };
+        // per copy, the far items (non-temporal loads, MRMF_TUNE_FAR_LOADS) first, then the near ones
         std::vector<std::vector<Item>> items(PU);
+        std::vector<int> nfar(PU, 0);
         for (int64_t j = 0; j < PU; ++j) {
-            for (int c : cG) {
-                const auto& ch = P.chans[c];
-                double u = 1.0;
-                auto mul_unrolled = [&](int s, int op) {
-                    if (s >= 0 && is_unrolled(s)) u *= factor_table(p, s, op)[udigit(s, j)];
-                };
-                mul_unrolled(ch.a, ch.opa);
-                mul_unrolled(ch.b, ch.opb);
-                if (u == 0.0) continue;
-                items[j].push_back({c, static_cast<int>(j), lane_group(ch.a, ch.opa, ch.b, ch.opb), u});
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c : cG) {
+                    const auto& ch = P.chans[c];
+                    if (far(ch.delta) != (pass == 0)) continue;
+                    double u = 1.0;
+                    auto mul_unrolled = [&](int s, int op) {
+                        if (s >= 0 && is_unrolled(s)) u *= factor_table(p, s, op)[udigit(s, j)];
+                    };
+                    mul_unrolled(ch.a, ch.opa);
+                    mul_unrolled(ch.b, ch.opb);
+                    if (u == 0.0) continue;
+                    items[j].push_back({c, static_cast<int>(j), lane_group(ch.a, ch.opa, ch.b, ch.opb), u});
+                    nfar[j] += pass == 0;
+                }
             }
         }
         const int NG = static_cast<int>(group_of.size()) + 2;  // + one, + sentinel
         const int ZG = NG - 1;
-        int cap = 1, NI = 0;
+        int capn = 1, capf = 0, NI = 0;
         std::vector<int> ioff(PU + 1, 0);
         for (int64_t j = 0; j < PU; ++j) {
-            cap = std::max<int>(cap, static_cast<int>(items[j].size()));
+            capf = std::max<int>(capf, nfar[j]);
+            capn = std::max<int>(capn, static_cast<int>(items[j].size()) - nfar[j]);
             ioff[j + 1] = ioff[j] + static_cast<int>(items[j].size());
         }
         NI = ioff[PU];
-        const int CAP = cap + U;  // room for the sentinel tail
+        // list of copy j in LDS: far entries at [j CAP, j CAP + n_far) followed by U sentinels (when any
+        // channel is far), near entries from j CAP + NB on, followed by U sentinels
+        const int NB = capf > 0 ? capf + U : 0;
+        const int CAP = NB + capn + U;
         // diagonal items of the uniform kind (summed) and mixed kind (uniform part per tile)
         const int nsum = static_cast<int>(gU.size()), nmd = static_cast<int>(gM.size());
 
@@ -918,6 +930,7 @@ struct Gen {
         if (cplx) o << "  __shared__ R lci[2][" << PU * CAP << "];\n";
         o << "  __shared__ int lcn[2][" << PU << "];\n"
           << "  __shared__ R lfac[" << NG * block << "];\n";
+        if (capf > 0) o << "  __shared__ int lcf[2][" << PU << "];\n";
         if (nmd > 0) {
             o << "  __shared__ R tr[2][" << nmd << "];\n";
             if (cplx) o << "  __shared__ R ti[2][" << nmd << "];\n";
@@ -1048,8 +1061,11 @@ struct Gen {
         }
         // list construction: wave w builds the lists of copies j = w, w + nw, ...
         if (NI > 0) {
+            const std::string sentinel = std::string("lso[par][q] = 0; lgr[par][q] = ") + std::to_string(ZG) +
+                                         "; lcr[par][q] = (R)0;" + (cplx ? " lci[par][q] = (R)0;" : "");
             o << "    for (unsigned j = wv; j < " << PU << "u; j += " << nw << "u) {\n"
               << "      unsigned base = 0u;\n"
+              << (capf > 0 ? "      unsigned basef = 0u;\n      const unsigned nfi = Enf[j];\n" : "")
               << "      const unsigned i0 = Eoff[j], ni = Eoff[j + 1u] - i0;\n"
               << "      for (unsigned h = 0u; h < ni; h += 64u) {\n"
               << "        const unsigned i = h + ln;\n"
@@ -1057,27 +1073,40 @@ struct Gen {
               << "        const unsigned e = i0 + (has ? i : 0u);\n"
               << "        const unsigned na = dig(t, Emam[e], Eda[e], Edam[e]), nb = dig(t, Embm[e], Edb[e], Edbm[e]);\n"
               << "        const R f = Kl[Eta[e] + na] * Kl[Etb[e] + nb];\n"
-              << "        const bool adm = has && f != (R)0;\n"
-              << "        const unsigned long long m = __ballot(adm);\n"
-              << "        if (adm) {\n"
-              << "          const unsigned pos = base + (unsigned)__popcll(m & ((1ull << ln) - 1ull));\n"
-              << "          const unsigned q = j * " << CAP << "u + pos;\n"
-              << "          const R th = theta[Epr[e]] * f;\n"
+              << "        const bool adm = has && f != (R)0;\n";
+            if (capf > 0)
+                o << "        const bool isf = i < nfi;\n"
+                  << "        const unsigned long long m = __ballot(adm && !isf), mf = __ballot(adm && isf);\n"
+                  << "        if (adm) {\n"
+                  << "          const unsigned long long lt = (1ull << ln) - 1ull;\n"
+                  << "          const unsigned q = j * " << CAP << "u + (isf ? basef + (unsigned)__popcll(mf & lt) : "
+                  << NB << "u + base + (unsigned)__popcll(m & lt));\n";
+            else
+                o << "        const unsigned long long m = __ballot(adm);\n"
+                  << "        if (adm) {\n"
+                  << "          const unsigned pos = base + (unsigned)__popcll(m & ((1ull << ln) - 1ull));\n"
+                  << "          const unsigned q = j * " << CAP << "u + pos;\n";
+            o << "          const R th = theta[Epr[e]] * f;\n"
               << "          lso[par][q] = Eso[e]; lgr[par][q] = Egr[e]; lcr[par][q] = th * Ewr[e];\n"
               << (cplx ? "          lci[par][q] = th * Ewi[e];\n" : "")
               << "        }\n"
               << "        base += (unsigned)__popcll(m);\n"
+              << (capf > 0 ? "        basef += (unsigned)__popcll(mf);\n" : "")
               << "      }\n"
               << "      if (ln < " << U << "u) {\n"
-              << "        const unsigned q = j * " << CAP << "u + base + ln;\n"
-              << "        lso[par][q] = 0; lgr[par][q] = " << ZG << "; lcr[par][q] = (R)0;\n"
-              << (cplx ? "        lci[par][q] = (R)0;\n" : "")
+              << "        { const unsigned q = j * " << CAP << "u + " << NB << "u + base + ln; " << sentinel << " }\n"
+              << (capf > 0 ? "        { const unsigned q = j * " + std::to_string(CAP) + "u + basef + ln; " + sentinel + " }\n"
+                           : std::string(""))
               << "      }\n"
-              << "      if (ln == 0u) lcn[par][j] = base;\n"
+              << "      if (ln == 0u) { lcn[par][j] = base;" << (capf > 0 ? " lcf[par][j] = basef;" : "") << " }\n"
               << "    }\n";
-            std::ostringstream eo;
+            std::ostringstream eo, fo;
             for (int64_t j = 0; j <= PU; ++j) eo << (j ? ", " : "") << ioff[j] << "u";
             pre << "__constant__ unsigned Eoff[" << PU + 1 << "] = {" << eo.str() << "};\n";
+            if (capf > 0) {
+                for (int64_t j = 0; j < PU; ++j) fo << (j ? ", " : "") << nfar[j] << "u";
+                pre << "__constant__ unsigned Enf[" << PU << "] = {" << fo.str() << "};\n";
+            }
         }
         // mixed diagonal uniform parts and the uniform diagonal sum (first waves)
         if (nmd > 0) {
@@ -1135,14 +1164,15 @@ struct Gen {
                     o << " }\n";
                 }
             }
-            if (NI > 0) {
-                o << "      const unsigned n = (unsigned)__builtin_amdgcn_readfirstlane(lcn[par][" << j << "]);\n"
-                  << "      for (unsigned k = " << j * CAP << "u; k < " << j * CAP << "u + n; k += " << U << "u) {\n";
+            // walk one sublist of copy j's list in chunks of U gathers (LD, or LDN for the far entries)
+            auto walk = [&](const std::string& count, int64_t start, const char* ld) {
+                o << "      { const unsigned n = (unsigned)__builtin_amdgcn_readfirstlane(" << count << ");\n"
+                  << "      for (unsigned k = " << start << "u; k < " << start << "u + n; k += " << U << "u) {\n";
                 for (int u = 0; u < U; ++u)
                     o << "        const int so" << u << " = __builtin_amdgcn_readfirstlane(lso[par][k + " << u << "u]);"
                       << " const int g" << u << " = __builtin_amdgcn_readfirstlane(lgr[par][k + " << u << "u]);"
                       << " const R f" << u << " = lfac[(unsigned)g" << u << " * " << block << "u + tid];"
-                      << " const C s" << u << " = LD(xs, f" << u << " != (R)0 ? voff : OOB, F0 + "
+                      << " const C s" << u << " = " << ld << "(xs, f" << u << " != (R)0 ? voff : OOB, F0 + "
                       << (wide ? "(unsigned long long)(long long)so" : "(unsigned)so") << u << ");\n";
                 for (int u = 0; u < U; ++u) {
                     o << "        { const R cr = lcr[par][k + " << u << "u] * f" << u << ";";
@@ -1151,7 +1181,11 @@ struct Gen {
                     acc(j, "cr", cplx ? "ci" : "", "s" + std::to_string(u));
                     o << " }\n";
                 }
-                o << "      }\n";
+                o << "      } }\n";
+            };
+            if (NI > 0) {
+                if (capf > 0) walk("lcf[par][" + std::to_string(j) + "]", j * CAP, "LDN");
+                walk("lcn[par][" + std::to_string(j) + "]", j * CAP + NB, "LD");
             }
             o << store_out("      ", j, soff(j, 0, "F0"), false) << "    }\n";
         }
@@ -1636,6 +1670,7 @@ std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl_out, bool epi)
     gen.epi = epi;
     gen.waves_per_eu = cfg.waves_per_eu;
     gen.far_nt = cfg.far_nt;
+    gen.far_dir = cfg.far_dir;
     gen.outer_first = cfg.outer_first;
     gen.sched = cfg.sched;
     gen.bskip = cfg.bskip != 0;
@@ -1914,7 +1949,7 @@ void set_cfg(mrmf_plan_t* plan, int slot, const mrmf::KernelCfg& c) {
     mrmf::KernelCfg& cur = plan->cfg[slot];
     const bool same = cur.inner == c.inner && cur.unroll == c.unroll && cur.sched == c.sched && cur.bskip == c.bskip &&
                       cur.group == c.group && cur.blocks_per_cu == c.blocks_per_cu && cur.variant == c.variant &&
-                      cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu && cur.far_nt == c.far_nt &&
+                      cur.wide == c.wide && cur.waves_per_eu == c.waves_per_eu && cur.far_nt == c.far_nt && cur.far_dir == c.far_dir &&
                       cur.outer_first == c.outer_first && cur.unroll_top == c.unroll_top &&
                       (slot != mrmf::kSlotCheb || plan->cheb_shape_set);
     cur = c;
@@ -1992,6 +2027,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 if (value != 0 && (value < 10 || value > 40)) return MRMF_E_INVALID_ARG;
                 c.far_nt = value;
                 break;
+            case MRMF_TUNE_FAR_DIR:
+                if (value < 0 || value > 2) return MRMF_E_INVALID_ARG;
+                c.far_dir = value;
+                break;
             case MRMF_TUNE_OUTER_FIRST:
                 if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
                 c.outer_first = value;
@@ -2030,6 +2069,7 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     c.cheb_fused = plan->cfg[dtype].cheb_fused;
     c.wide = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].wide;
     c.far_nt = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_nt;
+    c.far_dir = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_dir;
     c.outer_first = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].outer_first;
     c.unroll_top = unroll_top;
     set_cfg(plan, dtype, c);

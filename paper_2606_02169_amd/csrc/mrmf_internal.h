@@ -106,7 +106,8 @@ struct KernelCfg {
     int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
     int32_t cheb_fused = 1;  // time propagation: fused Chebyshev-step kernel (c128 configuration only)
     int32_t waves_per_eu = 0;  // register budget hint for the generated kernel (0: the compiler's choice)
-    int32_t far_nt = 0;  // > 0: masked-form gathers with |Delta| >= 2^far_nt bytes are non-temporal loads
+    int32_t far_nt = 0;  // > 0: gathers with |Delta| >= 2^far_nt bytes are non-temporal loads
+    int32_t far_dir = 0;  // which of those: 0 both directions, 1 sources behind (Delta > 0), 2 ahead (Delta < 0)
     int32_t grad_blocks_per_cu = 0;  // blocks per CU of the generated gradient kernel (0: the default, 2)
     int32_t outer_first = 0;  // the k most significant sites vary fastest in the super-tile sweep
     int32_t unroll_top = 0;   // k: sites 0..k-1 join the unrolled copies of every super-tile

@@ -267,7 +267,7 @@ class Plan:
 
     TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
               "cheb_fused": 6, "waves_per_eu": 7, "far_loads": 8, "grad_blocks_per_cu": 9,
-              "outer_first": 10, "unroll_top": 11}
+              "outer_first": 10, "unroll_top": 11, "far_dir": 12}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
@@ -275,8 +275,8 @@ class Plan:
         fit), variant (0 masked, 1 list), addressing (0 = 64-bit only where 32-bit offsets cannot reach,
         1 = always 64-bit), cheb_fused (1 = propagate with the fused Chebyshev-step kernel, 0 = matvec +
         update), waves_per_eu (0 = compiler's choice, else a minimum of resident waves per SIMD),
-        far_loads (0 = default cache policy, k = masked-form gathers reaching 2^k bytes or more are
-        non-temporal), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
+        far_loads (0 = default cache policy, k = gathers reaching 2^k bytes or more are non-temporal),
+        far_dir (which of those: 0 both directions, 1 sources behind the row, 2 ahead), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
         kernel, 0 = default), outer_first (k = the k most significant sites vary fastest in the sweep
         over super-tiles, 0 = index order), unroll_top (k = sites 0..k-1 join the unrolled copies, so terms
         between them and the low sites read LDS; 0 = off)."""

@@ -29,7 +29,7 @@ TUNING = {"schedule": L.MRMF_TUNE_SCHEDULE, "branch_skip": L.MRMF_TUNE_BRANCH_SK
           "load_group": L.MRMF_TUNE_LOAD_GROUP, "blocks_per_cu": L.MRMF_TUNE_BLOCKS_PER_CU,
           "variant": L.MRMF_TUNE_VARIANT, "addressing": L.MRMF_TUNE_ADDRESSING,
           "far_loads": L.MRMF_TUNE_FAR_LOADS, "outer_first": L.MRMF_TUNE_OUTER_FIRST,
-          "unroll_top": L.MRMF_TUNE_UNROLL_TOP}
+          "unroll_top": L.MRMF_TUNE_UNROLL_TOP, "far_dir": L.MRMF_TUNE_FAR_DIR}
 
 
 def kernel_source(model, dtype: int, inner: int = 0, unrolled: int = -1, require_hermitian=True,

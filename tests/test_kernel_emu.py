@@ -73,6 +73,9 @@ def test_random_models(seed):
                                          ({"schedule": 2}, 8), ({"variant": 1, "schedule": 2}, 7),
                                          ({"addressing": 1}, 8), ({"addressing": 1, "variant": 1}, 6),
                                          ({"far_loads": 10}, 8), ({"far_loads": 12, "addressing": 1}, 8),
+                                         ({"far_loads": 10, "variant": 1}, 8),
+                                         ({"far_loads": 12, "variant": 1, "far_dir": 1, "load_group": 3}, 5),
+                                         ({"far_loads": 11, "variant": 1, "far_dir": 2, "addressing": 1}, 8),
                                          ({"outer_first": 1}, 8), ({"outer_first": 2, "variant": 1}, 8),
                                          ({"outer_first": 3, "schedule": 1}, 5),
                                          ({"outer_first": 1, "variant": 1, "schedule": 2, "addressing": 1}, 7)])
