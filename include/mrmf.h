@@ -167,8 +167,10 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                                                   super-tiles (runs of one XCD adjacent).
  *   MRMF_TUNE_BRANCH_SKIP   : 1 = a channel whose tile-uniform source digits are inadmissible is skipped
  *                             by a scalar branch; 0 = its loads are issued and masked.
- *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default).
- *   MRMF_TUNE_BLOCKS_PER_CU : cap on resident blocks per compute unit (0 = as many as fit).
+ *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default);
+ *                             a sector made from the plan afterwards uses it in its generated kernel.
+ *   MRMF_TUNE_BLOCKS_PER_CU : cap on resident blocks per compute unit (0 = as many as fit); a sector
+ *                             made from the plan afterwards sizes its generated kernel's grid with it.
  *   MRMF_TUNE_VARIANT       : MRMF_VARIANT_MASKED - every channel that reads outside the super-tile is
  *                                                   issued, masked when inadmissible;
  *                             MRMF_VARIANT_LIST   - those channels are compacted per super-tile into a

@@ -1447,73 +1447,140 @@ std::string grad_source(const mrmf_plan_t* p) {
 // thread per packed row r: unrank r with the combinatorial rank tables (staged in LDS), the digit of site k
 // being the largest v <= min(q_k, d_k - 1) with R_k(q_k, v) <= the rank left, then the diagonal terms and
 // every sum-preserving channel on sites i < j, whose source rank is r plus the change of the table terms
-// of sites i..j (the remaining sums q_k, i < k <= j, move by the channel's shift).  Sites, shifts, factor
-// tables (selects over literals for d <= 3, LDS otherwise) and table offsets are compiled in; a zero factor
-// (source digit out of range) masks the gather to the out-of-range offset, and the table arguments of such
-// a channel are clamped into the tables.  Gathers are issued in groups behind a scheduling barrier.
+// of sites i..j (the remaining sums q_k, i < k <= j, move by the channel's shift).
+//
+// Coefficients come from tables in LDS that every block fills once from theta: per channel the value
+// theta_p w <n_a|O_a|n_a - q_a> <n_b|O_b|n_b - q_b> for every pair of target digits, per pair of sites the
+// sum of the diagonal terms on them (one-site terms folded into a pair that contains their site), so a row
+// reads one table entry per channel and per site pair instead of evaluating factor products.  A channel's
+// gather is issued when both source digits are in range (integer checks) and masked to the out-of-range
+// offset otherwise; the rank tables are padded by the largest digit shift on every side, so the table
+// arguments of a masked channel need no clamping.  Gathers are issued in groups behind a scheduling barrier.
 std::string sector_source(const mrmf_sector_t* S, int dtype) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int N = S->N, Q = S->Q, SZ = f32 ? 8 : 16;
     if (N < 1 || N > 64 || S->Dr < 1 || S->Dr * SZ >= (int64_t(1) << 31)) return "";
     const bool rt32 = S->rt_max < (int64_t(1) << 31);
-    const size_t rt_bytes = S->rt.size() * (rt32 ? 4 : 8);
-    if (rt_bytes > 48 * 1024) return "";
     const char* RT = rt32 ? "int" : "long long";
-    std::vector<double> lds;  // factor tables of sites with d > 3
-    size_t at = 0;            // walks S->tfac in the order the tables were built
-    auto factor = [&](int site) -> std::string {
+    const int nch = static_cast<int>(S->chans.size());
+    // padded rank tables: site k, remaining sum q in -P .. Q + P, digit v in -P .. d_k + P, entry at
+    // po[k] + (q + P) ps[k] + (v + P); zero outside the original table
+    int P = 0;
+    for (const auto& c : S->chans) P = std::max({P, std::abs(c.qa), std::abs(c.qb)});
+    std::vector<int64_t> prt, po(N), ps(N);
+    for (int k = 0; k < N; ++k) {
+        const int d = S->d[k];
+        ps[k] = d + 1 + 2 * P;
+        po[k] = static_cast<int64_t>(prt.size());
+        for (int q = -P; q <= Q + P; ++q)
+            for (int v = -P; v <= d + P; ++v)
+                prt.push_back(q >= 0 && q <= Q && v >= 0 && v <= d ? S->rt[S->rto[k] + int64_t(q) * (d + 1) + v] : 0);
+    }
+    if (prt.size() * (rt32 ? 4 : 8) > 48 * 1024) return "";
+    // factor tables <n|O|n - q> at the target digit, in the order they were built (diagonal terms, then
+    // channels; site a then site b)
+    size_t at = 0;
+    auto take = [&](int site) {
         const int d = S->d[site];
-        const std::string n = "n" + std::to_string(site);
-        const double* t = S->tfac.data() + at;
+        std::vector<double> t(S->tfac.begin() + static_cast<std::ptrdiff_t>(at),
+                              S->tfac.begin() + static_cast<std::ptrdiff_t>(at + d));
         at += d;
-        std::ostringstream e;
-        if (d == 1) {
-            e << lit(t[0], f32);
-        } else if (d <= 3) {
-            e << "(" << n << " == 0u ? " << lit(t[0], f32) << " : ";
-            if (d == 2) e << lit(t[1], f32) << ")";
-            else e << "(" << n << " == 1u ? " << lit(t[1], f32) << " : " << lit(t[2], f32) << "))";
-        } else {
-            e << "Kl[" << lds.size() << "u + " << n << "]";
-            for (int v = 0; v < d; ++v) lds.push_back(t[v]);
-        }
-        return e.str();
+        return t;
     };
-    // rank-table entry (site k, remaining sum q, digit v) as an LDS read
+    struct Contrib {
+        int param;
+        double vr, vi;
+    };
+    std::vector<std::vector<Contrib>> ent;  // coefficient-table entries, each a sum over parameters
+    bool cplx = false;
+    auto add = [&](size_t e, int param, double vr, double vi) {
+        if (vr == 0.0 && vi == 0.0) return;
+        cplx |= vi != 0.0;
+        for (auto& c : ent[e])
+            if (c.param == param) {
+                c.vr += vr;
+                c.vi += vi;
+                return;
+            }
+        ent[e].push_back({param, vr, vi});
+    };
+    // diagonal tables, keyed by (lo, hi) site pairs (hi = -1: one site); one-site terms join a pair that
+    // contains their site when there is one
+    const int ndg = static_cast<int>(S->diags.size());
+    std::vector<std::vector<double>> dfa(ndg), dfb(ndg);
+    for (int g = 0; g < ndg; ++g) {
+        dfa[g] = take(S->diags[g].a);
+        if (S->diags[g].b >= 0) dfb[g] = take(S->diags[g].b);
+    }
+    std::map<std::pair<int, int>, size_t> doff;  // key -> offset of its table in ent
+    std::vector<std::pair<int, int>> dkeys;
+    auto key_table = [&](std::pair<int, int> key) {
+        auto it = doff.find(key);
+        if (it != doff.end()) return it->second;
+        const size_t off = ent.size();
+        const int n = S->d[key.first] * (key.second >= 0 ? S->d[key.second] : 1);
+        ent.resize(off + n);
+        doff[key] = off;
+        dkeys.push_back(key);
+        return off;
+    };
+    for (int g = 0; g < ndg; ++g) {
+        const DevDiag& t = S->diags[g];
+        if (t.b >= 0) key_table({std::min(t.a, t.b), std::max(t.a, t.b)});
+    }
+    for (int g = 0; g < ndg; ++g) {
+        const DevDiag& t = S->diags[g];
+        std::pair<int, int> key{t.a, -1};
+        if (t.b >= 0) {
+            key = {std::min(t.a, t.b), std::max(t.a, t.b)};
+        } else {
+            for (const auto& k : dkeys)
+                if (k.second >= 0 && (k.first == t.a || k.second == t.a)) {
+                    key = k;
+                    break;
+                }
+        }
+        const size_t off = key_table(key);
+        const int dlo = S->d[key.first], dhi = key.second >= 0 ? S->d[key.second] : 1;
+        for (int nl = 0; nl < dlo; ++nl)
+            for (int nh = 0; nh < dhi; ++nh) {
+                // digits of the term's sites within the key
+                const int na = t.a == key.first ? nl : nh;
+                double f = dfa[g][na];
+                if (t.b >= 0) f *= dfb[g][t.b == key.first ? nl : nh];
+                add(off + size_t(nl) * dhi + nh, t.param, t.wr * f, t.wi * f);
+            }
+    }
+    // channel tables: entry (n_a, n_b) at co[c] + n_a d_b + n_b
+    std::vector<size_t> co(nch);
+    for (int c = 0; c < nch; ++c) {
+        const DevChan& ch = S->chans[c];
+        const std::vector<double> fa = take(ch.a), fb = take(ch.b);
+        const int da = S->d[ch.a], db = S->d[ch.b];
+        co[c] = ent.size();
+        ent.resize(ent.size() + size_t(da) * db);
+        for (int na = 0; na < da; ++na)
+            for (int nb = 0; nb < db; ++nb) add(co[c] + size_t(na) * db + nb, ch.param, ch.wr * fa[na] * fb[nb],
+                                                ch.wi * fa[na] * fb[nb]);
+    }
+    const size_t NE = std::max<size_t>(1, ent.size());
+    if (NE * (f32 ? 4 : 8) * (cplx ? 2 : 1) > 32 * 1024) return "";
+    std::vector<int32_t> cb{0}, cp;
+    std::vector<double> cvr, cvi;
+    for (const auto& e : ent) {
+        for (const auto& c : e) {
+            cp.push_back(c.param);
+            cvr.push_back(c.vr);
+            cvi.push_back(c.vi);
+        }
+        cb.push_back(static_cast<int32_t>(cp.size()));
+    }
+    // rank-table entry (site k, remaining sum q, digit v): int expressions q and v
     auto rte = [&](int k, const std::string& q, const std::string& v) {
         std::ostringstream e;
-        e << "L[" << S->rto[k] << "u + (" << q << ") * " << S->d[k] + 1 << "u + (" << v << ")]";
+        e << "L[" << po[k] + int64_t(P) * ps[k] + P << " + (" << q << ") * " << ps[k] << " + (" << v << ")]";
         return e.str();
     };
-    auto clampq = [&](int k, int dq) {
-        std::ostringstream e;
-        e << "(unsigned)clampi((int)q" << k << " - (" << dq << "), " << Q << ")";
-        return e.str();
-    };
-    auto clampd = [&](int k, int shift) {
-        std::ostringstream e;
-        e << "(unsigned)clampi((int)n" << k << " - (" << shift << "), " << S->d[k] - 1 << ")";
-        return e.str();
-    };
-    std::set<int> params;
-    for (const auto& g : S->diags) params.insert(g.param);
-    for (const auto& c : S->chans) params.insert(c.param);
-    // factor expressions of every term, in the order the tables were built
-    std::vector<std::string> gf(S->diags.size()), cfa(S->chans.size()), cfb(S->chans.size());
-    for (size_t g = 0; g < S->diags.size(); ++g) {
-        gf[g] = factor(S->diags[g].a);
-        if (S->diags[g].b >= 0) gf[g] = "(" + gf[g] + " * " + factor(S->diags[g].b) + ")";
-    }
-    for (size_t c = 0; c < S->chans.size(); ++c) {
-        cfa[c] = factor(S->chans[c].a);
-        cfb[c] = factor(S->chans[c].b);
-    }
-    // The row body in site order: after site k is unranked, the diagonal terms whose sites are all known
-    // are added, every channel spanning k adds site k's change of its rank, and the channels whose last
-    // site is k issue their gathers; every kGroup gathers are accumulated, behind a fence that keeps the
-    // next loads (and table reads) after them.  So each site's digit, remaining sum and table base die once
-    // the channels spanning it have used them, even for a bond between the first and the last site.
-    const int nch = static_cast<int>(S->chans.size());
     struct Span {
         int i, j, si, sj;
     };
@@ -1523,22 +1590,47 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
         const bool a_first = ch.a < ch.b;
         sp[c] = {a_first ? ch.a : ch.b, a_first ? ch.b : ch.a, a_first ? ch.qa : ch.qb, a_first ? ch.qb : ch.qa};
     }
-    constexpr int kGroup = 6;
+    // A channel on adjacent sites i, i + 1 changes the rank by an amount that depends on (q_i, n_i, n_{i+1})
+    // only (q_{i+1} = q_i - n_i): one table per such channel, entry at wo[c] + (q_i d_i + n_i) d_{i+1} + n_{i+1}
+    // (zero where the source digits or sums leave the table), when all of them fit 24 KB of LDS.
+    auto rt_at = [&](int k, int q, int v) { return S->rt[S->rto[k] + int64_t(q) * (S->d[k] + 1) + v]; };
+    std::vector<int64_t> wtab;
+    std::vector<int64_t> wo(nch, -1);
+    {
+        size_t need = 0;
+        for (int c = 0; c < nch; ++c)
+            if (sp[c].j == sp[c].i + 1) need += size_t(Q + 1) * S->d[sp[c].i] * S->d[sp[c].j];
+        if (need * (rt32 ? 4 : 8) <= 24 * 1024) {
+            for (int c = 0; c < nch; ++c) {
+                const Span& z = sp[c];
+                if (z.j != z.i + 1) continue;
+                const int di = S->d[z.i], dj = S->d[z.j];
+                wo[c] = static_cast<int64_t>(wtab.size());
+                for (int q = 0; q <= Q; ++q)
+                    for (int ni = 0; ni < di; ++ni)
+                        for (int nj = 0; nj < dj; ++nj) {
+                            const int si = ni - z.si, qj = q - ni, qs = qj + z.si, sj = nj - z.sj;
+                            const bool ok = ni <= q && si >= 0 && si < di && si <= q && sj >= 0 && sj < dj && qj >= 0 &&
+                                            qj <= Q && qs >= 0 && qs <= Q;
+                            wtab.push_back(ok ? rt_at(z.i, q, si) - rt_at(z.i, q, ni) + rt_at(z.j, qs, sj) - rt_at(z.j, qj, nj)
+                                              : 0);
+                        }
+            }
+        }
+    }
+    const int kGroup = S->group > 0 ? S->group : 10;
     std::vector<int> pending;
     std::ostringstream body;
     auto flush = [&](bool last) {
         if (pending.empty()) return;
         body << "    __builtin_amdgcn_sched_barrier(0);\n";
         for (int c : pending) {
-            const DevChan& ch = S->chans[c];
             const std::string u = std::to_string(c);
-            // (f w) theta: a product of loop-invariant factors would be hoisted out of the row loop and
-            // kept in registers for every channel
-            body << "    { const R cr = f" << u << " * " << lit(ch.wr, f32) << " * th" << ch.param << ";"
-                 << " ar = fma(cr, s" << u << ".x, ar); ai = fma(cr, s" << u << ".y, ai);";
-            if (ch.wi != 0.0)
-                body << " const R ci = f" << u << " * " << lit(ch.wi, f32) << " * th" << ch.param << ";"
-                     << " ar = fma(-ci, s" << u << ".y, ar); ai = fma(ci, s" << u << ".x, ai);";
+            body << "    { const R cr = Tr[" << co[c] << "u + x" << u << "]; ar = fma(cr, s" << u << ".x, ar); ai = fma(cr, s" << u
+                 << ".y, ai);";
+            if (cplx)
+                body << " const R ci = Ti[" << co[c] << "u + x" << u << "]; ar = fma(-ci, s" << u << ".y, ar); ai = fma(ci, s" << u
+                     << ".x, ai);";
             body << " }\n";
         }
         if (!last) body << "    MRMF_GROUP_FENCE(ar, ai);\n";
@@ -1549,42 +1641,55 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     for (int k = 0; k < N; ++k) {
         const int d = S->d[k];
         const std::string K = std::to_string(k);
-        body << "    const unsigned q" << K << " = q;\n"
-             << "    unsigned n" << K << " = 0u;\n"
+        body << "    const int q" << K << " = q;\n"
+             << "    int n" << K << " = 0;\n"
              << "    " << RT << " b" << K << " = 0;\n";  // R_k(q_k, n_k)
         if (d > 1) {
             body << "    {\n";
             for (int v = 1; v < d; ++v)
-                body << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v) + "u") << "; const bool ok = " << v
-                     << "u <= q && t <= left; n" << K << " = ok ? " << v << "u : n" << K << "; b" << K << " = ok ? t : b" << K
+                body << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v)) << "; const bool ok = " << v
+                     << " <= q && t <= left; n" << K << " = ok ? " << v << " : n" << K << "; b" << K << " = ok ? t : b" << K
                      << "; }\n";
             body << "      left -= b" << K << "; q -= n" << K << "; }\n";
         }
-        for (size_t g = 0; g < S->diags.size(); ++g) {
-            const DevDiag& t = S->diags[g];
-            if (std::max(t.a, t.b) != k) continue;
-            body << "    { const R f = " << gf[g] << "; dr = fma(f * " << lit(t.wr, f32) << ", th" << t.param << ", dr);";
-            if (t.wi != 0.0) body << " di = fma(f * " << lit(t.wi, f32) << ", th" << t.param << ", di);";
-            body << " }\n";
+        for (const auto& key : dkeys) {
+            if (std::max(key.first, key.second) != k) continue;
+            const size_t off = doff[key];
+            body << "    { const unsigned e = " << off << "u + ";
+            if (key.second >= 0) body << "(unsigned)n" << key.first << " * " << S->d[key.second] << "u + (unsigned)n" << key.second;
+            else body << "(unsigned)n" << key.first;
+            body << "; dr += Tr[e];" << (cplx ? " di += Ti[e];" : "") << " }\n";
         }
         for (int c = 0; c < nch; ++c) {
             const Span& z = sp[c];
             if (k < z.i || k > z.j) continue;
             const std::string u = std::to_string(c);
-            const int dq = -z.si;  // source digit minus target digit at site i
+            if (wo[c] >= 0) {
+                if (k == z.j)
+                    body << "    const " << RT << " e" << u << " = W[" << wo[c] << " + (q" << z.i << " * " << S->d[z.i] << " + n"
+                         << z.i << ") * " << S->d[z.j] << " + n" << z.j << "];\n";
+                continue;
+            }
+            // source remaining sum at sites after i: the target's plus the shift at site i
+            const std::string qs = "q" + K + " + (" + std::to_string(z.si) + ")";
             if (k == z.i)
-                body << "    " << RT << " e" << u << " = " << rte(k, "q" + K, clampd(k, z.si)) << " - b" << K << ";\n";
+                body << "    " << RT << " e" << u << " = " << rte(k, "q" + K, "n" + K + " - (" + std::to_string(z.si) + ")")
+                     << " - b" << K << ";\n";
             else if (k < z.j)
-                body << "    e" << u << " += " << rte(k, clampq(k, dq), "n" + K) << " - b" << K << ";\n";
+                body << "    e" << u << " += " << rte(k, qs, "n" + K) << " - b" << K << ";\n";
             else
-                body << "    e" << u << " += " << rte(k, clampq(k, dq), clampd(k, z.sj)) << " - b" << K << ";\n";
+                body << "    e" << u << " += " << rte(k, qs, "n" + K + " - (" + std::to_string(z.sj) + ")") << " - b" << K << ";\n";
         }
         for (int c = 0; c < nch; ++c) {
             if (sp[c].j != k) continue;
+            const DevChan& ch = S->chans[c];
             const std::string u = std::to_string(c);
-            body << "    const R f" << u << " = " << cfa[c] << " * " << cfb[c] << ";\n"
-                 << "    const C s" << u << " = LD(xs, f" << u << " != (R)0 ? (unsigned)((" << RT << ")r + e" << u << ") * "
-                 << SZ << "u : OOB);\n";
+            body << "    const bool k" << u << " = (unsigned)(n" << ch.a << " - (" << ch.qa << ")) < " << S->d[ch.a]
+                 << "u && (unsigned)(n" << ch.b << " - (" << ch.qb << ")) < " << S->d[ch.b] << "u;\n"
+                 << "    const unsigned x" << u << " = (unsigned)n" << ch.a << " * " << S->d[ch.b] << "u + (unsigned)n" << ch.b
+                 << ";\n"
+                 << "    const C s" << u << " = LD(xs, k" << u << " ? (unsigned)((" << RT << ")r + e" << u << ") * " << SZ
+                 << "u : OOB);\n";
             pending.push_back(c);
             if (static_cast<int>(pending.size()) >= kGroup) flush(false);
         }
@@ -1593,8 +1698,8 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     body << "    ar += dr * xf.x - di * xf.y;\n"
          << "    ai += dr * xf.y + di * xf.x;\n";
     std::ostringstream o;
-    o << "// generated sector kernel: " << N << " sites, digit sum " << Q << ", " << S->Dr << " packed states, "
-      << S->diags.size() << " diagonal terms, " << nch << " channels\n";
+    o << "// generated sector kernel: " << N << " sites, digit sum " << Q << ", " << S->Dr << " packed states, " << ndg
+      << " diagonal terms in " << dkeys.size() << " tables, " << nch << " channels\n";
     if (f32)
         o << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
           << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
@@ -1608,38 +1713,56 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     o << "#define OOB 0x80000000u\n"
       << "#ifndef MRMF_GROUP_FENCE\n"
       << "#define MRMF_GROUP_FENCE(a, b) __asm__ __volatile__(\"\" : \"+v\"(a), \"+v\"(b) : : \"memory\")\n"
-      << "#endif\n"
-      << "// v clamped into 0 .. hi\n"
-      << "__device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }\n";
-    o << "__constant__ " << RT << " RTC[" << S->rt.size() << "] = {";
-    for (size_t k = 0; k < S->rt.size(); ++k) o << (k ? ", " : "") << S->rt[k];
+      << "#endif\n";
+    o << "__constant__ " << RT << " RTC[" << prt.size() << "] = {";
+    for (size_t k = 0; k < prt.size(); ++k) o << (k ? ", " : "") << prt[k];
     o << "};\n";
-    if (!lds.empty()) {
-        o << "__constant__ R KC[" << lds.size() << "] = {";
-        for (size_t k = 0; k < lds.size(); ++k) o << (k ? ", " : "") << lit(lds[k], f32);
+    if (!wtab.empty()) {
+        o << "__constant__ " << RT << " WTC[" << wtab.size() << "] = {";
+        for (size_t k = 0; k < wtab.size(); ++k) o << (k ? ", " : "") << wtab[k];
         o << "};\n";
     }
+    auto arr = [&](const char* ty, const char* nm, size_t n, const std::function<std::string(size_t)>& f) {
+        o << "__constant__ " << ty << " " << nm << "[" << std::max<size_t>(1, n) << "] = {";
+        if (n == 0) o << "0";
+        for (size_t k = 0; k < n; ++k) o << (k ? ", " : "") << f(k);
+        o << "};\n";
+    };
+    arr("int", "CB", cb.size(), [&](size_t k) { return std::to_string(cb[k]); });
+    arr("int", "CP", cp.size(), [&](size_t k) { return std::to_string(cp[k]); });
+    arr("R", "CVR", cvr.size(), [&](size_t k) { return lit(cvr[k], f32); });
+    if (cplx) arr("R", "CVI", cvi.size(), [&](size_t k) { return lit(cvi[k], f32); });
     o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector(const R* __restrict__ theta,\n"
       << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
       << "  if (skip != nullptr && *skip != 0) return;\n"
-      << "  __shared__ " << RT << " L[" << S->rt.size() << "];\n"
-      << "  for (unsigned k = threadIdx.x; k < " << S->rt.size() << "u; k += 256u) L[k] = RTC[k];\n";
-    if (!lds.empty())
-        o << "  __shared__ R Kl[" << lds.size() << "];\n"
-          << "  for (unsigned k = threadIdx.x; k < " << lds.size() << "u; k += 256u) Kl[k] = KC[k];\n";
-    o << "  __syncthreads();\n"
+      << "  __shared__ " << RT << " L[" << prt.size() << "];\n"
+      << "  for (unsigned k = threadIdx.x; k < " << prt.size() << "u; k += 256u) L[k] = RTC[k];\n"
+      << "  __shared__ R Tr[" << NE << "];\n";
+    if (!wtab.empty())
+        o << "  __shared__ " << RT << " W[" << wtab.size() << "];\n"
+          << "  for (unsigned k = threadIdx.x; k < " << wtab.size() << "u; k += 256u) W[k] = WTC[k];\n";
+    if (cplx) o << "  __shared__ R Ti[" << NE << "];\n";
+    o << "  for (unsigned k = threadIdx.x; k < " << ent.size() << "u; k += 256u) {\n"
+      << "    R sr = (R)0, si = (R)0;\n"
+      << "    for (int u = CB[k]; u < CB[k + 1u]; ++u) { const R th = theta[CP[u]]; sr += th * CVR[u];"
+      << (cplx ? " si += th * CVI[u];" : "") << " }\n"
+      << "    Tr[k] = sr;" << (cplx ? " Ti[k] = si;" : "") << "\n"
+      << "  }\n"
+      << "  __syncthreads();\n"
       << "  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, " << S->Dr * SZ
       << ", 0x00020000);\n"
       << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)y, (short)0, " << S->Dr * SZ
-      << ", 0x00020000);\n";
-    for (int q : params) o << "  const R th" << q << " = theta[" << q << "];\n";
-    o << "  for (unsigned r = blockIdx.x * 256u + threadIdx.x; r < " << S->Dr << "u; r += gridDim.x * 256u) {\n"
-      << "    unsigned q = " << Q << "u;\n"
+      << ", 0x00020000);\n"
+      // windows of G row groups of 256: the blocks of one XCD (block b runs on XCD b mod 8) take one eighth of
+      // each window side by side, so the rows near a channel's source were just read through that XCD's L2
+      << "  const unsigned G = gridDim.x, bk = blockIdx.x;\n"
+      << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
+      << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n"
+      << "    int q = " << Q << ";\n"
       << "    " << RT << " left = (" << RT << ")r;\n";
     o << body.str()
       << "    { C out; out.x = ar; out.y = ai; ST(out, ys, r * " << SZ << "u); }\n"
       << "  }\n}\n";
-    (void)at;
     return o.str();
 }
 
@@ -1895,8 +2018,10 @@ mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
     hipFunction_t fn;
     const mrmf_status bs = rtc_build(src, "mrmf_sector", prop, &mod, &fn, &K.log);
     if (bs != MRMF_OK) return bs;
-    int per_cu = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    int per_cu = S->blocks_per_cu;
+    if (per_cu <= 0 &&
+        (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1))
+        per_cu = 1;
     const int64_t groups = (S->Dr + 255) / 256;
     K.mod = mod;
     K.fn = fn;

@@ -245,7 +245,7 @@ def test_sector_kernel(seed):
             continue
         x = W.random_state(lab.size, rng)
         ref = osec.matvec(m, Q, x, lab=lab)
-        for grid in ((lab.size + 255) // 256, 1):
+        for grid in ((lab.size + 255) // 256, 1, 8):
             y = E.run_sector(m, Q, x, grid)
             assert rel_err(y, ref) <= TOL_Z, (Q, grid)
         x32 = x.astype(np.complex64)
