@@ -388,12 +388,17 @@ mrmf_status mrmf_cheb_bessel(double z, double tol, int32_t cap, double* h_out, i
  * local digits sum to digit_sum (a spin digit is n = m + s, so a fixed total magnetization M is
  * digit_sum = M + sum_i s_i; with bosons the digit sum is the excitation number).  Sector vectors are
  * packed in ascending full-basis order (site 0 most significant); the packed position of a state is its
- * combinatorial rank (the Lehmer-code-style lookup of Sec. VI.B), so no table of labels is stored.
+ * combinatorial rank (the Lehmer-code-style lookup of Sec. VI.B), so source rows are found without a
+ * table of labels or a search.
  * The sector matvec is y = P H P^T x: channels whose source leaves the sector (every one-site ladder
  * channel, and pair channels with q_a + q_b != 0) contribute nothing and are dropped at creation.
  * mrmf_sector_create copies what it needs from the plan (the plan may be destroyed afterwards);
  * MRMF_E_INVALID_ARG for digit_sum outside 0 .. sum_i (d_i - 1) or a maximal digit sum above 65535.
- * Workspace: caller-owned, 256-B aligned, mrmf_sector_workspace_bytes, filled by mrmf_sector_upload. */
+ * Workspace: caller-owned, 256-B aligned, mrmf_sector_workspace_bytes, filled by mrmf_sector_upload
+ * (stream-ordered: a copy of the tables, then, unless the plan's kernel selection was MRMF_KERNEL_GENERIC,
+ * a kernel that writes every state's local digits packed into one 4- or 8-byte word, the inverse of the
+ * rank that the generated kernel reads instead of unranking its rows; none when the digits take more than
+ * 64 bits or the sector has 2^28 states or more). */
 typedef struct mrmf_sector_t* mrmf_sector;
 mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* out);
 void mrmf_sector_destroy(mrmf_sector sector);
@@ -403,8 +408,9 @@ mrmf_status mrmf_sector_upload(mrmf_sector sector, void* d_ws, size_t ws_bytes, 
 /* y = P H(theta) P^T x on packed sector vectors (c128 / c64, 16-B / 8-B aligned, not overlapping).
  * Unless the plan's kernel selection was MRMF_KERNEL_GENERIC when the sector was made, the first call
  * per element type and device generates and compiles a kernel for this sector (sites, channels, factor
- * and rank tables compiled in); sectors that do not qualify (more than 64 sites, rank tables over 48 KB,
- * vectors of 2^31 bytes or more) and generic-mode sectors run the generic kernel. */
+ * tables and rank-change tables compiled in); sectors that do not qualify (no packed digits, rank-change
+ * tables over 40 KB or coefficient tables over 32 KB, vectors of 2^31 bytes or more) and generic-mode
+ * sectors run the generic kernel. */
 mrmf_status mrmf_sector_matvec_z(mrmf_sector sector, const void* d_ws, const double* d_theta, const void* d_x,
                                  void* d_y, mrmf_stream stream);
 mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const float* d_theta, const void* d_x,

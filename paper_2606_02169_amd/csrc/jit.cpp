@@ -1444,39 +1444,32 @@ std::string grad_source(const mrmf_plan_t* p) {
 }
 
 // Sector kernel generated for one digit-sum sector (Sec. VI, case 2; App. D) and element type.  One
-// thread per packed row r: unrank r with the combinatorial rank tables (staged in LDS), the digit of site k
-// being the largest v <= min(q_k, d_k - 1) with R_k(q_k, v) <= the rank left, then the diagonal terms and
-// every sum-preserving channel on sites i < j, whose source rank is r plus the change of the table terms
-// of sites i..j (the remaining sums q_k, i < k <= j, move by the channel's shift).
+// thread per packed row r.  The row's digits come from the packed-digit table of the workspace (one word per
+// state, filled from the combinatorial rank tables when the workspace is uploaded) instead of unranking r,
+// and the remaining sums q_k = Q - n_0 - .. - n_{k-1} from the digits.  Then the diagonal terms and every
+// sum-preserving channel on sites i < j, whose source rank is r plus the change of the rank-table terms of
+// sites i..j (the remaining sums q_k, i < k <= j, move by the channel's shift at site i).
 //
 // Coefficients come from tables in LDS that every block fills once from theta: per channel the value
 // theta_p w <n_a|O_a|n_a - q_a> <n_b|O_b|n_b - q_b> for every pair of target digits, per pair of sites the
 // sum of the diagonal terms on them (one-site terms folded into a pair that contains their site), so a row
-// reads one table entry per channel and per site pair instead of evaluating factor products.  A channel's
-// gather is issued when both source digits are in range (integer checks) and masked to the out-of-range
-// offset otherwise; the rank tables are padded by the largest digit shift on every side, so the table
-// arguments of a masked channel need no clamping.  Gathers are issued in groups behind a scheduling barrier.
+// reads one table entry per channel and per site pair instead of evaluating factor products.
+//
+// Rank changes come from LDS tables too.  A channel's span i..j is cut into segments of two adjacent sites
+// (one for the last site of an odd span) from i on; a segment's table, indexed by (q, digits) of its first
+// site and the digit of its second, holds its sites' share of the change times SZ (a byte offset).
+// Channels of the same span share the segment indices and have their tables interleaved, so one LDS read
+// serves two of them.  When the span is one segment (adjacent sites) the entry is the whole offset, or 2^31
+// where a source digit leaves its range: the buffer load then lands past the end of x (whose byte size is
+// below 2^31) and returns zero, so such a channel needs no digit checks.  Longer spans add their segments in
+// 32-bit unsigned arithmetic (exact modulo 2^32; the true offset lies within +-2^31) and are masked to that
+// out-of-range offset by integer checks of their source digits.  Gathers are issued in groups behind a
+// scheduling barrier.
 std::string sector_source(const mrmf_sector_t* S, int dtype) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int N = S->N, Q = S->Q, SZ = f32 ? 8 : 16;
-    if (N < 1 || N > 64 || S->Dr < 1 || S->Dr * SZ >= (int64_t(1) << 31)) return "";
-    const bool rt32 = S->rt_max < (int64_t(1) << 31);
-    const char* RT = rt32 ? "int" : "long long";
+    if (N < 1 || N > 64 || S->Dr < 1 || S->Dr * SZ >= (int64_t(1) << 31) || S->lab_bytes == 0) return "";
     const int nch = static_cast<int>(S->chans.size());
-    // padded rank tables: site k, remaining sum q in -P .. Q + P, digit v in -P .. d_k + P, entry at
-    // po[k] + (q + P) ps[k] + (v + P); zero outside the original table
-    int P = 0;
-    for (const auto& c : S->chans) P = std::max({P, std::abs(c.qa), std::abs(c.qb)});
-    std::vector<int64_t> prt, po(N), ps(N);
-    for (int k = 0; k < N; ++k) {
-        const int d = S->d[k];
-        ps[k] = d + 1 + 2 * P;
-        po[k] = static_cast<int64_t>(prt.size());
-        for (int q = -P; q <= Q + P; ++q)
-            for (int v = -P; v <= d + P; ++v)
-                prt.push_back(q >= 0 && q <= Q && v >= 0 && v <= d ? S->rt[S->rto[k] + int64_t(q) * (d + 1) + v] : 0);
-    }
-    if (prt.size() * (rt32 ? 4 : 8) > 48 * 1024) return "";
     // factor tables <n|O|n - q> at the target digit, in the order they were built (diagonal terms, then
     // channels; site a then site b)
     size_t at = 0;
@@ -1575,14 +1568,10 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
         }
         cb.push_back(static_cast<int32_t>(cp.size()));
     }
-    // rank-table entry (site k, remaining sum q, digit v): int expressions q and v
-    auto rte = [&](int k, const std::string& q, const std::string& v) {
-        std::ostringstream e;
-        e << "L[" << po[k] + int64_t(P) * ps[k] + P << " + (" << q << ") * " << ps[k] << " + (" << v << ")]";
-        return e.str();
-    };
+
+    // rank-change segment tables
     struct Span {
-        int i, j, si, sj;
+        int i, j, si, sj;  // sites i < j; source digits n_i - si, n_j - sj
     };
     std::vector<Span> sp(nch);
     for (int c = 0; c < nch; ++c) {
@@ -1590,34 +1579,62 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
         const bool a_first = ch.a < ch.b;
         sp[c] = {a_first ? ch.a : ch.b, a_first ? ch.b : ch.a, a_first ? ch.qa : ch.qb, a_first ? ch.qb : ch.qa};
     }
-    // A channel on adjacent sites i, i + 1 changes the rank by an amount that depends on (q_i, n_i, n_{i+1})
-    // only (q_{i+1} = q_i - n_i): one table per such channel, entry at wo[c] + (q_i d_i + n_i) d_{i+1} + n_{i+1}
-    // (zero where the source digits or sums leave the table), when all of them fit 24 KB of LDS.
-    auto rt_at = [&](int k, int q, int v) { return S->rt[S->rto[k] + int64_t(q) * (S->d[k] + 1) + v]; };
-    std::vector<int64_t> wtab;
-    std::vector<int64_t> wo(nch, -1);
+    // R_k(q, v), zero outside q in 0 .. Q, v in 0 .. d_k
+    auto R = [&](int k, int q, int v) -> int64_t {
+        if (q < 0 || q > Q || v < 0 || v > S->d[k]) return 0;
+        return S->rt[S->rto[k] + int64_t(q) * (S->d[k] + 1) + v];
+    };
+    // site k's share of channel c's rank change at target (q_k, n_k)
+    auto share = [&](const Span& z, int k, int q, int n) -> int64_t {
+        if (k == z.i) return R(k, q, n - z.si) - R(k, q, n);
+        if (k < z.j) return R(k, q + z.si, n) - R(k, q, n);
+        return R(k, q + z.si, n - z.sj) - R(k, q, n);
+    };
+    // groups of at most two channels with the same span, in channel order
+    std::vector<std::vector<int>> groups;
     {
-        size_t need = 0;
-        for (int c = 0; c < nch; ++c)
-            if (sp[c].j == sp[c].i + 1) need += size_t(Q + 1) * S->d[sp[c].i] * S->d[sp[c].j];
-        if (need * (rt32 ? 4 : 8) <= 24 * 1024) {
-            for (int c = 0; c < nch; ++c) {
-                const Span& z = sp[c];
-                if (z.j != z.i + 1) continue;
-                const int di = S->d[z.i], dj = S->d[z.j];
-                wo[c] = static_cast<int64_t>(wtab.size());
-                for (int q = 0; q <= Q; ++q)
-                    for (int ni = 0; ni < di; ++ni)
-                        for (int nj = 0; nj < dj; ++nj) {
-                            const int si = ni - z.si, qj = q - ni, qs = qj + z.si, sj = nj - z.sj;
-                            const bool ok = ni <= q && si >= 0 && si < di && si <= q && sj >= 0 && sj < dj && qj >= 0 &&
-                                            qj <= Q && qs >= 0 && qs <= Q;
-                            wtab.push_back(ok ? rt_at(z.i, q, si) - rt_at(z.i, q, ni) + rt_at(z.j, qs, sj) - rt_at(z.j, qj, nj)
-                                              : 0);
-                        }
+        std::map<std::pair<int, int>, int> open;  // span -> group with one member
+        for (int c = 0; c < nch; ++c) {
+            const std::pair<int, int> key{sp[c].i, sp[c].j};
+            auto it = open.find(key);
+            if (it != open.end()) {
+                groups[it->second].push_back(c);
+                open.erase(it);
+            } else {
+                open[key] = static_cast<int>(groups.size());
+                groups.push_back({c});
             }
         }
     }
+    std::vector<uint32_t> seg;                     // all segment tables
+    std::vector<std::vector<size_t>> gso(groups.size());  // per group, offset of each segment's table
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const Span& z0 = sp[groups[g][0]];
+        const int gp = static_cast<int>(groups[g].size());
+        const bool single = z0.j == z0.i + 1;
+        for (int s = z0.i; s <= z0.j; s += 2) {
+            const bool pair = s + 1 <= z0.j;
+            const int ds = S->d[s], dt = pair ? S->d[s + 1] : 1;
+            if (seg.size() % 2) seg.push_back(0);  // 8-byte aligned tables for two-channel reads
+            gso[g].push_back(seg.size());
+            for (int q = 0; q <= Q; ++q)
+                for (int n = 0; n < ds; ++n)
+                    for (int m = 0; m < dt; ++m)
+                        for (int u = 0; u < gp; ++u) {
+                            const Span& z = sp[groups[g][u]];
+                            int64_t e = share(z, s, q, n);
+                            if (pair) e += share(z, s + 1, q - n, m);
+                            uint32_t v = static_cast<uint32_t>(e * SZ);
+                            if (single) {
+                                const bool ok = n - z.si >= 0 && n - z.si < ds && m - z.sj >= 0 && m - z.sj < dt && n <= q;
+                                v = ok ? v : 0x80000000u;
+                            }
+                            seg.push_back(v);
+                        }
+        }
+    }
+    if (seg.size() * 4 > 40 * 1024) return "";
+
     const int kGroup = S->group > 0 ? S->group : 10;
     std::vector<int> pending;
     std::ostringstream body;
@@ -1636,60 +1653,76 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
         if (!last) body << "    MRMF_GROUP_FENCE(ar, ai);\n";
         pending.clear();
     };
+    const bool w64 = S->lab_bytes == 8;
     body << "    R dr = (R)0, di = (R)0, ar = (R)0, ai = (R)0;\n"
-         << "    const C xf = LD(xs, r * " << SZ << "u);\n";
+         << "    const unsigned rb = r * " << SZ << "u;\n"
+         << "    const C xf = LD(xs, rb);\n";
+    if (w64)
+        body << "    const unsigned long long lw = __builtin_bit_cast(unsigned long long, "
+                "__builtin_amdgcn_raw_buffer_load_b64(ls, (int)(r * 8u), 0, 0));\n";
+    else
+        body << "    const unsigned lw = __builtin_amdgcn_raw_buffer_load_b32(ls, (int)(r * 4u), 0, 0);\n";
+    if (nch > 0) {
+        body << "    unsigned ";
+        for (int c = 0; c < nch; ++c) body << (c ? ", " : "") << "e" << c << " = 0u";
+        body << ";\n";
+    }
+    // bit offset of site k's digit in the packed word (site N - 1 lowest)
+    std::vector<int> off(N, 0);
+    for (int k = N - 2; k >= 0; --k) off[k] = off[k + 1] + S->lab_w[k + 1];
     for (int k = 0; k < N; ++k) {
-        const int d = S->d[k];
         const std::string K = std::to_string(k);
-        body << "    const int q" << K << " = q;\n"
-             << "    int n" << K << " = 0;\n"
-             << "    " << RT << " b" << K << " = 0;\n";  // R_k(q_k, n_k)
-        if (d > 1) {
-            body << "    {\n";
-            for (int v = 1; v < d; ++v)
-                body << "      { const " << RT << " t = " << rte(k, "q", std::to_string(v)) << "; const bool ok = " << v
-                     << " <= q && t <= left; n" << K << " = ok ? " << v << " : n" << K << "; b" << K << " = ok ? t : b" << K
-                     << "; }\n";
-            body << "      left -= b" << K << "; q -= n" << K << "; }\n";
-        }
+        // digit and remaining sum of site k (q_k in 0 .. Q: 24-bit multiplies for the table indices)
+        if (S->lab_w[k] > 0)
+            body << "    const int n" << K << " = (int)((lw >> " << off[k] << ") & " << ((1u << S->lab_w[k]) - 1) << "u);\n";
+        else
+            body << "    const int n" << K << " = 0;\n";
+        if (k == 0)
+            body << "    const int q0 = " << Q << ";\n";
+        else
+            body << "    const int q" << K << " = q" << k - 1 << " - n" << k - 1 << ";\n";
+        body << "    __builtin_assume((unsigned)q" << K << " <= " << Q << "u);\n";
         for (const auto& key : dkeys) {
             if (std::max(key.first, key.second) != k) continue;
-            const size_t off = doff[key];
-            body << "    { const unsigned e = " << off << "u + ";
+            const size_t o = doff[key];
+            body << "    { const unsigned e = " << o << "u + ";
             if (key.second >= 0) body << "(unsigned)n" << key.first << " * " << S->d[key.second] << "u + (unsigned)n" << key.second;
             else body << "(unsigned)n" << key.first;
             body << "; dr += Tr[e];" << (cplx ? " di += Ti[e];" : "") << " }\n";
         }
-        for (int c = 0; c < nch; ++c) {
-            const Span& z = sp[c];
-            if (k < z.i || k > z.j) continue;
-            const std::string u = std::to_string(c);
-            if (wo[c] >= 0) {
-                if (k == z.j)
-                    body << "    const " << RT << " e" << u << " = W[" << wo[c] << " + (q" << z.i << " * " << S->d[z.i] << " + n"
-                         << z.i << ") * " << S->d[z.j] << " + n" << z.j << "];\n";
-                continue;
+        // segments that end at site k: (s, s + 1) with k = s + 1, or the single last site of an odd span
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const Span& z0 = sp[groups[g][0]];
+            if (k < z0.i || k > z0.j) continue;
+            const int s0 = z0.i + ((k - z0.i) / 2) * 2;
+            if (!(k == s0 + 1 || (k == s0 && k == z0.j))) continue;
+            const size_t segi = static_cast<size_t>((s0 - z0.i) / 2);
+            std::ostringstream idx;
+            idx << "((unsigned)q" << s0 << " * " << S->d[s0] << "u + (unsigned)n" << s0 << ")";
+            if (k == s0 + 1) idx << " * " << S->d[k] << "u + (unsigned)n" << k;
+            const std::string c0 = std::to_string(groups[g][0]);
+            if (groups[g].size() == 2) {
+                const std::string c1 = std::to_string(groups[g][1]);
+                body << "    { const U2 t = *(const U2*)&SEG[" << gso[g][segi] << "u + 2u * (" << idx.str() << ")]; e" << c0
+                     << " += t.x; e" << c1 << " += t.y; }\n";
+            } else {
+                body << "    e" << c0 << " += SEG[" << gso[g][segi] << "u + " << idx.str() << "];\n";
             }
-            // source remaining sum at sites after i: the target's plus the shift at site i
-            const std::string qs = "q" + K + " + (" + std::to_string(z.si) + ")";
-            if (k == z.i)
-                body << "    " << RT << " e" << u << " = " << rte(k, "q" + K, "n" + K + " - (" + std::to_string(z.si) + ")")
-                     << " - b" << K << ";\n";
-            else if (k < z.j)
-                body << "    e" << u << " += " << rte(k, qs, "n" + K) << " - b" << K << ";\n";
-            else
-                body << "    e" << u << " += " << rte(k, qs, "n" + K + " - (" + std::to_string(z.sj) + ")") << " - b" << K << ";\n";
         }
+        // gathers of the channels whose span ends at site k
         for (int c = 0; c < nch; ++c) {
             if (sp[c].j != k) continue;
             const DevChan& ch = S->chans[c];
             const std::string u = std::to_string(c);
-            body << "    const bool k" << u << " = (unsigned)(n" << ch.a << " - (" << ch.qa << ")) < " << S->d[ch.a]
-                 << "u && (unsigned)(n" << ch.b << " - (" << ch.qb << ")) < " << S->d[ch.b] << "u;\n"
-                 << "    const unsigned x" << u << " = (unsigned)n" << ch.a << " * " << S->d[ch.b] << "u + (unsigned)n" << ch.b
-                 << ";\n"
-                 << "    const C s" << u << " = LD(xs, k" << u << " ? (unsigned)((" << RT << ")r + e" << u << ") * " << SZ
-                 << "u : OOB);\n";
+            body << "    const unsigned x" << u << " = (unsigned)n" << ch.a << " * " << S->d[ch.b] << "u + (unsigned)n" << ch.b
+                 << ";\n";
+            if (sp[c].j == sp[c].i + 1) {
+                body << "    const C s" << u << " = LD(xs, rb + e" << u << ");\n";
+            } else {
+                body << "    const bool k" << u << " = (unsigned)(n" << ch.a << " - (" << ch.qa << ")) < " << S->d[ch.a]
+                     << "u && (unsigned)(n" << ch.b << " - (" << ch.qb << ")) < " << S->d[ch.b] << "u;\n"
+                     << "    const C s" << u << " = LD(xs, k" << u << " ? rb + e" << u << " : OOB);\n";
+            }
             pending.push_back(c);
             if (static_cast<int>(pending.size()) >= kGroup) flush(false);
         }
@@ -1699,7 +1732,8 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
          << "    ai += dr * xf.y + di * xf.x;\n";
     std::ostringstream o;
     o << "// generated sector kernel: " << N << " sites, digit sum " << Q << ", " << S->Dr << " packed states, " << ndg
-      << " diagonal terms in " << dkeys.size() << " tables, " << nch << " channels\n";
+      << " diagonal terms in " << dkeys.size() << " tables, " << nch << " channels in " << groups.size()
+      << " span groups, " << seg.size() << " rank-change table entries\n";
     if (f32)
         o << "typedef float R;\ntypedef float C __attribute__((ext_vector_type(2)));\n"
           << "typedef unsigned U __attribute__((ext_vector_type(2)));\n"
@@ -1710,18 +1744,15 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
           << "typedef unsigned U __attribute__((ext_vector_type(4)));\n"
           << "#define LD(rs, vo) __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128((rs), (int)(vo), 0, 0))\n"
           << "#define ST(v, rs, vo) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, (v)), (rs), (int)(vo), 0, 2)\n";
-    o << "#define OOB 0x80000000u\n"
+    o << "typedef unsigned U2 __attribute__((ext_vector_type(2)));\n"
+      << "#define OOB 0x80000000u\n"
       << "#ifndef MRMF_GROUP_FENCE\n"
       << "#define MRMF_GROUP_FENCE(a, b) __asm__ __volatile__(\"\" : \"+v\"(a), \"+v\"(b) : : \"memory\")\n"
       << "#endif\n";
-    o << "__constant__ " << RT << " RTC[" << prt.size() << "] = {";
-    for (size_t k = 0; k < prt.size(); ++k) o << (k ? ", " : "") << prt[k];
+    o << "__constant__ unsigned SEGC[" << std::max<size_t>(1, seg.size()) << "] = {";
+    if (seg.empty()) o << "0u";
+    for (size_t k = 0; k < seg.size(); ++k) o << (k ? ", " : "") << seg[k] << "u";
     o << "};\n";
-    if (!wtab.empty()) {
-        o << "__constant__ " << RT << " WTC[" << wtab.size() << "] = {";
-        for (size_t k = 0; k < wtab.size(); ++k) o << (k ? ", " : "") << wtab[k];
-        o << "};\n";
-    }
     auto arr = [&](const char* ty, const char* nm, size_t n, const std::function<std::string(size_t)>& f) {
         o << "__constant__ " << ty << " " << nm << "[" << std::max<size_t>(1, n) << "] = {";
         if (n == 0) o << "0";
@@ -1732,15 +1763,13 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     arr("int", "CP", cp.size(), [&](size_t k) { return std::to_string(cp[k]); });
     arr("R", "CVR", cvr.size(), [&](size_t k) { return lit(cvr[k], f32); });
     if (cplx) arr("R", "CVI", cvi.size(), [&](size_t k) { return lit(cvi[k], f32); });
+    const size_t nseg = std::max<size_t>(2, seg.size() + (seg.size() % 2));
     o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector(const R* __restrict__ theta,\n"
-      << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip) {\n"
+      << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip, const void* __restrict__ lab) {\n"
       << "  if (skip != nullptr && *skip != 0) return;\n"
-      << "  __shared__ " << RT << " L[" << prt.size() << "];\n"
-      << "  for (unsigned k = threadIdx.x; k < " << prt.size() << "u; k += 256u) L[k] = RTC[k];\n"
+      << "  __shared__ __attribute__((aligned(16))) unsigned SEG[" << nseg << "];\n"
+      << "  for (unsigned k = threadIdx.x; k < " << seg.size() << "u; k += 256u) SEG[k] = SEGC[k];\n"
       << "  __shared__ R Tr[" << NE << "];\n";
-    if (!wtab.empty())
-        o << "  __shared__ " << RT << " W[" << wtab.size() << "];\n"
-          << "  for (unsigned k = threadIdx.x; k < " << wtab.size() << "u; k += 256u) W[k] = WTC[k];\n";
     if (cplx) o << "  __shared__ R Ti[" << NE << "];\n";
     o << "  for (unsigned k = threadIdx.x; k < " << ent.size() << "u; k += 256u) {\n"
       << "    R sr = (R)0, si = (R)0;\n"
@@ -1753,15 +1782,15 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
       << ", 0x00020000);\n"
       << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)y, (short)0, " << S->Dr * SZ
       << ", 0x00020000);\n"
+      << "  const __amdgpu_buffer_rsrc_t ls = __builtin_amdgcn_make_buffer_rsrc((void*)lab, (short)0, "
+      << S->Dr * S->lab_bytes << ", 0x00020000);\n"
       // windows of G row groups of 256: the blocks of one XCD (block b runs on XCD b mod 8) take one eighth of
       // each window side by side, so the rows near a channel's source were just read through that XCD's L2
       << "  const unsigned G = gridDim.x, bk = blockIdx.x;\n"
       << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
-      << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n"
-      << "    int q = " << Q << ";\n"
-      << "    " << RT << " left = (" << RT << ")r;\n";
+      << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n";
     o << body.str()
-      << "    { C out; out.x = ar; out.y = ai; ST(out, ys, r * " << SZ << "u); }\n"
+      << "    { C out; out.x = ar; out.y = ai; ST(out, ys, rb); }\n"
       << "  }\n}\n";
     return o.str();
 }
@@ -2032,8 +2061,8 @@ mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
     return MRMF_OK;
 }
 
-mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
-                              const int32_t* d_skip) {
+mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* lab, const void* theta, const void* x, void* y,
+                              hipStream_t s, const int32_t* d_skip) {
     mrmf_status st = sector_gen_prepare(S, dtype);
     if (st != MRMF_OK) return st;
     const SpecKernel& K = S->gen[dtype];
@@ -2042,7 +2071,8 @@ mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, co
         const void* x;
         void* y;
         const int32_t* skip;
-    } args{theta, x, y, d_skip};
+        const void* lab;
+    } args{theta, x, y, d_skip, lab};
     size_t size = sizeof(args);
     void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
     return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));

@@ -180,6 +180,13 @@ struct mrmf_sector_t {
     size_t off_site = 0, off_chan = 0, off_diag = 0, off_val = 0, off_up = 0, off_lofs = 0, off_rt = 0, off_rto = 0;
     int32_t n_rt = 0;
     int64_t rt_max = 0;  // largest rank-table entry (32-bit LDS tables when below 2^31)
+    // packed digits of every sector state, filled on the device by mrmf_sector_upload after the image: row r's
+    // word (lab_bytes = 4 or 8 bytes) at off_lab + r lab_bytes holds site k's digit in lab_w[k] bits, site
+    // N - 1 in the lowest bits and site 0 in the highest (the words increase with r); lab_bytes = 0 when the
+    // sector has none (digits over 64 bits, 2^28 states or more, or a generic-mode plan)
+    std::vector<int32_t> lab_w;
+    int32_t lab_bytes = 0;
+    size_t off_lab = 0;
     size_t ws_bytes = 0;
     // host copies for the generated kernel: rank tables (site k at rto[k], entry (q, v) at q (d_k + 1) + v)
     // and the factor tables <n|O|n - q> of every term (diagonal terms, then channels; a then b, d entries
@@ -260,11 +267,12 @@ double local_factor_host(const mrmf_plan_t* p, int site, int op, int n);
 // (*grid: the blocks launched).  MRMF_E_UNSUPPORTED when the plan does not qualify.
 std::string grad_source(const mrmf_plan_t* p);
 // Sector kernel generated for one sector and element type (jit.cpp): "" when the sector does not qualify
-// (more than 64 sites, no terms, or a vector of 2^31 bytes or more); launch returns MRMF_E_UNSUPPORTED then.
+// (no packed digits, tables over their LDS budget, or a vector of 2^31 bytes or more); launch returns
+// MRMF_E_UNSUPPORTED then.  lab: the packed digits in the uploaded workspace.
 std::string sector_source(const mrmf_sector_t* S, int dtype);
 mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype);
-mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* theta, const void* x, void* y, hipStream_t s,
-                              const int32_t* d_skip);
+mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* lab, const void* theta, const void* x, void* y,
+                              hipStream_t s, const int32_t* d_skip);
 mrmf_status grad_prepare(mrmf_plan_t* p);
 // true when the plan's generated gradient kernel is already built for the current device (compiles nothing)
 bool grad_built(mrmf_plan_t* p);

@@ -251,6 +251,48 @@ __global__ __launch_bounds__(kSB) void k_sector_labels(SectorArgs a, const int64
     }
 }
 
+// Packed digits of every sector state (the table the generated kernel reads instead of unranking): the
+// digit of site k in w_k = bit width of d_k - 1 bits, site 0 highest, so the word of row r is the mixed-width
+// concatenation n_0 n_1 .. n_{N-1}.  L is uint32_t or uint64_t.
+template <typename L>
+__global__ __launch_bounds__(kSB) void k_sector_pack(SectorArgs a, L* __restrict__ out) {
+    for (int64_t r = int64_t(blockIdx.x) * kSB + threadIdx.x; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
+        int q = a.Q;
+        int64_t left = r;
+        L word = 0;
+        for (int k = 0; k < a.p.N; ++k) {
+            const int d = a.p.site[k].d;
+            const int vmax = q < d - 1 ? q : d - 1;
+            const int64_t* R = a.rt + a.rto[k] + int64_t(q) * (d + 1);
+            int v = 0;
+            while (v < vmax && R[v + 1] <= left) ++v;
+            left -= R[v];
+            q -= v;
+            const int w = d > 1 ? 32 - __clz(d - 1) : 0;
+            word = (word << w) | static_cast<L>(v);
+        }
+        out[r] = word;
+    }
+}
+
+// Full-basis index F = sum_k n_k M_k of packed rows r0 .. r0 + count - 1 from the packed digits.
+template <typename L>
+__global__ __launch_bounds__(kSB) void k_sector_labels_packed(SectorArgs a, const L* __restrict__ lab,
+                                                              const int64_t* __restrict__ M, int64_t r0,
+                                                              int64_t count, int64_t* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * kSB + threadIdx.x; i < count; i += int64_t(gridDim.x) * kSB) {
+        L word = lab[r0 + i];
+        int64_t F = 0;
+        for (int k = a.p.N - 1; k >= 0; --k) {
+            const int d = a.p.site[k].d;
+            const int w = d > 1 ? 32 - __clz(d - 1) : 0;
+            F += static_cast<int64_t>(word & ((L(1) << w) - 1)) * M[k];
+            word >>= w;
+        }
+        out[i] = F;
+    }
+}
+
 // Packed row of each full-basis index, or -1 when it is not a sector state (membership test).
 __global__ __launch_bounds__(kSB) void k_sector_lookup(SectorArgs a, int64_t D, const int64_t* __restrict__ F,
                                                        int64_t count, int64_t* __restrict__ out) {
@@ -296,7 +338,8 @@ mrmf_status sector_matvec(mrmf_sector_t* S, const void* d_ws, const R* theta, co
     // kernels below when the sector does not qualify for it
     if (S->mode != MRMF_KERNEL_GENERIC) {
         const int dtype = sizeof(R) == 8 ? MRMF_DTYPE_Z : MRMF_DTYPE_C;
-        const mrmf_status st = sector_gen_launch(S, dtype, theta, x, y, s, skip);
+        const mrmf_status st = sector_gen_launch(S, dtype, static_cast<const unsigned char*>(d_ws) + S->off_lab, theta,
+                                                 x, y, s, skip);
         if (st != MRMF_E_UNSUPPORTED) return st;
     }
     const bool rt32 = S->rt_max < (int64_t(1) << 31);
@@ -402,8 +445,23 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->n_rt = static_cast<int32_t>(rt.size());
     for (int64_t v : rt) S->rt_max = std::max(S->rt_max, v);
     S->off_rto = section(sizeof(int64_t) * N);
+    // packed digits of every state after the image, for the generated kernel (not in the host image: the
+    // upload fills them on the device)
+    const size_t img = off;
+    int bits = 0;
+    S->lab_w.assign(N, 0);
+    for (int k = 0; k < N; ++k) {
+        int w = 0;
+        while ((1 << w) < plan->d[k]) ++w;
+        S->lab_w[k] = w;
+        bits += w;
+    }
+    S->lab_bytes = 0;
+    if (S->mode != MRMF_KERNEL_GENERIC && bits <= 64 && S->Dr < (int64_t(1) << 28))
+        S->lab_bytes = bits <= 32 ? 4 : 8;
+    if (S->lab_bytes > 0) S->off_lab = section(size_t(S->lab_bytes) * size_t(S->Dr));
     S->ws_bytes = off;
-    S->image.assign(off, 0);
+    S->image.assign(img, 0);
     std::memcpy(S->image.data() + S->off_site, plan->image.data() + plan->off_site, sizeof(DevSite) * N);
     if (!S->chans.empty()) std::memcpy(S->image.data() + S->off_chan, S->chans.data(), sizeof(DevChan) * S->chans.size());
     if (!S->diags.empty()) std::memcpy(S->image.data() + S->off_diag, S->diags.data(), sizeof(DevDiag) * S->diags.size());
@@ -434,8 +492,19 @@ mrmf_status mrmf_sector_workspace_bytes(mrmf_sector sector, size_t* bytes) {
 mrmf_status mrmf_sector_upload(mrmf_sector sector, void* d_ws, size_t ws_bytes, mrmf_stream stream) {
     if (!sector || !d_ws || !aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
     if (ws_bytes < sector->ws_bytes) return MRMF_E_WORKSPACE;
-    return hip_status(hipMemcpyAsync(d_ws, sector->image.data(), sector->ws_bytes, hipMemcpyHostToDevice,
-                                     static_cast<hipStream_t>(stream)));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const mrmf_status st =
+        hip_status(hipMemcpyAsync(d_ws, sector->image.data(), sector->image.size(), hipMemcpyHostToDevice, s));
+    if (st != MRMF_OK || sector->lab_bytes == 0) return st;
+    // the packed digits, from the rank tables just copied
+    void* lab = static_cast<unsigned char*>(d_ws) + sector->off_lab;
+    if (sector->lab_bytes == 4)
+        hipLaunchKernelGGL(k_sector_pack<uint32_t>, dim3(sector_grid(sector->Dr)), dim3(kSB), 0, s,
+                           sector_args(sector, d_ws), static_cast<uint32_t*>(lab));
+    else
+        hipLaunchKernelGGL(k_sector_pack<uint64_t>, dim3(sector_grid(sector->Dr)), dim3(kSB), 0, s,
+                           sector_args(sector, d_ws), static_cast<uint64_t*>(lab));
+    return launch_status();
 }
 
 mrmf_status mrmf_sector_matvec_z(mrmf_sector sector, const void* d_ws, const double* d_theta, const void* d_x,
@@ -489,8 +558,18 @@ mrmf_status mrmf_sector_labels(mrmf_sector sector, const void* d_ws, int64_t r0,
     const mrmf_status st = hip_status(hipMemcpyAsync(d_scratch, sector->M.data(), sizeof(int64_t) * sector->N,
                                                      hipMemcpyHostToDevice, s));
     if (st != MRMF_OK) return st;
-    hipLaunchKernelGGL(k_sector_labels, dim3(sector_grid(count)), dim3(kSB), 0, s, sector_args(sector, d_ws),
-                       static_cast<const int64_t*>(d_scratch), r0, count, d_out);
+    const unsigned char* lab = static_cast<const unsigned char*>(d_ws) + sector->off_lab;
+    const dim3 grid(sector_grid(count)), block(kSB);
+    const SectorArgs a = sector_args(sector, d_ws);
+    const int64_t* M = static_cast<const int64_t*>(d_scratch);
+    if (sector->lab_bytes == 4)
+        hipLaunchKernelGGL(k_sector_labels_packed<uint32_t>, grid, block, 0, s, a,
+                           reinterpret_cast<const uint32_t*>(lab), M, r0, count, d_out);
+    else if (sector->lab_bytes == 8)
+        hipLaunchKernelGGL(k_sector_labels_packed<uint64_t>, grid, block, 0, s, a,
+                           reinterpret_cast<const uint64_t*>(lab), M, r0, count, d_out);
+    else
+        hipLaunchKernelGGL(k_sector_labels, grid, block, 0, s, a, M, r0, count, d_out);
     return launch_status();
 }
 

@@ -60,7 +60,8 @@ void emu_check(const void* p, size_t n, const char* what) {
 extern "C" void mrmf_spec(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
 extern "C" void mrmf_grad(const double* theta, const void* x, const void* g, void* gx, double* partial)
     __attribute__((weak));
-extern "C" void mrmf_sector(const void* theta, const void* x, void* y, const int* skip) __attribute__((weak));
+extern "C" void mrmf_sector(const void* theta, const void* x, void* y, const int* skip, const void* lab)
+    __attribute__((weak));
 extern "C" void mrmf_spec_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
                                double ecr, double eci, const int* skip) __attribute__((weak));
 
@@ -82,7 +83,8 @@ struct GradCall {
     const void* g = nullptr;
     double* partial = nullptr;
 } g_grad;
-bool g_sector = false;  // the launch runs the generated sector kernel
+bool g_sector = false;        // the launch runs the generated sector kernel
+const void* g_lab = nullptr;  // its packed-digit table
 // One host thread per GPU thread of the block, kept for every block of the range; a block barrier
 // separates consecutive blocks (their __shared__ storage is the same static storage).
 void* thread_main(void* a) {
@@ -91,7 +93,7 @@ void* thread_main(void* a) {
     for (unsigned b = g->b0; b < g->b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
         if (g_sector)
-            mrmf_sector(g->theta, g->x, g->y, nullptr);
+            mrmf_sector(g->theta, g->x, g->y, nullptr, g_lab);
         else if (g_grad.on)
             mrmf_grad(static_cast<const double*>(g->theta), g->x, g_grad.g, g->y, g_grad.partial);
         else if (g_cheb.cheb)
@@ -180,11 +182,16 @@ extern "C" int emu_run_grad(unsigned grid, const void* theta, size_t theta_bytes
     return rc;
 }
 
-// The generated sector kernel over all `grid` blocks of 256 threads (packed vectors x, y).
+// The generated sector kernel over all `grid` blocks of 256 threads (packed vectors x, y; lab: the packed
+// digits of every state, lab_bytes bytes).
 extern "C" int emu_run_sector(unsigned grid, const void* theta, size_t theta_bytes, const void* x, size_t x_bytes,
-                              void* y, size_t y_bytes) {
+                              void* y, size_t y_bytes, const void* lab, size_t lab_bytes) {
     g_sector = true;
+    g_lab = lab;
+    g_extra = {static_cast<const char*>(lab), lab_bytes, "lab"};
     const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, y, y_bytes, 0, 0);
     g_sector = false;
+    g_lab = nullptr;
+    g_extra = {nullptr, 0, ""};
     return rc;
 }

@@ -138,6 +138,7 @@ inline void emu_store(V v, emu_rsrc r, int vo, int so) {
 }
 
 #define __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, aux) emu_load<emu_u4>((r), (vo), (so))
+#define __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, aux) emu_load<unsigned>((r), (vo), (so))
 #define __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, aux) emu_load<emu_u2>((r), (vo), (so))
 #define __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, aux) emu_store<emu_u4>((v), (r), (vo), (so))
 #define __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, aux) emu_store<emu_u2>((v), (r), (vo), (so))

@@ -79,7 +79,7 @@ def _compile(src: str) -> ctypes.CDLL:
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_sector.restype = ctypes.c_int
     lib.emu_run_sector.argtypes = [ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
-                                   ctypes.c_void_p, ctypes.c_size_t]
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t]
     lib.emu_run_cheb.restype = ctypes.c_int
     lib.emu_run_cheb.argtypes = ([ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
@@ -177,6 +177,23 @@ def sector_source(model, digit_sum: int, dtype: int) -> str | None:
         L.lib().mrmf_plan_destroy(h)
 
 
+def packed_digits(model, digit_sum: int) -> np.ndarray:
+    """The packed-digit table the generated sector kernel reads (the sector's states in packed-row order, site
+    k's digit in bit_length(d_k - 1) bits, site N - 1 lowest), built from the sector oracle's enumeration."""
+    from oracle import sector as osec
+    lab = osec.labels(model, digit_sum)
+    dims = [s.d for s in model.sites]
+    w = [(d - 1).bit_length() for d in dims]
+    word = np.dtype(np.uint32 if sum(w) <= 32 else np.uint64)
+    digits = np.unravel_index(lab, dims)
+    out = np.zeros(lab.size, dtype=np.uint64)
+    shift = 0
+    for k in range(len(dims) - 1, -1, -1):
+        out |= digits[k].astype(np.uint64) << np.uint64(shift)
+        shift += w[k]
+    return out.astype(word)
+
+
 def run_sector(model, digit_sum: int, x: np.ndarray, grid: int) -> np.ndarray:
     """y = P H P^T x on the packed sector vector x with the generated sector kernel, emulated on the CPU."""
     f32 = x.dtype == np.complex64
@@ -187,7 +204,9 @@ def run_sector(model, digit_sum: int, x: np.ndarray, grid: int) -> np.ndarray:
     th = np.ascontiguousarray(model.theta, dtype=np.float32 if f32 else np.float64)
     xx = np.ascontiguousarray(x)
     y = np.full_like(xx, np.nan)
-    rc = lib.emu_run_sector(grid, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data, y.nbytes)
+    lab = packed_digits(model, digit_sum)
+    rc = lib.emu_run_sector(grid, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, y.ctypes.data, y.nbytes,
+                            lab.ctypes.data, lab.nbytes)
     if rc != 0:
         raise RuntimeError(f"emu_run_sector failed: {rc}")
     return y

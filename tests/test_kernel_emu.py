@@ -251,3 +251,28 @@ def test_sector_kernel(seed):
         x32 = x.astype(np.complex64)
         y32 = E.run_sector(m, Q, x32, 2)
         assert rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128), lab=lab)) <= TOL_C
+
+
+@pytest.mark.parametrize("case", ["odd_ring", "wide_words"])
+def test_sector_kernel_spans_and_words(case):
+    """The generated sector kernel's two remaining layouts: a ring of odd length, whose closing bond spans
+    an odd number of sites (its rank change ends with a one-site segment), and 11 spin-2 sites, whose
+    packed digits take 33 bits (8-byte words)."""
+    from oracle import sector as osec
+    rng = np.random.default_rng(7900)
+    if case == "odd_ring":
+        m = W.staggered_xxz_ring([1, 2, 1, 2, 1, 2, 2], jxy=0.8, jz=1.1, h=0.3)
+        qs = (4, 5)
+    else:
+        m = W.staggered_xxz_ring([4] * 11, jxy=0.9, jz=0.7, h=0.2)
+        qs = (2, 3)
+    for Q in qs:
+        lab = osec.labels(m, Q)
+        assert E.packed_digits(m, Q).dtype == (np.uint64 if case == "wide_words" else np.uint32)
+        x = W.random_state(lab.size, rng)
+        ref = osec.matvec(m, Q, x, lab=lab)
+        for grid in (1, 8):
+            assert rel_err(E.run_sector(m, Q, x, grid), ref) <= TOL_Z, (Q, grid)
+        x32 = x.astype(np.complex64)
+        y32 = E.run_sector(m, Q, x32, 2)
+        assert rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128), lab=lab)) <= TOL_C
