@@ -1635,7 +1635,7 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     }
     if (seg.size() * 4 > 40 * 1024) return "";
 
-    const int kGroup = S->group > 0 ? S->group : 10;
+    const int kGroup = S->group > 0 ? S->group : 16;
     std::vector<int> pending;
     std::ostringstream body;
     auto flush = [&](bool last) {
