@@ -165,6 +165,8 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *                                                   super-tiles with its blocks side by side;
  *                             MRMF_SCHED_BLOCK_RUN - each block sweeps its own contiguous run of
  *                                                   super-tiles (runs of one XCD adjacent).
+ *                             A sector made from the plan afterwards schedules its generated kernel's
+ *                             groups of 256 rows the same way.
  *   MRMF_TUNE_BRANCH_SKIP   : 1 = a channel whose tile-uniform source digits are inadmissible is skipped
  *                             by a scalar branch; 0 = its loads are issued and masked.
  *   MRMF_TUNE_LOAD_GROUP    : channels whose gathers are issued ahead of their accumulation (0 = default);

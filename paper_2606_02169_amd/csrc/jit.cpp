@@ -1784,11 +1784,29 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
       << ", 0x00020000);\n"
       << "  const __amdgpu_buffer_rsrc_t ls = __builtin_amdgcn_make_buffer_rsrc((void*)lab, (short)0, "
       << S->Dr * S->lab_bytes << ", 0x00020000);\n"
-      // windows of G row groups of 256: the blocks of one XCD (block b runs on XCD b mod 8) take one eighth of
-      // each window side by side, so the rows near a channel's source were just read through that XCD's L2
-      << "  const unsigned G = gridDim.x, bk = blockIdx.x;\n"
-      << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
-      << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n";
+      << "  const unsigned G = gridDim.x, bk = blockIdx.x;\n";
+    const int64_t ng = (S->Dr + 255) / 256;  // row groups of 256
+    if (S->sched == MRMF_SCHED_XCD_CHUNK) {
+        // XCD x (= block mod 8) sweeps the contiguous x-th eighth of the row groups with its blocks side by side
+        o << "  const unsigned nx = (G % 8u == 0u) ? 8u : 1u, GX = G / nx, xcd = bk % nx;\n"
+          << "  const unsigned Cx = (" << ng << "u + nx - 1u) / nx;\n"
+          << "  const unsigned g_end = (xcd + 1u) * Cx < " << ng << "u ? (xcd + 1u) * Cx : " << ng << "u;\n"
+          << "  for (unsigned g = xcd * Cx + bk / nx; g < g_end; g += GX) {\n"
+          << "    const unsigned r = g * 256u + threadIdx.x;\n"
+          << "    if (r >= " << S->Dr << "u) break;\n";
+    } else if (S->sched == MRMF_SCHED_BLOCK_RUN) {
+        // every block sweeps its own contiguous run of row groups (the runs of one XCD adjacent)
+        o << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
+          << "  const unsigned g_end = (unsigned)(((unsigned long long)(v + 1u) * " << ng << "ull) / G);\n"
+          << "  for (unsigned g = (unsigned)(((unsigned long long)v * " << ng << "ull) / G); g < g_end; ++g) {\n"
+          << "    const unsigned r = g * 256u + threadIdx.x;\n"
+          << "    if (r >= " << S->Dr << "u) break;\n";
+    } else {
+        // windows of G row groups: the blocks of one XCD (block b runs on XCD b mod 8) take one eighth of each
+        // window side by side, so the rows near a channel's source were just read through that XCD's L2
+        o << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
+          << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n";
+    }
     o << body.str()
       << "    { C out; out.x = ar; out.y = ai; ST(out, ys, rb); }\n"
       << "  }\n}\n";

@@ -196,6 +196,7 @@ struct mrmf_sector_t {
     int32_t mode = MRMF_KERNEL_AUTO;  // the plan's kernel selection when the sector was made
     int32_t blocks_per_cu = 0;        // blocks per CU of the generated kernel's grid (0: as many as fit)
     int32_t group = 0;                // gathers issued together by the generated kernel (0: default)
+    int32_t sched = 0;                // MRMF_SCHED_* of the generated kernel's rows over the XCDs
     mrmf::SpecKernel gen[2];          // generated sector kernels, c128 and c64
     std::mutex mtx;
     ~mrmf_sector_t();

@@ -417,6 +417,7 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->mode = plan->cfg[MRMF_DTYPE_Z].mode;
     S->blocks_per_cu = plan->cfg[MRMF_DTYPE_Z].blocks_per_cu;
     S->group = plan->cfg[MRMF_DTYPE_Z].group;
+    S->sched = plan->cfg[MRMF_DTYPE_Z].sched;
     auto add_fac = [&](int site, int op) {
         for (int n = 0; n < plan->d[site]; ++n) S->tfac.push_back(local_factor_host(plan, site, op, n));
     };

@@ -159,11 +159,13 @@ def run_grad(model, x: np.ndarray, g: np.ndarray, grid: int):
     return gx, part
 
 
-def sector_source(model, digit_sum: int, dtype: int) -> str | None:
+def sector_source(model, digit_sum: int, dtype: int, tuning=None) -> str | None:
     st, h = host_plan(model)
     assert st == 0, st
     s = ctypes.c_void_p()
     try:
+        for k, v in (tuning or {}).items():
+            L.call("mrmf_plan_set_tuning", h, TUNING[k], int(v))
         L.call("mrmf_sector_create", h, int(digit_sum), ctypes.byref(s))
         n = ctypes.c_size_t()
         if L.lib().mrmf_sector_kernel_source(s, dtype, None, 0, ctypes.byref(n)) != 0:
@@ -194,10 +196,10 @@ def packed_digits(model, digit_sum: int) -> np.ndarray:
     return out.astype(word)
 
 
-def run_sector(model, digit_sum: int, x: np.ndarray, grid: int) -> np.ndarray:
+def run_sector(model, digit_sum: int, x: np.ndarray, grid: int, tuning=None) -> np.ndarray:
     """y = P H P^T x on the packed sector vector x with the generated sector kernel, emulated on the CPU."""
     f32 = x.dtype == np.complex64
-    src = sector_source(model, digit_sum, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z)
+    src = sector_source(model, digit_sum, L.MRMF_DTYPE_C if f32 else L.MRMF_DTYPE_Z, tuning)
     if src is None:
         raise ValueError("the sector does not qualify for the generated kernel")
     lib = _compile(src)

@@ -7,6 +7,7 @@ import pytest
 
 import workloads as W
 from oracle import mf
+from paper_2606_02169_amd import _lib as L
 from tests import kernel_emu as E
 from tests.helpers import rel_err
 
@@ -248,6 +249,11 @@ def test_sector_kernel(seed):
         for grid in ((lab.size + 255) // 256, 1, 8):
             y = E.run_sector(m, Q, x, grid)
             assert rel_err(y, ref) <= TOL_Z, (Q, grid)
+        # the other two row schedules over the XCDs (8 blocks: one per XCD; 16: two per XCD; 3: no XCD split)
+        for sched in (L.MRMF_SCHED_XCD_CHUNK, L.MRMF_SCHED_BLOCK_RUN):
+            for grid in (3, 8, 16):
+                y = E.run_sector(m, Q, x, grid, tuning={"schedule": sched})
+                assert rel_err(y, ref) <= TOL_Z, (Q, sched, grid)
         x32 = x.astype(np.complex64)
         y32 = E.run_sector(m, Q, x32, 2)
         assert rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128), lab=lab)) <= TOL_C
