@@ -478,9 +478,11 @@ mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t tile_rows_max, int32_
  * lattice): MRMF_BATCH_SCHED_RUNS (default) - each block takes a contiguous run of items, the runs of
  * one XCD adjacent; MRMF_BATCH_SCHED_WINDOWS - the grid sweeps windows of consecutive items, each XCD
  * taking one eighth of every window, so that the items one XCD holds at a time are neighbours (their
- * cross-tile gathers meet in that XCD's L2).  Results are identical. */
+ * cross-tile gathers meet in that XCD's L2); MRMF_BATCH_SCHED_XCD_CHUNK - each XCD sweeps its own
+ * contiguous eighth of the items with its blocks side by side.  Results are identical. */
 #define MRMF_BATCH_SCHED_RUNS 0
 #define MRMF_BATCH_SCHED_WINDOWS 1
+#define MRMF_BATCH_SCHED_XCD_CHUNK 2
 mrmf_status mrmf_batch_set_schedule(mrmf_batch batch, int32_t sched);
 /* Host out[0..3] = (tile-row limit, block threads, schedule, grid blocks) of the current launch shape. */
 mrmf_status mrmf_batch_get_shape(mrmf_batch batch, int32_t* out);

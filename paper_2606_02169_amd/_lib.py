@@ -37,7 +37,7 @@ MRMF_TUNE_UNROLL_TOP = 11
 MRMF_TUNE_FAR_DIR = 12
 MRMF_SOURCE_CHEB = 2
 MRMF_SOURCE_GRAD = 3
-MRMF_BATCH_SCHED_RUNS, MRMF_BATCH_SCHED_WINDOWS = 0, 1
+MRMF_BATCH_SCHED_RUNS, MRMF_BATCH_SCHED_WINDOWS, MRMF_BATCH_SCHED_XCD_CHUNK = 0, 1, 2
 MRMF_SCHED_WINDOWS, MRMF_SCHED_XCD_CHUNK, MRMF_SCHED_BLOCK_RUN = 0, 1, 2
 
 

@@ -145,10 +145,22 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const int64_t I = ibeg[A.n_lat];
     const unsigned G = gridDim.x, bid = blockIdx.x;
     const unsigned v = (G % 8u == 0u) ? (bid % 8u) * (G / 8u) + bid / 8u : bid;
-    const bool windows = sched == 1;
-    const int32_t i0 = windows ? static_cast<int32_t>(v) : static_cast<int32_t>(int64_t(v) * I / G);
-    const int32_t i1 = windows ? static_cast<int32_t>(I) : static_cast<int32_t>(int64_t(v + 1) * I / G);
-    const int32_t step = windows ? static_cast<int32_t>(G) : 1;
+    int32_t i0, i1, step;
+    if (sched == 1) {  // windows
+        i0 = static_cast<int32_t>(v);
+        i1 = static_cast<int32_t>(I);
+        step = static_cast<int32_t>(G);
+    } else if (sched == 2) {  // XCD x sweeps the x-th eighth of the items with its blocks side by side
+        const unsigned nx = (G % 8u == 0u) ? 8u : 1u, xcd = bid % nx;
+        const int64_t C = (I + nx - 1) / nx;
+        i0 = static_cast<int32_t>(xcd * C + bid / nx);
+        i1 = static_cast<int32_t>((xcd + 1) * C < I ? (xcd + 1) * C : I);
+        step = static_cast<int32_t>(G / nx);
+    } else {  // runs
+        i0 = static_cast<int32_t>(int64_t(v) * I / G);
+        i1 = static_cast<int32_t>(int64_t(v + 1) * I / G);
+        step = 1;
+    }
     // the current lattice's descriptor, kept in scalar registers (every field is block-uniform)
     int lb = -1;
     int32_t N = 0, n_chan = 0, n_diag = 0, D = 0, rows = 1, ks = 0, n_loc = 0;
@@ -595,7 +607,9 @@ mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t tile_rows_max, int32_t bl
 }
 
 mrmf_status mrmf_batch_set_schedule(mrmf_batch b, int32_t sched) {
-    if (!b || (sched != MRMF_BATCH_SCHED_RUNS && sched != MRMF_BATCH_SCHED_WINDOWS)) return MRMF_E_INVALID_ARG;
+    if (!b || (sched != MRMF_BATCH_SCHED_RUNS && sched != MRMF_BATCH_SCHED_WINDOWS &&
+               sched != MRMF_BATCH_SCHED_XCD_CHUNK))
+        return MRMF_E_INVALID_ARG;
     b->sched = sched;
     return MRMF_OK;
 }
@@ -624,8 +638,8 @@ mrmf_status mrmf_batch_autotune(mrmf_batch b, const void* d_ws, const float* d_t
     float best = 0.f;
     int best_i = -1;
     const int32_t R0 = b->rc, B0 = b->block, S0 = b->sched;
-    // candidates: every shape with the runs schedule, then every shape with the windows schedule
-    for (int i = 0; i < 2 * mrmf::kNumShapes && st == MRMF_OK; ++i) {
+    // candidates: every shape with the runs schedule, then with the windows schedule, then per-XCD chunks
+    for (int i = 0; i < 3 * mrmf::kNumShapes && st == MRMF_OK; ++i) {
         b->rc = mrmf::kShapes[i % mrmf::kNumShapes].rc;
         b->block = mrmf::kShapes[i % mrmf::kNumShapes].block;
         b->sched = i / mrmf::kNumShapes;

@@ -453,16 +453,19 @@ class Batch:
     def set_shape(self, tile_rows_max: int, block: int, schedule: str | None = None):
         """Launch shape: tiles of at most tile_rows_max rows ((64, 128, 256, 512) * 8 / nvec), block
         threads (a multiple of 64, at most 512 and 4096 / nvec) and, when given, the work schedule
-        ("runs": a contiguous run of items per block; "windows": consecutive items side by side)."""
+        ("runs": a contiguous run of items per block; "windows": consecutive items side by side;
+        "xcd_chunk": each XCD its own eighth of the items, its blocks side by side)."""
         L.call("mrmf_batch_set_shape", self._handle, int(tile_rows_max), int(block))
         if schedule is not None:
             L.call("mrmf_batch_set_schedule", self._handle,
-                   {"runs": L.MRMF_BATCH_SCHED_RUNS, "windows": L.MRMF_BATCH_SCHED_WINDOWS}[schedule])
+                   {"runs": L.MRMF_BATCH_SCHED_RUNS, "windows": L.MRMF_BATCH_SCHED_WINDOWS,
+                    "xcd_chunk": L.MRMF_BATCH_SCHED_XCD_CHUNK}[schedule])
 
     def shape(self) -> dict:
         out = (ctypes.c_int32 * 4)()
         L.call("mrmf_batch_get_shape", self._handle, out)
-        return dict(tile_rows_max=out[0], block=out[1], schedule=("runs", "windows")[out[2]], grid=out[3])
+        return dict(tile_rows_max=out[0], block=out[1], schedule=("runs", "windows", "xcd_chunk")[out[2]],
+                    grid=out[3])
 
 
 def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, theta_c, keep_basis) -> dict:

@@ -116,7 +116,7 @@ def test_batch_full_size_sampled():
             assert rel_err(yb[r, v], ref) <= TOL_C, (b, v)
 
 
-@pytest.mark.parametrize("schedule", ["runs", "windows"])
+@pytest.mark.parametrize("schedule", ["runs", "windows", "xcd_chunk"])
 @pytest.mark.parametrize("rmax,block", [(64, 64), (128, 128), (512, 256), (512, 512), (256, 512)])
 def test_batch_every_shape(rmax, block, schedule):
     """Each launch shape (tiles of at most rmax rows held in LDS, block threads, work schedule) gives the
