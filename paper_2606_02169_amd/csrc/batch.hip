@@ -10,13 +10,14 @@
 // Work.  For a launch shape (R_max, block B), lattice b's rows are cut into tiles spanned by its low
 // sites (T_b = prod of the low d_i, the largest such product <= R_max), and an item is the P = max(1,
 // B / T_b) consecutive tiles that one block holds in LDS at a time (rows stored vector-major, so that
-// consecutive threads read consecutive 8-byte words).  Items are numbered lattice by lattice.  Two
+// consecutive threads read consecutive 8-byte words).  Items are numbered lattice by lattice.  Three
 // schedules: runs - block v of the grid takes the contiguous item range [v I / G, (v+1) I / G), v chosen
 // so that the blocks of one XCD (block b runs on XCD b mod 8) hold neighbouring ranges; windows - the
 // grid sweeps windows of G consecutive items, the blocks of one XCD taking one eighth of each window side
 // by side, so that the items an XCD works on at one time are neighbours and the gathers of one item find
 // the rows its neighbours have just read in the XCD's L2 (at the price of reloading a lattice's
-// descriptors whenever a block moves to another lattice).  Every thread owns rows of the item; for each
+// descriptors whenever a block moves to another lattice); XCD chunks - XCD x sweeps the x-th eighth of
+// the items with its blocks side by side, so that its L2 also holds the rows it read further back.  Every thread owns rows of the item; for each
 // row it decodes the digits once into LDS, then for every channel forms the coefficient from the
 // per-site factor tables (zero where a source digit is inadmissible, App. A) and, where it is nonzero,
 // reads the nvec source amplitudes of row F - Delta: from LDS when both sites of the channel lie in the
