@@ -4,12 +4,13 @@
 // option of Sec. VI.B) instead of a search or a hash: with C_k(q) the number of digit tuples of sites
 // k..N-1 summing to q and R_k(q, v) = sum_{v' < v} C_{k+1}(q - v'),
 //     rank(n_0 .. n_{N-1}) = sum_k R_k(Q_k, n_k),     Q_0 = Q,  Q_{k+1} = Q_k - n_k,
-// and unranking walks the same tables site by site.  A target row is unranked once; the source of a
-// channel on sites i < j differs from the target only in n_i, n_j and in the remaining sums Q_k for
-// i < k <= j, so its rank is the target's plus the change of those j - i + 1 table terms: no search and
-// no table of labels in memory.  A channel that changes the digit sum has no source in the sector (the
-// failed membership test of Sec. VI.B) and is dropped when the sector is built; one-site ladder channels
-// are such channels.
+// and unranking walks the same tables site by site.  The source of a channel on sites i < j differs from
+// the target only in n_i, n_j and in the remaining sums Q_k for i < k <= j, so its rank is the target's
+// plus the change of those j - i + 1 table terms: no search and no table of labels to search.  The
+// generic kernels here unrank each target row; the kernel generated for the sector (jit.cpp) reads the
+// target's digits from a word per state that k_sector_pack writes into the workspace at upload.  A
+// channel that changes the digit sum has no source in the sector (the failed membership test of
+// Sec. VI.B) and is dropped when the sector is built; one-site ladder channels are such channels.
 #include <algorithm>
 #include <cstring>
 #include <vector>
