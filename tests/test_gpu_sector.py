@@ -58,6 +58,34 @@ def test_sector_random_models(seed, kind):
     assert rel_err(y32, ref32) <= TOL_C
 
 
+@pytest.mark.parametrize("case", ["odd_ring", "wide_words"])
+def test_sector_packed_digit_layouts(case):
+    """The generated kernel's packed digits in both word sizes, through the upload and mrmf_sector_labels
+    (bit-exact), and its matvec against the oracle: a 7-site mixed ring (closing bond over an odd span,
+    4-byte words) and 11 spin-2 sites (33 bits of digits, 8-byte words)."""
+    rng = np.random.default_rng(6400)
+    if case == "odd_ring":
+        m = W.staggered_xxz_ring([1, 2, 1, 2, 1, 2, 2], jxy=0.8, jz=1.1, h=0.3)
+        qs = (4, 5)
+    else:
+        m = W.staggered_xxz_ring([4] * 11, jxy=0.9, jz=0.7, h=0.2)
+        qs = (2, 3, 6)
+    for Q in qs:
+        lab = osec.labels(m, Q)
+        S = sector(m, Q)
+        print(f"{case} Q={Q} Dr={lab.size}", flush=True)
+        assert S.dim == lab.size and S.generated() and S.generated(torch.complex64)
+        assert np.array_equal(S.labels().cpu().numpy(), lab)
+        x = W.random_state(lab.size, rng)
+        y = S.matvec(t(m.theta), t(x)).cpu().numpy()
+        assert rel_err(y, osec.matvec(m, Q, x, lab=lab)) <= TOL_Z
+        x32 = x.astype(np.complex64)
+        y32 = S.matvec(t(m.theta.astype(np.float32)), t(x32)).cpu().numpy()
+        ref32 = osec.matvec(m, Q, x32.astype(np.complex128), theta=m.theta.astype(np.float32).astype(np.float64),
+                            lab=lab)
+        assert rel_err(y32, ref32) <= TOL_C
+
+
 def test_app_d_lookup_example_on_gpu():
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lookup_toy_N4_M0.json")))
     N, J = g["n_sites"], 1.7
