@@ -369,7 +369,8 @@ def bench_lanczos(args, dev):
         res = r["result"].cpu().numpy()
         k = int(res[3])
         out = dict(theta=float(res[0]), resid=float(res[2]), steps=k, seconds=dt,
-                   alpha=r["alpha"].cpu().numpy()[:k], beta=r["beta"].cpu().numpy()[:k])
+                   alpha=r["alpha"].cpu().numpy()[:k], beta=r["beta"].cpu().numpy()[:k],
+                   passes=[int(c) for c in r["counts"].cpu().numpy()])
         if certify and not args.profile:
             u = r["u"].cpu().numpy()
             del r
@@ -391,7 +392,9 @@ def bench_lanczos(args, dev):
     m = args.lanczos_steps
     for name, plan, prec, ro in (("fp64", pz, "z", "cgs2"), ("fp32_in_fp64", pc, "c_in_z", "cgs2"),
                                  ("fp64_cgs2_cond", pz, "z", "cgs2_cond"),
-                                 ("fp32_in_fp64_cgs2_cond", pc, "c_in_z", "cgs2_cond")):
+                                 ("fp32_in_fp64_cgs2_cond", pc, "c_in_z", "cgs2_cond"),
+                                 ("fp64_partial", pz, "z", "partial"),
+                                 ("fp32_in_fp64_partial", pc, "c_in_z", "partial")):
         full = run(plan, prec, m, ro, certify=True)
         curve = ritz_curve(full["alpha"], full["beta"], full["steps"])
         rel = np.abs(curve - E_ref) / abs(E_ref)
@@ -403,7 +406,10 @@ def bench_lanczos(args, dev):
             "residual": full["resid"], "oracle_residual": full.get("oracle_residual"), "seconds": full["seconds"],
             "steps_to_1e-5": k5, "seconds_to_1e-5": timed["seconds"] if timed else None,
             "rel_err_at_1e-5_run": (abs(timed["theta"] - E_ref) / abs(E_ref)) if timed else None,
-            "matvec_ms": mv_z if prec == "z" else mv_c}
+            "matvec_ms": mv_z if prec == "z" else mv_c,
+            # second passes taken (cgs2_cond) or passes taken (partial); cgs2 takes two at every step
+            "gram_schmidt_passes": (full["passes"][0] if ro == "cgs2_cond" else
+                                    full["passes"][1] if ro == "partial" else None)}
         log(f"{name}: {out['forms'][name]}")
     nz = run(pz, "z", m, reorth="none")
     nc = run(pc, "c_in_z", m, reorth="none")
@@ -434,7 +440,8 @@ def bench_lanczos_ring(args, dev):
            "workload": "ferrimagnetic_ring_N20_c128", "D": D, "seed": 2, "steps": m,
            "basis_GB": (m + 1) * D * 16 / 1e9, "forms": {}}
     for name, prec, ro in (("fp64", "z", "cgs2"), ("fp32_in_fp64", "c_in_z", "cgs2"),
-                           ("fp64_cgs2_cond", "z", "cgs2_cond"), ("fp32_in_fp64_cgs2_cond", "c_in_z", "cgs2_cond")):
+                           ("fp64_cgs2_cond", "z", "cgs2_cond"), ("fp32_in_fp64_cgs2_cond", "c_in_z", "cgs2_cond"),
+                           ("fp64_partial", "z", "partial"), ("fp32_in_fp64_partial", "c_in_z", "partial")):
         plan = Plan.from_model(model, device=dev)
         y = torch.empty_like(v0)
         plan.autotune(th64, v0, y)
@@ -449,11 +456,16 @@ def bench_lanczos_ring(args, dev):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = r["result"].cpu().numpy()
-        u = r["u"].cpu().numpy() if (ro == "cgs2" and not args.profile) else None
+        passes = [int(c) for c in r["counts"].cpu().numpy()]
+        u = r["u"].cpu().numpy() if (ro in ("cgs2", "partial") and not args.profile) else None
         del r
         torch.cuda.empty_cache()
         out["forms"][name] = {"reorth": ro, "seconds": dt, "ms_per_step": dt / max(1, int(res[3])) * 1e3, "E0": float(res[0]),
                               "residual": float(res[2]), "steps": int(res[3])}
+        if ro == "cgs2_cond":
+            out["forms"][name]["second_passes"] = passes[0]
+        elif ro == "partial":
+            out["forms"][name]["gram_schmidt_passes"] = passes[1]
         if u is not None:
             ro_res, nu = oracle_residual(model, u, float(res[0]))
             del u

@@ -101,6 +101,9 @@ typedef struct {
 #define MRMF_REORTH_CGS2_COND 2 /* full: classical Gram-Schmidt, the second pass only when the first
                                    one shrank ||w|| by more than 1/sqrt(2) (Daniel, Gragg, Kaufman and
                                    Stewart's criterion; the decision is taken on the device) */
+#define MRMF_REORTH_PARTIAL 3   /* partial (Simon 1984): the loss of orthogonality is estimated from
+                                   alpha and beta, and one Gram-Schmidt pass against all of V runs only
+                                   at the steps where an estimate passes sqrt(eps) and the step after */
 
 /* ---------------------------------------------------------------------------------------------- */
 /* Status text ("ok", "invalid argument", ...).  Static storage; never NULL. */
@@ -321,12 +324,15 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
 /* Device-resident Lanczos driving the matvec (the Krylov use of x -> H x, Sec. I).
  * Step j: w = H v_j; alpha_j = Re<v_j|w>; w -= alpha_j v_j + beta_{j-1} v_{j-1};
  * (MRMF_REORTH_CGS2) twice c = V^H w, w -= V c; (MRMF_REORTH_CGS2_COND) once, and a second time only
- * if that pass left ||w||^2 below half its value before it; beta_j = ||w||;
+ * if that pass left ||w||^2 below half its value before it; (MRMF_REORTH_PARTIAL) once, only where
+ * Simon's recurrence for the inner products <v_i|v_k> estimates one of them above sqrt(eps) and at the
+ * step after such a step (the basis stays semi-orthogonal: every |<v_i|v_k>| up to about sqrt(eps));
+ * beta_j = ||w||;
  * stop when beta_j <= 1e-14 * ||T|| (Gershgorin estimate);
  * v_{j+1} = w / beta_j.  Then the lowest eigenpair (theta, s) of the k x k tridiagonal T (bisection
  * and inverse iteration on the GPU), the Ritz vector u = V s, and the explicit residual
  * ||H u - theta u|| with the FP64 matvec.
- *   reorth   : MRMF_REORTH_CGS2, MRMF_REORTH_CGS2_COND or MRMF_REORTH_NONE
+ *   reorth   : MRMF_REORTH_CGS2, MRMF_REORTH_CGS2_COND, MRMF_REORTH_PARTIAL or MRMF_REORTH_NONE
  *   precision: MRMF_PREC_Z, or MRMF_PREC_C_IN_Z (then d_theta_c float[n_params] is required and the
  *              matvec runs in c64 on a c64 copy of v_j; everything else stays FP64)
  *   d_v0     : c128[D] start vector (normalised internally; zero norm -> steps = 0, theta = NaN)
@@ -339,6 +345,10 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
  * any launch): the recurrence keeps only Re<v_j|H v_j>, so its Ritz values mean nothing for other H.
  * All work is enqueued on the stream; the host never waits inside the call. */
 mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes);
+/* Device int32 d_out[0..1] = (second Gram-Schmidt passes taken under MRMF_REORTH_CGS2_COND, Gram-Schmidt
+ * passes taken under MRMF_REORTH_PARTIAL) by the mrmf_lanczos or mrmf_sector_lanczos call that last used
+ * d_scratch (enqueue it on that call's stream, before the scratch is reused); 4-B aligned d_out. */
+mrmf_status mrmf_lanczos_counts(const void* d_scratch, int32_t* d_out, mrmf_stream stream);
 mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z,
                          const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
                          const void* d_v0,

@@ -22,7 +22,7 @@ MRMF_SPIN, MRMF_BOSON = 0, 1
 MRMF_OP_Z, MRMF_OP_Z2, MRMF_OP_RAISE, MRMF_OP_LOWER, MRMF_OP_RAISE2, MRMF_OP_LOWER2 = 0, 1, 2, 3, 4, 5
 MRMF_REQUIRE_HERMITIAN = 1
 MRMF_PREC_Z, MRMF_PREC_C_IN_Z = 0, 1
-MRMF_REORTH_CGS2, MRMF_REORTH_NONE, MRMF_REORTH_CGS2_COND = 0, 1, 2
+MRMF_REORTH_CGS2, MRMF_REORTH_NONE, MRMF_REORTH_CGS2_COND, MRMF_REORTH_PARTIAL = 0, 1, 2, 3
 MRMF_KERNEL_AUTO, MRMF_KERNEL_GENERIC, MRMF_KERNEL_SPECIALIZED = 0, 1, 2
 MRMF_DTYPE_Z, MRMF_DTYPE_C = 0, 1
 MRMF_TUNE_SCHEDULE, MRMF_TUNE_BRANCH_SKIP, MRMF_TUNE_LOAD_GROUP, MRMF_TUNE_BLOCKS_PER_CU = 0, 1, 2, 3
@@ -101,6 +101,7 @@ SIGNATURES = {
     "mrmf_dot_z": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mrmf_norm_z": (_i32, [_i64, _vp, _vp, _vp, _sz, _vp]),
     "mrmf_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),
+    "mrmf_lanczos_counts": (_i32, [_vp, _vp, _vp]),
     "mrmf_lanczos": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _sz, _vp]),
     "mrmf_propagate_scratch_bytes": (_i32, [_vp, _P(_sz)]),

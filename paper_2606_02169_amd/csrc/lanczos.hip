@@ -3,6 +3,7 @@
 // Schmidt coefficients, the Ritz value) stays in device memory; the host only enqueues kernels.  After a
 // breakdown every later kernel of the call sees the `stopped` flag and returns at once.
 #include <cmath>
+#include <cstddef>
 
 #include "mrmf_internal.h"
 #include "reduce.h"
@@ -24,7 +25,9 @@ struct LzState {
     double theta;  // lowest Ritz value
     double wn2;    // conditional Gram-Schmidt: ||w||^2 before the first pass
     int32_t n_second;  // conditional Gram-Schmidt: second passes taken so far
-    int32_t pad[3];
+    int32_t n_pro;     // partial reorthogonalisation: full Gram-Schmidt passes taken so far
+    int32_t skip_pro;  // partial reorthogonalisation: this step's pass (and its norm) is skipped
+    int32_t force;     // partial reorthogonalisation: the next step reorthogonalises as well
 };
 
 int red_blocks(int64_t n) {
@@ -205,6 +208,9 @@ __global__ void k_init_finalize(const double* __restrict__ partial, int nb, LzSt
     st->skip2 = 0;
     st->wn2 = 0.0;
     st->n_second = 0;
+    st->n_pro = 0;
+    st->skip_pro = 1;
+    st->force = 0;
     st->tnorm = 0.0;
     st->nrm0 = nrm;
     st->theta = __builtin_nan("");
@@ -231,6 +237,80 @@ __global__ void k_cgs_norm(const double* __restrict__ partial, int nb, int store
     const int skip = st->stopped != 0 || s >= 0.5 * st->wn2;
     st->skip2 = skip;
     if (!skip) ++st->n_second;
+}
+
+// Partial reorthogonalisation (H. D. Simon, "The Lanczos algorithm with partial reorthogonalization",
+// Math. Comp. 42 (1984)): the inner products omega_{i,k} = <v_i|v_k> are not computed but estimated from
+// the recurrence that the Lanczos relation beta_j v_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}
+// implies for them,
+//     beta_j omega_{j+1,k} = beta_k omega_{j,k+1} + (alpha_k - alpha_j) omega_{j,k} + beta_{k-1} omega_{j,k-1}
+//                            - beta_{j-1} omega_{j-1,k},      omega_{k,k} = 1,
+// with a rounding term of eps ||T|| of the sign that increases |omega| added to every new estimate, and
+// omega_{j+1,j} = eps sqrt(D) ||T|| / beta_j (the level the three-term step leaves).  When some estimate
+// exceeds sqrt(eps), w = beta_j v_{j+1} is orthogonalised against every earlier vector (one classical
+// Gram-Schmidt pass), and so is the next step's (the loss of orthogonality spreads to it through the
+// recurrence); the estimates then restart at eps sqrt(D).  Semi-orthogonality (every |omega| <= sqrt(eps))
+// keeps the Ritz values as accurate as full reorthogonalisation would.
+// One block; omega rows i at omega + (i mod 3) (m + 2); partial: the ||w||^2 partial sums of this step.
+__global__ __launch_bounds__(kRB) void k_pro_estimate(const double* __restrict__ partial, int nb, int j, int m,
+                                                      int64_t D, const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta, double* __restrict__ omega,
+                                                      LzState* __restrict__ st) {
+    __shared__ double red[kRB];
+    __shared__ double s_bj;
+    const int tid = threadIdx.x;
+    if (st->stopped) {
+        if (tid == 0) st->skip_pro = 1;
+        return;
+    }
+    if (tid == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[b];
+        s_bj = sqrt(s);
+    }
+    __syncthreads();
+    const double bj = s_bj;
+    const double eps = 2.220446049250313e-16;
+    const double tn = fmax(st->tnorm, fabs(alpha[j]) + bj + (j > 0 ? beta[j - 1] : 0.0));
+    const double* wc = omega + (j % 3) * (m + 2);          // omega_{j, k}, k < j
+    const double* wp = omega + ((j + 2) % 3) * (m + 2);    // omega_{j-1, k}, k < j - 1
+    double* wn = omega + ((j + 1) % 3) * (m + 2);          // omega_{j+1, k}, k <= j
+    const double level = eps * sqrt(static_cast<double>(D));
+    const bool usable = bj > 0.0 && isfinite(bj);
+    double mx = 0.0;
+    if (usable) {
+        auto oc = [&](int k) { return k == j ? 1.0 : wc[k]; };
+        auto op = [&](int k) { return j == 0 ? 0.0 : (k == j - 1 ? 1.0 : wp[k]); };
+        for (int k = tid; k <= j; k += kRB) {
+            double t;
+            if (k < j) {
+                t = beta[k] * oc(k + 1) + (alpha[k] - alpha[j]) * oc(k) - (j > 0 ? beta[j - 1] * op(k) : 0.0);
+                if (k > 0) t += beta[k - 1] * oc(k - 1);
+                t += (t >= 0.0 ? 2.0 : -2.0) * eps * tn;
+                t /= bj;
+            } else {
+                t = level * tn / bj;
+            }
+            wn[k] = t;
+            mx = fmax(mx, fabs(t));
+        }
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int w = kRB / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    const bool over = usable && red[0] > sqrt(eps);
+    const bool now = usable && (over || st->force != 0);
+    __syncthreads();
+    if (now)
+        for (int k = tid; k <= j; k += kRB) wn[k] = level;
+    if (tid == 0) {
+        st->skip_pro = now ? 0 : 1;
+        st->force = over ? 1 : 0;
+        if (now) ++st->n_pro;
+    }
 }
 
 __global__ void k_beta_finalize(const double* __restrict__ partial, int nb, int j, int last,
@@ -392,7 +472,7 @@ __global__ void k_resid_finalize(const double* __restrict__ partial, int nb, con
 }
 
 struct LzLayout {
-    size_t state, partial, coef, svec, work, tmp, x32, y32, total;
+    size_t state, partial, coef, svec, work, omega, tmp, x32, y32, total;
 };
 
 LzLayout lz_layout(int64_t D, int32_t m, int32_t precision) {
@@ -408,6 +488,8 @@ LzLayout lz_layout(int64_t D, int32_t m, int32_t precision) {
     off = align_up(off + sizeof(double2) * size_t(m + 1), 256);
     L.work = off;
     off = align_up(off + sizeof(double) * 5 * size_t(m + 1), 256);
+    L.omega = off;
+    off = align_up(off + sizeof(double) * 3 * size_t(m + 2), 256);
     L.tmp = off;
     off = align_up(off + sizeof(double2) * size_t(D), 256);
     L.x32 = L.y32 = off;
@@ -464,6 +546,15 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
     return launch_status();
 }
 
+mrmf_status mrmf_lanczos_counts(const void* d_scratch, int32_t* d_out, mrmf_stream stream) {
+    if (!d_scratch || !d_out || !aligned(d_scratch, 256) || !aligned(d_out, 4)) return MRMF_E_INVALID_ARG;
+    // n_second and n_pro are adjacent in the state at the start of the scratch
+    const unsigned char* st = static_cast<const unsigned char*>(d_scratch) + offsetof(LzState, n_second);
+    static_assert(offsetof(LzState, n_pro) == offsetof(LzState, n_second) + sizeof(int32_t), "LzState layout");
+    return hip_status(hipMemcpyAsync(d_out, st, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                     static_cast<hipStream_t>(stream)));
+}
+
 mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes) {
     if (!plan) return MRMF_E_INVALID_ARG;
     return lanczos_scratch_bytes(plan->D, m, precision, bytes);
@@ -489,7 +580,8 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
     if (m < 1 || m > 100000) return MRMF_E_INVALID_ARG;
     if (precision != MRMF_PREC_Z && precision != MRMF_PREC_C_IN_Z) return MRMF_E_INVALID_ARG;
     if (precision == MRMF_PREC_C_IN_Z && !mv_c) return MRMF_E_INVALID_ARG;
-    if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE && reorth != MRMF_REORTH_CGS2_COND)
+    if (reorth != MRMF_REORTH_CGS2 && reorth != MRMF_REORTH_NONE && reorth != MRMF_REORTH_CGS2_COND &&
+        reorth != MRMF_REORTH_PARTIAL)
         return MRMF_E_INVALID_ARG;
     if (!aligned(d_scratch, 256) || !aligned(d_V, 16) || !aligned(d_u, 16) || !aligned(d_v0, 16))
         return MRMF_E_INVALID_ARG;
@@ -508,6 +600,7 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
     auto* coef = reinterpret_cast<double2*>(sc + Lo.coef);
     auto* svec = reinterpret_cast<double2*>(sc + Lo.svec);
     auto* work = reinterpret_cast<double*>(sc + Lo.work);
+    auto* omega = reinterpret_cast<double*>(sc + Lo.omega);
     auto* tmp = reinterpret_cast<double2*>(sc + Lo.tmp);
     auto* x32 = reinterpret_cast<float2*>(sc + Lo.x32);
     auto* y32 = reinterpret_cast<float2*>(sc + Lo.y32);
@@ -564,6 +657,20 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
             }
         }
         hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
+        if (reorth == MRMF_REORTH_PARTIAL) {
+            // estimate the loss of orthogonality from ||w||; only when it calls for one, a Gram-Schmidt pass
+            // against v_0 .. v_j and a new norm (the skipped kernels return at once, and the partial sums of
+            // ||w||^2 above stay for k_beta_finalize)
+            const int k = j + 1;
+            hipLaunchKernelGGL(k_pro_estimate, dim3(1), dim3(kRB), 0, s, part_d, nb, j, m, D, d_alpha, d_beta,
+                               omega, st);
+            const int32_t* stop = &st->skip_pro;
+            hipLaunchKernelGGL(k_gemvt_partial, dim3(nb, (k + kGroup - 1) / kGroup), dim3(kRB), 0, s, D, V, k, w,
+                               part_z, nb, stop);
+            hipLaunchKernelGGL(k_gemvt_finalize, dim3((k + 63) / 64), dim3(64), 0, s, k, nb, part_z, coef, stop);
+            hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, k, nullptr, coef, w, 0, -1.0, stop);
+            hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stop);
+        }
         hipLaunchKernelGGL(k_beta_finalize, dim3(1), dim3(1), 0, s, part_d, nb, j, j == m - 1 ? 1 : 0, d_alpha,
                            d_beta, st);
         if (j < m - 1)

@@ -251,9 +251,10 @@ class Plan:
                 reorth: str = "cgs2", theta_c: torch.Tensor | None = None, keep_basis: bool = False) -> dict:
         """Lowest eigenpair by device-resident Lanczos (mrmf_lanczos).  precision "z" (c128 matvec) or
         "c_in_z" (c64 matvec inside the FP64 recurrence); reorth "cgs2" (two Gram-Schmidt passes),
-        "cgs2_cond" (the second only when the first shrank ||w|| by more than 1/sqrt(2)) or "none".
-        Returns device tensors alpha, beta, the Ritz vector u and result = [theta, residual estimate,
-        explicit residual, steps]."""
+        "cgs2_cond" (the second only when the first shrank ||w|| by more than 1/sqrt(2)), "partial" (one
+        pass only where Simon's estimate of the loss of orthogonality passes sqrt(eps), and the step after)
+        or "none".  Returns device tensors alpha, beta, the Ritz vector u, result = [theta, residual
+        estimate, explicit residual, steps] and counts = [second passes (cgs2_cond), passes (partial)]."""
         return _lanczos("mrmf_lanczos", self._handle, self.ws, self.D, self.device, theta, v0, m, precision,
                         reorth, theta_c, keep_basis)
 
@@ -475,7 +476,8 @@ def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, 
     if v0.numel() != D:
         raise ValueError("v0 has the wrong length")
     prec = {"z": L.MRMF_PREC_Z, "c_in_z": L.MRMF_PREC_C_IN_Z}[precision]
-    ro = {"cgs2": L.MRMF_REORTH_CGS2, "cgs2_cond": L.MRMF_REORTH_CGS2_COND, "none": L.MRMF_REORTH_NONE}[reorth]
+    ro = {"cgs2": L.MRMF_REORTH_CGS2, "cgs2_cond": L.MRMF_REORTH_CGS2_COND, "partial": L.MRMF_REORTH_PARTIAL,
+          "none": L.MRMF_REORTH_NONE}[reorth]
     if prec == L.MRMF_PREC_C_IN_Z:
         if theta_c is None:
             theta_c = theta.to(torch.float32)
@@ -491,7 +493,9 @@ def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, 
     L.call(fn, handle, _ptr(ws), _ptr(theta), _ptr(theta_c) if theta_c is not None else None, prec, int(m), ro,
            _ptr(v0), _ptr(V), _ptr(alpha), _ptr(beta), _ptr(result), _ptr(u), _ptr(scratch), nb.value,
            _stream(dev))
-    out = dict(alpha=alpha, beta=beta, result=result, u=u, scratch=scratch)
+    counts = torch.zeros(2, dtype=torch.int32, device=dev)
+    L.call("mrmf_lanczos_counts", _ptr(scratch), _ptr(counts), _stream(dev))
+    out = dict(alpha=alpha, beta=beta, result=result, u=u, scratch=scratch, counts=counts)
     if keep_basis:
         out["V"] = V
     return out

@@ -312,6 +312,24 @@ def test_lanczos_refuses_non_hermitian_plans():
         L.lib().mrmf_plan_destroy(h)
 
 
+def test_lanczos_counts_and_reorth_arguments():
+    """mrmf_lanczos_counts refuses null or misaligned pointers before any HIP call, and the Lanczos entry
+    point refuses an unknown reorthogonalisation policy before any launch (partial reorthogonalisation,
+    policy 3, is a known one; the pointers below are never dereferenced)."""
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.lib().mrmf_lanczos_counts(None, fake, None) == L.MRMF_E_INVALID_ARG
+    assert L.lib().mrmf_lanczos_counts(fake, None, None) == L.MRMF_E_INVALID_ARG
+    assert L.lib().mrmf_lanczos_counts(ctypes.c_void_p((1 << 20) + 8), fake, None) == L.MRMF_E_INVALID_ARG
+    assert L.MRMF_REORTH_PARTIAL == 3
+    st, h = host_plan(W.config(1, with_state=False)[0])
+    assert st == 0
+    try:
+        args = (fake, fake, None, L.MRMF_PREC_Z, 4, 7, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
+        assert L.lib().mrmf_lanczos(h, *args) == L.MRMF_E_INVALID_ARG
+    finally:
+        L.lib().mrmf_plan_destroy(h)
+
+
 def test_noalloc_adjoint_size_limit():
     """mrmf_adjoint_z_noalloc refuses a plan whose partial sums exceed its static array, before any HIP
     call (the pointers below are never dereferenced)."""

@@ -87,9 +87,9 @@ def test_torus_whole_vector(torus, form):
     assert elementwise_ok(y, ref, TOL_C if f32 else TOL_Z)
 
 
-def certified_lanczos(m, v0, steps):
-    """FP64 and FP32-in-FP64 Lanczos (CGS2) from v0; each Ritz vector checked with the oracle's H.
-    Returns {form: (theta, gpu residual, oracle residual, ||u||)}."""
+def certified_lanczos(m, v0, steps, reorth="cgs2"):
+    """FP64 and FP32-in-FP64 Lanczos from v0 (CGS2, or the given reorthogonalisation); each Ritz vector
+    checked with the oracle's H.  Returns {form: (theta, gpu residual, oracle residual, ||u||)}."""
     from paper_2606_02169_amd.plan import Plan
     th64 = torch.as_tensor(m.theta, dtype=torch.float64, device=DEV)
     th32 = th64.float()
@@ -102,7 +102,7 @@ def certified_lanczos(m, v0, steps):
             xc = v0d.to(torch.complex64)
             p.autotune(th32, xc)
             del xc
-        r = p.lanczos(th64, v0d, steps, precision=prec, reorth="cgs2", theta_c=th32)
+        r = p.lanczos(th64, v0d, steps, precision=prec, reorth=reorth, theta_c=th32)
         res = r["result"].cpu().numpy()
         u = r["u"].cpu().numpy()
         del r, p
@@ -112,8 +112,8 @@ def certified_lanczos(m, v0, steps):
         r_oracle = float(np.linalg.norm(hu - theta * u))
         nu = float(np.linalg.norm(u))
         del hu
-        print(f"{prec}: steps {k} theta {theta!r} residual gpu {r_gpu:.6e} oracle {r_oracle:.6e} ||u|| {nu!r}",
-              flush=True)
+        print(f"{prec} ({reorth}): steps {k} theta {theta!r} residual gpu {r_gpu:.6e} oracle {r_oracle:.6e} "
+              f"||u|| {nu!r}", flush=True)
         assert k == steps
         assert abs(nu - 1.0) <= 1e-10
         # the two residuals are the same norm evaluated by two independent codes: equal to rounding
@@ -142,6 +142,17 @@ def test_torus_lanczos_certified_by_oracle(torus):
     (residual near rounding), so the oracle's residual pins it to an eigenvalue of H to ~1e-13."""
     m, x32 = torus
     out = certified_lanczos(m, x32.astype(np.complex128), 100)
+    t64, _, r64, n64 = out["z"]
+    assert r64 / n64 <= 1e-10 * abs(t64)
+    assert out["c_in_z"][2] <= 1e-4
+
+
+def test_torus_lanczos_partial_reorth_certified_by_oracle(torus):
+    """The same 100 steps with partial reorthogonalisation (Gram-Schmidt only where Simon's estimate of
+    the loss of orthogonality asks for it): the FP64 energy again pinned to an eigenvalue of H by the
+    oracle's residual."""
+    m, x32 = torus
+    out = certified_lanczos(m, x32.astype(np.complex128), 100, reorth="partial")
     t64, _, r64, n64 = out["z"]
     assert r64 / n64 <= 1e-10 * abs(t64)
     assert out["c_in_z"][2] <= 1e-4

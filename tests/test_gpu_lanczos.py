@@ -142,3 +142,56 @@ def test_conditional_second_pass(m_steps):
     V = out["V"].reshape(m_steps + 1, -1)[:m_steps].cpu().numpy()
     assert np.max(np.abs(V.conj() @ V.T - np.eye(m_steps))) <= 1e-12
     assert res[2] < 1e-8
+
+
+def _basis(model, x, m_steps, reorth):
+    p = Plan(model)
+    th = torch.as_tensor(model.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda(), m_steps,
+                    reorth=reorth, keep_basis=True)
+    torch.cuda.synchronize()
+    res = out["result"].cpu().numpy()
+    k = int(res[3])
+    V = out["V"].reshape(m_steps + 1, -1)[:k].cpu().numpy()
+    loss = float(np.max(np.abs(V.conj() @ V.T - np.eye(k))))
+    return res, out["counts"].cpu().numpy(), loss
+
+
+@pytest.mark.parametrize("m_steps", [50, 240])
+def test_partial_reorthogonalisation(m_steps):
+    """Simon's partial reorthogonalisation on config 1: the Ritz value of the oracle's fully
+    reorthogonalised recurrence to 1e-12, a semi-orthogonal basis (every |<v_i|v_k>| near sqrt(eps) at
+    most) while the plain recurrence loses orthogonality on the same run, and Gram-Schmidt passes at a
+    minority of the steps."""
+    m, x = W.config(1)
+    res, counts, loss = _basis(m, x, m_steps, "partial")
+    o = olz.lanczos(lambda v: mf.matvec(m, v), x, m_steps)
+    _, _, loss_none = _basis(m, x, m_steps, "none")
+    print(f"m={m_steps} theta {res[0]!r} oracle {o['theta']!r} passes {counts[1]} of {int(res[3])} steps, "
+          f"max |V^H V - I| {loss:.2e} (no reorthogonalisation: {loss_none:.2e})", flush=True)
+    assert int(res[3]) == o["steps"] == m_steps
+    assert abs(res[0] - o["theta"]) <= 1e-12 * abs(o["theta"])
+    assert loss <= 1e-7
+    assert res[2] < 1e-8
+    if m_steps == 240:
+        assert loss_none > 1e-3          # the plain recurrence does lose orthogonality here
+        assert 0 < counts[1] < m_steps // 2
+    else:
+        assert counts[1] < m_steps // 2
+
+
+def test_partial_reorthogonalisation_free_fermions():
+    """Partial reorthogonalisation on the XX chain N = 20 in a field (D = 2^20) against the closed form."""
+    N, J, h = 20, 1.0, 0.25
+    m = W.xx_chain_in_field(N, J, h)
+    eps = J * np.cos(np.arange(1, N + 1) * np.pi / (N + 1)) + h
+    e0 = eps[eps < 0].sum() - N * h / 2
+    x = W.random_state(m.dim, np.random.default_rng(9))
+    p = Plan(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(x).cuda(), 160, reorth="partial")
+    torch.cuda.synchronize()
+    res, counts = out["result"].cpu().numpy(), out["counts"].cpu().numpy()
+    print(f"E0 closed form {e0!r} gpu {res[0]!r} resid {res[2]:.2e}, passes {counts[1]}", flush=True)
+    assert abs(res[0] - e0) <= max(res[2], 1e-11)
+    assert abs(res[0] - e0) < 1e-9
