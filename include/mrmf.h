@@ -327,10 +327,11 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
  * if that pass left ||w||^2 below half its value before it; (MRMF_REORTH_PARTIAL) once, only where
  * Simon's recurrence for the inner products <v_i|v_k> estimates one of them above sqrt(eps) and at the
  * step after such a step (the basis stays semi-orthogonal: every |<v_i|v_k>| up to about sqrt(eps));
+ * eps is the machine epsilon of the matvec (FP64's, FP32's for MRMF_PREC_C_IN_Z);
  * beta_j = ||w||;
  * stop when beta_j <= 1e-14 * ||T|| (Gershgorin estimate);
  * v_{j+1} = w / beta_j.  Then the lowest eigenpair (theta, s) of the k x k tridiagonal T (bisection
- * and inverse iteration on the GPU), the Ritz vector u = V s, and the explicit residual
+ * and inverse iteration on the GPU), the unit Ritz vector u = V s / ||V s||, and the explicit residual
  * ||H u - theta u|| with the FP64 matvec.
  *   reorth   : MRMF_REORTH_CGS2, MRMF_REORTH_CGS2_COND, MRMF_REORTH_PARTIAL or MRMF_REORTH_NONE
  *   precision: MRMF_PREC_Z, or MRMF_PREC_C_IN_Z (then d_theta_c float[n_params] is required and the
@@ -339,7 +340,9 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
  *   d_V      : c128[(m + 1) * D] Lanczos basis, caller-owned; row j is v_j
  *   d_alpha, d_beta : double[m]
  *   d_result : double[4] = theta, residual estimate beta_{k-1}|s_{k-1}|, explicit residual, steps k
- *   d_u      : c128[D] Ritz vector (written)
+ *   d_u      : c128[D] Ritz vector u = V s / ||V s|| (written; ||V s|| is 1 to rounding with full
+ *              reorthogonalisation, 1 + O(sqrt(eps)) with the semi-orthogonal basis of
+ *              MRMF_REORTH_PARTIAL, and can differ more without reorthogonalisation)
  *   d_scratch: at least mrmf_lanczos_scratch_bytes(plan, m, precision)
  * Requires a plan whose parameter groups are Hermitian (MRMF_E_NOT_HERMITIAN otherwise, checked before
  * any launch): the recurrence keeps only Re<v_j|H v_j>, so its Ritz values mean nothing for other H.

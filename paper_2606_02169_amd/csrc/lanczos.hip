@@ -28,6 +28,9 @@ struct LzState {
     int32_t n_pro;     // partial reorthogonalisation: full Gram-Schmidt passes taken so far
     int32_t skip_pro;  // partial reorthogonalisation: this step's pass (and its norm) is skipped
     int32_t force;     // partial reorthogonalisation: the next step reorthogonalises as well
+    double unrm;       // ||V s|| of the Ritz vector before it is normalised
+    int32_t skip_u;    // the Ritz vector is zero (no step taken): left as it is
+    int32_t pad;
 };
 
 int red_blocks(int64_t n) {
@@ -64,6 +67,24 @@ __global__ __launch_bounds__(kRB) void k_dot_partial(int64_t n, const double2* _
         const double2 x = a[i], y = b[i];
         v[0] += x.x * y.x + x.y * y.y;
         v[1] += x.x * y.y - x.y * y.x;
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(v[0], v[1]);
+}
+
+// partial[b] = sum over the block's rows of conj(a) b for a c64 b (the c64 matvec's output, read as it is)
+__global__ __launch_bounds__(kRB) void k_dot_partial32(int64_t n, const double2* __restrict__ a,
+                                                        const float2* __restrict__ b,
+                                                        double2* __restrict__ partial,
+                                                        const int32_t* __restrict__ stopped) {
+    if (halted(stopped)) return;
+    __shared__ double lds[2 * kRB / 64];
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
+        const double2 x = a[i];
+        const float2 y = b[i];
+        v[0] += x.x * static_cast<double>(y.x) + x.y * static_cast<double>(y.y);
+        v[1] += x.x * static_cast<double>(y.y) - x.y * static_cast<double>(y.x);
     }
     block_sum<2>(v, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(v[0], v[1]);
@@ -151,18 +172,29 @@ __global__ __launch_bounds__(kRB) void k_gemv_acc(int64_t n, const double2* __re
     }
 }
 
-// w -= alpha v_j; w -= beta v_{j-1}
-__global__ __launch_bounds__(kRB) void k_three_term(int64_t n, double2* __restrict__ w,
-                                                     const double2* __restrict__ vj,
-                                                     const double2* __restrict__ vjm1,
-                                                     const double* __restrict__ alpha,
-                                                     const double* __restrict__ beta,
-                                                     const int32_t* __restrict__ stopped) {
+// w = (h32 ? h32 upcast : w) - alpha v_j - beta v_{j-1}, and the partial sums of ||w||^2 (one per block;
+// launched with the reduction grid, so the partials are those k_norm2_partial would give)
+__global__ __launch_bounds__(kRB) void k_three_term_norm(int64_t n, double2* __restrict__ w,
+                                                          const float2* __restrict__ h32,
+                                                          const double2* __restrict__ vj,
+                                                          const double2* __restrict__ vjm1,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          double* __restrict__ partial,
+                                                          const int32_t* __restrict__ stopped) {
     if (halted(stopped)) return;
+    __shared__ double lds[kRB / 64];
     const double a = *alpha;
     const double b = vjm1 ? *beta : 0.0;
+    double v[1] = {0.0};
     for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
-        double2 y = w[i];
+        double2 y;
+        if (h32) {
+            const float2 h = h32[i];
+            y = make_double2(h.x, h.y);
+        } else {
+            y = w[i];
+        }
         const double2 x = vj[i];
         y.x -= a * x.x;
         y.y -= a * x.y;
@@ -172,7 +204,10 @@ __global__ __launch_bounds__(kRB) void k_three_term(int64_t n, double2* __restri
             y.y -= b * z.y;
         }
         w[i] = y;
+        v[0] += y.x * y.x + y.y * y.y;
     }
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
 }
 
 // dst = src / denom (and a c64 copy when dst32 is given)
@@ -186,15 +221,6 @@ __global__ __launch_bounds__(kRB) void k_scale(int64_t n, const double2* src, do
         const double2 y = make_double2(x.x / s, x.y / s);
         dst[i] = y;
         if (dst32) dst32[i] = make_float2(static_cast<float>(y.x), static_cast<float>(y.y));
-    }
-}
-
-__global__ __launch_bounds__(kRB) void k_upcast(int64_t n, const float2* __restrict__ src, double2* __restrict__ dst,
-                                                 const int32_t* __restrict__ stopped) {
-    if (halted(stopped)) return;
-    for (int64_t i = int64_t(blockIdx.x) * kRB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kRB) {
-        const float2 x = src[i];
-        dst[i] = make_double2(x.x, x.y);
     }
 }
 
@@ -245,15 +271,19 @@ __global__ void k_cgs_norm(const double* __restrict__ partial, int nb, int store
 // implies for them,
 //     beta_j omega_{j+1,k} = beta_k omega_{j,k+1} + (alpha_k - alpha_j) omega_{j,k} + beta_{k-1} omega_{j,k-1}
 //                            - beta_{j-1} omega_{j-1,k},      omega_{k,k} = 1,
-// with a rounding term of eps ||T|| of the sign that increases |omega| added to every new estimate, and
-// omega_{j+1,j} = eps sqrt(D) ||T|| / beta_j (the level the three-term step leaves).  When some estimate
-// exceeds sqrt(eps), w = beta_j v_{j+1} is orthogonalised against every earlier vector (one classical
-// Gram-Schmidt pass), and so is the next step's (the loss of orthogonality spreads to it through the
-// recurrence); the estimates then restart at eps sqrt(D).  Semi-orthogonality (every |omega| <= sqrt(eps))
-// keeps the Ritz values as accurate as full reorthogonalisation would.
+// with a rounding term 2 eps ||T||, of the sign that increases |omega|, added to every new estimate, and
+// omega_{j+1,j} = eps64 sqrt(D) ||T|| / beta_j (the level the FP64 three-term step leaves).  eps is the
+// machine epsilon of the matvec: FP64's, or FP32's for the c64 form, whose matvec error of about
+// eps32 ||H|| per step is what its basis loses orthogonality to.  (A rounding term scaled down by
+// 1 / sqrt(D), as for an error vector unrelated to the basis, was measured to be unsafe: on the 20-site
+// ring the c64 form's basis then drifted to |<v_i|v_k>| = 0.13.)  When some estimate exceeds sqrt(eps),
+// w = beta_j v_{j+1} is orthogonalised against every earlier vector (one classical Gram-Schmidt pass, in
+// FP64), and so is the next step's (the loss of orthogonality spreads to it through the recurrence); the
+// estimates then restart at eps64 sqrt(D).  Semi-orthogonality (every |omega| <= sqrt(eps)) keeps the
+// Ritz values as accurate as full reorthogonalisation would, to O(eps ||H||).
 // One block; omega rows i at omega + (i mod 3) (m + 2); partial: the ||w||^2 partial sums of this step.
 __global__ __launch_bounds__(kRB) void k_pro_estimate(const double* __restrict__ partial, int nb, int j, int m,
-                                                      int64_t D, const double* __restrict__ alpha,
+                                                      int64_t D, double eps, const double* __restrict__ alpha,
                                                       const double* __restrict__ beta, double* __restrict__ omega,
                                                       LzState* __restrict__ st) {
     __shared__ double red[kRB];
@@ -270,12 +300,12 @@ __global__ __launch_bounds__(kRB) void k_pro_estimate(const double* __restrict__
     }
     __syncthreads();
     const double bj = s_bj;
-    const double eps = 2.220446049250313e-16;
+    const double eps64 = 2.220446049250313e-16;
     const double tn = fmax(st->tnorm, fabs(alpha[j]) + bj + (j > 0 ? beta[j - 1] : 0.0));
     const double* wc = omega + (j % 3) * (m + 2);          // omega_{j, k}, k < j
     const double* wp = omega + ((j + 2) % 3) * (m + 2);    // omega_{j-1, k}, k < j - 1
     double* wn = omega + ((j + 1) % 3) * (m + 2);          // omega_{j+1, k}, k <= j
-    const double level = eps * sqrt(static_cast<double>(D));
+    const double level = eps64 * sqrt(static_cast<double>(D));
     const bool usable = bj > 0.0 && isfinite(bj);
     double mx = 0.0;
     if (usable) {
@@ -330,6 +360,14 @@ __global__ void k_beta_finalize(const double* __restrict__ partial, int nb, int 
         st->stopped = 1;
         st->breakdown = 1;
     }
+}
+
+// ||V s|| of the Ritz vector (a basis that is only semi-orthogonal leaves it 1 + O(sqrt(eps))).
+__global__ void k_unorm_finalize(const double* __restrict__ partial, int nb, LzState* __restrict__ st) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    st->unrm = sqrt(s);
+    st->skip_u = (st->unrm > 0.0 && isfinite(st->unrm)) ? 0 : 1;
 }
 
 __global__ void k_scalar_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out, int sq) {
@@ -622,25 +660,25 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
 
     for (int j = 0; j < m; ++j) {
         double2* w = row(j + 1);
+        // w = H v_j (the c64 form leaves H v_j in y32, read as it is by the next two kernels); alpha_j; then
+        // the three-term update in one pass that also leaves the partial sums of ||w||^2 in part_d
         if (c32) {
             rc = mv_c(x32, y32, s, stopped);
             if (rc != MRMF_OK) return rc;
-            hipLaunchKernelGGL(k_upcast, dim3(g), dim3(kRB), 0, s, D, y32, w, stopped);
+            hipLaunchKernelGGL(k_dot_partial32, dim3(nb), dim3(kRB), 0, s, D, row(j), y32, part_z, stopped);
         } else {
             rc = mv_z(row(j), w, s, stopped);
             if (rc != MRMF_OK) return rc;
+            hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kRB), 0, s, D, row(j), w, part_z, stopped);
         }
-        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kRB), 0, s, D, row(j), w, part_z, stopped);
         hipLaunchKernelGGL(k_alpha_finalize, dim3(1), dim3(1), 0, s, part_z, nb, d_alpha + j, stopped);
-        hipLaunchKernelGGL(k_three_term, dim3(g), dim3(kRB), 0, s, D, w, row(j), j > 0 ? row(j - 1) : nullptr,
-                           d_alpha + j, j > 0 ? d_beta + (j - 1) : nullptr, stopped);
+        hipLaunchKernelGGL(k_three_term_norm, dim3(nb), dim3(kRB), 0, s, D, w, c32 ? y32 : nullptr, row(j),
+                           j > 0 ? row(j - 1) : nullptr, d_alpha + j, j > 0 ? d_beta + (j - 1) : nullptr, part_d,
+                           stopped);
         if (reorth == MRMF_REORTH_CGS2 || reorth == MRMF_REORTH_CGS2_COND) {
             const int k = j + 1;
             const bool cond = reorth == MRMF_REORTH_CGS2_COND;
-            if (cond) {
-                hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
-                hipLaunchKernelGGL(k_cgs_norm, dim3(1), dim3(1), 0, s, part_d, nb, 1, st);
-            }
+            if (cond) hipLaunchKernelGGL(k_cgs_norm, dim3(1), dim3(1), 0, s, part_d, nb, 1, st);
             for (int pass = 0; pass < 2; ++pass) {
                 // the second pass of the conditional form runs (its kernels return at once otherwise)
                 // only when the device-side test after the first pass asked for it
@@ -655,15 +693,17 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
                                    stop);
                 hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, k, nullptr, coef, w, 0, -1.0, stop);
             }
+            // ||w|| after the passes
+            hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
         }
-        hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, w, part_d, stopped);
         if (reorth == MRMF_REORTH_PARTIAL) {
             // estimate the loss of orthogonality from ||w||; only when it calls for one, a Gram-Schmidt pass
             // against v_0 .. v_j and a new norm (the skipped kernels return at once, and the partial sums of
-            // ||w||^2 above stay for k_beta_finalize)
+            // ||w||^2 from the three-term pass stay for k_beta_finalize)
             const int k = j + 1;
-            hipLaunchKernelGGL(k_pro_estimate, dim3(1), dim3(kRB), 0, s, part_d, nb, j, m, D, d_alpha, d_beta,
-                               omega, st);
+            const double eps = c32 ? 1.1920928955078125e-07 : 2.220446049250313e-16;  // 2^-23 or 2^-52
+            hipLaunchKernelGGL(k_pro_estimate, dim3(1), dim3(kRB), 0, s, part_d, nb, j, m, D, eps, d_alpha,
+                               d_beta, omega, st);
             const int32_t* stop = &st->skip_pro;
             hipLaunchKernelGGL(k_gemvt_partial, dim3(nb, (k + kGroup - 1) / kGroup), dim3(kRB), 0, s, D, V, k, w,
                                part_z, nb, stop);
@@ -682,6 +722,9 @@ mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, i
     // lowest Ritz pair of T, Ritz vector u = sum_i s_i v_i, explicit residual with the FP64 map
     hipLaunchKernelGGL(k_tridiag_lowest, dim3(1), dim3(1), 0, s, d_alpha, d_beta, m, st, work, svec, d_result);
     hipLaunchKernelGGL(k_gemv_acc, dim3(g), dim3(kRB), 0, s, D, V, m, &st->steps, svec, u, 1, 1.0, nullptr);
+    hipLaunchKernelGGL(k_norm2_partial, dim3(nb), dim3(kRB), 0, s, D, u, part_d, nullptr);
+    hipLaunchKernelGGL(k_unorm_finalize, dim3(1), dim3(1), 0, s, part_d, nb, st);
+    hipLaunchKernelGGL(k_scale, dim3(g), dim3(kRB), 0, s, D, u, u, &st->unrm, nullptr, &st->skip_u);
     rc = launch_status();
     if (rc != MRMF_OK) return rc;
     rc = mv_z(u, tmp, s, nullptr);
