@@ -378,7 +378,7 @@ def bench_lanczos(args, dev):
         return out
 
     m_ref = args.lanczos_ref_steps
-    ref = run(pz, "z", m_ref, certify=True)
+    ref = run(pz, "z", m_ref, reorth=args.lanczos_ref_reorth, certify=True)
     E_ref = ref["theta"]
     log(f"reference: {m_ref} FP64 steps, theta {E_ref!r} residual {ref['resid']:.3e} "
         f"(oracle {ref.get('oracle_residual', float('nan')):.3e}) in {ref['seconds']:.1f} s")
@@ -387,14 +387,17 @@ def bench_lanczos(args, dev):
            "reference": {"steps": ref["steps"], "theta": E_ref, "residual": ref["resid"],
                          "oracle_residual": ref.get("oracle_residual"),
                          "certified_within": (ref["oracle_residual"] / ref["u_norm"]) if "u_norm" in ref else None,
-                         "seconds": ref["seconds"]},
+                         "reorth": args.lanczos_ref_reorth, "seconds": ref["seconds"]},
            "matvec_ms": {"c128": mv_z, "c64": mv_c}, "forms": {}}
     m = args.lanczos_steps
+    forms = args.lanczos_forms.split(",")
     for name, plan, prec, ro in (("fp64", pz, "z", "cgs2"), ("fp32_in_fp64", pc, "c_in_z", "cgs2"),
                                  ("fp64_cgs2_cond", pz, "z", "cgs2_cond"),
                                  ("fp32_in_fp64_cgs2_cond", pc, "c_in_z", "cgs2_cond"),
                                  ("fp64_partial", pz, "z", "partial"),
                                  ("fp32_in_fp64_partial", pc, "c_in_z", "partial")):
+        if ro not in forms:
+            continue
         full = run(plan, prec, m, ro, certify=True)
         curve = ritz_curve(full["alpha"], full["beta"], full["steps"])
         rel = np.abs(curve - E_ref) / abs(E_ref)
@@ -420,9 +423,10 @@ def bench_lanczos(args, dev):
 
 
 def bench_lanczos_ring(args, dev):
-    """100 Lanczos steps (CGS2) on the 20-site ferrimagnetic ring from the seeded start vector, plain FP64
-    and FP32 matvec inside FP64; the full-basis ground energy beside the lowest sector energy (H keeps the
-    digit sum, so its lowest eigenvalue is the lowest over all sectors; sector Lanczos in every sector)."""
+    """100 Lanczos steps on the 20-site ferrimagnetic ring from the seeded start vector, plain FP64 and FP32
+    matvec inside FP64, with each reorthogonalisation (full CGS2, conditional second pass, partial); the
+    full-basis ground energy beside the lowest sector energy (H keeps the digit sum, so its lowest
+    eigenvalue is the lowest over all sectors; sector Lanczos in every sector)."""
     import numpy as np
     import torch
 
@@ -436,12 +440,15 @@ def bench_lanczos_ring(args, dev):
     th64 = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
     th32 = th64.float()
     m = args.lanczos_steps
-    out = {"metric": "Lanczos on the 20-site ferrimagnetic ring (c128 basis, CGS2): time per step and ground energy",
+    out = {"metric": "Lanczos on the 20-site ferrimagnetic ring (c128 basis): time per step and ground energy",
            "workload": "ferrimagnetic_ring_N20_c128", "D": D, "seed": 2, "steps": m,
            "basis_GB": (m + 1) * D * 16 / 1e9, "forms": {}}
+    forms = args.lanczos_forms.split(",")
     for name, prec, ro in (("fp64", "z", "cgs2"), ("fp32_in_fp64", "c_in_z", "cgs2"),
                            ("fp64_cgs2_cond", "z", "cgs2_cond"), ("fp32_in_fp64_cgs2_cond", "c_in_z", "cgs2_cond"),
                            ("fp64_partial", "z", "partial"), ("fp32_in_fp64_partial", "c_in_z", "partial")):
+        if ro not in forms:
+            continue
         plan = Plan.from_model(model, device=dev)
         y = torch.empty_like(v0)
         plan.autotune(th64, v0, y)
@@ -810,6 +817,10 @@ def main():
     ap.add_argument("--dtype", default=None, choices=["c64", "c128"], help="torus: one element type only")
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
+    ap.add_argument("--lanczos-ref-reorth", default="cgs2", choices=["cgs2", "cgs2_cond", "partial"],
+                    help="lanczos4x4: reorthogonalisation of the FP64 reference run")
+    ap.add_argument("--lanczos-forms", default="cgs2,cgs2_cond,partial",
+                    help="lanczos4x4 / lanczos_ring20: reorthogonalisations to time (comma list)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the matvec is measured on one GPU's share; "
