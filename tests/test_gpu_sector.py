@@ -127,6 +127,12 @@ def test_ring_sector_lanczos_reduced():
     r = S.lanczos(t(m.theta), t(x), 80)["result"].cpu().numpy()
     o = olz.lanczos(lambda v: osec.matvec(m, Q, v, lab=lab), x, 80)
     assert abs(r[0] - o["theta"]) <= 1e-10 * abs(o["theta"])
+    # partial reorthogonalisation reaches the same Ritz value with fewer Gram-Schmidt passes
+    out = S.lanczos(t(m.theta), t(x), 80, reorth="partial")
+    rp, passes = out["result"].cpu().numpy(), int(out["counts"].cpu().numpy()[1])
+    print(f"sector Lanczos: cgs2 {r[0]!r} partial {rp[0]!r} ({passes} passes) oracle {o['theta']!r}", flush=True)
+    assert abs(rp[0] - o["theta"]) <= 1e-10 * abs(o["theta"])
+    assert passes < 40
 
 
 def Sector_digit_sum(m, M):
