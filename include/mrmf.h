@@ -348,9 +348,11 @@ mrmf_status mrmf_norm_z(int64_t n, const void* d_a, double* d_out, void* d_scrat
  * any launch): the recurrence keeps only Re<v_j|H v_j>, so its Ritz values mean nothing for other H.
  * All work is enqueued on the stream; the host never waits inside the call. */
 mrmf_status mrmf_lanczos_scratch_bytes(mrmf_plan plan, int32_t m, int32_t precision, size_t* bytes);
-/* Device int32 d_out[0..1] = (second Gram-Schmidt passes taken under MRMF_REORTH_CGS2_COND, Gram-Schmidt
- * passes taken under MRMF_REORTH_PARTIAL) by the mrmf_lanczos or mrmf_sector_lanczos call that last used
- * d_scratch (enqueue it on that call's stream, before the scratch is reused); 4-B aligned d_out. */
+/* Work counts of the Lanczos above (Sec. I's Krylov use of x -> H x), for diagnostics: device int32
+ * d_out[0..1] = (second Gram-Schmidt passes taken under MRMF_REORTH_CGS2_COND, Gram-Schmidt passes taken
+ * under MRMF_REORTH_PARTIAL) by the mrmf_lanczos or mrmf_sector_lanczos call that last used d_scratch
+ * (the same 256-B aligned pointer; enqueue on that call's stream, before the scratch is reused).  d_out:
+ * 4-B aligned.  MRMF_E_INVALID_ARG for null or misaligned pointers. */
 mrmf_status mrmf_lanczos_counts(const void* d_scratch, int32_t* d_out, mrmf_stream stream);
 mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta_z,
                          const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
