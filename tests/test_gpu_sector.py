@@ -159,6 +159,27 @@ def test_ring20_sz0_sector_sampled():
     assert rel_err(got, osec.matvec(m, Q, x, lab=lab, rows=rows)) <= TOL_Z
 
 
+def test_ring20_sz0_sector_whole_vector():
+    """20-site ferrimagnetic ring, S_z = 0 sector (7,873,260 states), with the generated kernel the
+    benchmark times: every packed row against the oracle (c128 at 1e-12; c64 at 2e-5 with the oracle fed
+    the c64-rounded input), and every label (the packed digits) against the oracle's enumeration."""
+    m, _ = W.config(2, with_state=False)
+    Q = Sector_digit_sum(m, 0.0)
+    S = sector(m, Q)
+    assert S.generated() and S.generated(torch.complex64)
+    lab = osec.labels(m, Q)
+    assert np.array_equal(S.labels().cpu().numpy(), lab)
+    x = W.random_state(S.dim, np.random.default_rng(8))
+    y = S.matvec(t(m.theta), t(x)).cpu().numpy()
+    e = rel_err(y, osec.matvec(m, Q, x, lab=lab))
+    x32 = x.astype(np.complex64)
+    y32 = S.matvec(t(m.theta.astype(np.float32)), t(x32)).cpu().numpy()
+    e32 = rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128),
+                                   theta=m.theta.astype(np.float32).astype(np.float64), lab=lab))
+    print(f"sector whole vector: c128 {e:.2e}, c64 {e32:.2e}", flush=True)
+    assert e <= TOL_Z and e32 <= TOL_C
+
+
 def test_sector_edge_cases():
     """The two one-state sectors (all digits 0, all digits maximal), a sector of a one-site lattice, and
     argument errors."""
