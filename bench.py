@@ -823,8 +823,8 @@ def main():
                     help="lanczos4x4 / lanczos_ring20: reorthogonalisations to time (comma list)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the matvec is measured on one GPU's share; "
-              "a multi-GPU run is not part of this build (--gpus 1).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the matvec is measured on one GPU's share of the work; "
+              "runs over several GPUs are not supported (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -37,7 +37,7 @@ typedef int32_t mrmf_status;
 #define MRMF_E_OVERFLOW (-2)      /* D = prod d_i >= 2^62 (single-word index bound, Sec. VI)      */
 #define MRMF_E_NOT_HERMITIAN (-3) /* some parameter group h_p differs from its adjoint (IV.A, IV.B) */
 #define MRMF_E_HIP (-4)           /* a HIP runtime call or kernel launch failed                  */
-#define MRMF_E_UNSUPPORTED (-5)   /* valid request outside what this build implements            */
+#define MRMF_E_UNSUPPORTED (-5)   /* valid request outside what the library implements           */
 #define MRMF_E_WORKSPACE (-6)     /* workspace / scratch smaller than the size query returned     */
 
 typedef void* mrmf_stream; /* hipStream_t */
