@@ -220,3 +220,57 @@ def test_partial_reorthogonalisation_fp32_form():
     assert abs(rel) <= 1e-5
     assert rel >= -1e-6
     assert loss <= 2e-3
+
+
+def simon_passes(alpha, beta, D, eps):
+    """Gram-Schmidt passes that partial reorthogonalisation prescribes for a run with these alpha, beta:
+    Simon's recurrence for the estimates omega_{j+1,k} of <v_{j+1}|v_k>, a rounding term 2 eps ||T|| of
+    the sign that increases |omega|, omega_{j+1,j} = eps64 sqrt(D) ||T|| / beta_j, a pass where an estimate
+    exceeds sqrt(eps) and at the step after, the estimates restarting at eps64 sqrt(D) after a pass
+    (||T|| is the running Gershgorin estimate max |alpha_i| + beta_i + beta_{i-1})."""
+    eps64 = np.finfo(np.float64).eps
+    level = eps64 * np.sqrt(D)
+    rows = {0: np.zeros(0)}
+    tnorm, force, passes = 0.0, False, 0
+    for j in range(len(alpha)):
+        a, b = alpha, beta
+        tn = max(tnorm, abs(a[j]) + b[j] + (b[j - 1] if j > 0 else 0.0))
+        cur = np.append(rows[j], 1.0)                                   # omega_{j,k}, k <= j
+        prev = np.append(rows[j - 1], 1.0) if j > 0 else None           # omega_{j-1,k}, k <= j-1
+        new = np.empty(j + 1)
+        for k in range(j):
+            t = b[k] * cur[k + 1] + (a[k] - a[j]) * cur[k]
+            if k > 0:
+                t += b[k - 1] * cur[k - 1]
+            if j > 0:
+                t -= b[j - 1] * prev[k]
+            t += (2.0 if t >= 0 else -2.0) * eps * tn
+            new[k] = t / b[j]
+        new[j] = level * tn / b[j]
+        over = np.max(np.abs(new)) > np.sqrt(eps)
+        if over or force:
+            passes += 1
+            new[:] = level
+        force = over
+        rows[j + 1] = new
+        tnorm = max(tnorm, abs(a[j]) + b[j] + (b[j - 1] if j > 0 else 0.0))
+    return passes
+
+
+@pytest.mark.parametrize("prec", ["z", "c_in_z"])
+def test_partial_reorthogonalisation_pass_count(prec):
+    """The passes the device took equal those Simon's recurrence prescribes for the run's own alpha and beta
+    (the estimate replayed on the host from the method's definition): config 1, 240 steps, both forms."""
+    m, x = W.config(1)
+    p = Plan(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device="cuda")
+    out = p.lanczos(th, torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda(), 240,
+                    precision=prec, reorth="partial")
+    torch.cuda.synchronize()
+    k = int(out["result"][3])
+    a, b = out["alpha"].cpu().numpy()[:k], out["beta"].cpu().numpy()[:k]
+    eps = np.finfo(np.float32).eps if prec == "c_in_z" else np.finfo(np.float64).eps
+    want = simon_passes(a, b, m.dim, float(eps))
+    got = int(out["counts"].cpu().numpy()[1])
+    print(f"{prec}: passes device {got} host replay {want} in {k} steps", flush=True)
+    assert k == 240 and got == want and got > 0
