@@ -636,8 +636,9 @@ def bench_adjoint(args, dev):
 
 # ------------------------------------------------------------------------------------------ propagation
 def bench_propagate(args, dev):
-    """exp(-i H dt) on the 20-site ring (c128): Chebyshev terms per step, time per step and per term,
-    against the plain matvec; invariants (norm, reversal) on the same vector."""
+    """exp(-i H dt) on the 20-site ring (c128): Chebyshev terms per step, time per step with the fixed H's
+    steps merged into one series (the default) and with one series per step, time per term, against the
+    plain matvec; invariants (norm, reversal) on the same vector."""
     import torch
 
     import workloads as W
@@ -661,25 +662,38 @@ def bench_propagate(args, dev):
     nt = r["n_terms"]
     out = torch.empty_like(xt)
     reps = 1 if args.profile else 3
+    # the steps of this fixed H are taken as one longer step (exp(-i H dt)^q = exp(-i H q dt)); the same
+    # call with one series per step is timed below
+    nt_call = p.propagate(th, xt, dt, steps, bounds=bounds, out=out)["n_terms"]
     ms = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
+    p.set_tuning(cheb_merge=0)
+    ms_stepwise = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
+    x_stepwise = out.clone()
+    p.set_tuning(cheb_merge=1)
     nt_norm, ms_norm = None, None
     if not args.profile:
         nt_norm = p.propagate(th, xt, dt, 1, bounds=(-bnd, bnd))["n_terms"]
+        p.set_tuning(cheb_merge=0)   # per-step series, as ms_per_step_one_series_per_step
         ms_norm = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=(-bnd, bnd), out=out), stream,
                             reps) / steps
+        p.set_tuning(cheb_merge=1)
     y = torch.empty_like(xt)
     ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 3 if args.profile else 20)
-    p.set_tuning(cheb_fused=0)
+    p.set_tuning(cheb_fused=0, cheb_merge=0)
     ms_two = cuda_time(lambda: p.propagate(th, xt, dt, steps, bounds=bounds, out=out), stream, reps) / steps
-    p.set_tuning(cheb_fused=1)
+    p.set_tuning(cheb_fused=1, cheb_merge=1)
+    out = p.propagate(th, xt, dt, steps, bounds=bounds, out=out)["x"]
     back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
     res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
            "workload": "ferrimagnetic_ring_N20_c128", "D": model.dim, "dt": dt, "steps": steps,
-           "gershgorin_bounds": [lo, hi], "gershgorin_ms": ms_gersh, "terms_per_step": nt, "ms_per_step": ms,
-           "ms_per_term": ms / max(1, nt - 1), "norm_bound": bnd, "norm_bound_terms_per_step": nt_norm,
+           "gershgorin_bounds": [lo, hi], "gershgorin_ms": ms_gersh, "terms_per_step": nt,
+           "ms_per_step": ms, "terms_merged_call": nt_call,
+           "ms_per_step_one_series_per_step": ms_stepwise, "ms_per_term": ms_stepwise / max(1, nt - 1),
+           "merged_vs_stepwise_rel_diff": ((out - x_stepwise).norm() / x_stepwise.norm()).item(),
+           "norm_bound": bnd, "norm_bound_terms_per_step": nt_norm,
            "norm_bound_ms_per_step": ms_norm,
            "matvec_ms": ms_mv, "two_pass_ms_per_step": ms_two, "two_pass_ms_per_term": ms_two / max(1, nt - 1),
-           "fused_speedup": ms_two / ms, "cheb_kernel": {k: tuned_cheb.get(k) for k in
+           "fused_speedup": ms_two / ms_stepwise, "cheb_kernel": {k: tuned_cheb.get(k) for k in
                                                          ("key", "variant", "inner_sites", "unrolled_sites",
                                                           "load_group", "us_per_call")},
            "norm_drift": abs(torch.linalg.vector_norm(out).item() - torch.linalg.vector_norm(xt).item()),

@@ -188,6 +188,10 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
  *   MRMF_TUNE_CHEB_FUSED    : 1 = mrmf_propagate_z runs each Chebyshev term as one launch of the
  *                             specialized kernel with the Chebyshev-step epilogue (default); 0 = a matvec
  *                             and a separate vector update per term.
+ *   MRMF_TUNE_CHEB_MERGE    : 1 = mrmf_propagate_z takes consecutive steps of a fixed H (theta_stride 0)
+ *                             as one step of their summed length, exp(-i H dt)^q = exp(-i H q dt), q as
+ *                             large as keeps a series within 2048 terms (default); 0 = one series per
+ *                             step.
  *   MRMF_TUNE_WAVES_PER_EU  : 0 = the compiler's register allocation (default); 1..8 = ask for at least
  *                             that many resident waves per SIMD (a register budget; may spill).
  *   MRMF_TUNE_FAR_LOADS     : 0 = every gather with the default cache policy (default); k in 10..40 = a
@@ -223,6 +227,7 @@ mrmf_status mrmf_plan_set_kernel(mrmf_plan plan, int32_t kind, int32_t inner_sit
 #define MRMF_TUNE_OUTER_FIRST 10
 #define MRMF_TUNE_UNROLL_TOP 11
 #define MRMF_TUNE_FAR_DIR 12
+#define MRMF_TUNE_CHEB_MERGE 13
 #define MRMF_VARIANT_MASKED 0
 #define MRMF_VARIANT_LIST 1
 #define MRMF_SCHED_WINDOWS 0
@@ -373,7 +378,9 @@ mrmf_status mrmf_lanczos(mrmf_plan plan, const void* d_ws, const double* d_theta
  *   tol          : truncation bound relative to ||x0||, in (0, 1)
  *   d_x0, d_x    : c128[D]; d_x may equal d_x0 (in place) but may not partly overlap it
  *   d_scratch    : mrmf_propagate_scratch_bytes (three vectors), 256-B aligned
- *   h_n_terms    : host int32 (may be NULL): Chebyshev terms per step, known when the call returns
+ *   h_n_terms    : host int32 (may be NULL): Chebyshev terms taken over the whole call (the series'
+ *                  terms summed over the steps as taken; see MRMF_TUNE_CHEB_MERGE), known when the call
+ *                  returns
  * Requires a plan whose parameter groups are Hermitian (MRMF_E_NOT_HERMITIAN otherwise);
  * MRMF_E_UNSUPPORTED when a step would need more than 2^20 terms. */
 mrmf_status mrmf_propagate_scratch_bytes(mrmf_plan plan, size_t* bytes);

@@ -35,6 +35,7 @@ MRMF_TUNE_GRAD_BLOCKS_PER_CU = 9
 MRMF_TUNE_OUTER_FIRST = 10
 MRMF_TUNE_UNROLL_TOP = 11
 MRMF_TUNE_FAR_DIR = 12
+MRMF_TUNE_CHEB_MERGE = 13
 MRMF_SOURCE_CHEB = 2
 MRMF_SOURCE_GRAD = 3
 MRMF_BATCH_SCHED_RUNS, MRMF_BATCH_SCHED_WINDOWS, MRMF_BATCH_SCHED_XCD_CHUNK = 0, 1, 2

@@ -2192,6 +2192,10 @@ mrmf_status mrmf_plan_set_tuning(mrmf_plan plan, int32_t knob, int32_t value) {
                 if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
                 c.cheb_fused = value;
                 break;
+            case MRMF_TUNE_CHEB_MERGE:
+                if (value != 0 && value != 1) return MRMF_E_INVALID_ARG;
+                c.cheb_merge = value;
+                break;
             case MRMF_TUNE_WAVES_PER_EU:
                 if (value < 0 || value > 8) return MRMF_E_INVALID_ARG;
                 c.waves_per_eu = value;
@@ -2240,6 +2244,7 @@ mrmf_status mrmf_plan_set_shape(mrmf_plan plan, int32_t dtype, int32_t variant, 
     c.variant = variant;
     c.group = load_group;
     c.cheb_fused = plan->cfg[dtype].cheb_fused;
+    c.cheb_merge = plan->cfg[dtype].cheb_merge;
     c.wide = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].wide;
     c.far_nt = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_nt;
     c.far_dir = plan->cfg[dtype == MRMF_SOURCE_CHEB ? MRMF_DTYPE_Z : dtype].far_dir;
@@ -2322,6 +2327,7 @@ mrmf_status mrmf_plan_autotune(mrmf_plan plan, int32_t dtype, const void* d_ws, 
         k.unroll_top = c.top;
         k.wide = plan->cfg[cheb ? MRMF_DTYPE_Z : dtype].wide;
         k.cheb_fused = plan->cfg[dtype].cheb_fused;
+        k.cheb_merge = plan->cfg[dtype].cheb_merge;
         set_cfg(plan, dtype, k);
     };
     hipEvent_t e0, e1;

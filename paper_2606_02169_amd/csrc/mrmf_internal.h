@@ -105,6 +105,7 @@ struct KernelCfg {
     int32_t sched = MRMF_SCHED_WINDOWS, bskip = 0, group = 0, blocks_per_cu = 0, variant = MRMF_VARIANT_MASKED;
     int32_t wide = 0;  // 1 = 64-bit addresses even when 32-bit buffer offsets would do
     int32_t cheb_fused = 1;  // time propagation: fused Chebyshev-step kernel (c128 configuration only)
+    int32_t cheb_merge = 1;  // time propagation: steps of a fixed H taken as one series (c128 configuration)
     int32_t waves_per_eu = 0;  // register budget hint for the generated kernel (0: the compiler's choice)
     int32_t far_nt = 0;  // > 0: gathers with |Delta| >= 2^far_nt bytes are non-temporal loads
     int32_t far_dir = 0;  // which of those: 0 both directions, 1 sources behind (Delta > 0), 2 ahead (Delta < 0)

@@ -10,6 +10,11 @@
 // plans on the generic kernel, a matvec and a fused vector update; the series is cut where the remaining
 // Bessel weights sum below the tolerance (|T_k(Ht)| <= 1 on the spectrum).  A piecewise-constant drive supplies one
 // parameter vector per step (theta + s * theta_stride): the plan and its kernels are reused as they are.
+// With a fixed H, q consecutive steps are one step of length q dt (the exponential of a fixed H composes:
+// exp(-i H dt)^q = exp(-i H q dt)), whose series needs about a q |dt| + O((a q |dt|)^(1/3)) terms instead
+// of q times those of one step, and is truncated once instead of q times.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -159,25 +164,41 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
         ranges_overlap(d_scratch, need, d_x0, vb))
         return MRMF_E_INVALID_ARG;
     const double a = 0.5 * (e_max - e_min), b = 0.5 * (e_max + e_min);
-    std::vector<double> J;
-    const int nt = cheb_bessel(a * std::fabs(dt), tol, 1 << 20, J);
-    if (nt == 0) return MRMF_E_UNSUPPORTED;
-    if (h_n_terms) *h_n_terms = nt;
-    // c_k = (2 - delta_k0) (-i)^k J_k(a dt) exp(-i b dt), with J_k(-z) = (-1)^k J_k(z) for dt < 0
-    std::vector<double> cr(nt), ci(nt);
-    const double pr = std::cos(b * dt), pi = -std::sin(b * dt);
-    for (int k = 0; k < nt; ++k) {
-        double w = (k == 0 ? 1.0 : 2.0) * J[k];
-        if (dt < 0 && (k & 1)) w = -w;
-        double ur = 0.0, ui = 0.0;  // (-i)^k
-        switch (k & 3) {
-            case 0: ur = 1.0; break;
-            case 1: ui = -1.0; break;
-            case 2: ur = -1.0; break;
-            default: ui = 1.0; break;
+    // the coefficients c_k = (2 - delta_k0) (-i)^k J_k(a h) exp(-i b h) of a step of length h (J_k(-z) =
+    // (-1)^k J_k(z) for h < 0); 0 terms when the series needs more than cap
+    auto coefficients = [&](double h, int cap, std::vector<double>& cr, std::vector<double>& ci) {
+        std::vector<double> J;
+        const int nt = cheb_bessel(a * std::fabs(h), tol, cap, J);
+        cr.assign(nt, 0.0);
+        ci.assign(nt, 0.0);
+        const double pr = std::cos(b * h), pi = -std::sin(b * h);
+        for (int k = 0; k < nt; ++k) {
+            double w = (k == 0 ? 1.0 : 2.0) * J[k];
+            if (h < 0 && (k & 1)) w = -w;
+            double ur = 0.0, ui = 0.0;  // (-i)^k
+            switch (k & 3) {
+                case 0: ur = 1.0; break;
+                case 1: ui = -1.0; break;
+                case 2: ur = -1.0; break;
+                default: ui = 1.0; break;
+            }
+            cr[k] = w * (ur * pr - ui * pi);
+            ci[k] = w * (ur * pi + ui * pr);
         }
-        cr[k] = w * (ur * pr - ui * pi);
-        ci[k] = w * (ur * pi + ui * pr);
+        return nt;
+    };
+    // steps per series: 1, or for a fixed H (MRMF_TUNE_CHEB_MERGE) the largest q <= n_steps whose step
+    // q dt keeps the series within kMergeTerms terms (exp(-i H dt)^q = exp(-i H q dt); one truncation
+    // instead of q, and the terms grow about like a q |dt| rather than q times)
+    constexpr int kMergeTerms = 2048;
+    std::vector<double> cr, ci;
+    const int nt1 = coefficients(dt, 1 << 20, cr, ci);
+    if (nt1 == 0) return MRMF_E_UNSUPPORTED;
+    int q = 1;
+    if (theta_stride == 0 && plan->cfg[MRMF_DTYPE_Z].cheb_merge != 0 && n_steps > 1) {
+        std::vector<double> tr, ti;
+        for (q = n_steps; q > 1; q = (q + 1) / 2)
+            if (coefficients(q * dt, kMergeTerms, tr, ti) > 0) break;
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(d_scratch);
@@ -190,9 +211,19 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
     const int grid = prop_grid(n);
     // the specialized kernel with the Chebyshev-step epilogue does matvec and update in one pass (no
     // H phi vector written and read back); plans without a specialized kernel take the two-pass form
-    const bool fused = n_steps > 0 && nt > 1 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC &&
+    const bool fused = n_steps > 0 && nt1 > 1 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC &&
                        plan->cfg[MRMF_DTYPE_Z].cheb_fused != 0 && spec_prepare(plan, kSlotCheb) == MRMF_OK;
-    for (int st = 0; st < n_steps; ++st) {
+    int64_t total = 0;
+    int qcur = 0;  // steps of the series whose coefficients cr, ci hold
+    for (int st = 0; st < n_steps;) {
+        const int qs = std::min(q, n_steps - st);  // this series covers steps st .. st + qs - 1
+        if (qs != qcur) {
+            const int nt = coefficients(qs * dt, qs == 1 ? 1 << 20 : kMergeTerms, cr, ci);
+            if (nt == 0) return MRMF_E_UNSUPPORTED;
+            qcur = qs;
+        }
+        const int nt = static_cast<int>(cr.size());
+        total += nt;
         const double* th = plan->n_params > 0 ? d_theta + int64_t(st) * theta_stride : nullptr;
         const double2* state = st == 0 ? static_cast<const double2*>(d_x0) : x;
         double2* cur = v0;
@@ -218,7 +249,9 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
             cur = prev;
             prev = t;
         }
+        st += qs;
     }
+    if (h_n_terms) *h_n_terms = n_steps == 0 ? nt1 : static_cast<int32_t>(std::min<int64_t>(total, INT32_MAX));
     if (n_steps == 0 && d_x0 != d_x) return hip_status(hipMemcpyAsync(d_x, d_x0, vb, hipMemcpyDeviceToDevice, s));
     return MRMF_OK;
 }

@@ -202,7 +202,9 @@ class Plan:
         bounds = (e_min, e_max) must contain the spectrum of every step's H; default (None): the extreme
         Gershgorin ends over the steps' distinct theta rows (spectral_bounds), widened by a relative
         1e-9 against rounding; "norm": +-max over the steps of mrmf_plan_norm_bound (looser, host only).
-        Returns dict(x=..., n_terms=Chebyshev terms per step, bounds)."""
+        Returns dict(x=..., n_terms=Chebyshev terms over the whole call, bounds); with a fixed H the steps
+        are taken as one longer step where the series stays short (set_tuning(cheb_merge=0): one series per
+        step)."""
         _need_gpu(theta, "theta", torch.float64)
         _need_gpu(x0, "x0", torch.complex128)
         if x0.numel() != self.D:
@@ -268,7 +270,7 @@ class Plan:
 
     TUNING = {"schedule": 0, "branch_skip": 1, "load_group": 2, "blocks_per_cu": 3, "variant": 4, "addressing": 5,
               "cheb_fused": 6, "waves_per_eu": 7, "far_loads": 8, "grad_blocks_per_cu": 9,
-              "outer_first": 10, "unroll_top": 11, "far_dir": 12}
+              "outer_first": 10, "unroll_top": 11, "far_dir": 12, "cheb_merge": 13}
 
     def set_tuning(self, **knobs):
         """Tuning knobs of the specialized kernel: schedule (0 windows, 1 per-XCD chunks, 2 block runs),
@@ -280,7 +282,8 @@ class Plan:
         far_dir (which of those: 0 both directions, 1 sources behind the row, 2 ahead), grad_blocks_per_cu (blocks per CU of the adjoint's generated coupling-gradient
         kernel, 0 = default), outer_first (k = the k most significant sites vary fastest in the sweep
         over super-tiles, 0 = index order), unroll_top (k = sites 0..k-1 join the unrolled copies, so terms
-        between them and the low sites read LDS; 0 = off)."""
+        between them and the low sites read LDS; 0 = off), cheb_merge (1 = propagate takes consecutive
+        steps of a fixed H as one longer step, 0 = one Chebyshev series per step)."""
         for k, v in knobs.items():
             L.call("mrmf_plan_set_tuning", self._handle, self.TUNING[k], int(v))
 

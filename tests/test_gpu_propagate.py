@@ -118,6 +118,29 @@ def test_fused_step_matches_two_pass(k):
         assert rel_err(xa, oprop.propagate(m, x0, 0.2, 2)) <= 1e-11
 
 
+@pytest.mark.parametrize("steps", [2, 7, 401])
+def test_merged_steps_match_stepwise(steps):
+    """A fixed H's steps taken as longer steps (the default) against one series per step and against the
+    oracle; the merged run takes fewer Chebyshev terms in all.  401 steps of dt = 0.9 exceed what one
+    merged series may take (its terms are capped), so the run is split into series of fewer steps with a
+    shorter one at the end; the oracle there is one expm of the whole time 401 dt (the exponential of a
+    fixed H composes), the per-step product being too slow on the host."""
+    rng = np.random.default_rng(8400 + steps)
+    m = W.random_model(rng, n_sites=4, max_dim=400 if steps > 100 else 1200, n_params=2)
+    x0 = W.random_state(m.dim, rng)
+    dt = 0.9 if steps > 100 else 0.35
+    p = mk(m)
+    merged = p.propagate(t(m.theta), t(x0), dt, steps)
+    p.set_tuning(cheb_merge=0)
+    stepwise = p.propagate(t(m.theta), t(x0), dt, steps, bounds=merged["bounds"])
+    ref = oprop.propagate(m, x0, dt * steps, 1) if steps > 100 else oprop.propagate(m, x0, dt, steps)
+    xm, xs = merged["x"].cpu().numpy(), stepwise["x"].cpu().numpy()
+    print(f"steps {steps}: terms merged {merged['n_terms']} stepwise {stepwise['n_terms']}, "
+          f"bounds {merged['bounds']}, errors {rel_err(xm, ref):.2e} / {rel_err(xs, ref):.2e}", flush=True)
+    assert rel_err(xm, ref) <= 1e-11 and rel_err(xs, ref) <= 1e-9
+    assert merged["n_terms"] < stepwise["n_terms"]
+
+
 def test_propagate_errors():
     from paper_2606_02169_amd import _lib as L
     m = W.xx_chain_in_field(4, 1.0, 0.2)
