@@ -372,6 +372,11 @@ def test_general_operator_tables_against_products():
     want = [z @ z, z @ p, p @ z, z @ q, q @ z, p @ p, q @ q, p @ q, q @ p]
     for k, M in enumerate(want):
         assert np.allclose(kron.general_op(m, W.OP_LOCAL_BASE + k, 0), M, atol=1e-15, rtol=0)
+    # the input generator's spin matrices (the source of every general spin table) for s = 1/2 .. 3
+    for two_s in range(1, 7):
+        o = kron.local_ops(spin_site(two_s))
+        for got, op in zip(W.spin_matrices(two_s), (OP_Z, OP_RAISE, OP_LOWER)):
+            assert np.allclose(got, o[op], atol=1e-15, rtol=0), (two_s, op)
     rng = np.random.default_rng(17)
     for _ in range(6):
         g = W.random_general_model(rng, n_sites=4, max_dim=900)

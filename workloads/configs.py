@@ -175,7 +175,12 @@ def zero_field_splitting(two_s: int, Dz: float, E: float) -> Model:
 
 
 def spin_matrices(two_s: int):
-    """S_z, S_+, S_- of one spin as dense matrices (basis m = -s .. s, the digit order of Sec. III)."""
+    """S_z, S_+, S_- of one spin as dense matrices (basis m = -s .. s, the digit order of Sec. III).
+
+    Used only to write the value tables of general one-site operators, which are inputs handed alike to
+    the library and to the oracle; the built-in RAISE / LOWER operators never read them (the library and
+    the oracle each evaluate their own ladder elements).  The tables are checked against the oracle's
+    local operators and through the AKLT chain's exact ground energy."""
     s = two_s / 2.0
     m = np.arange(two_s + 1) - s
     up = np.zeros((two_s + 1, two_s + 1))
