@@ -88,6 +88,35 @@ def test_zero_start_vector():
     assert g["steps"] == 0 and np.isnan(g["theta"])
 
 
+@pytest.mark.parametrize("reorth", ["cgs2_cond", "partial"])
+def test_breakdown_and_zero_start_other_reorth(reorth):
+    """The conditional and partial forms stop like the full one: an eigenvector start breaks down after one
+    step with its exact energy, a zero start takes no step."""
+    m = W.ferrimagnetic_ring(8)
+    x = np.zeros(m.dim, dtype=np.complex128)
+    x[-1] = 1.0
+    g = run(m, x, 10, reorth=reorth)
+    assert g["steps"] == 1
+    assert abs(g["theta"] - mf.matvec(m, x)[-1].real) < 1e-14
+    z = run(m, np.zeros(m.dim, dtype=np.complex128), 5, reorth=reorth)
+    assert z["steps"] == 0 and np.isnan(z["theta"])
+
+
+@pytest.mark.parametrize("reorth", ["cgs2", "cgs2_cond", "partial"])
+def test_krylov_space_exhausted(reorth):
+    """More steps than the dimension (ferrimagnetic ring N = 4, D = 36, 80 steps): the recurrence breaks
+    down once the Krylov space is exhausted (a basis of at most D vectors), and the Ritz value is the
+    lowest eigenvalue of the oracle's dense H to rounding."""
+    m = W.ferrimagnetic_ring(4)
+    x = W.random_state(m.dim, np.random.default_rng(21))
+    g = run(m, x, 80, reorth=reorth)
+    ev = np.linalg.eigvalsh(__import__("oracle.kron", fromlist=["x"]).dense_H(m))[0]
+    print(f"{reorth}: steps {g['steps']} theta {g['theta']!r} exact {ev!r} residual {g['resid']:.2e}", flush=True)
+    assert 1 <= g["steps"] <= m.dim
+    assert abs(g["theta"] - ev) <= 1e-12 * abs(ev)
+    assert g["resid"] <= 1e-10
+
+
 def test_free_fermion_closed_form_large():
     """XX chain N=20 in a field (D = 2^20): E0 = sum_{eps_k<0} eps_k - N h/2, no oracle involved."""
     N, J, h = 20, 1.0, 0.25
