@@ -138,6 +138,32 @@ def cpu_baseline(model, x_host, rep_s: float = 3.0, one_core_rep_s: float = 2.0)
     return cb, rows, y_rows
 
 
+def cpu_lanczos_baseline(model, x_host, gpu_alpha=None, steps: int = 3):
+    """The oracle's FP64 Lanczos with full CGS2 on the host cores (its matvec on all the oracle's threads,
+    the Gram-Schmidt passes in numpy), on a bounded sample of the same run: the first `steps` steps from
+    the same start vector, after a one-step warm-up, as seconds per step.  The first steps have the
+    shortest Gram-Schmidt passes, so the figure is a lower bound on the oracle's time per step of a longer
+    run.  With the GPU's alpha_j of the same run, the largest difference over those steps is reported."""
+    import numpy as np
+    from oracle import lanczos as olz
+    from oracle import mf
+
+    def op(v):
+        return mf.matvec(model, v)
+
+    olz.lanczos(op, x_host, 1, explicit_residual=False)
+    t0 = time.perf_counter()
+    r = olz.lanczos(op, x_host, steps, explicit_residual=False)
+    dt = time.perf_counter() - t0
+    out = {"value": dt / steps, "unit": "s per Lanczos step", "kind": "oracle", "cores": mf.threads(),
+           "sample": f"the first {steps} steps of the same run (full CGS2), after a one-step warm-up; "
+                     f"{dt:.2f} s in all", **host_cpu_info()}
+    if gpu_alpha is not None:
+        k = min(steps, len(gpu_alpha))
+        out["max_abs_alpha_diff_vs_gpu"] = float(np.max(np.abs(np.asarray(gpu_alpha[:k]) - r["alpha"][:k])))
+    return out
+
+
 def oracle_residual(model, u, theta):
     """Oracle leg beside the CPU baseline: ||H u - theta u|| of a GPU Ritz vector u (host copy) with the
     oracle's H, and ||u||.  For Hermitian H an eigenvalue lies within ||H u - theta u|| / ||u|| of theta,
@@ -382,6 +408,10 @@ def bench_lanczos(args, dev):
     E_ref = ref["theta"]
     log(f"reference: {m_ref} FP64 steps, theta {E_ref!r} residual {ref['resid']:.3e} "
         f"(oracle {ref.get('oracle_residual', float('nan')):.3e}) in {ref['seconds']:.1f} s")
+    cpu_lz = None
+    if not (args.no_cpu_baseline or args.profile):
+        cpu_lz = cpu_lanczos_baseline(model, x32.astype(np.complex128), ref["alpha"])
+        log(f"oracle Lanczos on the host: {cpu_lz}")
     out = {"metric": "Lanczos ground energy: FP32 (c64) matvec in FP64 Lanczos vs plain FP64, time to 1e-5",
            "workload": "square4x4_spin1_periodic", "D": D, "seed": 3,
            "reference": {"steps": ref["steps"], "theta": E_ref, "residual": ref["resid"],
@@ -389,6 +419,8 @@ def bench_lanczos(args, dev):
                          "certified_within": (ref["oracle_residual"] / ref["u_norm"]) if "u_norm" in ref else None,
                          "reorth": args.lanczos_ref_reorth, "seconds": ref["seconds"]},
            "matvec_ms": {"c128": mv_z, "c64": mv_c}, "forms": {}}
+    if cpu_lz is not None:
+        out["cpu_baseline"] = cpu_lz
     m = args.lanczos_steps
     forms = args.lanczos_forms.split(",")
     for name, plan, prec, ro in (("fp64", pz, "z", "cgs2"), ("fp32_in_fp64", pc, "c_in_z", "cgs2"),
@@ -436,6 +468,10 @@ def bench_lanczos_ring(args, dev):
     model, x = W.config(2)
     D = model.dim
     v0 = torch.from_numpy(x).to(dev)
+    cpu_lz = None
+    if not (args.no_cpu_baseline or args.profile):
+        cpu_lz = cpu_lanczos_baseline(model, x)
+        log(f"oracle Lanczos on the host: {cpu_lz}")
     del x
     th64 = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
     th32 = th64.float()
@@ -443,6 +479,8 @@ def bench_lanczos_ring(args, dev):
     out = {"metric": "Lanczos on the 20-site ferrimagnetic ring (c128 basis): time per step and ground energy",
            "workload": "ferrimagnetic_ring_N20_c128", "D": D, "seed": 2, "steps": m,
            "basis_GB": (m + 1) * D * 16 / 1e9, "forms": {}}
+    if cpu_lz is not None:
+        out["cpu_baseline"] = cpu_lz
     forms = args.lanczos_forms.split(",")
     for name, prec, ro in (("fp64", "z", "cgs2"), ("fp32_in_fp64", "c_in_z", "cgs2"),
                            ("fp64_cgs2_cond", "z", "cgs2_cond"), ("fp32_in_fp64_cgs2_cond", "c_in_z", "cgs2_cond"),
