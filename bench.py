@@ -276,6 +276,7 @@ def bench_ring(args, dev):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_source": traffic_source,
                      "algorithmic_bytes_per_launch": alg_bytes, "mean_launch_ms": mean_launch_ms,
+                     "median_launch_ms": float(np.median(launch_ms)),
                      "kernel_fingerprint": fp, "copy_GBps": copy_GBps,
                      "frac_of_copy": achieved / copy_GBps if copy_GBps else None},
     }
