@@ -558,9 +558,10 @@ def bench_batched(args, dev):
     Y = torch.empty_like(X)
     th = torch.from_numpy(np.concatenate([m.theta for m in models]).astype(np.float32)).to(dev)
     if args.profile:
-        # a short run for profiler counters: the shape the autotuner selects for this workload on MI355X,
-        # warm-up and timed graph replays only
-        B.set_shape(512, 512, "windows")
+        # a short run for profiler counters: the tiles and block the autotuner selects for this workload on
+        # MI355X, with the window schedule it selects or another one (--batch-schedule); warm-up and timed
+        # graph replays only
+        B.set_shape(512, 512, args.batch_schedule)
         shape = B.shape()
     else:
         shape = B.autotune(th, X, Y)
@@ -884,6 +885,8 @@ def main():
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
     ap.add_argument("--lanczos-ref-reorth", default="cgs2", choices=["cgs2", "cgs2_cond", "partial"],
                     help="lanczos4x4: reorthogonalisation of the FP64 reference run")
+    ap.add_argument("--batch-schedule", default="windows", choices=["windows", "xcd_chunk", "runs"],
+                    help="work schedule of the batched leg under --profile (with the tiles the autotuner picks)")
     ap.add_argument("--lanczos-forms", default="cgs2,cgs2_cond,partial",
                     help="lanczos4x4 / lanczos_ring20: reorthogonalisations to time (comma list)")
     args = ap.parse_args()
