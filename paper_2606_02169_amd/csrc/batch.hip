@@ -43,7 +43,8 @@ constexpr int kBatchTileWords = 4096;  // 8-byte words of the LDS tile (32 KB): 
 constexpr int kBatchRmaxCands = 4;     // tile-row limits R_max = (64, 128, 256, 512) * 8 / nvec
 constexpr int kBatchMaxTerms = 128;    // terms (channels + diagonal) of one lattice, held in LDS
 constexpr int kBatchMaxParams = 128;   // couplings of one lattice, held in LDS
-constexpr int kBatchGather = 4;        // global-memory channels whose gathers are issued together
+constexpr int kBatchGather = 5;        // global-memory channels whose gathers are issued together (124 VGPRs:
+                                       // still 4 waves per SIMD; 6 or 8 fall to 3 or 2 and run slower)
 
 struct alignas(16) BLat {
     int32_t N, n_chan, n_diag, theta_off;
