@@ -135,6 +135,25 @@ def test_ring_sector_lanczos_reduced():
     assert passes < 40
 
 
+@pytest.mark.parametrize("reorth", ["cgs2", "partial"])
+def test_ring_sector_lanczos_fp32_form(reorth):
+    """Sector Lanczos with the c64 sector matvec inside the FP64 recurrence (the 12-site ring's S_z = 0
+    sector): the ground energy within 1e-5 of the oracle's FP64 sector Lanczos, and not below it by more
+    than FP32 rounding (no spurious level)."""
+    m, _ = W.config(2, reduced=12)
+    Q = Sector_digit_sum(m, 0.0)
+    lab = osec.labels(m, Q)
+    x = W.random_state(lab.size, np.random.default_rng(5))
+    S = sector(m, Q)
+    th = t(m.theta)
+    r = S.lanczos(th, t(x), 80, precision="c_in_z", reorth=reorth, theta_c=th.float())["result"].cpu().numpy()
+    o = olz.lanczos(lambda v: osec.matvec(m, Q, v, lab=lab), x, 80)
+    rel = (r[0] - o["theta"]) / abs(o["theta"])
+    print(f"sector fp32 form ({reorth}): {r[0]!r} oracle fp64 {o['theta']!r} rel {rel:.2e}", flush=True)
+    assert int(r[3]) == 80
+    assert abs(rel) <= 1e-5 and rel >= -1e-6
+
+
 def Sector_digit_sum(m, M):
     from paper_2606_02169_amd.plan import Sector
     return Sector.digit_sum_of(m.sites, M)
