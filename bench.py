@@ -13,8 +13,9 @@ Other workloads (one JSON line each; not part of the headline):
   --workload lanczos4x4  4x4 periodic spin-1 Heisenberg (D = 3^16): FP32 (c64) matvec inside the FP64
                          Lanczos against the plain FP64 form: steps and wall time to 1e-5 relative
                          ground-energy error, end to end and matvec only
-  --workload lanczos_ring20  100 CGS2 Lanczos steps on the headline ring (basis 97.7 GB), plain FP64 and
-                         FP32-in-FP64, beside the sector Lanczos energies of every digit sum
+  --workload lanczos_ring20  100 Lanczos steps on the headline ring (basis 97.7 GB), plain FP64 and
+                         FP32-in-FP64, each reorthogonalisation, beside the sector Lanczos energies of
+                         every digit sum
   --workload batched     256 open mixed chains x 8 c64 vectors in one persistent hipGraph launch,
                          against separate plain c64 and c128 calls per vector
   --workload adjoint     Tavis-Cummings (12 spins + boson cut at 64): forward and adjoint times and
@@ -23,6 +24,8 @@ Other workloads (one JSON line each; not part of the headline):
                          matvecs/s and a Lanczos ground state, beside the paper's CPU figures
   --workload propagate   Chebyshev time propagation on the ring: terms per step, time per term
   --workload sector      S_z = 0 sectors of the ring and of C1: sector matvec and sector Lanczos
+  --workload stream      stream ceilings of the GPU (standalone probe): reads by footprint and cache
+                         policy, copies, window gathers
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
@@ -807,6 +810,27 @@ def bench_sector(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------------------------------ stream ceilings
+def bench_stream(args, dev):
+    """Stream ceilings of this GPU from the standalone probe built beside the library (run as a child
+    process): reads of footprints from L2 size to HBM size with the default and the non-temporal cache
+    policy, copies, and 8-row window gathers of growing span.  These are the rates the gather kernels'
+    L2-miss traffic is compared with."""
+    import subprocess
+    from paper_2606_02169_amd.build import PROBE
+    if not os.path.exists(PROBE):
+        print(f"{PROBE} is missing: build with paper_2606_02169_amd.build.build()", file=sys.stderr)
+        sys.exit(1)
+    r = subprocess.run([PROBE], capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        print(r.stdout + r.stderr, file=sys.stderr)
+        sys.exit(r.returncode)
+    rows = [json.loads(line) for line in r.stdout.splitlines() if line.startswith("{")]
+    out = {"metric": "stream ceilings of one MI355X (GB/s): reads by footprint and cache policy, copy, "
+                     "window gathers", "lines": rows}
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------------------------------------ paper testbeds
 PAPER_TABLE1 = {  # Table I, matrix-free rows (CPU, model not stated, 60 threads): context only
     "spin1_ring_N15": {"matvecs_per_s": 6.137, "eigensolve_s": 29.28, "residual": 2.961e-10},
@@ -879,7 +903,8 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
     ap.add_argument("--workload", default="ring20", choices=["ring20", "torus", "lanczos4x4", "lanczos_ring20",
-                                                              "batched", "adjoint", "paper", "propagate", "sector"])
+                                                              "batched", "adjoint", "paper", "propagate", "sector",
+                                                              "stream"])
     ap.add_argument("--dtype", default=None, choices=["c64", "c128"], help="torus: one element type only")
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
@@ -902,7 +927,7 @@ def main():
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "torus": bench_torus, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
      "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
-     "sector": bench_sector}[args.workload](args, dev)
+     "sector": bench_sector, "stream": bench_stream}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

@@ -2,6 +2,8 @@
 
 Every translation unit under csrc/ is compiled to an object in _build/ (in parallel), then linked
 into paper_2606_02169_amd/libmrmf.so.  Device code is built with packed FP32 instructions disabled.
+The stream-ceiling probe (probe/stream_probe.hip, a standalone measurement program that bench.py runs)
+is built beside it as paper_2606_02169_amd/stream_probe.
 """
 from __future__ import annotations
 
@@ -20,6 +22,21 @@ ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+
+
+PROBE_SRC = os.path.join(HERE, "probe", "stream_probe.hip")
+PROBE = os.path.join(HERE, "stream_probe")
+
+
+def build_probe() -> str:
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, "-x", "hip", "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on the stream probe:\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 def sources():
@@ -41,7 +58,9 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        probe = ex.submit(build_probe)
         objs = list(ex.map(_compile, srcs))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
