@@ -460,6 +460,20 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
                                 const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
                                 const void* d_v0, void* d_V, double* d_alpha, double* d_beta, double* d_result,
                                 void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+/* Time propagation inside the sector, x = exp(-i P H P^T dt)^n_steps x0 on packed vectors (the restricted
+ * basis as the way to shrink the propagated state, Sec. VI and Sec. VIII): the arguments, the Chebyshev
+ * series, the merging of fixed-H steps (as the plan's MRMF_TUNE_CHEB_MERGE was when the sector was made)
+ * and the Hermiticity requirement of mrmf_propagate_z, with vectors of the sector's dimension; each term is
+ * one sector matvec and one fused vector update.  Since H keeps the digit sum, P H P^T is H on the sector
+ * and this equals the full-basis propagation of a vector supported on the sector.  The spectrum of P H P^T
+ * lies inside that of H (Cauchy interlacing), so the plan's bounds (mrmf_spectral_bounds,
+ * mrmf_plan_norm_bound) serve.  d_scratch: mrmf_sector_propagate_scratch_bytes (three sector vectors),
+ * 256-B aligned. */
+mrmf_status mrmf_sector_propagate_scratch_bytes(mrmf_sector sector, size_t* bytes);
+mrmf_status mrmf_sector_propagate_z(mrmf_sector sector, const void* d_ws, const double* d_theta, int64_t theta_stride,
+                                    double dt, int32_t n_steps, double e_min, double e_max, double tol,
+                                    const void* d_x0, void* d_x, void* d_scratch, size_t scratch_bytes,
+                                    int32_t* h_n_terms, mrmf_stream stream);
 
 /* Batched form: n independent lattices (plans), each applied to a block of nvec c64 vectors stored
  * row-major as [D_b][nvec] (row F of lattice b holds its nvec amplitudes contiguously), all in one

@@ -126,6 +126,9 @@ SIGNATURES = {
     "mrmf_sector_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),
     "mrmf_sector_lanczos": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _sz, _vp]),
+    "mrmf_sector_propagate_scratch_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_sector_propagate_z": (_i32, [_vp, _vp, _vp, _i64, ctypes.c_double, _i32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _sz, _P(_i32), _vp]),
     "mrmf_batch_create": (_i32, [_i32, _P(_vp), _i32, _P(_vp)]),
     "mrmf_batch_destroy": (None, [_vp]),
     "mrmf_batch_total_elems": (_i32, [_vp, _P(_i64)]),

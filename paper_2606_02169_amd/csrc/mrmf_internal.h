@@ -198,6 +198,7 @@ struct mrmf_sector_t {
     int32_t blocks_per_cu = 0;        // blocks per CU of the generated kernel's grid (0: as many as fit)
     int32_t group = 0;                // gathers issued together by the generated kernel (0: default)
     int32_t sched = 0;                // MRMF_SCHED_* of the generated kernel's rows over the XCDs
+    int32_t cheb_merge = 1;           // propagation: consecutive steps of a fixed H as one longer step
     mrmf::SpecKernel gen[2];          // generated sector kernels, c128 and c64
     std::mutex mtx;
     ~mrmf_sector_t();
@@ -255,6 +256,19 @@ mrmf_status lanczos_scratch_bytes(int64_t D, int32_t m, int32_t precision, size_
 mrmf_status lanczos_run(int64_t D, const MatvecOp& mv_z, const MatvecOp& mv_c, int32_t precision, int32_t m,
                         int32_t reorth, const void* d_v0, void* d_V, double* d_alpha, double* d_beta,
                         double* d_result, void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+// Time propagation (the Chebyshev series of mrmf_propagate_z) for any Hermitian map of dimension n: mv
+// applies it with the couplings of the current step (theta null when there are none); step, when not null,
+// is a fused Chebyshev step (p = ea H cur + eb cur + eg prev; prev = p; acc += (cr + i ci) p), used when
+// fused_ready() returns true; merge: consecutive steps of a fixed map are taken as one longer step.
+using ThetaMatvecOp = std::function<mrmf_status(const double* theta, const void* x, void* y, hipStream_t s)>;
+using ChebStepOp = std::function<mrmf_status(const double* theta, const void* cur, void* prev, void* acc,
+                                             double ea, double eb, double eg, double cr, double ci, hipStream_t s)>;
+size_t propagate_scratch_bytes(int64_t n);
+mrmf_status propagate_run(int64_t n, int32_t n_params, const ThetaMatvecOp& mv, const ChebStepOp* step,
+                          const std::function<bool()>& fused_ready, bool merge, const double* d_theta,
+                          int64_t theta_stride, double dt, int32_t n_steps, double e_min, double e_max, double tol,
+                          const void* d_x0, void* d_x, void* d_scratch, size_t scratch_bytes, int32_t* h_n_terms,
+                          hipStream_t s);
 // Generated source of the specialized kernel (no device needed); "" when the plan does not qualify.
 std::string spec_source(const mrmf_plan_t* p, int dtype, Tile* tl, bool epi = false);
 // Fused Chebyshev step (time propagation) with the specialized c128 kernel:

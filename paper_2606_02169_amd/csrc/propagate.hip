@@ -107,6 +107,112 @@ int cheb_bessel(double z, double tol, int cap, std::vector<double>& J) {
     return K + 1;
 }
 
+size_t propagate_scratch_bytes(int64_t n) { return 3 * (size_t(n) * 16 + 256); }
+
+mrmf_status propagate_run(int64_t n, int32_t n_params, const ThetaMatvecOp& mv, const ChebStepOp* step,
+                          const std::function<bool()>& fused_ready, bool merge, const double* d_theta,
+                          int64_t theta_stride, double dt, int32_t n_steps, double e_min, double e_max, double tol,
+                          const void* d_x0, void* d_x, void* d_scratch, size_t scratch_bytes, int32_t* h_n_terms,
+                          hipStream_t s) {
+    if (!d_x0 || !d_x || !d_scratch) return MRMF_E_INVALID_ARG;
+    if (n_steps < 0 || theta_stride < 0 || !std::isfinite(dt) || !std::isfinite(e_min) || !std::isfinite(e_max) ||
+        !(e_max > e_min) || !(tol > 0.0) || !(tol < 1.0))
+        return MRMF_E_INVALID_ARG;
+    if (!aligned(d_x0, 16) || !aligned(d_x, 16) || !aligned(d_scratch, 256)) return MRMF_E_INVALID_ARG;
+    const size_t vb = size_t(n) * 16;
+    const size_t need = propagate_scratch_bytes(n);
+    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
+    if ((d_x0 != d_x && ranges_overlap(d_x0, vb, d_x, vb)) || ranges_overlap(d_scratch, need, d_x, vb) ||
+        ranges_overlap(d_scratch, need, d_x0, vb))
+        return MRMF_E_INVALID_ARG;
+    const double a = 0.5 * (e_max - e_min), b = 0.5 * (e_max + e_min);
+    // the coefficients c_k = (2 - delta_k0) (-i)^k J_k(a h) exp(-i b h) of a step of length h (J_k(-z) =
+    // (-1)^k J_k(z) for h < 0); 0 terms when the series needs more than cap
+    auto coefficients = [&](double h, int cap, std::vector<double>& cr, std::vector<double>& ci) {
+        std::vector<double> J;
+        const int nt = cheb_bessel(a * std::fabs(h), tol, cap, J);
+        cr.assign(nt, 0.0);
+        ci.assign(nt, 0.0);
+        const double pr = std::cos(b * h), pi = -std::sin(b * h);
+        for (int k = 0; k < nt; ++k) {
+            double w = (k == 0 ? 1.0 : 2.0) * J[k];
+            if (h < 0 && (k & 1)) w = -w;
+            double ur = 0.0, ui = 0.0;  // (-i)^k
+            switch (k & 3) {
+                case 0: ur = 1.0; break;
+                case 1: ui = -1.0; break;
+                case 2: ur = -1.0; break;
+                default: ui = 1.0; break;
+            }
+            cr[k] = w * (ur * pr - ui * pi);
+            ci[k] = w * (ur * pi + ui * pr);
+        }
+        return nt;
+    };
+    // steps per series: 1, or for a fixed H (merge) the largest q <= n_steps whose step q dt keeps the
+    // series within kMergeTerms terms (exp(-i H dt)^q = exp(-i H q dt); one truncation instead of q, and
+    // the terms grow about like a q |dt| rather than q times)
+    constexpr int kMergeTerms = 2048;
+    std::vector<double> cr, ci;
+    const int nt1 = coefficients(dt, 1 << 20, cr, ci);
+    if (nt1 == 0) return MRMF_E_UNSUPPORTED;
+    int q = 1;
+    if (theta_stride == 0 && merge && n_steps > 1) {
+        std::vector<double> tr, ti;
+        for (q = n_steps; q > 1; q = (q + 1) / 2)
+            if (coefficients(q * dt, kMergeTerms, tr, ti) > 0) break;
+    }
+    char* base = static_cast<char*>(d_scratch);
+    const size_t slot = vb + 256 - (vb % 256 ? vb % 256 : 256);  // 256-B aligned slots
+    double2* v0 = reinterpret_cast<double2*>(base);
+    double2* v1 = reinterpret_cast<double2*>(base + slot);
+    double2* hv = reinterpret_cast<double2*>(base + 2 * slot);
+    double2* x = static_cast<double2*>(d_x);
+    const int grid = prop_grid(n);
+    const bool fused = step != nullptr && n_steps > 0 && nt1 > 1 && fused_ready();
+    int64_t total = 0;
+    int qcur = 0;  // steps of the series whose coefficients cr, ci hold
+    for (int st = 0; st < n_steps;) {
+        const int qs = std::min(q, n_steps - st);  // this series covers steps st .. st + qs - 1
+        if (qs != qcur) {
+            const int nt = coefficients(qs * dt, qs == 1 ? 1 << 20 : kMergeTerms, cr, ci);
+            if (nt == 0) return MRMF_E_UNSUPPORTED;
+            qcur = qs;
+        }
+        const int nt = static_cast<int>(cr.size());
+        total += nt;
+        const double* th = n_params > 0 ? d_theta + int64_t(st) * theta_stride : nullptr;
+        const double2* state = st == 0 ? static_cast<const double2*>(d_x0) : x;
+        double2* cur = v0;
+        double2* prev = v1;
+        hipLaunchKernelGGL(k_cheb_init, dim3(grid), dim3(kPB), 0, s, n, state, cur, prev, x, cr[0], ci[0]);
+        mrmf_status rc = launch_status();
+        if (rc != MRMF_OK) return rc;
+        for (int k = 1; k < nt; ++k) {
+            const bool first = k == 1;
+            const double ea = (first ? 1.0 : 2.0) / a, eb = -(first ? 1.0 : 2.0) * b / a, eg = first ? 0.0 : -1.0;
+            if (fused) {
+                rc = (*step)(th, cur, prev, x, ea, eb, eg, cr[k], ci[k], s);
+                if (rc != MRMF_OK) return rc;
+            } else {
+                rc = mv(th, cur, hv, s);
+                if (rc != MRMF_OK) return rc;
+                hipLaunchKernelGGL(k_cheb_update, dim3(grid), dim3(kPB), 0, s, n, hv, cur, prev, x, ea, eb, eg,
+                                   first ? 0 : 1, cr[k], ci[k]);
+                rc = launch_status();
+                if (rc != MRMF_OK) return rc;
+            }
+            double2* t = cur;
+            cur = prev;
+            prev = t;
+        }
+        st += qs;
+    }
+    if (h_n_terms) *h_n_terms = n_steps == 0 ? nt1 : static_cast<int32_t>(std::min<int64_t>(total, INT32_MAX));
+    if (n_steps == 0 && d_x0 != d_x) return hip_status(hipMemcpyAsync(d_x, d_x0, vb, hipMemcpyDeviceToDevice, s));
+    return MRMF_OK;
+}
+
 }  // namespace mrmf
 
 using namespace mrmf;
@@ -141,7 +247,7 @@ mrmf_status mrmf_cheb_bessel(double z, double tol, int32_t cap, double* h_out, i
 
 mrmf_status mrmf_propagate_scratch_bytes(mrmf_plan plan, size_t* bytes) {
     if (!plan || !bytes) return MRMF_E_INVALID_ARG;
-    *bytes = 3 * (size_t(plan->D) * 16 + 256);
+    *bytes = propagate_scratch_bytes(plan->D);
     return MRMF_OK;
 }
 
@@ -149,111 +255,25 @@ mrmf_status mrmf_propagate_z(mrmf_plan plan, const void* d_ws, const double* d_t
                              double dt, int32_t n_steps, double e_min, double e_max, double tol, const void* d_x0,
                              void* d_x, void* d_scratch, size_t scratch_bytes, int32_t* h_n_terms,
                              mrmf_stream stream) {
-    if (!plan || !d_ws || !d_x0 || !d_x || !d_scratch || (plan->n_params > 0 && !d_theta)) return MRMF_E_INVALID_ARG;
-    if (n_steps < 0 || theta_stride < 0 || !std::isfinite(dt) || !std::isfinite(e_min) || !std::isfinite(e_max) ||
-        !(e_max > e_min) || !(tol > 0.0) || !(tol < 1.0))
-        return MRMF_E_INVALID_ARG;
+    if (!plan || !d_ws || (plan->n_params > 0 && !d_theta)) return MRMF_E_INVALID_ARG;
     if (!plan->hermitian) return MRMF_E_NOT_HERMITIAN;
-    if (!aligned(d_ws, 256) || !aligned(d_x0, 16) || !aligned(d_x, 16) || !aligned(d_scratch, 256))
-        return MRMF_E_INVALID_ARG;
-    const size_t vb = size_t(plan->D) * 16;
-    size_t need = 0;
-    mrmf_propagate_scratch_bytes(plan, &need);
-    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
-    if ((d_x0 != d_x && ranges_overlap(d_x0, vb, d_x, vb)) || ranges_overlap(d_scratch, need, d_x, vb) ||
-        ranges_overlap(d_scratch, need, d_x0, vb))
-        return MRMF_E_INVALID_ARG;
-    const double a = 0.5 * (e_max - e_min), b = 0.5 * (e_max + e_min);
-    // the coefficients c_k = (2 - delta_k0) (-i)^k J_k(a h) exp(-i b h) of a step of length h (J_k(-z) =
-    // (-1)^k J_k(z) for h < 0); 0 terms when the series needs more than cap
-    auto coefficients = [&](double h, int cap, std::vector<double>& cr, std::vector<double>& ci) {
-        std::vector<double> J;
-        const int nt = cheb_bessel(a * std::fabs(h), tol, cap, J);
-        cr.assign(nt, 0.0);
-        ci.assign(nt, 0.0);
-        const double pr = std::cos(b * h), pi = -std::sin(b * h);
-        for (int k = 0; k < nt; ++k) {
-            double w = (k == 0 ? 1.0 : 2.0) * J[k];
-            if (h < 0 && (k & 1)) w = -w;
-            double ur = 0.0, ui = 0.0;  // (-i)^k
-            switch (k & 3) {
-                case 0: ur = 1.0; break;
-                case 1: ui = -1.0; break;
-                case 2: ur = -1.0; break;
-                default: ui = 1.0; break;
-            }
-            cr[k] = w * (ur * pr - ui * pi);
-            ci[k] = w * (ur * pi + ui * pr);
-        }
-        return nt;
+    if (!aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
+    const ThetaMatvecOp mv = [&](const double* th, const void* x, void* y, hipStream_t s) {
+        return matvec_z_impl(plan, d_ws, th, x, y, s, nullptr);
     };
-    // steps per series: 1, or for a fixed H (MRMF_TUNE_CHEB_MERGE) the largest q <= n_steps whose step
-    // q dt keeps the series within kMergeTerms terms (exp(-i H dt)^q = exp(-i H q dt); one truncation
-    // instead of q, and the terms grow about like a q |dt| rather than q times)
-    constexpr int kMergeTerms = 2048;
-    std::vector<double> cr, ci;
-    const int nt1 = coefficients(dt, 1 << 20, cr, ci);
-    if (nt1 == 0) return MRMF_E_UNSUPPORTED;
-    int q = 1;
-    if (theta_stride == 0 && plan->cfg[MRMF_DTYPE_Z].cheb_merge != 0 && n_steps > 1) {
-        std::vector<double> tr, ti;
-        for (q = n_steps; q > 1; q = (q + 1) / 2)
-            if (coefficients(q * dt, kMergeTerms, tr, ti) > 0) break;
-    }
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    char* base = static_cast<char*>(d_scratch);
-    const size_t slot = vb + 256 - (vb % 256 ? vb % 256 : 256);  // 256-B aligned slots
-    double2* v0 = reinterpret_cast<double2*>(base);
-    double2* v1 = reinterpret_cast<double2*>(base + slot);
-    double2* hv = reinterpret_cast<double2*>(base + 2 * slot);
-    double2* x = static_cast<double2*>(d_x);
-    const int64_t n = plan->D;
-    const int grid = prop_grid(n);
     // the specialized kernel with the Chebyshev-step epilogue does matvec and update in one pass (no
     // H phi vector written and read back); plans without a specialized kernel take the two-pass form
-    const bool fused = n_steps > 0 && nt1 > 1 && plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC &&
-                       plan->cfg[MRMF_DTYPE_Z].cheb_fused != 0 && spec_prepare(plan, kSlotCheb) == MRMF_OK;
-    int64_t total = 0;
-    int qcur = 0;  // steps of the series whose coefficients cr, ci hold
-    for (int st = 0; st < n_steps;) {
-        const int qs = std::min(q, n_steps - st);  // this series covers steps st .. st + qs - 1
-        if (qs != qcur) {
-            const int nt = coefficients(qs * dt, qs == 1 ? 1 << 20 : kMergeTerms, cr, ci);
-            if (nt == 0) return MRMF_E_UNSUPPORTED;
-            qcur = qs;
-        }
-        const int nt = static_cast<int>(cr.size());
-        total += nt;
-        const double* th = plan->n_params > 0 ? d_theta + int64_t(st) * theta_stride : nullptr;
-        const double2* state = st == 0 ? static_cast<const double2*>(d_x0) : x;
-        double2* cur = v0;
-        double2* prev = v1;
-        hipLaunchKernelGGL(k_cheb_init, dim3(grid), dim3(kPB), 0, s, n, state, cur, prev, x, cr[0], ci[0]);
-        mrmf_status rc = launch_status();
-        if (rc != MRMF_OK) return rc;
-        for (int k = 1; k < nt; ++k) {
-            const bool first = k == 1;
-            const double ea = (first ? 1.0 : 2.0) / a, eb = -(first ? 1.0 : 2.0) * b / a, eg = first ? 0.0 : -1.0;
-            if (fused) {
-                rc = spec_launch_cheb(plan, th, cur, prev, x, ea, eb, eg, cr[k], ci[k], s);
-                if (rc != MRMF_OK) return rc;
-            } else {
-                rc = matvec_z_impl(plan, d_ws, th, cur, hv, s, nullptr);
-                if (rc != MRMF_OK) return rc;
-                hipLaunchKernelGGL(k_cheb_update, dim3(grid), dim3(kPB), 0, s, n, hv, cur, prev, x, ea, eb, eg,
-                                   first ? 0 : 1, cr[k], ci[k]);
-                rc = launch_status();
-                if (rc != MRMF_OK) return rc;
-            }
-            double2* t = cur;
-            cur = prev;
-            prev = t;
-        }
-        st += qs;
-    }
-    if (h_n_terms) *h_n_terms = n_steps == 0 ? nt1 : static_cast<int32_t>(std::min<int64_t>(total, INT32_MAX));
-    if (n_steps == 0 && d_x0 != d_x) return hip_status(hipMemcpyAsync(d_x, d_x0, vb, hipMemcpyDeviceToDevice, s));
-    return MRMF_OK;
+    const ChebStepOp step = [&](const double* th, const void* cur, void* prev, void* acc, double ea, double eb,
+                                double eg, double cr, double ci, hipStream_t s) {
+        return spec_launch_cheb(plan, th, cur, prev, acc, ea, eb, eg, cr, ci, s);
+    };
+    const auto fused_ready = [&]() {
+        return plan->cfg[MRMF_DTYPE_Z].mode != MRMF_KERNEL_GENERIC && plan->cfg[MRMF_DTYPE_Z].cheb_fused != 0 &&
+               spec_prepare(plan, kSlotCheb) == MRMF_OK;
+    };
+    return propagate_run(plan->D, plan->n_params, mv, &step, fused_ready, plan->cfg[MRMF_DTYPE_Z].cheb_merge != 0,
+                         d_theta, theta_stride, dt, n_steps, e_min, e_max, tol, d_x0, d_x, d_scratch, scratch_bytes,
+                         h_n_terms, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

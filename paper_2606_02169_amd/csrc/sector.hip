@@ -419,6 +419,7 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->blocks_per_cu = plan->cfg[MRMF_DTYPE_Z].blocks_per_cu;
     S->group = plan->cfg[MRMF_DTYPE_Z].group;
     S->sched = plan->cfg[MRMF_DTYPE_Z].sched;
+    S->cheb_merge = plan->cfg[MRMF_DTYPE_Z].cheb_merge;
     auto add_fac = [&](int site, int op) {
         for (int n = 0; n < plan->d[site]; ++n) S->tfac.push_back(local_factor_host(plan, site, op, n));
     };
@@ -608,6 +609,27 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
     };
     return lanczos_run(sector->Dr, mv_z, mv_c, precision, m, reorth, d_v0, d_V, d_alpha, d_beta, d_result, d_u,
                        d_scratch, scratch_bytes, stream);
+}
+
+mrmf_status mrmf_sector_propagate_scratch_bytes(mrmf_sector sector, size_t* bytes) {
+    if (!sector || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = propagate_scratch_bytes(sector->Dr);
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_sector_propagate_z(mrmf_sector sector, const void* d_ws, const double* d_theta, int64_t theta_stride,
+                                    double dt, int32_t n_steps, double e_min, double e_max, double tol,
+                                    const void* d_x0, void* d_x, void* d_scratch, size_t scratch_bytes,
+                                    int32_t* h_n_terms, mrmf_stream stream) {
+    if (!sector || !d_ws || (sector->n_params > 0 && !d_theta) || !aligned(d_ws, 256)) return MRMF_E_INVALID_ARG;
+    // the series needs the spectrum of P H P^T inside [e_min, e_max]: real, i.e. P H P^T Hermitian
+    if (!sector->hermitian) return MRMF_E_NOT_HERMITIAN;
+    const ThetaMatvecOp mv = [&](const double* th, const void* x, void* y, hipStream_t s) {
+        return sector_matvec<double>(sector, d_ws, th, x, y, s, nullptr);
+    };
+    return propagate_run(sector->Dr, sector->n_params, mv, nullptr, [] { return false; }, sector->cheb_merge != 0,
+                         d_theta, theta_stride, dt, n_steps, e_min, e_max, tol, d_x0, d_x, d_scratch, scratch_bytes,
+                         h_n_terms, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

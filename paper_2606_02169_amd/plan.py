@@ -205,10 +205,25 @@ class Plan:
         Returns dict(x=..., n_terms=Chebyshev terms over the whole call, bounds); with a fixed H the steps
         are taken as one longer step where the series stays short (set_tuning(cheb_merge=0): one series per
         step)."""
-        _need_gpu(theta, "theta", torch.float64)
         _need_gpu(x0, "x0", torch.complex128)
         if x0.numel() != self.D:
             raise ValueError("x0 has the wrong length")
+        stride, bounds = self._propagation_args(theta, n_steps, bounds)
+        x = torch.empty_like(x0) if out is None else out
+        _need_gpu(x, "out", torch.complex128)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_propagate_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        nt = ctypes.c_int32()
+        L.call("mrmf_propagate_z", self._handle, _ptr(self.ws), _ptr(theta), int(stride), float(dt), int(n_steps),
+               float(bounds[0]), float(bounds[1]), float(tol), _ptr(x0), _ptr(x), _ptr(scratch), nb.value,
+               ctypes.byref(nt), _stream(self.device))
+        return dict(x=x, n_terms=int(nt.value), bounds=tuple(bounds), scratch=scratch)
+
+    def _propagation_args(self, theta: torch.Tensor, n_steps: int, bounds) -> tuple:
+        """(theta_stride, (e_min, e_max)) of a propagation call: the stride from theta's shape and the
+        bounds as described in propagate()."""
+        _need_gpu(theta, "theta", torch.float64)
         stride = 0
         if theta.dim() == 2:
             if theta.shape[0] < n_steps or theta.shape[1] != self.n_params:
@@ -237,16 +252,7 @@ class Plan:
                 bounds = (lo - pad, hi + pad)
             else:
                 raise ValueError(f"unknown bounds {bounds!r}")
-        x = torch.empty_like(x0) if out is None else out
-        _need_gpu(x, "out", torch.complex128)
-        nb = ctypes.c_size_t()
-        L.call("mrmf_propagate_scratch_bytes", self._handle, ctypes.byref(nb))
-        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        nt = ctypes.c_int32()
-        L.call("mrmf_propagate_z", self._handle, _ptr(self.ws), _ptr(theta), int(stride), float(dt), int(n_steps),
-               float(bounds[0]), float(bounds[1]), float(tol), _ptr(x0), _ptr(x), _ptr(scratch), nb.value,
-               ctypes.byref(nt), _stream(self.device))
-        return dict(x=x, n_terms=int(nt.value), bounds=tuple(bounds), scratch=scratch)
+        return stride, tuple(bounds)
 
     # ------------------------------------------------------------------ Lanczos
     def lanczos(self, theta: torch.Tensor, v0: torch.Tensor, m: int, precision: str = "z",
@@ -512,6 +518,7 @@ class Sector:
         self.device = plan.device
         self.n_params = plan.n_params
         self.digit_sum = int(digit_sum)
+        self._plan = plan   # spectral bounds for propagate()
         self._handle = ctypes.c_void_p()
         L.call("mrmf_sector_create", plan.handle, self.digit_sum, ctypes.byref(self._handle))
         n = ctypes.c_int64()
@@ -584,3 +591,22 @@ class Sector:
         """Lowest eigenpair in the sector (mrmf_sector_lanczos); the results of Plan.lanczos."""
         return _lanczos("mrmf_sector_lanczos", self._handle, self.ws, self.dim, self.device, theta, v0, m,
                         precision, reorth, theta_c, keep_basis)
+
+    def propagate(self, theta: torch.Tensor, x0: torch.Tensor, dt: float, n_steps: int = 1,
+                  bounds: tuple | str | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
+        """x = exp(-i P H P^T dt)^n_steps x0 on packed sector vectors (mrmf_sector_propagate_z); theta,
+        bounds and the result as in Plan.propagate (the plan's bounds contain the sector's spectrum)."""
+        _need_gpu(x0, "x0", torch.complex128)
+        if x0.numel() != self.dim:
+            raise ValueError("x0 has the wrong length")
+        stride, bounds = self._plan._propagation_args(theta, n_steps, bounds)
+        x = torch.empty_like(x0) if out is None else out
+        _need_gpu(x, "out", torch.complex128)
+        nb = ctypes.c_size_t()
+        L.call("mrmf_sector_propagate_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        nt = ctypes.c_int32()
+        L.call("mrmf_sector_propagate_z", self._handle, _ptr(self.ws), _ptr(theta), int(stride), float(dt),
+               int(n_steps), float(bounds[0]), float(bounds[1]), float(tol), _ptr(x0), _ptr(x), _ptr(scratch),
+               nb.value, ctypes.byref(nt), _stream(self.device))
+        return dict(x=x, n_terms=int(nt.value), bounds=tuple(bounds), scratch=scratch)
