@@ -798,6 +798,26 @@ def bench_sector(args, dev):
         plan.autotune(th, xf)
         yf = torch.empty_like(xf)
         ms_full = cuda_time(lambda: plan.matvec(th, xf, out=yf), stream, 20)
+        # time propagation, 4 steps of dt = 0.05, in the sector and on the full basis (a vector supported
+        # on the sector, so both compute the same state), with the same bounds
+        xf.zero_()
+        xf[S.labels()] = xt
+        prop = {}
+        for where, fn in (("sector", lambda b: S.propagate(th, xt, 0.05, 4, bounds=b)),
+                          ("full_basis", lambda b: plan.propagate(th, xf, 0.05, 4, bounds=b))):
+            b = fn(None)["bounds"] if where == "sector" else prop["sector"]["bounds"]
+            fn(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn(b)
+            torch.cuda.synchronize()
+            dt_p = time.perf_counter() - t0
+            prop[where] = {"seconds": dt_p, "terms": r["n_terms"], "ms_per_term": dt_p / r["n_terms"] * 1e3,
+                           "bounds": list(b)}
+            if where == "sector":
+                ys_prop = r["x"]
+            else:
+                prop["max_abs_diff_on_sector"] = float((r["x"][S.labels()] - ys_prop).abs().max())
         del xf, yf
         torch.cuda.empty_cache()
         out["cases"][name] = {
@@ -805,7 +825,7 @@ def bench_sector(args, dev):
             "sector_matvecs_per_s": 1000.0 / ms, "sector_rows_per_s": S.dim / ms * 1e3,
             "sector_effective_GBps": 2 * S.dim * 16 / ms / 1e6, "full_matvec_ms": ms_full,
             "sampled_rel_err_vs_oracle": err,
-            "lanczos": lzs["cgs2"], "lanczos_partial_reorth": lzs["partial"]}
+            "lanczos": lzs["cgs2"], "lanczos_partial_reorth": lzs["partial"], "propagate_4x0.05": prop}
         log(f"{name}: {out['cases'][name]}")
     print(json.dumps(out), flush=True)
 
