@@ -349,3 +349,55 @@ def test_noalloc_adjoint_size_limit():
         assert fn(None, f[0], f[1], f[2], f[3], f[4], f[0], None) == L.MRMF_E_INVALID_ARG
     finally:
         L.lib().mrmf_plan_destroy(h)
+
+
+def test_propagate_argument_checks():
+    """mrmf_propagate_z and mrmf_sector_propagate_z refuse, before any launch, a group that is not
+    Hermitian, a scratch smaller than their size query (three vectors), bounds that are not an interval, a
+    tolerance outside (0, 1), misaligned or overlapping vectors (the pointers below are distinct, aligned
+    and never dereferenced)."""
+    from workloads.model import OP_LOWER, OP_RAISE, Model, Term, spin_site
+    ptr = [ctypes.c_void_p((1 << 40) + (k << 34)) for k in range(4)]   # ws, x0, x, scratch
+    nh = Model([spin_site(1)] * 3, [Term(0, OP_RAISE, 1, OP_LOWER, 0, 1.0)], np.ones(1))
+    st, h = host_plan(nh, require_hermitian=False)
+    sec = ctypes.c_void_p()
+    try:
+        L.call("mrmf_sector_create", h, 1, ctypes.byref(sec))
+        for fn, obj in (("mrmf_propagate_z", h), ("mrmf_sector_propagate_z", sec)):
+            assert getattr(L.lib(), fn)(obj, ptr[0], ptr[0], 0, 0.1, 2, -1.0, 1.0, 1e-12, ptr[1], ptr[2], ptr[3],
+                                        1 << 30, None, None) == L.MRMF_E_NOT_HERMITIAN
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
+    m = W.ferrimagnetic_ring(8)
+    st, h = host_plan(m)
+    assert st == 0
+    sec = ctypes.c_void_p()
+    try:
+        from paper_2606_02169_amd.plan import Sector
+        L.call("mrmf_sector_create", h, Sector.digit_sum_of(m.sites, 0.0), ctypes.byref(sec))
+        dim = ctypes.c_int64()
+        L.call("mrmf_sector_dim", sec, ctypes.byref(dim))
+        for fn, qfn, obj, n in (("mrmf_propagate_z", "mrmf_propagate_scratch_bytes", h, m.dim),
+                                ("mrmf_sector_propagate_z", "mrmf_sector_propagate_scratch_bytes", sec, dim.value)):
+            need = ctypes.c_size_t()
+            L.call(qfn, obj, ctypes.byref(need))
+            assert need.value == 3 * (n * 16 + 256)
+            f = getattr(L.lib(), fn)
+
+            def call(dt=0.1, steps=2, lo=-30.0, hi=30.0, tol=1e-12, x0=ptr[1], x=ptr[2], scratch=ptr[3],
+                     nbytes=need.value):
+                return f(obj, ptr[0], ptr[0], 0, dt, steps, lo, hi, tol, x0, x, scratch, nbytes, None, None)
+
+            assert call(nbytes=need.value - 1) == L.MRMF_E_WORKSPACE
+            assert call(lo=1.0, hi=1.0) == L.MRMF_E_INVALID_ARG
+            assert call(tol=0.0) == L.MRMF_E_INVALID_ARG and call(tol=1.0) == L.MRMF_E_INVALID_ARG
+            assert call(steps=-1) == L.MRMF_E_INVALID_ARG and call(dt=float("nan")) == L.MRMF_E_INVALID_ARG
+            assert call(x0=ctypes.c_void_p(ptr[1].value + 8)) == L.MRMF_E_INVALID_ARG
+            assert call(x=ctypes.c_void_p(ptr[1].value + 16)) == L.MRMF_E_INVALID_ARG   # partly overlaps x0
+            assert call(scratch=ptr[1]) == L.MRMF_E_INVALID_ARG                          # scratch over x0
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
