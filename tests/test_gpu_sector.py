@@ -249,3 +249,38 @@ def test_ring20_spin_flip_and_full_lanczos():
     r = plan.lanczos(th, t(x), 100)["result"].cpu().numpy()
     print("full basis", repr(r[0]), r[2], flush=True)
     assert r[0] >= E[14] - 1e-9 and r[0] - E[14] <= r[2]
+
+
+def test_ring20_sector_lanczos_certified_by_oracle():
+    """Sector Lanczos at full size, certified by the oracle: the 20-site ring's digit-sum-14 sector (S_z =
+    -1, 7,473,840 states, the sector of the ring's ground level), 100 steps with partial
+    reorthogonalisation.  The Ritz vector is brought to the host and ||H_s u - theta u|| recomputed with
+    the oracle's sector matvec (P H P^T through the full-basis row loop): it must equal the GPU's residual,
+    and it pins the FP64 energy to an eigenvalue of H_s; the FP32-matvec form's energy is compared with
+    that certified value (1e-5 relative)."""
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m, _ = W.config(2, with_state=False)
+    Q = 14
+    lab = osec.labels(m, Q)
+    S = Sector(Plan.from_model(m), Q)
+    assert S.dim == lab.size
+    th = t(m.theta)
+    v0 = t(W.random_state(S.dim, np.random.default_rng(100 + Q)))
+    out = {}
+    for prec in ("z", "c_in_z"):
+        r = S.lanczos(th, v0, 100, precision=prec, reorth="partial", theta_c=th.float())
+        res = r["result"].cpu().numpy()
+        u = r["u"].cpu().numpy()
+        del r
+        theta, r_gpu = float(res[0]), float(res[2])
+        r_oracle = float(np.linalg.norm(osec.matvec(m, Q, u, lab=lab, rows=np.arange(lab.size)) - theta * u))
+        nu = float(np.linalg.norm(u))
+        print(f"{prec}: theta {theta!r} residual gpu {r_gpu:.3e} oracle {r_oracle:.3e} ||u|| {nu!r}", flush=True)
+        assert int(res[3]) == 100 and abs(nu - 1.0) <= 1e-10
+        assert abs(r_gpu - r_oracle) <= 1e-10 * r_oracle + 1e-13 * abs(theta)
+        out[prec] = (theta, r_oracle)
+    t64, r64 = out["z"]
+    assert r64 <= 1e-8
+    rel = abs(out["c_in_z"][0] - t64) / abs(t64)
+    print(f"FP64 sector energy {t64!r} within {r64:.1e} of an eigenvalue; FP32 form rel {rel:.2e}", flush=True)
+    assert rel <= 1e-5
