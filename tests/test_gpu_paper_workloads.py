@@ -42,3 +42,36 @@ def test_staggered_ring_lanczos_small():
     r = p.lanczos(th, torch.from_numpy(x).to(DEV), 60)["result"].cpu().numpy()
     o = olz.lanczos(lambda v: mf.matvec(m, v), x, 60)
     assert abs(r[0] - o["theta"]) <= 1e-10 * abs(o["theta"])
+
+
+def test_paper_c2_whole_vector_and_certified_lanczos():
+    """The mixed ring (1/2)^6 (1)^6 (3/2)^6 at full size (D = 191,102,976; 3.06 GB per c128 vector, the
+    64-bit-addressing form of the generated kernel): every element of y = H x against the oracle, then 60
+    Lanczos steps with partial reorthogonalisation whose Ritz vector's residual the oracle recomputes
+    (it must equal the GPU's, and it bounds the distance of the FP64 energy to the spectrum)."""
+    from paper_2606_02169_amd.plan import Plan
+    m = W.paper_c2()
+    x = W.random_state(m.dim, np.random.default_rng(22))
+    p = Plan.from_model(m)
+    th = torch.as_tensor(m.theta, dtype=torch.float64, device=DEV)
+    xt = torch.from_numpy(x).to(DEV)
+    p.autotune(th, xt)
+    y = p.matvec(th, xt).cpu().numpy()
+    del xt
+    torch.cuda.empty_cache()
+    ref = mf.matvec(m, x)
+    e = rel_err(y, ref)
+    worst, bound = float(np.max(np.abs(y - ref))), 1e-12 * float(np.max(np.abs(ref)))
+    print(f"C2 whole vector: rel 2-norm err {e:.2e}, max |err| {worst:.2e} (bound {bound:.2e})", flush=True)
+    del y, ref
+    assert e <= 1e-12 and worst <= bound
+    r = p.lanczos(th, torch.from_numpy(x).to(DEV), 60, reorth="partial")
+    res = r["result"].cpu().numpy()
+    u = r["u"].cpu().numpy()
+    del r
+    torch.cuda.empty_cache()
+    theta, r_gpu = float(res[0]), float(res[2])
+    r_oracle = float(np.linalg.norm(mf.matvec(m, u) - theta * u))
+    print(f"C2 Lanczos: theta {theta!r} residual gpu {r_gpu:.4e} oracle {r_oracle:.4e}", flush=True)
+    assert int(res[3]) == 60 and abs(np.linalg.norm(u) - 1.0) <= 1e-10
+    assert abs(r_gpu - r_oracle) <= 1e-10 * r_oracle + 1e-13 * abs(theta)
