@@ -10,7 +10,7 @@ full-size Lanczos energies.
   oracle's residual certifies the FP64 energy, and the FP32 form's energy is compared with that
   certified value (target: 1e-5 relative).
 * The batched form at full size (256 chains x 8 c64 vectors) replayed from a captured hipGraph: every
-  lattice and every vector on sampled rows against the oracle, replays bit-identical to the eager launch.
+  element of every lattice and vector against the oracle, replays bit-identical to the eager launch.
 """
 import numpy as np
 import pytest
@@ -160,8 +160,9 @@ def test_torus_lanczos_partial_reorth_certified_by_oracle(torus):
 
 def test_batch_full_size_graph_replays():
     """256 chains x 8 c64 vectors, launched from a captured graph: two replays (with eager work between
-    them) bit-identical to the eager launch, and every lattice and vector on sampled rows against the
-    oracle with the couplings rounded to FP32."""
+    them) bit-identical to the eager launch, and every element of every lattice and vector against the
+    oracle with the couplings rounded to FP32 (2e-5 relative per lattice and vector, and no element off
+    by more than 2e-5 of its block's largest)."""
     from paper_2606_02169_amd.plan import Batch, Plan
     models, xs = W.config(4)
     plans = [Plan.from_model(m, device=DEV) for m in models]
@@ -183,17 +184,15 @@ def test_batch_full_size_graph_replays():
         assert torch.equal(Y, Y_eager), k
         X.mul_(1.0)
         torch.cuda.synchronize()
-    rng = np.random.default_rng(44)
-    worst = 0.0
+    worst = worst_el = 0.0
     for b, (m, x) in enumerate(zip(models, xs)):
-        D = m.dim
-        rows = np.unique(np.concatenate([np.arange(min(D, 16)), np.arange(max(0, D - 16), D),
-                                         rng.choice(D, min(D, 64), replace=False)])).astype(np.int64)
-        yb = B.block(Y, b)[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+        yb = B.block(Y, b).cpu().numpy()
         theta = m.theta.astype(np.float32).astype(np.float64)
         for v in range(8):
-            ref = mf.matvec(m, x[:, v].astype(np.complex128), theta=theta, rows=rows)
+            ref = mf.matvec(m, x[:, v].astype(np.complex128), theta=theta)
             e = rel_err(yb[:, v], ref)
-            worst = max(worst, e)
-            assert e <= TOL_C, (b, v, e)
-    print(f"{len(models)} lattices x 8 vectors, worst sampled rel err {worst:.3e}", flush=True)
+            el = float(np.max(np.abs(yb[:, v] - ref)) / np.max(np.abs(ref)))
+            worst, worst_el = max(worst, e), max(worst_el, el)
+            assert e <= TOL_C and el <= TOL_C, (b, v, e, el)
+    print(f"{len(models)} lattices x 8 vectors, every element: worst rel err {worst:.3e}, worst element "
+          f"{worst_el:.3e} of its block's largest", flush=True)
