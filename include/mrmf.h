@@ -443,7 +443,9 @@ mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const flo
  * sector kernel (built now if it was not yet), 0 when it runs the generic one.  Synchronous. */
 mrmf_status mrmf_sector_generated(mrmf_sector sector, int32_t dtype, int32_t* used);
 /* Source text of the generated sector kernel, for inspection; buffer contract of mrmf_plan_kernel_source.
- * MRMF_E_UNSUPPORTED when the sector does not qualify.  Host only. */
+ * dtype MRMF_DTYPE_Z / MRMF_DTYPE_C, or MRMF_SOURCE_CHEB for the c128 kernel with the Chebyshev-step
+ * epilogue that mrmf_sector_propagate_z runs.  MRMF_E_UNSUPPORTED when the sector does not qualify.  Host
+ * only. */
 mrmf_status mrmf_sector_kernel_source(mrmf_sector sector, int32_t dtype, char* buf, size_t cap, size_t* len);
 /* d_out[i] = full-basis index of packed row r0 + i (int64, device); d_scratch: >= 8 N bytes of device
  * memory the call may overwrite. */
@@ -463,8 +465,11 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
 /* Time propagation inside the sector, x = exp(-i P H P^T dt)^n_steps x0 on packed vectors (the restricted
  * basis as the way to shrink the propagated state, Sec. VI and Sec. VIII): the arguments, the Chebyshev
  * series, the merging of fixed-H steps (as the plan's MRMF_TUNE_CHEB_MERGE was when the sector was made)
- * and the Hermiticity requirement of mrmf_propagate_z, with vectors of the sector's dimension; each term is
- * one sector matvec and one fused vector update.  Since H keeps the digit sum, P H P^T is H on the sector
+ * and the Hermiticity requirement of mrmf_propagate_z, with vectors of the sector's dimension.  Each term
+ * is one launch of the sector's generated kernel with a Chebyshev-step epilogue (the row's phi_{k-2} and
+ * accumulator read and written in the same pass, as the plan's MRMF_TUNE_CHEB_FUSED was when the sector
+ * was made), or a sector matvec and a fused vector update for sectors on the generic kernel.  Since H keeps
+ * the digit sum, P H P^T is H on the sector
  * and this equals the full-basis propagation of a vector supported on the sector.  The spectrum of P H P^T
  * lies inside that of H (Cauchy interlacing), so the plan's bounds (mrmf_spectral_bounds,
  * mrmf_plan_norm_bound) serve.  d_scratch: mrmf_sector_propagate_scratch_bytes (three sector vectors),

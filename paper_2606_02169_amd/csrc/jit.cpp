@@ -1465,10 +1465,11 @@ std::string grad_source(const mrmf_plan_t* p) {
 // 32-bit unsigned arithmetic (exact modulo 2^32; the true offset lies within +-2^31) and are masked to that
 // out-of-range offset by integer checks of their source digits.  Gathers are issued in groups behind a
 // scheduling barrier.
-std::string sector_source(const mrmf_sector_t* S, int dtype) {
+std::string sector_source(const mrmf_sector_t* S, int dtype, bool epi) {
     const bool f32 = dtype == MRMF_DTYPE_C;
     const int N = S->N, Q = S->Q, SZ = f32 ? 8 : 16;
     if (N < 1 || N > 64 || S->Dr < 1 || S->Dr * SZ >= (int64_t(1) << 31) || S->lab_bytes == 0) return "";
+    if (epi && f32) return "";  // the Chebyshev step is a c128 form
     const int nch = static_cast<int>(S->chans.size());
     // factor tables <n|O|n - q> at the target digit, in the order they were built (diagonal terms, then
     // channels; site a then site b)
@@ -1764,9 +1765,16 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
     arr("R", "CVR", cvr.size(), [&](size_t k) { return lit(cvr[k], f32); });
     if (cplx) arr("R", "CVI", cvi.size(), [&](size_t k) { return lit(cvi[k], f32); });
     const size_t nseg = std::max<size_t>(2, seg.size() + (seg.size() % 2));
-    o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector(const R* __restrict__ theta,\n"
-      << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip, const void* __restrict__ lab) {\n"
-      << "  if (skip != nullptr && *skip != 0) return;\n"
+    // Chebyshev-step epilogue (time propagation in the sector): instead of y = H x the kernel computes
+    // p = ea (H x) + eb x + eg y, writes it to y and adds (ecr + i eci) p to acc, row by row
+    if (epi)
+        o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector_cheb(const R* __restrict__ theta,\n"
+          << "    const C* __restrict__ x, C* __restrict__ y, C* __restrict__ acc, R ea, R eb, R eg, R ecr, R eci,\n"
+          << "    const int* __restrict__ skip, const void* __restrict__ lab) {\n";
+    else
+        o << "extern \"C\" __global__ __launch_bounds__(256) void mrmf_sector(const R* __restrict__ theta,\n"
+          << "    const C* __restrict__ x, C* __restrict__ y, const int* __restrict__ skip, const void* __restrict__ lab) {\n";
+    o << "  if (skip != nullptr && *skip != 0) return;\n"
       << "  __shared__ __attribute__((aligned(16))) unsigned SEG[" << nseg << "];\n"
       << "  for (unsigned k = threadIdx.x; k < " << seg.size() << "u; k += 256u) SEG[k] = SEGC[k];\n"
       << "  __shared__ R Tr[" << NE << "];\n";
@@ -1783,7 +1791,11 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
       << "  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc((void*)y, (short)0, " << S->Dr * SZ
       << ", 0x00020000);\n"
       << "  const __amdgpu_buffer_rsrc_t ls = __builtin_amdgcn_make_buffer_rsrc((void*)lab, (short)0, "
-      << S->Dr * S->lab_bytes << ", 0x00020000);\n"
+      << S->Dr * S->lab_bytes << ", 0x00020000);\n";
+    if (epi)
+        o << "  const __amdgpu_buffer_rsrc_t as = __builtin_amdgcn_make_buffer_rsrc((void*)acc, (short)0, " << S->Dr * SZ
+          << ", 0x00020000);\n";
+    o
       << "  const unsigned G = gridDim.x, bk = blockIdx.x;\n";
     const int64_t ng = (S->Dr + 255) / 256;  // row groups of 256
     if (S->sched == MRMF_SCHED_XCD_CHUNK) {
@@ -1807,9 +1819,16 @@ std::string sector_source(const mrmf_sector_t* S, int dtype) {
         o << "  const unsigned v = (G % 8u == 0u) ? (bk % 8u) * (G / 8u) + bk / 8u : bk;\n"
           << "  for (unsigned r = v * 256u + threadIdx.x; r < " << S->Dr << "u; r += G * 256u) {\n";
     }
-    o << body.str()
-      << "    { C out; out.x = ar; out.y = ai; ST(out, ys, rb); }\n"
-      << "  }\n}\n";
+    o << body.str();
+    if (epi)
+        o << "    { const C pv = LD(ys, rb), av = LD(as, rb);\n"
+          << "      C np; np.x = ea * ar + eb * xf.x + eg * pv.x; np.y = ea * ai + eb * xf.y + eg * pv.y;\n"
+          << "      ST(np, ys, rb);\n"
+          << "      C na; na.x = av.x + ecr * np.x - eci * np.y; na.y = av.y + ecr * np.y + eci * np.x;\n"
+          << "      ST(na, as, rb); }\n";
+    else
+        o << "    { C out; out.x = ar; out.y = ai; ST(out, ys, rb); }\n";
+    o << "  }\n}\n";
     return o.str();
 }
 
@@ -2043,10 +2062,11 @@ mrmf_status grad_launch(mrmf_plan_t* p, const double* theta, const void* x, cons
     return hip_status(hipModuleLaunchKernel(K.fn, *grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
 }
 
-mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
-    if (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) return MRMF_E_INVALID_ARG;
+mrmf_status sector_gen_prepare(mrmf_sector_t* S, int slot) {
+    if (slot != MRMF_DTYPE_Z && slot != MRMF_DTYPE_C && slot != kSectorSlotCheb) return MRMF_E_INVALID_ARG;
+    const bool epi = slot == kSectorSlotCheb;
     std::lock_guard<std::mutex> lk(S->mtx);
-    SpecKernel& K = S->gen[dtype];
+    SpecKernel& K = S->gen[slot];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return MRMF_E_HIP;
     if (K.tried && K.device == dev) return K.ok ? MRMF_OK : MRMF_E_UNSUPPORTED;
@@ -2054,7 +2074,7 @@ mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
     K = SpecKernel{};
     K.device = dev;
     K.tried = true;
-    const std::string src = sector_source(S, dtype);
+    const std::string src = sector_source(S, epi ? MRMF_DTYPE_Z : slot, epi);
     if (src.empty()) {
         K.log = "sector does not qualify for the generated kernel";
         return MRMF_E_UNSUPPORTED;
@@ -2063,7 +2083,7 @@ mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype) {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MRMF_E_HIP;
     hipModule_t mod;
     hipFunction_t fn;
-    const mrmf_status bs = rtc_build(src, "mrmf_sector", prop, &mod, &fn, &K.log);
+    const mrmf_status bs = rtc_build(src, epi ? "mrmf_sector_cheb" : "mrmf_sector", prop, &mod, &fn, &K.log);
     if (bs != MRMF_OK) return bs;
     int per_cu = S->blocks_per_cu;
     if (per_cu <= 0 &&
@@ -2091,6 +2111,25 @@ mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* lab, cons
         const int32_t* skip;
         const void* lab;
     } args{theta, x, y, d_skip, lab};
+    size_t size = sizeof(args);
+    void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
+    return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));
+}
+
+mrmf_status sector_gen_launch_cheb(mrmf_sector_t* S, const void* lab, const double* theta, const void* x, void* prev,
+                                   void* acc, double ea, double eb, double eg, double ecr, double eci, hipStream_t s) {
+    mrmf_status st = sector_gen_prepare(S, kSectorSlotCheb);
+    if (st != MRMF_OK) return st;
+    const SpecKernel& K = S->gen[kSectorSlotCheb];
+    struct {
+        const void* theta;
+        const void* x;
+        void* y;
+        void* acc;
+        double ea, eb, eg, ecr, eci;
+        const int32_t* skip;
+        const void* lab;
+    } args{theta, x, prev, acc, ea, eb, eg, ecr, eci, nullptr, lab};
     size_t size = sizeof(args);
     void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
     return hip_status(hipModuleLaunchKernel(K.fn, K.grid, 1, 1, K.block, 1, 1, 0, s, nullptr, config));

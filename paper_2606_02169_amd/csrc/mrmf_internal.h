@@ -199,7 +199,8 @@ struct mrmf_sector_t {
     int32_t group = 0;                // gathers issued together by the generated kernel (0: default)
     int32_t sched = 0;                // MRMF_SCHED_* of the generated kernel's rows over the XCDs
     int32_t cheb_merge = 1;           // propagation: consecutive steps of a fixed H as one longer step
-    mrmf::SpecKernel gen[2];          // generated sector kernels, c128 and c64
+    int32_t cheb_fused = 1;           // propagation: the generated kernel with the Chebyshev-step epilogue
+    mrmf::SpecKernel gen[3];          // generated sector kernels: c128, c64, c128 with the Chebyshev step
     std::mutex mtx;
     ~mrmf_sector_t();
 };
@@ -285,8 +286,13 @@ std::string grad_source(const mrmf_plan_t* p);
 // Sector kernel generated for one sector and element type (jit.cpp): "" when the sector does not qualify
 // (no packed digits, tables over their LDS budget, or a vector of 2^31 bytes or more); launch returns
 // MRMF_E_UNSUPPORTED then.  lab: the packed digits in the uploaded workspace.
-std::string sector_source(const mrmf_sector_t* S, int dtype);
-mrmf_status sector_gen_prepare(mrmf_sector_t* S, int dtype);
+std::string sector_source(const mrmf_sector_t* S, int dtype, bool epi = false);
+// slot: MRMF_DTYPE_Z, MRMF_DTYPE_C, or kSectorSlotCheb (c128 with the Chebyshev-step epilogue:
+// prev = ea (P H P^T x) + eb x + eg prev; acc += (ecr + i eci) prev, row by row)
+constexpr int kSectorSlotCheb = 2;
+mrmf_status sector_gen_prepare(mrmf_sector_t* S, int slot);
+mrmf_status sector_gen_launch_cheb(mrmf_sector_t* S, const void* lab, const double* theta, const void* x, void* prev,
+                                   void* acc, double ea, double eb, double eg, double ecr, double eci, hipStream_t s);
 mrmf_status sector_gen_launch(mrmf_sector_t* S, int dtype, const void* lab, const void* theta, const void* x, void* y,
                               hipStream_t s, const int32_t* d_skip);
 mrmf_status grad_prepare(mrmf_plan_t* p);

@@ -420,6 +420,7 @@ mrmf_status mrmf_sector_create(mrmf_plan plan, int32_t digit_sum, mrmf_sector* o
     S->group = plan->cfg[MRMF_DTYPE_Z].group;
     S->sched = plan->cfg[MRMF_DTYPE_Z].sched;
     S->cheb_merge = plan->cfg[MRMF_DTYPE_Z].cheb_merge;
+    S->cheb_fused = plan->cfg[MRMF_DTYPE_Z].cheb_fused;
     auto add_fac = [&](int site, int op) {
         for (int n = 0; n < plan->d[site]; ++n) S->tfac.push_back(local_factor_host(plan, site, op, n));
     };
@@ -525,9 +526,11 @@ mrmf_status mrmf_sector_matvec_c(mrmf_sector sector, const void* d_ws, const flo
 }
 
 mrmf_status mrmf_sector_kernel_source(mrmf_sector sector, int32_t dtype, char* buf, size_t cap, size_t* len) {
-    if (!sector || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C) || (cap > 0 && !buf))
+    if (!sector || !len || (dtype != MRMF_DTYPE_Z && dtype != MRMF_DTYPE_C && dtype != MRMF_SOURCE_CHEB) ||
+        (cap > 0 && !buf))
         return MRMF_E_INVALID_ARG;
-    const std::string src = sector_source(sector, dtype);
+    const bool cheb = dtype == MRMF_SOURCE_CHEB;
+    const std::string src = sector_source(sector, cheb ? MRMF_DTYPE_Z : dtype, cheb);
     if (src.empty()) return MRMF_E_UNSUPPORTED;
     *len = src.size();
     if (cap > 0) {
@@ -627,8 +630,19 @@ mrmf_status mrmf_sector_propagate_z(mrmf_sector sector, const void* d_ws, const 
     const ThetaMatvecOp mv = [&](const double* th, const void* x, void* y, hipStream_t s) {
         return sector_matvec<double>(sector, d_ws, th, x, y, s, nullptr);
     };
-    return propagate_run(sector->Dr, sector->n_params, mv, nullptr, [] { return false; }, sector->cheb_merge != 0,
-                         d_theta, theta_stride, dt, n_steps, e_min, e_max, tol, d_x0, d_x, d_scratch, scratch_bytes,
+    // the sector's generated kernel with the Chebyshev-step epilogue does the matvec and the update in one
+    // pass; sectors on the generic kernel take the two-pass form
+    const void* lab = static_cast<const unsigned char*>(d_ws) + sector->off_lab;
+    const ChebStepOp step = [&](const double* th, const void* cur, void* prev, void* acc, double ea, double eb,
+                                double eg, double cr, double ci, hipStream_t s) {
+        return sector_gen_launch_cheb(sector, lab, th, cur, prev, acc, ea, eb, eg, cr, ci, s);
+    };
+    const auto fused_ready = [&]() {
+        return sector->mode != MRMF_KERNEL_GENERIC && sector->cheb_fused != 0 &&
+               sector_gen_prepare(sector, kSectorSlotCheb) == MRMF_OK;
+    };
+    return propagate_run(sector->Dr, sector->n_params, mv, &step, fused_ready, sector->cheb_merge != 0, d_theta,
+                         theta_stride, dt, n_steps, e_min, e_max, tol, d_x0, d_x, d_scratch, scratch_bytes,
                          h_n_terms, static_cast<hipStream_t>(stream));
 }
 

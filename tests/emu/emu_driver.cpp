@@ -64,6 +64,8 @@ extern "C" void mrmf_sector(const void* theta, const void* x, void* y, const int
     __attribute__((weak));
 extern "C" void mrmf_spec_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
                                double ecr, double eci, const int* skip) __attribute__((weak));
+extern "C" void mrmf_sector_cheb(const void* theta, const void* x, void* y, void* acc, double ea, double eb, double eg,
+                                 double ecr, double eci, const int* skip, const void* lab) __attribute__((weak));
 
 namespace {
 struct Arg {
@@ -92,7 +94,10 @@ void* thread_main(void* a) {
     threadIdx = emu_dim3{g->tid, 0, 0};
     for (unsigned b = g->b0; b < g->b1; ++b) {
         blockIdx = emu_dim3{b, 0, 0};
-        if (g_sector)
+        if (g_sector && g_cheb.cheb)
+            mrmf_sector_cheb(g->theta, g->x, g->y, g_cheb.acc, g_cheb.ea, g_cheb.eb, g_cheb.eg, g_cheb.ecr, g_cheb.eci,
+                             nullptr, g_lab);
+        else if (g_sector)
             mrmf_sector(g->theta, g->x, g->y, nullptr, g_lab);
         else if (g_grad.on)
             mrmf_grad(static_cast<const double*>(g->theta), g->x, g_grad.g, g->y, g_grad.partial);
@@ -120,7 +125,7 @@ extern "C" int emu_run_range(unsigned grid, unsigned block, const void* theta, s
                              size_t x_bytes, void* y, size_t y_bytes, unsigned b0, unsigned b1) {
     if (b1 == 0 || b1 > grid) b1 = grid;
     if (block == 0 || block % 64 != 0 || block > 1024) return -1;
-    if (g_sector ? mrmf_sector == nullptr
+    if (g_sector ? (g_cheb.cheb ? mrmf_sector_cheb == nullptr : mrmf_sector == nullptr)
                  : g_grad.on ? mrmf_grad == nullptr : g_cheb.cheb ? mrmf_spec_cheb == nullptr : mrmf_spec == nullptr)
         return -3;
     g_bufs = {{static_cast<const char*>(x), x_bytes, "x"}, {static_cast<const char*>(y), y_bytes, "y"},
@@ -190,6 +195,23 @@ extern "C" int emu_run_sector(unsigned grid, const void* theta, size_t theta_byt
     g_lab = lab;
     g_extra = {static_cast<const char*>(lab), lab_bytes, "lab"};
     const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, y, y_bytes, 0, 0);
+    g_sector = false;
+    g_lab = nullptr;
+    g_extra = {nullptr, 0, ""};
+    return rc;
+}
+
+// The sector kernel with the Chebyshev-step epilogue over all `grid` blocks of 256 threads: prev and acc
+// (packed vectors, the length of x) are updated in place.
+extern "C" int emu_run_sector_cheb(unsigned grid, const void* theta, size_t theta_bytes, const void* x, size_t x_bytes,
+                                   void* prev, void* acc, double ea, double eb, double eg, double ecr, double eci,
+                                   const void* lab, size_t lab_bytes) {
+    g_sector = true;
+    g_lab = lab;
+    g_extra = {static_cast<const char*>(lab), lab_bytes, "lab"};
+    g_cheb = ChebCall{true, acc, ea, eb, eg, ecr, eci};
+    const int rc = emu_run_range(grid, 256, theta, theta_bytes, x, x_bytes, prev, x_bytes, 0, 0);
+    g_cheb = ChebCall{};
     g_sector = false;
     g_lab = nullptr;
     g_extra = {nullptr, 0, ""};

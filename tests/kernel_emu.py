@@ -84,6 +84,10 @@ def _compile(src: str) -> ctypes.CDLL:
     lib.emu_run_cheb.argtypes = ([ctypes.c_uint, ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
                                  + [ctypes.c_uint, ctypes.c_uint])
+    lib.emu_run_sector_cheb.restype = ctypes.c_int
+    lib.emu_run_sector_cheb.argtypes = ([ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_double] * 5
+                                        + [ctypes.c_void_p, ctypes.c_size_t])
     return lib
 
 
@@ -212,3 +216,23 @@ def run_sector(model, digit_sum: int, x: np.ndarray, grid: int, tuning=None) -> 
     if rc != 0:
         raise RuntimeError(f"emu_run_sector failed: {rc}")
     return y
+
+
+def run_sector_cheb(model, digit_sum: int, x: np.ndarray, prev: np.ndarray, acc: np.ndarray, ea: float, eb: float,
+                    eg: float, c: complex, grid: int, tuning=None):
+    """The sector kernel with the Chebyshev-step epilogue (c128), emulated on the CPU: returns (prev', acc')
+    with prev' = ea P H P^T x + eb x + eg prev and acc' = acc + c prev'."""
+    src = sector_source(model, digit_sum, L.MRMF_SOURCE_CHEB, tuning)
+    if src is None:
+        raise ValueError("the sector does not qualify for the generated kernel")
+    lib = _compile(src)
+    th = np.ascontiguousarray(model.theta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.complex128)
+    pv = np.array(prev, dtype=np.complex128, copy=True)
+    av = np.array(acc, dtype=np.complex128, copy=True)
+    lab = packed_digits(model, digit_sum)
+    rc = lib.emu_run_sector_cheb(grid, th.ctypes.data, th.nbytes, xx.ctypes.data, xx.nbytes, pv.ctypes.data,
+                                 av.ctypes.data, ea, eb, eg, c.real, c.imag, lab.ctypes.data, lab.nbytes)
+    if rc != 0:
+        raise RuntimeError(f"emu_run_sector_cheb failed: {rc}")
+    return pv, av

@@ -338,3 +338,24 @@ def test_sector_propagation_equals_full_basis():
     assert np.max(np.abs(np.delete(yf, lab))) <= 1e-13
     assert rel_err(yf[lab], ys) <= 1e-12
     assert abs(np.linalg.norm(ys) - 1.0) <= 1e-12
+
+
+def test_sector_propagation_fused_matches_two_pass():
+    """The sector's generated kernel with the Chebyshev-step epilogue (one launch per term) against the
+    sector matvec plus a separate update (the plan's cheb_fused = 0 when the sector is made): the same
+    state to rounding, on the 12-site ring's S_z = 0 sector, fixed couplings and a drive."""
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m, _ = W.config(2, reduced=12)
+    Q = Sector.digit_sum_of(m.sites, 0.0)
+    pf, p2 = Plan.from_model(m), Plan.from_model(m)
+    p2.set_tuning(cheb_fused=0)
+    Sf, S2 = Sector(pf, Q), Sector(p2, Q)
+    assert Sf.generated()
+    xs = t(W.random_state(Sf.dim, np.random.default_rng(8600)))
+    drive = np.stack([m.theta * (1 + 0.2 * np.sin(0.9 * s)) for s in range(3)])
+    for th, steps in ((t(m.theta), 5), (t(drive), 3)):
+        rf = Sf.propagate(th, xs, 0.15, steps)
+        r2 = S2.propagate(th, xs, 0.15, steps, bounds=rf["bounds"])
+        e = rel_err(rf["x"].cpu().numpy(), r2["x"].cpu().numpy())
+        print(f"steps {steps}: terms {rf['n_terms']} / {r2['n_terms']}, fused vs two-pass {e:.2e}", flush=True)
+        assert rf["n_terms"] == r2["n_terms"] and e <= 1e-13

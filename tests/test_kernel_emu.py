@@ -282,3 +282,29 @@ def test_sector_kernel_spans_and_words(case):
         x32 = x.astype(np.complex64)
         y32 = E.run_sector(m, Q, x32, 2)
         assert rel_err(y32, osec.matvec(m, Q, x32.astype(np.complex128), lab=lab)) <= TOL_C
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sector_chebyshev_step(seed):
+    """The sector kernel with the Chebyshev-step epilogue (time propagation in the sector): prev' = ea
+    P H P^T x + eb x + eg prev and acc' = acc + c prev' on every packed row against the sector oracle's
+    matvec, for the first step's weights (eg = 0) and a later step's, on rings and random models."""
+    from oracle import sector as osec
+    rng = np.random.default_rng(7900 + seed)
+    if seed == 0:
+        m = W.config(2, reduced=8, with_state=False)[0]
+    elif seed == 1:
+        m = W.tavis_cummings(5, 7, 1.0, 0.8, rng)
+    else:
+        m = W.random_model(rng, n_sites=int(rng.integers(3, 7)), max_dim=5000, n_params=3, n_terms=16)
+    qmax = sum(s.d - 1 for s in m.sites)
+    Q = qmax // 2
+    lab = osec.labels(m, Q)
+    x, prev, acc = (W.random_state(lab.size, rng) for _ in range(3))
+    hx = osec.matvec(m, Q, x, lab=lab)
+    for ea, eb, eg, c in ((0.3, -0.1, 0.0, 0.7 - 0.2j), (0.6, -0.2, -1.0, -0.1 + 0.4j)):
+        for grid in ((lab.size + 255) // 256, 3):
+            pv, av = E.run_sector_cheb(m, Q, x, prev, acc, ea, eb, eg, c, grid)
+            want_p = ea * hx + eb * x + eg * prev
+            assert rel_err(pv, want_p) <= TOL_Z, (ea, eg, grid)
+            assert rel_err(av, acc + c * want_p) <= TOL_Z, (ea, eg, grid)
