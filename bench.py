@@ -799,10 +799,14 @@ def bench_sector(args, dev):
         yf = torch.empty_like(xf)
         ms_full = cuda_time(lambda: plan.matvec(th, xf, out=yf), stream, 20)
         # time propagation, 4 steps of dt = 0.05, in the sector and on the full basis (a vector supported
-        # on the sector, so both compute the same state), with the same bounds
+        # on the sector, so both compute the same state), with the same bounds: the sector's own Gershgorin
+        # ends (the default), which the plan's contain
         xf.zero_()
         xf[S.labels()] = xt
-        prop = {}
+        sb = S.spectral_bounds(th)
+        pb = plan.spectral_bounds(th)
+        prop = {"sector_bounds": list(sb), "sector_bounds_ms": cuda_time(lambda: S.spectral_bounds(th), stream, 5),
+                "plan_bounds": list(pb), "terms_with_plan_bounds": S.propagate(th, xt, 0.05, 4, bounds=pb)["n_terms"]}
         for where, fn in (("sector", lambda b: S.propagate(th, xt, 0.05, 4, bounds=b)),
                           ("full_basis", lambda b: plan.propagate(th, xf, 0.05, 4, bounds=b))):
             b = fn(None)["bounds"] if where == "sector" else prop["sector"]["bounds"]

@@ -462,6 +462,17 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
                                 const float* d_theta_c, int32_t precision, int32_t m, int32_t reorth,
                                 const void* d_v0, void* d_V, double* d_alpha, double* d_beta, double* d_result,
                                 void* d_u, void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+/* Gershgorin bounds of the spectrum of P H(theta) P^T: d_out[0] <= every eigenvalue <= d_out[1] (device
+ * double[2]), the extreme ends over the sector's rows r of H_rr -+ R_r, with R_r the sum of |theta_p w f|
+ * over the row's off-diagonal channels whose source digits are in range (every such source lies in the
+ * sector: the channels keep the digit sum).  One device pass over the sector's rows, digits by unranking,
+ * no vector read; usually tighter than the plan's bounds (mrmf_spectral_bounds), which contain the
+ * sector's spectrum as well.  MRMF_E_NOT_HERMITIAN unless the sector's groups are Hermitian.
+ *   d_theta   : double[n_params] on the device.
+ *   d_scratch : mrmf_sector_spectral_bounds_scratch_bytes, 8-B aligned; d_out 8-B aligned. */
+mrmf_status mrmf_sector_spectral_bounds_scratch_bytes(mrmf_sector sector, size_t* bytes);
+mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, const double* d_theta, double* d_out,
+                                        void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
 /* Time propagation inside the sector, x = exp(-i P H P^T dt)^n_steps x0 on packed vectors (the restricted
  * basis as the way to shrink the propagated state, Sec. VI and Sec. VIII): the arguments, the Chebyshev
  * series, the merging of fixed-H steps (as the plan's MRMF_TUNE_CHEB_MERGE was when the sector was made)
@@ -470,9 +481,9 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
  * accumulator read and written in the same pass, as the plan's MRMF_TUNE_CHEB_FUSED was when the sector
  * was made), or a sector matvec and a fused vector update for sectors on the generic kernel.  Since H keeps
  * the digit sum, P H P^T is H on the sector
- * and this equals the full-basis propagation of a vector supported on the sector.  The spectrum of P H P^T
- * lies inside that of H (Cauchy interlacing), so the plan's bounds (mrmf_spectral_bounds,
- * mrmf_plan_norm_bound) serve.  d_scratch: mrmf_sector_propagate_scratch_bytes (three sector vectors),
+ * and this equals the full-basis propagation of a vector supported on the sector.  Bounds: the sector's own
+ * (mrmf_sector_spectral_bounds), or the plan's (mrmf_spectral_bounds, mrmf_plan_norm_bound), since the
+ * spectrum of P H P^T lies inside that of H (Cauchy interlacing).  d_scratch: mrmf_sector_propagate_scratch_bytes (three sector vectors),
  * 256-B aligned. */
 mrmf_status mrmf_sector_propagate_scratch_bytes(mrmf_sector sector, size_t* bytes);
 mrmf_status mrmf_sector_propagate_z(mrmf_sector sector, const void* d_ws, const double* d_theta, int64_t theta_stride,

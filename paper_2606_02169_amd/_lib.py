@@ -126,6 +126,8 @@ SIGNATURES = {
     "mrmf_sector_lanczos_scratch_bytes": (_i32, [_vp, _i32, _i32, _P(_sz)]),
     "mrmf_sector_lanczos": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _sz, _vp]),
+    "mrmf_sector_spectral_bounds_scratch_bytes": (_i32, [_vp, _P(_sz)]),
+    "mrmf_sector_spectral_bounds": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mrmf_sector_propagate_scratch_bytes": (_i32, [_vp, _P(_sz)]),
     "mrmf_sector_propagate_z": (_i32, [_vp, _vp, _vp, _i64, ctypes.c_double, _i32, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _sz, _P(_i32), _vp]),

@@ -326,6 +326,69 @@ __global__ __launch_bounds__(kSB) void k_sector_lookup(SectorArgs a, int64_t D, 
     }
 }
 
+// Gershgorin bounds of P H P^T: per packed row (digits by unranking), the diagonal entry (the real parts
+// of the diagonal terms; Hermitian groups have real diagonals) -+ the sum over the sector's channels whose
+// source digits are in range of |theta w f| (the channels keep the digit sum, so such a source is in the
+// sector); block min / max, then one thread over the blocks.
+__global__ __launch_bounds__(kSB) void k_sector_gershgorin(SectorArgs a, const double* __restrict__ theta,
+                                                           double* __restrict__ partial) {
+    __shared__ uint8_t dig[kMaxSites][kSB];
+    __shared__ uint16_t rem[kMaxSites][kSB];
+    __shared__ double slo[kSB], shi[kSB];
+    const int tid = threadIdx.x;
+    const PlanArgs& p = a.p;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (int64_t r = int64_t(blockIdx.x) * kSB + tid; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
+        unrank(a, r, dig, rem, tid);
+        double diag = 0.0, rad = 0.0;
+        for (int k = 0; k < p.n_diag; ++k) {
+            const DevDiag g = p.diag[k];
+            double f = sfactor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+            if (g.b >= 0) f *= sfactor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+            diag += theta[g.param] * g.wr * f;
+        }
+        for (int c = 0; c < p.n_chan; ++c) {
+            const DevChan ch = p.chan[c];
+            const int na = dig[ch.a][tid], nb = dig[ch.b][tid];
+            const int sa = na - ch.qa, sb = nb - ch.qb;
+            if (sa < 0 || sa >= p.site[ch.a].d || sb < 0 || sb >= p.site[ch.b].d) continue;
+            const double f = sfactor<double>(p, ch.opa, p.site[ch.a].tab, na) *
+                             sfactor<double>(p, ch.opb, p.site[ch.b].tab, nb);
+            rad += fabs(theta[ch.param] * f) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+        }
+        lo = fmin(lo, diag - rad);
+        hi = fmax(hi, diag + rad);
+    }
+    slo[tid] = lo;
+    shi[tid] = hi;
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 1; k < kSB; ++k) {
+            lo = fmin(lo, slo[k]);
+            hi = fmax(hi, shi[k]);
+        }
+        partial[2 * blockIdx.x] = lo;
+        partial[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ void k_sector_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    double lo = partial[0], hi = partial[1];
+    for (int b = 1; b < nb; ++b) {
+        lo = fmin(lo, partial[2 * b]);
+        hi = fmax(hi, partial[2 * b + 1]);
+    }
+    out[0] = lo;
+    out[1] = hi;
+}
+
+constexpr int kSectorGershMaxGrid = 1024;
+
+int sector_gersh_grid(int64_t n) {
+    const int64_t b = (n + kSB - 1) / kSB;
+    return static_cast<int>(b < kSectorGershMaxGrid ? (b < 1 ? 1 : b) : kSectorGershMaxGrid);
+}
+
 int sector_grid(int64_t n) {
     const int64_t b = (n + kSB - 1) / kSB;
     return static_cast<int>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
@@ -612,6 +675,29 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
     };
     return lanczos_run(sector->Dr, mv_z, mv_c, precision, m, reorth, d_v0, d_V, d_alpha, d_beta, d_result, d_u,
                        d_scratch, scratch_bytes, stream);
+}
+
+mrmf_status mrmf_sector_spectral_bounds_scratch_bytes(mrmf_sector sector, size_t* bytes) {
+    if (!sector || !bytes) return MRMF_E_INVALID_ARG;
+    *bytes = sizeof(double) * 2 * size_t(sector_gersh_grid(sector->Dr));
+    return MRMF_OK;
+}
+
+mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, const double* d_theta, double* d_out,
+                                        void* d_scratch, size_t scratch_bytes, mrmf_stream stream) {
+    if (!sector || !d_ws || !d_out || !d_scratch || (sector->n_params > 0 && !d_theta)) return MRMF_E_INVALID_ARG;
+    if (!sector->hermitian) return MRMF_E_NOT_HERMITIAN;
+    if (!aligned(d_ws, 256) || !aligned(d_scratch, 8) || !aligned(d_out, 8)) return MRMF_E_INVALID_ARG;
+    size_t need = 0;
+    mrmf_sector_spectral_bounds_scratch_bytes(sector, &need);
+    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = sector_gersh_grid(sector->Dr);
+    double* partial = static_cast<double*>(d_scratch);
+    const double* theta = sector->n_params > 0 ? d_theta : partial;  // never read when there are no params
+    hipLaunchKernelGGL(k_sector_gershgorin, dim3(grid), dim3(kSB), 0, s, sector_args(sector, d_ws), theta, partial);
+    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    return launch_status();
 }
 
 mrmf_status mrmf_sector_propagate_scratch_bytes(mrmf_sector sector, size_t* bytes) {

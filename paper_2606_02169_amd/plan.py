@@ -220,9 +220,11 @@ class Plan:
                ctypes.byref(nt), _stream(self.device))
         return dict(x=x, n_terms=int(nt.value), bounds=tuple(bounds), scratch=scratch)
 
-    def _propagation_args(self, theta: torch.Tensor, n_steps: int, bounds) -> tuple:
+    def _propagation_args(self, theta: torch.Tensor, n_steps: int, bounds, owner=None) -> tuple:
         """(theta_stride, (e_min, e_max)) of a propagation call: the stride from theta's shape and the
-        bounds as described in propagate()."""
+        bounds as described in propagate(); the default (Gershgorin) bounds are those of `owner` (this plan,
+        or a sector of it), cached per coupling vector on the owner."""
+        owner = self if owner is None else owner
         _need_gpu(theta, "theta", torch.float64)
         stride = 0
         if theta.dim() == 2:
@@ -238,14 +240,14 @@ class Plan:
                 bounds = (-b, b)
             elif bounds is None:
                 rows = np.unique(th, axis=0) if th.shape[1] else th[:1]
-                cache = self.__dict__.setdefault("_gersh_cache", {})   # the plan's terms never change
+                cache = owner.__dict__.setdefault("_gersh_cache", {})   # the owner's terms never change
                 ends = []
                 for r in rows:
                     key = np.ascontiguousarray(r).tobytes()
                     if key not in cache:
                         if len(cache) >= 256:
                             cache.clear()
-                        cache[key] = self.spectral_bounds(torch.from_numpy(np.ascontiguousarray(r)).to(self.device))
+                        cache[key] = owner.spectral_bounds(torch.from_numpy(np.ascontiguousarray(r)).to(self.device))
                     ends.append(cache[key])
                 lo, hi = min(e[0] for e in ends), max(e[1] for e in ends)
                 pad = 1e-9 * max(hi - lo, abs(lo), abs(hi), 1e-3)
@@ -592,14 +594,34 @@ class Sector:
         return _lanczos("mrmf_sector_lanczos", self._handle, self.ws, self.dim, self.device, theta, v0, m,
                         precision, reorth, theta_c, keep_basis)
 
+    def spectral_bounds(self, theta: torch.Tensor) -> tuple:
+        """(e_min, e_max) containing the spectrum of P H(theta) P^T, from the Gershgorin discs of the
+        sector's rows (mrmf_sector_spectral_bounds).  theta: float64 [n_params] on the device."""
+        _need_gpu(theta, "theta", torch.float64)
+        if theta.numel() < self.n_params:
+            raise ValueError("theta has fewer than n_params entries")
+        nb = ctypes.c_size_t()
+        L.call("mrmf_sector_spectral_bounds_scratch_bytes", self._handle, ctypes.byref(nb))
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        L.call("mrmf_sector_spectral_bounds", self._handle, _ptr(self.ws), _ptr(theta.contiguous()), _ptr(out),
+               _ptr(scratch), nb.value, _stream(self.device))
+        lo, hi = out.cpu().tolist()
+        return lo, hi
+
+    def norm_bound(self, theta) -> float:
+        """The plan's host norm bound (it bounds P H P^T as well)."""
+        return self._plan.norm_bound(theta)
+
     def propagate(self, theta: torch.Tensor, x0: torch.Tensor, dt: float, n_steps: int = 1,
                   bounds: tuple | str | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
         """x = exp(-i P H P^T dt)^n_steps x0 on packed sector vectors (mrmf_sector_propagate_z); theta,
-        bounds and the result as in Plan.propagate (the plan's bounds contain the sector's spectrum)."""
+        bounds and the result as in Plan.propagate, the default bounds from the sector's own Gershgorin
+        discs (spectral_bounds; the plan's bounds contain the sector's spectrum as well, but less tightly)."""
         _need_gpu(x0, "x0", torch.complex128)
         if x0.numel() != self.dim:
             raise ValueError("x0 has the wrong length")
-        stride, bounds = self._plan._propagation_args(theta, n_steps, bounds)
+        stride, bounds = self._plan._propagation_args(theta, n_steps, bounds, owner=self)
         x = torch.empty_like(x0) if out is None else out
         _need_gpu(x, "out", torch.complex128)
         nb = ctypes.c_size_t()

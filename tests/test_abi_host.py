@@ -289,6 +289,50 @@ def test_spectral_bounds_argument_checks():
         L.lib().mrmf_plan_destroy(q)
 
 
+def test_sector_spectral_bounds_argument_checks():
+    """mrmf_sector_spectral_bounds: a scratch of two doubles per block of the reduction, and refusals before
+    any launch for null pointers, a non-Hermitian group, misaligned buffers and too small a scratch (the
+    pointers below are never dereferenced)."""
+    from workloads.model import OP_LOWER, OP_RAISE, Model, Term, spin_site
+    from paper_2606_02169_amd.plan import Sector
+    m = W.ferrimagnetic_ring(8)
+    st, h = host_plan(m)
+    assert st == 0
+    sec = ctypes.c_void_p()
+    try:
+        L.call("mrmf_sector_create", h, Sector.digit_sum_of(m.sites, 0.0), ctypes.byref(sec))
+        nb = ctypes.c_size_t()
+        assert L.lib().mrmf_sector_spectral_bounds_scratch_bytes(sec, ctypes.byref(nb)) == 0
+        assert nb.value >= 16 and nb.value % 16 == 0
+        assert L.lib().mrmf_sector_spectral_bounds_scratch_bytes(None, ctypes.byref(nb)) == L.MRMF_E_INVALID_ARG
+        fake = ctypes.c_void_p(1 << 20)
+        fn = L.lib().mrmf_sector_spectral_bounds
+        assert fn(None, fake, fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, None, fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, fake, None, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, fake, fake, None, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, fake, fake, fake, None, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, ctypes.c_void_p((1 << 20) + 8), fake, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, fake, fake, ctypes.c_void_p((1 << 20) + 4), fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+        assert fn(sec, fake, fake, fake, fake, nb.value - 16, None) == L.MRMF_E_WORKSPACE
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
+    nh = Model([spin_site(1)] * 3, [Term(0, OP_RAISE, 1, OP_LOWER, 0, 1.0)], np.ones(1))
+    st, h = host_plan(nh, require_hermitian=False)
+    sec = ctypes.c_void_p()
+    try:
+        L.call("mrmf_sector_create", h, 1, ctypes.byref(sec))
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.lib().mrmf_sector_spectral_bounds(sec, fake, fake, fake, fake, 1 << 20,
+                                                   None) == L.MRMF_E_NOT_HERMITIAN
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
+
+
 def test_lanczos_refuses_non_hermitian_plans():
     """mrmf_lanczos and mrmf_sector_lanczos return MRMF_E_NOT_HERMITIAN, before any launch, for a plan
     built without MRMF_REQUIRE_HERMITIAN whose parameter group is not Hermitian (S_+ S_- without its

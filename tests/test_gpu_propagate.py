@@ -359,3 +359,80 @@ def test_sector_propagation_fused_matches_two_pass():
         e = rel_err(rf["x"].cpu().numpy(), r2["x"].cpu().numpy())
         print(f"steps {steps}: terms {rf['n_terms']} / {r2['n_terms']}, fused vs two-pass {e:.2e}", flush=True)
         assert rf["n_terms"] == r2["n_terms"] and e <= 1e-13
+
+
+def sector_gershgorin_dense(m, lab, theta=None):
+    """Gershgorin ends of P H P^T from the oracle's dense Kronecker H restricted to the sector's states."""
+    from oracle import kron
+    Hs = kron.dense_H(m, theta)[np.ix_(lab, lab)]
+    d = np.diag(Hs)
+    R = np.abs(Hs).sum(axis=1) - np.abs(d)
+    return float((d.real - R).min()), float((d.real + R).max()), np.linalg.eigvalsh(Hs)
+
+
+@pytest.mark.parametrize("case", ["ring6_half", "ring8_zero", "spin1_ring6", "mixed_ring6", "tavis_cummings"])
+def test_sector_spectral_bounds_match_gershgorin(case):
+    """mrmf_sector_spectral_bounds against the Gershgorin ends of the oracle's dense H restricted to the
+    sector (no two channels share an entry in these models), hence containing the sector's spectrum, and
+    inside the plan's bounds (every sector row is a row of H, with a subset of its off-diagonal entries)."""
+    from oracle import sector as osec
+    from paper_2606_02169_amd.plan import Plan, Sector
+    if case == "tavis_cummings":
+        m = W.tavis_cummings(4, 6, 1.0, 0.7, np.random.default_rng(5))
+        Q = 5
+    else:
+        m = {"ring6_half": lambda: W.ferrimagnetic_ring(6), "ring8_zero": lambda: W.ferrimagnetic_ring(8),
+             "spin1_ring6": lambda: W.staggered_xxz_ring([2] * 6),
+             "mixed_ring6": lambda: W.staggered_xxz_ring([1, 1, 2, 2, 3, 3])}[case]()
+        Q = Sector.digit_sum_of(m.sites, 0.5 if case == "ring6_half" else 0.0)
+    lab = osec.labels(m, Q)
+    p = Plan.from_model(m)
+    S = Sector(p, Q)
+    assert S.dim == lab.size
+    lo, hi = S.spectral_bounds(t(m.theta))
+    slo, shi, ev = sector_gershgorin_dense(m, lab)
+    plo, phi = p.spectral_bounds(t(m.theta))
+    tol = 1e-12 * max(1.0, abs(slo), abs(shi))
+    print(case, lab.size, (lo, hi), (slo, shi), (ev[0], ev[-1]), (plo, phi), flush=True)
+    assert abs(lo - slo) <= tol and abs(hi - shi) <= tol
+    assert lo <= ev[0] + tol and hi >= ev[-1] - tol
+    assert plo <= lo + tol and phi >= hi - tol
+
+
+def test_sector_spectral_bounds_default_and_fewer_terms():
+    """Sector propagation defaults to the sector's own bounds (extreme ends over a drive's steps): on the
+    12-site ring's S_z = 0 sector they are no wider than the plan's and need no more Chebyshev terms, for
+    the same state; on the 6-site ring's M = 1/2 sector the driven result matches exp(-i dt H_s) step by
+    step."""
+    from scipy.linalg import expm
+    from oracle import kron
+    from oracle import sector as osec
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m, _ = W.config(2, reduced=12)
+    p = Plan.from_model(m)
+    S = Sector(p, Sector.digit_sum_of(m.sites, 0.0))
+    th = t(m.theta)
+    xs = t(W.random_state(S.dim, np.random.default_rng(8700)))
+    rs = S.propagate(th, xs, 0.5, 2)
+    rp = S.propagate(th, xs, 0.5, 2, bounds=p.spectral_bounds(th))
+    lo, hi = S.spectral_bounds(th)
+    print("sector bounds", rs["bounds"], "plan bounds", rp["bounds"], "terms", rs["n_terms"], rp["n_terms"],
+          flush=True)
+    assert rs["bounds"][0] <= lo and rs["bounds"][1] >= hi
+    assert rs["bounds"][1] - rs["bounds"][0] <= rp["bounds"][1] - rp["bounds"][0]
+    assert rs["n_terms"] <= rp["n_terms"]
+    assert rel_err(rs["x"].cpu().numpy(), rp["x"].cpu().numpy()) <= 1e-11
+    m = W.ferrimagnetic_ring(6)
+    Q = Sector.digit_sum_of(m.sites, 0.5)
+    lab = osec.labels(m, Q)
+    S = Sector(Plan.from_model(m), Q)
+    steps, dt = 4, 0.3
+    thetas = np.stack([m.theta * np.array([1.0, 1 + 0.4 * np.sin(s), 1.0, 1 + 0.6 * np.cos(s)]) for s in range(steps)])
+    each = [S.spectral_bounds(t(x)) for x in thetas]
+    x0 = W.random_state(lab.size, np.random.default_rng(8701))
+    r = S.propagate(t(thetas), t(x0), dt, steps)
+    assert r["bounds"][0] <= min(e[0] for e in each) and r["bounds"][1] >= max(e[1] for e in each)
+    ref = x0.astype(np.complex128)
+    for x in thetas:
+        ref = expm(-1j * dt * kron.dense_H(m, x)[np.ix_(lab, lab)]) @ ref
+    assert rel_err(r["x"].cpu().numpy(), ref) <= 1e-11
