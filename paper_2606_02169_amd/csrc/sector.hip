@@ -13,6 +13,7 @@
 // Sec. VI.B) and is dropped when the sector is built; one-site ladder channels are such channels.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mrmf_internal.h"
@@ -326,35 +327,114 @@ __global__ __launch_bounds__(kSB) void k_sector_lookup(SectorArgs a, int64_t D, 
     }
 }
 
-// Gershgorin bounds of P H P^T: per packed row (digits by unranking), the diagonal entry (the real parts
-// of the diagonal terms; Hermitian groups have real diagonals) -+ the sum over the sector's channels whose
+// Gershgorin bounds of P H P^T: per packed row (digits from the packed-digit word when the workspace holds
+// them, L = uint32_t or uint64_t, else by unranking, L = void), the diagonal entry (the real parts of the
+// diagonal terms; Hermitian groups have real diagonals) -+ the sum over the sector's channels whose
 // source digits are in range of |theta w f| (the channels keep the digit sum, so such a source is in the
 // sector); block min / max, then one thread over the blocks.
-__global__ __launch_bounds__(kSB) void k_sector_gershgorin(SectorArgs a, const double* __restrict__ theta,
+//
+// TAB: every term's contribution as a function of its two digits is tabulated in LDS when the block starts
+// (diagonal terms: theta_p w_r f_a(n_a) f_b(n_b); channels: |theta_p w f_a(n_a) f_b(n_b)|, 0 where a
+// source digit leaves its range), so that a row costs one LDS read per term; the tables of all terms
+// together must fit kGershTab entries.  Without TAB the row evaluates the factors itself.
+constexpr int kGershTab = 2048;
+constexpr int kGershMaxTerms = 256;
+
+template <typename L>
+__device__ __forceinline__ void sector_row_digits(const SectorArgs& a, const void* lab, int64_t r,
+                                                  uint8_t (*dig)[kSB], uint16_t (*rem)[kSB], int tid) {
+    if constexpr (std::is_void_v<L>) {
+        unrank(a, r, dig, rem, tid);
+    } else {  // site N - 1 in the lowest bits, w_k = bit width of d_k - 1 (as k_sector_pack writes them)
+        L word = static_cast<const L*>(lab)[r];
+        for (int k = a.p.N - 1; k >= 0; --k) {
+            const int d = a.p.site[k].d;
+            const int w = d > 1 ? 32 - __clz(d - 1) : 0;
+            dig[k][tid] = static_cast<uint8_t>(word & ((L(1) << w) - 1));
+            word >>= w;
+        }
+    }
+}
+
+template <typename L, bool TAB>
+__global__ __launch_bounds__(kSB) void k_sector_gershgorin(SectorArgs a, const void* __restrict__ lab,
+                                                           const double* __restrict__ theta,
                                                            double* __restrict__ partial) {
     __shared__ uint8_t dig[kMaxSites][kSB];
     __shared__ uint16_t rem[kMaxSites][kSB];
     __shared__ double slo[kSB], shi[kSB];
+    __shared__ double tab[TAB ? kGershTab : 1];
+    __shared__ int4 td[TAB ? kGershMaxTerms : 1];  // per term: site a, site b (-1: none), d_b, table offset
     const int tid = threadIdx.x;
     const PlanArgs& p = a.p;
+    const int nt = p.n_diag + p.n_chan;
+    if constexpr (TAB) {
+        if (tid == 0) {  // table offsets, diagonal terms first (the host checked that they fit)
+            int off = 0;
+            for (int k = 0; k < nt; ++k) {
+                const bool dg = k < p.n_diag;
+                const int ta = dg ? p.diag[k].a : p.chan[k - p.n_diag].a;
+                const int tb = dg ? p.diag[k].b : p.chan[k - p.n_diag].b;
+                const int db = tb >= 0 ? p.site[tb].d : 1;
+                td[k] = make_int4(ta, tb, db, off);
+                off += p.site[ta].d * db;
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < nt; ++k) {
+            const int4 t = td[k];
+            const int n = p.site[t.x].d * t.z;
+            for (int e = tid; e < n; e += kSB) {
+                const int na = e / t.z, nb = e - na * t.z;
+                double v;
+                if (k < p.n_diag) {
+                    const DevDiag g = p.diag[k];
+                    double f = sfactor<double>(p, g.opa, p.site[g.a].tab, na);
+                    if (g.b >= 0) f *= sfactor<double>(p, g.opb, p.site[g.b].tab, nb);
+                    v = theta[g.param] * g.wr * f;
+                } else {
+                    const DevChan ch = p.chan[k - p.n_diag];
+                    const int sa = na - ch.qa, sb = nb - ch.qb;
+                    v = 0.0;
+                    if (sa >= 0 && sa < p.site[ch.a].d && sb >= 0 && sb < p.site[ch.b].d)
+                        v = fabs(theta[ch.param] * sfactor<double>(p, ch.opa, p.site[ch.a].tab, na) *
+                                 sfactor<double>(p, ch.opb, p.site[ch.b].tab, nb)) *
+                            sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+                }
+                tab[t.w + e] = v;
+            }
+        }
+        __syncthreads();
+    }
     double lo = __builtin_inf(), hi = -__builtin_inf();
     for (int64_t r = int64_t(blockIdx.x) * kSB + tid; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
-        unrank(a, r, dig, rem, tid);
+        sector_row_digits<L>(a, lab, r, dig, rem, tid);
         double diag = 0.0, rad = 0.0;
-        for (int k = 0; k < p.n_diag; ++k) {
-            const DevDiag g = p.diag[k];
-            double f = sfactor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
-            if (g.b >= 0) f *= sfactor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
-            diag += theta[g.param] * g.wr * f;
-        }
-        for (int c = 0; c < p.n_chan; ++c) {
-            const DevChan ch = p.chan[c];
-            const int na = dig[ch.a][tid], nb = dig[ch.b][tid];
-            const int sa = na - ch.qa, sb = nb - ch.qb;
-            if (sa < 0 || sa >= p.site[ch.a].d || sb < 0 || sb >= p.site[ch.b].d) continue;
-            const double f = sfactor<double>(p, ch.opa, p.site[ch.a].tab, na) *
-                             sfactor<double>(p, ch.opb, p.site[ch.b].tab, nb);
-            rad += fabs(theta[ch.param] * f) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+        if constexpr (TAB) {
+            for (int k = 0; k < nt; ++k) {
+                const int4 t = td[k];
+                const int e = dig[t.x][tid] * t.z + (t.y >= 0 ? dig[t.y][tid] : 0);
+                if (k < p.n_diag)
+                    diag += tab[t.w + e];
+                else
+                    rad += tab[t.w + e];
+            }
+        } else {
+            for (int k = 0; k < p.n_diag; ++k) {
+                const DevDiag g = p.diag[k];
+                double f = sfactor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+                if (g.b >= 0) f *= sfactor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+                diag += theta[g.param] * g.wr * f;
+            }
+            for (int c = 0; c < p.n_chan; ++c) {
+                const DevChan ch = p.chan[c];
+                const int na = dig[ch.a][tid], nb = dig[ch.b][tid];
+                const int sa = na - ch.qa, sb = nb - ch.qb;
+                if (sa < 0 || sa >= p.site[ch.a].d || sb < 0 || sb >= p.site[ch.b].d) continue;
+                const double f = sfactor<double>(p, ch.opa, p.site[ch.a].tab, na) *
+                                 sfactor<double>(p, ch.opb, p.site[ch.b].tab, nb);
+                rad += fabs(theta[ch.param] * f) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+            }
         }
         lo = fmin(lo, diag - rad);
         hi = fmax(hi, diag + rad);
@@ -695,7 +775,25 @@ mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, co
     const int grid = sector_gersh_grid(sector->Dr);
     double* partial = static_cast<double*>(d_scratch);
     const double* theta = sector->n_params > 0 ? d_theta : partial;  // never read when there are no params
-    hipLaunchKernelGGL(k_sector_gershgorin, dim3(grid), dim3(kSB), 0, s, sector_args(sector, d_ws), theta, partial);
+    const SectorArgs sa = sector_args(sector, d_ws);
+    const void* lab = static_cast<const unsigned char*>(d_ws) + sector->off_lab;
+    // per-term digit tables in LDS when they fit
+    const int nt = static_cast<int>(sector->diags.size() + sector->chans.size());
+    int64_t entries = 0;
+    for (const auto& g : sector->diags) entries += int64_t(sector->d[g.a]) * (g.b >= 0 ? sector->d[g.b] : 1);
+    for (const auto& c : sector->chans) entries += int64_t(sector->d[c.a]) * sector->d[c.b];
+    const bool tab = nt <= kGershMaxTerms && entries <= kGershTab;
+    const dim3 g(grid), b(kSB);
+    if (sector->lab_bytes == 4) {
+        if (tab) hipLaunchKernelGGL((k_sector_gershgorin<uint32_t, true>), g, b, 0, s, sa, lab, theta, partial);
+        else hipLaunchKernelGGL((k_sector_gershgorin<uint32_t, false>), g, b, 0, s, sa, lab, theta, partial);
+    } else if (sector->lab_bytes == 8) {
+        if (tab) hipLaunchKernelGGL((k_sector_gershgorin<uint64_t, true>), g, b, 0, s, sa, lab, theta, partial);
+        else hipLaunchKernelGGL((k_sector_gershgorin<uint64_t, false>), g, b, 0, s, sa, lab, theta, partial);
+    } else {
+        if (tab) hipLaunchKernelGGL((k_sector_gershgorin<void, true>), g, b, 0, s, sa, nullptr, theta, partial);
+        else hipLaunchKernelGGL((k_sector_gershgorin<void, false>), g, b, 0, s, sa, nullptr, theta, partial);
+    }
     hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
     return launch_status();
 }

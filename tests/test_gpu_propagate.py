@@ -370,23 +370,37 @@ def sector_gershgorin_dense(m, lab, theta=None):
     return float((d.real - R).min()), float((d.real + R).max()), np.linalg.eigvalsh(Hs)
 
 
-@pytest.mark.parametrize("case", ["ring6_half", "ring8_zero", "spin1_ring6", "mixed_ring6", "tavis_cummings"])
+@pytest.mark.parametrize("case", ["ring6_half", "ring8_zero", "ring8_generic", "spin1_ring6", "mixed_ring6",
+                                  "tavis_cummings", "two_bosons"])
 def test_sector_spectral_bounds_match_gershgorin(case):
     """mrmf_sector_spectral_bounds against the Gershgorin ends of the oracle's dense H restricted to the
-    sector (no two channels share an entry in these models), hence containing the sector's spectrum, and
-    inside the plan's bounds (every sector row is a row of H, with a subset of its off-diagonal entries)."""
+    sector (no two channels share an entry in these models; digits from the packed-digit words, or by
+    unranking for a sector made in generic mode), hence containing the sector's spectrum, and inside the
+    plan's bounds (every sector row is a row of H, with a subset of its off-diagonal entries)."""
     from oracle import sector as osec
     from paper_2606_02169_amd.plan import Plan, Sector
     if case == "tavis_cummings":
         m = W.tavis_cummings(4, 6, 1.0, 0.7, np.random.default_rng(5))
         Q = 5
+    elif case == "two_bosons":        # two 40-level modes and a spin between them: term tables too large to
+        from workloads.model import OP_LOWER, OP_RAISE, OP_Z, Model, Term, boson_site, spin_site
+        m = Model([boson_site(39), spin_site(1), boson_site(39)],   # tabulate, so rows evaluate factors
+                  [Term(0, OP_RAISE, 2, OP_LOWER, 0, 0.7 + 0.2j), Term(0, OP_LOWER, 2, OP_RAISE, 0, 0.7 - 0.2j),
+                   Term(0, OP_LOWER, 1, OP_RAISE, 1, 1.0), Term(0, OP_RAISE, 1, OP_LOWER, 1, 1.0),
+                   Term(0, OP_Z, -1, OP_Z, 2, 1.0), Term(2, OP_Z, -1, OP_Z, 2, 1.3), Term(1, OP_Z, -1, OP_Z, 3, 1.0),
+                   Term(0, OP_Z, 2, OP_Z, 3, 0.05)],
+                  np.array([1.0, 0.4, 0.9, 0.5]))
+        Q = 30
     else:
         m = {"ring6_half": lambda: W.ferrimagnetic_ring(6), "ring8_zero": lambda: W.ferrimagnetic_ring(8),
+             "ring8_generic": lambda: W.ferrimagnetic_ring(8),
              "spin1_ring6": lambda: W.staggered_xxz_ring([2] * 6),
              "mixed_ring6": lambda: W.staggered_xxz_ring([1, 1, 2, 2, 3, 3])}[case]()
         Q = Sector.digit_sum_of(m.sites, 0.5 if case == "ring6_half" else 0.0)
     lab = osec.labels(m, Q)
     p = Plan.from_model(m)
+    if case == "ring8_generic":       # a sector made from a plan in generic mode holds no packed digits: the
+        p.set_kernel("generic")       # bounds kernel unranks its rows
     S = Sector(p, Q)
     assert S.dim == lab.size
     lo, hi = S.spectral_bounds(t(m.theta))
