@@ -107,12 +107,62 @@ __global__ __launch_bounds__(kGenericBlock) void k_matvec_generic(
 // diagonal terms, and for R_F the sum over the admissible channels of |theta_p w f| (at least the row's
 // off-diagonal sum, several channels may meet in one entry).  Each block writes the minimum of
 // H_FF - R_F and the maximum of H_FF + R_F over its rows to partial[2 b], partial[2 b + 1].
-template <bool WIDE>
+//
+// TAB: every term's contribution as a function of its (one or two) digits is tabulated in LDS when the
+// block starts (diagonal terms: theta_p w_r f_a(n_a) f_b(n_b); channels: |theta_p w f_a(n_a) f_b(n_b)|, 0
+// where a source digit leaves its range), so that a row costs one LDS read per term; the tables of all
+// terms together must fit kGershTab entries.  Without TAB the row evaluates the factors itself.
+constexpr int kGershTab = 2048;
+constexpr int kGershMaxTerms = 256;
+
+template <bool WIDE, bool TAB>
 __global__ __launch_bounds__(kGenericBlock) void k_gershgorin(PlanArgs p, const double* __restrict__ theta,
                                                                double* __restrict__ partial) {
     __shared__ uint8_t dig[kMaxSites][kGenericBlock];
     __shared__ double slo[kGenericBlock], shi[kGenericBlock];
+    __shared__ double tab[TAB ? kGershTab : 1];
+    __shared__ int4 td[TAB ? kGershMaxTerms : 1];  // per term: site a, site b (-1: none), d_b (1), table offset
     const int tid = threadIdx.x;
+    const int nt = p.n_diag + p.n_chan;
+    if constexpr (TAB) {
+        if (tid == 0) {  // table offsets, diagonal terms first (the host checked that they fit)
+            int off = 0;
+            for (int k = 0; k < nt; ++k) {
+                const bool dg = k < p.n_diag;
+                const int ta = dg ? p.diag[k].a : p.chan[k - p.n_diag].a;
+                const int tb = dg ? p.diag[k].b : p.chan[k - p.n_diag].b;
+                const int db = tb >= 0 ? p.site[tb].d : 1;
+                td[k] = make_int4(ta, tb, db, off);
+                off += p.site[ta].d * db;
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < nt; ++k) {
+            const int4 t = td[k];
+            const int n = p.site[t.x].d * t.z;
+            for (int e = tid; e < n; e += kGenericBlock) {
+                const int na = e / t.z, nb = e - na * t.z;
+                double v;
+                if (k < p.n_diag) {
+                    const DevDiag g = p.diag[k];
+                    double f = local_factor<double>(p, g.opa, p.site[g.a].tab, na);
+                    if (g.b >= 0) f *= local_factor<double>(p, g.opb, p.site[g.b].tab, nb);
+                    v = theta[g.param] * g.wr * f;
+                } else {
+                    const DevChan ch = p.chan[k - p.n_diag];
+                    bool ok = na - ch.qa >= 0 && na - ch.qa < p.site[ch.a].d;
+                    double f = local_factor<double>(p, ch.opa, p.site[ch.a].tab, na);
+                    if (ch.b >= 0) {
+                        ok = ok && nb - ch.qb >= 0 && nb - ch.qb < p.site[ch.b].d;
+                        f *= local_factor<double>(p, ch.opb, p.site[ch.b].tab, nb);
+                    }
+                    v = ok ? fabs(theta[ch.param] * f) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi) : 0.0;
+                }
+                tab[t.w + e] = v;
+            }
+        }
+        __syncthreads();
+    }
     double lo = __builtin_inf(), hi = -__builtin_inf();
     const int64_t stride = int64_t(gridDim.x) * kGenericBlock;
     for (int64_t F = int64_t(blockIdx.x) * kGenericBlock + tid; F < p.D; F += stride) {
@@ -133,25 +183,36 @@ __global__ __launch_bounds__(kGenericBlock) void k_gershgorin(PlanArgs p, const 
             }
         }
         double diag = 0.0, rad = 0.0;
-        for (int k = 0; k < p.n_diag; ++k) {
-            const DevDiag g = p.diag[k];
-            double fa = local_factor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
-            if (g.b >= 0) fa *= local_factor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
-            diag += theta[g.param] * g.wr * fa;
-        }
-        for (int c = 0; c < p.n_chan; ++c) {
-            const DevChan ch = p.chan[c];
-            const DevSite sa = p.site[ch.a];
-            const int na = dig[ch.a][tid];
-            if (na - ch.qa < 0 || na - ch.qa >= sa.d) continue;
-            double fa = local_factor<double>(p, ch.opa, sa.tab, na);
-            if (ch.b >= 0) {
-                const DevSite sb = p.site[ch.b];
-                const int nb = dig[ch.b][tid];
-                if (nb - ch.qb < 0 || nb - ch.qb >= sb.d) continue;
-                fa *= local_factor<double>(p, ch.opb, sb.tab, nb);
+        if constexpr (TAB) {
+            for (int k = 0; k < nt; ++k) {
+                const int4 t = td[k];
+                const int e = dig[t.x][tid] * t.z + (t.y >= 0 ? dig[t.y][tid] : 0);
+                if (k < p.n_diag)
+                    diag += tab[t.w + e];
+                else
+                    rad += tab[t.w + e];
             }
-            rad += fabs(theta[ch.param] * fa) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+        } else {
+            for (int k = 0; k < p.n_diag; ++k) {
+                const DevDiag g = p.diag[k];
+                double fa = local_factor<double>(p, g.opa, p.site[g.a].tab, dig[g.a][tid]);
+                if (g.b >= 0) fa *= local_factor<double>(p, g.opb, p.site[g.b].tab, dig[g.b][tid]);
+                diag += theta[g.param] * g.wr * fa;
+            }
+            for (int c = 0; c < p.n_chan; ++c) {
+                const DevChan ch = p.chan[c];
+                const DevSite sa = p.site[ch.a];
+                const int na = dig[ch.a][tid];
+                if (na - ch.qa < 0 || na - ch.qa >= sa.d) continue;
+                double fa = local_factor<double>(p, ch.opa, sa.tab, na);
+                if (ch.b >= 0) {
+                    const DevSite sb = p.site[ch.b];
+                    const int nb = dig[ch.b][tid];
+                    if (nb - ch.qb < 0 || nb - ch.qb >= sb.d) continue;
+                    fa *= local_factor<double>(p, ch.opb, sb.tab, nb);
+                }
+                rad += fabs(theta[ch.param] * fa) * sqrt(ch.wr * ch.wr + ch.wi * ch.wi);
+            }
         }
         lo = fmin(lo, diag - rad);
         hi = fmax(hi, diag + rad);
@@ -294,12 +355,19 @@ mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double*
     const int grid = gershgorin_grid(plan->D);
     double* partial = static_cast<double*>(d_scratch);
     const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
-    if (plan->D <= int64_t(0xffffffffu))
-        hipLaunchKernelGGL(k_gershgorin<false>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws), theta,
-                           partial);
-    else
-        hipLaunchKernelGGL(k_gershgorin<true>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws), theta,
-                           partial);
+    // per-term digit tables in LDS when they fit
+    const int nt = static_cast<int>(plan->diags.size() + plan->chans.size());
+    int64_t entries = 0;
+    for (const auto& g : plan->diags) entries += int64_t(plan->d[g.a]) * (g.b >= 0 ? plan->d[g.b] : 1);
+    for (const auto& c : plan->chans) entries += int64_t(plan->d[c.a]) * (c.b >= 0 ? plan->d[c.b] : 1);
+    const bool tab = nt <= kGershMaxTerms && entries <= kGershTab;
+    const bool narrow = plan->D <= int64_t(0xffffffffu);
+    const dim3 g(grid), b(kGenericBlock);
+    const PlanArgs pa = plan_args(plan, d_ws);
+    if (narrow && tab) hipLaunchKernelGGL((k_gershgorin<false, true>), g, b, 0, s, pa, theta, partial);
+    else if (narrow) hipLaunchKernelGGL((k_gershgorin<false, false>), g, b, 0, s, pa, theta, partial);
+    else if (tab) hipLaunchKernelGGL((k_gershgorin<true, true>), g, b, 0, s, pa, theta, partial);
+    else hipLaunchKernelGGL((k_gershgorin<true, false>), g, b, 0, s, pa, theta, partial);
     hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
     return launch_status();
 }

@@ -224,8 +224,9 @@ def gershgorin_ring_dp(N, jxy=1.0, jz=1.2, dsi=0.5, hz=0.1):
 
 
 def test_spectral_bounds_match_gershgorin():
-    """Reduced rings and the 20-site ring (D = 60,466,176) against the max-plus ends, a reduced ring and a
-    spin-boson model against the sparse oracle matrix (no two channels share an entry in these models)."""
+    """Reduced rings and the 20-site ring (D = 60,466,176) against the max-plus ends, a reduced ring and
+    two spin-boson models against the sparse oracle matrix (no two channels share an entry in these
+    models)."""
     from paper_2606_02169_amd.plan import Plan
     for N in (8, 20):
         m, _ = W.config(2, reduced=N if N < 20 else 0, with_state=False)
@@ -239,6 +240,19 @@ def test_spectral_bounds_match_gershgorin():
     tc = W.tavis_cummings(4, 10, 1.0, 1.0, np.random.default_rng(5))
     lo, hi = Plan.from_model(tc).spectral_bounds(t(tc.theta))
     slo, shi = gershgorin_sparse(tc)
+    assert abs(lo - slo) <= 1e-12 * max(1.0, abs(slo)) and abs(hi - shi) <= 1e-12 * max(1.0, abs(shi))
+    # two 40-level modes and a spin: the term tables exceed what the kernel tabulates in LDS, so its rows
+    # evaluate their factors
+    from workloads.model import OP_LOWER, OP_RAISE, OP_Z, Model, Term, boson_site, spin_site
+    tb = Model([boson_site(39), spin_site(1), boson_site(39)],
+               [Term(0, OP_RAISE, 2, OP_LOWER, 0, 0.7 + 0.2j), Term(0, OP_LOWER, 2, OP_RAISE, 0, 0.7 - 0.2j),
+                Term(0, OP_LOWER, 1, OP_RAISE, 1, 1.0), Term(0, OP_RAISE, 1, OP_LOWER, 1, 1.0),
+                Term(1, OP_RAISE, -1, OP_Z, 1, 0.3), Term(1, OP_LOWER, -1, OP_Z, 1, 0.3),
+                Term(0, OP_Z, -1, OP_Z, 2, 1.0), Term(2, OP_Z, -1, OP_Z, 2, 1.3), Term(0, OP_Z, 2, OP_Z, 3, 0.05)],
+               np.array([1.0, 0.4, 0.9, 0.5]))
+    lo, hi = Plan.from_model(tb).spectral_bounds(t(tb.theta))
+    slo, shi = gershgorin_sparse(tb)
+    print("two bosons", (lo, hi), (slo, shi), flush=True)
     assert abs(lo - slo) <= 1e-12 * max(1.0, abs(slo)) and abs(hi - shi) <= 1e-12 * max(1.0, abs(shi))
 
 
