@@ -683,6 +683,7 @@ def bench_propagate(args, dev):
     """exp(-i H dt) on the 20-site ring (c128): Chebyshev terms per step, time per step with the fixed H's
     steps merged into one series (the default) and with one series per step, time per term, against the
     plain matvec; invariants (norm, reversal) on the same vector."""
+    import numpy as np
     import torch
 
     import workloads as W
@@ -700,6 +701,11 @@ def bench_propagate(args, dev):
     bnd = p.norm_bound(model.theta)
     lo, hi = p.spectral_bounds(th)
     ms_gersh = cuda_time(lambda: p.spectral_bounds(th), stream, 1 if args.profile else 5)
+    # the bounds of a 100-step piecewise drive (J_z and h_z modulated) in one pass over the rows
+    drive = torch.as_tensor(np.stack([model.theta * np.array([1.0, 1 + 0.3 * np.sin(0.1 * k), 1.0,
+                                                              1 + 0.5 * np.cos(0.1 * k)]) for k in range(100)]),
+                            dtype=torch.float64, device=dev)
+    ms_gersh_drive = cuda_time(lambda: p.spectral_bounds(drive), stream, 1 if args.profile else 3)
     pad = 1e-9 * max(hi - lo, abs(lo), abs(hi))
     bounds = (lo - pad, hi + pad)
     r = p.propagate(th, xt, dt, 1, bounds=bounds)
@@ -730,7 +736,9 @@ def bench_propagate(args, dev):
     back = p.propagate(th, out, -dt, steps, bounds=bounds)["x"]
     res = {"metric": "exp(-i H dt) x by Chebyshev expansion over the matvec (c128)",
            "workload": "ferrimagnetic_ring_N20_c128", "D": model.dim, "dt": dt, "steps": steps,
-           "gershgorin_bounds": [lo, hi], "gershgorin_ms": ms_gersh, "terms_per_step": nt,
+           "gershgorin_bounds": [lo, hi], "gershgorin_ms": ms_gersh,
+           "gershgorin_drive_100_steps": {"one_pass_ms": ms_gersh_drive, "one_vector_per_pass_ms": 100 * ms_gersh},
+           "terms_per_step": nt,
            "ms_per_step": ms, "terms_merged_call": nt_call,
            "ms_per_step_one_series_per_step": ms_stepwise, "ms_per_term": ms_stepwise / max(1, nt - 1),
            "merged_vs_stepwise_rel_diff": ((out - x_stepwise).norm() / x_stepwise.norm()).item(),

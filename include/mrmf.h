@@ -402,6 +402,19 @@ mrmf_status mrmf_plan_norm_bound(mrmf_plan plan, const double* h_theta, double* 
 mrmf_status mrmf_spectral_bounds_scratch_bytes(mrmf_plan plan, size_t* bytes);
 mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double* d_theta, double* d_out,
                                  void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+/* The same ends over count coupling vectors at once (a piecewise-constant drive, a parameter sweep):
+ * d_out[0] <= every eigenvalue of H(theta_s) <= d_out[1] for s = 0 .. count - 1, theta_s at
+ * d_theta + s * theta_stride (doubles; stride 0 repeats one vector).  One pass over the rows: since H is
+ * linear in the couplings (Sec. II: H = sum of parameter groups, each term carrying one coupling), a row's
+ * diagonal entry is sum_p theta_p A_p and its channel radius sum_p |theta_p| B_p, with A_p and B_p taken
+ * once per row from per-term tables in LDS; each further vector costs 2 n_params multiply-adds per row.
+ * The ends equal the extremes of count calls of mrmf_spectral_bounds up to the order of the sums.
+ * MRMF_E_UNSUPPORTED for plans with more than 8 couplings, more than 256 terms or term tables of more
+ * than 2048 entries (call mrmf_spectral_bounds per vector then); count >= 1, theta_stride >= 0.
+ *   d_scratch : mrmf_spectral_bounds_scratch_bytes, 8-B aligned. */
+mrmf_status mrmf_spectral_bounds_many(mrmf_plan plan, const void* d_ws, const double* d_theta, int64_t theta_stride,
+                                      int32_t count, double* d_out, void* d_scratch, size_t scratch_bytes,
+                                      mrmf_stream stream);
 
 /* Host-only: the Bessel weights J_0(z) .. J_{K}(z) (z >= 0) used by mrmf_propagate_z, with K the smallest
  * index whose tail 2 sum_{k > K} |J_k(z)| is <= tol; *n_terms = K + 1 and h_out (may be NULL, else at
@@ -473,6 +486,11 @@ mrmf_status mrmf_sector_lanczos(mrmf_sector sector, const void* d_ws, const doub
 mrmf_status mrmf_sector_spectral_bounds_scratch_bytes(mrmf_sector sector, size_t* bytes);
 mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, const double* d_theta, double* d_out,
                                         void* d_scratch, size_t scratch_bytes, mrmf_stream stream);
+/* The sector's ends over count coupling vectors in one pass, as mrmf_spectral_bounds_many is for the plan
+ * (same arguments, limits and MRMF_E_UNSUPPORTED); d_scratch: mrmf_sector_spectral_bounds_scratch_bytes. */
+mrmf_status mrmf_sector_spectral_bounds_many(mrmf_sector sector, const void* d_ws, const double* d_theta,
+                                             int64_t theta_stride, int32_t count, double* d_out, void* d_scratch,
+                                             size_t scratch_bytes, mrmf_stream stream);
 /* Time propagation inside the sector, x = exp(-i P H P^T dt)^n_steps x0 on packed vectors (the restricted
  * basis as the way to shrink the propagated state, Sec. VI and Sec. VIII): the arguments, the Chebyshev
  * series, the merging of fixed-H steps (as the plan's MRMF_TUNE_CHEB_MERGE was when the sector was made)

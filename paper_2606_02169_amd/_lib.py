@@ -111,6 +111,7 @@ SIGNATURES = {
     "mrmf_plan_norm_bound": (_i32, [_vp, _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mrmf_spectral_bounds_scratch_bytes": (_i32, [_vp, _P(ctypes.c_size_t)]),
     "mrmf_spectral_bounds": (_i32, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "mrmf_spectral_bounds_many": (_i32, [_vp, _vp, _vp, ctypes.c_int64, _i32, _vp, _vp, ctypes.c_size_t, _vp]),
     "mrmf_cheb_bessel": (_i32, [ctypes.c_double, ctypes.c_double, _i32, _P(ctypes.c_double), _P(_i32)]),
     "mrmf_sector_create": (_i32, [_vp, _i32, _P(_vp)]),
     "mrmf_sector_destroy": (None, [_vp]),
@@ -128,6 +129,7 @@ SIGNATURES = {
                                    _sz, _vp]),
     "mrmf_sector_spectral_bounds_scratch_bytes": (_i32, [_vp, _P(_sz)]),
     "mrmf_sector_spectral_bounds": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mrmf_sector_spectral_bounds_many": (_i32, [_vp, _vp, _vp, ctypes.c_int64, _i32, _vp, _vp, _sz, _vp]),
     "mrmf_sector_propagate_scratch_bytes": (_i32, [_vp, _P(_sz)]),
     "mrmf_sector_propagate_z": (_i32, [_vp, _vp, _vp, _i64, ctypes.c_double, _i32, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _sz, _P(_i32), _vp]),

@@ -7,6 +7,7 @@
 //
 // This kernel reads everything from the uploaded plan at run time, so it serves any Hamiltonian; the
 // digits of the thread's row are kept in LDS (one byte per site per thread).
+#include "gersh.h"
 #include "mrmf_internal.h"
 
 namespace mrmf {
@@ -230,6 +231,41 @@ __global__ __launch_bounds__(kGenericBlock) void k_gershgorin(PlanArgs p, const 
     }
 }
 
+// The same ends over count coupling vectors theta + s * stride in one pass (linear form of gersh.h).
+template <bool WIDE>
+__global__ __launch_bounds__(kGenericBlock) void k_gershgorin_lin(PlanArgs p, const double* __restrict__ theta,
+                                                                   int64_t stride, int32_t count,
+                                                                   double* __restrict__ partial) {
+    static_assert(kGenericBlock == kLinBlock, "block size of the shared bounds code");
+    __shared__ GershLinLds L;
+    __shared__ uint8_t dig[kMaxSites][kGenericBlock];
+    __shared__ double slo[kGenericBlock], shi[kGenericBlock];
+    const int tid = threadIdx.x;
+    gersh_lin_tables(p, [&](int op, int tab, int n) { return local_factor<double>(p, op, tab, n); }, L);
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    const int64_t step = int64_t(gridDim.x) * kGenericBlock;
+    for (int64_t F = int64_t(blockIdx.x) * kGenericBlock + tid; F < p.D; F += step) {
+        if (WIDE) {
+            int64_t f = F;
+            for (int i = p.N - 1; i >= 0; --i) {
+                const int64_t d = p.site[i].d;
+                const int64_t q = f / d;
+                dig[i][tid] = static_cast<uint8_t>(f - q * d);
+                f = q;
+            }
+        } else {
+            uint32_t f = static_cast<uint32_t>(F);
+            for (int i = p.N - 1; i >= 0; --i) {
+                const uint32_t q = div_magic(f, p.site[i].magic);
+                dig[i][tid] = static_cast<uint8_t>(f - q * static_cast<uint32_t>(p.site[i].d));
+                f = q;
+            }
+        }
+        gersh_lin_row(p, L, dig, theta, stride, count, lo, hi);
+    }
+    gersh_block_ends(lo, hi, slo, shi, partial);
+}
+
 __global__ void k_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
     double lo = partial[0], hi = partial[1];
     for (int b = 1; b < nb; ++b) {
@@ -368,6 +404,33 @@ mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double*
     else if (narrow) hipLaunchKernelGGL((k_gershgorin<false, false>), g, b, 0, s, pa, theta, partial);
     else if (tab) hipLaunchKernelGGL((k_gershgorin<true, true>), g, b, 0, s, pa, theta, partial);
     else hipLaunchKernelGGL((k_gershgorin<true, false>), g, b, 0, s, pa, theta, partial);
+    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    return launch_status();
+}
+
+mrmf_status mrmf_spectral_bounds_many(mrmf_plan plan, const void* d_ws, const double* d_theta, int64_t theta_stride,
+                                      int32_t count, double* d_out, void* d_scratch, size_t scratch_bytes,
+                                      mrmf_stream stream) {
+    using namespace mrmf;
+    if (!plan || !d_ws || !d_out || !d_scratch || (plan->n_params > 0 && !d_theta) || count < 1 ||
+        theta_stride < 0)
+        return MRMF_E_INVALID_ARG;
+    if (!plan->hermitian) return MRMF_E_NOT_HERMITIAN;
+    if (!aligned(d_ws, 256) || !aligned(d_scratch, 8) || !aligned(d_out, 8)) return MRMF_E_INVALID_ARG;
+    size_t need = 0;
+    mrmf_spectral_bounds_scratch_bytes(plan, &need);
+    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
+    if (!gersh_lin_fits(plan->n_params, plan->d, plan->diags, plan->chans)) return MRMF_E_UNSUPPORTED;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = gershgorin_grid(plan->D);
+    double* partial = static_cast<double*>(d_scratch);
+    const double* theta = plan->n_params > 0 ? d_theta : partial;  // never read when there are no params
+    if (plan->D <= int64_t(0xffffffffu))
+        hipLaunchKernelGGL(k_gershgorin_lin<false>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws),
+                           theta, theta_stride, count, partial);
+    else
+        hipLaunchKernelGGL(k_gershgorin_lin<true>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws),
+                           theta, theta_stride, count, partial);
     hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
     return launch_status();
 }

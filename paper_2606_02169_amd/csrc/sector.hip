@@ -16,6 +16,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "gersh.h"
 #include "mrmf_internal.h"
 
 namespace mrmf {
@@ -452,6 +453,27 @@ __global__ __launch_bounds__(kSB) void k_sector_gershgorin(SectorArgs a, const v
     }
 }
 
+// The same ends over count coupling vectors theta + s * stride in one pass (linear form of gersh.h).
+template <typename L>
+__global__ __launch_bounds__(kSB) void k_sector_gershgorin_lin(SectorArgs a, const void* __restrict__ lab,
+                                                               const double* __restrict__ theta, int64_t stride,
+                                                               int32_t count, double* __restrict__ partial) {
+    static_assert(kSB == kLinBlock, "block size of the shared bounds code");
+    __shared__ GershLinLds T;
+    __shared__ uint8_t dig[kMaxSites][kSB];
+    __shared__ uint16_t rem[kMaxSites][kSB];
+    __shared__ double slo[kSB], shi[kSB];
+    const int tid = threadIdx.x;
+    const PlanArgs& p = a.p;
+    gersh_lin_tables(p, [&](int op, int tab, int n) { return sfactor<double>(p, op, tab, n); }, T);
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (int64_t r = int64_t(blockIdx.x) * kSB + tid; r < a.Dr; r += int64_t(gridDim.x) * kSB) {
+        sector_row_digits<L>(a, lab, r, dig, rem, tid);
+        gersh_lin_row(p, T, dig, theta, stride, count, lo, hi);
+    }
+    gersh_block_ends(lo, hi, slo, shi, partial);
+}
+
 __global__ void k_sector_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
     double lo = partial[0], hi = partial[1];
     for (int b = 1; b < nb; ++b) {
@@ -794,6 +816,35 @@ mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, co
         if (tab) hipLaunchKernelGGL((k_sector_gershgorin<void, true>), g, b, 0, s, sa, nullptr, theta, partial);
         else hipLaunchKernelGGL((k_sector_gershgorin<void, false>), g, b, 0, s, sa, nullptr, theta, partial);
     }
+    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    return launch_status();
+}
+
+mrmf_status mrmf_sector_spectral_bounds_many(mrmf_sector sector, const void* d_ws, const double* d_theta,
+                                             int64_t theta_stride, int32_t count, double* d_out, void* d_scratch,
+                                             size_t scratch_bytes, mrmf_stream stream) {
+    if (!sector || !d_ws || !d_out || !d_scratch || (sector->n_params > 0 && !d_theta) || count < 1 ||
+        theta_stride < 0)
+        return MRMF_E_INVALID_ARG;
+    if (!sector->hermitian) return MRMF_E_NOT_HERMITIAN;
+    if (!aligned(d_ws, 256) || !aligned(d_scratch, 8) || !aligned(d_out, 8)) return MRMF_E_INVALID_ARG;
+    size_t need = 0;
+    mrmf_sector_spectral_bounds_scratch_bytes(sector, &need);
+    if (scratch_bytes < need) return MRMF_E_WORKSPACE;
+    if (!gersh_lin_fits(sector->n_params, sector->d, sector->diags, sector->chans)) return MRMF_E_UNSUPPORTED;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = sector_gersh_grid(sector->Dr);
+    double* partial = static_cast<double*>(d_scratch);
+    const double* theta = sector->n_params > 0 ? d_theta : partial;  // never read when there are no params
+    const SectorArgs sa = sector_args(sector, d_ws);
+    const void* lab = static_cast<const unsigned char*>(d_ws) + sector->off_lab;
+    const dim3 g(grid), b(kSB);
+    if (sector->lab_bytes == 4)
+        hipLaunchKernelGGL(k_sector_gershgorin_lin<uint32_t>, g, b, 0, s, sa, lab, theta, theta_stride, count, partial);
+    else if (sector->lab_bytes == 8)
+        hipLaunchKernelGGL(k_sector_gershgorin_lin<uint64_t>, g, b, 0, s, sa, lab, theta, theta_stride, count, partial);
+    else
+        hipLaunchKernelGGL(k_sector_gershgorin_lin<void>, g, b, 0, s, sa, nullptr, theta, theta_stride, count, partial);
     hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
     return launch_status();
 }

@@ -182,18 +182,10 @@ class Plan:
 
     def spectral_bounds(self, theta: torch.Tensor) -> tuple:
         """(e_min, e_max) containing the spectrum of H(theta), from the Gershgorin discs of its rows
-        (mrmf_spectral_bounds, one device pass over the rows).  theta: float64 [n_params] on the device."""
-        _need_gpu(theta, "theta", torch.float64)
-        if theta.numel() < self.n_params:
-            raise ValueError("theta has fewer than n_params entries")
-        nb = ctypes.c_size_t()
-        L.call("mrmf_spectral_bounds_scratch_bytes", self._handle, ctypes.byref(nb))
-        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        out = torch.empty(2, dtype=torch.float64, device=self.device)
-        L.call("mrmf_spectral_bounds", self._handle, _ptr(self.ws), _ptr(theta.contiguous()), _ptr(out),
-               _ptr(scratch), nb.value, _stream(self.device))
-        lo, hi = out.cpu().tolist()
-        return lo, hi
+        (mrmf_spectral_bounds, one device pass over the rows).  theta: float64 [n_params] on the device, or
+        [S, n_params] for the ends over S coupling vectors (mrmf_spectral_bounds_many: one pass for all of
+        them; one pass per vector for plans that form does not take)."""
+        return _spectral_bounds("mrmf_spectral_bounds", self._handle, self.ws, self.n_params, self.device, theta)
 
     def propagate(self, theta: torch.Tensor, x0: torch.Tensor, dt: float, n_steps: int = 1,
                   bounds: tuple | str | None = None, tol: float = 1e-12, out: torch.Tensor | None = None) -> dict:
@@ -239,17 +231,17 @@ class Plan:
                 b = b if b > 0 else 1.0
                 bounds = (-b, b)
             elif bounds is None:
-                rows = np.unique(th, axis=0) if th.shape[1] else th[:1]
-                cache = owner.__dict__.setdefault("_gersh_cache", {})   # the owner's terms never change
-                ends = []
-                for r in rows:
-                    key = np.ascontiguousarray(r).tobytes()
-                    if key not in cache:
-                        if len(cache) >= 256:
-                            cache.clear()
-                        cache[key] = owner.spectral_bounds(torch.from_numpy(np.ascontiguousarray(r)).to(self.device))
-                    ends.append(cache[key])
-                lo, hi = min(e[0] for e in ends), max(e[1] for e in ends)
+                # the distinct coupling vectors of the call, all in one device pass; cached on the owner
+                # (a plan or a sector: its terms never change) by those vectors
+                rows = np.ascontiguousarray(np.unique(th, axis=0) if th.shape[1] else th[:1])
+                cache = owner.__dict__.setdefault("_gersh_cache", {})
+                key = (rows.shape, rows.tobytes())
+                if key not in cache:
+                    if len(cache) >= 256:
+                        cache.clear()
+                    t = torch.from_numpy(rows).to(self.device)
+                    cache[key] = owner.spectral_bounds(t if rows.shape[0] > 1 else t[0])
+                lo, hi = cache[key]
                 pad = 1e-9 * max(hi - lo, abs(lo), abs(hi), 1e-3)
                 bounds = (lo - pad, hi + pad)
             else:
@@ -480,6 +472,33 @@ class Batch:
                     grid=out[3])
 
 
+def _spectral_bounds(fn: str, handle, ws, n_params: int, dev, theta: torch.Tensor) -> tuple:
+    """Gershgorin ends through fn (mrmf_spectral_bounds or mrmf_sector_spectral_bounds) for one coupling
+    vector, or through fn + "_many" for the rows of a [S, n_params] tensor (per row when the one-pass form
+    does not take the plan)."""
+    _need_gpu(theta, "theta", torch.float64)
+    nb = ctypes.c_size_t()
+    L.call(fn + "_scratch_bytes", handle, ctypes.byref(nb))
+    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    th = theta.contiguous()
+    if th.dim() == 2:
+        if th.shape[1] != n_params or th.shape[0] < 1:
+            raise ValueError("theta must be [S, n_params] with S >= 1")
+        st = getattr(L.lib(), fn + "_many")(handle, _ptr(ws), _ptr(th), n_params, th.shape[0], _ptr(out),
+                                            _ptr(scratch), nb.value, _stream(dev))
+        if st == L.MRMF_E_UNSUPPORTED:
+            ends = [_spectral_bounds(fn, handle, ws, n_params, dev, r) for r in th]
+            return min(e[0] for e in ends), max(e[1] for e in ends)
+        L.check(st, fn + "_many")
+    else:
+        if th.numel() < n_params:
+            raise ValueError("theta has fewer than n_params entries")
+        L.call(fn, handle, _ptr(ws), _ptr(th), _ptr(out), _ptr(scratch), nb.value, _stream(dev))
+    lo, hi = out.cpu().tolist()
+    return lo, hi
+
+
 def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, theta_c, keep_basis) -> dict:
     """Shared marshalling of mrmf_lanczos / mrmf_sector_lanczos (same arguments, vectors of length D)."""
     _need_gpu(theta, "theta", torch.float64)
@@ -596,18 +615,10 @@ class Sector:
 
     def spectral_bounds(self, theta: torch.Tensor) -> tuple:
         """(e_min, e_max) containing the spectrum of P H(theta) P^T, from the Gershgorin discs of the
-        sector's rows (mrmf_sector_spectral_bounds).  theta: float64 [n_params] on the device."""
-        _need_gpu(theta, "theta", torch.float64)
-        if theta.numel() < self.n_params:
-            raise ValueError("theta has fewer than n_params entries")
-        nb = ctypes.c_size_t()
-        L.call("mrmf_sector_spectral_bounds_scratch_bytes", self._handle, ctypes.byref(nb))
-        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
-        out = torch.empty(2, dtype=torch.float64, device=self.device)
-        L.call("mrmf_sector_spectral_bounds", self._handle, _ptr(self.ws), _ptr(theta.contiguous()), _ptr(out),
-               _ptr(scratch), nb.value, _stream(self.device))
-        lo, hi = out.cpu().tolist()
-        return lo, hi
+        sector's rows (mrmf_sector_spectral_bounds).  theta: float64 [n_params] on the device, or
+        [S, n_params] for the ends over S coupling vectors (mrmf_sector_spectral_bounds_many)."""
+        return _spectral_bounds("mrmf_sector_spectral_bounds", self._handle, self.ws, self.n_params, self.device,
+                                theta)
 
     def norm_bound(self, theta) -> float:
         """The plan's host norm bound (it bounds P H P^T as well)."""

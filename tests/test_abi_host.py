@@ -333,6 +333,51 @@ def test_sector_spectral_bounds_argument_checks():
         L.lib().mrmf_plan_destroy(h)
 
 
+def test_spectral_bounds_many_argument_checks():
+    """mrmf_spectral_bounds_many and mrmf_sector_spectral_bounds_many refuse, before any launch, null
+    pointers, count < 1, a negative stride, too small a scratch, and plans the one-pass form does not take
+    (more than 8 couplings: MRMF_E_UNSUPPORTED); the pointers below are never dereferenced."""
+    from workloads.model import OP_LOWER, OP_RAISE, OP_Z, Model, Term, spin_site
+    from paper_2606_02169_amd.plan import Sector
+    m = W.ferrimagnetic_ring(8)
+    st, h = host_plan(m)
+    assert st == 0
+    sec = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    try:
+        L.call("mrmf_sector_create", h, Sector.digit_sum_of(m.sites, 0.0), ctypes.byref(sec))
+        for fn, qfn, obj in (("mrmf_spectral_bounds_many", "mrmf_spectral_bounds_scratch_bytes", h),
+                             ("mrmf_sector_spectral_bounds_many", "mrmf_sector_spectral_bounds_scratch_bytes", sec)):
+            nb = ctypes.c_size_t()
+            L.call(qfn, obj, ctypes.byref(nb))
+            f = getattr(L.lib(), fn)
+            assert f(None, fake, fake, 4, 2, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, None, fake, 4, 2, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, None, 4, 2, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, fake, 4, 2, None, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, fake, 4, 0, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, fake, -1, 2, fake, fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, fake, 4, 2, ctypes.c_void_p((1 << 20) + 4), fake, nb.value, None) == L.MRMF_E_INVALID_ARG
+            assert f(obj, fake, fake, 4, 2, fake, fake, nb.value - 16, None) == L.MRMF_E_WORKSPACE
+    finally:
+        if sec.value:
+            L.lib().mrmf_sector_destroy(sec)
+        L.lib().mrmf_plan_destroy(h)
+    # nine couplings: more than the one-pass form holds per row
+    terms = [Term(i, OP_RAISE, i + 1, OP_LOWER, i, 0.5) for i in range(9)]
+    terms += [Term(i, OP_LOWER, i + 1, OP_RAISE, i, 0.5) for i in range(9)]
+    terms += [Term(i, OP_Z, -1, OP_Z, i % 9, 0.1) for i in range(10)]
+    st, h = host_plan(Model([spin_site(1)] * 10, terms, np.ones(9)))
+    assert st == 0
+    try:
+        nb = ctypes.c_size_t()
+        L.call("mrmf_spectral_bounds_scratch_bytes", h, ctypes.byref(nb))
+        assert L.lib().mrmf_spectral_bounds_many(h, fake, fake, 9, 2, fake, fake, nb.value, None) == \
+            L.MRMF_E_UNSUPPORTED
+    finally:
+        L.lib().mrmf_plan_destroy(h)
+
+
 def test_lanczos_refuses_non_hermitian_plans():
     """mrmf_lanczos and mrmf_sector_lanczos return MRMF_E_NOT_HERMITIAN, before any launch, for a plan
     built without MRMF_REQUIRE_HERMITIAN whose parameter group is not Hermitian (S_+ S_- without its

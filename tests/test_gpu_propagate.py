@@ -464,3 +464,99 @@ def test_sector_spectral_bounds_default_and_fewer_terms():
     for x in thetas:
         ref = expm(-1j * dt * kron.dense_H(m, x)[np.ix_(lab, lab)]) @ ref
     assert rel_err(r["x"].cpu().numpy(), ref) <= 1e-11
+
+
+# ------------------------------------------------------------------ bounds over many coupling vectors
+def drive_rows(theta, S, rng):
+    """S coupling vectors around theta, some of the couplings changing sign."""
+    return np.stack([theta * rng.uniform(-1.5, 1.5, size=theta.size) for _ in range(S)])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_spectral_bounds_many_random_models(seed):
+    """One pass over the rows for S coupling vectors (mrmf_spectral_bounds_many) against the extremes of
+    the per-vector device bounds and of the oracle matrix's Gershgorin ends per vector."""
+    rng = np.random.default_rng(8800 + seed)
+    m = W.random_model(rng, n_sites=int(rng.integers(2, 6)), max_dim=1200, n_params=int(rng.integers(1, 4)))
+    p = mk(m)
+    th = drive_rows(m.theta, 5, rng)
+    lo, hi = p.spectral_bounds(t(th))
+    each = [p.spectral_bounds(t(r)) for r in th]
+    ref = [gershgorin_sparse(m, r) for r in th]
+    elo, ehi = min(e[0] for e in each), max(e[1] for e in each)
+    slo, shi = min(e[0] for e in ref), max(e[1] for e in ref)
+    tol = 1e-12 * max(1.0, abs(elo), abs(ehi))
+    print(seed, m.dim, m.n_params, (lo, hi), (elo, ehi), (slo, shi), flush=True)
+    assert abs(lo - elo) <= tol and abs(hi - ehi) <= tol
+    assert lo <= slo + tol and hi >= shi - tol
+
+
+def test_spectral_bounds_many_full_ring_and_sector():
+    """The 20-site ring (D = 60,466,176) and its S_z = 0 sector with a drive of 6 coupling vectors: one pass
+    against six; stride 0 repeats one vector; a plan whose term tables are too large for the one-pass form
+    is answered per vector."""
+    from paper_2606_02169_amd import _lib as L
+    from paper_2606_02169_amd.plan import Plan, Sector, _ptr, _stream
+    m, _ = W.config(2, with_state=False)
+    rng = np.random.default_rng(8900)
+    th = drive_rows(m.theta, 6, rng)
+    p = Plan.from_model(m)
+    S = Sector(p, Sector.digit_sum_of(m.sites, 0.0))
+    for obj in (p, S):
+        lo, hi = obj.spectral_bounds(t(th))
+        each = [obj.spectral_bounds(t(r)) for r in th]
+        elo, ehi = min(e[0] for e in each), max(e[1] for e in each)
+        print(type(obj).__name__, (lo, hi), (elo, ehi), flush=True)
+        assert abs(lo - elo) <= 1e-12 * abs(elo) and abs(hi - ehi) <= 1e-12 * abs(ehi)
+    # stride 0: the same vector three times
+    nb = ctypes.c_size_t()
+    L.call("mrmf_spectral_bounds_scratch_bytes", p._handle, ctypes.byref(nb))
+    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=DEV)
+    out = torch.empty(2, dtype=torch.float64, device=DEV)
+    t0 = t(th[0])
+    L.call("mrmf_spectral_bounds_many", p._handle, _ptr(p.ws), _ptr(t0), 0, 3, _ptr(out), _ptr(scratch), nb.value,
+           _stream(DEV))
+    one = p.spectral_bounds(t0)
+    got = out.cpu().tolist()
+    assert abs(got[0] - one[0]) <= 1e-12 * abs(one[0]) and abs(got[1] - one[1]) <= 1e-12 * abs(one[1])
+    # too large for the one-pass form: the binding falls back to one pass per vector
+    from workloads.model import OP_LOWER, OP_RAISE, OP_Z, Model, Term, boson_site, spin_site
+    tb = Model([boson_site(39), spin_site(1), boson_site(39)],
+               [Term(0, OP_RAISE, 2, OP_LOWER, 0, 0.7), Term(0, OP_LOWER, 2, OP_RAISE, 0, 0.7),
+                Term(0, OP_Z, -1, OP_Z, 1, 1.0), Term(1, OP_Z, -1, OP_Z, 1, 1.0)], np.array([1.0, 0.5]))
+    pb = Plan.from_model(tb)
+    thb = drive_rows(tb.theta, 3, rng)
+    st = L.lib().mrmf_spectral_bounds_many(pb._handle, _ptr(pb.ws), _ptr(t(thb)), 2, 3, _ptr(out), _ptr(scratch),
+                                           nb.value, _stream(DEV))
+    assert st == L.MRMF_E_UNSUPPORTED
+    lo, hi = pb.spectral_bounds(t(thb))
+    ref = [gershgorin_sparse(tb, r) for r in thb]
+    assert abs(lo - min(e[0] for e in ref)) <= 1e-12 * max(1.0, abs(lo))
+    assert abs(hi - max(e[1] for e in ref)) <= 1e-12 * max(1.0, abs(hi))
+
+
+def test_sector_spectral_bounds_many_against_dense():
+    """The sector's one-pass ends over a drive against the Gershgorin ends of the oracle's dense P H P^T
+    per coupling vector, and a driven sector propagation with those bounds against exp(-i dt H_s) step by
+    step."""
+    from scipy.linalg import expm
+    from oracle import kron
+    from oracle import sector as osec
+    from paper_2606_02169_amd.plan import Plan, Sector
+    m = W.staggered_xxz_ring([1, 1, 2, 2, 3, 3])
+    Q = Sector.digit_sum_of(m.sites, 0.0)
+    lab = osec.labels(m, Q)
+    S = Sector(Plan.from_model(m), Q)
+    th = drive_rows(m.theta, 5, np.random.default_rng(9000))
+    lo, hi = S.spectral_bounds(t(th))
+    ref = [sector_gershgorin_dense(m, lab, r)[:2] for r in th]
+    slo, shi = min(e[0] for e in ref), max(e[1] for e in ref)
+    print((lo, hi), (slo, shi), flush=True)
+    assert abs(lo - slo) <= 1e-12 * max(1.0, abs(slo)) and abs(hi - shi) <= 1e-12 * max(1.0, abs(shi))
+    x0 = W.random_state(lab.size, np.random.default_rng(9001))
+    r = S.propagate(t(th), t(x0), 0.2, th.shape[0])
+    assert r["bounds"][0] <= lo and r["bounds"][1] >= hi
+    ref_x = x0.astype(np.complex128)
+    for x in th:
+        ref_x = expm(-1j * 0.2 * kron.dense_H(m, x)[np.ix_(lab, lab)]) @ ref_x
+    assert rel_err(r["x"].cpu().numpy(), ref_x) <= 1e-11
