@@ -136,4 +136,31 @@ __device__ __forceinline__ void gersh_block_ends(double lo, double hi, double* s
     }
 }
 
+// One block of kLinBlock threads: the minimum of partial[2 b] and the maximum of partial[2 b + 1] over the nb
+// blocks of a bounds pass to out[0], out[1] (min and max: the same result in any order).
+__device__ __forceinline__ void gersh_finalize_block(const double* __restrict__ partial, int nb,
+                                                     double* __restrict__ out) {
+    __shared__ double slo[kLinBlock], shi[kLinBlock];
+    const int tid = threadIdx.x;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (int b = tid; b < nb; b += kLinBlock) {
+        lo = fmin(lo, partial[2 * b]);
+        hi = fmax(hi, partial[2 * b + 1]);
+    }
+    slo[tid] = lo;
+    shi[tid] = hi;
+    __syncthreads();
+    for (int w = kLinBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            slo[tid] = fmin(slo[tid], slo[tid + w]);
+            shi[tid] = fmax(shi[tid], shi[tid + w]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = slo[0];
+        out[1] = shi[0];
+    }
+}
+
 }  // namespace mrmf

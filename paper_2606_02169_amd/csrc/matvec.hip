@@ -266,14 +266,9 @@ __global__ __launch_bounds__(kGenericBlock) void k_gershgorin_lin(PlanArgs p, co
     gersh_block_ends(lo, hi, slo, shi, partial);
 }
 
-__global__ void k_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
-    double lo = partial[0], hi = partial[1];
-    for (int b = 1; b < nb; ++b) {
-        lo = fmin(lo, partial[2 * b]);
-        hi = fmax(hi, partial[2 * b + 1]);
-    }
-    out[0] = lo;
-    out[1] = hi;
+__global__ __launch_bounds__(kLinBlock) void k_gershgorin_finalize(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+    gersh_finalize_block(partial, nb, out);
 }
 
 constexpr int kGershMaxGrid = 1024;
@@ -404,7 +399,7 @@ mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double*
     else if (narrow) hipLaunchKernelGGL((k_gershgorin<false, false>), g, b, 0, s, pa, theta, partial);
     else if (tab) hipLaunchKernelGGL((k_gershgorin<true, true>), g, b, 0, s, pa, theta, partial);
     else hipLaunchKernelGGL((k_gershgorin<true, false>), g, b, 0, s, pa, theta, partial);
-    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(kLinBlock), 0, s, partial, grid, d_out);
     return launch_status();
 }
 
@@ -431,7 +426,7 @@ mrmf_status mrmf_spectral_bounds_many(mrmf_plan plan, const void* d_ws, const do
     else
         hipLaunchKernelGGL(k_gershgorin_lin<true>, dim3(grid), dim3(kGenericBlock), 0, s, plan_args(plan, d_ws),
                            theta, theta_stride, count, partial);
-    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    hipLaunchKernelGGL(k_gershgorin_finalize, dim3(1), dim3(kLinBlock), 0, s, partial, grid, d_out);
     return launch_status();
 }
 

@@ -474,14 +474,9 @@ __global__ __launch_bounds__(kSB) void k_sector_gershgorin_lin(SectorArgs a, con
     gersh_block_ends(lo, hi, slo, shi, partial);
 }
 
-__global__ void k_sector_gershgorin_finalize(const double* __restrict__ partial, int nb, double* __restrict__ out) {
-    double lo = partial[0], hi = partial[1];
-    for (int b = 1; b < nb; ++b) {
-        lo = fmin(lo, partial[2 * b]);
-        hi = fmax(hi, partial[2 * b + 1]);
-    }
-    out[0] = lo;
-    out[1] = hi;
+__global__ __launch_bounds__(kLinBlock) void k_sector_gershgorin_finalize(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+    gersh_finalize_block(partial, nb, out);
 }
 
 constexpr int kSectorGershMaxGrid = 1024;
@@ -816,7 +811,7 @@ mrmf_status mrmf_sector_spectral_bounds(mrmf_sector sector, const void* d_ws, co
         if (tab) hipLaunchKernelGGL((k_sector_gershgorin<void, true>), g, b, 0, s, sa, nullptr, theta, partial);
         else hipLaunchKernelGGL((k_sector_gershgorin<void, false>), g, b, 0, s, sa, nullptr, theta, partial);
     }
-    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(kLinBlock), 0, s, partial, grid, d_out);
     return launch_status();
 }
 
@@ -845,7 +840,7 @@ mrmf_status mrmf_sector_spectral_bounds_many(mrmf_sector sector, const void* d_w
         hipLaunchKernelGGL(k_sector_gershgorin_lin<uint64_t>, g, b, 0, s, sa, lab, theta, theta_stride, count, partial);
     else
         hipLaunchKernelGGL(k_sector_gershgorin_lin<void>, g, b, 0, s, sa, nullptr, theta, theta_stride, count, partial);
-    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(1), 0, s, partial, grid, d_out);
+    hipLaunchKernelGGL(k_sector_gershgorin_finalize, dim3(1), dim3(kLinBlock), 0, s, partial, grid, d_out);
     return launch_status();
 }
 
