@@ -26,6 +26,8 @@ Other workloads (one JSON line each; not part of the headline):
   --workload sector      S_z = 0 sectors of the ring and of C1: sector matvec and sector Lanczos
   --workload stream      stream ceilings of the GPU (standalone probe): reads by footprint and cache
                          policy, copies, window gathers
+  --workload chain12     12-site spin-1/2 Heisenberg chain (D = 4096): H x and a 50-step Lanczos, eager
+                         and replayed from a HIP graph
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
@@ -842,6 +844,60 @@ def bench_sector(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------------------------------ small chain
+def bench_chain12(args, dev):
+    """The 12-site spin-1/2 Heisenberg chain (D = 4096, seed 1): one c128 H x and a 50-step Lanczos (CGS2),
+    each called eagerly and replayed from a HIP graph.  At this size every kernel is launch-bound, so the
+    graph removes the host's launch and marshalling time; the replayed Lanczos equals the eager one
+    bitwise (deterministic reductions)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import kron
+    from oracle import lanczos as olz
+    from oracle import mf
+    from paper_2606_02169_amd.plan import Plan
+
+    model, x = W.config(1)
+    p = Plan.from_model(model, device=dev)
+    xt = torch.from_numpy(x).to(dev)
+    th = torch.as_tensor(model.theta, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    steps = 50
+    ref = p.lanczos(th, xt, steps)                      # also builds the generated kernel
+    y = p.matvec(th, xt)
+    torch.cuda.synchronize()
+    ms_mv = cuda_time(lambda: p.matvec(th, xt, out=y), stream, 200)
+    ms_lz = cuda_time(lambda: p.lanczos(th, xt, steps), stream, 5)
+    gm = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gm):
+        for _ in range(20):
+            p.matvec(th, xt, out=y)
+    gl = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gl):
+        out = p.lanczos(th, xt, steps)
+    gm.replay()
+    gl.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out["alpha"], ref["alpha"]) and torch.equal(out["beta"], ref["beta"])
+                and torch.equal(out["result"], ref["result"]))
+    ms_mv_graph = cuda_time(gm.replay, stream, 20) / 20
+    ms_lz_graph = cuda_time(gl.replay, stream, 5)
+    res = ref["result"].cpu().numpy()
+    ev0 = float(np.linalg.eigvalsh(kron.dense_H(model))[0])
+    olz_ref = olz.lanczos(lambda v: mf.matvec(model, v), x, steps)
+    out_line = {"metric": "small-lattice H x and Lanczos, eager and replayed from a HIP graph",
+                "workload": "heisenberg_chain_N12_c128", "D": model.dim, "seed": 1, "lanczos_steps": steps,
+                "matvec_us": ms_mv * 1e3, "matvec_graph_us": ms_mv_graph * 1e3,
+                "lanczos_ms": ms_lz, "lanczos_graph_ms": ms_lz_graph,
+                "lanczos_graph_equals_eager_bitwise": same,
+                "E0": float(res[0]), "residual": float(res[2]), "E0_exact_diag": ev0,
+                "E0_oracle_lanczos": float(olz_ref["theta"]),
+                "max_abs_alpha_diff_vs_oracle": float(np.max(np.abs(ref["alpha"].cpu().numpy() - olz_ref["alpha"])))}
+    print(json.dumps(out_line), flush=True)
+
+
 # ------------------------------------------------------------------------------------------ stream ceilings
 def bench_stream(args, dev):
     """Stream ceilings of this GPU from the standalone probe built beside the library (run as a child
@@ -936,7 +992,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
     ap.add_argument("--workload", default="ring20", choices=["ring20", "torus", "lanczos4x4", "lanczos_ring20",
                                                               "batched", "adjoint", "paper", "propagate", "sector",
-                                                              "stream"])
+                                                              "stream", "chain12"])
     ap.add_argument("--dtype", default=None, choices=["c64", "c128"], help="torus: one element type only")
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
@@ -959,7 +1015,7 @@ def main():
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "torus": bench_torus, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
      "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
-     "sector": bench_sector, "stream": bench_stream}[args.workload](args, dev)
+     "sector": bench_sector, "stream": bench_stream, "chain12": bench_chain12}[args.workload](args, dev)
 
 
 if __name__ == "__main__":

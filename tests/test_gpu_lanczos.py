@@ -303,3 +303,34 @@ def test_partial_reorthogonalisation_pass_count(prec):
     got = int(out["counts"].cpu().numpy()[1])
     print(f"{prec}: passes device {got} host replay {want} in {k} steps", flush=True)
     assert k == 240 and got == want and got > 0
+
+
+def test_lanczos_graph_replays_match_eager():
+    """The 12-site Heisenberg chain (D = 4096, where every kernel is launch-bound): one 50-step mrmf_lanczos
+    call captured in a HIP graph and replayed three times, with eager Lanczos runs on other start vectors
+    and synchronisations between the replays; each replay's alpha, beta and result equal the eager call's
+    bitwise (the outputs are cleared before each replay, so a replay that did nothing would fail)."""
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    m, x = W.config(1)
+    p = Plan(m)
+    th, xt = t(m.theta), t(x)
+    ref = p.lanczos(th, xt, 50)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = p.lanczos(th, xt, 50)
+    rng = np.random.default_rng(9100)
+    for k in range(3):
+        out["alpha"].zero_()
+        out["beta"].zero_()
+        out["result"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        other = p.lanczos(th, t(W.random_state(m.dim, rng)), 20)
+        torch.cuda.synchronize()
+        print(k, float(out["result"][0]), float(ref["result"][0]), flush=True)
+        assert torch.equal(out["alpha"], ref["alpha"]) and torch.equal(out["beta"], ref["beta"])
+        assert torch.equal(out["result"], ref["result"])
+        assert torch.isfinite(other["result"][0])
