@@ -28,6 +28,8 @@ Other workloads (one JSON line each; not part of the headline):
                          policy, copies, window gathers
   --workload chain12     12-site spin-1/2 Heisenberg chain (D = 4096): H x and a 50-step Lanczos, eager
                          and replayed from a HIP graph
+  --workload sweep       parameter sweep: the 14-site ring at 256 coupling vectors x 8 c64 vectors in one
+                         batched launch, against separate plain calls
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--profile] [--workload W]
 """
@@ -844,6 +846,81 @@ def bench_sector(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------------------------------ parameter sweep
+def bench_sweep(args, dev):
+    """A parameter sweep as one batched launch: the 14-site ferrimagnetic ring (D = 279,936) at 256 coupling
+    vectors (64 values of J_z times 4 fields h_z), each applied to the same 8 c64 vectors, replayed from a
+    HIP graph; against the same 2048 products as separate c64 calls of the plain matvec, one coupling
+    vector and one vector per call.  Sampled rows of every 32nd point against the oracle in FP64."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import mf
+    from paper_2606_02169_amd.plan import Batch, Plan
+
+    base = W.ferrimagnetic_ring(14)
+    thetas = [np.array([1.0, jz, 0.5, hz]) for hz in (0.0, 0.1, 0.2, 0.3) for jz in np.linspace(0.5, 2.0, 64)]
+    models = [dataclasses.replace(base, theta=t) for t in thetas]
+    x = W.random_state(base.dim, np.random.default_rng(6), np.complex64, nvec=8)
+    plan = Plan.from_model(base, device=dev)
+    B = Batch([plan] * len(models), 8)
+    X = torch.zeros(B.total_elems, dtype=torch.complex64, device=dev)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    for b in range(len(models)):
+        B.block(X, b).copy_(xd)
+    Y = torch.empty_like(X)
+    th32 = np.concatenate(thetas).astype(np.float32)
+    th = torch.from_numpy(th32).to(dev)
+    shape = B.autotune(th, X, Y)
+    s = torch.cuda.Stream(device=dev)
+    B.capture(th, X, Y, s)
+    for _ in range(3):
+        B.replay(s)
+    s.synchronize()
+    K = 10
+    a = torch.cuda.Event(enable_timing=True)
+    b_ = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(K):
+        B.replay(s)
+    b_.record(s)
+    s.synchronize()
+    ms_graph = a.elapsed_time(b_) / K
+    n_mv = len(models) * 8
+    rng = np.random.default_rng(7)
+    r = np.unique(rng.choice(base.dim, 2000, replace=False)).astype(np.int64)
+    errs = []
+    for bi in range(0, len(models), 32):
+        m = dataclasses.replace(base, theta=th32[4 * bi: 4 * bi + 4].astype(np.float64))
+        yb = B.block(Y, bi).cpu().numpy()
+        for v in (0, 7):
+            ref = mf.matvec(m, x[:, v].astype(np.complex128), rows=r)
+            errs.append(float(np.linalg.norm(yb[r, v] - ref) / np.linalg.norm(ref)))
+    # the same products as separate plain c64 calls
+    stream = torch.cuda.current_stream(dev)
+    col = torch.from_numpy(np.ascontiguousarray(x[:, 0])).to(dev)
+    outc = torch.empty_like(col)
+    ths = [torch.from_numpy(th32[4 * k: 4 * k + 4].copy()).to(dev) for k in range(len(models))]
+    plan.matvec(ths[0], col, out=outc)
+
+    def separate():
+        for _ in range(8):
+            for t in ths:
+                plan.matvec(t, col, out=outc)
+    ms_sep = cuda_time(separate, stream, 1)
+    out = {"metric": "parameter sweep: vector-matvecs/s of one lattice at 256 coupling vectors x 8 c64 vectors",
+           "workload": "ferrimagnetic_ring_N14_sweep_256x8_c64", "D": base.dim, "points": len(models),
+           "vector_matvecs_per_launch": n_mv, "shape": shape, "ms_per_launch": ms_graph,
+           "vector_matvecs_per_s": n_mv / ms_graph * 1e3,
+           "effective_GBps": 2 * base.dim * len(models) * 8 * 8 / (ms_graph * 1e-3) / 1e9,
+           "separate_c64_calls": {"ms_for_2048": ms_sep, "vector_matvecs_per_s": n_mv / ms_sep * 1e3},
+           "max_rel_err_sampled_vs_fp64_oracle": max(errs)}
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------------------------------------ small chain
 def bench_chain12(args, dev):
     """The 12-site spin-1/2 Heisenberg chain (D = 4096, seed 1): one c128 H x and a 50-step Lanczos (CGS2),
@@ -992,7 +1069,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialized"])
     ap.add_argument("--workload", default="ring20", choices=["ring20", "torus", "lanczos4x4", "lanczos_ring20",
                                                               "batched", "adjoint", "paper", "propagate", "sector",
-                                                              "stream", "chain12"])
+                                                              "stream", "chain12", "sweep"])
     ap.add_argument("--dtype", default=None, choices=["c64", "c128"], help="torus: one element type only")
     ap.add_argument("--lanczos-steps", type=int, default=100)
     ap.add_argument("--lanczos-ref-steps", type=int, default=150)
@@ -1015,7 +1092,8 @@ def main():
     torch.cuda.set_device(dev)
     {"ring20": bench_ring, "torus": bench_torus, "lanczos4x4": bench_lanczos, "lanczos_ring20": bench_lanczos_ring, "batched": bench_batched,
      "adjoint": bench_adjoint, "paper": bench_paper, "propagate": bench_propagate,
-     "sector": bench_sector, "stream": bench_stream, "chain12": bench_chain12}[args.workload](args, dev)
+     "sector": bench_sector, "stream": bench_stream, "chain12": bench_chain12,
+     "sweep": bench_sweep}[args.workload](args, dev)
 
 
 if __name__ == "__main__":
