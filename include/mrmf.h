@@ -405,7 +405,7 @@ mrmf_status mrmf_spectral_bounds(mrmf_plan plan, const void* d_ws, const double*
 /* The same ends over count coupling vectors at once (a piecewise-constant drive, a parameter sweep):
  * d_out[0] <= every eigenvalue of H(theta_s) <= d_out[1] for s = 0 .. count - 1, theta_s at
  * d_theta + s * theta_stride (doubles; stride 0 repeats one vector).  One pass over the rows: since H is
- * linear in the couplings (Sec. II: H = sum of parameter groups, each term carrying one coupling), a row's
+ * linear in the couplings (Sec. I: H is a sum of local terms, here each carrying one coupling), a row's
  * diagonal entry is sum_p theta_p A_p and its channel radius sum_p |theta_p| B_p, with A_p and B_p taken
  * once per row from per-term tables in LDS; each further vector costs 2 n_params multiply-adds per row.
  * The ends equal the extremes of count calls of mrmf_spectral_bounds up to the order of the sums.
