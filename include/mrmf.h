@@ -556,6 +556,15 @@ mrmf_status mrmf_batch_set_shape(mrmf_batch batch, int32_t tile_rows_max, int32_
 mrmf_status mrmf_batch_set_schedule(mrmf_batch batch, int32_t sched);
 /* Host out[0..3] = (tile-row limit, block threads, schedule, grid blocks) of the current launch shape. */
 mrmf_status mrmf_batch_get_shape(mrmf_batch batch, int32_t* out);
+/* Shared input (on = 1), for parameter sweeps and disorder averages (many couplings on one structure,
+ * Sec. VII): every lattice reads its input rows from the one block [D][nvec] at the start of d_X (which
+ * then needs only that block: D * nvec elements, padded to the next multiple of 32), and the work items
+ * are taken tile by tile across the lattices, so that the items worked on together read the same input
+ * rows and gather windows.  Outputs stay in their own blocks of d_Y; each Y_b equals what the batch
+ * computes from a copy of the block in every X_b, bit for bit.  MRMF_E_UNSUPPORTED unless every lattice
+ * has the same local dimensions (then the same tiles).  on = 0 restores separate inputs.  A captured graph
+ * keeps the mode it was captured with. */
+mrmf_status mrmf_batch_share_input(mrmf_batch batch, int32_t on);
 
 #ifdef __cplusplus
 }

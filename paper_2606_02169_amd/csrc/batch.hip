@@ -7,6 +7,9 @@
 // (row F holds its nvec amplitudes contiguously, so one row is 8 * nvec bytes); offsets are multiples
 // of 32 elements.
 //
+// Shared input (parameter sweeps: the same vectors under many couplings): every lattice reads block 0 of X,
+// and the items are numbered tile by tile across the lattices instead of lattice by lattice.
+//
 // Work.  For a launch shape (R_max, block B), lattice b's rows are cut into tiles spanned by its low
 // sites (T_b = prod of the low d_i, the largest such product <= R_max), and an item is the P = max(1,
 // B / T_b) consecutive tiles that one block holds in LDS at a time (rows stored vector-major, so that
@@ -80,6 +83,7 @@ struct BatchArgs {
     const float* pool;   // factor tables of every lattice
     int32_t n_lat;
     int32_t all_real;
+    int32_t shared;  // every lattice reads its input rows from the one block at the start of X; items tile-major
 };
 
 __device__ __forceinline__ uint32_t umulhi_div(uint32_t n, uint64_t magic) {
@@ -169,7 +173,8 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     const float2* xb = X;
     float2* yb = Y;
     int b = 0;
-    {
+    const bool shared = A.shared != 0;
+    if (!shared) {
         int lo = 0, hi = A.n_lat - 1;  // last lattice with ibeg[b] <= i0
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -178,8 +183,18 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
         b = lo;
     }
     for (int32_t it = i0; it < i1; it += step) {
-        while (it >= ibeg[b + 1]) ++b;
+        // shared input: every lattice has the same tiles; item it is tile it / n of lattice it mod n, so the
+        // items worked on together read the same input rows
+        int32_t li;
+        if (shared) {
+            b = it % A.n_lat;
+            li = it / A.n_lat;
+        } else {
+            while (it >= ibeg[b + 1]) ++b;
+            li = it - ibeg[b];
+        }
         b = __builtin_amdgcn_readfirstlane(b);
+        li = __builtin_amdgcn_readfirstlane(li);
         __syncthreads();  // every thread is done with the previous item's tile (and tables)
         if (b != lb) {
             const BLat* L = A.lat + b;
@@ -192,7 +207,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
             n_loc = __builtin_amdgcn_readfirstlane(L->n_local[rc]);
             rows = T >= B ? T : (B / T) * T;
             const int64_t xo = L->x_off;
-            xb = X + xo;
+            xb = shared ? X : X + xo;
             yb = Y + xo;
             const int32_t po = __builtin_amdgcn_readfirstlane(L->pool_off), pn = __builtin_amdgcn_readfirstlane(L->pool_n);
             for (int k = tid; k < pn; k += B) pool[k] = A.pool[po + k];
@@ -204,7 +219,7 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
             lb = b;
             __syncthreads();
         }
-        const int32_t r0 = (it - ibeg[b]) * rows;
+        const int32_t r0 = li * rows;
         const int32_t nr = r0 + rows < D ? rows : D - r0;
         for (int32_t r = tid; r < nr; r += B) {
             float2 v[NV];
@@ -347,6 +362,8 @@ struct mrmf_batch_t {
     int32_t rc = 2, block = 256;  // R_max candidate index and block threads
     int32_t sched = 0;            // MRMF_BATCH_SCHED_*
     int32_t grid = 0;
+    bool shared = false;                     // mrmf_batch_share_input
+    std::vector<std::vector<int32_t>> dims;  // local dimensions of each lattice
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~mrmf_batch_t() {
@@ -366,6 +383,7 @@ mrmf::BatchArgs batch_args(const mrmf_batch_t* b, const void* d_ws) {
     a.pool = reinterpret_cast<const float*>(w + b->off_pool);
     a.n_lat = b->n;
     a.all_real = b->all_real ? 1 : 0;
+    a.shared = b->shared ? 1 : 0;
     return a;
 }
 
@@ -394,7 +412,8 @@ mrmf_status check_call(const mrmf_batch_t* b, const void* d_ws, const float* th,
     const size_t al = b->nvec >= 2 ? 16 : 8;  // rows are moved in 16-byte words when they hold two or more
     if (!mrmf::aligned(d_ws, 256) || !mrmf::aligned(X, al) || !mrmf::aligned(Y, al)) return MRMF_E_INVALID_ARG;
     const size_t bytes = size_t(b->total) * 8;
-    if (mrmf::ranges_overlap(X, bytes, Y, bytes)) return MRMF_E_INVALID_ARG;
+    const size_t x_bytes = b->shared ? size_t(b->off.size() > 1 ? b->off[1] : b->total) * 8 : bytes;
+    if (mrmf::ranges_overlap(X, x_bytes, Y, bytes)) return MRMF_E_INVALID_ARG;
     return MRMF_OK;
 }
 
@@ -434,6 +453,7 @@ mrmf_status mrmf_batch_create(int32_t n, const mrmf_plan* plans, int32_t nvec, m
             L.tile_rows[rc] = static_cast<int32_t>(T);
             L.tile_sites[rc] = k;
         }
+        b->dims.emplace_back(p->d.begin(), p->d.end());
         L.N = p->N;
         L.n_params = p->n_params;
         L.D = static_cast<int32_t>(p->D);
@@ -593,6 +613,15 @@ mrmf_status mrmf_batch_graph_capture(mrmf_batch b, const void* d_ws, const float
 mrmf_status mrmf_batch_graph_launch(mrmf_batch b, mrmf_stream stream) {
     if (!b || !b->exec) return MRMF_E_INVALID_ARG;
     return mrmf::hip_status(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+}
+
+mrmf_status mrmf_batch_share_input(mrmf_batch b, int32_t on) {
+    if (!b || (on != 0 && on != 1)) return MRMF_E_INVALID_ARG;
+    if (on)
+        for (const auto& d : b->dims)
+            if (d != b->dims[0]) return MRMF_E_UNSUPPORTED;
+    b->shared = on != 0;
+    return MRMF_OK;
 }
 
 mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t tile_rows_max, int32_t block_threads) {

@@ -419,17 +419,34 @@ class Batch:
         D = self.plans[b].D
         return T[self.offsets[b]: self.offsets[b] + D * self.nvec].view(D, self.nvec)
 
+    shared_input = False
+
+    def share_input(self, on: bool = True):
+        """Every lattice reads the one input block at the start of X (mrmf_batch_share_input): a parameter
+        sweep applies its couplings to the same vectors without a copy per lattice.  X then needs
+        input_elems entries."""
+        L.call("mrmf_batch_share_input", self._handle, 1 if on else 0)
+        self.shared_input = bool(on)
+
+    @property
+    def input_elems(self) -> int:
+        """Entries X needs: total_elems, or one padded block with a shared input."""
+        if not self.shared_input:
+            return self.total_elems
+        return (self.plans[0].D * self.nvec + 31) // 32 * 32
+
     def _check(self, theta_all, X, Y):
         _need_gpu(theta_all, "theta_all", torch.float32)
         _need_gpu(X, "X", torch.complex64)
         _need_gpu(Y, "Y", torch.complex64)
-        if X.numel() < self.total_elems or Y.numel() < self.total_elems:
-            raise ValueError("X and Y need total_elems entries")
+        if X.numel() < self.input_elems or Y.numel() < self.total_elems:
+            raise ValueError("X needs input_elems entries and Y total_elems")
         if theta_all.numel() < self.theta_offsets[-1]:
             raise ValueError("theta_all is too short")
 
     def matvec(self, theta_all: torch.Tensor, X: torch.Tensor, Y: torch.Tensor | None = None) -> torch.Tensor:
-        Y = torch.empty_like(X) if Y is None else Y
+        if Y is None:
+            Y = torch.empty(self.total_elems, dtype=torch.complex64, device=X.device)
         self._check(theta_all, X, Y)
         L.call("mrmf_batch_matvec_c", self._handle, _ptr(self.ws), _ptr(theta_all), _ptr(X), _ptr(Y),
                _stream(self.device))

@@ -378,6 +378,32 @@ def test_spectral_bounds_many_argument_checks():
         L.lib().mrmf_plan_destroy(h)
 
 
+def test_batch_share_input_rules():
+    """mrmf_batch_share_input: accepted for lattices with the same local dimensions (different couplings
+    or terms), MRMF_E_UNSUPPORTED for lattices of different dimensions, MRMF_E_INVALID_ARG for a flag other
+    than 0 or 1; switching back to separate inputs always works."""
+    plans = []
+    try:
+        for m in (W.ferrimagnetic_ring(6), W.ferrimagnetic_ring(6, jz=0.7), W.ferrimagnetic_ring(8)):
+            st, h = host_plan(m)
+            assert st == 0
+            plans.append(h)
+        for idx, want in (([0, 1, 0], 0), ([0, 2], L.MRMF_E_UNSUPPORTED)):
+            arr = (ctypes.c_void_p * len(idx))(*[plans[i].value for i in idx])
+            b = ctypes.c_void_p()
+            L.call("mrmf_batch_create", len(idx), arr, 8, ctypes.byref(b))
+            try:
+                assert L.lib().mrmf_batch_share_input(b, 1) == want
+                assert L.lib().mrmf_batch_share_input(b, 2) == L.MRMF_E_INVALID_ARG
+                assert L.lib().mrmf_batch_share_input(b, 0) == 0
+            finally:
+                L.lib().mrmf_batch_destroy(b)
+        assert L.lib().mrmf_batch_share_input(None, 1) == L.MRMF_E_INVALID_ARG
+    finally:
+        for h in plans:
+            L.lib().mrmf_plan_destroy(h)
+
+
 def test_lanczos_refuses_non_hermitian_plans():
     """mrmf_lanczos and mrmf_sector_lanczos return MRMF_E_NOT_HERMITIAN, before any launch, for a plan
     built without MRMF_REQUIRE_HERMITIAN whose parameter group is not Hermitian (S_+ S_- without its

@@ -180,3 +180,48 @@ def test_parameter_sweep_in_one_launch():
         for k in range(2, 6):
             pred = y0 + (jz[k] - jz[0]) * unit
             assert rel_err(ys[6 * h + k], pred) <= 1e-5, (h, k)
+
+
+def test_parameter_sweep_shared_input():
+    """The same sweep with one shared input block (mrmf_batch_share_input: every lattice reads the block at
+    the start of X, items tile by tile across the lattices): every output block equal, bit for bit, to the
+    batch with a copy of the vectors per lattice, for each work schedule and two launch shapes, and against
+    the oracle at its own couplings; a captured graph replays the shared mode."""
+    import dataclasses
+    from paper_2606_02169_amd.plan import Batch, Plan
+    base = W.ferrimagnetic_ring(10)                       # D = 7776
+    thetas = [np.array([1.0, j, 0.5, h]) for h in (0.0, 0.2, 0.4) for j in np.linspace(0.5, 1.5, 7)]
+    models = [dataclasses.replace(base, theta=t) for t in thetas]
+    x = W.random_state(base.dim, np.random.default_rng(72), np.complex64, nvec=8)
+    plan = Plan.from_model(base)
+    th = torch.from_numpy(np.concatenate(thetas).astype(np.float32)).to(DEV)
+    ref_b = Batch([plan] * len(models), 8)
+    Xc = torch.zeros(ref_b.total_elems, dtype=torch.complex64, device=DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    for b in range(len(models)):
+        ref_b.block(Xc, b).copy_(xd)
+    Yref = ref_b.matvec(th, Xc)
+    B = Batch([plan] * len(models), 8)
+    B.share_input(True)
+    assert B.input_elems < B.total_elems
+    Xs = torch.zeros(B.input_elems, dtype=torch.complex64, device=DEV)
+    Xs[: base.dim * 8].view(base.dim, 8).copy_(xd)
+    for shape in ((512, 512), (256, 256)):
+        for sched in ("runs", "windows", "xcd_chunk"):
+            B.set_shape(*shape, sched)
+            Y = torch.full((B.total_elems,), float("nan"), dtype=torch.complex64, device=DEV)
+            B.matvec(th, Xs, Y)
+            torch.cuda.synchronize()
+            for b in range(len(models)):
+                assert torch.equal(B.block(Y, b), ref_b.block(Yref, b)), (shape, sched, b)
+    check_all(B, models, [x] * len(models), Y)
+    s = torch.cuda.Stream(device=DEV)
+    Yg = torch.full((B.total_elems,), float("nan"), dtype=torch.complex64, device=DEV)
+    B.capture(th, Xs, Yg, s)
+    for _ in range(2):
+        Yg.fill_(float("nan"))
+        torch.cuda.synchronize()
+        B.replay(s)
+        s.synchronize()
+        for b in range(len(models)):
+            assert torch.equal(B.block(Yg, b), ref_b.block(Yref, b)), b
