@@ -754,6 +754,25 @@ def bench_propagate(args, dev):
                                                           "load_group", "us_per_call")},
            "norm_drift": abs(torch.linalg.vector_norm(out).item() - torch.linalg.vector_norm(xt).item()),
            "reversal_rel_err": ((back - xt).norm() / xt.norm()).item()}
+    if not args.profile:
+        # a piecewise-constant drive: 100 steps of dt = 0.05, J_z and h_z changed at every step (one series
+        # per step; the bounds of all steps from one pass over the rows, included in the time)
+        n_drive = 100
+        res_out = torch.empty_like(xt)
+        t0 = time.perf_counter()
+        rd = p.propagate(drive, xt, dt, n_drive, out=res_out)
+        torch.cuda.synchronize()
+        s_drive = time.perf_counter() - t0
+        p.__dict__.pop("_gersh_cache", None)    # time again with the bounds recomputed, not cached
+        t0 = time.perf_counter()
+        rd = p.propagate(drive, xt, dt, n_drive, out=res_out)
+        torch.cuda.synchronize()
+        s_drive = time.perf_counter() - t0
+        res["driven_100_steps"] = {"seconds": s_drive, "ms_per_step": s_drive / n_drive * 1e3,
+                                   "terms": rd["n_terms"], "terms_per_step": rd["n_terms"] / n_drive,
+                                   "bounds": list(rd["bounds"]),
+                                   "norm_drift": abs(torch.linalg.vector_norm(res_out).item()
+                                                     - torch.linalg.vector_norm(xt).item())}
     log(str(res))
     print(json.dumps(res), flush=True)
 
