@@ -225,3 +225,41 @@ def test_parameter_sweep_shared_input():
         s.synchronize()
         for b in range(len(models)):
             assert torch.equal(B.block(Yg, b), ref_b.block(Yref, b)), b
+
+
+def test_disorder_average_shared_input():
+    """Shared input across lattices with the same local dimensions but different terms (a disorder average:
+    10-site mixed chains, random J per bond, some with a next-nearest bond): each output block equal bit for
+    bit to the batch with a copy per lattice, and against the oracle."""
+    from workloads.model import Model, spin_site, xxz_bond_terms
+    from paper_2606_02169_amd.plan import Batch, Plan
+    rng = np.random.default_rng(73)
+    sites = [spin_site(k) for k in (1, 2, 3, 1, 2, 3, 1, 2, 1, 2)]
+    models = []
+    for r in range(6):
+        bonds = [(i, i + 1) for i in range(9)] + ([(0, 2), (5, 7)] if r % 2 else [])
+        terms, theta = [], []
+        for k, (i, j) in enumerate(bonds):
+            terms += xxz_bond_terms(i, j, 2 * k, 2 * k + 1)
+            theta += [rng.uniform(0.5, 1.5), rng.uniform(-1.0, 1.0)]
+        models.append(Model(sites, terms, np.array(theta)))
+    x = W.random_state(models[0].dim, np.random.default_rng(74), np.complex64, nvec=8)
+    plans = [Plan.from_model(m) for m in models]
+    th = torch.from_numpy(np.concatenate([m.theta for m in models]).astype(np.float32)).to(DEV)
+    ref_b = Batch(plans, 8)
+    Xc = torch.zeros(ref_b.total_elems, dtype=torch.complex64, device=DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    for b in range(len(models)):
+        ref_b.block(Xc, b).copy_(xd)
+    Yref = ref_b.matvec(th, Xc)
+    B = Batch(plans, 8)
+    B.share_input(True)
+    Xs = torch.zeros(B.input_elems, dtype=torch.complex64, device=DEV)
+    Xs[: models[0].dim * 8].view(models[0].dim, 8).copy_(xd)
+    for sched in ("runs", "windows", "xcd_chunk"):
+        B.set_shape(256, 256, sched)
+        Y = B.matvec(th, Xs)
+        torch.cuda.synchronize()
+        for b in range(len(models)):
+            assert torch.equal(B.block(Y, b), ref_b.block(Yref, b)), (sched, b)
+    check_all(B, models, [x] * len(models), Y)
