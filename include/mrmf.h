@@ -565,6 +565,16 @@ mrmf_status mrmf_batch_get_shape(mrmf_batch batch, int32_t* out);
  * has the same local dimensions (then the same tiles).  on = 0 restores separate inputs.  A captured graph
  * keeps the mode it was captured with. */
 mrmf_status mrmf_batch_share_input(mrmf_batch batch, int32_t on);
+/* Parameter sweep by linearity: H(theta) = sum_p theta_p h_p (each term carries one coupling, Sec. I), so
+ * the products of one structure at K coupling vectors are Y_k = sum_p theta_kp G_p with G_p = h_p X.
+ * Given the P group products G_p (c64, n entries each, G_p at d_G + p * g_stride elements; e.g. the output
+ * of a batch of P copies of the plan with a shared input and unit coupling vectors), this writes
+ * Y_k[i] = sum_p d_theta[k * P + p] G_p[i] to d_Y + k * y_stride for k < K (c64; d_theta: float[K][P] on
+ * the device).  One pass, bound by the writes of the K outputs; results equal the direct products up to
+ * the order of the FP32 sums.  1 <= P <= 16, K >= 1, strides >= n; 8-byte aligned, G and Y not
+ * overlapping. */
+mrmf_status mrmf_sweep_combine_c(const float* d_theta, int32_t K, int32_t P, int64_t n, const void* d_G,
+                                 int64_t g_stride, void* d_Y, int64_t y_stride, mrmf_stream stream);
 
 #ifdef __cplusplus
 }

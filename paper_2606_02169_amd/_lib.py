@@ -148,6 +148,7 @@ SIGNATURES = {
     "mrmf_batch_set_schedule": (_i32, [_vp, _i32]),
     "mrmf_batch_get_shape": (_i32, [_vp, _P(_i32)]),
     "mrmf_batch_share_input": (_i32, [_vp, _i32]),
+    "mrmf_sweep_combine_c": (_i32, [_vp, _i32, _i32, _i64, _vp, _i64, _vp, _i64, _vp]),
 }
 
 _lib = None

@@ -320,6 +320,51 @@ __global__ __launch_bounds__(kBatchMaxBlock) void k_batch(BatchArgs A, const flo
     }
 }
 
+// Linear combination of parameter-group products: Y_k[i] = sum_p theta[k][p] G_p[i] for k < K, i < n (c64
+// entries, real couplings).  A thread holds the P entries G_p[i] of its element in registers and writes
+// every Y_k[i]; the couplings of the sweep sit in LDS.  Bound by the writes of the K outputs.
+constexpr int kCombMaxP = 16;
+constexpr int kCombTheta = 4096;  // couplings held in LDS at a time (16 KB)
+constexpr int kCombBlock = 256;
+
+template <int P>
+__global__ __launch_bounds__(kCombBlock) void k_sweep_combine(const float* __restrict__ theta, int32_t K,
+                                                              int64_t n, const float2* __restrict__ G,
+                                                              int64_t g_stride, float2* __restrict__ Y,
+                                                              int64_t y_stride) {
+    __shared__ float th[kCombTheta];  // a chunk of the sweep's couplings, rows of P
+    const int64_t i = int64_t(blockIdx.x) * kCombBlock + threadIdx.x;
+    float2 g[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) g[p] = i < n ? G[p * g_stride + i] : make_float2(0.f, 0.f);
+    const int kc = kCombTheta / P;  // sweep rows per chunk
+    for (int k0 = 0; k0 < K; k0 += kc) {
+        const int kn = K - k0 < kc ? K - k0 : kc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kn * P; e += kCombBlock) th[e] = theta[int64_t(k0) * P + e];
+        __syncthreads();
+        if (i < n)
+            for (int k = 0; k < kn; ++k) {
+                float yr = 0.f, yi = 0.f;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float t = th[k * P + p];
+                    yr += t * g[p].x;
+                    yi += t * g[p].y;
+                }
+                Y[(k0 + k) * y_stride + i] = make_float2(yr, yi);
+            }
+    }
+}
+
+template <int P>
+void launch_combine(const float* theta, int32_t K, int64_t n, const float2* G, int64_t gs, float2* Y, int64_t ys,
+                    hipStream_t s) {
+    const int64_t grid = (n + kCombBlock - 1) / kCombBlock;
+    hipLaunchKernelGGL(k_sweep_combine<P>, dim3(static_cast<unsigned>(grid)), dim3(kCombBlock), 0, s, theta, K, n,
+                       G, gs, Y, ys);
+}
+
 template <int NV>
 void* batch_kernel_ptr(bool cplx) {
     return cplx ? reinterpret_cast<void*>(&k_batch<NV, true>) : reinterpret_cast<void*>(&k_batch<NV, false>);
@@ -622,6 +667,30 @@ mrmf_status mrmf_batch_share_input(mrmf_batch b, int32_t on) {
             if (d != b->dims[0]) return MRMF_E_UNSUPPORTED;
     b->shared = on != 0;
     return MRMF_OK;
+}
+
+mrmf_status mrmf_sweep_combine_c(const float* d_theta, int32_t K, int32_t P, int64_t n, const void* d_G,
+                                 int64_t g_stride, void* d_Y, int64_t y_stride, mrmf_stream stream) {
+    using namespace mrmf;
+    if (!d_theta || !d_G || !d_Y || K < 1 || P < 1 || P > kCombMaxP || n < 1 || g_stride < n || y_stride < n)
+        return MRMF_E_INVALID_ARG;
+    if (n >= (int64_t(1) << 31) * kCombBlock) return MRMF_E_INVALID_ARG;
+    if (!aligned(d_G, 8) || !aligned(d_Y, 8) || !aligned(d_theta, 4)) return MRMF_E_INVALID_ARG;
+    const size_t gb = size_t(g_stride) * (P - 1) * 8 + size_t(n) * 8, yb = size_t(y_stride) * (K - 1) * 8 + size_t(n) * 8;
+    if (ranges_overlap(d_G, gb, d_Y, yb)) return MRMF_E_INVALID_ARG;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const auto* G = static_cast<const float2*>(d_G);
+    auto* Y = static_cast<float2*>(d_Y);
+    switch (P) {
+#define MRMF_COMB_CASE(q) \
+    case q: launch_combine<q>(d_theta, K, n, G, g_stride, Y, y_stride, s); break;
+        MRMF_COMB_CASE(1) MRMF_COMB_CASE(2) MRMF_COMB_CASE(3) MRMF_COMB_CASE(4) MRMF_COMB_CASE(5) MRMF_COMB_CASE(6)
+        MRMF_COMB_CASE(7) MRMF_COMB_CASE(8) MRMF_COMB_CASE(9) MRMF_COMB_CASE(10) MRMF_COMB_CASE(11)
+        MRMF_COMB_CASE(12) MRMF_COMB_CASE(13) MRMF_COMB_CASE(14) MRMF_COMB_CASE(15) MRMF_COMB_CASE(16)
+#undef MRMF_COMB_CASE
+        default: return MRMF_E_INVALID_ARG;
+    }
+    return launch_status();
 }
 
 mrmf_status mrmf_batch_set_shape(mrmf_batch b, int32_t tile_rows_max, int32_t block_threads) {

@@ -548,6 +548,49 @@ def _lanczos(fn: str, handle, ws, D: int, dev, theta, v0, m, precision, reorth, 
     return out
 
 
+class Sweep:
+    """A parameter sweep of one plan by linearity: H(theta) = sum_p theta_p h_p, so the products at K coupling
+    vectors are Y_k = sum_p theta_kp (h_p X).  The P group products h_p X come from one batched launch of P
+    copies of the plan with a shared input and unit coupling vectors (mrmf_batch_matvec_c), the K outputs
+    from one combining pass (mrmf_sweep_combine_c).  X: nvec c64 vectors as one [D, nvec] block (input_elems
+    entries); output k is block(Y, k)."""
+
+    def __init__(self, plan: "Plan", nvec: int = 8):
+        P = plan.n_params
+        if not 1 <= P <= 16:
+            raise ValueError("a sweep by linearity needs 1 to 16 couplings")
+        self.plan, self.nvec, self.P, self.device = plan, int(nvec), P, plan.device
+        self.basis = Batch([plan] * P, self.nvec)
+        self.basis.share_input(True)
+        self.n = plan.D * self.nvec
+        self.stride = (self.n + 31) // 32 * 32          # the batch's block pitch (offsets padded to 32)
+        if P > 1 and self.basis.offsets[1] - self.basis.offsets[0] != self.stride:
+            raise RuntimeError("unexpected batch block pitch")
+        self.input_elems = self.basis.input_elems
+        self.unit = torch.eye(P, dtype=torch.float32, device=self.device).reshape(-1).contiguous()
+        self.G = torch.empty(self.basis.total_elems, dtype=torch.complex64, device=self.device)
+
+    def block(self, Y: torch.Tensor, k: int) -> torch.Tensor:
+        """View of output k, [D, nvec]."""
+        return Y[k * self.stride: k * self.stride + self.n].view(self.plan.D, self.nvec)
+
+    def run(self, thetas: torch.Tensor, X: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """thetas: float32 [K, P] on the device; X: complex64, at least input_elems entries.  Returns Y with
+        K blocks of stride entries."""
+        _need_gpu(thetas, "thetas", torch.float32)
+        if thetas.dim() != 2 or thetas.shape[1] != self.P:
+            raise ValueError("thetas must be [K, n_params]")
+        K = int(thetas.shape[0])
+        Y = torch.empty(K * self.stride, dtype=torch.complex64, device=self.device) if out is None else out
+        _need_gpu(Y, "out", torch.complex64)
+        if Y.numel() < K * self.stride:
+            raise ValueError("out needs K * stride entries")
+        self.basis.matvec(self.unit, X, self.G)
+        L.call("mrmf_sweep_combine_c", _ptr(thetas.contiguous()), K, self.P, self.n, _ptr(self.G), self.stride,
+               _ptr(Y), self.stride, _stream(self.device))
+        return Y
+
+
 class Sector:
     """Restricted basis of the states whose local digits sum to digit_sum (mrmf_sector_*): packed vectors
     of length dim in ascending full-basis order, the matvec P H P^T, labels, lookup and Lanczos."""

@@ -404,6 +404,24 @@ def test_batch_share_input_rules():
             L.lib().mrmf_plan_destroy(h)
 
 
+def test_sweep_combine_argument_checks():
+    """mrmf_sweep_combine_c refuses, before any launch, null pointers, K < 1, P outside 1..16, n < 1,
+    strides shorter than n, misaligned or overlapping buffers (the pointers are never dereferenced)."""
+    g, y, th = (ctypes.c_void_p((1 << 40) + (k << 34)) for k in range(3))
+    f = L.lib().mrmf_sweep_combine_c
+
+    def call(theta=th, K=4, P=3, n=100, G=g, gs=128, Y=y, ys=128):
+        return f(theta, K, P, n, G, gs, Y, ys, None)
+
+    assert call(theta=None) == L.MRMF_E_INVALID_ARG and call(G=None) == L.MRMF_E_INVALID_ARG
+    assert call(Y=None) == L.MRMF_E_INVALID_ARG and call(K=0) == L.MRMF_E_INVALID_ARG
+    assert call(P=0) == L.MRMF_E_INVALID_ARG and call(P=17) == L.MRMF_E_INVALID_ARG
+    assert call(n=0) == L.MRMF_E_INVALID_ARG and call(gs=99) == L.MRMF_E_INVALID_ARG
+    assert call(ys=99) == L.MRMF_E_INVALID_ARG
+    assert call(G=ctypes.c_void_p(g.value + 4)) == L.MRMF_E_INVALID_ARG
+    assert call(Y=ctypes.c_void_p(g.value + 8 * 200)) == L.MRMF_E_INVALID_ARG      # Y inside G's span
+
+
 def test_lanczos_refuses_non_hermitian_plans():
     """mrmf_lanczos and mrmf_sector_lanczos return MRMF_E_NOT_HERMITIAN, before any launch, for a plan
     built without MRMF_REQUIRE_HERMITIAN whose parameter group is not Hermitian (S_+ S_- without its

@@ -263,3 +263,36 @@ def test_disorder_average_shared_input():
         for b in range(len(models)):
             assert torch.equal(B.block(Y, b), ref_b.block(Yref, b)), (sched, b)
     check_all(B, models, [x] * len(models), Y)
+
+
+def test_sweep_by_linearity():
+    """Sweep (group products h_p X from one batched launch, then Y_k = sum_p theta_kp h_p X in one combining
+    pass) against the direct batched products at each coupling vector (FP32 sums in another order: within
+    2e-6 relative) and against the oracle in FP64; the group products equal the plan's matvec at unit
+    couplings."""
+    import dataclasses
+    from paper_2606_02169_amd.plan import Batch, Plan, Sweep
+    base = W.ferrimagnetic_ring(10)
+    thetas = [np.array([1.0, j, 0.5, h]) for h in (0.0, 0.3, -0.2) for j in np.linspace(0.4, 1.6, 9)]
+    models = [dataclasses.replace(base, theta=t) for t in thetas]
+    x = W.random_state(base.dim, np.random.default_rng(75), np.complex64, nvec=8)
+    plan = Plan.from_model(base)
+    sw = Sweep(plan, 8)
+    X = torch.zeros(sw.input_elems, dtype=torch.complex64, device=DEV)
+    X[: sw.n].view(base.dim, 8).copy_(torch.from_numpy(x).to(DEV))
+    th = torch.from_numpy(np.stack(thetas).astype(np.float32)).to(DEV)
+    Y = sw.run(th, X)
+    B = Batch([plan] * len(models), 8)
+    B.share_input(True)
+    Yd = B.matvec(th.reshape(-1), X)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k in range(len(models)):
+        a, b = sw.block(Y, k).cpu().numpy(), B.block(Yd, k).cpu().numpy()
+        worst = max(worst, rel_err(a, b))
+    print("sweep by linearity vs direct", worst, flush=True)
+    assert worst <= 2e-6
+    class _View:                                    # check_all reads blocks through .block
+        def block(self, T, k):
+            return sw.block(T, k)
+    check_all(_View(), models, [x] * len(models), Y)
